@@ -1,0 +1,114 @@
+"""Patch families (Section 3.1 and Section 3.2, Eq. cav_patch_set).
+
+Every patch is a sorted array of global unknown indices in the [u; v; p]
+ordering of `oracle.mac`.
+
+* Standard pressure-centred Vanka patch V_ij = {p_ij} U U_ij with
+  U_ij = {u_ij, u_{i+1,j}, v_ij, v_{i,j+1}}.
+* V(C) = union of V_c over a cell set C.
+* CAV: U_hat = U_ij plus every velocity k with (E_E)_{kl} != 0 or
+  (E_E)_{lk} != 0 for some l in U_ij; if U_hat = U_ij the patch is V_ij,
+  otherwise V(C(U_hat)) with C(u_ij) = {(i-1,j),(i,j)}, C(v_ij) = {(i,j-1),(i,j)}.
+  "Nonzero" is read structurally (a reading): the pattern is that of the
+  all-ones products, so no numerical cancellation removes a coupling.
+* Box B(b,o): b x b cell blocks expanded by o layers; restricted injection
+  keeps only the unknowns of the unexpanded block (Section 3.3).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from .mac import iu
+
+
+def cell_velocities(N: int, i: int, j: int):
+    """U_ij as global indices."""
+    return [int(iu(N, i, j)), int(iu(N, i + 1, j)), N * N + int(iu(N, i, j)), N * N + int(iu(N, i, j + 1))]
+
+
+def vanka_patch(N: int, i: int, j: int) -> np.ndarray:
+    return np.array(sorted([2 * N * N + int(iu(N, i, j))] + cell_velocities(N, i, j)), dtype=np.int64)
+
+
+def union_patch(N: int, cells) -> np.ndarray:
+    """V(C) for a set of cells C."""
+    s = set()
+    for (a, b) in cells:
+        s.add(2 * N * N + int(iu(N, a, b)))
+        s.update(cell_velocities(N, a, b))
+    return np.array(sorted(s), dtype=np.int64)
+
+
+def incident_cells(N: int, dof: int):
+    """C(w): the two cells whose divergence rows contain velocity w."""
+    if dof < N * N:
+        i, j = divmod(dof, N)
+        return [((i - 1) % N, j), (i, j)]
+    d = dof - N * N
+    i, j = divmod(d, N)
+    return [(i, (j - 1) % N), (i, j)]
+
+
+def cav_patches(N: int, pattern: sp.spmatrix):
+    """One CAV patch per cell, in lexicographic cell order (i first).
+
+    Returns (patches, standard) where standard[c] is True when U_hat = U
+    for cell c = i*N + j.
+    """
+    P = (pattern != 0).astype(np.int8)
+    Ps = ((P + P.T) != 0).tocsr()
+    row_nnz = np.diff(Ps.indptr)
+    patches = []
+    standard = np.zeros(N * N, dtype=bool)
+    for i in range(N):
+        for j in range(N):
+            U = cell_velocities(N, i, j)
+            if all(row_nnz[d] == 0 for d in U):
+                patches.append(vanka_patch(N, i, j))
+                standard[i * N + j] = True
+                continue
+            Uhat = set(U)
+            for d in U:
+                Uhat.update(Ps.indices[Ps.indptr[d]:Ps.indptr[d + 1]].tolist())
+            if Uhat == set(U):
+                patches.append(vanka_patch(N, i, j))
+                standard[i * N + j] = True
+                continue
+            cells = set()
+            for w in Uhat:
+                cells.update(incident_cells(N, w))
+            patches.append(union_patch(N, cells))
+    return patches, standard
+
+
+def vanka_patches(N: int):
+    """B(1,0): the standard Vanka family."""
+    return [vanka_patch(N, i, j) for i in range(N) for j in range(N)], np.ones(N * N, dtype=bool)
+
+
+def box_patches(N: int, b: int, o: int):
+    """B(b,o) patches and their restricted-injection masks (Section 3.1, 3.3).
+
+    Block lower-left cells visited in lexicographic order; returns
+    (patches, inject) where inject[k] is a boolean mask over patches[k] that
+    keeps the unknowns of the unexpanded b x b block V(block)."""
+    assert N % b == 0
+    patches, inject = [], []
+    for I in range(0, N, b):
+        for J in range(0, N, b):
+            ext = [((I + r) % N, (J + s) % N) for r in range(-o, b + o) for s in range(-o, b + o)]
+            core = [((I + r) % N, (J + s) % N) for r in range(b) for s in range(b)]
+            patch = union_patch(N, ext)
+            core_dofs = set(union_patch(N, core).tolist())
+            patches.append(patch)
+            inject.append(np.array([d in core_dofs for d in patch.tolist()]))
+    return patches, inject
+
+
+def patch_counts(n: int, patches) -> np.ndarray:
+    """cnt(d): the number of patches that contain unknown d."""
+    cnt = np.zeros(n, dtype=np.int64)
+    for p in patches:
+        cnt[p] += 1
+    return cnt

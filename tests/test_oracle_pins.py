@@ -1,0 +1,478 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test names what it pins and which plausible mistake it would catch.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads
+from oracle import direct, hierarchy, ib, krylov, mac, multigrid, patches, smoothers
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- MAC grid ---
+
+def _face_coords(N):
+    h = 1.0 / N
+    i, j = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    return h, i.ravel(), j.ravel()
+
+
+def test_divergence_kills_discrete_curl():
+    """u = d(psi)/dy, v = -d(psi)/dx with psi at grid nodes is exactly
+    divergence free on the MAC grid (pins D's index convention)."""
+    N = 12
+    h, i, j = _face_coords(N)
+    psi = np.random.default_rng(3).standard_normal((N, N))   # psi at nodes (i h, j h)
+    u = (psi[i, (j + 1) % N] - psi[i, j]) / h                 # u_ij at (i h, (j+1/2) h)
+    v = -(psi[(i + 1) % N, j] - psi[i, j]) / h                # v_ij at ((i+1/2) h, j h)
+    D = mac.divergence(N, h)
+    assert np.abs(D @ np.concatenate([u, v])).max() < 1e-9 * np.abs(u).max() / h
+
+
+def test_divergence_and_gradient_are_centred_differences():
+    """Smooth fields: D and G give the derivative at the right staggered
+    location to O(h^2) (pins sign and half-cell offsets)."""
+    errs = []
+    for N in (16, 32):
+        h, i, j = _face_coords(N)
+        k = 2 * np.pi
+        u = np.sin(k * i * h) * np.cos(k * (j + 0.5) * h)             # at u faces
+        v = np.zeros_like(u)
+        div_exact = k * np.cos(k * (i + 0.5) * h) * np.cos(k * (j + 0.5) * h)
+        p = np.sin(k * (i + 0.5) * h) * np.sin(k * (j + 0.5) * h)     # at centres
+        gu_exact = k * np.cos(k * i * h) * np.sin(k * (j + 0.5) * h)
+        gv_exact = k * np.sin(k * (i + 0.5) * h) * np.cos(k * j * h)
+        e1 = np.abs(mac.divergence(N, h) @ np.concatenate([u, v]) - div_exact).max()
+        g = mac.gradient(N, h) @ p
+        e2 = max(np.abs(g[:N * N] - gu_exact).max(), np.abs(g[N * N:] - gv_exact).max())
+        errs.append((e1, e2))
+    for a in range(2):
+        assert errs[0][a] < 0.2
+        assert errs[1][a] < errs[0][a] / 3.5          # second order
+
+
+def test_D_equals_minus_G_transpose_and_commutes_with_laplacian():
+    N = 8
+    h = 1.0 / N
+    D, G = mac.divergence(N, h), mac.gradient(N, h)
+    assert abs(D + G.T).max() == 0.0
+    # periodic MAC: D L_vel = L_p D
+    lhs = D @ mac.vector_laplacian(N, h)
+    rhs = mac.scalar_laplacian(N, h) @ D
+    assert abs(lhs - rhs).max() < 1e-9 * abs(lhs).max()
+
+
+def test_discrete_projection_is_divergence_free_and_idempotent():
+    """Pi = I - G (DG)^+ D: D Pi = 0, Pi^2 = Pi (the discrete divergence-free projection)."""
+    N = 8
+    h = 1.0 / N
+    D = mac.divergence(N, h).toarray()
+    G = mac.gradient(N, h).toarray()
+    Pi = np.eye(2 * N * N) - G @ np.linalg.pinv(D @ G) @ D
+    assert np.abs(D @ Pi).max() < 1e-11 * np.abs(D).max()
+    assert np.abs(Pi @ Pi - Pi).max() < 1e-12
+
+
+def test_laplacian_eigenfunction():
+    N = 32
+    h, i, j = _face_coords(N)
+    k = 2 * np.pi
+    f = np.sin(k * i * h) * np.sin(k * (j + 0.5) * h)
+    Lf = mac.scalar_laplacian(N, h) @ f
+    lam = -8 * np.sin(k * h / 2) ** 2 / h ** 2             # 5-point symbol, both directions
+    assert np.abs(Lf - lam * f).max() < 1e-8 * abs(lam)
+
+
+# --------------------------------------------------------- IB coupling ---
+
+def test_phi4_moment_conditions():
+    """Peskin's 4-point kernel: sum phi = 1, first moment 0, sum phi^2 = 3/8,
+    even and odd sums 1/2, for arbitrary shifts."""
+    r = np.random.default_rng(0).uniform(0, 1, 200)
+    js = np.arange(-3, 4)
+    W = ib.phi4(r[:, None] - js[None, :])
+    assert np.abs(W.sum(1) - 1).max() < 1e-14
+    assert np.abs((W * (r[:, None] - js[None, :])).sum(1)).max() < 1e-14
+    assert np.abs((W ** 2).sum(1) - 3 / 8).max() < 1e-14
+    even = (js % 2 == 0)
+    assert np.abs(W[:, even].sum(1) - 0.5).max() < 1e-14
+    assert abs(ib.phi4(np.array([0.0]))[0] - 0.5) < 1e-15
+    assert ib.phi4(np.array([2.0, 2.5, -2.0]))[:].max() == 0.0
+
+
+def test_interpolation_reproduces_constants_and_linears():
+    """J interpolates constant and (locally) linear fields exactly, for both
+    components: pins the 4x4 support box and the face offsets."""
+    N = 32
+    h, i, j = _face_coords(N)
+    X = np.random.default_rng(1).uniform(0.3, 0.7, (40, 2))
+    J = ib.interpolation(N, X)
+    ones = np.ones(2 * N * N)
+    assert np.abs(J @ ones - 1).max() < 1e-14
+    ux = np.concatenate([i * h, (i + 0.5) * h])            # x coordinate of u and v faces
+    uy = np.concatenate([(j + 0.5) * h, j * h])            # y coordinate
+    U = J @ ux
+    V = J @ uy
+    assert np.abs(U - X[:, 0].repeat(2)).max() < 1e-13
+    assert np.abs(V - X[:, 1].repeat(2)).max() < 1e-13
+
+
+def test_spread_interp_adjoint_and_force_conservation():
+    """<u, S F>_E = <J u, F>_L with <a,b>_E = h^2 a.b and <A,B>_L = sum omega_k A_k.B_k
+    (Section 2); total spread force equals total Lagrangian force."""
+    s = workloads.membrane_ellipse(32, 3, 1e4, 0)
+    N = s.N
+    h = 1.0 / N
+    X, om = s.markers(), s.weights()
+    J = ib.interpolation(N, X)
+    S = ib.spreading(N, J, om)
+    g = np.random.default_rng(2)
+    u = g.standard_normal(2 * N * N)
+    F = g.standard_normal(2 * len(X))
+    lhs = h * h * u @ (S @ F)
+    rhs = np.sum(np.repeat(om, 2) * (J @ u) * F)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+    f = S @ F
+    assert abs(h * h * f[:N * N].sum() - (om * F[0::2]).sum()) < 1e-12 * np.abs(F).sum()
+
+
+def test_force_laws():
+    """Membrane: -X^T W E X = kappa_s sum |X_{k+1}-X_k|^2 / ds (spring energy);
+    closed laws annihilate translations; open beam annihilates translations and
+    its bending part annihilates straight lines; target: -kappa I."""
+    seg = workloads.ellipse(0.5, 0.5, 0.2, 0.15, 1 / 64)
+    M, ds = len(seg.X), seg.ds
+    E = ib.segment_elasticity("membrane", {"kappa_s": 7.0}, M, True, ds)
+    x = seg.X[:, 0]
+    d = np.roll(x, -1) - x
+    assert abs(-ds * x @ (E @ x) - 7.0 * np.sum(d * d) / ds) < 1e-9 * 7.0 * np.sum(d * d) / ds
+    assert np.abs(E @ np.ones(M)).max() < 1e-6 * abs(E).max()
+    Eb = ib.segment_elasticity("beam_closed", {"kappa_b": 1.0}, M, True, ds)
+    assert np.abs(Eb @ np.ones(M)).max() < 1e-6 * abs(Eb).max()
+    Mo = 30
+    Eo = ib.segment_elasticity("beam_open", {"kappa_b": 2.0, "kappa_s": 0.0}, Mo, False, 0.1)
+    s = np.arange(Mo) * 0.1
+    assert np.abs(Eo @ (3 + 2 * s)).max() < 1e-9 * abs(Eo).max()
+    assert np.abs(Eo @ s ** 2).max() > 1.0
+    Et = ib.segment_elasticity("target", {"kappa_t": 5.0}, 4, True, 0.1)
+    assert np.allclose(Et.toarray(), -5 * np.eye(4))
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: workloads.target_circle(16, 2, 1e4, 0),
+    lambda: workloads.membrane_ellipse(16, 2, 1e4, 0),
+    lambda: workloads.beam_fibres(16, 2, 1.0, 1e4, seed=0),
+])
+def test_eulerian_elasticity_symmetric_nsd_on_every_level(maker):
+    """E_E self-adjoint and negative semidefinite when E is (Section 1,
+    Appendix A); also after Galerkin coarsening."""
+    s = maker()
+    EE, pat = ib.eulerian_elasticity(s)
+    lev = [(EE, pat)]
+    lev.append(hierarchy.galerkin(EE, pat, s.N // 2))
+    for A, P in lev:
+        A = A.toarray()
+        nrm = np.abs(A).max()
+        assert np.abs(A - A.T).max() < 1e-12 * nrm
+        w = np.linalg.eigvalsh(0.5 * (A + A.T))
+        assert w.max() < 1e-10 * nrm
+        assert (P.toarray() != 0)[A != 0].all()       # numeric nonzeros lie inside the pattern
+
+
+# --------------------------------------------------------------- transfers ---
+
+def test_transfers():
+    """R = P^*/... : R 1 = 1 for velocity, D_f P_u = injection of D_c (RT0
+    commuting property), bilinear pressure prolongation reproduces constants
+    and linear fields away from the periodic seam, averaging restriction."""
+    Nc = 8
+    Nf = 2 * Nc
+    P = hierarchy.prolong_velocity(Nc)
+    R = hierarchy.restrict_velocity(Nc)
+    assert np.abs(R @ np.ones(2 * Nf * Nf) - 1).max() < 1e-15
+    assert abs(R - 0.25 * P.T).max() == 0
+    uc = np.random.default_rng(0).standard_normal(2 * Nc * Nc)
+    Df, Dc = mac.divergence(Nf, 1 / Nf), mac.divergence(Nc, 1 / Nc)
+    dc = Dc @ uc
+    df = Df @ (P @ uc)
+    I, J = np.meshgrid(np.arange(Nf), np.arange(Nf), indexing="ij")
+    assert np.abs(df - dc[mac.iu(Nc, I.ravel() // 2, J.ravel() // 2)]).max() < 1e-12 * np.abs(dc).max()
+    Pp = hierarchy.prolong_pressure(Nc)
+    assert np.abs(Pp @ np.ones(Nc * Nc) - 1).max() < 1e-15
+    Ic, Jc = np.meshgrid(np.arange(Nc), np.arange(Nc), indexing="ij")
+    lin_c = ((Ic + 0.5) * 2 + 3 * (Jc + 0.5) * 2).ravel()          # linear in fine-cell units
+    lin_f = ((I + 0.5) + 3 * (J + 0.5)).ravel()
+    inner = ((I >= 2) & (I < Nf - 2) & (J >= 2) & (J < Nf - 2)).ravel()
+    assert np.abs((Pp @ lin_c - lin_f)[inner]).max() < 1e-12
+    Rp = hierarchy.restrict_pressure(Nc)
+    assert np.abs(Rp @ lin_f - lin_c).max() < 1e-12
+    assert np.abs(Rp @ np.ones(Nf * Nf) - 1).max() == 0
+
+
+# ----------------------------------------------------------------- patches ---
+
+def test_cav_without_elasticity_is_standard_vanka():
+    """With no Eulerian coupling U_hat = U everywhere, so CAV = B(1,0)."""
+    N = 8
+    pat = sp.csr_matrix((2 * N * N, 2 * N * N))
+    ps, std = patches.cav_patches(N, pat)
+    vk, _ = patches.vanka_patches(N)
+    assert std.all()
+    assert all(np.array_equal(a, b) for a, b in zip(ps, vk))
+    assert all(len(p) == 5 for p in ps)
+
+
+def test_cav_patch_single_target_marker_hand_derived():
+    """One target marker at (1/2,1/2) on N=8. By hand: u faces in the kernel box
+    have i in 3..6, j in 2..5; v faces i in 2..5, j in 3..6. Cell (4,4)
+    touches both boxes, so U_hat adds all 32 faces; their incident cells are
+    {2..6}x{2..5} U {2..5}x{2..6} (24 cells) and the union patch has
+    24 pressures + 29 u + 29 v = 82 unknowns. Cells (1,1) and (2,1) touch no
+    box and stay standard; cell (2,2) holds u_32 and is enlarged."""
+    N = 8
+    sy = workloads.System("one", N, 2, 1.0, 0.01, 1e-3, "target", {"kappa_t": 1.0},
+                          [workloads.Segment(np.array([[0.5, 0.5]]), True, 0.1)], np.zeros(3 * N * N))
+    _, pat = ib.eulerian_elasticity(sy)
+    ps, std = patches.cav_patches(N, pat)
+    cells = {(a, b) for a in range(2, 7) for b in range(2, 6)} | {(a, b) for a in range(2, 6) for b in range(2, 7)}
+    assert len(cells) == 24
+    expect = set()
+    for (a, b) in cells:
+        expect |= {2 * N * N + a * N + b, a * N + b, (a + 1) * N + b, N * N + a * N + b, N * N + a * N + b + 1}
+    assert len(expect) == 82
+    assert set(ps[4 * N + 4].tolist()) == expect and not std[4 * N + 4]
+    assert std[1 * N + 1] and std[2 * N + 1] and not std[2 * N + 2]
+    assert len(ps[0]) == 5
+
+
+def test_cav_patch_sizes_bounded_under_refinement():
+    """Bounded patch size at fixed physical geometry (Section 3.3, Table 3)."""
+    mx = []
+    for N in (32, 64, 128):
+        s = workloads.membrane_ellipse(N, 2, 1e4, 0)
+        _, pat = ib.eulerian_elasticity(s)
+        ps, std = patches.cav_patches(N, pat)
+        mx.append(max(len(p) for p in ps))
+    assert max(mx) <= 1.3 * min(mx)
+
+
+def test_box_patch_and_injection():
+    """B(4,2) on N=16: 4 blocks; each patch spans 8x8 cells (64 p, 72 u, 72 v);
+    the injected core spans 4x4 cells (16 p, 20 u, 20 v)."""
+    N = 16
+    ps, inj = patches.box_patches(N, 4, 2)
+    assert len(ps) == 16
+    assert all(len(p) == 64 + 72 + 72 for p in ps)
+    assert all(int(m.sum()) == 16 + 20 + 20 for m in inj)
+
+
+# ------------------------------------------------------------ local solves ---
+
+def test_standard_vanka_local_solve_closed_form():
+    """E = 0: the 5x5 patch system [[A, g], [g^T, 0]] has
+    A = blockdiag([[d,-c],[-c,d]] x 2), d = rho/dt + 4 mu/h^2, c = mu/h^2,
+    g = (1,-1,1,-1)/h, so dp = (g^T A^-1 r_u - r_p)/(g^T A^-1 g),
+    du = A^-1 (r_u - g dp). Equilibration must not change the answer."""
+    N, rho, mu, dt = 8, 1.0, 0.01, 1e-3
+    h = 1 / N
+    K = mac.reduced_operator(N, rho, mu, dt, sp.csr_matrix((2 * N * N, 2 * N * N)))
+    ps, std = patches.vanka_patches(N)
+    sol = smoothers.PatchSolvers(K, ps, std)
+    d, c = rho / dt + 4 * mu / h ** 2, mu / h ** 2
+    A = np.array([[d, -c, 0, 0], [-c, d, 0, 0], [0, 0, d, -c], [0, 0, -c, d]])
+    gv = np.array([1, -1, 1, -1]) / h
+    r = np.random.default_rng(5).standard_normal(3 * N * N)
+    cell = 3 * N + 5
+    p = ps[cell]                                  # sorted: u_ij, u_{i+1,j}, v_ij, v_{i,j+1}, p_ij
+    ru, rp = r[p[:4]], r[p[4]]
+    Ai = np.linalg.inv(A)
+    dp = (gv @ Ai @ ru - rp) / (gv @ Ai @ gv)
+    du = Ai @ (ru - gv * dp)
+    got = sol.corrections(r)[cell]
+    assert np.abs(got - np.concatenate([du, [dp]])).max() < 1e-12 * np.abs(np.concatenate([du, [dp]])).max()
+    # unequilibrated LU of the raw patch agrees
+    raw = np.linalg.solve(K[p][:, p].toarray(), r[p])
+    assert np.abs(raw - got).max() < 1e-12 * np.abs(raw).max()
+
+
+def test_equilibration_is_exact_power_of_two_and_correction_neutral():
+    s = workloads.beam_fibres(32, 2, 1.0, 1e4, seed=0)
+    H = multigrid.Hierarchy(s, alpha=0.7)
+    lev = H.levels[1]
+    k = int(np.nonzero(~lev.standard)[0][0])
+    p = lev.patches[k]
+    Kp = lev.K[p][:, p].toarray()
+    Kt, rs, cs = smoothers.equilibrate(Kp)
+    assert np.all(np.log2(rs) == np.round(np.log2(rs))) and np.all(np.log2(cs) == np.round(np.log2(cs)))
+    assert np.abs(np.abs(Kt).max(axis=0) - 1.5).max() <= 0.5
+    r = np.random.default_rng(1).standard_normal(len(p))
+    d_eq = lev.solvers.solve_one(k, r)
+    d_raw = np.linalg.solve(Kp, r)
+    cond = np.linalg.cond(Kp)
+    assert np.linalg.norm(d_eq - d_raw) <= 1e-15 * cond * np.linalg.norm(d_raw) * 10
+
+
+# ---------------------------------------------------------------- smoother ---
+
+def test_patch_count_weights_are_partition_of_unity():
+    """sum_p R_p^T Theta_p R_p = I with Theta_p = diag(1/cnt) (Appendix A)."""
+    s = workloads.membrane_ellipse(32, 2, 1e4, 0)
+    H = multigrid.Hierarchy(s, alpha=0.7)
+    lev = H.levels[1]
+    n = lev.K.shape[0]
+    acc = np.zeros(n)
+    for p in lev.patches:
+        acc[p] += 1.0 / lev.cnt[p]
+    assert np.abs(acc - 1).max() < 1e-14
+
+
+def test_additive_sweep_matches_dense_formula():
+    """The sweep equals alpha sum_i R_i^T Theta_i (R_i K R_i^T)^-1 R_i r
+    (Eq. additive_cav_saddle) built densely from explicit restriction
+    matrices and inverses, followed by mean-pressure removal."""
+    s = workloads.target_circle(16, 2, 1e4, 0)
+    alpha = 0.7
+    H = multigrid.Hierarchy(s, alpha=alpha)
+    lev = H.levels[1]
+    n = lev.K.shape[0]
+    N = lev.N
+    Kd = lev.K.toarray()
+    cnt = np.zeros(n)
+    for p in lev.patches:
+        cnt[p] += 1
+    B = np.zeros((n, n))
+    for p in lev.patches:
+        Rm = np.zeros((len(p), n))
+        Rm[np.arange(len(p)), p] = 1.0
+        B += Rm.T @ np.diag(1.0 / cnt[p]) @ np.linalg.inv(Rm @ Kd @ Rm.T) @ Rm
+    B *= alpha
+    b = np.random.default_rng(9).standard_normal(n)
+    z = B @ b
+    z[2 * N * N:] -= z[2 * N * N:].mean()
+    got = H.smooth(1, b, np.zeros(n))
+    assert np.linalg.norm(got - z) < 1e-10 * np.linalg.norm(z)
+
+
+# ---------------------------------------------------- multigrid and krylov ---
+
+def test_one_level_vcycle_is_exact_and_fgmres_takes_one_step():
+    """N=8 with a single level: the V-cycle is the bordered direct solve, so
+    FGMRES converges in one iteration to the mean-zero solution."""
+    s = workloads.target_circle(8, 1, 1e4, 0)
+    H = multigrid.Hierarchy(s)
+    K = H.levels[0].K
+    res = krylov.fgmres(lambda x: K @ x, H.vcycle, s.b, 1e-10, 10)
+    xs = direct.solve(K, 8, s.b)
+    assert res.iterations == 1
+    assert np.linalg.norm(res.x - xs) < 1e-10 * np.linalg.norm(xs)
+    assert abs(res.x[128:].sum()) < 1e-10
+
+
+def test_fgmres_estimate_equals_bruteforce_least_squares():
+    """With B = I the rotated estimate after k steps equals
+    min_y || b - K [b, Kb, ..., K^{k-1} b] y || / ||b|| (dense least squares)."""
+    s = workloads.membrane_ellipse(8, 1, 1e2, 0)
+    H = multigrid.Hierarchy(s)
+    K = H.levels[0].K.toarray()
+    b = s.b / np.linalg.norm(s.b)
+    res = krylov.fgmres(lambda x: K @ x, lambda v: v, b, 1e-30, 6)
+    Kr = [b]
+    for k in range(1, 7):
+        Q, _ = np.linalg.qr(np.stack(Kr, axis=1))
+        y, *_ = np.linalg.lstsq(K @ Q, b, rcond=None)
+        est = np.linalg.norm(b - K @ Q @ y)
+        # the monomial Krylov basis loses conditioning quickly; 1e-7 leaves room for that
+        assert abs(res.history[k - 1] - est) < 1e-7 * max(est, 1e-3), (k, res.history[k - 1], est)
+        Kr.append(K @ Kr[-1])
+        Kr[-1] = Kr[-1] / np.linalg.norm(Kr[-1])
+    for variant in ("mgs",):
+        r2 = krylov.fgmres(lambda x: K @ x, lambda v: v, b, 1e-30, 6, orth=variant)
+        assert np.allclose(r2.history, res.history, rtol=1e-6)
+
+
+def test_fgmres_with_exact_inverse_converges_in_one_step():
+    s = workloads.target_circle(8, 1, 1e4, 0)
+    K = multigrid.Hierarchy(s).levels[0].K
+    res = krylov.fgmres(lambda x: K @ x, lambda v: direct.solve(K, 8, v), s.b, 1e-10, 5)
+    assert res.iterations == 1
+
+
+def test_small_target_solve_reaches_tolerance_and_matches_direct():
+    """32x32 target circle, 3 levels, additive CAV (alpha 0.7): the estimate
+    reaches 1e-10, the true residual agrees while above the rounding floor,
+    and the solution matches the direct solve within cond * tol."""
+    s = workloads.small_target(0)
+    H = multigrid.Hierarchy(s, alpha=0.7)
+    K = H.levels[-1].K
+    res = krylov.fgmres(lambda x: K @ x, H.vcycle, s.b, 1e-10, 150)
+    assert res.converged
+    true = np.linalg.norm(s.b - K @ res.x) / np.linalg.norm(s.b)
+    assert true < 2e-10
+    xs = direct.solve(K, s.N, s.b)
+    assert np.linalg.norm(res.x - xs) / np.linalg.norm(xs) < 1e-8
+
+
+# ------------------------------------------------------- paper's numbers ---
+
+def _physical_rhs(s):
+    X = s.markers()
+    J = ib.interpolation(s.N, X)
+    S = ib.spreading(s.N, J, s.weights())
+    b = np.zeros(3 * s.N * s.N)
+    b[:2 * s.N * s.N] = S @ (ib.elasticity(s) @ X.ravel())
+    return b
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                rows.append(line.split())
+    return rows
+
+
+def test_paper_table1_two_grid_spectrum_kappa_1e2():
+    """Table 1, kappa_s = 1e2: the multiplicative CAV two-grid cycle on the
+    N=16 membrane. Marker placement is only 'approximately h/2' in the paper,
+    so the band is loose; the stiffer rows depend strongly on that placement
+    and are reported, not pinned."""
+    g = {r[0]: float(r[1]) for r in _read_golden("paper_table1_kappa1e2.txt")}
+    s = workloads.paper_membrane(16, kappa=g["kappa_s"])
+    s.n_levels = 2
+    H = multigrid.Hierarchy(s, family="cav", smoother="multiplicative")
+    K = H.levels[-1].K.toarray()
+    n, N = K.shape[0], 16
+    T = np.eye(n) - H.vcycle(np.eye(n)) @ K
+    D = np.zeros((N * N, N * N - 1))
+    D[np.arange(N * N - 1), np.arange(N * N - 1)] = 1
+    D[np.arange(1, N * N), np.arange(N * N - 1)] = -1
+    Qp, _ = np.linalg.qr(D)
+    Q = np.zeros((n, n - 1))
+    Q[:2 * N * N, :2 * N * N] = np.eye(2 * N * N)
+    Q[2 * N * N:, 2 * N * N:] = Qp
+    lam = np.linalg.eigvals(Q.T @ T @ Q)
+    rho = np.abs(lam).max()
+    mod = np.abs(1 - lam)
+    assert abs(rho - g["rho_T"]) < 0.02
+    assert abs(mod.min() - g["min_abs_lambda"]) < 0.02
+    assert abs(mod.max() - g["max_abs_lambda"]) < 0.02
+
+
+def test_paper_membrane_fgmres_count_N16():
+    """Section 5.1: CAV-preconditioned FGMRES needs 9 iterations at N=16."""
+    rows = _read_golden("paper_membrane_counts.txt")
+    want = {int(r[0]): int(r[1]) for r in rows}
+    s = workloads.paper_membrane(16)
+    s.b = _physical_rhs(s)
+    H = multigrid.Hierarchy(s, family="cav", smoother="multiplicative")
+    K = H.levels[-1].K
+    res = krylov.fgmres(lambda x: K @ x, H.vcycle, s.b, 1e-10, 60)
+    assert res.iterations == want[16]
