@@ -1,0 +1,187 @@
+/*
+ * cavmg.h - C ABI of the MI355X (gfx950) CAV-multigrid FGMRES solver for the
+ * reduced Eulerian velocity-pressure immersed-boundary system.
+ *
+ * The system (Gruninger & Griffith, Section 2, Eq. intro_saddle / Eq. Eul_schur):
+ *     K_E [u; p] = [b_u; b_p],   K_E = [[A, G], [-D, 0]],
+ *     A = A0 - dt E_E,  A0 = (rho/dt) I - mu L,  E_E = S E J,
+ * on a periodic N x N MAC grid with h = 1/N.
+ *
+ * Vector layout (every device vector argument): 3 N^2 doubles, [u | v | p],
+ * each block an N x N array indexed [i][j] (i = x index, slowest; j = y index,
+ * fastest). u_ij sits at (i h, (j+1/2) h), v_ij at ((i+1/2) h, j h), p_ij at
+ * the cell centre. Indices are periodic.
+ *
+ * Execution model: every call enqueues its work on the context's HIP stream.
+ * Calls that return statistics or a solve summary synchronise that stream.
+ * A context is not thread safe; separate contexts are independent.
+ * Ownership: the caller owns every pointer argument; host descriptors are
+ * copied during the call; device vectors must stay valid until the work on
+ * the stream has finished. The context owns all hierarchy, patch and factor
+ * memory and frees it in cav_destroy.
+ * Errors: functions return a cav_status; nothing throws across the ABI.
+ * cav_last_error(ctx) gives a message for the most recent failure.
+ */
+#ifndef CAVMG_H
+#define CAVMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cav_ctx_s* cav_ctx;
+
+typedef enum {
+  CAV_OK = 0,
+  CAV_ERR_INVALID_ARG = 1,     /* malformed descriptor, size or non-finite input */
+  CAV_ERR_OUT_OF_MEMORY = 2,
+  CAV_ERR_HIP = 3,             /* a HIP runtime call failed */
+  CAV_ERR_SINGULAR_PATCH = 4,  /* zero pivot or non-finite value in a patch factorisation */
+  CAV_ERR_SINGULAR_COARSE = 5, /* zero pivot in the coarsest direct factorisation */
+  CAV_ERR_NOT_BUILT = 6,       /* a stage was called before the stages it depends on */
+  CAV_WARN_NOT_CONVERGED = 100,/* FGMRES reached max_it without meeting rtol */
+  CAV_WARN_FLOOR_LIMITED = 101 /* estimate met rtol, true residual did not (rounding floor) */
+} cav_status;
+
+/* Force laws (per Cartesian component, no coupling between components):
+ *  TARGET       E = -kappa_t I                              (Section 5.2)
+ *  MEMBRANE     F_k = kappa_s/ds^2 (X_{k+1}+X_{k-1}-2X_k), closed curves (Eq. disc_force_law)
+ *  BEAM_CLOSED  F = -kappa_b d^4X/ds^4, centred 5-point stencil, closed curves (Section 5.2)
+ *  BEAM_OPEN    E = -(kappa_b/ds^4) D2^T D2 - (kappa_s/ds^2) D1^T D1, open curves
+ *               (bending by second differences plus stretching springs, free ends)
+ *  CSR          caller supplies E (2M x 2M, component-interleaved: row 2k+c is
+ *               marker k, component c); E must be structurally symmetric and
+ *               W E symmetric negative semidefinite for the method's guarantees. */
+enum { CAV_LAW_TARGET = 0, CAV_LAW_MEMBRANE = 1, CAV_LAW_BEAM_CLOSED = 2, CAV_LAW_BEAM_OPEN = 3,
+       CAV_LAW_CSR = 4 };
+
+enum { CAV_FAMILY_CAV = 0, CAV_FAMILY_VANKA = 1 };         /* patch families (Section 3) */
+enum { CAV_PREC_FP64 = 0, CAV_PREC_MIXED = 1 };            /* factor storage policy */
+
+typedef struct {
+  int32_t N;         /* finest cells per side; power of two, N >> (n_levels-1) >= 4 */
+  int32_t n_levels;  /* hierarchy depth, >= 1; level 0 is the coarsest */
+  double rho, mu, dt;
+} cav_grid_desc;
+
+typedef struct {
+  int32_t M;               /* number of Lagrangian markers (>= 0) */
+  const double* X;         /* host, 2M, interleaved (x_k, y_k); any real values (wrapped periodically) */
+  const double* omega;     /* host, M quadrature weights (omega_k = ds for uniform spacing) */
+  int32_t law;             /* CAV_LAW_* */
+  double kappa_t, kappa_s, kappa_b;
+  int32_t n_segments;      /* curves for the built-in laws */
+  const int32_t* seg_start;/* host, n_segments+1 marker offsets (first = 0, last = M) */
+  const int32_t* seg_closed;/* host, n_segments flags */
+  const double* seg_ds;    /* host, n_segments uniform spacings */
+  int32_t E_nnz;           /* CAV_LAW_CSR only */
+  const int32_t* E_rowptr; /* host, 2M+1 */
+  const int32_t* E_col;    /* host, E_nnz */
+  const double* E_val;     /* host, E_nnz */
+} cav_structure_desc;
+
+typedef struct {           /* per smoothed level (index = level, 0 unused) */
+  int32_t N;
+  int32_t n_patches;       /* one per cell */
+  int32_t n_explicit;      /* patches with their own factor (enlarged or touching E_E) */
+  int32_t max_np;
+  double avg_np;           /* over all patches of the level */
+  int64_t sum_np2;         /* over explicit patches */
+  int64_t n_touched;       /* unknowns inside at least one explicit patch */
+  int64_t ee_nnz;          /* nonzeros of the level's E_E */
+} cav_level_stats;
+
+typedef struct {
+  int32_t n_fp64;          /* explicit patches stored in FP64 */
+  int32_t n_fp32;          /* explicit patches stored in FP32 (mixed policy, kappa_1 <= threshold) */
+  double max_cond;         /* largest kappa_1 of an equilibrated patch matrix */
+  int64_t factor_bytes;    /* bytes the smoother streams per sweep over all levels */
+  double coarse_cond_est;  /* ||B||_1 ||B^-1||_1 of the bordered coarse matrix */
+} cav_factor_stats;
+
+typedef struct {
+  double rtol;             /* relative residual target, e.g. 1e-10 */
+  int32_t max_it;          /* iteration cap (no restarts) */
+  int32_t use_learned;     /* nonzero: apply the attached learned stage after each V-cycle */
+  double* history;         /* optional host array of max_it doubles: estimate after each iteration */
+} cav_fgmres_opts;
+
+typedef struct {
+  int32_t iterations;      /* preconditioner applications */
+  int32_t converged;
+  double est_rel_residual; /* Givens estimate at exit */
+  double true_rel_residual;/* ||b - K x|| / ||b|| evaluated in FP64 after the solve */
+  double pressure_mean_removed; /* mean of the pressure RHS that was projected out */
+  int32_t learned_accepted, learned_rejected;
+} cav_solve_info;
+
+/* ---- lifecycle ---- */
+cav_status cav_create(cav_ctx* out, int device, void* hip_stream);
+cav_status cav_destroy(cav_ctx ctx);
+cav_status cav_set_stream(cav_ctx ctx, void* hip_stream);
+const char* cav_status_string(cav_status s);
+const char* cav_last_error(cav_ctx ctx);
+
+/* ---- setup (Section 2, Section 3, Section 4) ----
+ * cav_build_operator: assembles J (4-point kernel, fixed 4x4 face box per
+ *   marker and component), E for the chosen law, E_E = S E J on the finest
+ *   level, the Galerkin coarse E_E^(l-1) = R E_E^(l) P on every coarser level
+ *   (R = P^T/4, RT0 velocity prolongation), and the rediscretised Stokes
+ *   stencils. Validates the grid (power of two, levels), finite X and E.
+ * cav_build_cav_patches: one patch per cell on every level except the
+ *   coarsest (Eq. cav_patch_set for CAV_FAMILY_CAV; the standard Vanka patch
+ *   for CAV_FAMILY_VANKA), read from the structural pattern of the level's
+ *   E_E. `out` (optional) receives n_levels entries.
+ * cav_factor_patches: assembles every explicit patch matrix K_p = R_p K_E R_p^T,
+ *   applies one row then column max-norm equilibration (powers of two), inverts
+ *   it by Gauss-Jordan elimination with partial pivoting, folds the scalings
+ *   into the stored inverse and records kappa_1 (Section 3.3). Patches with no
+ *   E_E entry share one 5x5 inverse per level. Under CAV_PREC_MIXED a patch
+ *   whose kappa_1 <= cond_threshold is stored in FP32. Also factors the
+ *   coarsest bordered matrix [[K_0, e], [e^T, 0]] (e = constant pressure). */
+cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* grid, const cav_structure_desc* st);
+cav_status cav_build_cav_patches(cav_ctx ctx, int family, cav_level_stats* out);
+cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold, cav_factor_stats* out);
+/* Weighted additive smoother (Appendix A, Eq. additive_cav_saddle):
+ * w <- w + alpha sum_p R_p^T Theta_p K_p^{-1} R_p (b - K w), Theta_p = diag(1/cnt),
+ * then the mean pressure is removed. pre/post = sweeps per V-cycle leg (1, 1). */
+cav_status cav_set_smoother(cav_ctx ctx, double alpha, int pre, int post);
+
+/* ---- application ---- */
+/* y = K_E x on the finest level (x, y device, 3N^2, must not alias). */
+cav_status cav_apply_operator(cav_ctx ctx, const double* x, double* y);
+/* z = V(r): one V(pre,post)-cycle on the finest level (Section 4). */
+cav_status cav_vcycle(cav_ctx ctx, const double* r, double* z);
+/* Right-preconditioned FGMRES from x0 = 0 (Section 5): one V-cycle per
+ * iteration, CGS2 orthogonalisation with fixed-order reductions, Givens
+ * rotations; stops when the estimate <= rtol or on exact breakdown. b is
+ * not modified; a nonzero pressure mean in b is projected out and reported.
+ * Returns CAV_WARN_NOT_CONVERGED at max_it and CAV_WARN_FLOOR_LIMITED when the
+ * estimate met rtol but the true FP64 residual exceeds 10 * rtol. */
+cav_status cav_fgmres_solve(cav_ctx ctx, const double* b, double* x, const cav_fgmres_opts* opts,
+                            cav_solve_info* info);
+
+/* ---- per-level access for parity checks ----
+ * op: 0 y = K_l x; 1 y = R_l x (level l -> l-1, y on level l-1);
+ *     2 y = P_l x (level l-1 -> l, x on level l-1, y on level l);
+ *     3 y = S_l(b = x, w = 0) one smoother sweep from zero;
+ *     4 y = coarse direct solve (level 0 only);
+ *     5 y = V-cycle starting at level l. Device vectors of the level's size. */
+cav_status cav_level_apply(cav_ctx ctx, int level, int op, const double* x, double* y);
+/* Size of level l's grid (cells per side), or 0. */
+int32_t cav_level_N(cav_ctx ctx, int level);
+/* Patch sets of level l copied to host: offsets (n_patches+1, int64) and
+ * unknown indices (sorted ascending inside each patch). Pass NULL dofs to
+ * query the total length through *total. */
+cav_status cav_export_patches(cav_ctx ctx, int level, int64_t* offsets, int32_t* dofs, int64_t* total);
+/* E_E of level l (unscaled, symmetric) as host CSR over the 2N_l^2 velocity
+ * unknowns: rowptr (2N_l^2+1), col, val; NULL col/val queries *nnz. */
+cav_status cav_export_ee(cav_ctx ctx, int level, int64_t* rowptr, int32_t* col, double* val, int64_t* nnz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAVMG_H */

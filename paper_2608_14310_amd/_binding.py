@@ -1,0 +1,274 @@
+"""ctypes binding of libcavmg.so: argument marshalling only.
+
+Every computation happens in the HIP library; this module converts Python /
+numpy / torch arguments into the C structures of include/cavmg.h, passes
+device pointers of contiguous float64 torch tensors, and turns status codes
+into exceptions (warnings are returned in the solve summary).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path() -> str:
+    return os.path.join(HERE, "libcavmg.so")
+
+
+class CAVError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"cavmg status {status}: {msg}")
+        self.status = status
+
+
+CAV_LAW = {"target": 0, "membrane": 1, "beam_closed": 2, "beam_open": 3, "csr": 4}
+FAMILY = {"cav": 0, "vanka": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
+WARN_NOT_CONVERGED, WARN_FLOOR_LIMITED = 100, 101
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("N", C.c_int32), ("n_levels", C.c_int32), ("rho", C.c_double), ("mu", C.c_double),
+                ("dt", C.c_double)]
+
+
+class StructureDesc(C.Structure):
+    _fields_ = [("M", C.c_int32), ("X", C.POINTER(C.c_double)), ("omega", C.POINTER(C.c_double)),
+                ("law", C.c_int32), ("kappa_t", C.c_double), ("kappa_s", C.c_double), ("kappa_b", C.c_double),
+                ("n_segments", C.c_int32), ("seg_start", C.POINTER(C.c_int32)),
+                ("seg_closed", C.POINTER(C.c_int32)), ("seg_ds", C.POINTER(C.c_double)),
+                ("E_nnz", C.c_int32), ("E_rowptr", C.POINTER(C.c_int32)), ("E_col", C.POINTER(C.c_int32)),
+                ("E_val", C.POINTER(C.c_double))]
+
+
+class LevelStats(C.Structure):
+    _fields_ = [("N", C.c_int32), ("n_patches", C.c_int32), ("n_explicit", C.c_int32), ("max_np", C.c_int32),
+                ("avg_np", C.c_double), ("sum_np2", C.c_int64), ("n_touched", C.c_int64), ("ee_nnz", C.c_int64)]
+
+
+class FactorStats(C.Structure):
+    _fields_ = [("n_fp64", C.c_int32), ("n_fp32", C.c_int32), ("max_cond", C.c_double),
+                ("factor_bytes", C.c_int64), ("coarse_cond_est", C.c_double)]
+
+
+class FgmresOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_it", C.c_int32), ("use_learned", C.c_int32),
+                ("history", C.POINTER(C.c_double))]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("est_rel_residual", C.c_double),
+                ("true_rel_residual", C.c_double), ("pressure_mean_removed", C.c_double),
+                ("learned_accepted", C.c_int32), ("learned_rejected", C.c_int32)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "cav_create": ([C.POINTER(_P), C.c_int, _P], C.c_int),
+    "cav_destroy": ([_P], C.c_int),
+    "cav_set_stream": ([_P, _P], C.c_int),
+    "cav_status_string": ([C.c_int], C.c_char_p),
+    "cav_last_error": ([_P], C.c_char_p),
+    "cav_build_operator": ([_P, C.POINTER(GridDesc), C.POINTER(StructureDesc)], C.c_int),
+    "cav_build_cav_patches": ([_P, C.c_int, C.POINTER(LevelStats)], C.c_int),
+    "cav_factor_patches": ([_P, C.c_int, C.c_double, C.POINTER(FactorStats)], C.c_int),
+    "cav_set_smoother": ([_P, C.c_double, C.c_int, C.c_int], C.c_int),
+    "cav_apply_operator": ([_P, _P, _P], C.c_int),
+    "cav_vcycle": ([_P, _P, _P], C.c_int),
+    "cav_fgmres_solve": ([_P, _P, _P, C.POINTER(FgmresOpts), C.POINTER(SolveInfo)], C.c_int),
+    "cav_level_apply": ([_P, C.c_int, C.c_int, _P, _P], C.c_int),
+    "cav_level_N": ([_P, C.c_int], C.c_int32),
+    "cav_export_patches": ([_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
+    "cav_export_ee": ([_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                       C.POINTER(C.c_int64)], C.c_int),
+}
+EXPORTED_SYMBOLS = tuple(_SIGS)
+
+_lib = None
+
+
+def lib():
+    """Load libcavmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build the HIP library first (__graft_entry__.build())")
+        L = C.CDLL(path)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _arr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None and a.size else None
+
+
+def describe_structure(system):
+    """Marshal a workloads.System's structure into StructureDesc (keeps arrays alive)."""
+    X = np.ascontiguousarray(system.markers().ravel(), dtype=np.float64)
+    om = np.ascontiguousarray(system.weights(), dtype=np.float64)
+    segs = system.segments
+    start = np.zeros(len(segs) + 1, dtype=np.int32)
+    start[1:] = np.cumsum([len(s.X) for s in segs])
+    closed = np.array([1 if s.closed else 0 for s in segs], dtype=np.int32)
+    ds = np.array([s.ds for s in segs], dtype=np.float64)
+    k = system.kappa
+    d = StructureDesc()
+    d.M = int(len(om))
+    d.X = _arr(X, C.c_double)
+    d.omega = _arr(om, C.c_double)
+    d.law = CAV_LAW[system.law]
+    d.kappa_t = float(k.get("kappa_t", 0.0))
+    d.kappa_s = float(k.get("kappa_s", 0.0))
+    d.kappa_b = float(k.get("kappa_b", 0.0))
+    d.n_segments = len(segs)
+    d.seg_start = _arr(start, C.c_int32)
+    d.seg_closed = _arr(closed, C.c_int32)
+    d.seg_ds = _arr(ds, C.c_double)
+    return d, (X, om, start, closed, ds)
+
+
+def _dev_ptr(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 tensor on a ROCm device")
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One solver context on one device; all work runs on the current torch stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self._torch = torch
+        self.device = torch.device("cuda", device)
+        self._L = lib()
+        h = C.c_void_p()
+        st = self._L.cav_create(C.byref(h), int(device), self._stream())
+        if st != 0:
+            raise CAVError(st, "cav_create failed (no ROCm device?)")
+        self._h = h
+        self.N = None
+        self.n_levels = None
+
+    def _stream(self):
+        return C.c_void_p(self._torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _check(self, st):
+        if st not in (0, WARN_NOT_CONVERGED, WARN_FLOOR_LIMITED):
+            raise CAVError(st, self._L.cav_last_error(self._h).decode())
+        return st
+
+    def _sync_stream(self):
+        self._L.cav_set_stream(self._h, self._stream())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.cav_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- setup ----
+    def build_operator(self, system) -> None:
+        self._sync_stream()
+        g = GridDesc(system.N, system.n_levels, system.rho, system.mu, system.dt)
+        d, keep = describe_structure(system)
+        self._check(self._L.cav_build_operator(self._h, C.byref(g), C.byref(d)))
+        del keep
+        self.N, self.n_levels = system.N, system.n_levels
+
+    def build_cav_patches(self, family: str = "cav") -> List[Dict]:
+        self._sync_stream()
+        out = (LevelStats * self.n_levels)()
+        self._check(self._L.cav_build_cav_patches(self._h, FAMILY[family], out))
+        return [{f: getattr(o, f) for f, _ in LevelStats._fields_} for o in out]
+
+    def factor_patches(self, precision: str = "fp64", cond_threshold: float = 1e6) -> Dict:
+        self._sync_stream()
+        st = FactorStats()
+        self._check(self._L.cav_factor_patches(self._h, PRECISION[precision], float(cond_threshold), C.byref(st)))
+        return {f: getattr(st, f) for f, _ in FactorStats._fields_}
+
+    def set_smoother(self, alpha: float = 0.7, pre: int = 1, post: int = 1) -> None:
+        self._check(self._L.cav_set_smoother(self._h, float(alpha), int(pre), int(post)))
+
+    def setup(self, system, family="cav", precision="fp64", cond_threshold=1e6, alpha=0.7):
+        self.build_operator(system)
+        stats = self.build_cav_patches(family)
+        fstats = self.factor_patches(precision, cond_threshold)
+        self.set_smoother(alpha)
+        return stats, fstats
+
+    # ---- application ----
+    def n(self, level: Optional[int] = None) -> int:
+        N = self.N if level is None else int(self._L.cav_level_N(self._h, level))
+        return 3 * N * N
+
+    def empty(self, level: Optional[int] = None):
+        return self._torch.empty(self.n(level), dtype=self._torch.float64, device=self.device)
+
+    def apply_operator(self, x, out=None):
+        self._sync_stream()
+        y = self.empty() if out is None else out
+        self._check(self._L.cav_apply_operator(self._h, _dev_ptr(x), _dev_ptr(y)))
+        return y
+
+    def vcycle(self, r, out=None):
+        self._sync_stream()
+        z = self.empty() if out is None else out
+        self._check(self._L.cav_vcycle(self._h, _dev_ptr(r), _dev_ptr(z)))
+        return z
+
+    def level_apply(self, level: int, op: int, x, out_level: Optional[int] = None):
+        self._sync_stream()
+        y = self.empty(level if out_level is None else out_level)
+        self._check(self._L.cav_level_apply(self._h, int(level), int(op), _dev_ptr(x), _dev_ptr(y)))
+        return y
+
+    def fgmres_solve(self, b, rtol: float = 1e-10, max_it: int = 150, out=None, history: bool = True):
+        self._sync_stream()
+        x = self.empty() if out is None else out
+        hist = np.zeros(max_it, dtype=np.float64)
+        o = FgmresOpts(float(rtol), int(max_it), 0, _arr(hist, C.c_double) if history else None)
+        info = SolveInfo()
+        st = self._check(self._L.cav_fgmres_solve(self._h, _dev_ptr(b), _dev_ptr(x), C.byref(o), C.byref(info)))
+        d = {f: getattr(info, f) for f, _ in SolveInfo._fields_}
+        d["status"] = st
+        d["history"] = hist[:info.iterations].copy()
+        return x, d
+
+    # ---- host exports for parity checks ----
+    def export_patches(self, level: int):
+        tot = C.c_int64()
+        self._check(self._L.cav_export_patches(self._h, level, None, None, C.byref(tot)))
+        N = int(self._L.cav_level_N(self._h, level))
+        off = np.zeros(N * N + 1, dtype=np.int64)
+        dofs = np.zeros(tot.value, dtype=np.int32)
+        self._check(self._L.cav_export_patches(self._h, level, _arr(off, C.c_int64), _arr(dofs, C.c_int32),
+                                               C.byref(tot)))
+        return off, dofs
+
+    def export_ee(self, level: int):
+        nnz = C.c_int64()
+        self._check(self._L.cav_export_ee(self._h, level, None, None, None, C.byref(nnz)))
+        N = int(self._L.cav_level_N(self._h, level))
+        rp = np.zeros(2 * N * N + 1, dtype=np.int64)
+        col = np.zeros(nnz.value, dtype=np.int32)
+        val = np.zeros(nnz.value, dtype=np.float64)
+        self._check(self._L.cav_export_ee(self._h, level, _arr(rp, C.c_int64), _arr(col, C.c_int32),
+                                          _arr(val, C.c_double), C.byref(nnz)))
+        return rp, col, val

@@ -1,0 +1,542 @@
+// C ABI: context lifecycle, setup orchestration, V-cycle and FGMRES.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <unordered_set>
+
+#include "cav_internal.hpp"
+
+struct cav_ctx_s {
+  cav::Ctx c;
+  std::unordered_set<void*> live;
+};
+
+namespace cav {
+
+static cav_ctx_s* owner(Ctx& c) { return reinterpret_cast<cav_ctx_s*>(&c); }
+
+void* dev_alloc(Ctx& c, size_t bytes) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 16));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw StatusError(CAV_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  owner(c)->live.insert(p);
+  return p;
+}
+
+void dev_free(Ctx& c, void* p) {
+  if (!p) return;
+  owner(c)->live.erase(p);
+  (void)hipFree(p);
+}
+
+namespace {
+constexpr int TPB = 256;
+
+__global__ void k_axpby(double* __restrict__ y, double a, const double* __restrict__ x, double b, int64_t n) {
+  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (t >= n) return;
+  y[t] = a * x[t] + (b == 0.0 ? 0.0 : b * y[t]);
+}
+
+inline unsigned nblocks(int64_t n) { return unsigned((n + TPB - 1) / TPB); }
+
+template <typename T>
+T* upload(Ctx& c, const std::vector<T>& h) {
+  if (h.empty()) return nullptr;
+  T* d = static_cast<T*>(dev_alloc(c, h.size() * sizeof(T)));
+  CAV_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c.stream));
+  return d;
+}
+
+void free_level(Ctx& c, Level& L) {
+  for (void* p : {(void*)L.d_erow_id, (void*)L.d_erow_ptr, (void*)L.d_ecol, (void*)L.d_eval, (void*)L.d_erow_full,
+                  (void*)L.d_cellflag, (void*)L.d_slot_dof, (void*)L.d_delta, (void*)L.d_t_dof, (void*)L.d_t_inv,
+                  (void*)L.d_t_ptr, (void*)L.d_t_slot, (void*)L.d_std_inv, (void*)L.d_rec64, (void*)L.d_rec32,
+                  (void*)L.d_f64, (void*)L.d_f32, (void*)L.d_b, (void*)L.d_x, (void*)L.d_r, (void*)L.d_z,
+                  (void*)L.d_part})
+    dev_free(c, p);
+  L = Level();
+}
+
+void free_patches(Ctx& c, Level& L) {
+  for (void** p : {(void**)&L.d_cellflag, (void**)&L.d_slot_dof, (void**)&L.d_delta, (void**)&L.d_t_dof,
+                   (void**)&L.d_t_inv, (void**)&L.d_t_ptr, (void**)&L.d_t_slot, (void**)&L.d_std_inv,
+                   (void**)&L.d_rec64, (void**)&L.d_rec32, (void**)&L.d_f64, (void**)&L.d_f32}) {
+    dev_free(c, *p);
+    *p = nullptr;
+  }
+  L.rec64_h.clear();
+  L.rec32_h.clear();
+  L.has_patches = false;
+  L.factored = false;
+}
+
+void vcycle_level(Ctx& c, int l, const double* b, double* x) {
+  hipStream_t s = c.stream;
+  if (l == 0) {
+    launch_coarse_solve(c, b, x, s);
+    return;
+  }
+  Level& L = c.lv[l];
+  const int64_t n = 3 * int64_t(L.N) * L.N;
+  if (c.pre == 0) CAV_HIP(hipMemsetAsync(x, 0, size_t(n) * sizeof(double), s));
+  for (int k = 0; k < c.pre; ++k) launch_smoother(c, L, b, x, k == 0, s);
+  Level& C = c.lv[l - 1];
+  launch_apply_op(L, x, L.d_r, b, s);  // r = b - K x
+  launch_restrict(L, L.d_r, C.d_b, s);
+  vcycle_level(c, l - 1, C.d_b, C.d_x);
+  launch_prolong_add(L, C.d_x, x, s);
+  for (int k = 0; k < c.post; ++k) launch_smoother(c, L, b, x, false, s);
+}
+
+void require(bool ok, cav_status st, const char* msg) {
+  if (!ok) throw StatusError(st, msg);
+}
+
+void ensure_workspace(Ctx& c, int max_it) {
+  if (c.ws_maxit >= max_it && c.d_V) return;
+  for (void* p : {(void*)c.d_V, (void*)c.d_Z, (void*)c.d_w, (void*)c.d_bb, (void*)c.d_h, (void*)c.d_part})
+    dev_free(c, p);
+  if (c.h_pinned) (void)hipHostFree(c.h_pinned);
+  const Level& F = c.lv.back();
+  const int64_t n = 3 * int64_t(F.N) * F.N;
+  c.d_V = static_cast<double*>(dev_alloc(c, size_t(max_it + 1) * n * sizeof(double)));
+  c.d_Z = static_cast<double*>(dev_alloc(c, size_t(max_it) * n * sizeof(double)));
+  c.d_w = static_cast<double*>(dev_alloc(c, size_t(n) * sizeof(double)));
+  c.d_bb = static_cast<double*>(dev_alloc(c, size_t(n) * sizeof(double)));
+  c.d_h = static_cast<double*>(dev_alloc(c, size_t(3 * (max_it + 2)) * sizeof(double)));
+  c.d_part = static_cast<double*>(dev_alloc(c, size_t(dots_blocks(n)) * (max_it + 2) * sizeof(double)));
+  CAV_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.h_pinned), size_t(3 * (max_it + 2)) * sizeof(double),
+                        hipHostMallocDefault));
+  c.ws_maxit = max_it;
+}
+
+// ||x||_2 of a device vector (fixed-order reduction), synchronising.
+double dnorm(Ctx& c, const double* x, int64_t n) {
+  const int nb = dots_blocks(n);
+  launch_dots(x, n, 1, x, n, c.d_part, nb, c.d_h, c.stream);
+  double v = 0;
+  CAV_HIP(hipMemcpyAsync(&v, c.d_h, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  CAV_HIP(hipStreamSynchronize(c.stream));
+  return std::sqrt(v);
+}
+
+}  // namespace
+}  // namespace cav
+
+using namespace cav;
+
+#define API_BEGIN try {
+#define API_END                                                  \
+  }                                                              \
+  catch (const StatusError& e) {                                 \
+    ctx->c.err = e.msg;                                          \
+    return e.st;                                                 \
+  }                                                              \
+  catch (const HipError& e) {                                    \
+    ctx->c.err = e.msg;                                          \
+    return CAV_ERR_HIP;                                          \
+  }                                                              \
+  catch (const std::bad_alloc&) {                                \
+    ctx->c.err = "host allocation failed";                       \
+    return CAV_ERR_OUT_OF_MEMORY;                                \
+  }
+
+extern "C" {
+
+const char* cav_status_string(cav_status s) {
+  switch (s) {
+    case CAV_OK: return "ok";
+    case CAV_ERR_INVALID_ARG: return "invalid argument";
+    case CAV_ERR_OUT_OF_MEMORY: return "out of memory";
+    case CAV_ERR_HIP: return "HIP runtime error";
+    case CAV_ERR_SINGULAR_PATCH: return "singular patch matrix";
+    case CAV_ERR_SINGULAR_COARSE: return "singular coarsest matrix";
+    case CAV_ERR_NOT_BUILT: return "stage called before its prerequisites";
+    case CAV_WARN_NOT_CONVERGED: return "not converged within max_it";
+    case CAV_WARN_FLOOR_LIMITED: return "estimate converged, true residual limited by rounding";
+  }
+  return "unknown status";
+}
+
+const char* cav_last_error(cav_ctx ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+cav_status cav_create(cav_ctx* out, int device, void* stream) {
+  if (!out) return CAV_ERR_INVALID_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CAV_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return CAV_ERR_HIP;
+  cav_ctx ctx = new (std::nothrow) cav_ctx_s();
+  if (!ctx) return CAV_ERR_OUT_OF_MEMORY;
+  ctx->c.device = device;
+  ctx->c.stream = static_cast<hipStream_t>(stream);
+  *out = ctx;
+  return CAV_OK;
+}
+
+cav_status cav_set_stream(cav_ctx ctx, void* stream) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  ctx->c.stream = static_cast<hipStream_t>(stream);
+  return CAV_OK;
+}
+
+cav_status cav_destroy(cav_ctx ctx) {
+  if (!ctx) return CAV_OK;
+  (void)hipSetDevice(ctx->c.device);
+  if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+  for (void* p : ctx->live) (void)hipFree(p);
+  if (ctx->c.h_pinned) (void)hipHostFree(ctx->c.h_pinned);
+  delete ctx;
+  return CAV_OK;
+}
+
+cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* g, const cav_structure_desc* st) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(g != nullptr, CAV_ERR_INVALID_ARG, "grid descriptor is NULL");
+  const int N = g->N, L = g->n_levels;
+  require(N >= 4 && (N & (N - 1)) == 0, CAV_ERR_INVALID_ARG, "N must be a power of two >= 4");
+  require(L >= 1 && L <= 30 && (N >> (L - 1)) >= 4 && ((N >> (L - 1)) << (L - 1)) == N, CAV_ERR_INVALID_ARG,
+          "n_levels must leave a coarsest grid of at least 4 x 4 cells");
+  require(std::isfinite(g->rho) && g->rho > 0 && std::isfinite(g->mu) && g->mu >= 0 && std::isfinite(g->dt) &&
+              g->dt > 0,
+          CAV_ERR_INVALID_ARG, "rho, dt must be positive and mu non-negative");
+  require(int64_t(3) * N * N < (int64_t(1) << 31), CAV_ERR_INVALID_ARG, "grid too large for 32-bit unknown indices");
+  Structure S;
+  std::string err;
+  const cav_status ss = make_structure(st, S, err);
+  if (ss != CAV_OK) throw StatusError(ss, err);
+  CAV_HIP(hipSetDevice(c.device));
+  for (auto& lev : c.lv) free_level(c, lev);
+  c.lv.assign(L, Level());
+  c.built = c.patched = c.factored = false;
+  c.n_levels = L;
+  c.rho = g->rho;
+  c.mu = g->mu;
+  c.dt = g->dt;
+  for (int l = 0; l < L; ++l) {
+    Level& lev = c.lv[l];
+    lev.N = N >> (L - 1 - l);
+    lev.h = 1.0 / lev.N;
+    lev.sc.N = lev.N;
+    lev.sc.diag = c.rho / c.dt + 4.0 * c.mu / (lev.h * lev.h);
+    lev.sc.off = c.mu / (lev.h * lev.h);
+    lev.sc.invh = 1.0 / lev.h;
+  }
+  assemble_ee_finest(N, S, c.lv[L - 1].ee);
+  for (int l = L - 1; l >= 1; --l) galerkin_coarsen(c.lv[l - 1].N, c.lv[l].ee, c.lv[l - 1].ee);
+  for (int l = 0; l < L; ++l) {
+    Level& lev = c.lv[l];
+    const HostCSR& E = lev.ee;
+    require(E.nnz() < (int64_t(1) << 31), CAV_ERR_INVALID_ARG, "E_E too large");
+    std::vector<int32_t> rid, rptr(1, 0), full(E.n + 1);
+    for (int64_t r = 0; r < E.n; ++r) {
+      full[r] = int32_t(E.rowptr[r]);
+      if (E.rowptr[r + 1] > E.rowptr[r]) {
+        rid.push_back(int32_t(r));
+        rptr.push_back(int32_t(E.rowptr[r + 1]));
+      }
+    }
+    full[E.n] = int32_t(E.nnz());
+    std::vector<double> sval(E.val.size());
+    for (size_t k = 0; k < sval.size(); ++k) sval[k] = -c.dt * E.val[k];
+    lev.n_erows = int32_t(rid.size());
+    lev.d_erow_id = upload(c, rid);
+    lev.d_erow_ptr = upload(c, rptr);
+    lev.d_ecol = upload(c, E.col);
+    lev.d_eval = upload(c, sval);
+    lev.d_erow_full = upload(c, full);
+    const int64_t n = 3 * int64_t(lev.N) * lev.N;
+    lev.d_b = static_cast<double*>(dev_alloc(c, n * sizeof(double)));
+    lev.d_x = static_cast<double*>(dev_alloc(c, n * sizeof(double)));
+    lev.d_r = static_cast<double*>(dev_alloc(c, n * sizeof(double)));
+    lev.d_z = static_cast<double*>(dev_alloc(c, n * sizeof(double)));
+    lev.d_part = static_cast<double*>(dev_alloc(c, 1024 * sizeof(double)));
+  }
+  CAV_HIP(hipStreamSynchronize(c.stream));
+  c.built = true;
+  return CAV_OK;
+  API_END
+}
+
+cav_status cav_build_cav_patches(cav_ctx ctx, int family, cav_level_stats* out) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.built, CAV_ERR_NOT_BUILT, "cav_build_operator has not succeeded");
+  require(family == CAV_FAMILY_CAV || family == CAV_FAMILY_VANKA, CAV_ERR_INVALID_ARG, "unknown patch family");
+  CAV_HIP(hipSetDevice(c.device));
+  c.family = family;
+  c.patched = c.factored = false;
+  for (int l = 1; l < c.n_levels; ++l) {
+    Level& L = c.lv[l];
+    free_patches(c, L);
+    build_patches(L.N, L.ee, family, L);
+    L.d_cellflag = upload(c, L.cellflag);
+    L.d_slot_dof = upload(c, L.slot_dof_h);
+    L.d_delta = static_cast<double*>(dev_alloc(c, size_t(std::max<int64_t>(L.n_slots, 1)) * sizeof(double)));
+    L.d_t_dof = upload(c, L.t_dof_h);
+    L.d_t_inv = upload(c, L.t_inv_h);
+    L.d_t_ptr = upload(c, L.t_ptr_h);
+    L.d_t_slot = upload(c, L.t_slot_h);
+    L.has_patches = true;
+  }
+  if (out) {
+    for (int l = 0; l < c.n_levels; ++l) {
+      out[l] = c.lv[l].stats;
+      out[l].N = c.lv[l].N;
+    }
+  }
+  CAV_HIP(hipStreamSynchronize(c.stream));
+  c.patched = true;
+  return CAV_OK;
+  API_END
+}
+
+cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold, cav_factor_stats* out) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.patched, CAV_ERR_NOT_BUILT, "cav_build_cav_patches has not succeeded");
+  require(precision == CAV_PREC_FP64 || precision == CAV_PREC_MIXED, CAV_ERR_INVALID_ARG, "unknown precision");
+  require(!std::isnan(cond_threshold), CAV_ERR_INVALID_ARG, "cond_threshold is NaN");
+  CAV_HIP(hipSetDevice(c.device));
+  c.factored = false;
+  cav_factor_stats st{};
+  for (int l = 1; l < c.n_levels; ++l) factor_level(c, c.lv[l], precision, cond_threshold, &st);
+  factor_coarse(c);
+  st.coarse_cond_est = -1.0;
+  if (out) *out = st;
+  c.factored = true;
+  return CAV_OK;
+  API_END
+}
+
+cav_status cav_set_smoother(cav_ctx ctx, double alpha, int pre, int post) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  if (!std::isfinite(alpha) || pre < 0 || post < 0 || pre + post < 1) {
+    ctx->c.err = "alpha must be finite and pre + post >= 1";
+    return CAV_ERR_INVALID_ARG;
+  }
+  ctx->c.alpha = alpha;
+  ctx->c.pre = pre;
+  ctx->c.post = post;
+  return CAV_OK;
+}
+
+cav_status cav_apply_operator(cav_ctx ctx, const double* x, double* y) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.built, CAV_ERR_NOT_BUILT, "operator not built");
+  require(x && y && x != y, CAV_ERR_INVALID_ARG, "x and y must be distinct device pointers");
+  launch_apply_op(c.lv.back(), x, y, nullptr, c.stream);
+  CAV_HIP(hipGetLastError());
+  return CAV_OK;
+  API_END
+}
+
+cav_status cav_vcycle(cav_ctx ctx, const double* r, double* z) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require(r && z && r != z, CAV_ERR_INVALID_ARG, "r and z must be distinct device pointers");
+  vcycle_level(c, c.n_levels - 1, r, z);
+  CAV_HIP(hipGetLastError());
+  return CAV_OK;
+  API_END
+}
+
+cav_status cav_fgmres_solve(cav_ctx ctx, const double* b, double* x, const cav_fgmres_opts* opts,
+                            cav_solve_info* info) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require(b && x && b != x, CAV_ERR_INVALID_ARG, "b and x must be distinct device pointers");
+  const double rtol = opts ? opts->rtol : 1e-10;
+  const int max_it = opts ? opts->max_it : 150;
+  require(max_it >= 1 && max_it <= 10000 && rtol >= 0.0, CAV_ERR_INVALID_ARG, "bad FGMRES options");
+  hipStream_t s = c.stream;
+  Level& F = c.lv.back();
+  const int64_t n = 3 * int64_t(F.N) * F.N, n2 = int64_t(F.N) * F.N;
+  ensure_workspace(c, max_it);
+  // b' = b with the pressure mean projected out (the range of K_E excludes constant pressure)
+  CAV_HIP(hipMemcpyAsync(c.d_bb, b, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_block_sum(c.d_bb + 2 * n2, n2, c.d_part, c.d_h, s);
+  double psum = 0.0;
+  CAV_HIP(hipMemcpyAsync(&psum, c.d_h, sizeof(double), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipStreamSynchronize(s));
+  const double pmean = psum / double(n2);
+  require(std::isfinite(pmean), CAV_ERR_INVALID_ARG, "right-hand side is not finite");
+  launch_pressure_mean_remove(c.d_bb, F.N, c.d_part, s);
+  CAV_HIP(hipGetLastError());
+  const double beta = dnorm(c, c.d_bb, n);
+  cav_solve_info inf{};
+  if (!(beta > 0.0) || !std::isfinite(beta)) {
+    require(std::isfinite(beta), CAV_ERR_INVALID_ARG, "right-hand side is not finite");
+    CAV_HIP(hipMemsetAsync(x, 0, size_t(n) * sizeof(double), s));
+    CAV_HIP(hipStreamSynchronize(s));
+    inf.converged = 1;
+    if (info) *info = inf;
+    return CAV_OK;
+  }
+  double* V = c.d_V;
+  double* Z = c.d_Z;
+  k_axpby<<<nblocks(n), TPB, 0, s>>>(V, 1.0 / beta, c.d_bb, 0.0, n);
+  const int nbk = dots_blocks(n);
+  std::vector<double> H(size_t(max_it + 1) * max_it, 0.0), cs(max_it), sn(max_it), g(max_it + 1, 0.0);
+  auto Hat = [&](int i, int j) -> double& { return H[size_t(j) * (max_it + 1) + i]; };
+  g[0] = beta;
+  int k = 0;
+  bool conv = false;
+  double est = 1.0;
+  double* hd1 = c.d_h;
+  double* hd2 = c.d_h + (max_it + 2);
+  double* hdn = c.d_h + 2 * (max_it + 2);
+  double* hh = c.h_pinned;
+  for (int j = 0; j < max_it; ++j) {
+    double* vj = V + int64_t(j) * n;
+    double* zj = Z + int64_t(j) * n;
+    vcycle_level(c, c.n_levels - 1, vj, zj);
+    double* w = c.d_w;
+    launch_apply_op(F, zj, w, nullptr, s);
+    // CGS2
+    launch_dots(V, n, j + 1, w, n, c.d_part, nbk, hd1, s);
+    launch_multi_axpy(w, V, n, j + 1, hd1, -1.0, n, s);
+    launch_dots(V, n, j + 1, w, n, c.d_part, nbk, hd2, s);
+    launch_multi_axpy(w, V, n, j + 1, hd2, -1.0, n, s);
+    launch_dots(w, n, 1, w, n, c.d_part, nbk, hdn, s);
+    CAV_HIP(hipMemcpyAsync(hh, c.d_h, size_t(3 * (max_it + 2)) * sizeof(double), hipMemcpyDeviceToHost, s));
+    CAV_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i <= j; ++i) Hat(i, j) = hh[i] + hh[(max_it + 2) + i];
+    const double hn = std::sqrt(hh[2 * (max_it + 2)]);
+    Hat(j + 1, j) = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = Hat(i, j), bq = Hat(i + 1, j);
+      Hat(i, j) = cs[i] * a + sn[i] * bq;
+      Hat(i + 1, j) = -sn[i] * a + cs[i] * bq;
+    }
+    const double rr = std::hypot(Hat(j, j), Hat(j + 1, j));
+    const double cj = rr == 0.0 ? 1.0 : Hat(j, j) / rr, sj = rr == 0.0 ? 0.0 : Hat(j + 1, j) / rr;
+    cs[j] = cj;
+    sn[j] = sj;
+    Hat(j, j) = rr;
+    Hat(j + 1, j) = 0.0;
+    g[j + 1] = -sj * g[j];
+    g[j] = cj * g[j];
+    k = j + 1;
+    est = std::fabs(g[j + 1]) / beta;
+    if (opts && opts->history) opts->history[j] = est;
+    if (!std::isfinite(est)) throw StatusError(CAV_ERR_INVALID_ARG, "non-finite value in FGMRES (check inputs)");
+    if (est <= rtol) { conv = true; break; }
+    if (hn == 0.0) { conv = true; break; }
+    k_axpby<<<nblocks(n), TPB, 0, s>>>(V + int64_t(j + 1) * n, 1.0 / hn, w, 0.0, n);
+  }
+  // y = H_k^{-1} g, x = Z_k y
+  std::vector<double> y(k, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int q = i + 1; q < k; ++q) acc -= Hat(i, q) * y[q];
+    y[i] = acc / Hat(i, i);
+  }
+  CAV_HIP(hipMemcpyAsync(c.d_h, y.data(), size_t(k) * sizeof(double), hipMemcpyHostToDevice, s));
+  CAV_HIP(hipMemsetAsync(x, 0, size_t(n) * sizeof(double), s));
+  launch_multi_axpy(x, Z, n, k, c.d_h, 1.0, n, s);
+  // true residual in FP64
+  launch_apply_op(F, x, c.d_w, c.d_bb, s);
+  const double rn = dnorm(c, c.d_w, n);
+  inf.iterations = k;
+  inf.converged = conv ? 1 : 0;
+  inf.est_rel_residual = est;
+  inf.true_rel_residual = rn / beta;
+  inf.pressure_mean_removed = pmean;
+  if (info) *info = inf;
+  if (!conv) return CAV_WARN_NOT_CONVERGED;
+  if (inf.true_rel_residual > 10.0 * rtol) return CAV_WARN_FLOOR_LIMITED;
+  return CAV_OK;
+  API_END
+}
+
+int32_t cav_level_N(cav_ctx ctx, int level) {
+  if (!ctx || level < 0 || level >= ctx->c.n_levels) return 0;
+  return ctx->c.lv[level].N;
+}
+
+cav_status cav_level_apply(cav_ctx ctx, int level, int op, const double* x, double* y) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.built, CAV_ERR_NOT_BUILT, "operator not built");
+  require(level >= 0 && level < c.n_levels, CAV_ERR_INVALID_ARG, "level out of range");
+  require(x && y && x != y, CAV_ERR_INVALID_ARG, "x and y must be distinct device pointers");
+  Level& L = c.lv[level];
+  hipStream_t s = c.stream;
+  switch (op) {
+    case 0: launch_apply_op(L, x, y, nullptr, s); break;
+    case 1:
+      require(level >= 1, CAV_ERR_INVALID_ARG, "restriction needs level >= 1");
+      launch_restrict(L, x, y, s);
+      break;
+    case 2: {
+      require(level >= 1, CAV_ERR_INVALID_ARG, "prolongation needs level >= 1");
+      const int64_t n = 3 * int64_t(L.N) * L.N;
+      CAV_HIP(hipMemsetAsync(y, 0, size_t(n) * sizeof(double), s));
+      launch_prolong_add(L, x, y, s);
+      break;
+    }
+    case 3:
+      require(c.factored && level >= 1, CAV_ERR_NOT_BUILT, "smoother needs factored patches on level >= 1");
+      launch_smoother(c, L, x, y, true, s);
+      break;
+    case 4:
+      require(c.factored && level == 0, CAV_ERR_INVALID_ARG, "coarse solve is for level 0 after factorisation");
+      launch_coarse_solve(c, x, y, s);
+      break;
+    case 5:
+      require(c.factored, CAV_ERR_NOT_BUILT, "V-cycle needs factored patches");
+      vcycle_level(c, level, x, y);
+      break;
+    default: throw StatusError(CAV_ERR_INVALID_ARG, "unknown op");
+  }
+  CAV_HIP(hipGetLastError());
+  return CAV_OK;
+  API_END
+}
+
+cav_status cav_export_patches(cav_ctx ctx, int level, int64_t* offsets, int32_t* dofs, int64_t* total) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  if (!c.patched || level < 1 || level >= c.n_levels) {
+    c.err = "no patches on this level";
+    return CAV_ERR_NOT_BUILT;
+  }
+  const Level& L = c.lv[level];
+  if (total) *total = int64_t(L.patch_dofs.size());
+  if (offsets) std::memcpy(offsets, L.patch_off.data(), L.patch_off.size() * sizeof(int64_t));
+  if (dofs) std::memcpy(dofs, L.patch_dofs.data(), L.patch_dofs.size() * sizeof(int32_t));
+  return CAV_OK;
+}
+
+cav_status cav_export_ee(cav_ctx ctx, int level, int64_t* rowptr, int32_t* col, double* val, int64_t* nnz) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  if (!c.built || level < 0 || level >= c.n_levels) {
+    c.err = "operator not built or level out of range";
+    return CAV_ERR_NOT_BUILT;
+  }
+  const HostCSR& E = c.lv[level].ee;
+  if (nnz) *nnz = E.nnz();
+  if (rowptr) std::memcpy(rowptr, E.rowptr.data(), E.rowptr.size() * sizeof(int64_t));
+  if (col) std::memcpy(col, E.col.data(), E.col.size() * sizeof(int32_t));
+  if (val) std::memcpy(val, E.val.data(), E.val.size() * sizeof(double));
+  return CAV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,708 @@
+// Patch factorisation (Section 3.3) and the coarsest direct solve (Section 4).
+//
+// Every explicit patch matrix K_p = R_p K_E R_p^T is assembled on the device
+// from the level's stencils and E_E rows, equilibrated by one pass of row and
+// then column max-norm scaling (powers of two, so exact), and inverted in
+// place by Gauss-Jordan elimination with partial pivoting (first maximum on
+// ties). The elimination is blocked: NB pivot columns are processed in LDS,
+// then the remaining columns receive the accumulated transformation as a
+// rank-NB update (one thread per column, coalesced row-major rows).
+// kappa_1 = ||K~||_1 ||K~^{-1}||_1 is exact given the inverse. The stored
+// operator is M_p = C K~^{-1} R (column-major), which equals K_p^{-1}.
+#include <algorithm>
+#include <cmath>
+
+#include "cav_internal.hpp"
+
+namespace cav {
+
+namespace {
+constexpr int FT = 256;  // threads per patch workgroup
+constexpr int NB = 16;   // Gauss-Jordan panel width
+
+__device__ __forceinline__ double pow2_recip(double m) {
+  // 2^(1-e) for m = f 2^e, f in [1/2, 1): maps m into [1, 2) exactly
+  int e;
+  frexp(m, &e);
+  return ldexp(1.0, 1 - e);
+}
+
+// Entry (a, b) of the rediscretised Stokes part of K_E on an N grid (N >= 4).
+__device__ double stencil_entry(int64_t da, int64_t db, const StencilCoef& sc) {
+  const int N = sc.N;
+  const int64_t n2 = int64_t(N) * N;
+  const int ta = int(da / n2), tb = int(db / n2);
+  const int64_t ca = da - ta * n2, cb = db - tb * n2;
+  const int ia = int(ca / N), ja = int(ca % N), ib = int(cb / N), jb = int(cb % N);
+  const int m = N - 1;
+  if (ta < 2 && tb < 2) {
+    if (ta != tb) return 0.0;
+    if (ca == cb) return sc.diag;
+    const int di = (ib - ia) & m, dj = (jb - ja) & m;
+    if ((dj == 0 && (di == 1 || di == m)) || (di == 0 && (dj == 1 || dj == m))) return -sc.off;
+    return 0.0;
+  }
+  if (ta < 2 && tb == 2) {  // G: (p_ij - p_{i-1,j})/h at u_ij, (p_ij - p_{i,j-1})/h at v_ij
+    if (cb == ca) return sc.invh;
+    if (ta == 0 && jb == ja && ib == ((ia - 1) & m)) return -sc.invh;
+    if (ta == 1 && ib == ia && jb == ((ja - 1) & m)) return -sc.invh;
+    return 0.0;
+  }
+  if (ta == 2 && tb < 2) {  // -D: -(u_{i+1,j} - u_ij + v_{i,j+1} - v_ij)/h
+    if (cb == ca) return sc.invh;
+    if (tb == 0 && jb == ja && ib == ((ia + 1) & m)) return -sc.invh;
+    if (tb == 1 && ib == ia && jb == ((ja + 1) & m)) return -sc.invh;
+    return 0.0;
+  }
+  return 0.0;
+}
+
+struct FactorJob {
+  const PatchRec* recs;  // fac = offset into work (row-major n x n)
+  double* work;
+  const int32_t* slot_dof;
+  double* rs;            // per slot
+  double* cs;            // per slot
+  int32_t* sigma;        // per slot: pivots during elimination, column order afterwards
+  double* kappa;         // per patch id
+  int32_t* status;       // per patch id: 0 ok, 1 zero or non-finite pivot
+  StencilCoef sc;
+  const int32_t* erow_full;
+  const int32_t* ecol;
+  const double* eval;    // -dt E_E
+  int use_ee;
+};
+
+__device__ __forceinline__ void argmax_combine(double& v, int& i, double v2, int i2) {
+  if (v2 > v || (v2 == v && i2 < i)) {
+    v = v2;
+    i = i2;
+  }
+}
+
+// Block-wide argmax of (value, index) for FT threads; result valid in all threads.
+__device__ void block_argmax(double& v, int& i, double* sv, int* si) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v2 = __shfl_down(v, o, 64);
+    const int i2 = __shfl_down(i, o, 64);
+    argmax_combine(v, i, v2, i2);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sv[w] = v;
+    si[w] = i;
+  }
+  __syncthreads();
+  v = sv[0];
+  i = si[0];
+  for (int k = 1; k < int(blockDim.x >> 6); ++k) argmax_combine(v, i, sv[k], si[k]);
+  __syncthreads();
+}
+
+__device__ double block_max(double v, double* sv) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sv[w] = v;
+  __syncthreads();
+  double r = sv[0];
+  for (int k = 1; k < int(blockDim.x >> 6); ++k) r = fmax(r, sv[k]);
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
+  extern __shared__ double P[];  // panel, row-major n x NB
+  __shared__ double sv[FT / 64];
+  __shared__ int si[FT / 64];
+  __shared__ int s_flag;
+  __shared__ int s_piv[NB];
+  __shared__ int s_nperm;
+  __shared__ int s_pd[2 * NB], s_ps[2 * NB];
+  const PatchRec rec = J.recs[blockIdx.x];
+  const int n = rec.n;
+  const int tid = threadIdx.x;
+  double* W = J.work + rec.fac;
+  const int32_t* dofs = J.slot_dof + rec.slot;
+  double* rs = J.rs + rec.slot;
+  double* cs = J.cs + rec.slot;
+  int32_t* piv = J.sigma + rec.slot;
+
+  // 1. K_p from the stencils
+  for (int64_t e = tid; e < int64_t(n) * n; e += FT) {
+    const int a = int(e / n), b = int(e % n);
+    W[e] = stencil_entry(dofs[a], dofs[b], J.sc);
+  }
+  __syncthreads();
+  // 2. plus -dt E_E entries whose column lies in the patch (dofs are sorted)
+  if (J.use_ee) {
+    const int64_t nv = 2 * int64_t(J.sc.N) * J.sc.N;
+    for (int a = tid; a < n; a += FT) {
+      const int64_t da = dofs[a];
+      if (da >= nv) continue;
+      for (int q = J.erow_full[da]; q < J.erow_full[da + 1]; ++q) {
+        const int32_t g = J.ecol[q];
+        int lo = 0, hi = n;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (dofs[mid] < g) lo = mid + 1; else hi = mid;
+        }
+        if (lo < n && dofs[lo] == g) W[int64_t(a) * n + lo] += J.eval[q];
+      }
+    }
+  }
+  __syncthreads();
+  // 3. row, then column max-norm equilibration
+  for (int a = tid; a < n; a += FT) {
+    double m = 0.0;
+    for (int b = 0; b < n; ++b) m = fmax(m, fabs(W[int64_t(a) * n + b]));
+    const double s = (m > 0.0 && isfinite(m)) ? pow2_recip(m) : 1.0;
+    rs[a] = s;
+    for (int b = 0; b < n; ++b) W[int64_t(a) * n + b] *= s;
+  }
+  __syncthreads();
+  double colmax = 0.0;
+  for (int b = tid; b < n; b += FT) {
+    double m = 0.0;
+    for (int a = 0; a < n; ++a) m = fmax(m, fabs(W[int64_t(a) * n + b]));
+    const double s = (m > 0.0 && isfinite(m)) ? pow2_recip(m) : 1.0;
+    cs[b] = s;
+    double sum = 0.0;
+    for (int a = 0; a < n; ++a) {
+      const double v = W[int64_t(a) * n + b] * s;
+      W[int64_t(a) * n + b] = v;
+      sum += fabs(v);
+    }
+    colmax = fmax(colmax, sum);
+  }
+  const double norm1 = block_max(colmax, sv);
+  if (tid == 0) s_flag = 0;
+  __syncthreads();
+
+  // 4. blocked in-place Gauss-Jordan with partial pivoting
+  for (int c0 = 0; c0 < n; c0 += NB) {
+    const int nbp = min(NB, n - c0);
+    for (int e = tid; e < n * nbp; e += FT) {
+      const int a = e / nbp, t = e % nbp;
+      P[a * NB + t] = W[int64_t(a) * n + c0 + t];
+    }
+    __syncthreads();
+    for (int t = 0; t < nbp; ++t) {
+      const int c = c0 + t;
+      double bv = -1.0;
+      int bi = n;
+      for (int a = c + tid; a < n; a += FT) argmax_combine(bv, bi, fabs(P[a * NB + t]), a);
+      block_argmax(bv, bi, sv, si);
+      if (!(bv > 0.0) || !isfinite(bv)) {
+        if (tid == 0) s_flag = 1;
+        __syncthreads();
+        break;
+      }
+      if (tid == 0) {
+        s_piv[t] = bi;
+        piv[c] = bi;
+      }
+      if (bi != c && tid < nbp) {
+        const double tmp = P[c * NB + tid];
+        P[c * NB + tid] = P[bi * NB + tid];
+        P[bi * NB + tid] = tmp;
+      }
+      __syncthreads();
+      const double pv = P[c * NB + t];
+      __syncthreads();
+      if (tid < nbp) P[c * NB + tid] = (tid == t ? 1.0 : P[c * NB + tid]) / pv;
+      __syncthreads();
+      for (int a = tid; a < n; a += FT) {
+        if (a == c) continue;
+        const double f = P[a * NB + t];
+        for (int u = 0; u < nbp; ++u)
+          if (u != t) P[a * NB + u] -= f * P[c * NB + u];
+        P[a * NB + t] = -f * P[c * NB + t];
+      }
+      __syncthreads();
+    }
+    if (s_flag) break;
+    for (int e = tid; e < n * nbp; e += FT) {
+      const int a = e / nbp, t = e % nbp;
+      W[int64_t(a) * n + c0 + t] = P[a * NB + t];
+    }
+    // composite row permutation of this panel's interchanges
+    if (tid == 0) {
+      int rows[2 * NB], src[2 * NB], m = 0;
+      auto idx = [&](int r) {
+        for (int k = 0; k < m; ++k)
+          if (rows[k] == r) return k;
+        rows[m] = r;
+        src[m] = r;
+        return m++;
+      };
+      for (int t = 0; t < nbp; ++t) {
+        const int a = idx(c0 + t), b = idx(s_piv[t]);
+        const int tmp = src[a];
+        src[a] = src[b];
+        src[b] = tmp;
+      }
+      int np = 0;
+      for (int k = 0; k < m; ++k)
+        if (src[k] != rows[k]) {
+          s_pd[np] = rows[k];
+          s_ps[np] = src[k];
+          ++np;
+        }
+      s_nperm = np;
+    }
+    __syncthreads();
+    const int np = s_nperm;
+    for (int j = tid; j < n; j += FT) {
+      if (j >= c0 && j < c0 + nbp) continue;
+      double tmp[2 * NB];
+      for (int k = 0; k < np; ++k) tmp[k] = W[int64_t(s_ps[k]) * n + j];
+      for (int k = 0; k < np; ++k) W[int64_t(s_pd[k]) * n + j] = tmp[k];
+    }
+    __syncthreads();
+    // rank-nbp update of the other columns: pivot rows <- P11 y, other rows += P_a y
+    for (int j = tid; j < n; j += FT) {
+      if (j >= c0 && j < c0 + nbp) continue;
+      double y[NB];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) y[t] = (t < nbp) ? W[int64_t(c0 + t) * n + j] : 0.0;
+      for (int a = 0; a < n; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) s += P[a * NB + t] * y[t];
+        if (a >= c0 && a < c0 + nbp)
+          W[int64_t(a) * n + j] = s;
+        else
+          W[int64_t(a) * n + j] += s;
+      }
+    }
+    __syncthreads();
+  }
+  if (s_flag) {
+    if (tid == 0) {
+      J.status[rec.id] = 1;
+      J.kappa[rec.id] = INFINITY;
+    }
+    return;
+  }
+  // 5. kappa_1 = ||K~||_1 ||K~^{-1}||_1 (column sums of the inverse, in any column order)
+  double cm = 0.0;
+  for (int b = tid; b < n; b += FT) {
+    double sum = 0.0;
+    for (int a = 0; a < n; ++a) sum += fabs(W[int64_t(a) * n + b]);
+    cm = fmax(cm, sum);
+  }
+  const double ninv = block_max(cm, sv);
+  if (tid == 0) {
+    J.status[rec.id] = isfinite(ninv) ? 0 : 1;
+    J.kappa[rec.id] = norm1 * ninv;
+  }
+}
+
+// Column order of the inverse: undo the row interchanges on the columns in
+// reverse order, sigma = identity then swap(sigma[c], sigma[piv[c]]) for
+// c = n-1 .. 0. Done in place over the pivot array: since piv[c] >= c, slot c
+// still holds piv[c] when step c runs and slots > c already hold sigma values.
+__global__ void k_sigma(const PatchRec* __restrict__ recs, int count, int32_t* __restrict__ sigma,
+                        const int32_t* __restrict__ status) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const PatchRec rec = recs[p];
+  if (status[rec.id]) return;
+  int32_t* s = sigma + rec.slot;
+  for (int c = rec.n - 1; c >= 0; --c) {
+    const int q = s[c];
+    if (q == c) continue;
+    s[c] = s[q];
+    s[q] = c;
+  }
+}
+
+// M[i + j n] = cs[i] * W[i][sigma[j]] * rs[j]  (= K_p^{-1}), cast to T.
+template <typename T>
+__global__ __launch_bounds__(256) void k_finalize(const PatchRec* __restrict__ wrec, const PatchRec* __restrict__ orec,
+                                                  const double* __restrict__ work, const double* __restrict__ rs,
+                                                  const double* __restrict__ cs, const int32_t* __restrict__ sigma,
+                                                  T* __restrict__ out) {
+  const PatchRec w = wrec[blockIdx.x];
+  const PatchRec o = orec[blockIdx.x];
+  const int n = w.n;
+  const double* W = work + w.fac;
+  const double* r = rs + w.slot;
+  const double* c = cs + w.slot;
+  const int32_t* sg = sigma + w.slot;
+  T* M = out + o.fac;
+  for (int64_t e = threadIdx.x; e < int64_t(n) * n; e += 256) {
+    const int i = int(e % n), j = int(e / n);
+    M[e] = T(c[i] * W[int64_t(i) * n + sg[j]] * r[j]);
+  }
+}
+
+// ------------------------------------------------------ coarsest level ---
+// Bordered matrix B = [[K_0, e], [e^T, 0]] (row-major, size nb = 3 N^2 + 1),
+// inverted by the same blocked Gauss-Jordan, spread over the device.
+__global__ void k_coarse_assemble(double* __restrict__ B, int nb, StencilCoef sc) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= int64_t(nb) * nb) return;
+  const int a = int(e / nb), b = int(e % nb);
+  const int n0 = nb - 1;
+  const int64_t n2 = int64_t(sc.N) * sc.N;
+  double v;
+  if (a < n0 && b < n0) v = stencil_entry(a, b, sc);
+  else if (a == n0 && b == n0) v = 0.0;
+  else if (a == n0) v = (b >= 2 * n2) ? 1.0 : 0.0;
+  else v = (a >= 2 * n2) ? 1.0 : 0.0;
+  B[e] = v;
+}
+
+__global__ void k_coarse_add_ee(double* __restrict__ B, int nb, int64_t nv, const int32_t* __restrict__ rptr,
+                                const int32_t* __restrict__ col, const double* __restrict__ val) {
+  const int64_t a = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (a >= nv) return;
+  for (int q = rptr[a]; q < rptr[a + 1]; ++q) B[a * nb + col[q]] += val[q];
+}
+
+__global__ void k_cp_load(const double* __restrict__ W, int n, int c0, int nbp, double* __restrict__ Pb) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= int64_t(n) * nbp) return;
+  const int a = int(e / nbp), t = int(e % nbp);
+  Pb[int64_t(a) * NB + t] = W[int64_t(a) * n + c0 + t];
+}
+
+// One workgroup: Gauss-Jordan steps on the n x nbp panel held in global memory.
+__global__ __launch_bounds__(1024) void k_cp_panel(double* __restrict__ Pb, int n, int c0, int nbp,
+                                                   int32_t* __restrict__ piv, int32_t* __restrict__ status) {
+  __shared__ double sv[16];
+  __shared__ int si[16];
+  __shared__ int s_flag;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_flag = 0;
+  __syncthreads();
+  for (int t = 0; t < nbp; ++t) {
+    const int c = c0 + t;
+    double bv = -1.0;
+    int bi = n;
+    for (int a = c + tid; a < n; a += 1024) argmax_combine(bv, bi, fabs(Pb[int64_t(a) * NB + t]), a);
+    block_argmax(bv, bi, sv, si);
+    if (!(bv > 0.0) || !isfinite(bv)) {
+      if (tid == 0) status[0] = 1;
+      return;
+    }
+    if (tid == 0) piv[c] = bi;
+    if (bi != c && tid < nbp) {
+      const double tmp = Pb[int64_t(c) * NB + tid];
+      Pb[int64_t(c) * NB + tid] = Pb[int64_t(bi) * NB + tid];
+      Pb[int64_t(bi) * NB + tid] = tmp;
+    }
+    __syncthreads();
+    const double pv = Pb[int64_t(c) * NB + t];
+    __syncthreads();
+    if (tid < nbp) Pb[int64_t(c) * NB + tid] = (tid == t ? 1.0 : Pb[int64_t(c) * NB + tid]) / pv;
+    __syncthreads();
+    for (int a = tid; a < n; a += 1024) {
+      if (a == c) continue;
+      const double f = Pb[int64_t(a) * NB + t];
+      for (int u = 0; u < nbp; ++u)
+        if (u != t) Pb[int64_t(a) * NB + u] -= f * Pb[int64_t(c) * NB + u];
+      Pb[int64_t(a) * NB + t] = -f * Pb[int64_t(c) * NB + t];
+    }
+    __syncthreads();
+  }
+  (void)s_flag;
+}
+
+// Apply this panel's composite row interchange to the other columns and copy
+// the (interchanged) pivot rows into Y (nbp x n).
+__global__ void k_cp_perm(double* __restrict__ W, int n, int c0, int nbp, const int32_t* __restrict__ piv,
+                          double* __restrict__ Y) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n || (j >= c0 && j < c0 + nbp)) return;
+  int rows[2 * NB], src[2 * NB], m = 0;
+  auto idx = [&](int r) {
+    for (int k = 0; k < m; ++k)
+      if (rows[k] == r) return k;
+    rows[m] = r;
+    src[m] = r;
+    return m++;
+  };
+  for (int t = 0; t < nbp; ++t) {
+    const int a = idx(c0 + t), b = idx(piv[c0 + t]);
+    const int tmp = src[a];
+    src[a] = src[b];
+    src[b] = tmp;
+  }
+  double tmp[2 * NB];
+  for (int k = 0; k < m; ++k) tmp[k] = W[int64_t(src[k]) * n + j];
+  for (int k = 0; k < m; ++k) W[int64_t(rows[k]) * n + j] = tmp[k];
+  for (int t = 0; t < nbp; ++t) Y[int64_t(t) * n + j] = W[int64_t(c0 + t) * n + j];
+}
+
+// W[a][j] (+)= sum_t Pb[a][t] Y[t][j]; panel columns receive the panel.
+__global__ __launch_bounds__(256) void k_cp_update(double* __restrict__ W, int n, int c0, int nbp,
+                                                   const double* __restrict__ Pb, const double* __restrict__ Y, int rows_per) {
+  __shared__ double Ps[64 * NB];
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int a0 = blockIdx.y * rows_per;
+  const int a1 = min(n, a0 + rows_per);
+  for (int e = threadIdx.x; e < (a1 - a0) * NB; e += 256) Ps[e] = Pb[int64_t(a0) * NB + e];
+  __syncthreads();
+  if (j >= n) return;
+  if (j >= c0 && j < c0 + nbp) {
+    for (int a = a0; a < a1; ++a) W[int64_t(a) * n + j] = Ps[(a - a0) * NB + (j - c0)];
+    return;
+  }
+  double y[NB];
+#pragma unroll
+  for (int t = 0; t < NB; ++t) y[t] = (t < nbp) ? Y[int64_t(t) * n + j] : 0.0;
+  for (int a = a0; a < a1; ++a) {
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < NB; ++t) s += Ps[(a - a0) * NB + t] * y[t];
+    if (a >= c0 && a < c0 + nbp)
+      W[int64_t(a) * n + j] = s;
+    else
+      W[int64_t(a) * n + j] += s;
+  }
+}
+
+// y[i] = sum_k W[i][k] xb[perm[k]], xb = [b; 0] (perm[k] == n0 selects the 0).
+__global__ __launch_bounds__(256) void k_coarse_gemv(const double* __restrict__ W, int nb, const int32_t* __restrict__ perm,
+                                                     const double* __restrict__ b, double* __restrict__ y) {
+  extern __shared__ double xp[];
+  const int n0 = nb - 1;
+  for (int k = threadIdx.x; k < nb; k += 256) {
+    const int q = perm[k];
+    xp[k] = (q < n0) ? b[q] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n0) return;
+  const double* Wr = W + int64_t(row) * nb;
+  double acc = 0.0;
+  for (int k = lane; k < nb; k += 64) acc += Wr[k] * xp[k];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (lane == 0) y[row] = acc;
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return unsigned((n + t - 1) / t); }
+}  // namespace
+
+// ----------------------------------------------------------------- host ---
+namespace {
+template <typename T>
+T* upload(Ctx& c, const std::vector<T>& h) {
+  if (h.empty()) return nullptr;
+  T* d = static_cast<T*>(dev_alloc(c, h.size() * sizeof(T)));
+  CAV_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c.stream));
+  return d;
+}
+}  // namespace
+
+cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, cav_factor_stats* st) {
+  hipStream_t s = c.stream;
+  const int ne = L.n_exp;
+  // work records: every explicit patch plus the shared standard patch (index ne)
+  std::vector<PatchRec> wrec(ne + 1);
+  int64_t wtot = 0;
+  for (int e = 0; e < ne; ++e) {
+    const int n = int(L.exp_off[e + 1] - L.exp_off[e]);
+    wrec[e] = PatchRec{n, e, L.exp_off[e], wtot};
+    wtot += int64_t(n) * n;
+  }
+  // shared standard patch of cell (0,0) in role order u_00, u_10, v_00, v_01, p_00
+  const int N = L.N;
+  const int64_t n2 = int64_t(N) * N;
+  std::vector<int32_t> std_dofs = {0, int32_t(N), int32_t(n2), int32_t(n2 + 1), int32_t(2 * n2)};
+  const int64_t std_slot = L.n_slots;
+  wrec[ne] = PatchRec{5, ne, std_slot, wtot};
+  wtot += 25;
+  std::vector<int32_t> slot_all(L.slot_dof_h);
+  slot_all.insert(slot_all.end(), std_dofs.begin(), std_dofs.end());
+  const int64_t nslot = int64_t(slot_all.size());
+
+  double* work = static_cast<double*>(dev_alloc(c, size_t(wtot) * sizeof(double)));
+  double* rs = static_cast<double*>(dev_alloc(c, size_t(nslot) * sizeof(double)));
+  double* cs = static_cast<double*>(dev_alloc(c, size_t(nslot) * sizeof(double)));
+  int32_t* sig = static_cast<int32_t*>(dev_alloc(c, size_t(nslot) * sizeof(int32_t)));
+  double* kap = static_cast<double*>(dev_alloc(c, size_t(ne + 1) * sizeof(double)));
+  int32_t* sts = static_cast<int32_t*>(dev_alloc(c, size_t(ne + 1) * sizeof(int32_t)));
+  int32_t* d_slot_all = upload(c, slot_all);
+  // sort work by size (largest first) so the long factorisations start first
+  std::vector<PatchRec> order(wrec);
+  std::stable_sort(order.begin(), order.end(), [](const PatchRec& a, const PatchRec& b) { return a.n > b.n; });
+  PatchRec* d_order = upload(c, order);
+  CAV_HIP(hipMemsetAsync(sts, 0, size_t(ne + 1) * sizeof(int32_t), s));
+
+  FactorJob J{};
+  J.work = work;
+  J.slot_dof = d_slot_all;
+  J.rs = rs;
+  J.cs = cs;
+  J.sigma = sig;
+  J.kappa = kap;
+  J.status = sts;
+  J.sc = L.sc;
+  J.erow_full = L.d_erow_full;
+  J.ecol = L.d_ecol;
+  J.eval = L.d_eval;
+  // explicit patches with E_E, the shared patch without
+  const int nmax = order.empty() ? 5 : order[0].n;
+  const size_t lds = size_t(std::max(nmax, 5)) * NB * sizeof(double);
+  if (lds > 64 * 1024)
+    CAV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_factor),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  int idx_std = -1;
+  for (size_t k = 0; k < order.size(); ++k)
+    if (order[k].id == ne) idx_std = int(k);
+  // launch the explicit patches (all records except the shared one) with E_E
+  std::vector<PatchRec> exp_only, std_only;
+  for (auto& r : order) (r.id == ne ? std_only : exp_only).push_back(r);
+  PatchRec* d_exp = upload(c, exp_only);
+  PatchRec* d_std = upload(c, std_only);
+  (void)idx_std;
+  (void)d_order;
+  if (!exp_only.empty()) {
+    J.recs = d_exp;
+    J.use_ee = 1;
+    k_factor<<<unsigned(exp_only.size()), FT, lds, s>>>(J);
+  }
+  J.recs = d_std;
+  J.use_ee = 0;
+  k_factor<<<1, FT, 5 * NB * sizeof(double), s>>>(J);
+  std::vector<PatchRec> all_rec(exp_only);
+  all_rec.insert(all_rec.end(), std_only.begin(), std_only.end());
+  PatchRec* d_all = upload(c, all_rec);
+  k_sigma<<<nblk(int64_t(all_rec.size()), 64), 64, 0, s>>>(d_all, int(all_rec.size()), sig, sts);
+  CAV_HIP(hipGetLastError());
+
+  std::vector<double> kap_h(ne + 1);
+  std::vector<int32_t> sts_h(ne + 1);
+  CAV_HIP(hipMemcpyAsync(kap_h.data(), kap, kap_h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipMemcpyAsync(sts_h.data(), sts, sts_h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipStreamSynchronize(s));
+  for (int e = 0; e <= ne; ++e)
+    if (sts_h[e]) {
+      throw StatusError(CAV_ERR_SINGULAR_PATCH,
+                        "singular patch on level N=" + std::to_string(N) + " (explicit patch " + std::to_string(e) +
+                            (e == ne ? ", the shared standard patch)" : ")"));
+    }
+  // precision per patch, arena offsets, records sorted by size (descending)
+  std::vector<PatchRec> w64, o64, w32, o32;
+  int64_t a64 = 0, a32 = 0;
+  double maxc = 0.0;
+  for (auto& r : exp_only) {
+    maxc = std::max(maxc, kap_h[r.id]);
+    const bool f32 = precision == CAV_PREC_MIXED && kap_h[r.id] <= cond_threshold;
+    const int64_t sz = int64_t(r.n) * r.n;
+    if (f32) {
+      w32.push_back(r);
+      o32.push_back(PatchRec{r.n, r.id, r.slot, a32});
+      a32 += sz;
+    } else {
+      w64.push_back(r);
+      o64.push_back(PatchRec{r.n, r.id, r.slot, a64});
+      a64 += sz;
+    }
+  }
+  if (L.d_f64) dev_free(c, L.d_f64);
+  if (L.d_f32) dev_free(c, L.d_f32);
+  L.d_f64 = a64 ? static_cast<double*>(dev_alloc(c, size_t(a64) * sizeof(double))) : nullptr;
+  L.d_f32 = a32 ? static_cast<float*>(dev_alloc(c, size_t(a32) * sizeof(float))) : nullptr;
+  if (!L.d_std_inv) L.d_std_inv = static_cast<double*>(dev_alloc(c, 25 * sizeof(double)));
+  if (!w64.empty()) {
+    PatchRec* dw = upload(c, w64);
+    PatchRec* dout = upload(c, o64);
+    k_finalize<double><<<unsigned(w64.size()), 256, 0, s>>>(dw, dout, work, rs, cs, sig, L.d_f64);
+  }
+  if (!w32.empty()) {
+    PatchRec* dw = upload(c, w32);
+    PatchRec* dout = upload(c, o32);
+    k_finalize<float><<<unsigned(w32.size()), 256, 0, s>>>(dw, dout, work, rs, cs, sig, L.d_f32);
+  }
+  {
+    std::vector<PatchRec> so = {PatchRec{5, ne, std_slot, 0}};
+    PatchRec* dout = upload(c, so);
+    k_finalize<double><<<1, 256, 0, s>>>(d_std, dout, work, rs, cs, sig, L.d_std_inv);
+  }
+  CAV_HIP(hipGetLastError());
+  // records the smoother launches, with slots in the level's slot space
+  if (L.d_rec64) dev_free(c, L.d_rec64);
+  if (L.d_rec32) dev_free(c, L.d_rec32);
+  L.rec64_h = o64;
+  L.rec32_h = o32;
+  L.d_rec64 = upload(c, o64);
+  L.d_rec32 = upload(c, o32);
+  CAV_HIP(hipStreamSynchronize(s));
+  // scratch is released once the finalize kernels are done
+  for (void* p : {(void*)work, (void*)rs, (void*)cs, (void*)sig, (void*)kap, (void*)sts, (void*)d_slot_all,
+                  (void*)d_order, (void*)d_exp, (void*)d_std, (void*)d_all})
+    if (p) dev_free(c, p);
+  if (st) {
+    st->n_fp64 += int32_t(w64.size());
+    st->n_fp32 += int32_t(w32.size());
+    st->max_cond = std::max(st->max_cond, maxc);
+    st->factor_bytes += a64 * 8 + a32 * 4;
+  }
+  L.factored = true;
+  return CAV_OK;
+}
+
+cav_status factor_coarse(Ctx& c) {
+  hipStream_t s = c.stream;
+  Level& L = c.lv[0];
+  const int N = L.N;
+  const int64_t n2 = int64_t(N) * N;
+  const int n0 = int(3 * n2);
+  const int nb = n0 + 1;
+  if (c.d_cinv) dev_free(c, c.d_cinv);
+  if (c.d_cperm) dev_free(c, c.d_cperm);
+  c.nc = nb;
+  double* W = static_cast<double*>(dev_alloc(c, size_t(nb) * nb * sizeof(double)));
+  double* Pb = static_cast<double*>(dev_alloc(c, size_t(nb) * NB * sizeof(double)));
+  double* Y = static_cast<double*>(dev_alloc(c, size_t(nb) * NB * sizeof(double)));
+  int32_t* piv = static_cast<int32_t*>(dev_alloc(c, size_t(nb) * sizeof(int32_t)));
+  int32_t* sts = static_cast<int32_t*>(dev_alloc(c, sizeof(int32_t)));
+  CAV_HIP(hipMemsetAsync(sts, 0, sizeof(int32_t), s));
+  k_coarse_assemble<<<nblk(int64_t(nb) * nb), 256, 0, s>>>(W, nb, L.sc);
+  if (L.ee.nnz() > 0)
+    k_coarse_add_ee<<<nblk(2 * n2), 256, 0, s>>>(W, nb, 2 * n2, L.d_erow_full, L.d_ecol, L.d_eval);
+  const int rows_per = 64;
+  for (int c0 = 0; c0 < nb; c0 += NB) {
+    const int nbp = std::min(NB, nb - c0);
+    k_cp_load<<<nblk(int64_t(nb) * nbp), 256, 0, s>>>(W, nb, c0, nbp, Pb);
+    k_cp_panel<<<1, 1024, 0, s>>>(Pb, nb, c0, nbp, piv, sts);
+    k_cp_perm<<<nblk(nb), 256, 0, s>>>(W, nb, c0, nbp, piv, Y);
+    dim3 g(nblk(nb), unsigned((nb + rows_per - 1) / rows_per));
+    k_cp_update<<<g, 256, 0, s>>>(W, nb, c0, nbp, Pb, Y, rows_per);
+  }
+  CAV_HIP(hipGetLastError());
+  int32_t sts_h = 0;
+  std::vector<int32_t> piv_h(nb);
+  CAV_HIP(hipMemcpyAsync(&sts_h, sts, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipMemcpyAsync(piv_h.data(), piv, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipStreamSynchronize(s));
+  dev_free(c, Pb);
+  dev_free(c, Y);
+  dev_free(c, piv);
+  dev_free(c, sts);
+  if (sts_h) {
+    dev_free(c, W);
+    throw StatusError(CAV_ERR_SINGULAR_COARSE, "zero pivot in the coarsest bordered factorisation");
+  }
+  // column j of the inverse is column sigma[j] of W; the GEMV reads x[sigma^-1(k)] at column k
+  std::vector<int32_t> sigma(nb), perm(nb);
+  for (int k = 0; k < nb; ++k) sigma[k] = k;
+  for (int k = nb - 1; k >= 0; --k) std::swap(sigma[k], sigma[piv_h[k]]);
+  for (int j = 0; j < nb; ++j) perm[sigma[j]] = j;
+  c.d_cinv = W;
+  c.d_cperm = upload(c, perm);
+  CAV_HIP(hipStreamSynchronize(s));
+  return CAV_OK;
+}
+
+void launch_coarse_solve(const Ctx& c, const double* b, double* x, hipStream_t s) {
+  const int nb = c.nc;
+  k_coarse_gemv<<<nblk(nb - 1, 4), 256, size_t(nb) * sizeof(double), s>>>(c.d_cinv, nb, c.d_cperm, b, x);
+}
+
+}  // namespace cav

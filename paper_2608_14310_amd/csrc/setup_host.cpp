@@ -1,0 +1,447 @@
+// Host-side setup: force laws, interpolation weights, E_E = S E J on the finest
+// level, Galerkin coarsening, and patch construction (Sections 2-4).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "cav_internal.hpp"
+
+namespace cav {
+
+namespace {
+
+inline int pmod(int64_t a, int n) {
+  int64_t r = a % n;
+  return int(r < 0 ? r + n : r);
+}
+
+// Peskin's four-point kernel (the textbook closed form used in Section 2).
+inline double phi4(double r) {
+  double a = std::fabs(r);
+  if (a <= 1.0) return (3.0 - 2.0 * a + std::sqrt(std::max(1.0 + 4.0 * a - 4.0 * a * a, 0.0))) * 0.125;
+  if (a <= 2.0) return (5.0 - 2.0 * a - std::sqrt(std::max(-7.0 + 12.0 * a - 4.0 * a * a, 0.0))) * 0.125;
+  return 0.0;
+}
+
+// Kernel support of marker k, component c on an N grid: 16 faces and weights.
+// u faces sit at (i, j+1/2) h, v faces at (i+1/2, j) h; the 4x4 box starts at
+// floor(X/h - sigma) - 1 on each axis and every face of the box is kept.
+struct Support {
+  int32_t face[16];
+  double w[16];
+};
+
+inline void support(int N, double x, double y, int c, Support& s) {
+  const double h = 1.0 / N;
+  const double sx = (c == 0) ? 0.0 : 0.5, sy = (c == 0) ? 0.5 : 0.0;
+  const double gx = x / h - sx, gy = y / h - sy;
+  const int64_t i0 = int64_t(std::floor(gx)) - 1, j0 = int64_t(std::floor(gy)) - 1;
+  double wx[4], wy[4];
+  for (int a = 0; a < 4; ++a) {
+    wx[a] = phi4(double(i0 + a) - gx);
+    wy[a] = phi4(double(j0 + a) - gy);
+  }
+  const int64_t base = int64_t(c) * N * N;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      s.face[a * 4 + b] = int32_t(base + int64_t(pmod(i0 + a, N)) * N + pmod(j0 + b, N));
+      s.w[a * 4 + b] = wx[a] * wy[b];
+    }
+}
+
+// Scalar elasticity of one segment, as (row, col, val) triplets in marker indices.
+void segment_law(int law, double kt, double ks, double kb, int m0, int M, bool closed, double ds,
+                 std::map<std::pair<int, int>, double>& acc) {
+  auto add = [&](int a, int b, double v) { acc[{m0 + a, m0 + b}] += v; };
+  auto wrap = [&](int k) { return ((k % M) + M) % M; };
+  if (law == CAV_LAW_TARGET) {
+    for (int k = 0; k < M; ++k) add(k, k, -kt);
+  } else if (law == CAV_LAW_MEMBRANE) {
+    const double c = ks / (ds * ds);
+    for (int k = 0; k < M; ++k) {
+      add(k, wrap(k - 1), c);
+      add(k, k, -2.0 * c);
+      add(k, wrap(k + 1), c);
+    }
+  } else if (law == CAV_LAW_BEAM_CLOSED) {
+    const double c = -kb / (ds * ds * ds * ds);
+    const double st[5] = {1, -4, 6, -4, 1};
+    for (int k = 0; k < M; ++k)
+      for (int o = -2; o <= 2; ++o) add(k, wrap(k + o), c * st[o + 2]);
+  } else if (law == CAV_LAW_BEAM_OPEN) {
+    const double cb = -kb / (ds * ds * ds * ds), cs = -ks / (ds * ds);
+    const double d2[3] = {1, -2, 1};
+    for (int r = 0; r + 2 < M; ++r)               // -(kb/ds^4) D2^T D2
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) add(r + a, r + b, cb * d2[a] * d2[b]);
+    const double d1[2] = {-1, 1};
+    for (int r = 0; r + 1 < M; ++r)               // -(ks/ds^2) D1^T D1
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) add(r + a, r + b, cs * d1[a] * d1[b]);
+  }
+}
+
+}  // namespace
+
+cav_status make_structure(const cav_structure_desc* st, Structure& s, std::string& err) {
+  if (!st) { s.M = 0; s.E.n = 0; s.E.rowptr.assign(1, 0); return CAV_OK; }
+  if (st->M < 0) { err = "M < 0"; return CAV_ERR_INVALID_ARG; }
+  s.M = st->M;
+  const int M = s.M;
+  if (M > 0 && (!st->X || !st->omega)) { err = "X and omega are required when M > 0"; return CAV_ERR_INVALID_ARG; }
+  s.X.assign(st->X, st->X + 2 * size_t(M));
+  s.omega.assign(st->omega, st->omega + size_t(M));
+  for (double v : s.X) if (!std::isfinite(v)) { err = "non-finite marker position"; return CAV_ERR_INVALID_ARG; }
+  for (double v : s.omega) if (!std::isfinite(v)) { err = "non-finite quadrature weight"; return CAV_ERR_INVALID_ARG; }
+  HostCSR& E = s.E;
+  E.n = 2 * int64_t(M);
+  if (st->law == CAV_LAW_CSR) {
+    if (M > 0 && (!st->E_rowptr || !st->E_col || !st->E_val)) { err = "CSR law needs E arrays"; return CAV_ERR_INVALID_ARG; }
+    E.rowptr.resize(E.n + 1);
+    for (int64_t r = 0; r <= E.n; ++r) E.rowptr[r] = st->E_rowptr[r];
+    if (E.rowptr[0] != 0 || E.rowptr[E.n] != st->E_nnz) { err = "E_rowptr inconsistent with E_nnz"; return CAV_ERR_INVALID_ARG; }
+    for (int64_t r = 0; r < E.n; ++r)
+      if (E.rowptr[r + 1] < E.rowptr[r]) { err = "E_rowptr not monotone"; return CAV_ERR_INVALID_ARG; }
+    E.col.assign(st->E_col, st->E_col + st->E_nnz);
+    E.val.assign(st->E_val, st->E_val + st->E_nnz);
+    for (int64_t k = 0; k < st->E_nnz; ++k) {
+      if (E.col[k] < 0 || E.col[k] >= E.n) { err = "E column out of range"; return CAV_ERR_INVALID_ARG; }
+      if (!std::isfinite(E.val[k])) { err = "non-finite E value"; return CAV_ERR_INVALID_ARG; }
+    }
+    // structural symmetry
+    std::vector<std::pair<int, int>> pairs, tr;
+    for (int64_t r = 0; r < E.n; ++r)
+      for (int64_t k = E.rowptr[r]; k < E.rowptr[r + 1]; ++k) {
+        pairs.push_back({int(r), E.col[k]});
+        tr.push_back({E.col[k], int(r)});
+      }
+    std::sort(pairs.begin(), pairs.end());
+    std::sort(tr.begin(), tr.end());
+    pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+    tr.erase(std::unique(tr.begin(), tr.end()), tr.end());
+    if (pairs != tr) { err = "E is not structurally symmetric"; return CAV_ERR_INVALID_ARG; }
+    return CAV_OK;
+  }
+  if (st->law < CAV_LAW_TARGET || st->law > CAV_LAW_BEAM_OPEN) { err = "unknown law"; return CAV_ERR_INVALID_ARG; }
+  if (M > 0 && (st->n_segments < 1 || !st->seg_start || !st->seg_closed || !st->seg_ds)) {
+    err = "segments are required for the built-in laws"; return CAV_ERR_INVALID_ARG;
+  }
+  std::map<std::pair<int, int>, double> acc;
+  if (M > 0) {
+    if (st->seg_start[0] != 0 || st->seg_start[st->n_segments] != M) { err = "seg_start must run from 0 to M"; return CAV_ERR_INVALID_ARG; }
+    for (int g = 0; g < st->n_segments; ++g) {
+      const int m0 = st->seg_start[g], m1 = st->seg_start[g + 1];
+      if (m1 <= m0) { err = "empty segment"; return CAV_ERR_INVALID_ARG; }
+      const bool closed = st->seg_closed[g] != 0;
+      const double ds = st->seg_ds[g];
+      if (!(ds > 0) || !std::isfinite(ds)) { err = "segment spacing must be positive"; return CAV_ERR_INVALID_ARG; }
+      if ((st->law == CAV_LAW_MEMBRANE || st->law == CAV_LAW_BEAM_CLOSED) && !closed) {
+        err = "membrane and closed-beam laws need closed segments"; return CAV_ERR_INVALID_ARG;
+      }
+      if (st->law == CAV_LAW_BEAM_OPEN && closed) { err = "open-beam law needs open segments"; return CAV_ERR_INVALID_ARG; }
+      segment_law(st->law, st->kappa_t, st->kappa_s, st->kappa_b, m0, m1 - m0, closed, ds, acc);
+    }
+  }
+  // interleave the scalar law onto both components
+  std::vector<std::vector<std::pair<int, double>>> rows(M);
+  for (auto& kv : acc) rows[kv.first.first].push_back({kv.first.second, kv.second});
+  E.rowptr.assign(E.n + 1, 0);
+  for (int k = 0; k < M; ++k)
+    for (int c = 0; c < 2; ++c) {
+      const int64_t r = 2 * int64_t(k) + c;
+      for (auto& e : rows[k]) {
+        E.col.push_back(2 * e.first + c);
+        E.val.push_back(e.second);
+      }
+      E.rowptr[r + 1] = int64_t(E.col.size());
+    }
+  for (double v : E.val) if (!std::isfinite(v)) { err = "non-finite E value"; return CAV_ERR_INVALID_ARG; }
+  return CAV_OK;
+}
+
+// E_E = (1/h^2) J^T (W E) J with W = diag(omega) on both components, accumulated
+// row by row with a dense sparse accumulator. Every generated (row, col) pair
+// is kept (structural pattern).
+void assemble_ee_finest(int N, const Structure& s, HostCSR& ee) {
+  const int64_t nv = 2 * int64_t(N) * N;
+  const double h = 1.0 / N, ih2 = 1.0 / (h * h);
+  const int64_t nr = 2 * int64_t(s.M);
+  std::vector<Support> sup(nr);
+  for (int64_t r = 0; r < nr; ++r) support(N, s.X[2 * (r / 2)], s.X[2 * (r / 2) + 1], int(r % 2), sup[r]);
+  // face -> (Lagrangian row, weight), grouped by face with a counting sort
+  std::vector<int64_t> fptr(nv + 1, 0);
+  for (int64_t r = 0; r < nr; ++r)
+    for (int t = 0; t < 16; ++t) fptr[sup[r].face[t] + 1]++;
+  for (int64_t f = 0; f < nv; ++f) fptr[f + 1] += fptr[f];
+  std::vector<int64_t> fr(fptr.back());
+  std::vector<double> fw(fptr.back());
+  {
+    std::vector<int64_t> pos(fptr.begin(), fptr.end() - 1);
+    for (int64_t r = 0; r < nr; ++r)
+      for (int t = 0; t < 16; ++t) {
+        const int64_t q = pos[sup[r].face[t]]++;
+        fr[q] = r;
+        fw[q] = sup[r].w[t];
+      }
+  }
+  ee.n = nv;
+  ee.rowptr.assign(nv + 1, 0);
+  ee.col.clear();
+  ee.val.clear();
+  std::vector<double> acc(nv, 0.0);
+  std::vector<int32_t> mark(nv, -1), touched;
+  touched.reserve(4096);
+  for (int64_t f = 0; f < nv; ++f) {
+    if (fptr[f + 1] > fptr[f]) {
+      touched.clear();
+      for (int64_t q = fptr[f]; q < fptr[f + 1]; ++q) {
+        const int64_t r = fr[q];
+        const double wf = fw[q] * s.omega[r / 2] * ih2;
+        for (int64_t k = s.E.rowptr[r]; k < s.E.rowptr[r + 1]; ++k) {
+          const int64_t r2 = s.E.col[k];
+          const double cf = wf * s.E.val[k];
+          const Support& sg = sup[r2];
+          for (int t = 0; t < 16; ++t) {
+            const int32_t g = sg.face[t];
+            if (mark[g] != int32_t(f)) {
+              mark[g] = int32_t(f);
+              acc[g] = 0.0;
+              touched.push_back(g);
+            }
+            acc[g] += cf * sg.w[t];
+          }
+        }
+      }
+      std::sort(touched.begin(), touched.end());
+      for (int32_t g : touched) {
+        ee.col.push_back(g);
+        ee.val.push_back(acc[g]);
+      }
+    }
+    ee.rowptr[f + 1] = int64_t(ee.col.size());
+  }
+}
+
+namespace {
+// RT0 velocity prolongation stencils between a coarse grid Nc and fine grid 2Nc.
+// pcol: coarse unknown -> (fine unknown, weight); prow: fine -> (coarse, weight).
+inline int pcol(int Nc, int64_t F, int32_t* f, double* w) {
+  const int Nf = 2 * Nc;
+  const int64_t nc2 = int64_t(Nc) * Nc, nf2 = int64_t(Nf) * Nf;
+  if (F < nc2) {
+    const int I = int(F / Nc), J = int(F % Nc);
+    int k = 0;
+    for (int dj = 0; dj < 2; ++dj) {
+      f[k] = int32_t(int64_t(pmod(2 * I, Nf)) * Nf + pmod(2 * J + dj, Nf)); w[k++] = 1.0;
+      f[k] = int32_t(int64_t(pmod(2 * I + 1, Nf)) * Nf + pmod(2 * J + dj, Nf)); w[k++] = 0.5;
+      f[k] = int32_t(int64_t(pmod(2 * I - 1, Nf)) * Nf + pmod(2 * J + dj, Nf)); w[k++] = 0.5;
+    }
+    return k;
+  }
+  const int64_t G = F - nc2;
+  const int I = int(G / Nc), J = int(G % Nc);
+  int k = 0;
+  for (int di = 0; di < 2; ++di) {
+    f[k] = int32_t(nf2 + int64_t(pmod(2 * I + di, Nf)) * Nf + pmod(2 * J, Nf)); w[k++] = 1.0;
+    f[k] = int32_t(nf2 + int64_t(pmod(2 * I + di, Nf)) * Nf + pmod(2 * J + 1, Nf)); w[k++] = 0.5;
+    f[k] = int32_t(nf2 + int64_t(pmod(2 * I + di, Nf)) * Nf + pmod(2 * J - 1, Nf)); w[k++] = 0.5;
+  }
+  return k;
+}
+
+inline int prow(int Nc, int64_t g, int32_t* G, double* w) {
+  const int Nf = 2 * Nc;
+  const int64_t nc2 = int64_t(Nc) * Nc, nf2 = int64_t(Nf) * Nf;
+  if (g < nf2) {
+    const int i = int(g / Nf), j = int(g % Nf);
+    if (i % 2 == 0) { G[0] = int32_t(int64_t(i / 2) * Nc + j / 2); w[0] = 1.0; return 1; }
+    G[0] = int32_t(int64_t((i - 1) / 2) * Nc + j / 2); w[0] = 0.5;
+    G[1] = int32_t(int64_t(pmod((i + 1) / 2, Nc)) * Nc + j / 2); w[1] = 0.5;
+    return 2;
+  }
+  const int64_t q = g - nf2;
+  const int i = int(q / Nf), j = int(q % Nf);
+  if (j % 2 == 0) { G[0] = int32_t(nc2 + int64_t(i / 2) * Nc + j / 2); w[0] = 1.0; return 1; }
+  G[0] = int32_t(nc2 + int64_t(i / 2) * Nc + (j - 1) / 2); w[0] = 0.5;
+  G[1] = int32_t(nc2 + int64_t(i / 2) * Nc + pmod((j + 1) / 2, Nc)); w[1] = 0.5;
+  return 2;
+}
+}  // namespace
+
+// E_E^(l-1) = R E_E^(l) P with R = P^T / 4, row by row (Section 4).
+void galerkin_coarsen(int Nc, const HostCSR& fine, HostCSR& coarse) {
+  const int64_t nvc = 2 * int64_t(Nc) * Nc;
+  coarse.n = nvc;
+  coarse.rowptr.assign(nvc + 1, 0);
+  coarse.col.clear();
+  coarse.val.clear();
+  std::vector<double> acc(nvc, 0.0);
+  std::vector<int64_t> mark(nvc, -1);
+  std::vector<int32_t> touched;
+  int32_t f[6], G[2];
+  double wf[6], wg[2];
+  for (int64_t F = 0; F < nvc; ++F) {
+    const int nf = pcol(Nc, F, f, wf);
+    touched.clear();
+    for (int a = 0; a < nf; ++a) {
+      const int64_t r = f[a];
+      for (int64_t k = fine.rowptr[r]; k < fine.rowptr[r + 1]; ++k) {
+        const double e = 0.25 * wf[a] * fine.val[k];
+        const int ng = prow(Nc, fine.col[k], G, wg);
+        for (int b = 0; b < ng; ++b) {
+          if (mark[G[b]] != F) { mark[G[b]] = F; acc[G[b]] = 0.0; touched.push_back(G[b]); }
+          acc[G[b]] += e * wg[b];
+        }
+      }
+    }
+    std::sort(touched.begin(), touched.end());
+    for (int32_t g : touched) {
+      coarse.col.push_back(g);
+      coarse.val.push_back(acc[g]);
+    }
+    coarse.rowptr[F + 1] = int64_t(coarse.col.size());
+  }
+}
+
+// CAV patch family (Eq. cav_patch_set) on one level, plus the arrays the
+// smoother needs: cell flags, explicit patch slots and the unknown -> slot
+// transpose with 1/cnt weights (Appendix A's partition of unity).
+void build_patches(int N, const HostCSR& ee, int family, Level& L) {
+  const int64_t n2 = int64_t(N) * N, nv = 2 * n2, n = 3 * n2;
+  auto U_of = [&](int i, int j, int32_t* U) {
+    U[0] = int32_t(int64_t(i) * N + j);
+    U[1] = int32_t(int64_t(pmod(i + 1, N)) * N + j);
+    U[2] = int32_t(n2 + int64_t(i) * N + j);
+    U[3] = int32_t(n2 + int64_t(i) * N + pmod(j + 1, N));
+  };
+  auto rowlen = [&](int64_t d) { return ee.rowptr[d + 1] - ee.rowptr[d]; };
+  L.cellflag.assign(n2, 0);
+  L.patch_off.assign(n2 + 1, 0);
+  L.patch_dofs.clear();
+  L.patch_dofs.reserve(size_t(n2) * 5 + 1024);
+  L.exp_cells.clear();
+  L.exp_off.assign(1, 0);
+  L.slot_dof_h.clear();
+  std::vector<int32_t> cmark(n2, -1), dmark(n, -1);
+  std::vector<int32_t> cells, dofs;
+  std::vector<std::vector<int32_t>> covered_by;  // cells covered by each explicit patch
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const int32_t cell = int32_t(int64_t(i) * N + j);
+      int32_t U[4];
+      U_of(i, j, U);
+      bool anyrow = false;
+      for (int k = 0; k < 4; ++k) anyrow |= rowlen(U[k]) > 0;
+      dofs.clear();
+      cells.clear();
+      bool enlarged = false;
+      if (anyrow && family == CAV_FAMILY_CAV) {
+        // U_hat = U plus every velocity coupled to U through E_E (pattern is symmetric)
+        std::vector<int32_t> uhat(U, U + 4);
+        for (int k = 0; k < 4; ++k)
+          for (int64_t q = ee.rowptr[U[k]]; q < ee.rowptr[U[k] + 1]; ++q) {
+            const int32_t w = ee.col[q];
+            if (w != U[0] && w != U[1] && w != U[2] && w != U[3]) { enlarged = true; uhat.push_back(w); }
+          }
+        if (enlarged) {
+          for (int32_t w : uhat) {   // C(w): the two cells whose divergence rows hold w
+            int32_t c2[2];
+            if (w < n2) {
+              const int a = w / N, b = w % N;
+              c2[0] = int32_t(int64_t(pmod(a - 1, N)) * N + b);
+              c2[1] = w;
+            } else {
+              const int32_t q = int32_t(w - n2);
+              const int a = q / N, b = q % N;
+              c2[0] = int32_t(int64_t(a) * N + pmod(b - 1, N));
+              c2[1] = q;
+            }
+            for (int t = 0; t < 2; ++t)
+              if (cmark[c2[t]] != cell) { cmark[c2[t]] = cell; cells.push_back(c2[t]); }
+          }
+          for (int32_t c : cells) {  // V(C): pressure and the four velocities of each cell
+            int32_t Uc[4];
+            U_of(c / N, c % N, Uc);
+            const int32_t pc = int32_t(2 * n2 + c);
+            for (int32_t d : {Uc[0], Uc[1], Uc[2], Uc[3], pc})
+              if (dmark[d] != cell) { dmark[d] = cell; dofs.push_back(d); }
+          }
+        }
+      }
+      if (!enlarged) {
+        dofs.assign(U, U + 4);
+        dofs.push_back(int32_t(2 * n2 + cell));
+        cells.assign(1, cell);
+      }
+      std::sort(dofs.begin(), dofs.end());
+      L.patch_dofs.insert(L.patch_dofs.end(), dofs.begin(), dofs.end());
+      L.patch_off[cell + 1] = int64_t(L.patch_dofs.size());
+      const bool expl = anyrow;  // own factor whenever E_E enters the local matrix
+      if (expl) {
+        L.cellflag[cell] |= 1;
+        L.exp_cells.push_back(cell);
+        L.slot_dof_h.insert(L.slot_dof_h.end(), dofs.begin(), dofs.end());
+        L.exp_off.push_back(int64_t(L.slot_dof_h.size()));
+        covered_by.push_back(cells);
+      }
+    }
+  for (auto& cs : covered_by)
+    for (int32_t c : cs) L.cellflag[c] |= 2;
+  L.n_exp = int32_t(L.exp_cells.size());
+  L.n_slots = int64_t(L.slot_dof_h.size());
+
+  // unknown -> slots transpose (counting sort, slots ascending within each unknown)
+  std::vector<int32_t> nsl(n + 1, 0);
+  for (int32_t d : L.slot_dof_h) nsl[d + 1]++;
+  L.t_dof_h.clear();
+  L.t_ptr_h.assign(1, 0);
+  std::vector<int64_t> start(n, -1);
+  for (int64_t d = 0; d < n; ++d)
+    if (nsl[d + 1] > 0) {
+      start[d] = L.t_ptr_h.back();
+      L.t_dof_h.push_back(int32_t(d));
+      L.t_ptr_h.push_back(L.t_ptr_h.back() + nsl[d + 1]);
+    }
+  L.t_slot_h.assign(L.n_slots, 0);
+  for (int64_t sl = 0; sl < L.n_slots; ++sl) L.t_slot_h[start[L.slot_dof_h[sl]]++] = int32_t(sl);
+  // cnt(d) = explicit patches holding d + shared standard patches holding d
+  L.t_inv_h.resize(L.t_dof_h.size());
+  for (size_t t = 0; t < L.t_dof_h.size(); ++t) {
+    const int32_t d = L.t_dof_h[t];
+    int cnt = L.t_ptr_h[t + 1] - L.t_ptr_h[t];
+    int32_t inc[2];
+    int ninc;
+    if (d < n2) {
+      const int a = d / N, b = d % N;
+      inc[0] = int32_t(int64_t(pmod(a - 1, N)) * N + b); inc[1] = d; ninc = 2;
+    } else if (d < nv) {
+      const int32_t q = int32_t(d - n2);
+      const int a = q / N, b = q % N;
+      inc[0] = int32_t(int64_t(a) * N + pmod(b - 1, N)); inc[1] = q; ninc = 2;
+    } else {
+      inc[0] = int32_t(d - nv); ninc = 1;
+    }
+    for (int k = 0; k < ninc; ++k) cnt += (L.cellflag[inc[k]] & 1) ? 0 : 1;
+    L.t_inv_h[t] = 1.0 / double(cnt);
+  }
+  L.n_touched = int32_t(L.t_dof_h.size());
+
+  // stats
+  cav_level_stats& st = L.stats;
+  st.N = N;
+  st.n_patches = int32_t(n2);
+  st.n_explicit = L.n_exp;
+  st.max_np = 0;
+  st.sum_np2 = 0;
+  for (int64_t c = 0; c < n2; ++c) st.max_np = std::max<int32_t>(st.max_np, int32_t(L.patch_off[c + 1] - L.patch_off[c]));
+  st.avg_np = double(L.patch_dofs.size()) / double(n2);
+  for (int32_t e = 0; e < L.n_exp; ++e) {
+    const int64_t np = L.exp_off[e + 1] - L.exp_off[e];
+    st.sum_np2 += np * np;
+  }
+  st.ee_nnz = ee.nnz();
+  st.n_touched = L.n_touched;
+}
+
+}  // namespace cav

@@ -1,0 +1,149 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances. Stencils, transfers and E_E are the same sums in a different order:
+relative 1e-13 of the largest entry. Local solves use an explicit inverse on
+the GPU and LU solves in the oracle; both are backward stable for the
+equilibrated matrix, so they differ by about kappa_1 * 2^-53 per patch; the
+smoother / V-cycle bound is 64 * max(kappa_1) * 2^-53 (floor 1e-12).
+FGMRES: iteration counts identical, estimate <= 1e-10, true residual and
+solution error against the oracle's bounds (1e-10 relative residual, 1e-8
+relative solution error in FP64).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads
+from oracle import direct, hierarchy, krylov, multigrid
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ALPHA = 0.7
+U = 2.0 ** -53
+
+
+def _solver():
+    from paper_2608_14310_amd import Solver
+    return Solver(0)
+
+
+def _t(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+CASES = {
+    "target32": lambda: workloads.small_target(0),
+    "membrane32": lambda: workloads.membrane_ellipse(32, 3, 1e4, 1),
+    "beam64": lambda: workloads.beam_fibres(64, 4, 1.0, 1e4, seed=0),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def pair(request):
+    s = CASES[request.param]()
+    print(f"[gpu parity] case {request.param} N={s.N} levels={s.n_levels}", flush=True)
+    H = multigrid.Hierarchy(s, alpha=ALPHA)
+    g = _solver()
+    stats, fst = g.setup(s, alpha=ALPHA)
+    yield request.param, s, H, g, stats, fst
+    g.close()
+
+
+def _tol(fst):
+    return max(1e-12, 64 * fst["max_cond"] * U)
+
+
+def test_eulerian_elasticity_matches(pair):
+    name, s, H, g, stats, fst = pair
+    for l, lev in enumerate(H.levels):
+        rp, col, val = g.export_ee(l)
+        n = 2 * lev.N * lev.N
+        G = sp.csr_matrix((val, col, rp), shape=(n, n))
+        P = lev.pattern.tocsr()
+        assert np.array_equal(np.diff(G.indptr), np.diff(P.indptr)), (name, l)
+        assert np.array_equal(G.indices, P.indices), (name, l)
+        d = (G - lev.EE).tocsr()
+        assert (abs(d).max() if d.nnz else 0.0) <= 1e-13 * abs(lev.EE).max(), (name, l)
+
+
+def test_patches_match_exactly(pair):
+    name, s, H, g, stats, fst = pair
+    for l in range(1, len(H.levels)):
+        off, dofs = g.export_patches(l)
+        ps = H.levels[l].patches
+        assert len(off) == len(ps) + 1
+        for c, p in enumerate(ps):
+            assert np.array_equal(dofs[off[c]:off[c + 1]], p), (name, l, c)
+        assert stats[l]["max_np"] == max(len(p) for p in ps)
+
+
+def test_operator_restrict_prolong(pair):
+    name, s, H, g, stats, fst = pair
+    rng = np.random.default_rng(7)
+    for l, lev in enumerate(H.levels):
+        x = rng.standard_normal(lev.K.shape[0])
+        y = _np(g.level_apply(l, 0, _t(x)))
+        assert _rel(y, lev.K @ x) < 1e-13, (name, l)
+        if l >= 1:
+            R, P = H.transfers(l)
+            yr = _np(g.level_apply(l, 1, _t(x), out_level=l - 1))
+            assert _rel(yr, R @ x) < 1e-14
+            xc = rng.standard_normal(H.levels[l - 1].K.shape[0])
+            yp = _np(g.level_apply(l, 2, _t(xc)))
+            assert _rel(yp, P @ xc) < 1e-14
+
+
+def test_smoother_sweep(pair):
+    name, s, H, g, stats, fst = pair
+    rng = np.random.default_rng(8)
+    tol = _tol(fst)
+    for l in range(1, len(H.levels)):
+        b = rng.standard_normal(H.levels[l].K.shape[0])
+        y = _np(g.level_apply(l, 3, _t(b)))
+        ref = H.smooth(l, b, np.zeros_like(b))
+        assert _rel(y, ref) < tol, (name, l, _rel(y, ref), tol)
+
+
+def test_coarse_solve(pair):
+    name, s, H, g, stats, fst = pair
+    b = np.random.default_rng(9).standard_normal(H.levels[0].K.shape[0])
+    N0 = H.levels[0].N
+    b[2 * N0 * N0:] -= b[2 * N0 * N0:].mean()
+    y = _np(g.level_apply(0, 4, _t(b)))
+    ref = H.coarse_solve(b)
+    assert _rel(y, ref) < 1e-10, _rel(y, ref)
+
+
+def test_vcycle(pair):
+    name, s, H, g, stats, fst = pair
+    b = s.b.copy()
+    z = _np(g.vcycle(_t(b)))
+    ref = H.vcycle(b)
+    assert _rel(z, ref) < _tol(fst) * 4, (_rel(z, ref), _tol(fst))
+
+
+def test_fgmres_matches_oracle(pair):
+    name, s, H, g, stats, fst = pair
+    K = H.levels[-1].K
+    res = krylov.fgmres(lambda x: K @ x, H.vcycle, s.b, 1e-10, 150)
+    x, info = g.fgmres_solve(_t(s.b), rtol=1e-10, max_it=150)
+    xg = _np(x)
+    print(f"[gpu parity] {name}: oracle its={res.iterations} gpu its={info['iterations']} "
+          f"est={info['est_rel_residual']:.3e} true={info['true_rel_residual']:.3e}", flush=True)
+    assert info["converged"] == 1
+    assert info["iterations"] == res.iterations
+    true = np.linalg.norm(s.b - K @ xg) / np.linalg.norm(s.b)
+    floor = direct.rounding_floor(K, res.x, s.b)
+    assert true <= max(1e-10, 10 * floor) * 2
+    assert np.linalg.norm(xg - res.x) / np.linalg.norm(res.x) < 1e-8
+    np.testing.assert_allclose(info["history"], res.history, rtol=1e-5, atol=1e-13)
