@@ -59,6 +59,13 @@ enum { CAV_LAW_TARGET = 0, CAV_LAW_MEMBRANE = 1, CAV_LAW_BEAM_CLOSED = 2, CAV_LA
        CAV_LAW_CSR = 4 };
 
 enum { CAV_FAMILY_CAV = 0, CAV_FAMILY_VANKA = 1 };         /* patch families (Section 3) */
+/* Smoothers: ADDITIVE is the weighted additive sweep of Appendix A
+ * (Eq. additive_cav_saddle, Theta = 1/cnt); MULTIPLICATIVE is the
+ * multiplicative Schwarz sweep of Section 3.3 in a coloured order (patches
+ * with E_E entries in greedy colour phases, then the shared standard patches
+ * in 8 phases by (i + 3j) mod 8); patches in one phase are independent, so
+ * the sweep equals the sequential sweep in that order. */
+enum { CAV_SMOOTHER_ADDITIVE = 0, CAV_SMOOTHER_MULTIPLICATIVE = 1 };
 enum { CAV_PREC_FP64 = 0, CAV_PREC_MIXED = 1 };            /* factor storage policy */
 
 typedef struct {
@@ -145,10 +152,12 @@ const char* cav_last_error(cav_ctx ctx);
 cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* grid, const cav_structure_desc* st);
 cav_status cav_build_cav_patches(cav_ctx ctx, int family, cav_level_stats* out);
 cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold, cav_factor_stats* out);
-/* Weighted additive smoother (Appendix A, Eq. additive_cav_saddle):
- * w <- w + alpha sum_p R_p^T Theta_p K_p^{-1} R_p (b - K w), Theta_p = diag(1/cnt),
- * then the mean pressure is removed. pre/post = sweeps per V-cycle leg (1, 1). */
-cav_status cav_set_smoother(cav_ctx ctx, double alpha, int pre, int post);
+/* Smoother choice (kind = CAV_SMOOTHER_*). Additive (Appendix A,
+ * Eq. additive_cav_saddle): w <- w + alpha sum_p R_p^T Theta_p K_p^{-1} R_p (b - K w),
+ * Theta_p = diag(1/cnt). Multiplicative (Section 3.3): for each patch in the
+ * coloured order, w <- w + alpha R_p^T K_p^{-1} R_p (b - K w). Both remove the
+ * mean pressure after the sweep. pre/post = sweeps per V-cycle leg (1, 1). */
+cav_status cav_set_smoother(cav_ctx ctx, int kind, double alpha, int pre, int post);
 
 /* ---- application ---- */
 /* y = K_E x on the finest level (x, y device, 3N^2, must not alias). */
@@ -177,6 +186,43 @@ int32_t cav_level_N(cav_ctx ctx, int level);
  * unknown indices (sorted ascending inside each patch). Pass NULL dofs to
  * query the total length through *total. */
 cav_status cav_export_patches(cav_ctx ctx, int level, int64_t* offsets, int32_t* dofs, int64_t* total);
+/* Multiplicative phases of level l: phases of explicit patches as seed-cell
+ * indices (ptr has n_phases+1 offsets into cells). NULL arrays query the sizes.
+ * The 8 phases of shared standard patches follow them in every sweep. */
+cav_status cav_export_phases(cav_ctx ctx, int level, int32_t* ptr, int32_t* cells, int32_t* n_phases,
+                             int32_t* n_cells);
+
+/* ---- host-only analysis (no device needed) ----
+ * cav_analyze runs the host part of the setup (force law, E_E = S E J,
+ * Galerkin coarsening, patch families, multiplicative phases) exactly as
+ * cav_build_operator + cav_build_cav_patches do, and keeps the result in a
+ * host handle whose levels can be exported like a context's. */
+typedef struct cav_analysis_s* cav_analysis;
+cav_status cav_analyze(const cav_grid_desc* grid, const cav_structure_desc* st, int family, cav_analysis* out);
+cav_status cav_analysis_destroy(cav_analysis a);
+cav_status cav_analysis_export_ee(cav_analysis a, int level, int64_t* rowptr, int32_t* col, double* val,
+                                  int64_t* nnz);
+cav_status cav_analysis_export_patches(cav_analysis a, int level, int64_t* offsets, int32_t* dofs, int64_t* total);
+cav_status cav_analysis_export_phases(cav_analysis a, int level, int32_t* ptr, int32_t* cells, int32_t* n_phases,
+                                      int32_t* n_cells);
+/* per-unknown touched list of level l: unknowns inside explicit patches and 1/cnt */
+cav_status cav_analysis_export_weights(cav_analysis a, int level, int32_t* dofs, double* inv_cnt, int32_t* n_touched);
+
+/* ---- live timing ----
+ * Between cav_kernel_timing(ctx, 1, NULL) and a later call, the library
+ * records HIP events on its stream around every launch of the explicit-patch
+ * GEMV (the smoother's dominant kernel) and around every top-level V-cycle.
+ * A call with out != NULL synchronises the stream and returns the totals
+ * since recording started; every call clears the records; enable = 0 stops. */
+typedef struct {
+  int64_t launches;        /* explicit-patch GEMV launches */
+  double ms;               /* their summed durations */
+  double bytes;            /* their summed algorithmic bytes: sum_p n_p^2 s + 20 n_p */
+  int64_t vcycles;         /* top-level V-cycles */
+  double vcycle_ms;        /* their summed durations */
+} cav_kernel_timing_info;
+cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* out);
+
 /* E_E of level l (unscaled, symmetric) as host CSR over the 2N_l^2 velocity
  * unknowns: rowptr (2N_l^2+1), col, val; NULL col/val queries *nnz. */
 cav_status cav_export_ee(cav_ctx ctx, int level, int64_t* rowptr, int32_t* col, double* val, int64_t* nnz);

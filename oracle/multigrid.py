@@ -33,6 +33,9 @@ class Level:
     inject: Optional[list] = None
     cnt: Optional[np.ndarray] = None
     solvers: Optional[smoothers.PatchSolvers] = None
+    theta: Optional[list] = None
+    phases: Optional[list] = None
+    msolvers: Optional[smoothers.PatchSolvers] = None
 
 
 class Hierarchy:
@@ -88,8 +91,20 @@ class Hierarchy:
             if self.family == "box":
                 return smoothers.restricted_additive_sweep(lev.K, lev.solvers, b, w, self.alpha, lev.N)
             return smoothers.additive_sweep(lev.K, lev.solvers, lev.cnt, b, w, self.alpha, lev.N)
+        if self.smoother == "restricted":
+            if lev.theta is None:
+                lev.theta = smoothers.seed_weights(lev.N, lev.patches)
+            return smoothers.seed_restricted_sweep(lev.K, lev.solvers, lev.theta, b, w, self.alpha, lev.N)
         if self.smoother == "multiplicative":
             return smoothers.multiplicative_sweep(lev.K, lev.solvers, b, w, lev.N, lev.inject)
+        if self.smoother == "coloured":
+            if lev.phases is None:
+                # structural stencil pattern (unit coefficients so no coupling vanishes when mu = 0)
+                stencil = mac.reduced_operator(lev.N, 1.0, 1.0, 1.0, sp.csr_matrix((2 * lev.N ** 2, 2 * lev.N ** 2)))
+                lev.phases = pmod.coloured_order(lev.N, lev.patches, lev.pattern, stencil)
+                order = [c for ph in lev.phases for c in ph]
+                lev.msolvers = smoothers.PatchSolvers(lev.K, [lev.patches[c] for c in order], lev.standard[order])
+            return smoothers.multiplicative_sweep(lev.K, lev.msolvers, b, w, lev.N)
         raise ValueError(self.smoother)
 
     def vcycle(self, b: np.ndarray, l: Optional[int] = None) -> np.ndarray:

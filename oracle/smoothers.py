@@ -129,6 +129,35 @@ def additive_sweep(K, solvers: PatchSolvers, cnt: np.ndarray, b, w, alpha: float
     return remove_mean_pressure(w + alpha * z, N)
 
 
+def seed_weights(N: int, patches) -> list:
+    """Restricted-injection Theta for one-patch-per-cell families (Appendix A
+    names restricted additive injection as the alternative to 1/cnt). Reading:
+    the patch of cell (i,j) injects only into the standard Vanka unknowns of
+    its own cell, V_ij, with weight 1 on p_ij and 1/2 on the four faces (each
+    face belongs to the Vanka patches of its two incident cells), so that
+    sum_i R_i^T Theta_i R_i = I."""
+    n2 = N * N
+    out = []
+    for c, p in enumerate(patches):
+        i, j = divmod(c, N)
+        own = {i * N + j: 0.5, ((i + 1) % N) * N + j: 0.5, n2 + i * N + j: 0.5, n2 + i * N + (j + 1) % N: 0.5,
+               2 * n2 + c: 1.0}
+        out.append(np.array([own.get(int(d), 0.0) for d in p]))
+    return out
+
+
+def seed_restricted_sweep(K, solvers: PatchSolvers, theta, b, w, alpha: float, N: int):
+    """Additive sweep of Eq. additive_cav_saddle with the restricted-injection
+    Theta of `seed_weights`, then mean-pressure removal."""
+    r = b - K @ w
+    deltas = solvers.corrections(r)
+    z = np.zeros_like(w)
+    idx = np.concatenate(solvers.patches)
+    th = np.concatenate(theta).reshape((len(idx),) + (1,) * (w.ndim - 1))
+    np.add.at(z, idx, th * np.concatenate(deltas, axis=0))
+    return remove_mean_pressure(w + alpha * z, N)
+
+
 def restricted_additive_sweep(K, solvers: PatchSolvers, b, w, alpha: float, N: int):
     """Additive sweep with restricted injection (Appendix A's alternative
     choice of Theta): each patch writes only its injection mask."""

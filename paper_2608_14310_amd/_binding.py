@@ -28,6 +28,7 @@ class CAVError(RuntimeError):
 
 CAV_LAW = {"target": 0, "membrane": 1, "beam_closed": 2, "beam_open": 3, "csr": 4}
 FAMILY = {"cav": 0, "vanka": 1}
+SMOOTHER = {"additive": 0, "multiplicative": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
 WARN_NOT_CONVERGED, WARN_FLOOR_LIMITED = 100, 101
 
@@ -67,8 +68,26 @@ class SolveInfo(C.Structure):
                 ("learned_accepted", C.c_int32), ("learned_rejected", C.c_int32)]
 
 
+class KernelTiming(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double), ("vcycles", C.c_int64),
+                ("vcycle_ms", C.c_double)]
+
+
 _P = C.c_void_p
 _SIGS = {
+    "cav_kernel_timing": ([_P, C.c_int, C.POINTER(KernelTiming)], C.c_int),
+    "cav_analyze": ([C.POINTER(GridDesc), C.POINTER(StructureDesc), C.c_int, C.POINTER(_P)], C.c_int),
+    "cav_analysis_destroy": ([_P], C.c_int),
+    "cav_analysis_export_ee": ([_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                C.POINTER(C.c_int64)], C.c_int),
+    "cav_analysis_export_patches": ([_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int64)], C.c_int),
+    "cav_analysis_export_phases": ([_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)], C.c_int),
+    "cav_analysis_export_weights": ([_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_int32)], C.c_int),
+    "cav_export_phases": ([_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                           C.POINTER(C.c_int32)], C.c_int),
     "cav_create": ([C.POINTER(_P), C.c_int, _P], C.c_int),
     "cav_destroy": ([_P], C.c_int),
     "cav_set_stream": ([_P, _P], C.c_int),
@@ -77,7 +96,7 @@ _SIGS = {
     "cav_build_operator": ([_P, C.POINTER(GridDesc), C.POINTER(StructureDesc)], C.c_int),
     "cav_build_cav_patches": ([_P, C.c_int, C.POINTER(LevelStats)], C.c_int),
     "cav_factor_patches": ([_P, C.c_int, C.c_double, C.POINTER(FactorStats)], C.c_int),
-    "cav_set_smoother": ([_P, C.c_double, C.c_int, C.c_int], C.c_int),
+    "cav_set_smoother": ([_P, C.c_int, C.c_double, C.c_int, C.c_int], C.c_int),
     "cav_apply_operator": ([_P, _P, _P], C.c_int),
     "cav_vcycle": ([_P, _P, _P], C.c_int),
     "cav_fgmres_solve": ([_P, _P, _P, C.POINTER(FgmresOpts), C.POINTER(SolveInfo)], C.c_int),
@@ -135,6 +154,74 @@ def describe_structure(system):
     d.seg_closed = _arr(closed, C.c_int32)
     d.seg_ds = _arr(ds, C.c_double)
     return d, (X, om, start, closed, ds)
+
+
+class Analysis:
+    """Host-only setup of one system (no device): E_E per level, patch sets,
+    multiplicative phases and partition-of-unity weights, from libcavmg."""
+
+    def __init__(self, system, family: str = "cav"):
+        self._L = lib()
+        g = GridDesc(system.N, system.n_levels, system.rho, system.mu, system.dt)
+        d, keep = describe_structure(system)
+        h = C.c_void_p()
+        st = self._L.cav_analyze(C.byref(g), C.byref(d), FAMILY[family], C.byref(h))
+        del keep
+        if st != 0:
+            raise CAVError(st, "cav_analyze failed")
+        self._h = h
+        self.N, self.n_levels = system.N, system.n_levels
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.cav_analysis_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_N(self, level):
+        return self.N >> (self.n_levels - 1 - level)
+
+    def ee(self, level):
+        nnz = C.c_int64()
+        self._L.cav_analysis_export_ee(self._h, level, None, None, None, C.byref(nnz))
+        N = self.level_N(level)
+        rp = np.zeros(2 * N * N + 1, dtype=np.int64)
+        col = np.zeros(nnz.value, dtype=np.int32)
+        val = np.zeros(nnz.value, dtype=np.float64)
+        self._L.cav_analysis_export_ee(self._h, level, _arr(rp, C.c_int64), _arr(col, C.c_int32),
+                                       _arr(val, C.c_double), C.byref(nnz))
+        return rp, col, val
+
+    def patches(self, level):
+        tot = C.c_int64()
+        self._L.cav_analysis_export_patches(self._h, level, None, None, C.byref(tot))
+        N = self.level_N(level)
+        off = np.zeros(N * N + 1, dtype=np.int64)
+        dofs = np.zeros(tot.value, dtype=np.int32)
+        self._L.cav_analysis_export_patches(self._h, level, _arr(off, C.c_int64), _arr(dofs, C.c_int32), C.byref(tot))
+        return [dofs[off[c]:off[c + 1]] for c in range(N * N)]
+
+    def phases(self, level):
+        nph, ncell = C.c_int32(), C.c_int32()
+        self._L.cav_analysis_export_phases(self._h, level, None, None, C.byref(nph), C.byref(ncell))
+        ptr = np.zeros(nph.value + 1, dtype=np.int32)
+        cells = np.zeros(ncell.value, dtype=np.int32)
+        self._L.cav_analysis_export_phases(self._h, level, _arr(ptr, C.c_int32), _arr(cells, C.c_int32),
+                                           C.byref(nph), C.byref(ncell))
+        return [cells[ptr[k]:ptr[k + 1]].tolist() for k in range(nph.value)]
+
+    def weights(self, level):
+        nt = C.c_int32()
+        self._L.cav_analysis_export_weights(self._h, level, None, None, C.byref(nt))
+        dofs = np.zeros(nt.value, dtype=np.int32)
+        inv = np.zeros(nt.value, dtype=np.float64)
+        self._L.cav_analysis_export_weights(self._h, level, _arr(dofs, C.c_int32), _arr(inv, C.c_double), C.byref(nt))
+        return dofs, inv
 
 
 def _dev_ptr(t):
@@ -203,14 +290,14 @@ class Solver:
         self._check(self._L.cav_factor_patches(self._h, PRECISION[precision], float(cond_threshold), C.byref(st)))
         return {f: getattr(st, f) for f, _ in FactorStats._fields_}
 
-    def set_smoother(self, alpha: float = 0.7, pre: int = 1, post: int = 1) -> None:
-        self._check(self._L.cav_set_smoother(self._h, float(alpha), int(pre), int(post)))
+    def set_smoother(self, kind: str = "additive", alpha: float = 0.7, pre: int = 1, post: int = 1) -> None:
+        self._check(self._L.cav_set_smoother(self._h, SMOOTHER[kind], float(alpha), int(pre), int(post)))
 
-    def setup(self, system, family="cav", precision="fp64", cond_threshold=1e6, alpha=0.7):
+    def setup(self, system, family="cav", precision="fp64", cond_threshold=1e6, alpha=0.7, smoother="additive"):
         self.build_operator(system)
         stats = self.build_cav_patches(family)
         fstats = self.factor_patches(precision, cond_threshold)
-        self.set_smoother(alpha)
+        self.set_smoother(smoother, alpha)
         return stats, fstats
 
     # ---- application ----
@@ -251,6 +338,16 @@ class Solver:
         d["history"] = hist[:info.iterations].copy()
         return x, d
 
+    def kernel_timing(self, enable: bool) -> Dict:
+        """Start (True) or stop (False) live HIP-event timing of the explicit-patch
+        GEMV and of top-level V-cycles; returns the totals recorded so far."""
+        self._sync_stream()
+        t = KernelTiming()
+        self._check(self._L.cav_kernel_timing(self._h, 1 if enable else 0, C.byref(t)))
+        d = {f: getattr(t, f) for f, _ in KernelTiming._fields_}
+        d["vcycle_ms"] = d["vcycle_ms"] / d["vcycles"] if d["vcycles"] else 0.0
+        return d
+
     # ---- host exports for parity checks ----
     def export_patches(self, level: int):
         tot = C.c_int64()
@@ -261,6 +358,16 @@ class Solver:
         self._check(self._L.cav_export_patches(self._h, level, _arr(off, C.c_int64), _arr(dofs, C.c_int32),
                                                C.byref(tot)))
         return off, dofs
+
+    def export_phases(self, level: int):
+        """Explicit-patch phases of the multiplicative sweep as lists of seed cells."""
+        nph, ncell = C.c_int32(), C.c_int32()
+        self._check(self._L.cav_export_phases(self._h, level, None, None, C.byref(nph), C.byref(ncell)))
+        ptr = np.zeros(nph.value + 1, dtype=np.int32)
+        cells = np.zeros(ncell.value, dtype=np.int32)
+        self._check(self._L.cav_export_phases(self._h, level, _arr(ptr, C.c_int32), _arr(cells, C.c_int32),
+                                              C.byref(nph), C.byref(ncell)))
+        return [cells[ptr[k]:ptr[k + 1]].tolist() for k in range(nph.value)]
 
     def export_ee(self, level: int):
         nnz = C.c_int64()

@@ -33,6 +33,15 @@ void dev_free(Ctx& c, void* p) {
   (void)hipFree(p);
 }
 
+hipEvent_t next_event(Ctx& c) {
+  if (c.ev_used == c.ev_pool.size()) {
+    hipEvent_t e;
+    CAV_HIP(hipEventCreate(&e));
+    c.ev_pool.push_back(e);
+  }
+  return c.ev_pool[c.ev_used++];
+}
+
 namespace {
 constexpr int TPB = 256;
 
@@ -57,7 +66,7 @@ void free_level(Ctx& c, Level& L) {
                   (void*)L.d_cellflag, (void*)L.d_slot_dof, (void*)L.d_delta, (void*)L.d_t_dof, (void*)L.d_t_inv,
                   (void*)L.d_t_ptr, (void*)L.d_t_slot, (void*)L.d_std_inv, (void*)L.d_rec64, (void*)L.d_rec32,
                   (void*)L.d_f64, (void*)L.d_f32, (void*)L.d_b, (void*)L.d_x, (void*)L.d_r, (void*)L.d_z,
-                  (void*)L.d_part})
+                  (void*)L.d_part, (void*)L.d_mrec})
     dev_free(c, p);
   L = Level();
 }
@@ -65,7 +74,8 @@ void free_level(Ctx& c, Level& L) {
 void free_patches(Ctx& c, Level& L) {
   for (void** p : {(void**)&L.d_cellflag, (void**)&L.d_slot_dof, (void**)&L.d_delta, (void**)&L.d_t_dof,
                    (void**)&L.d_t_inv, (void**)&L.d_t_ptr, (void**)&L.d_t_slot, (void**)&L.d_std_inv,
-                   (void**)&L.d_rec64, (void**)&L.d_rec32, (void**)&L.d_f64, (void**)&L.d_f32}) {
+                   (void**)&L.d_rec64, (void**)&L.d_rec32, (void**)&L.d_f64, (void**)&L.d_f32,
+                   (void**)&L.d_mrec}) {
     dev_free(c, *p);
     *p = nullptr;
   }
@@ -97,13 +107,31 @@ void require(bool ok, cav_status st, const char* msg) {
   if (!ok) throw StatusError(st, msg);
 }
 
+// Top-level V-cycle on the finest level, timed when live timing is on.
+void vcycle_top(Ctx& c, const double* r, double* z) {
+  int start = -1;
+  if (c.timing) {
+    hipEvent_t e = next_event(c);
+    start = int(c.ev_used - 1);
+    CAV_HIP(hipEventRecord(e, c.stream));
+  }
+  vcycle_level(c, c.n_levels - 1, r, z);
+  if (c.timing) {
+    hipEvent_t e = next_event(c);
+    c.vc_marks.push_back({start, int(c.ev_used - 1)});
+    CAV_HIP(hipEventRecord(e, c.stream));
+  }
+}
+
 void ensure_workspace(Ctx& c, int max_it) {
-  if (c.ws_maxit >= max_it && c.d_V) return;
+  const Level& F = c.lv.back();
+  const int64_t n = 3 * int64_t(F.N) * F.N;
+  if (c.ws_maxit >= max_it && c.ws_n == n && c.d_V) return;
   for (void* p : {(void*)c.d_V, (void*)c.d_Z, (void*)c.d_w, (void*)c.d_bb, (void*)c.d_h, (void*)c.d_part})
     dev_free(c, p);
   if (c.h_pinned) (void)hipHostFree(c.h_pinned);
-  const Level& F = c.lv.back();
-  const int64_t n = 3 * int64_t(F.N) * F.N;
+  c.h_pinned = nullptr;
+  c.ws_n = n;
   c.d_V = static_cast<double*>(dev_alloc(c, size_t(max_it + 1) * n * sizeof(double)));
   c.d_Z = static_cast<double*>(dev_alloc(c, size_t(max_it) * n * sizeof(double)));
   c.d_w = static_cast<double*>(dev_alloc(c, size_t(n) * sizeof(double)));
@@ -190,6 +218,7 @@ cav_status cav_destroy(cav_ctx ctx) {
   if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
   for (void* p : ctx->live) (void)hipFree(p);
   if (ctx->c.h_pinned) (void)hipHostFree(ctx->c.h_pinned);
+  for (hipEvent_t e : ctx->c.ev_pool) (void)hipEventDestroy(e);
   delete ctx;
   return CAV_OK;
 }
@@ -317,12 +346,14 @@ cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold,
   API_END
 }
 
-cav_status cav_set_smoother(cav_ctx ctx, double alpha, int pre, int post) {
+cav_status cav_set_smoother(cav_ctx ctx, int kind, double alpha, int pre, int post) {
   if (!ctx) return CAV_ERR_INVALID_ARG;
-  if (!std::isfinite(alpha) || pre < 0 || post < 0 || pre + post < 1) {
-    ctx->c.err = "alpha must be finite and pre + post >= 1";
+  if (!std::isfinite(alpha) || pre < 0 || post < 0 || pre + post < 1 ||
+      (kind != CAV_SMOOTHER_ADDITIVE && kind != CAV_SMOOTHER_MULTIPLICATIVE)) {
+    ctx->c.err = "unknown smoother kind, or alpha not finite, or pre + post < 1";
     return CAV_ERR_INVALID_ARG;
   }
+  ctx->c.smoother = kind;
   ctx->c.alpha = alpha;
   ctx->c.pre = pre;
   ctx->c.post = post;
@@ -347,7 +378,7 @@ cav_status cav_vcycle(cav_ctx ctx, const double* r, double* z) {
   API_BEGIN
   require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
   require(r && z && r != z, CAV_ERR_INVALID_ARG, "r and z must be distinct device pointers");
-  vcycle_level(c, c.n_levels - 1, r, z);
+  vcycle_top(c, r, z);
   CAV_HIP(hipGetLastError());
   return CAV_OK;
   API_END
@@ -404,7 +435,7 @@ cav_status cav_fgmres_solve(cav_ctx ctx, const double* b, double* x, const cav_f
   for (int j = 0; j < max_it; ++j) {
     double* vj = V + int64_t(j) * n;
     double* zj = Z + int64_t(j) * n;
-    vcycle_level(c, c.n_levels - 1, vj, zj);
+    vcycle_top(c, vj, zj);
     double* w = c.d_w;
     launch_apply_op(F, zj, w, nullptr, s);
     // CGS2
@@ -522,6 +553,52 @@ cav_status cav_export_patches(cav_ctx ctx, int level, int64_t* offsets, int32_t*
   if (offsets) std::memcpy(offsets, L.patch_off.data(), L.patch_off.size() * sizeof(int64_t));
   if (dofs) std::memcpy(dofs, L.patch_dofs.data(), L.patch_dofs.size() * sizeof(int32_t));
   return CAV_OK;
+}
+
+cav_status cav_export_phases(cav_ctx ctx, int level, int32_t* ptr, int32_t* cells, int32_t* n_phases,
+                             int32_t* n_cells) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  if (!c.patched || level < 1 || level >= c.n_levels) {
+    c.err = "no patches on this level";
+    return CAV_ERR_NOT_BUILT;
+  }
+  const Level& L = c.lv[level];
+  if (n_phases) *n_phases = int32_t(L.ph_ptr.size()) - 1;
+  if (n_cells) *n_cells = int32_t(L.ph_exp.size());
+  if (ptr) std::memcpy(ptr, L.ph_ptr.data(), L.ph_ptr.size() * sizeof(int32_t));
+  if (cells)
+    for (size_t k = 0; k < L.ph_exp.size(); ++k) cells[k] = L.exp_cells[L.ph_exp[k]];
+  return CAV_OK;
+}
+
+cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* out) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  if (out) {
+    *out = cav_kernel_timing_info{};
+    if (!c.kt_marks.empty() || !c.vc_marks.empty()) CAV_HIP(hipStreamSynchronize(c.stream));
+    for (auto& m : c.kt_marks) {
+      float ms = 0.f;
+      CAV_HIP(hipEventElapsedTime(&ms, c.ev_pool[m.first], c.ev_pool[m.first + 1]));
+      out->launches += 1;
+      out->ms += ms;
+      out->bytes += m.second;
+    }
+    for (auto& m : c.vc_marks) {
+      float ms = 0.f;
+      CAV_HIP(hipEventElapsedTime(&ms, c.ev_pool[m.first], c.ev_pool[m.second]));
+      out->vcycles += 1;
+      out->vcycle_ms += ms;
+    }
+  }
+  c.kt_marks.clear();
+  c.vc_marks.clear();
+  c.ev_used = 0;
+  c.timing = enable != 0;
+  return CAV_OK;
+  API_END
 }
 
 cav_status cav_export_ee(cav_ctx ctx, int level, int64_t* rowptr, int32_t* col, double* val, int64_t* nnz) {

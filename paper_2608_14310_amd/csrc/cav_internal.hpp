@@ -28,6 +28,14 @@ struct PatchRec {
   int64_t fac;      // element offset into the factor arena of its precision
 };
 
+// An explicit patch in a multiplicative phase: precision picks the arena.
+struct MultRec {
+  int32_t n;
+  int32_t f32;      // 1: factor in the FP32 arena
+  int64_t slot;
+  int64_t fac;
+};
+
 // Stencil coefficients of one level's rediscretised Stokes part.
 struct StencilCoef {
   int N;
@@ -72,6 +80,13 @@ struct Level {
   int32_t* d_t_ptr = nullptr;
   int32_t* d_t_slot = nullptr;
   cav_level_stats stats{};
+  // multiplicative sweep: explicit patches in colour phases
+  std::vector<int32_t> ph_ptr;            // n_phases + 1 offsets into ph_exp
+  std::vector<int32_t> ph_exp;            // explicit patch ids, phase-major
+  MultRec* d_mrec = nullptr;              // records in ph_exp order
+  int32_t mrec_max_n = 0;
+  std::vector<double> ph_bytes;           // algorithmic bytes of each phase launch
+  size_t mx_lds = 0;                      // dynamic LDS of the phase kernel
 
   // factors
   bool factored = false;
@@ -81,6 +96,7 @@ struct Level {
   PatchRec* d_rec32 = nullptr;
   double* d_f64 = nullptr;
   float* d_f32 = nullptr;
+  double bytes64 = 0, bytes32 = 0;        // algorithmic bytes of one GEMV launch per precision
 
   // per-level vectors (3 N^2)
   double *d_b = nullptr, *d_x = nullptr, *d_r = nullptr, *d_z = nullptr;
@@ -98,17 +114,39 @@ struct Ctx {
   int family = CAV_FAMILY_CAV;
   double alpha = 0.7;
   int pre = 1, post = 1;
+  int smoother = CAV_SMOOTHER_ADDITIVE;
   // coarsest bordered inverse (nb x nb, column-major) and its column permutation
   int nc = 0;                              // bordered size
   double* d_cinv = nullptr;
   int32_t* d_cperm = nullptr;
   // FGMRES workspace
   int ws_maxit = 0;
+  int64_t ws_n = 0;  // vector length the workspace was sized for
   double *d_V = nullptr, *d_Z = nullptr, *d_w = nullptr, *d_bb = nullptr;
   double *d_h = nullptr, *d_part = nullptr;
   double* h_pinned = nullptr;
   std::vector<void*> allocs;
+  // live timing of the explicit-patch GEMV and of whole V-cycles (HIP events)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, double>> kt_marks;   // (event index of the start, bytes)
+  std::vector<std::pair<int, int>> vc_marks;      // event indices around each V-cycle
 };
+
+hipEvent_t next_event(Ctx& c);
+inline void timing_begin(Ctx& c, hipStream_t s) {
+  if (!c.timing) return;
+  hipEvent_t e = next_event(c);
+  c.kt_marks.push_back({int(c.ev_used - 1), 0.0});
+  (void)hipEventRecord(e, s);
+}
+inline void timing_end(Ctx& c, hipStream_t s, double bytes) {
+  if (!c.timing) return;
+  hipEvent_t e = next_event(c);
+  c.kt_marks.back().second = bytes;
+  (void)hipEventRecord(e, s);
+}
 
 // ---- host setup (setup_host.cpp) ----
 struct Structure {
@@ -126,6 +164,9 @@ void launch_apply_op(const Level& L, const double* x, double* y, const double* b
 void launch_restrict(const Level& Lf, const double* rf, double* bc, hipStream_t s);
 void launch_prolong_add(const Level& Lf, const double* xc, double* xf, hipStream_t s);
 void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
+void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
+void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+void colour_explicit(int N, const HostCSR& ee, Level& L);
 void launch_coarse_solve(const Ctx& c, const double* b, double* x, hipStream_t s);
 cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, cav_factor_stats* st);
 cav_status factor_coarse(Ctx& c);

@@ -11,6 +11,7 @@
 // operator is M_p = C K~^{-1} R (column-major), which equals K_p^{-1}.
 #include <algorithm>
 #include <cmath>
+#include <utility>
 
 #include "cav_internal.hpp"
 
@@ -181,9 +182,10 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
   // 4. blocked in-place Gauss-Jordan with partial pivoting
   for (int c0 = 0; c0 < n; c0 += NB) {
     const int nbp = min(NB, n - c0);
-    for (int e = tid; e < n * nbp; e += FT) {
-      const int a = e / nbp, t = e % nbp;
-      P[a * NB + t] = W[int64_t(a) * n + c0 + t];
+    // columns past nbp stay zero: the rank-NB update below reads all NB of them
+    for (int e = tid; e < n * NB; e += FT) {
+      const int a = e / NB, t = e % NB;
+      P[e] = t < nbp ? W[int64_t(a) * n + c0 + t] : 0.0;
     }
     __syncthreads();
     for (int t = 0; t < nbp; ++t) {
@@ -225,38 +227,16 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
       const int a = e / nbp, t = e % nbp;
       W[int64_t(a) * n + c0 + t] = P[a * NB + t];
     }
-    // composite row permutation of this panel's interchanges
-    if (tid == 0) {
-      int rows[2 * NB], src[2 * NB], m = 0;
-      auto idx = [&](int r) {
-        for (int k = 0; k < m; ++k)
-          if (rows[k] == r) return k;
-        rows[m] = r;
-        src[m] = r;
-        return m++;
-      };
-      for (int t = 0; t < nbp; ++t) {
-        const int a = idx(c0 + t), b = idx(s_piv[t]);
-        const int tmp = src[a];
-        src[a] = src[b];
-        src[b] = tmp;
-      }
-      int np = 0;
-      for (int k = 0; k < m; ++k)
-        if (src[k] != rows[k]) {
-          s_pd[np] = rows[k];
-          s_ps[np] = src[k];
-          ++np;
-        }
-      s_nperm = np;
-    }
-    __syncthreads();
-    const int np = s_nperm;
+    // this panel's row interchanges, in order, on the other columns (one thread per column)
     for (int j = tid; j < n; j += FT) {
       if (j >= c0 && j < c0 + nbp) continue;
-      double tmp[2 * NB];
-      for (int k = 0; k < np; ++k) tmp[k] = W[int64_t(s_ps[k]) * n + j];
-      for (int k = 0; k < np; ++k) W[int64_t(s_pd[k]) * n + j] = tmp[k];
+      for (int t = 0; t < nbp; ++t) {
+        const int r = s_piv[t];
+        if (r == c0 + t) continue;
+        const double tmp = W[int64_t(c0 + t) * n + j];
+        W[int64_t(c0 + t) * n + j] = W[int64_t(r) * n + j];
+        W[int64_t(r) * n + j] = tmp;
+      }
     }
     __syncthreads();
     // rank-nbp update of the other columns: pivot rows <- P11 y, other rows += P_a y
@@ -338,6 +318,10 @@ __global__ __launch_bounds__(256) void k_finalize(const PatchRec* __restrict__ w
 }
 
 // ------------------------------------------------------ coarsest level ---
+// Panel width of the coarse factorisation: 8 keeps four rows per thread in
+// registers for bordered sizes up to 4096.
+constexpr int CNB = 8;
+
 // Bordered matrix B = [[K_0, e], [e^T, 0]] (row-major, size nb = 3 N^2 + 1),
 // inverted by the same blocked Gauss-Jordan, spread over the device.
 __global__ void k_coarse_assemble(double* __restrict__ B, int nb, StencilCoef sc) {
@@ -365,49 +349,107 @@ __global__ void k_cp_load(const double* __restrict__ W, int n, int c0, int nbp, 
   const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (e >= int64_t(n) * nbp) return;
   const int a = int(e / nbp), t = int(e % nbp);
-  Pb[int64_t(a) * NB + t] = W[int64_t(a) * n + c0 + t];
+  Pb[int64_t(a) * CNB + t] = W[int64_t(a) * n + c0 + t];
 }
 
-// One workgroup: Gauss-Jordan steps on the n x nbp panel held in global memory.
-__global__ __launch_bounds__(1024) void k_cp_panel(double* __restrict__ Pb, int n, int c0, int nbp,
-                                                   int32_t* __restrict__ piv, int32_t* __restrict__ status) {
+// One workgroup of 1024 threads: Gauss-Jordan steps on the n x nbp panel,
+// held in registers (thread t owns rows t, t + 1024, ...). Reads the panel
+// columns of W, leaves the eliminated panel in Pb (row-major, CNB wide) and
+// the pivot rows in piv.
+// One Gauss-Jordan step on the register panel for the compile-time column T.
+template <int RPT, int T>
+__device__ __forceinline__ void cp_step(double (&P)[RPT][CNB], int c0, int nbp, int n, double* sv, int* si,
+                                        double* rowC, double* rowP, int32_t* piv, int& bad) {
+  if (T >= nbp || bad) return;  // both uniform across the workgroup
+  const int tid = threadIdx.x;
+  const int c = c0 + T;
+  double bv = -1.0;
+  int bi = n;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int a = tid + 1024 * k;
+    if (a >= c && a < n) argmax_combine(bv, bi, fabs(P[k][T]), a);
+  }
+  block_argmax(bv, bi, sv, si);
+  if (!(bv > 0.0) || !isfinite(bv)) {
+    bad = 1;
+    return;
+  }
+  if (tid == 0) piv[c] = bi;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int a = tid + 1024 * k;
+    if (a == c)
+#pragma unroll
+      for (int u = 0; u < CNB; ++u) rowC[u] = P[k][u];
+    if (a == bi)
+#pragma unroll
+      for (int u = 0; u < CNB; ++u) rowP[u] = P[k][u];
+  }
+  __syncthreads();
+  // after the interchange row c holds old row bi, scaled by its pivot
+  const double pv = rowP[T];
+  auto prow = [&](int u) { return (u == T ? 1.0 : rowP[u]) / pv; };
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int a = tid + 1024 * k;
+    if (a >= n) continue;
+    if (a == c) {
+#pragma unroll
+      for (int u = 0; u < CNB; ++u) P[k][u] = prow(u);
+      continue;
+    }
+    if (a == bi)
+#pragma unroll
+      for (int u = 0; u < CNB; ++u) P[k][u] = rowC[u];
+    const double f = P[k][T];
+#pragma unroll
+    for (int u = 0; u < CNB; ++u)
+      if (u != T) P[k][u] -= f * prow(u);
+    P[k][T] = -f * prow(T);
+  }
+  __syncthreads();
+}
+
+template <int RPT, int... Ts>
+__device__ __forceinline__ void cp_steps(double (&P)[RPT][CNB], int c0, int nbp, int n, double* sv, int* si,
+                                         double* rowC, double* rowP, int32_t* piv, int& bad,
+                                         std::integer_sequence<int, Ts...>) {
+  (cp_step<RPT, Ts>(P, c0, nbp, n, sv, si, rowC, rowP, piv, bad), ...);
+}
+
+// One workgroup of 1024 threads: Gauss-Jordan steps on the n x nbp panel,
+// held in registers (thread t owns rows t, t + 1024, ...). Reads the panel
+// columns of W, leaves the eliminated panel in Pb (row-major, CNB wide) and
+// the pivot rows in piv.
+template <int RPT>
+__global__ __launch_bounds__(1024) void k_cp_panel(const double* __restrict__ W, double* __restrict__ Pb, int n,
+                                                   int c0, int nbp, int32_t* __restrict__ piv,
+                                                   int32_t* __restrict__ status) {
   __shared__ double sv[16];
   __shared__ int si[16];
-  __shared__ int s_flag;
+  __shared__ double rowC[CNB], rowP[CNB];
   const int tid = threadIdx.x;
-  if (tid == 0) s_flag = 0;
-  __syncthreads();
-  for (int t = 0; t < nbp; ++t) {
-    const int c = c0 + t;
-    double bv = -1.0;
-    int bi = n;
-    for (int a = c + tid; a < n; a += 1024) argmax_combine(bv, bi, fabs(Pb[int64_t(a) * NB + t]), a);
-    block_argmax(bv, bi, sv, si);
-    if (!(bv > 0.0) || !isfinite(bv)) {
-      if (tid == 0) status[0] = 1;
-      return;
-    }
-    if (tid == 0) piv[c] = bi;
-    if (bi != c && tid < nbp) {
-      const double tmp = Pb[int64_t(c) * NB + tid];
-      Pb[int64_t(c) * NB + tid] = Pb[int64_t(bi) * NB + tid];
-      Pb[int64_t(bi) * NB + tid] = tmp;
-    }
-    __syncthreads();
-    const double pv = Pb[int64_t(c) * NB + t];
-    __syncthreads();
-    if (tid < nbp) Pb[int64_t(c) * NB + tid] = (tid == t ? 1.0 : Pb[int64_t(c) * NB + tid]) / pv;
-    __syncthreads();
-    for (int a = tid; a < n; a += 1024) {
-      if (a == c) continue;
-      const double f = Pb[int64_t(a) * NB + t];
-      for (int u = 0; u < nbp; ++u)
-        if (u != t) Pb[int64_t(a) * NB + u] -= f * Pb[int64_t(c) * NB + u];
-      Pb[int64_t(a) * NB + t] = -f * Pb[int64_t(c) * NB + t];
-    }
-    __syncthreads();
+  double P[RPT][CNB];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int a = tid + 1024 * k;
+#pragma unroll
+    for (int u = 0; u < CNB; ++u) P[k][u] = (a < n && u < nbp) ? W[int64_t(a) * n + c0 + u] : 0.0;
   }
-  (void)s_flag;
+  int bad = 0;
+  cp_steps<RPT>(P, c0, nbp, n, sv, si, rowC, rowP, piv, bad, std::make_integer_sequence<int, CNB>{});
+  if (bad) {
+    if (tid == 0) status[0] = 1;
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int a = tid + 1024 * k;
+    if (a < n)
+#pragma unroll
+      for (int u = 0; u < CNB; ++u) Pb[int64_t(a) * CNB + u] = P[k][u];
+  }
 }
 
 // Apply this panel's composite row interchange to the other columns and copy
@@ -416,47 +458,37 @@ __global__ void k_cp_perm(double* __restrict__ W, int n, int c0, int nbp, const 
                           double* __restrict__ Y) {
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= n || (j >= c0 && j < c0 + nbp)) return;
-  int rows[2 * NB], src[2 * NB], m = 0;
-  auto idx = [&](int r) {
-    for (int k = 0; k < m; ++k)
-      if (rows[k] == r) return k;
-    rows[m] = r;
-    src[m] = r;
-    return m++;
-  };
   for (int t = 0; t < nbp; ++t) {
-    const int a = idx(c0 + t), b = idx(piv[c0 + t]);
-    const int tmp = src[a];
-    src[a] = src[b];
-    src[b] = tmp;
+    const int r = piv[c0 + t];
+    if (r == c0 + t) continue;
+    const double tmp = W[int64_t(c0 + t) * n + j];
+    W[int64_t(c0 + t) * n + j] = W[int64_t(r) * n + j];
+    W[int64_t(r) * n + j] = tmp;
   }
-  double tmp[2 * NB];
-  for (int k = 0; k < m; ++k) tmp[k] = W[int64_t(src[k]) * n + j];
-  for (int k = 0; k < m; ++k) W[int64_t(rows[k]) * n + j] = tmp[k];
   for (int t = 0; t < nbp; ++t) Y[int64_t(t) * n + j] = W[int64_t(c0 + t) * n + j];
 }
 
 // W[a][j] (+)= sum_t Pb[a][t] Y[t][j]; panel columns receive the panel.
 __global__ __launch_bounds__(256) void k_cp_update(double* __restrict__ W, int n, int c0, int nbp,
                                                    const double* __restrict__ Pb, const double* __restrict__ Y, int rows_per) {
-  __shared__ double Ps[64 * NB];
+  __shared__ double Ps[64 * CNB];
   const int j = blockIdx.x * 256 + threadIdx.x;
   const int a0 = blockIdx.y * rows_per;
   const int a1 = min(n, a0 + rows_per);
-  for (int e = threadIdx.x; e < (a1 - a0) * NB; e += 256) Ps[e] = Pb[int64_t(a0) * NB + e];
+  for (int e = threadIdx.x; e < (a1 - a0) * CNB; e += 256) Ps[e] = Pb[int64_t(a0) * CNB + e];
   __syncthreads();
   if (j >= n) return;
   if (j >= c0 && j < c0 + nbp) {
-    for (int a = a0; a < a1; ++a) W[int64_t(a) * n + j] = Ps[(a - a0) * NB + (j - c0)];
+    for (int a = a0; a < a1; ++a) W[int64_t(a) * n + j] = Ps[(a - a0) * CNB + (j - c0)];
     return;
   }
-  double y[NB];
+  double y[CNB];
 #pragma unroll
-  for (int t = 0; t < NB; ++t) y[t] = (t < nbp) ? Y[int64_t(t) * n + j] : 0.0;
+  for (int t = 0; t < CNB; ++t) y[t] = (t < nbp) ? Y[int64_t(t) * n + j] : 0.0;
   for (int a = a0; a < a1; ++a) {
     double s = 0.0;
 #pragma unroll
-    for (int t = 0; t < NB; ++t) s += Ps[(a - a0) * NB + t] * y[t];
+    for (int t = 0; t < CNB; ++t) s += Ps[(a - a0) * CNB + t] * y[t];
     if (a >= c0 && a < c0 + nbp)
       W[int64_t(a) * n + j] = s;
     else
@@ -630,6 +662,37 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   if (L.d_rec32) dev_free(c, L.d_rec32);
   L.rec64_h = o64;
   L.rec32_h = o32;
+  // algorithmic bytes of one GEMV launch: factors n^2 s, slot indices 4n, gathered r 8n, delta 8n
+  L.bytes64 = 0;
+  L.bytes32 = 0;
+  for (auto& r : o64) L.bytes64 += double(r.n) * r.n * 8 + 20.0 * r.n;
+  for (auto& r : o32) L.bytes32 += double(r.n) * r.n * 4 + 20.0 * r.n;
+  // multiplicative phases: records in colour order, each naming its arena
+  {
+    std::vector<MultRec> byid(ne);
+    for (auto& r : o64) byid[r.id] = MultRec{r.n, 0, r.slot, r.fac};
+    for (auto& r : o32) byid[r.id] = MultRec{r.n, 1, r.slot, r.fac};
+    std::vector<MultRec> mrec;
+    mrec.reserve(L.ph_exp.size());
+    L.mrec_max_n = 0;
+    for (int32_t e : L.ph_exp) {
+      mrec.push_back(byid[e]);
+      L.mrec_max_n = std::max(L.mrec_max_n, byid[e].n);
+    }
+    L.ph_bytes.assign(L.ph_ptr.empty() ? 0 : L.ph_ptr.size() - 1, 0.0);
+    for (size_t ph = 0; ph + 1 < L.ph_ptr.size(); ++ph)
+      for (int32_t q = L.ph_ptr[ph]; q < L.ph_ptr[ph + 1]; ++q) {
+        const MultRec& m = mrec[q];
+        L.ph_bytes[ph] += double(m.n) * m.n * (m.f32 ? 4 : 8) + 20.0 * m.n;
+      }
+    // LDS of the phase kernel: residual (n doubles), block partials or the
+    // 2048-entry staging buffer, E_E row starts (n) and prefix (n + 1)
+    const int64_t mn = std::max<int32_t>(L.mrec_max_n, 1);
+    L.mx_lds = size_t(mn + std::max<int64_t>(((mn + 31) / 32) * mn, 2048)) * sizeof(double) +
+               size_t(2 * mn + 1) * sizeof(int32_t);
+    if (L.d_mrec) dev_free(c, L.d_mrec);
+    L.d_mrec = upload(c, mrec);
+  }
   L.d_rec64 = upload(c, o64);
   L.d_rec32 = upload(c, o32);
   CAV_HIP(hipStreamSynchronize(s));
@@ -654,12 +717,13 @@ cav_status factor_coarse(Ctx& c) {
   const int64_t n2 = int64_t(N) * N;
   const int n0 = int(3 * n2);
   const int nb = n0 + 1;
+  if (nb > 4096) throw StatusError(CAV_ERR_INVALID_ARG, "coarsest grid too large for the dense solve (3 N0^2 + 1 > 4096)");
   if (c.d_cinv) dev_free(c, c.d_cinv);
   if (c.d_cperm) dev_free(c, c.d_cperm);
   c.nc = nb;
   double* W = static_cast<double*>(dev_alloc(c, size_t(nb) * nb * sizeof(double)));
-  double* Pb = static_cast<double*>(dev_alloc(c, size_t(nb) * NB * sizeof(double)));
-  double* Y = static_cast<double*>(dev_alloc(c, size_t(nb) * NB * sizeof(double)));
+  double* Pb = static_cast<double*>(dev_alloc(c, size_t(nb) * CNB * sizeof(double)));
+  double* Y = static_cast<double*>(dev_alloc(c, size_t(nb) * CNB * sizeof(double)));
   int32_t* piv = static_cast<int32_t*>(dev_alloc(c, size_t(nb) * sizeof(int32_t)));
   int32_t* sts = static_cast<int32_t*>(dev_alloc(c, sizeof(int32_t)));
   CAV_HIP(hipMemsetAsync(sts, 0, sizeof(int32_t), s));
@@ -667,10 +731,14 @@ cav_status factor_coarse(Ctx& c) {
   if (L.ee.nnz() > 0)
     k_coarse_add_ee<<<nblk(2 * n2), 256, 0, s>>>(W, nb, 2 * n2, L.d_erow_full, L.d_ecol, L.d_eval);
   const int rows_per = 64;
-  for (int c0 = 0; c0 < nb; c0 += NB) {
-    const int nbp = std::min(NB, nb - c0);
-    k_cp_load<<<nblk(int64_t(nb) * nbp), 256, 0, s>>>(W, nb, c0, nbp, Pb);
-    k_cp_panel<<<1, 1024, 0, s>>>(Pb, nb, c0, nbp, piv, sts);
+  for (int c0 = 0; c0 < nb; c0 += CNB) {
+    const int nbp = std::min(CNB, nb - c0);
+    switch ((nb + 1023) / 1024) {
+      case 1: k_cp_panel<1><<<1, 1024, 0, s>>>(W, Pb, nb, c0, nbp, piv, sts); break;
+      case 2: k_cp_panel<2><<<1, 1024, 0, s>>>(W, Pb, nb, c0, nbp, piv, sts); break;
+      case 3: k_cp_panel<3><<<1, 1024, 0, s>>>(W, Pb, nb, c0, nbp, piv, sts); break;
+      default: k_cp_panel<4><<<1, 1024, 0, s>>>(W, Pb, nb, c0, nbp, piv, sts); break;
+    }
     k_cp_perm<<<nblk(nb), 256, 0, s>>>(W, nb, c0, nbp, piv, Y);
     dim3 g(nblk(nb), unsigned((nb + rows_per - 1) / rows_per));
     k_cp_update<<<g, 256, 0, s>>>(W, nb, c0, nbp, Pb, Y, rows_per);

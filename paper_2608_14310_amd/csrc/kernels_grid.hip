@@ -230,6 +230,13 @@ void launch_scale(double* y, const double* x, const double* denom, int64_t n, hi
   k_scale<<<nblocks(n), TPB, 0, s>>>(y, x, denom, n);
 }
 
+__global__ __launch_bounds__(TPB) void k_fill(double* __restrict__ x, double v, int64_t n) {
+  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (t < n) x[t] = v;
+}
+
+void launch_fill(double* x, double v, int64_t n, hipStream_t s) { k_fill<<<nblocks(n), TPB, 0, s>>>(x, v, n); }
+
 void launch_block_sum(const double* x, int64_t n, double* part, double* out, hipStream_t s) {
   const int nblk = dots_blocks(n);
   k_psum_partial<<<nblk, TPB, 0, s>>>(x, n, part, nblk);

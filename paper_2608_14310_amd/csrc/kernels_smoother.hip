@@ -10,12 +10,16 @@
 //    kernel, bucketed by size, FP64 or FP32 factors;
 //  * unknowns inside an explicit patch ("touched") pull their slot deltas in a
 //    fixed order and apply 1/cnt. Every sum has a fixed order (no atomics).
+#include <algorithm>
+
 #include "cav_internal.hpp"
 
 namespace cav {
 
 namespace {
 constexpr int TPB = 256;
+constexpr int PA_THREADS = 256;
+constexpr int MX_THREADS = 1024;
 
 __device__ __forceinline__ int wrapi(int a, int N) { return a & (N - 1); }
 
@@ -129,32 +133,194 @@ __global__ __launch_bounds__(TPB) void k_update(double* __restrict__ x, const do
 
 inline unsigned nblocks(int64_t n) { return unsigned((n + TPB - 1) / TPB); }
 
-template <typename T>
-void launch_bucketed(const std::vector<PatchRec>& recs_h, const PatchRec* recs_d, const T* arena, const Level& L,
-                     const double* r, hipStream_t s) {
-  // recs are sorted by n descending; consecutive runs share a workgroup size
-  const int total = int(recs_h.size());
-  int b0 = 0;
-  while (b0 < total) {
-    const int nmax = recs_h[b0].n;
-    int nt = nmax > 256 ? 512 : nmax > 128 ? 256 : nmax > 64 ? 128 : 64;
-    const int lower = nt / 2;
-    int b1 = b0;
-    while (b1 < total && (recs_h[b1].n > lower || nt == 64)) ++b1;
-    const size_t lds = size_t(nmax) * sizeof(T);
-    const unsigned grid = unsigned(b1 - b0);
-    switch (nt) {
-      case 512: k_patch_apply<T, 512><<<grid, 512, lds, s>>>(recs_d + b0, arena, L.d_slot_dof, r, L.d_delta); break;
-      case 256: k_patch_apply<T, 256><<<grid, 256, lds, s>>>(recs_d + b0, arena, L.d_slot_dof, r, L.d_delta); break;
-      case 128: k_patch_apply<T, 128><<<grid, 128, lds, s>>>(recs_d + b0, arena, L.d_slot_dof, r, L.d_delta); break;
-      default: k_patch_apply<T, 64><<<grid, 64, lds, s>>>(recs_d + b0, arena, L.d_slot_dof, r, L.d_delta); break;
-    }
-    b0 = b1;
+// (K_E x)_d for one unknown: MAC stencil row plus the -dt E_E row.
+__device__ __forceinline__ double krow(int64_t d, const double* __restrict__ x, const StencilCoef& sc,
+                                       const int32_t* __restrict__ erow, const int32_t* __restrict__ ecol,
+                                       const double* __restrict__ eval) {
+  const int N = sc.N;
+  const int64_t n2 = int64_t(N) * N;
+  const int t = int(d / n2);
+  const int64_t c = d - t * n2;
+  const int i = int(c / N), j = int(c % N);
+  const int ip = wrapi(i + 1, N), im = wrapi(i - 1, N), jp = wrapi(j + 1, N), jm = wrapi(j - 1, N);
+  auto C = [N](int a, int b) { return int64_t(a) * N + b; };
+  const double* u = x;
+  const double* v = x + n2;
+  const double* p = x + 2 * n2;
+  double acc;
+  if (t == 0) {
+    acc = sc.diag * u[c] - sc.off * (u[C(ip, j)] + u[C(im, j)] + u[C(i, jp)] + u[C(i, jm)]) +
+          sc.invh * (p[c] - p[C(im, j)]);
+  } else if (t == 1) {
+    acc = sc.diag * v[c] - sc.off * (v[C(ip, j)] + v[C(im, j)] + v[C(i, jp)] + v[C(i, jm)]) +
+          sc.invh * (p[c] - p[C(i, jm)]);
+  } else {
+    return -sc.invh * ((u[C(ip, j)] - u[c]) + (v[C(i, jp)] - v[c]));
   }
+  if (erow)
+    for (int q = erow[d]; q < erow[d + 1]; ++q) acc += eval[q] * x[ecol[q]];
+  return acc;
+}
+
+// One phase of the multiplicative sweep over explicit patches: one 1024-thread
+// workgroup per patch. (1) Residual rows r_i = b_i - (K x)_i of all patch
+// unknowns, 16 lanes per row over the row's E_E entries (indices loaded
+// before the gathers) and a fixed-tree reduction. (2) delta = K_p^{-1} r as
+// (row, 32-column block) items whose loads are all issued before use, with the
+// block partials summed in block order from LDS. (3) x[dofs] += alpha delta.
+// Patches of one phase share no unknown and no coupling, so nothing races.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_mult_exp(const MultRec* __restrict__ recs, const double* __restrict__ a64,
+                                                 const float* __restrict__ a32, const int32_t* __restrict__ slot_dof,
+                                                 StencilCoef sc, const int32_t* __restrict__ erow,
+                                                 const int32_t* __restrict__ ecol, const double* __restrict__ eval,
+                                                 const double* __restrict__ b, double* __restrict__ x, double alpha) {
+  constexpr int G = 16;          // lanes per residual row
+  constexpr int PER = 4;         // E_E entries a lane loads at once
+  constexpr int CB = 32;         // columns per GEMV item
+  extern __shared__ double smem[];
+  const MultRec rec = recs[blockIdx.x];
+  const int n = rec.n;
+  const int nb = (n + CB - 1) / CB;
+  double* rp = smem;             // n
+  double* pp = smem + n;         // nb x n block partials
+  const int32_t* dofs = slot_dof + rec.slot;
+  const int64_t nv = 2 * int64_t(sc.N) * sc.N;
+  const int grp = threadIdx.x / G, gl = threadIdx.x % G;
+  for (int rr = grp; rr < n; rr += NT / G) {
+    const int64_t d = dofs[rr];
+    double acc = 0.0;
+    if (d < nv) {
+      const int q0 = erow[d], q1 = erow[d + 1];
+      for (int qb = q0; qb < q1; qb += G * PER) {
+        int cidx[PER];
+        double cv[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+          const int q = qb + gl + G * k;
+          cidx[k] = q < q1 ? ecol[q] : -1;
+          cv[k] = q < q1 ? eval[q] : 0.0;
+        }
+        double xv[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) xv[k] = cidx[k] >= 0 ? x[cidx[k]] : 0.0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) acc += cv[k] * xv[k];
+      }
+    }
+    if (gl == 0) acc += krow(d, x, sc, nullptr, nullptr, nullptr);
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, G);
+    if (gl == 0) rp[rr] = b[d] - acc;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n * nb; t += NT) {
+    const int i = t % n, cb = t / n;
+    const int j0 = cb * CB, w = min(CB, n - j0);
+    double acc;
+    if (rec.f32) {
+      const float* col = a32 + rec.fac + int64_t(j0) * n + i;
+      float m[CB];
+#pragma unroll
+      for (int jj = 0; jj < CB; ++jj) m[jj] = jj < w ? col[int64_t(jj) * n] : 0.f;
+      float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+      for (int jj = 0; jj < CB; jj += 2) {
+        s0 += m[jj] * (jj < w ? float(rp[j0 + jj]) : 0.f);
+        s1 += m[jj + 1] * (jj + 1 < w ? float(rp[j0 + jj + 1]) : 0.f);
+      }
+      acc = double(s0 + s1);
+    } else {
+      const double* col = a64 + rec.fac + int64_t(j0) * n + i;
+      double m[CB];
+#pragma unroll
+      for (int jj = 0; jj < CB; ++jj) m[jj] = jj < w ? col[int64_t(jj) * n] : 0.0;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < CB; jj += 2) {
+        s0 += m[jj] * (jj < w ? rp[j0 + jj] : 0.0);
+        s1 += m[jj + 1] * (jj + 1 < w ? rp[j0 + jj + 1] : 0.0);
+      }
+      acc = s0 + s1;
+    }
+    pp[int64_t(cb) * n + i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += NT) {
+    double s = 0.0;
+    for (int cb = 0; cb < nb; ++cb) s += pp[int64_t(cb) * n + i];
+    x[dofs[i]] += alpha * s;
+  }
+}
+
+// One colour phase of the shared standard patches: cells with
+// (i + 3 j) mod 8 == colour and no E_E entries solve their 5x5 patch from the
+// current residual and update x.
+__global__ __launch_bounds__(TPB) void k_mult_std(int N, int colour, const uint8_t* __restrict__ flag,
+                                                  const double* __restrict__ Minv, StencilCoef sc,
+                                                  const double* __restrict__ b, double* __restrict__ x, double alpha) {
+  const int per = N / 8;  // cells of one colour per column j
+  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (t >= int64_t(N) * per) return;
+  const int j = int(t / per), k = int(t % per);
+  const int i = ((colour - 3 * j) % 8 + 8) % 8 + 8 * k;
+  const int64_t n2 = int64_t(N) * N;
+  const int64_t c = int64_t(i) * N + j;
+  if (flag[c] & 1) return;
+  const int64_t d[5] = {c, int64_t(wrapi(i + 1, N)) * N + j, n2 + c, n2 + int64_t(i) * N + wrapi(j + 1, N), 2 * n2 + c};
+  double r[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) r[q] = b[d[q]] - krow(d[q], x, sc, nullptr, nullptr, nullptr);
+  double dl[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) s += Minv[q + 5 * m] * r[m];
+    dl[q] = s;
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) x[d[q]] += alpha * dl[q];
+}
+
+template <typename T>
+void launch_patch_apply(Ctx& c, const std::vector<PatchRec>& recs_h, const PatchRec* recs_d, const T* arena,
+                        const Level& L, const double* r, double bytes, hipStream_t s) {
+  // one launch per level and precision; records are sorted by n descending
+  const int total = int(recs_h.size());
+  const size_t lds = size_t(recs_h[0].n) * sizeof(T);
+  timing_begin(c, s);
+  k_patch_apply<T, PA_THREADS><<<unsigned(total), PA_THREADS, lds, s>>>(recs_d, arena, L.d_slot_dof, r, L.d_delta);
+  timing_end(c, s, bytes);
 }
 }  // namespace
 
+void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s) {
+  const int64_t n2 = int64_t(L.N) * L.N, n = 3 * n2;
+  if (zero_guess) launch_fill(x, 0.0, n, s);
+  const int nph = int(L.ph_ptr.size()) - 1;
+  if (L.mx_lds > 64 * 1024)
+    CAV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_mult_exp<MX_THREADS>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(L.mx_lds)));
+  for (int ph = 0; ph < nph; ++ph) {
+    const int a = L.ph_ptr[ph], cnt = L.ph_ptr[ph + 1] - a;
+    timing_begin(c, s);
+    k_mult_exp<MX_THREADS><<<unsigned(cnt), MX_THREADS, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof,
+                                                                      L.sc, L.d_erow_full, L.d_ecol, L.d_eval, b, x,
+                                                                      c.alpha);
+    timing_end(c, s, L.ph_bytes[ph]);
+  }
+  const int64_t per_colour = n2 / 8;
+  for (int col = 0; col < 8; ++col)
+    k_mult_std<<<nblocks(per_colour), TPB, 0, s>>>(L.N, col, L.d_cellflag, L.d_std_inv, L.sc, b, x, c.alpha);
+  launch_pressure_mean_remove(x, L.N, L.d_part, s);
+}
+
 void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s) {
+  if (c.smoother == CAV_SMOOTHER_MULTIPLICATIVE) {
+    launch_mult_smoother(c, L, b, x, zero_guess, s);
+    return;
+  }
   const int64_t n2 = int64_t(L.N) * L.N, n = 3 * n2;
   const double* r = b;
   if (!zero_guess) {
@@ -162,8 +328,8 @@ void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_gue
     r = L.d_r;
   }
   k_std_smooth<<<nblocks(n2), TPB, 0, s>>>(L.N, L.d_cellflag, L.d_std_inv, r, L.d_z);
-  if (!L.rec64_h.empty()) launch_bucketed<double>(L.rec64_h, L.d_rec64, L.d_f64, L, r, s);
-  if (!L.rec32_h.empty()) launch_bucketed<float>(L.rec32_h, L.d_rec32, L.d_f32, L, r, s);
+  if (!L.rec64_h.empty()) launch_patch_apply<double>(c, L.rec64_h, L.d_rec64, L.d_f64, L, r, L.bytes64, s);
+  if (!L.rec32_h.empty()) launch_patch_apply<float>(c, L.rec32_h, L.d_rec32, L.d_f32, L, r, L.bytes32, s);
   if (L.n_touched > 0)
     k_touched<<<nblocks(L.n_touched), TPB, 0, s>>>(L.n_touched, L.d_t_dof, L.d_t_inv, L.d_t_ptr, L.d_t_slot, L.d_delta,
                                                    L.d_z);

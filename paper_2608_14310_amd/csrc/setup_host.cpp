@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <thread>
 
 #include "cav_internal.hpp"
 
@@ -14,6 +15,23 @@ namespace {
 inline int pmod(int64_t a, int n) {
   int64_t r = a % n;
   return int(r < 0 ? r + n : r);
+}
+
+// f(begin, end) over contiguous ranges of [0, n) on up to 16 host threads.
+template <typename F>
+void parallel_chunks(int64_t n, F&& f) {
+  int nt = int(std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u));
+  if (n < 256) nt = 1;
+  if (nt <= 1) {
+    f(int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) {
+    const int64_t b = n * t / nt, e = n * (t + 1) / nt;
+    th.emplace_back([&f, b, e] { f(b, e); });
+  }
+  for (auto& x : th) x.join();
 }
 
 // Peskin's four-point kernel (the textbook closed form used in Section 2).
@@ -304,6 +322,120 @@ void galerkin_coarsen(int Nc, const HostCSR& fine, HostCSR& coarse) {
   }
 }
 
+template <typename V>
+void visit_reach(int N, const HostCSR& ee, const Level& L, int e, V&& visit);
+
+// Phases of the multiplicative sweep for the explicit patches: greedy colouring
+// of the conflict graph (two patches conflict when one holds an unknown that
+// the other's unknowns reach through a structural entry of K_E, itself
+// included), visiting patches by decreasing size then cell index and giving
+// each the smallest colour free among its coloured neighbours. Patches of one
+// colour share no unknown and no coupling, so they can be applied at once.
+void colour_explicit(int N, const HostCSR& ee, Level& L) {
+  const int64_t n2 = int64_t(N) * N, nv = 2 * n2, n = 3 * n2;
+  const int ne = L.n_exp;
+  L.ph_ptr.assign(1, 0);
+  L.ph_exp.clear();
+  if (ne == 0) return;
+  // owners: unknown -> explicit patches holding it
+  std::vector<int32_t> optr(n + 1, 0);
+  for (int32_t d : L.slot_dof_h) optr[d + 1]++;
+  for (int64_t d = 0; d < n; ++d) optr[d + 1] += optr[d];
+  std::vector<int32_t> own(optr.back());
+  {
+    std::vector<int32_t> pos(optr.begin(), optr.end() - 1);
+    for (int e = 0; e < ne; ++e)
+      for (int64_t s = L.exp_off[e]; s < L.exp_off[e + 1]; ++s) own[pos[L.slot_dof_h[s]]++] = e;
+  }
+  std::vector<int> order(ne);
+  for (int e = 0; e < ne; ++e) order[e] = e;
+  auto np_of = [&](int e) { return L.exp_off[e + 1] - L.exp_off[e]; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (np_of(a) != np_of(b)) return np_of(a) > np_of(b);
+    return L.exp_cells[a] < L.exp_cells[b];
+  });
+  // conflict lists, independently per patch (in parallel); then the greedy pass
+  std::vector<std::vector<int32_t>> nbr(ne);
+  parallel_chunks(ne, [&](int64_t e0, int64_t e1) {
+    std::vector<int32_t> stamp(n, -1), pmark(ne, -1);
+    for (int64_t ee_ = e0; ee_ < e1; ++ee_) {
+      const int e = int(ee_);
+      std::vector<int32_t>& out = nbr[e];
+      auto visit = [&](int64_t d) {
+        if (stamp[d] == e) return;
+        stamp[d] = e;
+        for (int32_t q = optr[d]; q < optr[d + 1]; ++q) {
+          const int32_t o = own[q];
+          if (o != e && pmark[o] != e) {
+            pmark[o] = e;
+            out.push_back(o);
+          }
+        }
+      };
+      visit_reach(N, ee, L, e, visit);
+    }
+  });
+  std::vector<int> colour(ne, -1), cmark;
+  int ncol = 0;
+  for (int e : order) {
+    cmark.resize(size_t(ncol) + 1, -1);
+    for (int32_t q : nbr[e])
+      if (colour[q] >= 0) cmark[colour[q]] = e;
+    int c = 0;
+    while (c < ncol && cmark[c] == e) ++c;
+    colour[e] = c;
+    if (c == ncol) ++ncol;
+  }
+  // phases: colour-major, explicit patches by ascending cell inside a colour
+  std::vector<std::vector<int32_t>> by(ncol);
+  for (int e = 0; e < ne; ++e) by[colour[e]].push_back(e);  // e ascends with the cell index
+  for (int c = 0; c < ncol; ++c) {
+    L.ph_exp.insert(L.ph_exp.end(), by[c].begin(), by[c].end());
+    L.ph_ptr.push_back(int32_t(L.ph_exp.size()));
+  }
+}
+
+// Visits every unknown that explicit patch e's unknowns reach through a
+// structural entry of K_E (themselves included): MAC stencil neighbours and
+// E_E rows.
+template <typename V>
+void visit_reach(int N, const HostCSR& ee, const Level& L, int e, V&& visit) {
+  const int64_t n2 = int64_t(N) * N, nv = 2 * n2;
+  {
+    for (int64_t s = L.exp_off[e]; s < L.exp_off[e + 1]; ++s) {
+      const int64_t d = L.slot_dof_h[s];
+      visit(d);
+      if (d < n2) {                      // u_ij: u neighbours, p_ij, p_{i-1,j}, E_E row
+        const int i = int(d / N), j = int(d % N);
+        visit(int64_t(pmod(i + 1, N)) * N + j);
+        visit(int64_t(pmod(i - 1, N)) * N + j);
+        visit(int64_t(i) * N + pmod(j + 1, N));
+        visit(int64_t(i) * N + pmod(j - 1, N));
+        visit(nv + d);
+        visit(nv + int64_t(pmod(i - 1, N)) * N + j);
+      } else if (d < nv) {               // v_ij: v neighbours, p_ij, p_{i,j-1}, E_E row
+        const int64_t q = d - n2;
+        const int i = int(q / N), j = int(q % N);
+        visit(n2 + int64_t(pmod(i + 1, N)) * N + j);
+        visit(n2 + int64_t(pmod(i - 1, N)) * N + j);
+        visit(n2 + int64_t(i) * N + pmod(j + 1, N));
+        visit(n2 + int64_t(i) * N + pmod(j - 1, N));
+        visit(nv + q);
+        visit(nv + int64_t(i) * N + pmod(j - 1, N));
+      } else {                           // p_ij: the four faces of its cell
+        const int64_t q = d - nv;
+        const int i = int(q / N), j = int(q % N);
+        visit(q);
+        visit(int64_t(pmod(i + 1, N)) * N + j);
+        visit(n2 + q);
+        visit(n2 + int64_t(i) * N + pmod(j + 1, N));
+      }
+      if (d < nv)
+        for (int64_t k = ee.rowptr[d]; k < ee.rowptr[d + 1]; ++k) visit(ee.col[k]);
+    }
+  }
+}
+
 // CAV patch family (Eq. cav_patch_set) on one level, plus the arrays the
 // smoother needs: cell flags, explicit patch slots and the unknown -> slot
 // transpose with 1/cnt weights (Appendix A's partition of unity).
@@ -323,10 +455,19 @@ void build_patches(int N, const HostCSR& ee, int family, Level& L) {
   L.exp_cells.clear();
   L.exp_off.assign(1, 0);
   L.slot_dof_h.clear();
-  std::vector<int32_t> cmark(n2, -1), dmark(n, -1);
-  std::vector<int32_t> cells, dofs;
-  std::vector<std::vector<int32_t>> covered_by;  // cells covered by each explicit patch
-  for (int i = 0; i < N; ++i)
+  // rows of cells in parallel; each range keeps its own output, merged in order
+  struct Part {
+    std::vector<int32_t> dofs, plen, ecells, slot, elen, cov;
+  };
+  const int nchunk = std::max(1, std::min(N, 64));
+  std::vector<Part> parts(nchunk);
+  parallel_chunks(nchunk, [&](int64_t k0, int64_t k1) {
+    std::vector<int32_t> cmark(n2, -1), dmark(n, -1);
+    std::vector<int32_t> cells, dofs;
+    for (int64_t kc = k0; kc < k1; ++kc) {
+    Part& P = parts[kc];
+    const int i0 = int(int64_t(N) * kc / nchunk), i1 = int(int64_t(N) * (kc + 1) / nchunk);
+    for (int i = i0; i < i1; ++i)
     for (int j = 0; j < N; ++j) {
       const int32_t cell = int32_t(int64_t(i) * N + j);
       int32_t U[4];
@@ -375,19 +516,34 @@ void build_patches(int N, const HostCSR& ee, int family, Level& L) {
         cells.assign(1, cell);
       }
       std::sort(dofs.begin(), dofs.end());
-      L.patch_dofs.insert(L.patch_dofs.end(), dofs.begin(), dofs.end());
-      L.patch_off[cell + 1] = int64_t(L.patch_dofs.size());
-      const bool expl = anyrow;  // own factor whenever E_E enters the local matrix
-      if (expl) {
-        L.cellflag[cell] |= 1;
-        L.exp_cells.push_back(cell);
-        L.slot_dof_h.insert(L.slot_dof_h.end(), dofs.begin(), dofs.end());
-        L.exp_off.push_back(int64_t(L.slot_dof_h.size()));
-        covered_by.push_back(cells);
+      P.dofs.insert(P.dofs.end(), dofs.begin(), dofs.end());
+      P.plen.push_back(int32_t(dofs.size()));
+      if (anyrow) {  // own factor whenever E_E enters the local matrix
+        P.ecells.push_back(cell);
+        P.slot.insert(P.slot.end(), dofs.begin(), dofs.end());
+        P.elen.push_back(int32_t(dofs.size()));
+        P.cov.insert(P.cov.end(), cells.begin(), cells.end());
       }
     }
-  for (auto& cs : covered_by)
-    for (int32_t c : cs) L.cellflag[c] |= 2;
+    }
+  });
+  {
+    int64_t c = 0;
+    for (auto& P : parts) {
+      for (int32_t len : P.plen) {
+        L.patch_off[c + 1] = L.patch_off[c] + len;
+        ++c;
+      }
+      L.patch_dofs.insert(L.patch_dofs.end(), P.dofs.begin(), P.dofs.end());
+      for (size_t k = 0; k < P.ecells.size(); ++k) {
+        L.cellflag[P.ecells[k]] |= 1;
+        L.exp_cells.push_back(P.ecells[k]);
+        L.exp_off.push_back(L.exp_off.back() + P.elen[k]);
+      }
+      L.slot_dof_h.insert(L.slot_dof_h.end(), P.slot.begin(), P.slot.end());
+      for (int32_t cc : P.cov) L.cellflag[cc] |= 2;
+    }
+  }
   L.n_exp = int32_t(L.exp_cells.size());
   L.n_slots = int64_t(L.slot_dof_h.size());
 
@@ -426,6 +582,7 @@ void build_patches(int N, const HostCSR& ee, int family, Level& L) {
     L.t_inv_h[t] = 1.0 / double(cnt);
   }
   L.n_touched = int32_t(L.t_dof_h.size());
+  colour_explicit(N, ee, L);
 
   // stats
   cav_level_stats& st = L.stats;

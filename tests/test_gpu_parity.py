@@ -147,3 +147,63 @@ def test_fgmres_matches_oracle(pair):
     assert true <= max(1e-10, 10 * floor) * 2
     assert np.linalg.norm(xg - res.x) / np.linalg.norm(res.x) < 1e-8
     np.testing.assert_allclose(info["history"], res.history, rtol=1e-5, atol=1e-13)
+
+
+# ------------------------------------------- multiplicative (coloured) sweep ---
+
+MCASES = {
+    "target32": lambda: workloads.small_target(0),
+    "beam64": lambda: workloads.beam_fibres(64, 2, 1.0, 1e4, seed=0),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(MCASES))
+def mpair(request):
+    s = MCASES[request.param]()
+    print(f"[gpu parity] multiplicative case {request.param} N={s.N} levels={s.n_levels}", flush=True)
+    H = multigrid.Hierarchy(s, alpha=1.0, smoother="coloured")
+    g = _solver()
+    stats, fst = g.setup(s, alpha=1.0, smoother="multiplicative")
+    yield request.param, s, H, g, stats, fst
+    g.close()
+
+
+def test_multiplicative_phases_match_exactly(mpair):
+    name, s, H, g, stats, fst = mpair
+    b = np.zeros(H.levels[-1].K.shape[0])
+    H.smooth(len(H.levels) - 1, b, np.zeros_like(b))   # builds the oracle's phases lazily
+    for l in range(1, len(H.levels)):
+        if H.levels[l].phases is None:
+            H.smooth(l, np.zeros(H.levels[l].K.shape[0]), np.zeros(H.levels[l].K.shape[0]))
+        N = H.levels[l].N
+        want = [ph for ph in H.levels[l].phases]
+        got = g.export_phases(l)
+        assert got == want[:len(got)], (name, l)
+        rest = want[len(got):]
+        assert len(rest) == 8 and sorted(c for ph in rest for c in ph) == sorted(
+            c for c in range(N * N) if c not in {x for ph in got for x in ph})
+
+
+def test_multiplicative_sweep_and_vcycle(mpair):
+    name, s, H, g, stats, fst = mpair
+    rng = np.random.default_rng(11)
+    tol = _tol(fst)
+    for l in range(1, len(H.levels)):
+        b = rng.standard_normal(H.levels[l].K.shape[0])
+        y = _np(g.level_apply(l, 3, _t(b)))
+        ref = H.smooth(l, b, np.zeros_like(b))
+        assert _rel(y, ref) < tol, (name, l, _rel(y, ref), tol)
+    z = _np(g.vcycle(_t(s.b)))
+    ref = H.vcycle(s.b)
+    assert _rel(z, ref) < 4 * tol, (_rel(z, ref), tol)
+
+
+def test_multiplicative_fgmres_matches_oracle(mpair):
+    name, s, H, g, stats, fst = mpair
+    K = H.levels[-1].K
+    res = krylov.fgmres(lambda x: K @ x, H.vcycle, s.b, 1e-10, 150)
+    x, info = g.fgmres_solve(_t(s.b), rtol=1e-10, max_it=150)
+    xg = _np(x)
+    print(f"[gpu parity] multiplicative {name}: oracle its={res.iterations} gpu its={info['iterations']}", flush=True)
+    assert info["converged"] == 1 and info["iterations"] == res.iterations
+    assert np.linalg.norm(xg - res.x) / np.linalg.norm(res.x) < 1e-8

@@ -1,0 +1,96 @@
+"""Host logic of the HIP library against the oracle, on the CPU.
+
+cav_analyze runs the host part of the setup (force law, E_E = S E J,
+Galerkin coarsening, CAV patches, multiplicative colour phases, 1/cnt
+weights) with no device; every result must equal the oracle's: patch sets
+and phases exactly, E_E to rounding.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads
+from oracle import ib, hierarchy, mac, multigrid, patches as pmod
+
+
+def _analysis(s, family="cav"):
+    from paper_2608_14310_amd._binding import Analysis
+    return Analysis(s, family)
+
+
+CASES = {
+    "target32": lambda: workloads.small_target(0),
+    "membrane32": lambda: workloads.membrane_ellipse(32, 3, 1e4, 1),
+    "beam64": lambda: workloads.beam_fibres(64, 4, 1.0, 1e4, seed=0),
+    "closedbeam32": lambda: workloads.paper_beam(32),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def pair(request):
+    s = CASES[request.param]()
+    a = _analysis(s)
+    EE, pat = ib.eulerian_elasticity(s)
+    ee = [None] * s.n_levels
+    ee[-1] = (EE, pat)
+    for l in range(s.n_levels - 1, 0, -1):
+        ee[l - 1] = hierarchy.galerkin(ee[l][0], ee[l][1], s.N >> (s.n_levels - l))
+    yield request.param, s, a, ee
+    a.close()
+
+
+def test_library_exports_every_declared_symbol():
+    """Every function include/cavmg.h declares is exported by libcavmg.so."""
+    import os
+    import re
+    import ctypes
+    from paper_2608_14310_amd import library_path
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "cavmg.h")).read()
+    names = set(re.findall(r"\b(cav_[a-z_0-9]+)\s*\(", hdr))
+    L = ctypes.CDLL(library_path())
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert names and not missing, missing
+
+
+def test_ee_matches_oracle(pair):
+    name, s, a, ee = pair
+    for l in range(s.n_levels):
+        rp, col, val = a.ee(l)
+        N = s.N >> (s.n_levels - 1 - l)
+        G = sp.csr_matrix((val, col, rp), shape=(2 * N * N, 2 * N * N))
+        EE, pat = ee[l]
+        P = pat.tocsr()
+        assert np.array_equal(np.diff(G.indptr), np.diff(P.indptr)), (name, l)
+        assert np.array_equal(G.indices, P.indices), (name, l)
+        d = (G - EE).tocsr()
+        assert (abs(d).max() if d.nnz else 0.0) <= 1e-13 * max(abs(EE).max(), 1e-300), (name, l)
+
+
+def test_patches_phases_and_weights_match_oracle(pair):
+    name, s, a, ee = pair
+    for l in range(1, s.n_levels):
+        N = s.N >> (s.n_levels - 1 - l)
+        ps, std = pmod.cav_patches(N, ee[l][1])
+        got = a.patches(l)
+        assert len(got) == len(ps)
+        assert all(np.array_equal(g, p) for g, p in zip(got, ps)), (name, l)
+        stencil = mac.reduced_operator(N, 1.0, 1.0, 1.0, sp.csr_matrix((2 * N * N, 2 * N * N)))
+        want = pmod.coloured_order(N, ps, ee[l][1], stencil)
+        ph = a.phases(l)
+        assert ph == want[:len(ph)], (name, l)
+        cnt = pmod.patch_counts(3 * N * N, ps)
+        dofs, inv = a.weights(l)
+        assert np.array_equal(inv, 1.0 / cnt[dofs]), (name, l)
+        # every unknown outside the touched list sits in exactly the standard count of patches
+        rest = np.setdiff1d(np.arange(3 * N * N), dofs)
+        assert np.all(cnt[rest[rest < 2 * N * N]] == 2) and np.all(cnt[rest[rest >= 2 * N * N]] == 1)
+
+
+def test_vanka_family_is_standard():
+    s = workloads.small_target(0)
+    a = _analysis(s, "vanka")
+    for l in range(1, s.n_levels):
+        N = s.N >> (s.n_levels - 1 - l)
+        got = a.patches(l)
+        assert all(len(p) == 5 for p in got)
+        assert all(np.array_equal(g, pmod.vanka_patch(N, c // N, c % N)) for c, g in enumerate(got))
