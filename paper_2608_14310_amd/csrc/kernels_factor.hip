@@ -685,11 +685,9 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
         const MultRec& m = mrec[q];
         L.ph_bytes[ph] += double(m.n) * m.n * (m.f32 ? 4 : 8) + 20.0 * m.n;
       }
-    // LDS of the phase kernel: residual (n doubles), block partials or the
-    // 2048-entry staging buffer, E_E row starts (n) and prefix (n + 1)
+    // LDS of the phase kernel: residual (n doubles) and 16-column block partials
     const int64_t mn = std::max<int32_t>(L.mrec_max_n, 1);
-    L.mx_lds = size_t(mn + std::max<int64_t>(((mn + 31) / 32) * mn, 2048)) * sizeof(double) +
-               size_t(2 * mn + 1) * sizeof(int32_t);
+    L.mx_lds = size_t(mn + ((mn + 15) / 16) * mn) * sizeof(double);
     if (L.d_mrec) dev_free(c, L.d_mrec);
     L.d_mrec = upload(c, mrec);
   }

@@ -177,7 +177,7 @@ __global__ __launch_bounds__(NT) void k_mult_exp(const MultRec* __restrict__ rec
                                                  const double* __restrict__ b, double* __restrict__ x, double alpha) {
   constexpr int G = 16;          // lanes per residual row
   constexpr int PER = 4;         // E_E entries a lane loads at once
-  constexpr int CB = 32;         // columns per GEMV item
+  constexpr int CB = 16;         // columns per GEMV item (keeps the tile in registers at 1024 threads)
   extern __shared__ double smem[];
   const MultRec rec = recs[blockIdx.x];
   const int n = rec.n;

@@ -207,3 +207,32 @@ def test_multiplicative_fgmres_matches_oracle(mpair):
     print(f"[gpu parity] multiplicative {name}: oracle its={res.iterations} gpu its={info['iterations']}", flush=True)
     assert info["converged"] == 1 and info["iterations"] == res.iterations
     assert np.linalg.norm(xg - res.x) / np.linalg.norm(res.x) < 1e-8
+
+
+# ------------------------------------------------------- mixed precision ---
+
+@pytest.mark.parametrize("smoother,alpha,name", [("additive", 0.7, "target32"), ("multiplicative", 1.0, "beam64")])
+def test_mixed_precision_solve(smoother, alpha, name):
+    """FP32 factors for patches with kappa_1 <= 1e6, FP32 GEMV arithmetic,
+    FP64 everywhere else: the V-cycle stays within the FP32 rounding bound of
+    the FP64 oracle's (64 kappa_1 2^-24 with the largest FP32-stored kappa),
+    FGMRES still reaches 1e-10 and the solution matches the oracle within 1e-8."""
+    s = (MCASES if smoother == "multiplicative" else CASES)[name]()
+    H = multigrid.Hierarchy(s, alpha=alpha, smoother="coloured" if smoother == "multiplicative" else "additive")
+    g = _solver()
+    stats, fst = g.setup(s, precision="mixed", cond_threshold=1e6, alpha=alpha, smoother=smoother)
+    assert fst["n_fp32"] > 0
+    z = _np(g.vcycle(_t(s.b)))
+    ref = H.vcycle(s.b)
+    tol = 64 * min(fst["max_cond"], 1e6) * 2.0 ** -24
+    assert _rel(z, ref) < tol, (_rel(z, ref), tol)
+    K = H.levels[-1].K
+    res = krylov.fgmres(lambda x: K @ x, H.vcycle, s.b, 1e-10, 150)
+    x, info = g.fgmres_solve(_t(s.b), rtol=1e-10, max_it=150)
+    xg = _np(x)
+    print(f"[gpu parity] mixed {smoother} {name}: fp32={fst['n_fp32']} fp64={fst['n_fp64']} "
+          f"its={info['iterations']} (fp64 oracle {res.iterations})", flush=True)
+    assert info["converged"] == 1 and info["iterations"] <= res.iterations + 3
+    assert np.linalg.norm(s.b - K @ xg) / np.linalg.norm(s.b) < 2e-10
+    assert np.linalg.norm(xg - res.x) / np.linalg.norm(res.x) < 1e-8
+    g.close()
