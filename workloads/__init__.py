@@ -225,3 +225,29 @@ def paper_target(N: int, kappa: float = 1e6, mu: float = 1.0, seed: int = 0) -> 
     segs = [row_of_markers(0.25, h / 2), row_of_markers(0.75, h / 2)]
     return System(f"paper_target_N{N}", N, levels_to(N, 8), 1.0, mu, h / 2, "target",
                   {"kappa_t": kappa}, segs, random_rhs(N, seed))
+
+
+# ---------------------------------------------------------------------------
+# learned correction stage: seeded initial weights and sample draws
+# ---------------------------------------------------------------------------
+NET_SHAPES = ((32, 3, 3, 3), (32, 32, 3, 3), (3, 32, 3, 3))
+
+
+def net_init(seed: int = 0) -> np.ndarray:
+    """Initial master weights (float32, 10 944): each layer uniform on
+    [-s, s] with s = sqrt(6 / fan_in), fan_in = input channels x 9."""
+    rng = np.random.default_rng([seed, 3])
+    parts = []
+    for co, ci, kh, kw in NET_SHAPES:
+        s = math.sqrt(6.0 / (ci * kh * kw))
+        parts.append(rng.uniform(-s, s, co * ci * kh * kw))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def random_solutions(N: int, count: int, seed: int) -> np.ndarray:
+    """count exact solutions x* (count x 3N^2): uniform[-1, 1] entries with the
+    pressure block shifted to mean zero."""
+    rng = np.random.default_rng([seed, 4])
+    x = rng.uniform(-1.0, 1.0, (count, 3 * N * N))
+    x[:, 2 * N * N:] -= x[:, 2 * N * N:].mean(axis=1, keepdims=True)
+    return x
