@@ -223,6 +223,58 @@ typedef struct {
 } cav_kernel_timing_info;
 cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* out);
 
+/* ---- learned correction stage ----
+ * The paper has no learned component; this stage is an extra, optional part
+ * of the variable preconditioner that flexible GMRES (Section 5) admits.
+ * Net N: R^{3 x N x N} -> R^{3 x N x N}, three periodic 3x3 cross-correlations
+ *   y1 = W1 * x, a1 = relu(y1); y2 = W2 * a1, a2 = relu(y2); y3 = W3 * a2,
+ *   out[co,i,j] = sum_{ci,a,c} W[co,ci,a,c] x[ci, i+a-1, j+c-1] (mod N),
+ * channels 3 -> 32 -> 32 -> 3, no biases. Channels 0, 1, 2 of a sample are the
+ * u, v, p blocks of a grid vector (each [i][j]), so a sample is laid out
+ * exactly like a solver vector. Master weights are FP32, flat, in the order
+ * W1 (32,3,3,3), W2 (32,32,3,3), W3 (3,32,3,3), C-ordered: CAV_NET_WEIGHTS
+ * numbers. Kernels round weights, the input and both hidden activations to
+ * bfloat16 (nearest even, from FP32) and accumulate in FP32.
+ * The net handle owns its weights, Adam state and activation buffers; it is
+ * not thread safe; it may be attached to several contexts on its device. */
+#define CAV_NET_WEIGHTS 10944
+typedef struct cav_net_s* cav_net;
+cav_status cav_net_create(cav_net* out, int device, void* hip_stream); /* weights zero */
+cav_status cav_net_destroy(cav_net net);
+cav_status cav_net_set_stream(cav_net net, void* hip_stream);
+const char* cav_net_last_error(cav_net net);
+/* w: host, CAV_NET_WEIGHTS finite floats (copied). Resets the Adam state. */
+cav_status cav_net_set_weights(cav_net net, const float* w);
+/* Copies the master weights and/or the gradient of the last training step to
+ * host arrays of CAV_NET_WEIGHTS floats (either may be NULL); synchronises. */
+cav_status cav_net_get_weights(cav_net net, float* w, float* grad);
+/* out_b = N(in_b), b < batch. in, out: device FP32, batch x 3 x N x N, N a
+ * power of two in [8, 32768]. */
+cav_status cav_net_forward(cav_net net, int32_t N, int32_t batch, const float* in, float* out);
+/* FP64 correction of one residual: c = ||r|| N(r / ||r||), then the mean of c's
+ * pressure block is removed (c = 0 when r = 0). r, c: device, 3N^2 doubles. */
+cav_status cav_net_correct(cav_net net, int32_t N, const double* r, double* c);
+/* One Adam step (beta 0.9/0.999, eps 1e-8, bias-corrected) on the loss
+ *   L = (1/B) sum_b ||N(rhat_s) - ehat_s||^2 / ||ehat_s||^2,  s = index[b]
+ * (s = b when index is NULL). rhat, ehat: device FP32, n_samples x 3 x N x N;
+ * index: host, batch sample numbers in [0, n_samples). loss (host, optional)
+ * receives L before the update; the call synchronises. */
+cav_status cav_net_train_step(cav_net net, int32_t N, int32_t batch, const float* rhat, const float* ehat,
+                              const int32_t* index, int64_t n_samples, double lr, double* loss);
+/* Training pairs from the context's V-cycle: for each exact solution x*_q
+ * (device, count x 3N^2), b = K x*, x_0 = 0, x_k = x_{k-1} + V(b - K x_{k-1});
+ * after iteration k (1..iters) writes rhat = r_k/||r_k||, ehat = (x* - x_k)/||r_k||
+ * with r_k = b - K x_k, as FP32 at sample q*iters + k-1 of rhat/ehat (device,
+ * count*iters x 3N^2). Synchronises. */
+cav_status cav_learned_pairs(cav_ctx ctx, int32_t count, const double* xstar, int32_t iters, float* rhat,
+                             float* ehat);
+/* Attach (or detach with NULL) a net for cav_fgmres_solve with use_learned.
+ * Each iteration then computes z0 = V(v), r' = v - K z0, c = cav_net_correct(r'),
+ * gamma = <r', Kc>/||Kc||^2 and takes z = z0 + gamma c when
+ * <r', Kc>^2/||Kc||^2 >= margin ||r'||^2 (the V-cycle judges the correction),
+ * otherwise z = z0. The net must match the finest grid. margin in [0, 1). */
+cav_status cav_attach_net(cav_ctx ctx, cav_net net, double margin);
+
 /* E_E of level l (unscaled, symmetric) as host CSR over the 2N_l^2 velocity
  * unknowns: rowptr (2N_l^2+1), col, val; NULL col/val queries *nnz. */
 cav_status cav_export_ee(cav_ctx ctx, int level, int64_t* rowptr, int32_t* col, double* val, int64_t* nnz);

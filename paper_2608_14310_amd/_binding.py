@@ -105,7 +105,20 @@ _SIGS = {
     "cav_export_patches": ([_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
     "cav_export_ee": ([_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                        C.POINTER(C.c_int64)], C.c_int),
+    "cav_net_create": ([C.POINTER(_P), C.c_int, _P], C.c_int),
+    "cav_net_destroy": ([_P], C.c_int),
+    "cav_net_set_stream": ([_P, _P], C.c_int),
+    "cav_net_last_error": ([_P], C.c_char_p),
+    "cav_net_set_weights": ([_P, C.POINTER(C.c_float)], C.c_int),
+    "cav_net_get_weights": ([_P, C.POINTER(C.c_float), C.POINTER(C.c_float)], C.c_int),
+    "cav_net_forward": ([_P, C.c_int32, C.c_int32, _P, _P], C.c_int),
+    "cav_net_correct": ([_P, C.c_int32, _P, _P], C.c_int),
+    "cav_net_train_step": ([_P, C.c_int32, C.c_int32, _P, _P, C.POINTER(C.c_int32), C.c_int64, C.c_double,
+                            C.POINTER(C.c_double)], C.c_int),
+    "cav_learned_pairs": ([_P, C.c_int32, _P, C.c_int32, _P, _P], C.c_int),
+    "cav_attach_net": ([_P, _P, C.c_double], C.c_int),
 }
+NET_WEIGHTS = 10944
 EXPORTED_SYMBOLS = tuple(_SIGS)
 
 _lib = None
@@ -224,11 +237,98 @@ class Analysis:
         return dofs, inv
 
 
-def _dev_ptr(t):
+def _dev_ptr(t, dtype=None):
     import torch
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-        raise TypeError("expected a contiguous float64 tensor on a ROCm device")
+    dtype = torch.float64 if dtype is None else dtype
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"expected a contiguous {dtype} tensor on a ROCm device")
     return C.c_void_p(t.data_ptr())
+
+
+class Net:
+    """Learned correction net (3x3 periodic convs 3 -> 32 -> 32 -> 3) on one device:
+    forward, FP64 correction, Adam training steps; weights live on the device."""
+
+    def __init__(self, device: int = 0, weights: Optional[np.ndarray] = None):
+        import torch
+        self._torch = torch
+        self.device = torch.device("cuda", device)
+        self._L = lib()
+        h = C.c_void_p()
+        st = self._L.cav_net_create(C.byref(h), int(device), self._stream())
+        if st != 0:
+            raise CAVError(st, "cav_net_create failed")
+        self._h = h
+        if weights is not None:
+            self.set_weights(weights)
+
+    def _stream(self):
+        return C.c_void_p(self._torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _check(self, st):
+        if st != 0:
+            raise CAVError(st, self._L.cav_net_last_error(self._h).decode())
+
+    def _sync_stream(self):
+        self._L.cav_net_set_stream(self._h, self._stream())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.cav_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, w) -> None:
+        self._sync_stream()
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        if w.shape != (NET_WEIGHTS,):
+            raise ValueError(f"expected {NET_WEIGHTS} weights")
+        self._check(self._L.cav_net_set_weights(self._h, _arr(w, C.c_float)))
+
+    def weights(self):
+        """(master weights, gradient of the last training step) as float32 numpy arrays."""
+        self._sync_stream()
+        w = np.zeros(NET_WEIGHTS, dtype=np.float32)
+        g = np.zeros(NET_WEIGHTS, dtype=np.float32)
+        self._check(self._L.cav_net_get_weights(self._h, _arr(w, C.c_float), _arr(g, C.c_float)))
+        return w, g
+
+    def forward(self, x, N: int):
+        """x: float32 device tensor (batch, 3, N, N) -> N(x) of the same shape."""
+        self._sync_stream()
+        out = self._torch.empty_like(x)
+        self._check(self._L.cav_net_forward(self._h, int(N), int(x.shape[0]),
+                                            _dev_ptr(x, self._torch.float32), _dev_ptr(out, self._torch.float32)))
+        return out
+
+    def correct(self, r, N: int):
+        """c = ||r|| N(r/||r||) with the pressure mean removed (float64 device vectors)."""
+        self._sync_stream()
+        c = self._torch.empty_like(r)
+        self._check(self._L.cav_net_correct(self._h, int(N), _dev_ptr(r), _dev_ptr(c)))
+        return c
+
+    def train_step(self, rhat, ehat, N: int, index=None, lr: float = 1e-3) -> float:
+        """One Adam step on samples `index` (host ints) of rhat/ehat (float32 device,
+        n_samples x 3N^2); returns the loss before the update."""
+        self._sync_stream()
+        f32 = self._torch.float32
+        ns = int(rhat.shape[0])
+        if index is None:
+            idx, batch = None, ns
+        else:
+            idx = np.ascontiguousarray(index, dtype=np.int32)
+            batch = int(idx.size)
+        loss = C.c_double(0.0)
+        self._check(self._L.cav_net_train_step(self._h, int(N), batch, _dev_ptr(rhat, f32), _dev_ptr(ehat, f32),
+                                               _arr(idx, C.c_int32) if idx is not None else None, ns, float(lr),
+                                               C.byref(loss)))
+        return loss.value
 
 
 class Solver:
@@ -326,17 +426,33 @@ class Solver:
         self._check(self._L.cav_level_apply(self._h, int(level), int(op), _dev_ptr(x), _dev_ptr(y)))
         return y
 
-    def fgmres_solve(self, b, rtol: float = 1e-10, max_it: int = 150, out=None, history: bool = True):
+    def fgmres_solve(self, b, rtol: float = 1e-10, max_it: int = 150, out=None, history: bool = True,
+                     learned: bool = False):
         self._sync_stream()
         x = self.empty() if out is None else out
         hist = np.zeros(max_it, dtype=np.float64)
-        o = FgmresOpts(float(rtol), int(max_it), 0, _arr(hist, C.c_double) if history else None)
+        o = FgmresOpts(float(rtol), int(max_it), 1 if learned else 0, _arr(hist, C.c_double) if history else None)
         info = SolveInfo()
         st = self._check(self._L.cav_fgmres_solve(self._h, _dev_ptr(b), _dev_ptr(x), C.byref(o), C.byref(info)))
         d = {f: getattr(info, f) for f, _ in SolveInfo._fields_}
         d["status"] = st
         d["history"] = hist[:info.iterations].copy()
         return x, d
+
+    def attach_net(self, net: Optional[Net], margin: float = 1e-3) -> None:
+        self._check(self._L.cav_attach_net(self._h, net._h if net is not None else None, float(margin)))
+        self._net = net  # keep the handle alive while attached
+
+    def learned_pairs(self, xstar, iters: int = 3):
+        """(rhat, ehat) float32 device tensors (count*iters, 3N^2) from V-cycle iterations on b = K x*."""
+        self._sync_stream()
+        count = int(xstar.shape[0])
+        t = self._torch
+        rh = t.empty((count * iters, self.n()), dtype=t.float32, device=self.device)
+        eh = t.empty_like(rh)
+        self._check(self._L.cav_learned_pairs(self._h, count, _dev_ptr(xstar), int(iters),
+                                              _dev_ptr(rh, t.float32), _dev_ptr(eh, t.float32)))
+        return rh, eh
 
     def kernel_timing(self, enable: bool) -> Dict:
         """Start (True) or stop (False) live HIP-event timing of the explicit-patch

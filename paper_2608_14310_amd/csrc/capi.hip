@@ -153,6 +153,39 @@ double dnorm(Ctx& c, const double* x, int64_t n) {
   return std::sqrt(v);
 }
 
+// Stage workspace: r', c, K c (3 n doubles) and 8 scalars
+// {||r'||^2, <r', Kc>, ||Kc||^2, gamma, accepted, rejected, -, -}.
+void ensure_stage_workspace(Ctx& c) {
+  const Level& F = c.lv.back();
+  const int64_t n = 3 * int64_t(F.N) * F.N;
+  if (c.d_st && c.st_n == n) return;
+  dev_free(c, c.d_st);
+  dev_free(c, c.d_sc);
+  c.d_st = static_cast<double*>(dev_alloc(c, size_t(3 * n) * sizeof(double)));
+  c.d_sc = static_cast<double*>(dev_alloc(c, 8 * sizeof(double)));
+  c.st_n = n;
+}
+
+// Learned correction after z0 = V(v): r' = v - K z0, c = ||r'|| N(r'/||r'||)
+// (pressure mean removed), gamma = <r', Kc>/||Kc||^2; z0 += gamma c when the
+// stage cuts ||r'||^2 by at least the margin, else z0 is kept. All on device.
+void learned_stage(Ctx& c, const double* v, double* z, int nbk) {
+  const Level& F = c.lv.back();
+  hipStream_t s = c.stream;
+  const int64_t n = 3 * int64_t(F.N) * F.N;
+  double* rp = c.d_st;
+  double* cc = c.d_st + n;
+  double* kc = c.d_st + 2 * n;
+  launch_apply_op(F, z, rp, v, s);
+  launch_dots(rp, n, 1, rp, n, c.d_part, nbk, c.d_sc, s);
+  net_correct_f64(*c.net, F.N, rp, c.d_sc, cc, c.d_part, s);
+  launch_apply_op(F, cc, kc, nullptr, s);
+  launch_dots(kc, n, 1, rp, n, c.d_part, nbk, c.d_sc + 1, s);
+  launch_dots(kc, n, 1, kc, n, c.d_part, nbk, c.d_sc + 2, s);
+  launch_stage_decide(c.d_sc, c.net_margin, c.d_sc + 3, c.d_sc + 4, s);
+  launch_axpy_dev(z, c.d_sc + 3, cc, n, s);
+}
+
 }  // namespace
 }  // namespace cav
 
@@ -422,6 +455,12 @@ cav_status cav_fgmres_solve(cav_ctx ctx, const double* b, double* x, const cav_f
   double* Z = c.d_Z;
   k_axpby<<<nblocks(n), TPB, 0, s>>>(V, 1.0 / beta, c.d_bb, 0.0, n);
   const int nbk = dots_blocks(n);
+  const bool learned = opts && opts->use_learned;
+  if (learned) {
+    require(c.net != nullptr, CAV_ERR_NOT_BUILT, "use_learned is set but no net is attached");
+    ensure_stage_workspace(c);
+    CAV_HIP(hipMemsetAsync(c.d_sc, 0, 8 * sizeof(double), s));
+  }
   std::vector<double> H(size_t(max_it + 1) * max_it, 0.0), cs(max_it), sn(max_it), g(max_it + 1, 0.0);
   auto Hat = [&](int i, int j) -> double& { return H[size_t(j) * (max_it + 1) + i]; };
   g[0] = beta;
@@ -436,6 +475,7 @@ cav_status cav_fgmres_solve(cav_ctx ctx, const double* b, double* x, const cav_f
     double* vj = V + int64_t(j) * n;
     double* zj = Z + int64_t(j) * n;
     vcycle_top(c, vj, zj);
+    if (learned) learned_stage(c, vj, zj, nbk);
     double* w = c.d_w;
     launch_apply_op(F, zj, w, nullptr, s);
     // CGS2
@@ -488,6 +528,13 @@ cav_status cav_fgmres_solve(cav_ctx ctx, const double* b, double* x, const cav_f
   inf.est_rel_residual = est;
   inf.true_rel_residual = rn / beta;
   inf.pressure_mean_removed = pmean;
+  if (learned) {
+    double cnt[2] = {0.0, 0.0};
+    CAV_HIP(hipMemcpyAsync(cnt, c.d_sc + 4, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    CAV_HIP(hipStreamSynchronize(s));
+    inf.learned_accepted = int32_t(cnt[0]);
+    inf.learned_rejected = int32_t(cnt[1]);
+  }
   if (info) *info = inf;
   if (!conv) return CAV_WARN_NOT_CONVERGED;
   if (inf.true_rel_residual > 10.0 * rtol) return CAV_WARN_FLOOR_LIMITED;
@@ -614,6 +661,66 @@ cav_status cav_export_ee(cav_ctx ctx, int level, int64_t* rowptr, int32_t* col, 
   if (col) std::memcpy(col, E.col.data(), E.col.size() * sizeof(int32_t));
   if (val) std::memcpy(val, E.val.data(), E.val.size() * sizeof(double));
   return CAV_OK;
+}
+
+
+cav_status cav_attach_net(cav_ctx ctx, cav_net net, double margin) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(std::isfinite(margin) && margin >= 0.0 && margin < 1.0, CAV_ERR_INVALID_ARG, "margin must be in [0, 1)");
+  require(!net || net->n.device == c.device, CAV_ERR_INVALID_ARG, "net and context must share a device");
+  c.net = net ? &net->n : nullptr;
+  c.net_margin = margin;
+  return CAV_OK;
+  API_END
+}
+
+cav_status cav_learned_pairs(cav_ctx ctx, int32_t count, const double* xstar, int32_t iters, float* rhat,
+                             float* ehat) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require(count >= 0 && iters >= 1 && iters <= 64, CAV_ERR_INVALID_ARG, "count >= 0 and 1 <= iters <= 64");
+  if (count == 0) return CAV_OK;
+  require(xstar && rhat && ehat, CAV_ERR_INVALID_ARG, "xstar, rhat and ehat must be device pointers");
+  hipStream_t s = c.stream;
+  Level& F = c.lv.back();
+  const int64_t n = 3 * int64_t(F.N) * F.N;
+  const int nbk = dots_blocks(n);
+  if (!c.d_pw || c.pw_n != n) {
+    dev_free(c, c.d_pw);
+    c.d_pw = static_cast<double*>(dev_alloc(c, size_t(5 * n + nbk + 1) * sizeof(double)));
+    c.pw_n = n;
+  }
+  double* pb = c.d_pw;
+  double* px = pb + n;
+  double* pr = pb + 2 * n;
+  double* pz = pb + 3 * n;
+  double* pe = pb + 4 * n;
+  double* nrm = pb + 5 * n;
+  double* part = nrm + 1;
+  for (int32_t q = 0; q < count; ++q) {
+    const double* xs = xstar + int64_t(q) * n;
+    launch_apply_op(F, xs, pb, nullptr, s);  // b = K x*
+    launch_fill(px, 0.0, n, s);
+    for (int32_t k = 0; k < iters; ++k) {
+      launch_apply_op(F, px, pr, pb, s);     // r = b - K x
+      vcycle_top(c, pr, pz);
+      k_axpby<<<nblocks(n), TPB, 0, s>>>(px, 1.0, pz, 1.0, n);
+      launch_apply_op(F, px, pr, pb, s);
+      k_axpby<<<nblocks(n), TPB, 0, s>>>(pe, 1.0, xs, 0.0, n);
+      k_axpby<<<nblocks(n), TPB, 0, s>>>(pe, -1.0, px, 1.0, n);
+      launch_dots(pr, n, 1, pr, n, part, nbk, nrm, s);
+      const int64_t off = (int64_t(q) * iters + k) * n;
+      launch_pair_write(pr, pe, nrm, rhat + off, ehat + off, n, s);
+    }
+  }
+  CAV_HIP(hipGetLastError());
+  CAV_HIP(hipStreamSynchronize(s));
+  return CAV_OK;
+  API_END
 }
 
 }  // extern "C"

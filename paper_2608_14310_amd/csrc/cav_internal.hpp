@@ -103,6 +103,45 @@ struct Level {
   double* d_part = nullptr;               // reduction partials
 };
 
+// Learned correction stage: 3x3 periodic conv net 3 -> 32 -> 32 -> 3 (no biases).
+constexpr int NET_CH = 32;
+constexpr int NET_W = 32 * 3 * 9 + 32 * 32 * 9 + 3 * 32 * 9;  // 10 944 master weights
+// packed bf16-rounded float layouts used by the kernels (offsets into Net::d_pk)
+constexpr int PK_L1F = 0;                 // layer 1 forward  [a][c][ci][co]  9 x 3 x 32
+constexpr int PK_L2T = PK_L1F + 864;      // layer 2 backward [a][c][co][ci]  9 x 32 x 32
+constexpr int PK_L3F = PK_L2T + 9216;     // layer 3 forward  [a][c][ci][co]  9 x 32 x 3
+constexpr int PK_L3T = PK_L3F + 864;      // layer 3 backward [a][c][co][ci]  9 x 3 x 32
+constexpr int PK_TOTAL = PK_L3T + 864;
+
+struct Net {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  float* d_w = nullptr;          // master weights (FP32), flat: W1 (32,3,3,3), W2 (32,32,3,3), W3 (3,32,3,3)
+  float* d_g = nullptr;          // gradient of the last training step
+  float* d_m = nullptr;          // Adam moments
+  float* d_v = nullptr;
+  int64_t adam_t = 0;
+  float* d_pk = nullptr;         // PK_TOTAL floats
+  uint16_t* d_w2m = nullptr;     // layer 2 for the matrix-core kernel: bf16 [co][(a*3+c)*32+ci]
+  int64_t cap_pix = 0;           // pixels (batch x N^2) the activation buffers hold
+  uint16_t* d_a1 = nullptr;      // NHWC bf16, 32 channels
+  uint16_t* d_a2 = nullptr;
+  float* d_y3 = nullptr;         // [b][3][N][N]
+  float* d_g3 = nullptr;         // [b][3][N][N]
+  float* d_g2 = nullptr;         // NHWC FP32
+  float* d_g1 = nullptr;
+  float* d_wpart = nullptr;      // weight-gradient partials
+  int64_t wpart_cap = 0;
+  double* d_ls = nullptr;        // loss partials and per-sample sums
+  int64_t ls_cap = 0;
+  int32_t* d_idx = nullptr;
+  int idx_cap = 0;
+  double* d_red = nullptr;       // reductions of the FP64 stage (norms)
+  int64_t red_cap = 0;
+  std::vector<void*> allocs;
+};
+
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -126,6 +165,14 @@ struct Ctx {
   double *d_h = nullptr, *d_part = nullptr;
   double* h_pinned = nullptr;
   std::vector<void*> allocs;
+  // learned stage (not owned) and its workspace
+  Net* net = nullptr;
+  double net_margin = 1e-3;
+  double* d_st = nullptr;        // r', c, K c (3 n)
+  double* d_sc = nullptr;        // stage scalars and counters
+  int64_t st_n = 0;
+  double *d_pw = nullptr;        // residual-pair workspace (5 n)
+  int64_t pw_n = 0;
   // live timing of the explicit-patch GEMV and of whole V-cycles (HIP events)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -184,7 +231,25 @@ int dots_blocks(int64_t n);
 void* dev_alloc(Ctx& c, size_t bytes);
 void dev_free(Ctx& c, void* p);
 
+// learned stage (kernels_learned.hip)
+void net_alloc(Net& n, int64_t pix);
+void* net_dev_alloc(Net& n, size_t bytes);
+void net_pack(Net& n, hipStream_t s);
+void net_forward_f32(Net& n, int N, int B, const float* in, const int32_t* idx, float* out, hipStream_t s);
+// c = ||r|| N(r / ||r||) with the pressure mean of c removed; nrm2 = device ||r||^2 (one double)
+void net_correct_f64(Net& n, int N, const double* r, const double* nrm2, double* c, double* part, hipStream_t s);
+void net_train_step(Net& n, int N, int B, const float* rhat, const float* ehat, const int32_t* idx, double lr,
+                    double* loss, hipStream_t s);
+void launch_pair_write(const double* r, const double* e, const double* nrm2, float* rhat, float* ehat, int64_t n,
+                       hipStream_t s);
+void launch_stage_decide(const double* sc, double margin, double* gamma_out, double* counters, hipStream_t s);
+void launch_axpy_dev(double* y, const double* a, const double* x, int64_t n, hipStream_t s);
+
 }  // namespace cav
+
+struct cav_net_s {
+  cav::Net n;
+};
 
 #define CAV_HIP(call)                                                                 \
   do {                                                                                \
