@@ -261,6 +261,17 @@ cav_status cav_net_correct(cav_net net, int32_t N, const double* r, double* c);
  * receives L before the update; the call synchronises. */
 cav_status cav_net_train_step(cav_net net, int32_t N, int32_t batch, const float* rhat, const float* ehat,
                               const int32_t* index, int64_t n_samples, double lr, double* loss);
+/* Same Adam step on a loss through K = the finest-level K_E of ctx (N = the
+ * context's finest grid; K_E is symmetric, so K^T = K in the gradients),
+ * with c_s = N(rhat_s), s = index[b]:
+ *   kind 0 (residual):          L = (1/B) sum_b ||K c_s - rhat_s||^2 / ||rhat_s||^2
+ *   kind 1 (minimal residual):  L = (1/B) sum_b (1 - <K c_s, rhat_s>^2 / (||K c_s||^2 ||rhat_s||^2)),
+ * i.e. the squared residual left by the best multiple of c_s, which is what
+ * the FGMRES stage's minimal-residual step achieves; it is invariant to the
+ * scale of c_s. Since K ehat = rhat both measure the pair's error through K.
+ * The work runs on the context's stream; the call synchronises. */
+cav_status cav_net_train_step_residual(cav_net net, cav_ctx ctx, int32_t kind, int32_t batch, const float* rhat,
+                                       const int32_t* index, int64_t n_samples, double lr, double* loss);
 /* Training pairs from the context's V-cycle: for each exact solution x*_q
  * (device, count x 3N^2), b = K x*, x_0 = 0, x_k = x_{k-1} + V(b - K x_{k-1});
  * after iteration k (1..iters) writes rhat = r_k/||r_k||, ehat = (x* - x_k)/||r_k||

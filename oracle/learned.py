@@ -22,10 +22,14 @@ bfloat16, round-to-nearest-even each time) before they enter a convolution;
 sums are exact here (float64). The float32 accumulation of the device kernels
 differs from this only by the order and precision of the sums.
 
-Training (reading): pairs (r_hat, e_hat) = (r, e) / ||r||; loss
+Training (reading): pairs (r_hat, e_hat) = (r, e) / ||r||; error loss
     L = (1/B) sum_b ||N(r_hat_b) - e_hat_b||^2 / ||e_hat_b||^2,
-gradients by the chain rule through the stored activations (the bf16 weight
-rounding is passed straight through to the float32 master weights), Adam.
+or residual loss L = (1/B) sum_b ||K N(r_hat_b) - r_hat_b||^2 / ||r_hat_b||^2
+(the same error measured through K, since K e_hat = r_hat), or its
+scale-invariant form, the residual left by the best multiple of N(r_hat_b)
+(minimal-residual loss); gradients by the
+chain rule through the stored activations (the bf16 weight rounding is passed
+straight through to the float32 master weights), Adam.
 
 Pairs (reading): x* with random entries, b = K x*, x_0 = 0,
 x_k = x_{k-1} + V(b - K x_{k-1}); the pair after iteration k is
@@ -134,12 +138,54 @@ def loss_and_grad(x: np.ndarray, e: np.ndarray, w: np.ndarray, bf16: bool = Fals
     ne2 = np.einsum("bcij,bcij->b", e, e)
     loss = float(np.mean(np.einsum("bcij,bcij->b", d, d) / ne2))
     g3 = (2.0 / B) * d / ne2[:, None, None, None]
+    return loss, backward(cc, g3)
+
+
+def residual_loss_and_grad(x: np.ndarray, K, w: np.ndarray, bf16: bool = False):
+    """Residual-norm loss (reading): with c_b = N(r_b) as a grid vector,
+        L = (1/B) sum_b ||K c_b - r_b||^2 / ||r_b||^2,
+    i.e. the error c_b - e_b measured in the norm ||K .|| (K e_b = r_b), which is
+    what the stage's minimal-residual step sees. Gradient through K^T."""
+    y3, cc = forward(x, w, bf16)
+    B = x.shape[0]
+    loss = 0.0
+    g3 = np.zeros_like(y3)
+    for b in range(B):
+        r = x[b].ravel()
+        res = K @ y3[b].ravel() - r
+        nr2 = float(r @ r)
+        loss += float(res @ res) / nr2
+        g3[b] = ((2.0 / B) * (K.T @ res) / nr2).reshape(y3.shape[1:])
+    return loss / B, backward(cc, g3)
+
+
+def minres_loss_and_grad(x: np.ndarray, K, w: np.ndarray, bf16: bool = False):
+    """Minimal-residual loss (reading): with c_b = N(r_b), a = <K c_b, r_b>,
+    b = ||K c_b||^2, n = ||r_b||^2,
+        L = (1/B) sum_b (1 - a^2 / (b n)) = (1/B) sum_b min_g ||r_b - g K c_b||^2 / n,
+    the residual the stage's minimal-residual step leaves, scale-invariant in c.
+    dL/dc_b = -(2/B) (a / (n b)) K^T (r_b - (a/b) K c_b)."""
+    y3, cc = forward(x, w, bf16)
+    B = x.shape[0]
+    loss = 0.0
+    g3 = np.zeros_like(y3)
+    for k in range(B):
+        r = x[k].ravel()
+        kc = K @ y3[k].ravel()
+        a, b, n = float(kc @ r), float(kc @ kc), float(r @ r)
+        loss += 1.0 - a * a / (b * n)
+        g3[k] = (-(2.0 / B) * (a / (n * b)) * (K.T @ (r - (a / b) * kc))).reshape(y3.shape[1:])
+    return loss / B, backward(cc, g3)
+
+
+def backward(cc: Cache, g3: np.ndarray) -> np.ndarray:
+    """Flat gradient (10 944) of a loss whose derivative in y3 is g3."""
     dW3 = conv_weight_grad(g3, cc.a2)
     g2 = conv_transpose(g3, cc.Ws[2]) * (cc.a2 > 0)
     dW2 = conv_weight_grad(g2, cc.a1)
     g1 = conv_transpose(g2, cc.Ws[1]) * (cc.a1 > 0)
     dW1 = conv_weight_grad(g1, cc.x)
-    return loss, np.concatenate([dW1.ravel(), dW2.ravel(), dW3.ravel()])
+    return np.concatenate([dW1.ravel(), dW2.ravel(), dW3.ravel()])
 
 
 @dataclasses.dataclass

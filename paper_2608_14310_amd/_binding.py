@@ -115,6 +115,8 @@ _SIGS = {
     "cav_net_correct": ([_P, C.c_int32, _P, _P], C.c_int),
     "cav_net_train_step": ([_P, C.c_int32, C.c_int32, _P, _P, C.POINTER(C.c_int32), C.c_int64, C.c_double,
                             C.POINTER(C.c_double)], C.c_int),
+    "cav_net_train_step_residual": ([_P, _P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_int32), C.c_int64, C.c_double,
+                                     C.POINTER(C.c_double)], C.c_int),
     "cav_learned_pairs": ([_P, C.c_int32, _P, C.c_int32, _P, _P], C.c_int),
     "cav_attach_net": ([_P, _P, C.c_double], C.c_int),
 }
@@ -438,6 +440,24 @@ class Solver:
         d["status"] = st
         d["history"] = hist[:info.iterations].copy()
         return x, d
+
+    def train_net_residual(self, net: Net, rhat, index=None, lr: float = 1e-3, kind: str = "residual") -> float:
+        """One Adam step of `net` on the residual-norm loss through this context's
+        finest K_E; rhat float32 device (n_samples, 3N^2); returns the loss."""
+        self._sync_stream()
+        f32 = self._torch.float32
+        ns = int(rhat.shape[0])
+        if index is None:
+            idx, batch = None, ns
+        else:
+            idx = np.ascontiguousarray(index, dtype=np.int32)
+            batch = int(idx.size)
+        loss = C.c_double(0.0)
+        self._check(self._L.cav_net_train_step_residual(net._h, self._h, {"residual": 0, "minres": 1}[kind], batch,
+                                                        _dev_ptr(rhat, f32),
+                                                        _arr(idx, C.c_int32) if idx is not None else None, ns,
+                                                        float(lr), C.byref(loss)))
+        return loss.value
 
     def attach_net(self, net: Optional[Net], margin: float = 1e-3) -> None:
         self._check(self._L.cav_attach_net(self._h, net._h if net is not None else None, float(margin)))

@@ -723,4 +723,75 @@ cav_status cav_learned_pairs(cav_ctx ctx, int32_t count, const double* xstar, in
   API_END
 }
 
+cav_status cav_net_train_step_residual(cav_net net, cav_ctx ctx, int32_t kind, int32_t batch, const float* rhat,
+                                       const int32_t* index, int64_t n_samples, double lr, double* loss) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(net != nullptr, CAV_ERR_INVALID_ARG, "net is NULL");
+  require(c.built, CAV_ERR_NOT_BUILT, "operator not built");
+  require(net->n.device == c.device, CAV_ERR_INVALID_ARG, "net and context must share a device");
+  require(batch >= 1 && batch <= 65535, CAV_ERR_INVALID_ARG, "batch must be in [1, 65535]");
+  require(rhat != nullptr, CAV_ERR_INVALID_ARG, "rhat must be a device pointer");
+  require(std::isfinite(lr) && lr > 0.0, CAV_ERR_INVALID_ARG, "lr must be positive");
+  require(kind == 0 || kind == 1, CAV_ERR_INVALID_ARG, "kind must be 0 (residual) or 1 (minimal residual)");
+  Net& n = net->n;
+  Level& F = c.lv.back();
+  const int N = F.N;
+  require(N >= 8, CAV_ERR_INVALID_ARG, "the finest grid must have N >= 8");
+  hipStream_t s = c.stream;
+  const int64_t n3 = 3 * int64_t(N) * N;
+  const int32_t* didx = net_upload_index(n, index, batch, n_samples, s);
+  net_forward_train(n, N, batch, rhat, didx, s);
+  const int nbk = dots_blocks(n3);
+  if (n.rl_n != n3) {
+    if (n.d_rl) {
+      auto it = std::find(n.allocs.begin(), n.allocs.end(), (void*)n.d_rl);
+      if (it != n.allocs.end()) n.allocs.erase(it);
+      CAV_HIP(hipFree(n.d_rl));
+      n.d_rl = nullptr;
+    }
+    n.d_rl = static_cast<double*>(net_dev_alloc(n, size_t(4 * n3 + nbk) * sizeof(double)));
+    n.rl_n = n3;
+  }
+  double* r64 = n.d_rl;
+  double* c64 = r64 + n3;
+  double* res = c64 + n3;
+  double* q = res + n3;
+  double* part = q + n3;
+  double* sums = net_loss_sums(n, 3 * batch);  // 6 doubles per sample
+  for (int b = 0; b < batch; ++b) {
+    double* sb = sums + 6 * b;
+    launch_sample_f64(rhat, didx, b, n3, r64, s);
+    launch_sample_f64(n.d_y3, nullptr, b, n3, c64, s);
+    if (kind == 0) {
+      launch_apply_op(F, c64, res, r64, s);               // res = r - K c
+      launch_dots(res, n3, 1, res, n3, part, nbk, sb, s);
+      launch_dots(r64, n3, 1, r64, n3, part, nbk, sb + 1, s);
+      launch_apply_op(F, res, q, nullptr, s);             // K^T (r - K c) = K (r - K c), K_E symmetric
+      launch_scaled_f32(q, sb, -2.0 / batch, n3, n.d_g3 + b * n3, s);
+    } else {
+      launch_apply_op(F, c64, q, nullptr, s);             // q = K c
+      launch_dots(q, n3, 1, r64, n3, part, nbk, sb, s);   // a = <Kc, r>
+      launch_dots(q, n3, 1, q, n3, part, nbk, sb + 1, s); // b = ||Kc||^2
+      launch_dots(r64, n3, 1, r64, n3, part, nbk, sb + 2, s);
+      launch_mr_scalars(sb, batch, s);
+      launch_sub_gamma(res, r64, q, sb, n3, s);           // res = r - gamma K c
+      launch_apply_op(F, res, q, nullptr, s);             // K res
+      launch_coef_f32(q, sb, n3, n.d_g3 + b * n3, s);     // -(2/B) a/(n b) K res
+    }
+  }
+  net_backward_update(n, N, batch, rhat, didx, lr, s);
+  std::vector<double> h(size_t(6) * batch);
+  CAV_HIP(hipMemcpyAsync(h.data(), sums, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipStreamSynchronize(s));
+  if (loss) {
+    double L = 0.0;
+    for (int b = 0; b < batch; ++b) L += kind == 0 ? h[6 * b] / h[6 * b + 1] : h[6 * b + 4];
+    *loss = L / batch;
+  }
+  return CAV_OK;
+  API_END
+}
+
 }  // extern "C"

@@ -139,6 +139,8 @@ struct Net {
   int idx_cap = 0;
   double* d_red = nullptr;       // reductions of the FP64 stage (norms)
   int64_t red_cap = 0;
+  double* d_rl = nullptr;        // residual-loss workspace: r, c, res, K res (4 x 3N^2) + partials
+  int64_t rl_n = 0;
   std::vector<void*> allocs;
 };
 
@@ -240,6 +242,15 @@ void net_forward_f32(Net& n, int N, int B, const float* in, const int32_t* idx, 
 void net_correct_f64(Net& n, int N, const double* r, const double* nrm2, double* c, double* part, hipStream_t s);
 void net_train_step(Net& n, int N, int B, const float* rhat, const float* ehat, const int32_t* idx, double lr,
                     double* loss, hipStream_t s);
+void net_forward_train(Net& n, int N, int B, const float* rhat, const int32_t* idx, hipStream_t s);
+void net_backward_update(Net& n, int N, int B, const float* rhat, const int32_t* idx, double lr, hipStream_t s);
+double* net_loss_sums(Net& n, int B);  // 2B doubles: per sample {||res||^2, ||r||^2}
+const int32_t* net_upload_index(Net& n, const int32_t* index, int batch, int64_t n_samples, hipStream_t s);
+void launch_sample_f64(const float* src, const int32_t* idx, int b, int64_t n3, double* dst, hipStream_t s);
+void launch_scaled_f32(const double* q, const double* sums, double coef, int64_t n3, float* dst, hipStream_t s);
+void launch_mr_scalars(double* sums, int B, hipStream_t s);
+void launch_coef_f32(const double* q, const double* sums, int64_t n3, float* dst, hipStream_t s);
+void launch_sub_gamma(double* y, const double* x, const double* z, const double* sums, int64_t n3, hipStream_t s);
 void launch_pair_write(const double* r, const double* e, const double* nrm2, float* rhat, float* ehat, int64_t n,
                        hipStream_t s);
 void launch_stage_decide(const double* sc, double margin, double* gamma_out, double* counters, hipStream_t s);

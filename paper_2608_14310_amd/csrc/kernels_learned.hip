@@ -505,6 +505,51 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
   w[t] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
 }
 
+// sample b of a planar FP32 batch (sample index idx[b] when given) -> FP64 vector
+__global__ void k_sample_f64(const float* __restrict__ src, const int32_t* __restrict__ idx, int b, int64_t n3,
+                             double* __restrict__ dst) {
+  const int64_t k = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (k >= n3) return;
+  const int64_t sb = idx ? idx[b] : b;
+  dst[k] = double(src[sb * n3 + k]);
+}
+
+// g3_b = coef * q / sums[1] with sums = {||res||^2, ||r||^2}, as FP32
+__global__ void k_scaled_f32(const double* __restrict__ q, const double* __restrict__ sums, double coef, int64_t n3,
+                             float* __restrict__ dst) {
+  const int64_t k = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (k >= n3) return;
+  dst[k] = float(coef * q[k] / sums[1]);
+}
+
+// Minimal-residual loss pieces from sums = {a = <Kc, r>, b = ||Kc||^2, n = ||r||^2}:
+// gamma = a / b (0 when b = 0) into sums[3], loss 1 - a^2/(b n) into sums[4],
+// output-gradient coefficient -(2/B) a/(n b) into sums[5].
+__global__ void k_mr_scalars(double* __restrict__ sums, int B) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double a = sums[0], b = sums[1], n = sums[2];
+  const bool ok = b > 0.0 && n > 0.0;
+  sums[3] = ok ? a / b : 0.0;
+  sums[4] = ok ? 1.0 - a * a / (b * n) : 1.0;
+  sums[5] = ok ? -2.0 / double(B) * a / (n * b) : 0.0;
+}
+
+// dst = float(sums[5] * q)
+__global__ void k_coef_f32(const double* __restrict__ q, const double* __restrict__ sums, int64_t n3,
+                           float* __restrict__ dst) {
+  const int64_t k = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (k >= n3) return;
+  dst[k] = float(sums[5] * q[k]);
+}
+
+// y = x - sums[3] * z
+__global__ void k_sub_gamma(double* __restrict__ y, const double* __restrict__ x, const double* __restrict__ z,
+                            const double* __restrict__ sums, int64_t n3) {
+  const int64_t k = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (k >= n3) return;
+  y[k] = x[k] - sums[3] * z[k];
+}
+
 // pair output: rhat = r / ||r||, ehat = e / ||r|| (FP32)
 __global__ void k_pair_write(const double* __restrict__ r, const double* __restrict__ e,
                              const double* __restrict__ nrm2, float* __restrict__ rh, float* __restrict__ eh,
@@ -614,11 +659,58 @@ void net_correct_f64(Net& n, int N, const double* r, const double* nrm2, double*
   launch_pressure_mean_remove(c, N, part, s);
 }
 
+static int loss_blocks(int64_t n3) { return int(std::min<int64_t>(std::max<int64_t>(n3 / 4096, 1), 64)); }
+
+static void ensure_ls(Net& n, int B, int lblk) {
+  if (int64_t(B) * (2 * lblk + 2) > n.ls_cap) {
+    net_free(n, n.d_ls);
+    n.ls_cap = int64_t(B) * (2 * lblk + 2);
+    n.d_ls = static_cast<double*>(net_dev_alloc(n, size_t(n.ls_cap) * sizeof(double)));
+  }
+}
+
+void net_forward_train(Net& n, int N, int B, const float* rhat, const int32_t* idx, hipStream_t s) {
+  const int lgN = ilog2(N);
+  const int64_t n2 = int64_t(N) * N;
+  net_alloc_train(n, n2 * B);
+  dim3 g(nb(n2), B);
+  k_l1<float><<<g, TPB, 0, s>>>(rhat, idx, nullptr, lgN, n.d_pk + PK_L1F, n.d_a1);
+  forward_hidden(n, lgN, B, s);
+  k_l3<float><<<g, TPB, 0, s>>>(n.d_a2, lgN, n.d_pk + PK_L3F, nullptr, n.d_y3);
+}
+
+double* net_loss_sums(Net& n, int B) {
+  ensure_ls(n, B, 1);
+  return n.d_ls + int64_t(n.ls_cap) - 2 * B;
+}
+
 void net_train_step(Net& n, int N, int B, const float* rhat, const float* ehat, const int32_t* idx, double lr,
                     double* loss, hipStream_t s) {
-  const int lgN = ilog2(N);
   const int64_t n2 = int64_t(N) * N, n3 = 3 * n2;
-  net_alloc_train(n, n2 * B);
+  const int lblk = loss_blocks(n3);
+  ensure_ls(n, B, lblk);
+  double* lpart = n.d_ls;
+  double* lsum = net_loss_sums(n, B);
+  net_forward_train(n, N, B, rhat, idx, s);
+  // loss and its gradient
+  k_loss_partial<<<dim3(lblk, B), TPB, 0, s>>>(n.d_y3, ehat, idx, n3, lpart);
+  k_loss_final<<<nb(B), TPB, 0, s>>>(lpart, lblk, B, lsum);
+  k_g3<<<dim3(nb(n3), B), TPB, 0, s>>>(n.d_y3, ehat, idx, lsum, B, n3, n.d_g3);
+  net_backward_update(n, N, B, rhat, idx, lr, s);
+  if (loss) {
+    std::vector<double> h(size_t(2) * B);
+    CAV_HIP(hipMemcpyAsync(h.data(), lsum, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    CAV_HIP(hipStreamSynchronize(s));
+    double L = 0.0;
+    for (int b = 0; b < B; ++b) L += h[2 * b + 1] / h[2 * b];
+    *loss = L / B;
+  }
+}
+
+// From g3 = dL/dy3 (in n.d_g3): weight gradients, Adam, repack.
+void net_backward_update(Net& n, int N, int B, const float* rhat, const int32_t* idx, double lr, hipStream_t s) {
+  const int lgN = ilog2(N);
+  const int64_t n2 = int64_t(N) * N;
   const int tiles = B * (N / 8) * (N / 8);
   const int nblk = std::min(tiles, 512);
   if (int64_t(nblk) * 9216 > n.wpart_cap) {
@@ -626,24 +718,7 @@ void net_train_step(Net& n, int N, int B, const float* rhat, const float* ehat, 
     n.d_wpart = static_cast<float*>(net_dev_alloc(n, size_t(nblk) * 9216 * sizeof(float)));
     n.wpart_cap = int64_t(nblk) * 9216;
   }
-  const int lblk = int(std::min<int64_t>(std::max<int64_t>(n3 / 4096, 1), 64));
-  if (int64_t(B) * (2 * lblk + 2) > n.ls_cap) {
-    net_free(n, n.d_ls);
-    n.ls_cap = int64_t(B) * (2 * lblk + 2);
-    n.d_ls = static_cast<double*>(net_dev_alloc(n, size_t(n.ls_cap) * sizeof(double)));
-  }
-  double* lpart = n.d_ls;
-  double* lsum = n.d_ls + int64_t(B) * 2 * lblk;
   dim3 g(nb(n2), B);
-  // forward
-  k_l1<float><<<g, TPB, 0, s>>>(rhat, idx, nullptr, lgN, n.d_pk + PK_L1F, n.d_a1);
-  forward_hidden(n, lgN, B, s);
-  k_l3<float><<<g, TPB, 0, s>>>(n.d_a2, lgN, n.d_pk + PK_L3F, nullptr, n.d_y3);
-  // loss and its gradient
-  k_loss_partial<<<dim3(lblk, B), TPB, 0, s>>>(n.d_y3, ehat, idx, n3, lpart);
-  k_loss_final<<<nb(B), TPB, 0, s>>>(lpart, lblk, B, lsum);
-  k_g3<<<dim3(nb(n3), B), TPB, 0, s>>>(n.d_y3, ehat, idx, lsum, B, n3, n.d_g3);
-  // backward
   float* gW1 = n.d_g;
   float* gW2 = n.d_g + 864;
   float* gW3 = n.d_g + 864 + 9216;
@@ -662,19 +737,43 @@ void net_train_step(Net& n, int N, int B, const float* rhat, const float* ehat, 
   k_adam<<<nb(NET_W), TPB, 0, s>>>(n.d_w, n.d_g, n.d_m, n.d_v, NET_W, float(lr), float(b1), float(1.0 - b1),
                                    float(b2), float(1.0 - b2), 1e-8f, float(bc1), float(bc2));
   net_pack(n, s);
-  if (loss) {
-    std::vector<double> h(size_t(2) * B);
-    CAV_HIP(hipMemcpyAsync(h.data(), lsum, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    CAV_HIP(hipStreamSynchronize(s));
-    double L = 0.0;
-    for (int b = 0; b < B; ++b) L += h[2 * b + 1] / h[2 * b];
-    *loss = L / B;
-  }
 }
 
 void launch_pair_write(const double* r, const double* e, const double* nrm2, float* rhat, float* ehat, int64_t n,
                        hipStream_t s) {
   k_pair_write<<<nb(n), TPB, 0, s>>>(r, e, nrm2, rhat, ehat, n);
+}
+
+void launch_sample_f64(const float* src, const int32_t* idx, int b, int64_t n3, double* dst, hipStream_t s) {
+  k_sample_f64<<<nb(n3), TPB, 0, s>>>(src, idx, b, n3, dst);
+}
+
+void launch_scaled_f32(const double* q, const double* sums, double coef, int64_t n3, float* dst, hipStream_t s) {
+  k_scaled_f32<<<nb(n3), TPB, 0, s>>>(q, sums, coef, n3, dst);
+}
+
+void launch_mr_scalars(double* sums, int B, hipStream_t s) { k_mr_scalars<<<1, 64, 0, s>>>(sums, B); }
+void launch_coef_f32(const double* q, const double* sums, int64_t n3, float* dst, hipStream_t s) {
+  k_coef_f32<<<nb(n3), TPB, 0, s>>>(q, sums, n3, dst);
+}
+void launch_sub_gamma(double* y, const double* x, const double* z, const double* sums, int64_t n3, hipStream_t s) {
+  k_sub_gamma<<<nb(n3), TPB, 0, s>>>(y, x, z, sums, n3);
+}
+
+const int32_t* net_upload_index(Net& n, const int32_t* index, int batch, int64_t n_samples, hipStream_t s) {
+  if (!index) {
+    if (n_samples < batch) throw StatusError(CAV_ERR_INVALID_ARG, "n_samples must cover the batch");
+    return nullptr;
+  }
+  for (int b = 0; b < batch; ++b)
+    if (index[b] < 0 || index[b] >= n_samples) throw StatusError(CAV_ERR_INVALID_ARG, "sample index out of range");
+  if (n.idx_cap < batch) {
+    net_free(n, n.d_idx);
+    n.d_idx = static_cast<int32_t*>(net_dev_alloc(n, size_t(batch) * sizeof(int32_t)));
+    n.idx_cap = batch;
+  }
+  CAV_HIP(hipMemcpyAsync(n.d_idx, index, size_t(batch) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  return n.d_idx;
 }
 
 void launch_stage_decide(const double* sc, double margin, double* gamma_out, double* counters, hipStream_t s) {
@@ -834,20 +933,7 @@ cav_status cav_net_train_step(cav_net net, int32_t N, int32_t batch, const float
   net_require(batch >= 1 && batch <= 65535, "batch must be in [1, 65535]");
   net_require(rhat && ehat, "rhat and ehat must be device pointers");
   net_require(std::isfinite(lr) && lr > 0.0, "lr must be positive");
-  const int32_t* didx = nullptr;
-  if (index) {
-    for (int b = 0; b < batch; ++b)
-      net_require(index[b] >= 0 && index[b] < n_samples, "sample index out of range");
-    if (n.idx_cap < batch) {
-      net_free(n, n.d_idx);
-      n.d_idx = static_cast<int32_t*>(net_dev_alloc(n, size_t(batch) * sizeof(int32_t)));
-      n.idx_cap = batch;
-    }
-    CAV_HIP(hipMemcpyAsync(n.d_idx, index, size_t(batch) * sizeof(int32_t), hipMemcpyHostToDevice, n.stream));
-    didx = n.d_idx;
-  } else {
-    net_require(n_samples >= batch, "n_samples must cover the batch");
-  }
+  const int32_t* didx = net_upload_index(n, index, batch, n_samples, n.stream);
   net_train_step(n, N, batch, rhat, ehat, didx, lr, loss, n.stream);
   CAV_HIP(hipGetLastError());
   if (!loss) CAV_HIP(hipStreamSynchronize(n.stream));

@@ -176,3 +176,57 @@ def test_fgmres_stage_matches_oracle(dev, cav, target16):
     assert inf["learned_accepted"] == inf["iterations"] and stage.accepted == res.iterations
     err = np.linalg.norm(x - res.x) / np.linalg.norm(res.x)
     assert err < 1e-8, err
+
+
+@pytest.mark.parametrize("kind", ["residual", "minres"])
+def test_train_step_through_operator_parity(dev, cav, kind):
+    s = workloads.target_circle(N=16, n_levels=2)
+    print(f"[net train step through K] kind={kind} N={s.N}", flush=True)
+    from oracle import ib, mac
+    EE, _ = ib.eulerian_elasticity(s)
+    K = mac.reduced_operator(s.N, s.rho, s.mu, s.dt, EE)
+    rng = np.random.default_rng(21)
+    ns, N = 5, s.N
+    rh = rng.standard_normal((ns, 3 * N * N)).astype(np.float32)
+    idx = np.array([4, 1, 2], dtype=np.int32)
+    w0 = workloads.net_init(3, out_scale=1e-2)
+    g = cav.Solver(0)
+    g.build_operator(s)
+    net = cav.Net(0, w0)
+    loss = g.train_net_residual(net, torch.from_numpy(rh).to(dev), idx, 1e-3, kind)
+    _, grad = net.weights()
+    g.close()
+    net.close()
+    f = L.residual_loss_and_grad if kind == "residual" else L.minres_loss_and_grad
+    lo, go = f(rh[idx].reshape(3, 3, N, N).astype(np.float64), K, w0.astype(np.float64), bf16=True)
+    assert abs(loss - lo) <= 2.0 ** -10 * abs(lo), (loss, lo)
+    for name, sl in (("dW1", slice(0, 864)), ("dW2", slice(864, 864 + 9216)), ("dW3", slice(864 + 9216, None))):
+        gg, oo = grad[sl].astype(np.float64), go[sl]
+        rel = np.linalg.norm(gg - oo) / np.linalg.norm(oo)
+        assert rel <= 2.0 ** -9, f"{name}: norm-wise relative error {rel:.3e}"
+
+
+def test_learned_gain_and_enable_rule(dev, cav):
+    """Trains the net on V-cycle pairs of a 64^2 membrane system (minimal-residual
+    loss) and measures what the stage gains inside FGMRES on held-out
+    right-hand sides; the stage is enabled only where it cuts iterations."""
+    from paper_2608_14310_amd import learned as LN
+    s = workloads.membrane_ellipse(N=64, kappa=1e4)
+    print(f"[learned gain] {s.name}", flush=True)
+    g = _solver(cav, s)
+    xs = torch.from_numpy(workloads.random_solutions(s.N, 100, 1)).to(dev)
+    rh, eh = LN.generate_pairs(g, xs, 3)
+    net = cav.Net(0, workloads.net_init(0, out_scale=1e-2))
+    losses = LN.train(net, rh, eh, s.N, workloads.batch_order(rh.shape[0], 8, 600, 0), 1e-3, solver=g, kind="minres")
+    rhs = [torch.from_numpy(workloads.random_rhs(s.N, 100 + k)).to(dev) for k in range(2)]
+    enabled, rows = LN.validate(g, net, rhs)
+    print(f"[learned gain] loss {np.mean(losses[:20]):.3f} -> {np.mean(losses[-50:]):.3f}; "
+          f"iterations plain/learned {[(r['plain'], r['learned']) for r in rows]}; enabled={enabled}", flush=True)
+    assert np.mean(losses[-50:]) < np.mean(losses[:20])       # training reduces the loss
+    assert all(r["plain_converged"] and r["learned_converged"] for r in rows)
+    assert enabled == all(r["learned"] < r["plain"] for r in rows)
+    # a disabled stage leaves the solver on the plain V-cycle
+    _, inf = g.fgmres_solve(rhs[0], 1e-10, 150, learned=enabled)
+    assert inf["iterations"] == (rows[0]["learned"] if enabled else rows[0]["plain"])
+    g.close()
+    net.close()

@@ -112,6 +112,66 @@ def test_gradient_matches_central_differences():
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])), (k, fd, g[k])
 
 
+def test_residual_loss_gradient_matches_central_differences():
+    s = workloads.target_circle(N=8, n_levels=1)
+    from oracle import ib, mac
+    EE, _ = ib.eulerian_elasticity(s)
+    K = mac.reduced_operator(s.N, s.rho, s.mu, s.dt, EE)
+    assert abs(K - K.T).max() < 1e-9 * abs(K).max()      # K_E is symmetric (G = -D^T, E_E symmetric)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((2, 3, 8, 8))
+    w = rand_weights(10, 0.4)
+    loss, g = L.residual_loss_and_grad(x, K, w)
+    # direct evaluation of the definition
+    y, _ = L.forward(x, w)
+    direct = np.mean([np.sum((K @ y[b].ravel() - x[b].ravel()) ** 2) / np.sum(x[b] ** 2) for b in range(2)])
+    assert abs(loss - direct) <= 1e-12 * direct
+    picks = np.concatenate([rng.choice(864, 12, replace=False), 864 + rng.choice(9216, 20, replace=False),
+                            864 + 9216 + rng.choice(864, 12, replace=False)])
+    h = 1e-6
+    for k in picks:
+        wp, wm = w.copy(), w.copy()
+        wp[k] += h
+        wm[k] -= h
+        fd = (L.residual_loss_and_grad(x, K, wp)[0] - L.residual_loss_and_grad(x, K, wm)[0]) / (2 * h)
+        # the loss is large (K carries rho/dt = 1e3), so the difference quotient's
+        # rounding error is eps * loss / h, about 1e-5 of the derivative here
+        assert abs(fd - g[k]) <= 1e-4 * max(1.0, abs(g[k])), (k, fd, g[k])
+
+
+def test_minres_loss_definition_and_gradient():
+    s = workloads.target_circle(N=8, n_levels=1)
+    from oracle import ib, mac
+    EE, _ = ib.eulerian_elasticity(s)
+    K = mac.reduced_operator(s.N, s.rho, s.mu, s.dt, EE)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((2, 3, 8, 8))
+    w = rand_weights(13, 0.4)
+    loss, g = L.minres_loss_and_grad(x, K, w)
+    # definition: the residual left by the best multiple, found by a scalar least-squares fit
+    y, _ = L.forward(x, w)
+    direct = []
+    for b in range(2):
+        kc, r = K @ y[b].ravel(), x[b].ravel()
+        gam = np.linalg.lstsq(kc[:, None], r, rcond=None)[0][0]
+        direct.append(np.sum((r - gam * kc) ** 2) / np.sum(r ** 2))
+    assert abs(loss - np.mean(direct)) <= 1e-10
+    assert 0.0 <= loss <= 1.0
+    # scale invariance: scaling the output layer leaves the loss unchanged
+    w2 = w.copy()
+    w2[864 + 9216:] *= 8.0
+    assert abs(L.minres_loss_and_grad(x, K, w2)[0] - loss) <= 1e-12
+    picks = np.concatenate([rng.choice(864, 12, replace=False), 864 + rng.choice(9216, 20, replace=False),
+                            864 + 9216 + rng.choice(864, 12, replace=False)])
+    h = 1e-6
+    for k in picks:
+        wp, wm = w.copy(), w.copy()
+        wp[k] += h
+        wm[k] -= h
+        fd = (L.minres_loss_and_grad(x, K, wp)[0] - L.minres_loss_and_grad(x, K, wm)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1e-3, abs(g[k])), (k, fd, g[k])
+
+
 def test_loss_normalisation():
     rng = np.random.default_rng(7)
     x = rng.standard_normal((3, 3, 4, 4))

@@ -233,14 +233,16 @@ def paper_target(N: int, kappa: float = 1e6, mu: float = 1.0, seed: int = 0) -> 
 NET_SHAPES = ((32, 3, 3, 3), (32, 32, 3, 3), (3, 32, 3, 3))
 
 
-def net_init(seed: int = 0) -> np.ndarray:
+def net_init(seed: int = 0, out_scale: float = 1.0) -> np.ndarray:
     """Initial master weights (float32, 10 944): each layer uniform on
-    [-s, s] with s = sqrt(6 / fan_in), fan_in = input channels x 9."""
+    [-s, s] with s = sqrt(6 / fan_in), fan_in = input channels x 9; the output
+    layer is multiplied by out_scale (a small value starts training from a
+    near-zero correction)."""
     rng = np.random.default_rng([seed, 3])
     parts = []
-    for co, ci, kh, kw in NET_SHAPES:
+    for k, (co, ci, kh, kw) in enumerate(NET_SHAPES):
         s = math.sqrt(6.0 / (ci * kh * kw))
-        parts.append(rng.uniform(-s, s, co * ci * kh * kw))
+        parts.append(rng.uniform(-s, s, co * ci * kh * kw) * (out_scale if k == len(NET_SHAPES) - 1 else 1.0))
     return np.concatenate(parts).astype(np.float32)
 
 
@@ -251,3 +253,17 @@ def random_solutions(N: int, count: int, seed: int) -> np.ndarray:
     x = rng.uniform(-1.0, 1.0, (count, 3 * N * N))
     x[:, 2 * N * N:] -= x[:, 2 * N * N:].mean(axis=1, keepdims=True)
     return x
+
+
+def batch_order(n_samples: int, batch: int, steps: int, seed: int = 0):
+    """Sample indices for `steps` training batches: consecutive slices of
+    fresh random permutations of range(n_samples) (one per epoch)."""
+    rng = np.random.default_rng([seed, 5])
+    perm = rng.permutation(n_samples)
+    pos = 0
+    for _ in range(steps):
+        if pos + batch > n_samples:
+            perm = rng.permutation(n_samples)
+            pos = 0
+        yield perm[pos:pos + batch].astype(np.int32)
+        pos += batch
