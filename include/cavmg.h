@@ -173,6 +173,35 @@ cav_status cav_vcycle(cav_ctx ctx, const double* r, double* z);
 cav_status cav_fgmres_solve(cav_ctx ctx, const double* b, double* x, const cav_fgmres_opts* opts,
                             cav_solve_info* info);
 
+/* ---- graph execution and batches of independent systems ----
+ * cav_fgmres_solve_graph: the same solve as cav_fgmres_solve (same kernels,
+ * reductions and results), with the whole iteration body (V-cycle, K_E apply,
+ * CGS2, Givens rotations, next basis vector) captured once into a hipGraph
+ * and replayed; the iteration index, rotations and done flag live in device
+ * memory, and the host reads one flag per iteration. The graph is captured on
+ * a stream the context owns, ordered after the caller's stream, and is
+ * re-captured after any setup call. use_learned must be 0.
+ * cav_batch_solve: solves n_sys independent systems (ctxs[i], b[i] -> x[i],
+ * device vectors of each context's finest size) by rounds: each round runs one
+ * iteration of every unfinished system. mode 0 captures the active systems'
+ * bodies as parallel branches of ONE graph (one launch per round), recaptured
+ * when a quarter of its systems have finished (finished systems replay their
+ * last iteration without changing their state); mode 1 launches each system's
+ * own graph on its own stream. infos (optional) receives n_sys summaries;
+ * returns the first non-OK status of any system. Contexts must be distinct,
+ * factored and on one device; synchronises. */
+typedef struct {
+  int32_t rounds;          /* rounds (iterations of the slowest system) */
+  int32_t graph_launches;  /* hipGraphLaunch calls */
+  int32_t captures;        /* graph captures */
+  int64_t iterations;      /* FGMRES iterations summed over systems */
+} cav_batch_stats;
+cav_status cav_fgmres_solve_graph(cav_ctx ctx, const double* b, double* x, const cav_fgmres_opts* opts,
+                                  cav_solve_info* info);
+cav_status cav_batch_solve(cav_ctx* ctxs, int32_t n_sys, const double* const* b, double* const* x,
+                           const cav_fgmres_opts* opts, cav_solve_info* infos, int32_t mode,
+                           cav_batch_stats* stats);
+
 /* ---- per-level access for parity checks ----
  * op: 0 y = K_l x; 1 y = R_l x (level l -> l-1, y on level l-1);
  *     2 y = P_l x (level l-1 -> l, x on level l-1, y on level l);

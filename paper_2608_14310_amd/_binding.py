@@ -68,6 +68,11 @@ class SolveInfo(C.Structure):
                 ("learned_accepted", C.c_int32), ("learned_rejected", C.c_int32)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("graph_launches", C.c_int32), ("captures", C.c_int32),
+                ("iterations", C.c_int64)]
+
+
 class KernelTiming(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double), ("vcycles", C.c_int64),
                 ("vcycle_ms", C.c_double)]
@@ -118,6 +123,9 @@ _SIGS = {
     "cav_net_train_step_residual": ([_P, _P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_int32), C.c_int64, C.c_double,
                                      C.POINTER(C.c_double)], C.c_int),
     "cav_learned_pairs": ([_P, C.c_int32, _P, C.c_int32, _P, _P], C.c_int),
+    "cav_fgmres_solve_graph": ([_P, _P, _P, C.POINTER(FgmresOpts), C.POINTER(SolveInfo)], C.c_int),
+    "cav_batch_solve": ([C.POINTER(_P), C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(FgmresOpts),
+                         C.POINTER(SolveInfo), C.c_int32, C.POINTER(BatchStats)], C.c_int),
     "cav_attach_net": ([_P, _P, C.c_double], C.c_int),
 }
 NET_WEIGHTS = 10944
@@ -429,13 +437,15 @@ class Solver:
         return y
 
     def fgmres_solve(self, b, rtol: float = 1e-10, max_it: int = 150, out=None, history: bool = True,
-                     learned: bool = False):
+                     learned: bool = False, graph: bool = False):
+        """FGMRES to rtol; graph=True replays the captured iteration body (same results)."""
         self._sync_stream()
         x = self.empty() if out is None else out
         hist = np.zeros(max_it, dtype=np.float64)
         o = FgmresOpts(float(rtol), int(max_it), 1 if learned else 0, _arr(hist, C.c_double) if history else None)
         info = SolveInfo()
-        st = self._check(self._L.cav_fgmres_solve(self._h, _dev_ptr(b), _dev_ptr(x), C.byref(o), C.byref(info)))
+        fn = self._L.cav_fgmres_solve_graph if graph else self._L.cav_fgmres_solve
+        st = self._check(fn(self._h, _dev_ptr(b), _dev_ptr(x), C.byref(o), C.byref(info)))
         d = {f: getattr(info, f) for f, _ in SolveInfo._fields_}
         d["status"] = st
         d["history"] = hist[:info.iterations].copy()
@@ -515,3 +525,24 @@ class Solver:
         self._check(self._L.cav_export_ee(self._h, level, _arr(rp, C.c_int64), _arr(col, C.c_int32),
                                           _arr(val, C.c_double), C.byref(nnz)))
         return rp, col, val
+
+
+def batch_solve(solvers, bs, rtol: float = 1e-10, max_it: int = 150, mode: int = 0):
+    """Solve independent systems together (cav_batch_solve): solvers[i] with
+    right-hand side bs[i] (float64 device tensors). Returns (xs, infos, stats)."""
+    n = len(solvers)
+    L = lib()
+    for s in solvers:
+        s._sync_stream()
+    xs = [s.empty() for s in solvers]
+    hs = (_P * n)(*[s._h for s in solvers])
+    bp = (_P * n)(*[_dev_ptr(b) for b in bs])
+    xp = (_P * n)(*[_dev_ptr(x) for x in xs])
+    o = FgmresOpts(float(rtol), int(max_it), 0, None)
+    infos = (SolveInfo * n)()
+    st = BatchStats()
+    code = L.cav_batch_solve(hs, n, bp, xp, C.byref(o), infos, int(mode), C.byref(st))
+    if code not in (0, WARN_NOT_CONVERGED, WARN_FLOOR_LIMITED):
+        raise CAVError(code, L.cav_last_error(solvers[0]._h).decode())
+    out = [{f: getattr(i, f) for f, _ in SolveInfo._fields_} for i in infos]
+    return xs, out, {f: getattr(st, f) for f, _ in BatchStats._fields_}

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcavmg.so")
 SOURCES = ["capi.hip", "kernels_grid.hip", "kernels_smoother.hip", "kernels_factor.hip", "kernels_learned.hip",
-           "setup_host.cpp",
+           "kernels_krylov.hip", "setup_host.cpp",
            "analysis.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <functional>
 #include <unordered_set>
 
 #include "cav_internal.hpp"
@@ -93,7 +94,7 @@ void vcycle_level(Ctx& c, int l, const double* b, double* x) {
   }
   Level& L = c.lv[l];
   const int64_t n = 3 * int64_t(L.N) * L.N;
-  if (c.pre == 0) CAV_HIP(hipMemsetAsync(x, 0, size_t(n) * sizeof(double), s));
+  if (c.pre == 0) launch_fill(x, 0.0, n, s);
   for (int k = 0; k < c.pre; ++k) launch_smoother(c, L, b, x, k == 0, s);
   Level& C = c.lv[l - 1];
   launch_apply_op(L, x, L.d_r, b, s);  // r = b - K x
@@ -151,6 +152,206 @@ double dnorm(Ctx& c, const double* x, int64_t n) {
   CAV_HIP(hipMemcpyAsync(&v, c.d_h, sizeof(double), hipMemcpyDeviceToHost, c.stream));
   CAV_HIP(hipStreamSynchronize(c.stream));
   return std::sqrt(v);
+}
+
+// ---- graph-mode FGMRES ----
+void drop_graph(Ctx& c) {
+  if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
+  if (c.graph) (void)hipGraphDestroy(c.graph);
+  c.gexec = nullptr;
+  c.graph = nullptr;
+  c.graph_generation = 0;
+}
+
+void graph_workspace(Ctx& c, int max_it) {
+  ensure_workspace(c, max_it);
+  const int64_t n = c.ws_n;
+  if (!c.gstream) CAV_HIP(hipStreamCreateWithFlags(&c.gstream, hipStreamNonBlocking));
+  if (c.d_gi && c.g_maxit == max_it && c.g_n == n) return;
+  drop_graph(c);
+  for (void* p : {(void*)c.d_gi, (void*)c.d_gs, (void*)c.d_vin, (void*)c.d_zout}) dev_free(c, p);
+  c.d_gi = static_cast<int32_t*>(dev_alloc(c, GI_COUNT * sizeof(int32_t)));
+  c.d_gs = static_cast<double*>(dev_alloc(c, size_t(GS_SIZE(max_it)) * sizeof(double)));
+  c.d_vin = static_cast<double*>(dev_alloc(c, size_t(n) * sizeof(double)));
+  c.d_zout = static_cast<double*>(dev_alloc(c, size_t(n) * sizeof(double)));
+  c.g_maxit = max_it;
+  c.g_n = n;
+}
+
+// One FGMRES iteration of the context's system, enqueued on c.stream; every
+// launch reads the iteration index from device memory.
+void graph_body(Ctx& c, double rtol) {
+  const Level& F = c.lv.back();
+  const int64_t n = c.g_n;
+  launch_col_get(c.d_V, n, c.d_gi, c.d_vin, n, c.stream);
+  vcycle_level(c, c.n_levels - 1, c.d_vin, c.d_zout);
+  launch_arnoldi_dk(F, c.d_V, c.d_Z, n, c.d_gi, c.d_gi, c.d_gs, c.d_zout, c.d_w, c.d_part, c.d_h, c.g_maxit, rtol,
+                    c.stream);
+}
+
+// Capture `bodies` on the streams of the given contexts, forked from and joined
+// into `origin`, as one graph.
+hipGraphExec_t capture_bodies(const std::vector<Ctx*>& cs, hipStream_t origin, double rtol, hipGraph_t* out_graph) {
+  std::vector<hipStream_t> saved;
+  std::vector<bool> tsaved;
+  for (Ctx* c : cs) {
+    saved.push_back(c->stream);
+    tsaved.push_back(c->timing);
+    c->timing = false;
+  }
+  hipEvent_t fork;
+  CAV_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  std::vector<hipEvent_t> joins(cs.size(), nullptr);
+  hipGraph_t g = nullptr;
+  bool capturing = false;
+  try {
+    CAV_HIP(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
+    capturing = true;
+    CAV_HIP(hipEventRecord(fork, origin));
+    for (size_t i = 0; i < cs.size(); ++i) {
+      Ctx& c = *cs[i];
+      c.stream = c.gstream == origin ? origin : c.gstream;
+      if (c.stream != origin) CAV_HIP(hipStreamWaitEvent(c.stream, fork, 0));
+      graph_body(c, rtol);
+      if (c.stream != origin) {
+        CAV_HIP(hipEventCreateWithFlags(&joins[i], hipEventDisableTiming));
+        CAV_HIP(hipEventRecord(joins[i], c.stream));
+        CAV_HIP(hipStreamWaitEvent(origin, joins[i], 0));
+      }
+    }
+    capturing = false;
+    CAV_HIP(hipStreamEndCapture(origin, &g));
+  } catch (...) {
+    if (capturing) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(origin, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+    }
+    for (size_t i = 0; i < cs.size(); ++i) {
+      cs[i]->stream = saved[i];
+      cs[i]->timing = tsaved[i];
+    }
+    (void)hipEventDestroy(fork);
+    for (hipEvent_t e : joins)
+      if (e) (void)hipEventDestroy(e);
+    throw;
+  }
+  for (size_t i = 0; i < cs.size(); ++i) {
+    cs[i]->stream = saved[i];
+    cs[i]->timing = tsaved[i];
+  }
+  (void)hipEventDestroy(fork);
+  for (hipEvent_t e : joins)
+    if (e) (void)hipEventDestroy(e);
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  *out_graph = g;
+  return ex;
+}
+
+// Prologue shared by the graph solves: b' = b minus its pressure mean (into
+// d_bb), beta = ||b'||, v_0 = b'/beta, device state reset. Runs on c.stream.
+struct Start {
+  double beta = 0.0, pmean = 0.0;
+};
+Start graph_start(Ctx& c, const double* b) {
+  hipStream_t s = c.stream;
+  const Level& F = c.lv.back();
+  const int64_t n = c.g_n, n2 = int64_t(F.N) * F.N;
+  Start st;
+  CAV_HIP(hipMemcpyAsync(c.d_bb, b, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_block_sum(c.d_bb + 2 * n2, n2, c.d_part, c.d_h, s);
+  double psum = 0.0;
+  CAV_HIP(hipMemcpyAsync(&psum, c.d_h, sizeof(double), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipStreamSynchronize(s));
+  st.pmean = psum / double(n2);
+  require(std::isfinite(st.pmean), CAV_ERR_INVALID_ARG, "right-hand side is not finite");
+  launch_pressure_mean_remove(c.d_bb, F.N, c.d_part, s);
+  st.beta = dnorm(c, c.d_bb, n);
+  require(std::isfinite(st.beta), CAV_ERR_INVALID_ARG, "right-hand side is not finite");
+  if (st.beta > 0.0) {
+    k_axpby<<<nblocks(n), TPB, 0, s>>>(c.d_V, 1.0 / st.beta, c.d_bb, 0.0, n);
+    launch_gstate_init(c.d_gi, c.d_gs, st.beta, c.g_maxit, s);
+  }
+  return st;
+}
+
+// Epilogue: y = H_k^{-1} g on the host, x = Z_k y, true residual, summary.
+cav_status graph_finish(Ctx& c, const Start& st, double* x, double rtol, const cav_fgmres_opts* opts,
+                        cav_solve_info* info) {
+  hipStream_t s = c.stream;
+  const Level& F = c.lv.back();
+  const int64_t n = c.g_n;
+  const int m = c.g_maxit;
+  cav_solve_info inf{};
+  inf.pressure_mean_removed = st.pmean;
+  if (!(st.beta > 0.0)) {
+    launch_fill(x, 0.0, n, s);
+    CAV_HIP(hipStreamSynchronize(s));
+    inf.converged = 1;
+    if (info) *info = inf;
+    return CAV_OK;
+  }
+  int32_t gi[GI_COUNT];
+  std::vector<double> gs(size_t(GS_SIZE(m)));
+  CAV_HIP(hipMemcpyAsync(gi, c.d_gi, sizeof(gi), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipMemcpyAsync(gs.data(), c.d_gs, gs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipStreamSynchronize(s));
+  if (gi[GI_DONE] == 2) throw StatusError(CAV_ERR_INVALID_ARG, "non-finite value in FGMRES (check inputs)");
+  const int k = gi[GI_K];
+  const double* H = gs.data() + GS_H(m);
+  const double* g = gs.data() + GS_CS + 2 * m;
+  const double* hist = g + (m + 1);
+  std::vector<double> y(size_t(std::max(k, 1)), 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int q = i + 1; q < k; ++q) acc -= H[int64_t(q) * (m + 1) + i] * y[q];
+    y[i] = acc / H[int64_t(i) * (m + 1) + i];
+  }
+  if (opts && opts->history)
+    for (int j = 0; j < k; ++j) opts->history[j] = hist[j];
+  CAV_HIP(hipMemcpyAsync(c.d_h, y.data(), size_t(k) * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_fill(x, 0.0, n, s);
+  launch_multi_axpy(x, c.d_Z, n, k, c.d_h, 1.0, n, s);
+  launch_apply_op(F, x, c.d_w, c.d_bb, s);
+  const double rn = dnorm(c, c.d_w, n);
+  inf.iterations = k;
+  inf.converged = gi[GI_CONV];
+  inf.est_rel_residual = gs[GS_EST];
+  inf.true_rel_residual = rn / st.beta;
+  if (info) *info = inf;
+  if (!inf.converged) return CAV_WARN_NOT_CONVERGED;
+  if (inf.true_rel_residual > 10.0 * rtol) return CAV_WARN_FLOOR_LIMITED;
+  return CAV_OK;
+}
+
+// Runs `fn` with c.stream switched to the context's own capture-capable stream,
+// ordered after the caller's stream and before its later work.
+template <typename Fn>
+auto on_graph_stream(Ctx& c, Fn fn) -> decltype(fn()) {
+  if (!c.gstream) CAV_HIP(hipStreamCreateWithFlags(&c.gstream, hipStreamNonBlocking));
+  hipStream_t caller = c.stream;
+  hipEvent_t e;
+  CAV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  CAV_HIP(hipEventRecord(e, caller));
+  CAV_HIP(hipStreamWaitEvent(c.gstream, e, 0));
+  c.stream = c.gstream;
+  struct Restore {
+    Ctx& c;
+    hipStream_t caller;
+    hipEvent_t e;
+    ~Restore() {
+      (void)hipEventRecord(e, c.gstream);
+      (void)hipStreamWaitEvent(caller, e, 0);
+      (void)hipEventDestroy(e);
+      c.stream = caller;
+    }
+  } restore{c, caller, e};
+  return fn();
 }
 
 // Stage workspace: r', c, K c (3 n doubles) and 8 scalars
@@ -249,6 +450,12 @@ cav_status cav_destroy(cav_ctx ctx) {
   if (!ctx) return CAV_OK;
   (void)hipSetDevice(ctx->c.device);
   if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+  if (ctx->c.gexec) (void)hipGraphExecDestroy(ctx->c.gexec);
+  if (ctx->c.graph) (void)hipGraphDestroy(ctx->c.graph);
+  if (ctx->c.gstream) {
+    (void)hipStreamSynchronize(ctx->c.gstream);
+    (void)hipStreamDestroy(ctx->c.gstream);
+  }
   for (void* p : ctx->live) (void)hipFree(p);
   if (ctx->c.h_pinned) (void)hipHostFree(ctx->c.h_pinned);
   for (hipEvent_t e : ctx->c.ev_pool) (void)hipEventDestroy(e);
@@ -259,6 +466,7 @@ cav_status cav_destroy(cav_ctx ctx) {
 cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* g, const cav_structure_desc* st) {
   if (!ctx) return CAV_ERR_INVALID_ARG;
   Ctx& c = ctx->c;
+  ++c.generation;
   API_BEGIN
   require(g != nullptr, CAV_ERR_INVALID_ARG, "grid descriptor is NULL");
   const int N = g->N, L = g->n_levels;
@@ -329,6 +537,7 @@ cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* g, const cav_str
 cav_status cav_build_cav_patches(cav_ctx ctx, int family, cav_level_stats* out) {
   if (!ctx) return CAV_ERR_INVALID_ARG;
   Ctx& c = ctx->c;
+  ++c.generation;
   API_BEGIN
   require(c.built, CAV_ERR_NOT_BUILT, "cav_build_operator has not succeeded");
   require(family == CAV_FAMILY_CAV || family == CAV_FAMILY_VANKA, CAV_ERR_INVALID_ARG, "unknown patch family");
@@ -363,6 +572,7 @@ cav_status cav_build_cav_patches(cav_ctx ctx, int family, cav_level_stats* out) 
 cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold, cav_factor_stats* out) {
   if (!ctx) return CAV_ERR_INVALID_ARG;
   Ctx& c = ctx->c;
+  ++c.generation;
   API_BEGIN
   require(c.patched, CAV_ERR_NOT_BUILT, "cav_build_cav_patches has not succeeded");
   require(precision == CAV_PREC_FP64 || precision == CAV_PREC_MIXED, CAV_ERR_INVALID_ARG, "unknown precision");
@@ -386,6 +596,7 @@ cav_status cav_set_smoother(cav_ctx ctx, int kind, double alpha, int pre, int po
     ctx->c.err = "unknown smoother kind, or alpha not finite, or pre + post < 1";
     return CAV_ERR_INVALID_ARG;
   }
+  ++ctx->c.generation;
   ctx->c.smoother = kind;
   ctx->c.alpha = alpha;
   ctx->c.pre = pre;
@@ -791,6 +1002,179 @@ cav_status cav_net_train_step_residual(cav_net net, cav_ctx ctx, int32_t kind, i
     *loss = L / batch;
   }
   return CAV_OK;
+  API_END
+}
+
+cav_status cav_fgmres_solve_graph(cav_ctx ctx, const double* b, double* x, const cav_fgmres_opts* opts,
+                                  cav_solve_info* info) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require(b && x && b != x, CAV_ERR_INVALID_ARG, "b and x must be distinct device pointers");
+  require(!(opts && opts->use_learned), CAV_ERR_INVALID_ARG, "the graph solve has no learned stage");
+  const double rtol = opts ? opts->rtol : 1e-10;
+  const int max_it = opts ? opts->max_it : 150;
+  require(max_it >= 1 && max_it <= 10000 && rtol >= 0.0, CAV_ERR_INVALID_ARG, "bad FGMRES options");
+  return on_graph_stream(c, [&]() -> cav_status {
+    graph_workspace(c, max_it);
+    const Start st = graph_start(c, b);
+    if (st.beta > 0.0) {
+      if (!c.gexec || c.graph_generation != c.generation || c.graph_rtol != rtol) {
+        drop_graph(c);
+        c.gexec = capture_bodies({&c}, c.stream, rtol, &c.graph);
+        c.graph_generation = c.generation;
+        c.graph_rtol = rtol;
+      }
+      int32_t* done = reinterpret_cast<int32_t*>(c.h_pinned);
+      for (int it = 0; it < max_it; ++it) {
+        CAV_HIP(hipGraphLaunch(c.gexec, c.stream));
+        CAV_HIP(hipMemcpyAsync(done, c.d_gi + GI_DONE, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+        CAV_HIP(hipStreamSynchronize(c.stream));
+        if (*done) break;
+      }
+    }
+    return graph_finish(c, st, x, rtol, opts, info);
+  });
+  API_END
+}
+
+cav_status cav_batch_solve(cav_ctx* ctxs, int32_t n_sys, const double* const* b, double* const* x,
+                           const cav_fgmres_opts* opts, cav_solve_info* infos, int32_t mode,
+                           cav_batch_stats* stats) {
+  if (!ctxs || n_sys < 1 || !b || !x) return CAV_ERR_INVALID_ARG;
+  for (int i = 0; i < n_sys; ++i)
+    if (!ctxs[i]) return CAV_ERR_INVALID_ARG;
+  cav_ctx ctx = ctxs[0];
+  Ctx& c0 = ctx->c;
+  API_BEGIN
+  require(mode == 0 || mode == 1, CAV_ERR_INVALID_ARG, "mode must be 0 (one graph) or 1 (graph per system)");
+  require(!(opts && opts->use_learned), CAV_ERR_INVALID_ARG, "the batch solve has no learned stage");
+  const double rtol = opts ? opts->rtol : 1e-10;
+  const int max_it = opts ? opts->max_it : 150;
+  require(max_it >= 1 && max_it <= 10000 && rtol >= 0.0, CAV_ERR_INVALID_ARG, "bad FGMRES options");
+  for (int i = 0; i < n_sys; ++i) {
+    Ctx& c = ctxs[i]->c;
+    require(c.factored, CAV_ERR_NOT_BUILT, "every context must be factored");
+    require(c.device == c0.device, CAV_ERR_INVALID_ARG, "all contexts must share a device");
+    require(b[i] && x[i] && b[i] != x[i], CAV_ERR_INVALID_ARG, "b and x must be distinct device pointers");
+    for (int j = 0; j < i; ++j) require(ctxs[j] != ctxs[i], CAV_ERR_INVALID_ARG, "a context appears twice");
+  }
+  hipStream_t caller = c0.stream;
+  hipStream_t origin = nullptr;
+  CAV_HIP(hipStreamCreateWithFlags(&origin, hipStreamNonBlocking));
+  hipEvent_t ev;
+  CAV_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  std::vector<hipStream_t> saved(n_sys, nullptr);
+  std::vector<char> touched(n_sys, 0);
+  std::vector<Start> starts(n_sys);
+  std::vector<char> active(n_sys, 0);
+  cav_batch_stats bs{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int32_t* flags = nullptr;
+  cav_status ret = CAV_OK;
+  struct Cleanup {
+    std::function<void()> f;
+    ~Cleanup() { f(); }
+  } cleanup{[&]() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (flags) (void)hipHostFree(flags);
+    (void)hipStreamSynchronize(origin);
+    for (int i = 0; i < n_sys; ++i)
+      if (touched[i]) ctxs[i]->c.stream = saved[i];
+    (void)hipEventRecord(ev, origin);
+    (void)hipStreamWaitEvent(caller, ev, 0);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(origin);
+  }};
+  CAV_HIP(hipHostMalloc(reinterpret_cast<void**>(&flags), size_t(n_sys) * sizeof(int32_t), hipHostMallocDefault));
+  CAV_HIP(hipEventRecord(ev, caller));
+  CAV_HIP(hipStreamWaitEvent(origin, ev, 0));
+  // prologues (each on its system's own stream)
+  for (int i = 0; i < n_sys; ++i) {
+    Ctx& c = ctxs[i]->c;
+    graph_workspace(c, max_it);
+    CAV_HIP(hipEventRecord(ev, c.stream));   // the system's caller-stream work comes first
+    CAV_HIP(hipStreamWaitEvent(c.gstream, ev, 0));
+    saved[i] = c.stream;
+    touched[i] = 1;
+    c.stream = c.gstream;
+    starts[i] = graph_start(c, b[i]);
+    active[i] = starts[i].beta > 0.0;
+  }
+  // rounds: one iteration of every active system per round
+  std::vector<Ctx*> members;
+  int launched_members = 0;
+  for (int round = 0; round < max_it; ++round) {
+    std::vector<Ctx*> act;
+    std::vector<int> ids;
+    for (int i = 0; i < n_sys; ++i)
+      if (active[i]) {
+        act.push_back(&ctxs[i]->c);
+        ids.push_back(i);
+      }
+    if (act.empty()) break;
+    if (mode == 0) {
+      // recapture when a quarter of the graph's systems have finished
+      if (!gexec || int(act.size()) * 4 <= launched_members * 3) {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        // order each system's prior work before the origin stream
+        for (Ctx* c : act) {
+          hipEvent_t e;
+          CAV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+          CAV_HIP(hipEventRecord(e, c->stream));
+          CAV_HIP(hipStreamWaitEvent(origin, e, 0));
+          (void)hipEventDestroy(e);
+        }
+        gexec = capture_bodies(act, origin, rtol, &graph);
+        launched_members = int(act.size());
+        members = act;
+        ++bs.captures;
+      }
+      CAV_HIP(hipGraphLaunch(gexec, origin));
+      ++bs.graph_launches;
+      for (int i = 0; i < n_sys; ++i)
+        if (active[i])
+          CAV_HIP(hipMemcpyAsync(flags + i, ctxs[i]->c.d_gi + GI_DONE, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                 origin));
+      CAV_HIP(hipStreamSynchronize(origin));
+    } else {
+      for (size_t q = 0; q < act.size(); ++q) {
+        Ctx& c = *act[q];
+        if (!c.gexec || c.graph_generation != c.generation || c.graph_rtol != rtol) {
+          drop_graph(c);
+          c.gexec = capture_bodies({&c}, c.stream, rtol, &c.graph);
+          c.graph_generation = c.generation;
+          c.graph_rtol = rtol;
+          ++bs.captures;
+        }
+        CAV_HIP(hipGraphLaunch(c.gexec, c.stream));
+        ++bs.graph_launches;
+        CAV_HIP(hipMemcpyAsync(flags + ids[q], c.d_gi + GI_DONE, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+      }
+      for (Ctx* c : act) CAV_HIP(hipStreamSynchronize(c->stream));
+    }
+    ++bs.rounds;
+    for (int i : ids)
+      if (flags[i]) active[i] = 0;
+  }
+  // the origin stream's graph work precedes each system's epilogue
+  CAV_HIP(hipStreamSynchronize(origin));
+  for (int i = 0; i < n_sys; ++i) {
+    Ctx& c = ctxs[i]->c;
+    cav_solve_info inf{};
+    cav_status st = graph_finish(c, starts[i], x[i], rtol, nullptr, &inf);
+    if (infos) infos[i] = inf;
+    if (st != CAV_OK && ret == CAV_OK) ret = st;
+    bs.iterations += inf.iterations;
+  }
+  if (stats) *stats = bs;
+  return ret;
   API_END
 }
 

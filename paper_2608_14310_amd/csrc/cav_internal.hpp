@@ -144,6 +144,13 @@ struct Net {
   std::vector<void*> allocs;
 };
 
+// Device-resident FGMRES state (graph mode). Integer slots:
+enum { GI_J = 0, GI_DONE = 1, GI_K = 2, GI_CONV = 3, GI_COUNT = 4 };
+// Double slots: beta, estimate, 1/h_{j+1,j}, then cs[m], sn[m], g[m+1], hist[m], H[(m+1) x m] (column-major).
+enum { GS_BETA = 0, GS_EST = 1, GS_INVHN = 2, GS_CS = 4 };
+constexpr int64_t GS_H(int m) { return GS_CS + 4 * int64_t(m) + 1; }
+constexpr int64_t GS_SIZE(int m) { return GS_H(m) + int64_t(m + 1) * m; }
+
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -175,6 +182,20 @@ struct Ctx {
   int64_t st_n = 0;
   double *d_pw = nullptr;        // residual-pair workspace (5 n)
   int64_t pw_n = 0;
+  // graph-mode FGMRES: own stream (capture needs a non-default stream),
+  // device state, fixed V-cycle input/output, captured iteration body
+  hipStream_t gstream = nullptr;
+  int32_t* d_gi = nullptr;
+  double* d_gs = nullptr;
+  double* d_vin = nullptr;
+  double* d_zout = nullptr;
+  int g_maxit = 0;
+  int64_t g_n = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  uint64_t generation = 1;        // bumped by every setup call; a captured body is valid for one generation
+  uint64_t graph_generation = 0;
+  double graph_rtol = -1.0;
   // live timing of the explicit-patch GEMV and of whole V-cycles (HIP events)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -214,6 +235,7 @@ void launch_restrict(const Level& Lf, const double* rf, double* bc, hipStream_t 
 void launch_prolong_add(const Level& Lf, const double* xc, double* xf, hipStream_t s);
 void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
 void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
+void prepare_mult_smoother(size_t lds);
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
 void colour_explicit(int N, const HostCSR& ee, Level& L);
 void launch_coarse_solve(const Ctx& c, const double* b, double* x, hipStream_t s);
@@ -251,6 +273,12 @@ void launch_scaled_f32(const double* q, const double* sums, double coef, int64_t
 void launch_mr_scalars(double* sums, int B, hipStream_t s);
 void launch_coef_f32(const double* q, const double* sums, int64_t n3, float* dst, hipStream_t s);
 void launch_sub_gamma(double* y, const double* x, const double* z, const double* sums, int64_t n3, hipStream_t s);
+// graph-mode FGMRES (kernels_krylov.hip)
+void launch_gstate_init(int32_t* gi, double* gs, double beta, int max_it, hipStream_t s);
+void launch_col_get(const double* V, int64_t ldv, const int32_t* gi, double* out, int64_t n, hipStream_t s);
+void launch_arnoldi_dk(const Level& F, double* V, double* Z, int64_t n, const int32_t* gi_c, int32_t* gi, double* gs,
+                       const double* zout, double* w, double* part, double* hd, int max_it, double rtol,
+                       hipStream_t s);
 void launch_pair_write(const double* r, const double* e, const double* nrm2, float* rhat, float* ehat, int64_t n,
                        hipStream_t s);
 void launch_stage_decide(const double* sc, double margin, double* gamma_out, double* counters, hipStream_t s);

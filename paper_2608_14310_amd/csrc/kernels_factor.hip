@@ -688,6 +688,7 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
     // LDS of the phase kernel: residual (n doubles) and 16-column block partials
     const int64_t mn = std::max<int32_t>(L.mrec_max_n, 1);
     L.mx_lds = size_t(mn + ((mn + 15) / 16) * mn) * sizeof(double);
+    prepare_mult_smoother(L.mx_lds);
     if (L.d_mrec) dev_free(c, L.d_mrec);
     L.d_mrec = upload(c, mrec);
   }

@@ -299,9 +299,6 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
   const int64_t n2 = int64_t(L.N) * L.N, n = 3 * n2;
   if (zero_guess) launch_fill(x, 0.0, n, s);
   const int nph = int(L.ph_ptr.size()) - 1;
-  if (L.mx_lds > 64 * 1024)
-    CAV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_mult_exp<MX_THREADS>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(L.mx_lds)));
   for (int ph = 0; ph < nph; ++ph) {
     const int a = L.ph_ptr[ph], cnt = L.ph_ptr[ph + 1] - a;
     timing_begin(c, s);
@@ -314,6 +311,16 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
   for (int col = 0; col < 8; ++col)
     k_mult_std<<<nblocks(per_colour), TPB, 0, s>>>(L.N, col, L.d_cellflag, L.d_std_inv, L.sc, b, x, c.alpha);
   launch_pressure_mean_remove(x, L.N, L.d_part, s);
+}
+
+// Raises the phase kernel's dynamic-LDS limit once (at setup, never inside a
+// launch sequence that may be captured into a graph).
+void prepare_mult_smoother(size_t lds) {
+  static size_t set_to = 64 * 1024;
+  if (lds <= set_to) return;
+  CAV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_mult_exp<MX_THREADS>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  set_to = lds;
 }
 
 void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s) {
