@@ -3,13 +3,16 @@
 One step = the whole path on the 512^2 open-fibre beam system (4 fibres of
 length 0.4, ds = h/2, bending kappa_b = 1e-2, springs 1e4, 5-level V(1,1)):
 build_operator -> build_cav_patches -> factor_patches -> fgmres_solve to 1e-10.
-The stiffer members of the kappa_b sweep (1, 1e2) are run once after the
-timed steps and reported with their iteration counts (they do not reach
-1e-10 within 150 iterations at this resolution).
-Inputs (markers, RHS on the device) are prepared before the timed region.
-`value` is the mean wall time per solve (ms, lower is better), hierarchy
-build included. The dominant kernel (explicit-patch GEMV of the smoother) is
-timed live with HIP events around each of its launches on the library stream.
+`value` is the mean wall time per step (T_total, ms, lower is better);
+`t_solve_ms` is the solve alone. Inputs (markers, RHS on the device) are
+prepared before the timed region; the phase-kernel table is autotuned once
+before it. The dominant kernel (explicit-patch phase kernel of the
+multiplicative smoother) is timed live with HIP events on the library stream
+around each sweep's run of phase launches.
+After the timed steps: the other precision on the same system, the stiffer
+kappa_b values (reported with their iteration counts), the learned stage
+(trained on 256^2 pairs, judged on this solve), the batched mix of independent
+systems in one captured graph, and the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -114,6 +117,74 @@ def copy_calibration(nbytes: int):
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}))
 
 
+def batched_leg(n_systems: int, max_it: int):
+    """Independent systems of the batched mix (grids 64..512, target /
+    membrane / beam laws, stiffness log-uniform 1e2..1e6), mixed precision,
+    multiplicative CAV V-cycle, all unfinished systems advanced one FGMRES
+    iteration per launch of one captured graph. Setup is outside the timing."""
+    import torch
+
+    import workloads
+    from paper_2608_14310_amd import Solver, batch_solve
+    systems = workloads.batched_mix(n_systems)
+    solvers = []
+    t0 = time.perf_counter()
+    for s in systems:
+        g = Solver(0)
+        g.setup(s, precision="mixed", alpha=1.0, smoother="multiplicative")
+        solvers.append(g)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    bs = [torch.from_numpy(s.b).to(torch.device("cuda", 0)) for s in systems]
+    batch_solve(solvers, bs, 1e-10, max_it, 0)          # warm-up: captures and first replays
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, infos, st = batch_solve(solvers, bs, 1e-10, max_it, 0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for g in solvers:
+        g.close()
+    its = [i["iterations"] for i in infos]
+    return {"systems": n_systems, "grids": sorted({s.N for s in systems}), "seconds": round(dt, 3),
+            "solves_per_s": round(n_systems / dt, 2), "vcycles_per_s": round(sum(its) / dt, 1),
+            "converged": int(sum(i["converged"] for i in infos)), "iterations_min_max": [min(its), max(its)],
+            "rounds": st["rounds"], "graph_launches": st["graph_launches"], "captures": st["captures"],
+            "setup_s": round(t_setup, 2), "max_it": max_it, "precision": "mixed", "mode": "one graph per round"}
+
+
+def learned_leg(g_eval, b_eval, train_pairs: int, steps: int):
+    """Train the learned stage on V-cycle pairs of a 256^2 beam system
+    (minimal-residual loss) and judge it on the 512^2 solve: kept only if it
+    cuts the iteration count."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2608_14310_amd import Net, Solver
+    from paper_2608_14310_amd import learned as LN
+    dev = torch.device("cuda", 0)
+    st = workloads.beam_fibres(N=256, n_levels=4, kappa_b=1e-2, seed=1)
+    gt = Solver(0)
+    gt.setup(st, precision="mixed", alpha=1.0, smoother="multiplicative")
+    t0 = time.perf_counter()
+    xs = torch.from_numpy(workloads.random_solutions(st.N, max(train_pairs // 3, 1), 1)).to(dev)
+    rh, eh = LN.generate_pairs(gt, xs, 3)
+    net = Net(0, workloads.net_init(0, out_scale=1e-2))
+    losses = LN.train(net, rh, eh, st.N, workloads.batch_order(rh.shape[0], 8, steps, 0), 1e-3, solver=gt,
+                      kind="minres")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    gt.close()
+    enabled, rows = LN.validate(g_eval, net, [b_eval])
+    g_eval.attach_net(None)
+    net.close()
+    return {"train": f"{rh.shape[0]} pairs from 256^2 beam V-cycles, {steps} Adam steps (batch 8, minimal-residual loss)",
+            "train_s": round(t_train, 2), "loss_first": round(float(np.mean(losses[:20])), 4),
+            "loss_last": round(float(np.mean(losses[-50:])), 4), "eval": "512^2 beam kappa_b=1e-2, rtol 1e-10",
+            "plain_its": rows[0]["plain"], "learned_its": rows[0]["learned"], "accepted": rows[0]["accepted"],
+            "enabled": enabled}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,8 +192,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--smoother", default="multiplicative", choices=["multiplicative", "additive"])
-    ap.add_argument("--kappa-b", type=float, nargs="*", default=[1e-2])
+    ap.add_argument("--kappa-b", type=float, default=1e-2)
     ap.add_argument("--stiff-sweep", type=float, nargs="*", default=[1.0, 1e2])
+    ap.add_argument("--tune", default="auto", choices=["auto", "none", "split"],
+                    help="phase-kernel table: autotuned, default 1024 threads, or split form everywhere")
+    ap.add_argument("--batch", type=int, default=64, help="systems in the batched leg (0: skip)")
+    ap.add_argument("--learned-pairs", type=int, default=600, help="training pairs of the learned leg (0: skip)")
+    ap.add_argument("--learned-steps", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, help="run only a plain copy of this many bytes")
@@ -141,60 +217,62 @@ def main():
     from paper_2608_14310_amd import Solver
 
     dev = torch.device("cuda", 0)
-    systems = [workloads.beam_512(kb) for kb in a.kappa_b]
-    rhs = [torch.from_numpy(s.b).to(dev) for s in systems]
+    s = workloads.beam_512(a.kappa_b)
+    b = torch.from_numpy(s.b).to(dev)
     g = Solver(0)
-    stream = torch.cuda.current_stream(dev)
     alpha = 1.0 if a.smoother == "multiplicative" else 0.7
+    table = None
 
-    def one_step(record):
-        out = []
-        for s, b in zip(systems, rhs):
-            t0 = time.perf_counter()
-            g.build_operator(s)
-            t1 = time.perf_counter()
-            stats = g.build_cav_patches("cav")
-            t2 = time.perf_counter()
-            fst = g.factor_patches(a.precision, 1e6)
-            g.set_smoother(a.smoother, alpha)
-            t3 = time.perf_counter()
-            g.kernel_timing(True)
-            x, info = g.fgmres_solve(b, rtol=1e-10, max_it=150)
-            kt = g.kernel_timing(False)
-            t4 = time.perf_counter()
-            out.append(dict(kb=s.kappa["kappa_b"], build=t1 - t0, patches=t2 - t1, factor=t3 - t2, solve=t4 - t3,
-                            its=info["iterations"], conv=info["converged"], est=info["est_rel_residual"],
-                            true=info["true_rel_residual"], stats=stats, fst=fst, kt=kt))
-        return out
+    def setup(precision):
+        t0 = time.perf_counter()
+        g.build_operator(s)
+        t1 = time.perf_counter()
+        stats = g.build_cav_patches("cav")
+        t2 = time.perf_counter()
+        fst = g.factor_patches(precision, 1e6)
+        g.set_smoother(a.smoother, alpha)
+        if table is not None:
+            g.set_tuning(table)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        return dict(build=t1 - t0, patches=t2 - t1, factor=t3 - t2), stats, fst
 
+    def one_step(precision):
+        tm, stats, fst = setup(precision)
+        g.kernel_timing(True)
+        t3 = time.perf_counter()
+        x, info = g.fgmres_solve(b, rtol=1e-10, max_it=150)
+        torch.cuda.synchronize()
+        tm["solve"] = time.perf_counter() - t3
+        kt = g.kernel_timing(False)
+        return dict(tm, its=info["iterations"], conv=info["converged"], est=info["est_rel_residual"],
+                    true=info["true_rel_residual"], stats=stats, fst=fst, kt=kt)
+
+    # phase-kernel table for this hierarchy shape (outside the timed region)
+    setup(a.precision)
+    if a.tune == "auto":
+        table = g.autotune(reps=3)
+    elif a.tune == "split":
+        table = np.zeros((s.n_levels, 4), dtype=np.int32)
     for _ in range(a.warmup):
-        one_step(False)
+        one_step(a.precision)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
     t0 = time.perf_counter()
-    runs = []
-    for _ in range(a.steps):
-        runs.append(one_step(True))
-    ev1.record(stream)
+    runs = [one_step(a.precision) for _ in range(a.steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    n_solves = a.steps * len(systems)
     ms_per_step = 1e3 * wall / a.steps
-    ms_per_solve = 1e3 * wall / n_solves
 
-    # dominant kernel: explicit-patch GEMV, bytes and time accumulated by the library
-    kb_bytes = sum(r["kt"]["bytes"] for run in runs for r in run)
-    kb_ms = sum(r["kt"]["ms"] for run in runs for r in run)
-    kb_launch = sum(r["kt"]["launches"] for run in runs for r in run)
+    kb_bytes = sum(r["kt"]["bytes"] for r in runs)
+    kb_ms = sum(r["kt"]["ms"] for r in runs)
+    kb_launch = sum(r["kt"]["launches"] for r in runs)
     achieved = kb_bytes / (kb_ms * 1e-3) / 1e9 if kb_ms > 0 else 0.0
     last = runs[-1]
-    per_sys = [{k: (float("%.4g" % v) if isinstance(v, float) else v) for k, v in r.items()
-                if k not in ("stats", "fst", "kt")} for r in last]
-    vcycle_ms = [r["kt"]["vcycle_ms"] for r in last]
+    kernel = "k_mult_exp" if a.smoother == "multiplicative" else "k_patch_apply"
+    solve_ms = [1e3 * r["solve"] for r in runs]
     line = {
         "metric": "FGMRES(CAV-MG) time-to-1e-10 rel. residual at 512^2; V-cycle HBM GB/s",
-        "value": round(ms_per_solve, 3),
+        "value": round(ms_per_step, 3),
         "unit": "ms",
         "n_gpus": 1,
         "steps": a.steps,
@@ -205,41 +283,56 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "beam512: 512x512 MAC grid, 5-level V(1,1), 4 open fibres L=0.4 ds=h/2, "
-                               "kappa_b sweep " + ",".join(f"{k:g}" for k in a.kappa_b) +
-                               ", kappa_s=1e4, rho=1 mu=0.01 dt=1e-3, seeded U[-1,1] RHS, FGMRES rtol 1e-10",
-                   "precision": a.precision, "smoother": a.smoother, "alpha": alpha},
-        "per_system": per_sys,
+        "config": {"workload": "beam512: 512x512 MAC grid, 5-level V(1,1) CAV multigrid, 4 open fibres L=0.4 "
+                               f"ds=h/2, kappa_b={a.kappa_b:g}, kappa_s=1e4, rho=1 mu=0.01 dt=1e-3, seeded U[-1,1] "
+                               "RHS, FGMRES rtol 1e-10; value = T_total (operator + patches + factors + solve)",
+                   "precision": a.precision, "smoother": a.smoother, "alpha": alpha, "tune": a.tune},
+        "t_solve_ms": round(float(np.median(solve_ms)), 3),
+        "per_step": {k: (float("%.4g" % v) if isinstance(v, float) else v) for k, v in last.items()
+                     if k not in ("stats", "fst", "kt")},
+        "vcycle_ms": round(last["kt"]["vcycle_ms"], 4),
+        "vcycles_per_s": round(1e3 / last["kt"]["vcycle_ms"], 1) if last["kt"]["vcycle_ms"] else None,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("k_mult_exp" if a.smoother == "multiplicative" else "k_patch_apply",
-                                                 a.precision, a.smoother),
-                     "kernel": "k_mult_exp" if a.smoother == "multiplicative" else "k_patch_apply",
-                     "launches": kb_launch,
+                     "traffic": measured_traffic(kernel, a.precision, a.smoother),
+                     "kernel": kernel, "launches": kb_launch,
                      "bytes_per_launch": int(kb_bytes / max(kb_launch, 1)),
                      "avg_launch_us": round(1e3 * kb_ms / max(kb_launch, 1), 3)},
-        "vcycle_ms": [round(v, 4) for v in vcycle_ms],
     }
+    if table is not None:
+        line["tuning_table"] = np.asarray(table).tolist()
+    # the other precision, same workload, for comparison
+    other = "mixed" if a.precision == "fp64" else "fp64"
+    o = one_step(other)
+    line["other_precision"] = {"precision": other, "t_total_ms": round(1e3 * (o["build"] + o["patches"] + o["factor"]
+                                                                               + o["solve"]), 1),
+                               "t_solve_ms": round(1e3 * o["solve"], 1), "its": o["its"], "true": o["true"],
+                               "n_fp32_patches": o["fst"]["n_fp32"], "n_fp64_patches": o["fst"]["n_fp64"]}
     sweep = []
     for kb in a.stiff_sweep:
-        s = workloads.beam_512(kb)
-        g.build_operator(s)
+        sk = workloads.beam_512(kb)
+        g.build_operator(sk)
         g.build_cav_patches("cav")
         g.factor_patches(a.precision, 1e6)
         g.set_smoother(a.smoother, alpha)
         t0s = time.perf_counter()
-        _, inf = g.fgmres_solve(torch.from_numpy(s.b).to(dev), rtol=1e-10, max_it=150)
+        _, inf = g.fgmres_solve(torch.from_numpy(sk.b).to(dev), rtol=1e-10, max_it=150)
         torch.cuda.synchronize()
         sweep.append({"kappa_b": kb, "iterations": inf["iterations"], "converged": inf["converged"],
-                      "est_rel_residual": inf["est_rel_residual"], "solve_ms": round(1e3 * (time.perf_counter() - t0s), 1)})
+                      "est_rel_residual": float("%.4g" % inf["est_rel_residual"]),
+                      "solve_ms": round(1e3 * (time.perf_counter() - t0s), 1)})
     line["stiffness_sweep"] = sweep
+    if a.learned_pairs > 0:
+        setup("mixed")
+        line["learned"] = learned_leg(g, b, a.learned_pairs, a.learned_steps)
     if a.verbose:
-        line["level_stats"] = last[0]["stats"]
-        line["factor_stats"] = [r["fst"] for r in last]
-    if not a.no_cpu_baseline:
-        mid = last[len(last) // 2]
-        line["cpu_baseline"] = cpu_baseline(mid["kb"], mid["its"], a.smoother, alpha)
+        line["level_stats"] = last["stats"]
+        line["factor_stats"] = last["fst"]
     g.close()
+    if a.batch > 0:
+        line["batched"] = batched_leg(a.batch, 150)
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(a.kappa_b, last["its"], a.smoother, alpha)
     print(json.dumps(line))
 
 

@@ -202,6 +202,20 @@ cav_status cav_batch_solve(cav_ctx* ctxs, int32_t n_sys, const double* const* b,
                            const cav_fgmres_opts* opts, cav_solve_info* infos, int32_t mode,
                            cav_batch_stats* stats);
 
+/* ---- autotuning ----
+ * The multiplicative sweep launches one kernel per colour phase; each patch
+ * of a phase gets one workgroup of 256, 512 or 1024 threads. cav_autotune
+ * times the three sizes on the context's own phases, per smoothed level and
+ * per size bucket of a phase's largest patch (<= 64, <= 128, <= 256, larger),
+ * `reps` repetitions each, keeps the fastest, and writes the table (4 ints per
+ * level, levels 0 .. n_levels-1; level 0 is unused) to `table` (optional).
+ * Results do not depend on the choice (every patch's arithmetic is the same
+ * for all three sizes). Uses the levels' scratch vectors; synchronises.
+ * cav_set_tuning applies a stored table (entries 256, 512 or 1024), e.g. one
+ * cached in a file by the caller. */
+cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table);
+cav_status cav_set_tuning(cav_ctx ctx, const int32_t* table);
+
 /* ---- per-level access for parity checks ----
  * op: 0 y = K_l x; 1 y = R_l x (level l -> l-1, y on level l-1);
  *     2 y = P_l x (level l-1 -> l, x on level l-1, y on level l);
@@ -239,13 +253,16 @@ cav_status cav_analysis_export_weights(cav_analysis a, int level, int32_t* dofs,
 
 /* ---- live timing ----
  * Between cav_kernel_timing(ctx, 1, NULL) and a later call, the library
- * records HIP events on its stream around every launch of the explicit-patch
- * GEMV (the smoother's dominant kernel) and around every top-level V-cycle.
+ * records HIP events on its stream around the explicit-patch kernels (the
+ * smoother's dominant kernels): one pair around each additive GEMV launch and
+ * one pair around each run of consecutive multiplicative phase launches (one
+ * run per sweep and level), plus one pair around every top-level V-cycle. A
+ * bracket's duration includes the dispatch gaps between the launches it holds.
  * A call with out != NULL synchronises the stream and returns the totals
  * since recording started; every call clears the records; enable = 0 stops. */
 typedef struct {
-  int64_t launches;        /* explicit-patch GEMV launches */
-  double ms;               /* their summed durations */
+  int64_t launches;        /* explicit-patch kernel launches inside the brackets */
+  double ms;               /* summed bracket durations */
   double bytes;            /* their summed algorithmic bytes: sum_p n_p^2 s + 20 n_p */
   int64_t vcycles;         /* top-level V-cycles */
   double vcycle_ms;        /* their summed durations */

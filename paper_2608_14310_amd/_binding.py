@@ -123,6 +123,8 @@ _SIGS = {
     "cav_net_train_step_residual": ([_P, _P, C.c_int32, C.c_int32, _P, C.POINTER(C.c_int32), C.c_int64, C.c_double,
                                      C.POINTER(C.c_double)], C.c_int),
     "cav_learned_pairs": ([_P, C.c_int32, _P, C.c_int32, _P, _P], C.c_int),
+    "cav_autotune": ([_P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+    "cav_set_tuning": ([_P, C.POINTER(C.c_int32)], C.c_int),
     "cav_fgmres_solve_graph": ([_P, _P, _P, C.POINTER(FgmresOpts), C.POINTER(SolveInfo)], C.c_int),
     "cav_batch_solve": ([C.POINTER(_P), C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(FgmresOpts),
                          C.POINTER(SolveInfo), C.c_int32, C.POINTER(BatchStats)], C.c_int),
@@ -468,6 +470,51 @@ class Solver:
                                                         _arr(idx, C.c_int32) if idx is not None else None, ns,
                                                         float(lr), C.byref(loss)))
         return loss.value
+
+    def autotune(self, reps: int = 3, cache: Optional[str] = None) -> np.ndarray:
+        """Time the phase kernel's thread counts per level and size bucket and keep
+        the fastest (cav_autotune); with `cache`, the table is stored as JSON
+        under a key for this hierarchy (grid, levels, patch histogram) and reused."""
+        import json
+        key = None
+        if cache is not None:
+            key = self._tuning_key()
+            try:
+                with open(cache) as f:
+                    stored = json.load(f).get(key)
+            except (OSError, ValueError):
+                stored = None
+            if stored is not None:
+                t = np.ascontiguousarray(stored, dtype=np.int32)
+                self.set_tuning(t)
+                return t.reshape(self.n_levels, 4)
+        self._sync_stream()
+        t = np.zeros(4 * self.n_levels, dtype=np.int32)
+        self._check(self._L.cav_autotune(self._h, int(reps), _arr(t, C.c_int32)))
+        if cache is not None:
+            try:
+                with open(cache) as f:
+                    data = json.load(f)
+            except (OSError, ValueError):
+                data = {}
+            data[key] = t.tolist()
+            with open(cache, "w") as f:
+                json.dump(data, f, indent=1)
+        return t.reshape(self.n_levels, 4)
+
+    def set_tuning(self, table) -> None:
+        """Apply a phase-kernel table (n_levels x 4 entries of 0, 256, 512, 1024)."""
+        t = np.ascontiguousarray(table, dtype=np.int32).ravel()
+        self._check(self._L.cav_set_tuning(self._h, _arr(t, C.c_int32)))
+
+    def _tuning_key(self) -> str:
+        """gfx950 / grid / levels / patch-count signature of the built hierarchy."""
+        parts = [f"gfx950:N{self.N}:L{self.n_levels}"]
+        for l in range(1, self.n_levels):
+            nph, ncell = C.c_int32(), C.c_int32()
+            self._L.cav_export_phases(self._h, l, None, None, C.byref(nph), C.byref(ncell))
+            parts.append(f"{nph.value}/{ncell.value}")
+        return ":".join(parts)
 
     def attach_net(self, net: Optional[Net], margin: float = 1e-3) -> None:
         self._check(self._L.cav_attach_net(self._h, net._h if net is not None else None, float(margin)))

@@ -67,7 +67,7 @@ void free_level(Ctx& c, Level& L) {
                   (void*)L.d_cellflag, (void*)L.d_slot_dof, (void*)L.d_delta, (void*)L.d_t_dof, (void*)L.d_t_inv,
                   (void*)L.d_t_ptr, (void*)L.d_t_slot, (void*)L.d_std_inv, (void*)L.d_rec64, (void*)L.d_rec32,
                   (void*)L.d_f64, (void*)L.d_f32, (void*)L.d_b, (void*)L.d_x, (void*)L.d_r, (void*)L.d_z,
-                  (void*)L.d_part, (void*)L.d_mrec})
+                  (void*)L.d_part, (void*)L.d_mrec, (void*)L.d_wrk})
     dev_free(c, p);
   L = Level();
 }
@@ -76,7 +76,7 @@ void free_patches(Ctx& c, Level& L) {
   for (void** p : {(void**)&L.d_cellflag, (void**)&L.d_slot_dof, (void**)&L.d_delta, (void**)&L.d_t_dof,
                    (void**)&L.d_t_inv, (void**)&L.d_t_ptr, (void**)&L.d_t_slot, (void**)&L.d_std_inv,
                    (void**)&L.d_rec64, (void**)&L.d_rec32, (void**)&L.d_f64, (void**)&L.d_f32,
-                   (void**)&L.d_mrec}) {
+                   (void**)&L.d_mrec, (void**)&L.d_wrk}) {
     dev_free(c, *p);
     *p = nullptr;
   }
@@ -839,10 +839,10 @@ cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* ou
     if (!c.kt_marks.empty() || !c.vc_marks.empty()) CAV_HIP(hipStreamSynchronize(c.stream));
     for (auto& m : c.kt_marks) {
       float ms = 0.f;
-      CAV_HIP(hipEventElapsedTime(&ms, c.ev_pool[m.first], c.ev_pool[m.first + 1]));
-      out->launches += 1;
+      CAV_HIP(hipEventElapsedTime(&ms, c.ev_pool[m.ev], c.ev_pool[m.ev + 1]));
+      out->launches += m.launches;
       out->ms += ms;
-      out->bytes += m.second;
+      out->bytes += m.bytes;
     }
     for (auto& m : c.vc_marks) {
       float ms = 0.f;
@@ -1175,6 +1175,82 @@ cav_status cav_batch_solve(cav_ctx* ctxs, int32_t n_sys, const double* const* b,
   }
   if (stats) *stats = bs;
   return ret;
+  API_END
+}
+
+cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require(reps >= 1 && reps <= 1000, CAV_ERR_INVALID_ARG, "reps must be in [1, 1000]");
+  hipStream_t s = c.stream;
+  hipEvent_t e0, e1;
+  CAV_HIP(hipEventCreate(&e0));
+  CAV_HIP(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  const bool timing = c.timing;
+  c.timing = false;
+  const int cand[4] = {256, 512, 1024, 0};
+  for (int l = 1; l < c.n_levels; ++l) {
+    Level& L = c.lv[l];
+    const int nph = int(L.ph_ptr.size()) - 1;
+    if (nph <= 0) continue;
+    const int64_t n = 3 * int64_t(L.N) * L.N;
+    launch_fill(L.d_b, 1.0, n, s);
+    launch_fill(L.d_x, 0.0, n, s);
+    for (int bk = 0; bk < 4; ++bk) {
+      std::vector<int> phs;
+      for (int ph = 0; ph < nph; ++ph)
+        if (mx_bucket(L.ph_maxn[ph]) == bk) phs.push_back(ph);
+      if (phs.empty()) continue;
+      float best = 1e30f;
+      int pick = L.mx_nt[bk];
+      for (int nt : cand) {
+        for (int ph : phs) launch_mult_phase(c, L, ph, nt, L.d_b, L.d_x, s);  // warm-up
+        CAV_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r)
+          for (int ph : phs) launch_mult_phase(c, L, ph, nt, L.d_b, L.d_x, s);
+        CAV_HIP(hipEventRecord(e1, s));
+        CAV_HIP(hipEventSynchronize(e1));
+        CAV_HIP(hipGetLastError());
+        float ms = 0.f;
+        CAV_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          pick = nt;
+        }
+      }
+      L.mx_nt[bk] = pick;
+    }
+  }
+  c.timing = timing;
+  ++c.generation;
+  if (table)
+    for (int l = 0; l < c.n_levels; ++l)
+      for (int bk = 0; bk < 4; ++bk) table[4 * l + bk] = c.lv[l].mx_nt[bk];
+  return CAV_OK;
+  API_END
+}
+
+cav_status cav_set_tuning(cav_ctx ctx, const int32_t* table) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.built && table != nullptr, CAV_ERR_INVALID_ARG, "needs a built context and a table");
+  for (int q = 0; q < 4 * c.n_levels; ++q)
+    require(table[q] == 256 || table[q] == 512 || table[q] == 1024 || table[q] == 0, CAV_ERR_INVALID_ARG,
+            "table entries must be 256, 512, 1024 or 0 (split form)");
+  for (int l = 0; l < c.n_levels; ++l)
+    for (int bk = 0; bk < 4; ++bk) c.lv[l].mx_nt[bk] = table[4 * l + bk];
+  ++c.generation;
+  return CAV_OK;
   API_END
 }
 

@@ -86,6 +86,11 @@ struct Level {
   MultRec* d_mrec = nullptr;              // records in ph_exp order
   int32_t mrec_max_n = 0;
   std::vector<double> ph_bytes;           // algorithmic bytes of each phase launch
+  std::vector<int32_t> ph_maxn;           // largest patch of each phase
+  int32_t mx_nt[4] = {1024, 1024, 1024, 1024};  // per size bucket: 256/512/1024 threads, 0 = split form (autotuned)
+  std::vector<int32_t> ph_wptr;           // split form: work items of each phase (offsets)
+  int2* d_wrk = nullptr;                  // (record index in d_mrec, first row)
+  size_t sp_lds = 0;                      // dynamic LDS of the split GEMV kernel
   size_t mx_lds = 0;                      // dynamic LDS of the phase kernel
 
   // factors
@@ -200,7 +205,12 @@ struct Ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  std::vector<std::pair<int, double>> kt_marks;   // (event index of the start, bytes)
+  struct KtMark {
+    int ev;          // event index of the start (the end is ev + 1)
+    double bytes;    // algorithmic bytes of the bracketed launches
+    int launches;    // launches inside the bracket
+  };
+  std::vector<KtMark> kt_marks;
   std::vector<std::pair<int, int>> vc_marks;      // event indices around each V-cycle
 };
 
@@ -208,13 +218,14 @@ hipEvent_t next_event(Ctx& c);
 inline void timing_begin(Ctx& c, hipStream_t s) {
   if (!c.timing) return;
   hipEvent_t e = next_event(c);
-  c.kt_marks.push_back({int(c.ev_used - 1), 0.0});
+  c.kt_marks.push_back({int(c.ev_used - 1), 0.0, 0});
   (void)hipEventRecord(e, s);
 }
-inline void timing_end(Ctx& c, hipStream_t s, double bytes) {
+inline void timing_end(Ctx& c, hipStream_t s, double bytes, int launches = 1) {
   if (!c.timing) return;
   hipEvent_t e = next_event(c);
-  c.kt_marks.back().second = bytes;
+  c.kt_marks.back().bytes = bytes;
+  c.kt_marks.back().launches = launches;
   (void)hipEventRecord(e, s);
 }
 
@@ -236,6 +247,10 @@ void launch_prolong_add(const Level& Lf, const double* xc, double* xf, hipStream
 void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
 void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
 void prepare_mult_smoother(size_t lds);
+// size bucket of a phase by its largest patch: <= 64, <= 128, <= 256, larger
+inline int mx_bucket(int n) { return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : 3; }
+// one explicit phase: nt = 256, 512 or 1024 threads per patch, or 0 for the split form
+void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double* x, hipStream_t s);
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
 void colour_explicit(int N, const HostCSR& ee, Level& L);
 void launch_coarse_solve(const Ctx& c, const double* b, double* x, hipStream_t s);

@@ -680,10 +680,12 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
       L.mrec_max_n = std::max(L.mrec_max_n, byid[e].n);
     }
     L.ph_bytes.assign(L.ph_ptr.empty() ? 0 : L.ph_ptr.size() - 1, 0.0);
+    L.ph_maxn.assign(L.ph_bytes.size(), 0);
     for (size_t ph = 0; ph + 1 < L.ph_ptr.size(); ++ph)
       for (int32_t q = L.ph_ptr[ph]; q < L.ph_ptr[ph + 1]; ++q) {
         const MultRec& m = mrec[q];
         L.ph_bytes[ph] += double(m.n) * m.n * (m.f32 ? 4 : 8) + 20.0 * m.n;
+        L.ph_maxn[ph] = std::max(L.ph_maxn[ph], m.n);
       }
     // LDS of the phase kernel: residual (n doubles) and 16-column block partials
     const int64_t mn = std::max<int32_t>(L.mrec_max_n, 1);
@@ -691,6 +693,18 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
     prepare_mult_smoother(L.mx_lds);
     if (L.d_mrec) dev_free(c, L.d_mrec);
     L.d_mrec = upload(c, mrec);
+    // split form: one item per (patch, block of 64 rows), grouped by phase
+    std::vector<int2> wrk;
+    L.ph_wptr.assign(1, 0);
+    for (size_t ph = 0; ph + 1 < L.ph_ptr.size(); ++ph) {
+      for (int32_t q = L.ph_ptr[ph]; q < L.ph_ptr[ph + 1]; ++q)
+        for (int32_t r0 = 0; r0 < mrec[q].n; r0 += 64) wrk.push_back(make_int2(q, r0));
+      L.ph_wptr.push_back(int32_t(wrk.size()));
+    }
+    if (L.d_wrk) dev_free(c, L.d_wrk);
+    L.d_wrk = upload(c, wrk);
+    L.sp_lds = size_t(mn + ((mn + 15) / 16) * 64) * sizeof(double);
+    prepare_mult_smoother(L.sp_lds);
   }
   L.d_rec64 = upload(c, o64);
   L.d_rec32 = upload(c, o32);

@@ -169,87 +169,161 @@ __device__ __forceinline__ double krow(int64_t d, const double* __restrict__ x, 
 // (row, 32-column block) items whose loads are all issued before use, with the
 // block partials summed in block order from LDS. (3) x[dofs] += alpha delta.
 // Patches of one phase share no unknown and no coupling, so nothing races.
+constexpr int MX_G = 16;    // lanes per residual row
+constexpr int MX_PER = 4;   // E_E entries a lane loads at once
+constexpr int MX_CB = 16;   // columns per GEMV item (keeps the tile in registers at 1024 threads)
+constexpr int MX_RB = 64;   // rows per workgroup in the split phase kernels
+
+// Residual row r = b_d - (K x)_d of unknown d, computed by a group of MX_G
+// lanes (gl = lane in group): E_E entries strided over the group, indices
+// loaded before the gathers, stencil part on lane 0, fixed-tree reduction.
+// Valid on lane 0. Every phase kernel uses exactly this arithmetic.
+__device__ __forceinline__ double mx_row_residual(int64_t d, int gl, StencilCoef sc, int64_t nv,
+                                                  const int32_t* __restrict__ erow, const int32_t* __restrict__ ecol,
+                                                  const double* __restrict__ eval, const double* __restrict__ b,
+                                                  const double* __restrict__ x) {
+  double acc = 0.0;
+  if (d < nv) {
+    const int q0 = erow[d], q1 = erow[d + 1];
+    for (int qb = q0; qb < q1; qb += MX_G * MX_PER) {
+      int cidx[MX_PER];
+      double cv[MX_PER];
+#pragma unroll
+      for (int k = 0; k < MX_PER; ++k) {
+        const int q = qb + gl + MX_G * k;
+        cidx[k] = q < q1 ? ecol[q] : -1;
+        cv[k] = q < q1 ? eval[q] : 0.0;
+      }
+      double xv[MX_PER];
+#pragma unroll
+      for (int k = 0; k < MX_PER; ++k) xv[k] = cidx[k] >= 0 ? x[cidx[k]] : 0.0;
+#pragma unroll
+      for (int k = 0; k < MX_PER; ++k) acc += cv[k] * xv[k];
+    }
+  }
+  if (gl == 0) acc += krow(d, x, sc, nullptr, nullptr, nullptr);
+#pragma unroll
+  for (int o = MX_G / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, MX_G);
+  return b[d] - acc;
+}
+
+// GEMV item (row i, column block cb) of the stored inverse (column-major n x n)
+// against r: s0 over even and s1 over odd columns of the block, then s0 + s1.
+__device__ __forceinline__ double mx_gemv_item(const MultRec& rec, const double* __restrict__ a64,
+                                               const float* __restrict__ a32, const double* __restrict__ rp, int n,
+                                               int i, int cb) {
+  const int j0 = cb * MX_CB, w = min(MX_CB, n - j0);
+  if (rec.f32) {
+    const float* col = a32 + rec.fac + int64_t(j0) * n + i;
+    float m[MX_CB];
+#pragma unroll
+    for (int jj = 0; jj < MX_CB; ++jj) m[jj] = jj < w ? col[int64_t(jj) * n] : 0.f;
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int jj = 0; jj < MX_CB; jj += 2) {
+      s0 += m[jj] * (jj < w ? float(rp[j0 + jj]) : 0.f);
+      s1 += m[jj + 1] * (jj + 1 < w ? float(rp[j0 + jj + 1]) : 0.f);
+    }
+    return double(s0 + s1);
+  }
+  const double* col = a64 + rec.fac + int64_t(j0) * n + i;
+  double m[MX_CB];
+#pragma unroll
+  for (int jj = 0; jj < MX_CB; ++jj) m[jj] = jj < w ? col[int64_t(jj) * n] : 0.0;
+  double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+  for (int jj = 0; jj < MX_CB; jj += 2) {
+    s0 += m[jj] * (jj < w ? rp[j0 + jj] : 0.0);
+    s1 += m[jj + 1] * (jj + 1 < w ? rp[j0 + jj + 1] : 0.0);
+  }
+  return s0 + s1;
+}
+
+// One phase of the multiplicative sweep over explicit patches, one workgroup
+// per patch (NT threads). (1) All residual rows of the patch into LDS.
+// (2) delta = K_p^{-1} r as (row, 16-column block) items, block partials in
+// LDS. (3) x[dofs] += alpha delta, partials summed in block order.
+// Patches of one phase share no unknown and no coupling, so nothing races.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_mult_exp(const MultRec* __restrict__ recs, const double* __restrict__ a64,
                                                  const float* __restrict__ a32, const int32_t* __restrict__ slot_dof,
                                                  StencilCoef sc, const int32_t* __restrict__ erow,
                                                  const int32_t* __restrict__ ecol, const double* __restrict__ eval,
                                                  const double* __restrict__ b, double* __restrict__ x, double alpha) {
-  constexpr int G = 16;          // lanes per residual row
-  constexpr int PER = 4;         // E_E entries a lane loads at once
-  constexpr int CB = 16;         // columns per GEMV item (keeps the tile in registers at 1024 threads)
   extern __shared__ double smem[];
   const MultRec rec = recs[blockIdx.x];
   const int n = rec.n;
-  const int nb = (n + CB - 1) / CB;
+  const int nb = (n + MX_CB - 1) / MX_CB;
   double* rp = smem;             // n
   double* pp = smem + n;         // nb x n block partials
   const int32_t* dofs = slot_dof + rec.slot;
   const int64_t nv = 2 * int64_t(sc.N) * sc.N;
-  const int grp = threadIdx.x / G, gl = threadIdx.x % G;
-  for (int rr = grp; rr < n; rr += NT / G) {
-    const int64_t d = dofs[rr];
-    double acc = 0.0;
-    if (d < nv) {
-      const int q0 = erow[d], q1 = erow[d + 1];
-      for (int qb = q0; qb < q1; qb += G * PER) {
-        int cidx[PER];
-        double cv[PER];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-          const int q = qb + gl + G * k;
-          cidx[k] = q < q1 ? ecol[q] : -1;
-          cv[k] = q < q1 ? eval[q] : 0.0;
-        }
-        double xv[PER];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) xv[k] = cidx[k] >= 0 ? x[cidx[k]] : 0.0;
-#pragma unroll
-        for (int k = 0; k < PER; ++k) acc += cv[k] * xv[k];
-      }
-    }
-    if (gl == 0) acc += krow(d, x, sc, nullptr, nullptr, nullptr);
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, G);
-    if (gl == 0) rp[rr] = b[d] - acc;
+  const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
+  for (int rr = grp; rr < n; rr += NT / MX_G) {
+    const double r = mx_row_residual(dofs[rr], gl, sc, nv, erow, ecol, eval, b, x);
+    if (gl == 0) rp[rr] = r;
   }
   __syncthreads();
   for (int t = threadIdx.x; t < n * nb; t += NT) {
     const int i = t % n, cb = t / n;
-    const int j0 = cb * CB, w = min(CB, n - j0);
-    double acc;
-    if (rec.f32) {
-      const float* col = a32 + rec.fac + int64_t(j0) * n + i;
-      float m[CB];
-#pragma unroll
-      for (int jj = 0; jj < CB; ++jj) m[jj] = jj < w ? col[int64_t(jj) * n] : 0.f;
-      float s0 = 0.f, s1 = 0.f;
-#pragma unroll
-      for (int jj = 0; jj < CB; jj += 2) {
-        s0 += m[jj] * (jj < w ? float(rp[j0 + jj]) : 0.f);
-        s1 += m[jj + 1] * (jj + 1 < w ? float(rp[j0 + jj + 1]) : 0.f);
-      }
-      acc = double(s0 + s1);
-    } else {
-      const double* col = a64 + rec.fac + int64_t(j0) * n + i;
-      double m[CB];
-#pragma unroll
-      for (int jj = 0; jj < CB; ++jj) m[jj] = jj < w ? col[int64_t(jj) * n] : 0.0;
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int jj = 0; jj < CB; jj += 2) {
-        s0 += m[jj] * (jj < w ? rp[j0 + jj] : 0.0);
-        s1 += m[jj + 1] * (jj + 1 < w ? rp[j0 + jj + 1] : 0.0);
-      }
-      acc = s0 + s1;
-    }
-    pp[int64_t(cb) * n + i] = acc;
+    pp[int64_t(cb) * n + i] = mx_gemv_item(rec, a64, a32, rp, n, i, cb);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += NT) {
     double s = 0.0;
     for (int cb = 0; cb < nb; ++cb) s += pp[int64_t(cb) * n + i];
     x[dofs[i]] += alpha * s;
+  }
+}
+
+// Split form of one phase, for patches too large for one workgroup to stream
+// quickly: work items (patch, block of MX_RB rows). k_mult_res writes the
+// item's residual rows to the patch's slots of `rbuf` (reads x only);
+// k_mult_gemv then reads the whole patch residual from `rbuf`, forms its rows
+// of delta with the same items and block order as k_mult_exp, and updates x
+// at its rows' unknowns only. The results equal k_mult_exp's bit for bit.
+__global__ __launch_bounds__(256) void k_mult_res(const int2* __restrict__ items, const MultRec* __restrict__ recs,
+                                                  const int32_t* __restrict__ slot_dof, StencilCoef sc,
+                                                  const int32_t* __restrict__ erow, const int32_t* __restrict__ ecol,
+                                                  const double* __restrict__ eval, const double* __restrict__ b,
+                                                  const double* __restrict__ x, double* __restrict__ rbuf) {
+  const int2 it = items[blockIdx.x];
+  const MultRec rec = recs[it.x];
+  const int r0 = it.y, r1 = min(rec.n, it.y + MX_RB);
+  const int32_t* dofs = slot_dof + rec.slot;
+  const int64_t nv = 2 * int64_t(sc.N) * sc.N;
+  const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
+  for (int rr = r0 + grp; rr < r1; rr += 256 / MX_G) {
+    const double r = mx_row_residual(dofs[rr], gl, sc, nv, erow, ecol, eval, b, x);
+    if (gl == 0) rbuf[rec.slot + rr] = r;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mult_gemv(const int2* __restrict__ items, const MultRec* __restrict__ recs,
+                                                   const double* __restrict__ a64, const float* __restrict__ a32,
+                                                   const int32_t* __restrict__ slot_dof,
+                                                   const double* __restrict__ rbuf, double* __restrict__ x,
+                                                   double alpha) {
+  extern __shared__ double smem[];
+  const int2 it = items[blockIdx.x];
+  const MultRec rec = recs[it.x];
+  const int n = rec.n;
+  const int nb = (n + MX_CB - 1) / MX_CB;
+  const int r0 = it.y, nr = min(MX_RB, n - r0);
+  double* rp = smem;             // n
+  double* pp = smem + n;         // nb x MX_RB block partials
+  for (int j = threadIdx.x; j < n; j += 256) rp[j] = rbuf[rec.slot + j];
+  __syncthreads();
+  for (int t = threadIdx.x; t < nr * nb; t += 256) {
+    const int ii = t % nr, cb = t / nr;
+    pp[cb * MX_RB + ii] = mx_gemv_item(rec, a64, a32, rp, n, r0 + ii, cb);
+  }
+  __syncthreads();
+  const int32_t* dofs = slot_dof + rec.slot;
+  for (int ii = threadIdx.x; ii < nr; ii += 256) {
+    double s = 0.0;
+    for (int cb = 0; cb < nb; ++cb) s += pp[cb * MX_RB + ii];
+    x[dofs[r0 + ii]] += alpha * s;
   }
 }
 
@@ -299,13 +373,15 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
   const int64_t n2 = int64_t(L.N) * L.N, n = 3 * n2;
   if (zero_guess) launch_fill(x, 0.0, n, s);
   const int nph = int(L.ph_ptr.size()) - 1;
-  for (int ph = 0; ph < nph; ++ph) {
-    const int a = L.ph_ptr[ph], cnt = L.ph_ptr[ph + 1] - a;
+  if (nph > 0) {
+    // one bracket around the run of phase launches of this sweep
     timing_begin(c, s);
-    k_mult_exp<MX_THREADS><<<unsigned(cnt), MX_THREADS, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof,
-                                                                      L.sc, L.d_erow_full, L.d_ecol, L.d_eval, b, x,
-                                                                      c.alpha);
-    timing_end(c, s, L.ph_bytes[ph]);
+    double bytes = 0.0;
+    for (int ph = 0; ph < nph; ++ph) {
+      launch_mult_phase(c, L, ph, L.mx_nt[mx_bucket(L.ph_maxn[ph])], b, x, s);
+      bytes += L.ph_bytes[ph];
+    }
+    timing_end(c, s, bytes, nph);
   }
   const int64_t per_colour = n2 / 8;
   for (int col = 0; col < 8; ++col)
@@ -313,13 +389,40 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
   launch_pressure_mean_remove(x, L.N, L.d_part, s);
 }
 
+void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double* x, hipStream_t s) {
+  const int a = L.ph_ptr[ph], cnt = L.ph_ptr[ph + 1] - a;
+  const unsigned g = unsigned(cnt);
+  if (nt == 0) {
+    const int w0 = L.ph_wptr[ph], nw = L.ph_wptr[ph + 1] - w0;
+    k_mult_res<<<unsigned(nw), 256, 0, s>>>(L.d_wrk + w0, L.d_mrec, L.d_slot_dof, L.sc, L.d_erow_full, L.d_ecol,
+                                            L.d_eval, b, x, L.d_delta);
+    k_mult_gemv<<<unsigned(nw), 256, L.sp_lds, s>>>(L.d_wrk + w0, L.d_mrec, L.d_f64, L.d_f32, L.d_slot_dof,
+                                                    L.d_delta, x, c.alpha);
+    return;
+  }
+  switch (nt) {
+    case 256:
+      k_mult_exp<256><<<g, 256, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full,
+                                               L.d_ecol, L.d_eval, b, x, c.alpha);
+      break;
+    case 512:
+      k_mult_exp<512><<<g, 512, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full,
+                                               L.d_ecol, L.d_eval, b, x, c.alpha);
+      break;
+    default:
+      k_mult_exp<1024><<<g, 1024, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full,
+                                                 L.d_ecol, L.d_eval, b, x, c.alpha);
+  }
+}
+
 // Raises the phase kernel's dynamic-LDS limit once (at setup, never inside a
 // launch sequence that may be captured into a graph).
 void prepare_mult_smoother(size_t lds) {
   static size_t set_to = 64 * 1024;
   if (lds <= set_to) return;
-  CAV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_mult_exp<MX_THREADS>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  for (const void* f : {reinterpret_cast<const void*>(k_mult_exp<256>), reinterpret_cast<const void*>(k_mult_exp<512>),
+                        reinterpret_cast<const void*>(k_mult_exp<1024>), reinterpret_cast<const void*>(k_mult_gemv)})
+    CAV_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   set_to = lds;
 }
 

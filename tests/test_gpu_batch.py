@@ -128,3 +128,28 @@ def test_batch_solve_matches_individual_solves(dev, cav, mode):
         assert np.linalg.norm(x.cpu().numpy() - xr.cpu().numpy()) <= 1e-12 * np.linalg.norm(xr.cpu().numpy())
     for g in solvers:
         g.close()
+
+
+def test_autotune_keeps_results(dev, cav, tmp_path):
+    s = workloads.beam_fibres(N=64, n_levels=4, kappa_b=1e-2)
+    print("[autotune] beam64", flush=True)
+    g = _setup(cav, s, "multiplicative", 1.0)
+    b = torch.from_numpy(s.b).to(dev)
+    z0 = g.vcycle(b).cpu().numpy()
+    x0, i0 = g.fgmres_solve(b, 1e-10, 150)
+    g.autotune(reps=1)
+    for table in (np.full(4 * s.n_levels, 256, np.int32), np.full(4 * s.n_levels, 512, np.int32),
+                  np.full(4 * s.n_levels, 0, np.int32), None):
+        if table is not None:
+            g._check(g._L.cav_set_tuning(g._h, table.ctypes.data_as(cav._binding.C.POINTER(cav._binding.C.c_int32))))
+        np.testing.assert_array_equal(g.vcycle(b).cpu().numpy(), z0)
+        x, inf = g.fgmres_solve(b, 1e-10, 150)
+        assert inf["iterations"] == i0["iterations"]
+        np.testing.assert_array_equal(x.cpu().numpy(), x0.cpu().numpy())
+    # the JSON cache round-trips
+    cache = str(tmp_path / "tune.json")
+    t1 = g.autotune(reps=1, cache=cache)
+    t2 = g.autotune(reps=1, cache=cache)
+    np.testing.assert_array_equal(t1, t2)
+    assert set(np.unique(t1)) <= {0, 256, 512, 1024}
+    g.close()
