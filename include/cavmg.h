@@ -158,6 +158,11 @@ cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold,
  * coloured order, w <- w + alpha R_p^T K_p^{-1} R_p (b - K w). Both remove the
  * mean pressure after the sweep. pre/post = sweeps per V-cycle leg (1, 1). */
 cav_status cav_set_smoother(cav_ctx ctx, int kind, double alpha, int pre, int post);
+/* Per-level override (kind -1 restores the context's choice): level in
+ * 1 .. n_levels-1 uses `kind` with damping `alpha`, e.g. the multiplicative
+ * sweep on the finest level and the additive one below it. Cleared by
+ * cav_build_operator. */
+cav_status cav_set_level_smoother(cav_ctx ctx, int level, int kind, double alpha);
 
 /* ---- application ---- */
 /* y = K_E x on the finest level (x, y device, 3N^2, must not alias). */

@@ -124,6 +124,7 @@ _SIGS = {
                                      C.POINTER(C.c_double)], C.c_int),
     "cav_learned_pairs": ([_P, C.c_int32, _P, C.c_int32, _P, _P], C.c_int),
     "cav_autotune": ([_P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+    "cav_set_level_smoother": ([_P, C.c_int, C.c_int, C.c_double], C.c_int),
     "cav_set_tuning": ([_P, C.POINTER(C.c_int32)], C.c_int),
     "cav_fgmres_solve_graph": ([_P, _P, _P, C.POINTER(FgmresOpts), C.POINTER(SolveInfo)], C.c_int),
     "cav_batch_solve": ([C.POINTER(_P), C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(FgmresOpts),
@@ -404,6 +405,11 @@ class Solver:
 
     def set_smoother(self, kind: str = "additive", alpha: float = 0.7, pre: int = 1, post: int = 1) -> None:
         self._check(self._L.cav_set_smoother(self._h, SMOOTHER[kind], float(alpha), int(pre), int(post)))
+
+    def set_level_smoother(self, level: int, kind: Optional[str], alpha: float = 0.7) -> None:
+        """Override the smoother of one smoothed level (None restores the context's)."""
+        self._check(self._L.cav_set_level_smoother(self._h, int(level), -1 if kind is None else SMOOTHER[kind],
+                                                   float(alpha)))
 
     def setup(self, system, family="cav", precision="fp64", cond_threshold=1e6, alpha=0.7, smoother="additive"):
         self.build_operator(system)

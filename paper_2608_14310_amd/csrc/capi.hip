@@ -1254,4 +1254,20 @@ cav_status cav_set_tuning(cav_ctx ctx, const int32_t* table) {
   API_END
 }
 
+cav_status cav_set_level_smoother(cav_ctx ctx, int level, int kind, double alpha) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.built, CAV_ERR_NOT_BUILT, "cav_build_operator has not succeeded");
+  require(level >= 1 && level < c.n_levels, CAV_ERR_INVALID_ARG, "level must be a smoothed level (1 .. n_levels-1)");
+  require(kind == -1 || kind == CAV_SMOOTHER_ADDITIVE || kind == CAV_SMOOTHER_MULTIPLICATIVE, CAV_ERR_INVALID_ARG,
+          "kind must be -1 or a CAV_SMOOTHER_* value");
+  require(kind == -1 || std::isfinite(alpha), CAV_ERR_INVALID_ARG, "alpha must be finite");
+  c.lv[level].smoother = kind;
+  c.lv[level].alpha = alpha;
+  ++c.generation;
+  return CAV_OK;
+  API_END
+}
+
 }  // extern "C"

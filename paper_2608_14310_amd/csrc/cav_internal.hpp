@@ -87,6 +87,8 @@ struct Level {
   int32_t mrec_max_n = 0;
   std::vector<double> ph_bytes;           // algorithmic bytes of each phase launch
   std::vector<int32_t> ph_maxn;           // largest patch of each phase
+  int32_t smoother = -1;                  // per-level smoother kind (-1: the context's)
+  double alpha = 0.0;                     // its damping when smoother >= 0
   int32_t mx_nt[4] = {1024, 1024, 1024, 1024};  // per size bucket: 256/512/1024 threads, 0 = split form (autotuned)
   std::vector<int32_t> ph_wptr;           // split form: work items of each phase (offsets)
   int2* d_wrk = nullptr;                  // (record index in d_mrec, first row)
@@ -247,6 +249,8 @@ void launch_prolong_add(const Level& Lf, const double* xc, double* xf, hipStream
 void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
 void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
 void prepare_mult_smoother(size_t lds);
+inline int level_smoother(const Ctx& c, const Level& L) { return L.smoother >= 0 ? L.smoother : c.smoother; }
+inline double level_alpha(const Ctx& c, const Level& L) { return L.smoother >= 0 ? L.alpha : c.alpha; }
 // size bucket of a phase by its largest patch: <= 64, <= 128, <= 256, larger
 inline int mx_bucket(int n) { return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : 3; }
 // one explicit phase: nt = 256, 512 or 1024 threads per patch, or 0 for the split form

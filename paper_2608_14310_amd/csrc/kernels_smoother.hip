@@ -174,62 +174,99 @@ constexpr int MX_PER = 4;   // E_E entries a lane loads at once
 constexpr int MX_CB = 16;   // columns per GEMV item (keeps the tile in registers at 1024 threads)
 constexpr int MX_RB = 64;   // rows per workgroup in the split phase kernels
 
-// Residual row r = b_d - (K x)_d of unknown d, computed by a group of MX_G
-// lanes (gl = lane in group): E_E entries strided over the group, indices
-// loaded before the gathers, stencil part on lane 0, fixed-tree reduction.
-// Valid on lane 0. Every phase kernel uses exactly this arithmetic.
-__device__ __forceinline__ double mx_row_residual(int64_t d, int gl, StencilCoef sc, int64_t nv,
-                                                  const int32_t* __restrict__ erow, const int32_t* __restrict__ ecol,
-                                                  const double* __restrict__ eval, const double* __restrict__ b,
-                                                  const double* __restrict__ x) {
-  double acc = 0.0;
-  if (d < nv) {
-    const int q0 = erow[d], q1 = erow[d + 1];
-    for (int qb = q0; qb < q1; qb += MX_G * MX_PER) {
-      int cidx[MX_PER];
-      double cv[MX_PER];
+// Residual rows r = b_d - (K x)_d of the patch unknowns dofs[rr], for rows
+// rr = r0 + u * step (u < MX_R, rr < r1), each computed by one group of MX_G
+// lanes (gl = lane in group): E_E entries strided over the group in rounds of
+// MX_G * MX_PER, indices loaded before the gathers, the stencil part added on
+// lane 0, then a fixed-tree reduction; lane 0 passes each row to `emit`.
+// The MX_R rows of a group are interleaved so that their dependent loads are
+// in flight together; each row's own sequence of operations (and so its
+// value) does not depend on how rows are grouped, which keeps every phase
+// kernel bit-identical.
+constexpr int MX_R = 4;
+template <typename Emit>
+__device__ __forceinline__ void mx_residual_rows(const int32_t* __restrict__ dofs, int r0, int step, int r1, int gl,
+                                                 StencilCoef sc, int64_t nv, const int32_t* __restrict__ erow,
+                                                 const int32_t* __restrict__ ecol, const double* __restrict__ eval,
+                                                 const double* __restrict__ b, const double* __restrict__ x,
+                                                 Emit emit) {
+  int64_t d[MX_R];
+  int q0[MX_R], q1[MX_R];
+#pragma unroll
+  for (int u = 0; u < MX_R; ++u) {
+    const int rr = r0 + u * step;
+    d[u] = rr < r1 ? int64_t(dofs[rr]) : int64_t(-1);
+  }
+  int rounds = 0;
+#pragma unroll
+  for (int u = 0; u < MX_R; ++u) {
+    const bool ee = d[u] >= 0 && d[u] < nv;
+    q0[u] = ee ? erow[d[u]] : 0;
+    q1[u] = ee ? erow[d[u] + 1] : 0;
+    rounds = max(rounds, (q1[u] - q0[u] + MX_G * MX_PER - 1) / (MX_G * MX_PER));
+  }
+  double acc[MX_R];
+#pragma unroll
+  for (int u = 0; u < MX_R; ++u) acc[u] = 0.0;
+  for (int k0 = 0; k0 < rounds; ++k0) {
+    int cidx[MX_R][MX_PER];
+    double cv[MX_R][MX_PER];
+#pragma unroll
+    for (int u = 0; u < MX_R; ++u)
 #pragma unroll
       for (int k = 0; k < MX_PER; ++k) {
-        const int q = qb + gl + MX_G * k;
-        cidx[k] = q < q1 ? ecol[q] : -1;
-        cv[k] = q < q1 ? eval[q] : 0.0;
+        const int q = q0[u] + k0 * MX_G * MX_PER + gl + MX_G * k;
+        cidx[u][k] = q < q1[u] ? ecol[q] : -1;
+        cv[u][k] = q < q1[u] ? eval[q] : 0.0;
       }
-      double xv[MX_PER];
+    double xv[MX_R][MX_PER];
 #pragma unroll
-      for (int k = 0; k < MX_PER; ++k) xv[k] = cidx[k] >= 0 ? x[cidx[k]] : 0.0;
+    for (int u = 0; u < MX_R; ++u)
 #pragma unroll
-      for (int k = 0; k < MX_PER; ++k) acc += cv[k] * xv[k];
-    }
+      for (int k = 0; k < MX_PER; ++k) xv[u][k] = cidx[u][k] >= 0 ? x[cidx[u][k]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < MX_R; ++u)
+      if (q0[u] + k0 * MX_G * MX_PER < q1[u]) {
+#pragma unroll
+        for (int k = 0; k < MX_PER; ++k) acc[u] += cv[u][k] * xv[u][k];
+      }
   }
-  if (gl == 0) acc += krow(d, x, sc, nullptr, nullptr, nullptr);
 #pragma unroll
-  for (int o = MX_G / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, MX_G);
-  return b[d] - acc;
+  for (int u = 0; u < MX_R; ++u) {
+    if (gl == 0 && d[u] >= 0) acc[u] += krow(d[u], x, sc, nullptr, nullptr, nullptr);
+#pragma unroll
+    for (int o = MX_G / 2; o > 0; o >>= 1) acc[u] += __shfl_down(acc[u], o, MX_G);
+    if (gl == 0 && d[u] >= 0) emit(r0 + u * step, b[d[u]] - acc[u]);
+  }
 }
 
 // GEMV item (row i, column block cb) of the stored inverse (column-major n x n)
 // against r: s0 over even and s1 over odd columns of the block, then s0 + s1.
-__device__ __forceinline__ double mx_gemv_item(const MultRec& rec, const double* __restrict__ a64,
-                                               const float* __restrict__ a32, const double* __restrict__ rp, int n,
-                                               int i, int cb) {
+// Items come in pairs whose loads are all issued before either is used (two
+// HBM round trips overlap instead of following each other); each item's
+// arithmetic is the same whether it is paired or not.
+template <typename T>
+__device__ __forceinline__ void mx_load_item(const T* __restrict__ arena, int64_t fac, int n, int i, int cb, bool ok,
+                                             T (&m)[MX_CB]) {
+  const int j0 = cb * MX_CB, w = ok ? min(MX_CB, n - j0) : 0;
+  const T* col = arena + fac + int64_t(j0) * n + i;
+#pragma unroll
+  for (int jj = 0; jj < MX_CB; ++jj) m[jj] = jj < w ? col[int64_t(jj) * n] : T(0);
+}
+
+__device__ __forceinline__ double mx_dot_item(const float (&m)[MX_CB], const double* __restrict__ rp, int n, int cb) {
   const int j0 = cb * MX_CB, w = min(MX_CB, n - j0);
-  if (rec.f32) {
-    const float* col = a32 + rec.fac + int64_t(j0) * n + i;
-    float m[MX_CB];
+  float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-    for (int jj = 0; jj < MX_CB; ++jj) m[jj] = jj < w ? col[int64_t(jj) * n] : 0.f;
-    float s0 = 0.f, s1 = 0.f;
-#pragma unroll
-    for (int jj = 0; jj < MX_CB; jj += 2) {
-      s0 += m[jj] * (jj < w ? float(rp[j0 + jj]) : 0.f);
-      s1 += m[jj + 1] * (jj + 1 < w ? float(rp[j0 + jj + 1]) : 0.f);
-    }
-    return double(s0 + s1);
+  for (int jj = 0; jj < MX_CB; jj += 2) {
+    s0 += m[jj] * (jj < w ? float(rp[j0 + jj]) : 0.f);
+    s1 += m[jj + 1] * (jj + 1 < w ? float(rp[j0 + jj + 1]) : 0.f);
   }
-  const double* col = a64 + rec.fac + int64_t(j0) * n + i;
-  double m[MX_CB];
-#pragma unroll
-  for (int jj = 0; jj < MX_CB; ++jj) m[jj] = jj < w ? col[int64_t(jj) * n] : 0.0;
+  return double(s0 + s1);
+}
+
+__device__ __forceinline__ double mx_dot_item(const double (&m)[MX_CB], const double* __restrict__ rp, int n, int cb) {
+  const int j0 = cb * MX_CB, w = min(MX_CB, n - j0);
   double s0 = 0.0, s1 = 0.0;
 #pragma unroll
   for (int jj = 0; jj < MX_CB; jj += 2) {
@@ -237,6 +274,25 @@ __device__ __forceinline__ double mx_gemv_item(const MultRec& rec, const double*
     s1 += m[jj + 1] * (jj + 1 < w ? rp[j0 + jj + 1] : 0.0);
   }
   return s0 + s1;
+}
+
+// items t and t + stride (t < count) of an item list mapped by `ij` to
+// (row, block); results go to `put(t, value)`.
+template <typename T, typename IJ, typename Put>
+__device__ __forceinline__ void mx_gemv_pairs(const T* __restrict__ arena, int64_t fac, const double* __restrict__ rp,
+                                              int n, int count, int stride, IJ ij, Put put) {
+  for (int t = threadIdx.x; t < count; t += 2 * stride) {
+    const int t2 = t + stride;
+    const bool ok2 = t2 < count;
+    int i1, c1, i2 = 0, c2 = 0;
+    ij(t, i1, c1);
+    if (ok2) ij(t2, i2, c2);
+    T m1[MX_CB], m2[MX_CB];
+    mx_load_item(arena, fac, n, i1, c1, true, m1);
+    mx_load_item(arena, fac, n, i2, c2, ok2, m2);
+    put(t, mx_dot_item(m1, rp, n, c1));
+    if (ok2) put(t2, mx_dot_item(m2, rp, n, c2));
+  }
 }
 
 // One phase of the multiplicative sweep over explicit patches, one workgroup
@@ -259,14 +315,20 @@ __global__ __launch_bounds__(NT) void k_mult_exp(const MultRec* __restrict__ rec
   const int32_t* dofs = slot_dof + rec.slot;
   const int64_t nv = 2 * int64_t(sc.N) * sc.N;
   const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
-  for (int rr = grp; rr < n; rr += NT / MX_G) {
-    const double r = mx_row_residual(dofs[rr], gl, sc, nv, erow, ecol, eval, b, x);
-    if (gl == 0) rp[rr] = r;
-  }
+  constexpr int NG = NT / MX_G;
+  for (int rb = grp; rb < n; rb += NG * MX_R)
+    mx_residual_rows(dofs, rb, NG, n, gl, sc, nv, erow, ecol, eval, b, x, [&](int rr, double r) { rp[rr] = r; });
   __syncthreads();
-  for (int t = threadIdx.x; t < n * nb; t += NT) {
-    const int i = t % n, cb = t / n;
-    pp[int64_t(cb) * n + i] = mx_gemv_item(rec, a64, a32, rp, n, i, cb);
+  {
+    auto ij = [n](int t, int& i, int& cb) {
+      i = t % n;
+      cb = t / n;
+    };
+    auto put = [pp](int t, double v) { pp[t] = v; };  // item t = cb * n + i
+    if (rec.f32)
+      mx_gemv_pairs(a32, rec.fac, rp, n, n * nb, NT, ij, put);
+    else
+      mx_gemv_pairs(a64, rec.fac, rp, n, n * nb, NT, ij, put);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += NT) {
@@ -293,10 +355,10 @@ __global__ __launch_bounds__(256) void k_mult_res(const int2* __restrict__ items
   const int32_t* dofs = slot_dof + rec.slot;
   const int64_t nv = 2 * int64_t(sc.N) * sc.N;
   const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
-  for (int rr = r0 + grp; rr < r1; rr += 256 / MX_G) {
-    const double r = mx_row_residual(dofs[rr], gl, sc, nv, erow, ecol, eval, b, x);
-    if (gl == 0) rbuf[rec.slot + rr] = r;
-  }
+  constexpr int NG = 256 / MX_G;
+  for (int rb = r0 + grp; rb < r1; rb += NG * MX_R)
+    mx_residual_rows(dofs, rb, NG, r1, gl, sc, nv, erow, ecol, eval, b, x,
+                     [&](int rr, double r) { rbuf[rec.slot + rr] = r; });
 }
 
 __global__ __launch_bounds__(256) void k_mult_gemv(const int2* __restrict__ items, const MultRec* __restrict__ recs,
@@ -314,9 +376,16 @@ __global__ __launch_bounds__(256) void k_mult_gemv(const int2* __restrict__ item
   double* pp = smem + n;         // nb x MX_RB block partials
   for (int j = threadIdx.x; j < n; j += 256) rp[j] = rbuf[rec.slot + j];
   __syncthreads();
-  for (int t = threadIdx.x; t < nr * nb; t += 256) {
-    const int ii = t % nr, cb = t / nr;
-    pp[cb * MX_RB + ii] = mx_gemv_item(rec, a64, a32, rp, n, r0 + ii, cb);
+  {
+    auto ij = [nr, r0](int t, int& i, int& cb) {
+      i = r0 + t % nr;
+      cb = t / nr;
+    };
+    auto put = [pp, nr](int t, double v) { pp[(t / nr) * MX_RB + t % nr] = v; };
+    if (rec.f32)
+      mx_gemv_pairs(a32, rec.fac, rp, n, nr * nb, 256, ij, put);
+    else
+      mx_gemv_pairs(a64, rec.fac, rp, n, nr * nb, 256, ij, put);
   }
   __syncthreads();
   const int32_t* dofs = slot_dof + rec.slot;
@@ -385,7 +454,8 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
   }
   const int64_t per_colour = n2 / 8;
   for (int col = 0; col < 8; ++col)
-    k_mult_std<<<nblocks(per_colour), TPB, 0, s>>>(L.N, col, L.d_cellflag, L.d_std_inv, L.sc, b, x, c.alpha);
+    k_mult_std<<<nblocks(per_colour), TPB, 0, s>>>(L.N, col, L.d_cellflag, L.d_std_inv, L.sc, b, x,
+                                                   level_alpha(c, L));
   launch_pressure_mean_remove(x, L.N, L.d_part, s);
 }
 
@@ -397,21 +467,21 @@ void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double
     k_mult_res<<<unsigned(nw), 256, 0, s>>>(L.d_wrk + w0, L.d_mrec, L.d_slot_dof, L.sc, L.d_erow_full, L.d_ecol,
                                             L.d_eval, b, x, L.d_delta);
     k_mult_gemv<<<unsigned(nw), 256, L.sp_lds, s>>>(L.d_wrk + w0, L.d_mrec, L.d_f64, L.d_f32, L.d_slot_dof,
-                                                    L.d_delta, x, c.alpha);
+                                                    L.d_delta, x, level_alpha(c, L));
     return;
   }
   switch (nt) {
     case 256:
       k_mult_exp<256><<<g, 256, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full,
-                                               L.d_ecol, L.d_eval, b, x, c.alpha);
+                                               L.d_ecol, L.d_eval, b, x, level_alpha(c, L));
       break;
     case 512:
       k_mult_exp<512><<<g, 512, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full,
-                                               L.d_ecol, L.d_eval, b, x, c.alpha);
+                                               L.d_ecol, L.d_eval, b, x, level_alpha(c, L));
       break;
     default:
       k_mult_exp<1024><<<g, 1024, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full,
-                                                 L.d_ecol, L.d_eval, b, x, c.alpha);
+                                                 L.d_ecol, L.d_eval, b, x, level_alpha(c, L));
   }
 }
 
@@ -427,7 +497,7 @@ void prepare_mult_smoother(size_t lds) {
 }
 
 void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s) {
-  if (c.smoother == CAV_SMOOTHER_MULTIPLICATIVE) {
+  if (level_smoother(c, L) == CAV_SMOOTHER_MULTIPLICATIVE) {
     launch_mult_smoother(c, L, b, x, zero_guess, s);
     return;
   }
@@ -443,7 +513,7 @@ void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_gue
   if (L.n_touched > 0)
     k_touched<<<nblocks(L.n_touched), TPB, 0, s>>>(L.n_touched, L.d_t_dof, L.d_t_inv, L.d_t_ptr, L.d_t_slot, L.d_delta,
                                                    L.d_z);
-  k_update<<<nblocks(n), TPB, 0, s>>>(x, L.d_z, c.alpha, zero_guess ? 1 : 0, n);
+  k_update<<<nblocks(n), TPB, 0, s>>>(x, L.d_z, level_alpha(c, L), zero_guess ? 1 : 0, n);
   launch_pressure_mean_remove(x, L.N, L.d_part, s);
 }
 

@@ -153,3 +153,24 @@ def test_autotune_keeps_results(dev, cav, tmp_path):
     np.testing.assert_array_equal(t1, t2)
     assert set(np.unique(t1)) <= {0, 256, 512, 1024}
     g.close()
+
+
+def test_level_smoother_override(dev, cav):
+    s = workloads.beam_fibres(N=64, n_levels=4, kappa_b=1e-2)
+    print("[level smoother override] beam64", flush=True)
+    g = _setup(cav, s, "multiplicative", 1.0)
+    b = torch.from_numpy(s.b).to(dev)
+    z0 = g.vcycle(b).cpu().numpy()
+    for l in range(1, s.n_levels):                    # the same choice, per level: same bits
+        g.set_level_smoother(l, "multiplicative", 1.0)
+    np.testing.assert_array_equal(g.vcycle(b).cpu().numpy(), z0)
+    for l in range(1, s.n_levels - 1):                # additive below the finest level
+        g.set_level_smoother(l, "additive", 1.0)
+    z1 = g.vcycle(b).cpu().numpy()
+    assert not np.array_equal(z1, z0)
+    _, inf = g.fgmres_solve(b, 1e-10, 150)
+    assert inf["converged"] and inf["true_rel_residual"] < 2e-10
+    for l in range(1, s.n_levels):                    # None restores the context's smoother
+        g.set_level_smoother(l, None)
+    np.testing.assert_array_equal(g.vcycle(b).cpu().numpy(), z0)
+    g.close()
