@@ -194,7 +194,7 @@ def main():
     ap.add_argument("--smoother", default="multiplicative", choices=["multiplicative", "additive"])
     ap.add_argument("--kappa-b", type=float, default=1e-2)
     ap.add_argument("--stiff-sweep", type=float, nargs="*", default=[1.0, 1e2])
-    ap.add_argument("--tune", default="none", choices=["auto", "none", "split"],
+    ap.add_argument("--tune", default="none", choices=["auto", "none", "split", "sweep"],
                     help="phase-kernel table of the timed steps: 1024 threads per patch everywhere (none), "
                          "autotuned, or the split form everywhere; the autotuned table is reported after them")
     ap.add_argument("--no-other-precision", action="store_true")
@@ -255,7 +255,10 @@ def main():
     if a.tune == "auto":
         table = g.autotune(reps=3)
     elif a.tune == "split":
-        table = np.zeros((s.n_levels, 4), dtype=np.int32)
+        table = np.zeros((s.n_levels, 5), dtype=np.int32)
+    elif a.tune == "sweep":
+        table = np.full((s.n_levels, 5), 1024, dtype=np.int32)
+        table[:, 4] = 1
     for _ in range(a.warmup):
         one_step(a.precision)
     torch.cuda.synchronize()

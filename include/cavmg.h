@@ -209,15 +209,21 @@ cav_status cav_batch_solve(cav_ctx* ctxs, int32_t n_sys, const double* const* b,
 
 /* ---- autotuning ----
  * The multiplicative sweep launches one kernel per colour phase; each patch
- * of a phase gets one workgroup of 256, 512 or 1024 threads. cav_autotune
- * times the three sizes on the context's own phases, per smoothed level and
- * per size bucket of a phase's largest patch (<= 64, <= 128, <= 256, larger),
- * `reps` repetitions each, keeps the fastest, and writes the table (4 ints per
- * level, levels 0 .. n_levels-1; level 0 is unused) to `table` (optional).
- * Results do not depend on the choice (every patch's arithmetic is the same
- * for all three sizes). Uses the levels' scratch vectors; synchronises.
- * cav_set_tuning applies a stored table (entries 256, 512 or 1024), e.g. one
- * cached in a file by the caller. */
+ * of a phase gets one workgroup of 256, 512 or 1024 threads, or (entry 0) the
+ * split form: its residual rows and GEMV row blocks spread over several
+ * workgroups in two launches. Alternatively the whole sweep of a level runs
+ * in one cooperative launch with a bounded grid barrier after each phase.
+ * cav_autotune times the choices on the context's own phases, per smoothed
+ * level and per size bucket of a phase's largest patch (<= 64, <= 128,
+ * <= 256, larger), then per level per-phase launches against the one-launch
+ * sweep, `reps` repetitions each, keeps the fastest, and writes the table
+ * (5 ints per level, levels 0 .. n_levels-1, level 0 unused: 4 bucket
+ * entries, then 1 for the one-launch sweep) to `table` (optional). Results do
+ * not depend on the choice (every patch's and cell's arithmetic is the same).
+ * Uses the levels' scratch vectors; synchronises. A one-launch sweep whose
+ * barrier wait times out stops early and makes the next FGMRES solve return
+ * CAV_ERR_HIP. cav_set_tuning applies a stored table, e.g. one cached in a
+ * file by the caller. */
 cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table);
 cav_status cav_set_tuning(cav_ctx ctx, const int32_t* table);
 

@@ -493,9 +493,9 @@ class Solver:
             if stored is not None:
                 t = np.ascontiguousarray(stored, dtype=np.int32)
                 self.set_tuning(t)
-                return t.reshape(self.n_levels, 4)
+                return t.reshape(self.n_levels, 5)
         self._sync_stream()
-        t = np.zeros(4 * self.n_levels, dtype=np.int32)
+        t = np.zeros(5 * self.n_levels, dtype=np.int32)
         self._check(self._L.cav_autotune(self._h, int(reps), _arr(t, C.c_int32)))
         if cache is not None:
             try:
@@ -506,10 +506,11 @@ class Solver:
             data[key] = t.tolist()
             with open(cache, "w") as f:
                 json.dump(data, f, indent=1)
-        return t.reshape(self.n_levels, 4)
+        return t.reshape(self.n_levels, 5)
 
     def set_tuning(self, table) -> None:
-        """Apply a phase-kernel table (n_levels x 4 entries of 0, 256, 512, 1024)."""
+        """Apply a phase-kernel table (n_levels x 5: four bucket entries of 0, 256,
+        512 or 1024, then 1 for the one-launch sweep of that level)."""
         t = np.ascontiguousarray(table, dtype=np.int32).ravel()
         self._check(self._L.cav_set_tuning(self._h, _arr(t, C.c_int32)))
 

@@ -67,7 +67,7 @@ void free_level(Ctx& c, Level& L) {
                   (void*)L.d_cellflag, (void*)L.d_slot_dof, (void*)L.d_delta, (void*)L.d_t_dof, (void*)L.d_t_inv,
                   (void*)L.d_t_ptr, (void*)L.d_t_slot, (void*)L.d_std_inv, (void*)L.d_rec64, (void*)L.d_rec32,
                   (void*)L.d_f64, (void*)L.d_f32, (void*)L.d_b, (void*)L.d_x, (void*)L.d_r, (void*)L.d_z,
-                  (void*)L.d_part, (void*)L.d_mrec, (void*)L.d_wrk})
+                  (void*)L.d_part, (void*)L.d_mrec, (void*)L.d_wrk, (void*)L.d_ph_ptr})
     dev_free(c, p);
   L = Level();
 }
@@ -76,7 +76,7 @@ void free_patches(Ctx& c, Level& L) {
   for (void** p : {(void**)&L.d_cellflag, (void**)&L.d_slot_dof, (void**)&L.d_delta, (void**)&L.d_t_dof,
                    (void**)&L.d_t_inv, (void**)&L.d_t_ptr, (void**)&L.d_t_slot, (void**)&L.d_std_inv,
                    (void**)&L.d_rec64, (void**)&L.d_rec32, (void**)&L.d_f64, (void**)&L.d_f32,
-                   (void**)&L.d_mrec, (void**)&L.d_wrk}) {
+                   (void**)&L.d_mrec, (void**)&L.d_wrk, (void**)&L.d_ph_ptr}) {
     dev_free(c, *p);
     *p = nullptr;
   }
@@ -154,6 +154,18 @@ double dnorm(Ctx& c, const double* x, int64_t n) {
   return std::sqrt(v);
 }
 
+// A persistent sweep whose grid barrier timed out leaves a flag: report it.
+void check_sweep_flags(Ctx& c) {
+  if (!c.d_bar) return;
+  unsigned long long f[2] = {0, 0};
+  CAV_HIP(hipMemcpyAsync(f, c.d_bar, sizeof(f), hipMemcpyDeviceToHost, c.stream));
+  CAV_HIP(hipStreamSynchronize(c.stream));
+  if (f[1] != 0) {
+    launch_clear_sweep_flags(c, c.stream);
+    throw StatusError(CAV_ERR_HIP, "a persistent smoother sweep timed out at a grid barrier; results are invalid");
+  }
+}
+
 // ---- graph-mode FGMRES ----
 void drop_graph(Ctx& c) {
   if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
@@ -198,6 +210,7 @@ hipGraphExec_t capture_bodies(const std::vector<Ctx*>& cs, hipStream_t origin, d
     saved.push_back(c->stream);
     tsaved.push_back(c->timing);
     c->timing = false;
+    c->capturing = true;  // per-phase launches only (no cooperative launch inside a graph)
   }
   hipEvent_t fork;
   CAV_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
@@ -230,6 +243,7 @@ hipGraphExec_t capture_bodies(const std::vector<Ctx*>& cs, hipStream_t origin, d
     for (size_t i = 0; i < cs.size(); ++i) {
       cs[i]->stream = saved[i];
       cs[i]->timing = tsaved[i];
+      cs[i]->capturing = false;
     }
     (void)hipEventDestroy(fork);
     for (hipEvent_t e : joins)
@@ -239,6 +253,7 @@ hipGraphExec_t capture_bodies(const std::vector<Ctx*>& cs, hipStream_t origin, d
   for (size_t i = 0; i < cs.size(); ++i) {
     cs[i]->stream = saved[i];
     cs[i]->timing = tsaved[i];
+    cs[i]->capturing = false;
   }
   (void)hipEventDestroy(fork);
   for (hipEvent_t e : joins)
@@ -319,6 +334,7 @@ cav_status graph_finish(Ctx& c, const Start& st, double* x, double rtol, const c
   launch_multi_axpy(x, c.d_Z, n, k, c.d_h, 1.0, n, s);
   launch_apply_op(F, x, c.d_w, c.d_bb, s);
   const double rn = dnorm(c, c.d_w, n);
+  check_sweep_flags(c);
   inf.iterations = k;
   inf.converged = gi[GI_CONV];
   inf.est_rel_residual = gs[GS_EST];
@@ -666,6 +682,7 @@ cav_status cav_fgmres_solve(cav_ctx ctx, const double* b, double* x, const cav_f
   double* Z = c.d_Z;
   k_axpby<<<nblocks(n), TPB, 0, s>>>(V, 1.0 / beta, c.d_bb, 0.0, n);
   const int nbk = dots_blocks(n);
+  launch_clear_sweep_flags(c, s);
   const bool learned = opts && opts->use_learned;
   if (learned) {
     require(c.net != nullptr, CAV_ERR_NOT_BUILT, "use_learned is set but no net is attached");
@@ -1197,6 +1214,7 @@ cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table) {
   } guard{e0, e1};
   const bool timing = c.timing;
   c.timing = false;
+  launch_clear_sweep_flags(c, s);
   const int cand[4] = {256, 512, 1024, 0};
   for (int l = 1; l < c.n_levels; ++l) {
     Level& L = c.lv[l];
@@ -1229,12 +1247,28 @@ cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table) {
       }
       L.mx_nt[bk] = pick;
     }
+    // whole sweep: per-phase launches with the table above, or one cooperative launch
+    float t_sweep[2] = {0.f, 0.f};
+    for (int pers = 0; pers < 2; ++pers) {
+      L.persistent = pers != 0;
+      launch_mult_smoother(c, L, L.d_b, L.d_x, false, s);  // warm-up
+      CAV_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) launch_mult_smoother(c, L, L.d_b, L.d_x, false, s);
+      CAV_HIP(hipEventRecord(e1, s));
+      CAV_HIP(hipEventSynchronize(e1));
+      CAV_HIP(hipGetLastError());
+      CAV_HIP(hipEventElapsedTime(&t_sweep[pers], e0, e1));
+    }
+    check_sweep_flags(c);
+    L.persistent = t_sweep[1] < t_sweep[0];
   }
   c.timing = timing;
   ++c.generation;
   if (table)
-    for (int l = 0; l < c.n_levels; ++l)
-      for (int bk = 0; bk < 4; ++bk) table[4 * l + bk] = c.lv[l].mx_nt[bk];
+    for (int l = 0; l < c.n_levels; ++l) {
+      for (int bk = 0; bk < 4; ++bk) table[5 * l + bk] = c.lv[l].mx_nt[bk];
+      table[5 * l + 4] = c.lv[l].persistent ? 1 : 0;
+    }
   return CAV_OK;
   API_END
 }
@@ -1244,11 +1278,18 @@ cav_status cav_set_tuning(cav_ctx ctx, const int32_t* table) {
   Ctx& c = ctx->c;
   API_BEGIN
   require(c.built && table != nullptr, CAV_ERR_INVALID_ARG, "needs a built context and a table");
-  for (int q = 0; q < 4 * c.n_levels; ++q)
-    require(table[q] == 256 || table[q] == 512 || table[q] == 1024 || table[q] == 0, CAV_ERR_INVALID_ARG,
-            "table entries must be 256, 512, 1024 or 0 (split form)");
-  for (int l = 0; l < c.n_levels; ++l)
-    for (int bk = 0; bk < 4; ++bk) c.lv[l].mx_nt[bk] = table[4 * l + bk];
+  for (int l = 0; l < c.n_levels; ++l) {
+    for (int bk = 0; bk < 4; ++bk) {
+      const int v = table[5 * l + bk];
+      require(v == 256 || v == 512 || v == 1024 || v == 0, CAV_ERR_INVALID_ARG,
+              "bucket entries must be 256, 512, 1024 or 0 (split form)");
+    }
+    require(table[5 * l + 4] == 0 || table[5 * l + 4] == 1, CAV_ERR_INVALID_ARG, "the sweep entry must be 0 or 1");
+  }
+  for (int l = 0; l < c.n_levels; ++l) {
+    for (int bk = 0; bk < 4; ++bk) c.lv[l].mx_nt[bk] = table[5 * l + bk];
+    c.lv[l].persistent = table[5 * l + 4] != 0;
+  }
   ++c.generation;
   return CAV_OK;
   API_END

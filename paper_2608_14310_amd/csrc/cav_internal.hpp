@@ -90,6 +90,9 @@ struct Level {
   int32_t smoother = -1;                  // per-level smoother kind (-1: the context's)
   double alpha = 0.0;                     // its damping when smoother >= 0
   int32_t mx_nt[4] = {1024, 1024, 1024, 1024};  // per size bucket: 256/512/1024 threads, 0 = split form (autotuned)
+  int32_t* d_ph_ptr = nullptr;            // device copy of ph_ptr (persistent sweep)
+  bool persistent = false;                // whole sweep in one cooperative launch (autotuned)
+  int sweep_grid = 0;                     // its workgroups (0: not yet computed)
   std::vector<int32_t> ph_wptr;           // split form: work items of each phase (offsets)
   int2* d_wrk = nullptr;                  // (record index in d_mrec, first row)
   size_t sp_lds = 0;                      // dynamic LDS of the split GEMV kernel
@@ -191,6 +194,8 @@ struct Ctx {
   int64_t pw_n = 0;
   // graph-mode FGMRES: own stream (capture needs a non-default stream),
   // device state, fixed V-cycle input/output, captured iteration body
+  unsigned long long* d_bar = nullptr;   // persistent-sweep barrier counter and error flag (2 x u64)
+  bool capturing = false;                // set while a graph is being captured
   hipStream_t gstream = nullptr;
   int32_t* d_gi = nullptr;
   double* d_gs = nullptr;
@@ -249,6 +254,9 @@ void launch_prolong_add(const Level& Lf, const double* xc, double* xf, hipStream
 void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
 void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
 void prepare_mult_smoother(size_t lds);
+// the whole multiplicative sweep of level L in one cooperative launch; false if not possible
+bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t s);
+void launch_clear_sweep_flags(Ctx& c, hipStream_t s);
 inline int level_smoother(const Ctx& c, const Level& L) { return L.smoother >= 0 ? L.smoother : c.smoother; }
 inline double level_alpha(const Ctx& c, const Level& L) { return L.smoother >= 0 ? L.alpha : c.alpha; }
 // size bucket of a phase by its largest patch: <= 64, <= 128, <= 256, larger

@@ -703,6 +703,13 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
     }
     if (L.d_wrk) dev_free(c, L.d_wrk);
     L.d_wrk = upload(c, wrk);
+    if (L.d_ph_ptr) dev_free(c, L.d_ph_ptr);
+    L.d_ph_ptr = upload(c, L.ph_ptr);
+    L.sweep_grid = 0;
+    if (!c.d_bar) {
+      c.d_bar = static_cast<unsigned long long*>(dev_alloc(c, 2 * sizeof(unsigned long long)));
+      CAV_HIP(hipMemsetAsync(c.d_bar, 0, 2 * sizeof(unsigned long long), s));
+    }
     L.sp_lds = size_t(mn + ((mn + 15) / 16) * 64) * sizeof(double);
     prepare_mult_smoother(L.sp_lds);
   }

@@ -301,13 +301,11 @@ __device__ __forceinline__ void mx_gemv_pairs(const T* __restrict__ arena, int64
 // LDS. (3) x[dofs] += alpha delta, partials summed in block order.
 // Patches of one phase share no unknown and no coupling, so nothing races.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_mult_exp(const MultRec* __restrict__ recs, const double* __restrict__ a64,
-                                                 const float* __restrict__ a32, const int32_t* __restrict__ slot_dof,
-                                                 StencilCoef sc, const int32_t* __restrict__ erow,
-                                                 const int32_t* __restrict__ ecol, const double* __restrict__ eval,
-                                                 const double* __restrict__ b, double* __restrict__ x, double alpha) {
-  extern __shared__ double smem[];
-  const MultRec rec = recs[blockIdx.x];
+__device__ __forceinline__ void mx_patch(const MultRec& rec, double* smem, const double* __restrict__ a64,
+                                         const float* __restrict__ a32, const int32_t* __restrict__ slot_dof,
+                                         StencilCoef sc, const int32_t* __restrict__ erow,
+                                         const int32_t* __restrict__ ecol, const double* __restrict__ eval,
+                                         const double* __restrict__ b, double* __restrict__ x, double alpha) {
   const int n = rec.n;
   const int nb = (n + MX_CB - 1) / MX_CB;
   double* rp = smem;             // n
@@ -336,6 +334,22 @@ __global__ __launch_bounds__(NT) void k_mult_exp(const MultRec* __restrict__ rec
     for (int cb = 0; cb < nb; ++cb) s += pp[int64_t(cb) * n + i];
     x[dofs[i]] += alpha * s;
   }
+}
+
+// One phase of the multiplicative sweep over explicit patches, one workgroup
+// per patch (NT threads). (1) All residual rows of the patch into LDS.
+// (2) delta = K_p^{-1} r as (row, 16-column block) items, block partials in
+// LDS. (3) x[dofs] += alpha delta, partials summed in block order.
+// Patches of one phase share no unknown and no coupling, so nothing races.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_mult_exp(const MultRec* __restrict__ recs, const double* __restrict__ a64,
+                                                 const float* __restrict__ a32, const int32_t* __restrict__ slot_dof,
+                                                 StencilCoef sc, const int32_t* __restrict__ erow,
+                                                 const int32_t* __restrict__ ecol, const double* __restrict__ eval,
+                                                 const double* __restrict__ b, double* __restrict__ x, double alpha) {
+  extern __shared__ double smem[];
+  const MultRec rec = recs[blockIdx.x];
+  mx_patch<NT>(rec, smem, a64, a32, slot_dof, sc, erow, ecol, eval, b, x, alpha);
 }
 
 // Split form of one phase, for patches too large for one workgroup to stream
@@ -399,12 +413,10 @@ __global__ __launch_bounds__(256) void k_mult_gemv(const int2* __restrict__ item
 // One colour phase of the shared standard patches: cells with
 // (i + 3 j) mod 8 == colour and no E_E entries solve their 5x5 patch from the
 // current residual and update x.
-__global__ __launch_bounds__(TPB) void k_mult_std(int N, int colour, const uint8_t* __restrict__ flag,
-                                                  const double* __restrict__ Minv, StencilCoef sc,
-                                                  const double* __restrict__ b, double* __restrict__ x, double alpha) {
+__device__ __forceinline__ void std_cell(int N, int colour, int64_t t, const uint8_t* __restrict__ flag,
+                                         const double* __restrict__ Minv, StencilCoef sc,
+                                         const double* __restrict__ b, double* __restrict__ x, double alpha) {
   const int per = N / 8;  // cells of one colour per column j
-  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
-  if (t >= int64_t(N) * per) return;
   const int j = int(t / per), k = int(t % per);
   const int i = ((colour - 3 * j) % 8 + 8) % 8 + 8 * k;
   const int64_t n2 = int64_t(N) * N;
@@ -426,6 +438,101 @@ __global__ __launch_bounds__(TPB) void k_mult_std(int N, int colour, const uint8
   for (int q = 0; q < 5; ++q) x[d[q]] += alpha * dl[q];
 }
 
+__global__ __launch_bounds__(TPB) void k_mult_std(int N, int colour, const uint8_t* __restrict__ flag,
+                                                  const double* __restrict__ Minv, StencilCoef sc,
+                                                  const double* __restrict__ b, double* __restrict__ x, double alpha) {
+  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  if (t >= int64_t(N) * (N / 8)) return;
+  std_cell(N, colour, t, flag, Minv, sc, b, x, alpha);
+}
+
+// Grid-wide barrier of the persistent sweep: every workgroup adds one to a
+// device counter and waits until it reaches `target` (gridDim.x per barrier
+// so far). Release and acquire fences at device scope make the phase's x
+// updates visible to every workgroup. The wait is bounded: after `limit`
+// polls, or once another workgroup has reported a timeout, the workgroup
+// records the failure and returns false, and the kernel stops.
+__device__ bool grid_sync(unsigned long long* __restrict__ bar, unsigned long long target, int* __restrict__ err,
+                          unsigned limit) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(bar, 1ull);
+    int good = 1;
+    unsigned spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > limit) {
+        atomicExch(err, 1);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+struct SweepArgs {
+  const MultRec* recs;
+  const int32_t* ph_ptr;   // device copy of the phase offsets
+  int nph;
+  const double* a64;
+  const float* a32;
+  const int32_t* slot_dof;
+  StencilCoef sc;
+  const int32_t* erow;
+  const int32_t* ecol;
+  const double* eval;
+  const uint8_t* flag;
+  const double* std_inv;
+  const double* b;
+  double* x;
+  double alpha;
+  unsigned long long* bar;
+  int* err;
+  unsigned limit;
+};
+
+// The whole multiplicative sweep of one level in one cooperative launch: the
+// explicit colour phases (patches of a phase spread over the workgroups, each
+// processed exactly as by k_mult_exp), then the 8 colours of shared standard
+// patches (each cell exactly as by k_mult_std), a grid barrier after each
+// phase. Same arithmetic, same order of phases: bit-identical to the
+// per-phase launches.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_mult_sweep(SweepArgs a) {
+  extern __shared__ double smem[];
+  const unsigned long long G = gridDim.x;
+  unsigned long long target = 0;
+  for (int ph = 0; ph < a.nph; ++ph) {
+    const int p1 = a.ph_ptr[ph + 1];
+    for (int p = a.ph_ptr[ph] + int(blockIdx.x); p < p1; p += int(G)) {
+      const MultRec rec = a.recs[p];
+      mx_patch<NT>(rec, smem, a.a64, a.a32, a.slot_dof, a.sc, a.erow, a.ecol, a.eval, a.b, a.x, a.alpha);
+      __syncthreads();
+    }
+    target += G;
+    if (!grid_sync(a.bar, target, a.err, a.limit)) return;
+  }
+  const int N = a.sc.N;
+  const int64_t total = int64_t(N) * (N / 8);
+  for (int col = 0; col < 8; ++col) {
+    for (int64_t t = int64_t(blockIdx.x) * NT + threadIdx.x; t < total; t += int64_t(G) * NT)
+      std_cell(N, col, t, a.flag, a.std_inv, a.sc, a.b, a.x, a.alpha);
+    if (col == 7) break;
+    target += G;
+    if (!grid_sync(a.bar, target, a.err, a.limit)) return;
+  }
+}
+
+__global__ void k_zero_bar(unsigned long long* bar, int words) {
+  if (blockIdx.x == 0 && int(threadIdx.x) < words) bar[threadIdx.x] = 0ull;
+}
+
 template <typename T>
 void launch_patch_apply(Ctx& c, const std::vector<PatchRec>& recs_h, const PatchRec* recs_d, const T* arena,
                         const Level& L, const double* r, double bytes, hipStream_t s) {
@@ -438,10 +545,53 @@ void launch_patch_apply(Ctx& c, const std::vector<PatchRec>& recs_h, const Patch
 }
 }  // namespace
 
+// Workgroups of the cooperative sweep of level L (0: not possible).
+static int sweep_grid(const Level& L) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_mult_sweep<1024>), 1024,
+                                                   L.mx_lds) != hipSuccess)
+    return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess)
+    return 0;
+  const int cap = per_cu * cus;
+  int want = int((int64_t(L.N) * (L.N / 8) + 1023) / 1024);
+  for (size_t ph = 0; ph + 1 < L.ph_ptr.size(); ++ph) want = std::max(want, L.ph_ptr[ph + 1] - L.ph_ptr[ph]);
+  return std::min(cap, std::max(want, 1));
+}
+
+void launch_clear_sweep_flags(Ctx& c, hipStream_t s) {
+  if (c.d_bar) k_zero_bar<<<1, 64, 0, s>>>(c.d_bar, 2);
+}
+
+bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t s) {
+  const int nph = int(L.ph_ptr.size()) - 1;
+  if (nph <= 0 || !L.d_ph_ptr || !c.d_bar) return false;
+  if (L.sweep_grid == 0) L.sweep_grid = sweep_grid(L);
+  if (L.sweep_grid <= 0) return false;
+  SweepArgs a{L.d_mrec, L.d_ph_ptr, nph, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full, L.d_ecol, L.d_eval,
+              L.d_cellflag, L.d_std_inv, b, x, level_alpha(c, L), c.d_bar, reinterpret_cast<int*>(c.d_bar + 1),
+              1u << 21};
+  k_zero_bar<<<1, 64, 0, s>>>(c.d_bar, 1);
+  double bytes = 0.0;
+  for (double v : L.ph_bytes) bytes += v;
+  timing_begin(c, s);
+  void* args[] = {&a};
+  CAV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_mult_sweep<1024>), dim3(L.sweep_grid),
+                                     dim3(1024), args, L.mx_lds, s));
+  timing_end(c, s, bytes, nph);
+  return true;
+}
+
 void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s) {
   const int64_t n2 = int64_t(L.N) * L.N, n = 3 * n2;
   if (zero_guess) launch_fill(x, 0.0, n, s);
   const int nph = int(L.ph_ptr.size()) - 1;
+  if (L.persistent && !c.capturing && launch_mult_sweep(c, L, b, x, s)) {
+    launch_pressure_mean_remove(x, L.N, L.d_part, s);
+    return;
+  }
   if (nph > 0) {
     // one bracket around the run of phase launches of this sweep
     timing_begin(c, s);
@@ -491,7 +641,8 @@ void prepare_mult_smoother(size_t lds) {
   static size_t set_to = 64 * 1024;
   if (lds <= set_to) return;
   for (const void* f : {reinterpret_cast<const void*>(k_mult_exp<256>), reinterpret_cast<const void*>(k_mult_exp<512>),
-                        reinterpret_cast<const void*>(k_mult_exp<1024>), reinterpret_cast<const void*>(k_mult_gemv)})
+                        reinterpret_cast<const void*>(k_mult_exp<1024>), reinterpret_cast<const void*>(k_mult_gemv),
+                        reinterpret_cast<const void*>(k_mult_sweep<1024>)})
     CAV_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   set_to = lds;
 }

@@ -138,10 +138,14 @@ def test_autotune_keeps_results(dev, cav, tmp_path):
     z0 = g.vcycle(b).cpu().numpy()
     x0, i0 = g.fgmres_solve(b, 1e-10, 150)
     g.autotune(reps=1)
-    for table in (np.full(4 * s.n_levels, 256, np.int32), np.full(4 * s.n_levels, 512, np.int32),
-                  np.full(4 * s.n_levels, 0, np.int32), None):
+    def tab(nt, sweep):
+        t = np.full((s.n_levels, 5), nt, np.int32)
+        t[:, 4] = sweep
+        return t
+
+    for table in (tab(256, 0), tab(512, 0), tab(0, 0), tab(1024, 1), None):
         if table is not None:
-            g._check(g._L.cav_set_tuning(g._h, table.ctypes.data_as(cav._binding.C.POINTER(cav._binding.C.c_int32))))
+            g.set_tuning(table)
         np.testing.assert_array_equal(g.vcycle(b).cpu().numpy(), z0)
         x, inf = g.fgmres_solve(b, 1e-10, 150)
         assert inf["iterations"] == i0["iterations"]
@@ -151,7 +155,7 @@ def test_autotune_keeps_results(dev, cav, tmp_path):
     t1 = g.autotune(reps=1, cache=cache)
     t2 = g.autotune(reps=1, cache=cache)
     np.testing.assert_array_equal(t1, t2)
-    assert set(np.unique(t1)) <= {0, 256, 512, 1024}
+    assert set(np.unique(t1[:, :4])) <= {0, 256, 512, 1024} and set(np.unique(t1[:, 4])) <= {0, 1}
     g.close()
 
 
