@@ -185,6 +185,31 @@ def learned_leg(g_eval, b_eval, train_pairs: int, steps: int):
             "enabled": enabled}
 
 
+def two_grid_leg():
+    """Two-grid spectrum of the coloured multiplicative CAV cycle on the paper's
+    N=16 membrane (Section 5.1) for the kappa_s of Table 1, assembled on the
+    GPU; the paper's printed values are given beside them as context."""
+    from paper_2608_14310_amd import Solver, spectral
+    import workloads
+    paper = {}
+    with open(os.path.join(ROOT, "tests", "golden", "paper_table1.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, r, lo, hi = line.split()
+                paper[float(k)] = (float(r), float(lo), float(hi))
+    rows = []
+    for k in sorted(paper):
+        s = workloads.paper_membrane(16, kappa=k)
+        s.n_levels = 2
+        g = Solver(0)
+        g.setup(s, precision="fp64", alpha=1.0, smoother="multiplicative")
+        sp = spectral.spectrum(spectral.iteration_matrix(g), 16)
+        g.close()
+        rows.append({"kappa_s": k, **{q: round(v, 4) for q, v in sp.items()},
+                     "paper": dict(zip(("rho_T", "min_abs_lambda", "max_abs_lambda"), paper[k]))})
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +223,7 @@ def main():
                     help="phase-kernel table of the timed steps: 1024 threads per patch everywhere (none), "
                          "autotuned, or the split form everywhere; the autotuned table is reported after them")
     ap.add_argument("--no-other-precision", action="store_true")
+    ap.add_argument("--no-two-grid", action="store_true", help="skip the Table 1 two-grid spectra")
     ap.add_argument("--batch", type=int, default=64, help="systems in the batched leg (0: skip)")
     ap.add_argument("--learned-pairs", type=int, default=600, help="training pairs of the learned leg (0: skip)")
     ap.add_argument("--learned-steps", type=int, default=600)
@@ -341,6 +367,8 @@ def main():
     if a.learned_pairs > 0:
         setup("mixed")
         line["learned"] = learned_leg(g, b, a.learned_pairs, a.learned_steps)
+    if not a.no_two_grid:
+        line["two_grid_table1"] = two_grid_leg()
     if a.verbose:
         line["level_stats"] = last["stats"]
         line["factor_stats"] = last["fst"]

@@ -227,6 +227,13 @@ cav_status cav_batch_solve(cav_ctx* ctxs, int32_t n_sys, const double* const* b,
 cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table);
 cav_status cav_set_tuning(cav_ctx ctx, const int32_t* table);
 
+/* ---- error propagation (Section 5.1, Table 1 diagnostic) ----
+ * T_q = X_q - V(K_E X_q) for the k columns X_q (device, column-major, each a
+ * finest-level vector): the V-cycle's iteration matrix applied to X. With a
+ * two-level hierarchy and X = I this assembles the two-grid iteration matrix
+ * whose spectrum Table 1 reports. Enqueued on the context's stream. */
+cav_status cav_error_propagation(cav_ctx ctx, int32_t k, const double* X, double* T);
+
 /* ---- per-level access for parity checks ----
  * op: 0 y = K_l x; 1 y = R_l x (level l -> l-1, y on level l-1);
  *     2 y = P_l x (level l-1 -> l, x on level l-1, y on level l);

@@ -125,6 +125,7 @@ _SIGS = {
     "cav_learned_pairs": ([_P, C.c_int32, _P, C.c_int32, _P, _P], C.c_int),
     "cav_autotune": ([_P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "cav_set_level_smoother": ([_P, C.c_int, C.c_int, C.c_double], C.c_int),
+    "cav_error_propagation": ([_P, C.c_int32, _P, _P], C.c_int),
     "cav_set_tuning": ([_P, C.POINTER(C.c_int32)], C.c_int),
     "cav_fgmres_solve_graph": ([_P, _P, _P, C.POINTER(FgmresOpts), C.POINTER(SolveInfo)], C.c_int),
     "cav_batch_solve": ([C.POINTER(_P), C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(FgmresOpts),
@@ -405,6 +406,13 @@ class Solver:
 
     def set_smoother(self, kind: str = "additive", alpha: float = 0.7, pre: int = 1, post: int = 1) -> None:
         self._check(self._L.cav_set_smoother(self._h, SMOOTHER[kind], float(alpha), int(pre), int(post)))
+
+    def error_propagation(self, X):
+        """T = X - V(K X) column by column; X float64 device (k, n), rows are vectors."""
+        self._sync_stream()
+        T = self._torch.empty_like(X)
+        self._check(self._L.cav_error_propagation(self._h, int(X.shape[0]), _dev_ptr(X), _dev_ptr(T)))
+        return T
 
     def set_level_smoother(self, level: int, kind: Optional[str], alpha: float = 0.7) -> None:
         """Override the smoother of one smoothed level (None restores the context's)."""

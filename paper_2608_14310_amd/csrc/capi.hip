@@ -1311,4 +1311,28 @@ cav_status cav_set_level_smoother(cav_ctx ctx, int level, int kind, double alpha
   API_END
 }
 
+cav_status cav_error_propagation(cav_ctx ctx, int32_t k, const double* X, double* T) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require(k >= 0, CAV_ERR_INVALID_ARG, "k must be non-negative");
+  if (k == 0) return CAV_OK;
+  require(X && T && X != T, CAV_ERR_INVALID_ARG, "X and T must be distinct device pointers");
+  ensure_workspace(c, 1);
+  Level& F = c.lv.back();
+  hipStream_t s = c.stream;
+  const int64_t n = 3 * int64_t(F.N) * F.N;
+  for (int32_t q = 0; q < k; ++q) {
+    const double* xq = X + int64_t(q) * n;
+    double* tq = T + int64_t(q) * n;
+    launch_apply_op(F, xq, c.d_w, nullptr, s);   // w = K x
+    vcycle_top(c, c.d_w, tq);                    // t = V(K x)
+    k_axpby<<<nblocks(n), TPB, 0, s>>>(tq, 1.0, xq, -1.0, n);  // t = x - V(K x)
+  }
+  CAV_HIP(hipGetLastError());
+  return CAV_OK;
+  API_END
+}
+
 }  // extern "C"
