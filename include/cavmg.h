@@ -66,6 +66,8 @@ enum { CAV_FAMILY_CAV = 0, CAV_FAMILY_VANKA = 1 };         /* patch families (Se
  * in 8 phases by (i + 3j) mod 8); patches in one phase are independent, so
  * the sweep equals the sequential sweep in that order. */
 enum { CAV_SMOOTHER_ADDITIVE = 0, CAV_SMOOTHER_MULTIPLICATIVE = 1 };
+/* Order of the two groups of phases in every multiplicative sweep. */
+enum { CAV_ORDER_EXPLICIT_FIRST = 0, CAV_ORDER_STANDARD_FIRST = 1 };
 enum { CAV_PREC_FP64 = 0, CAV_PREC_MIXED = 1 };            /* factor storage policy */
 
 typedef struct {
@@ -158,6 +160,13 @@ cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold,
  * coloured order, w <- w + alpha R_p^T K_p^{-1} R_p (b - K w). Both remove the
  * mean pressure after the sweep. pre/post = sweeps per V-cycle leg (1, 1). */
 cav_status cav_set_smoother(cav_ctx ctx, int kind, double alpha, int pre, int post);
+/* Multiplicative phase order (reading: the paper visits patches
+ * lexicographically, Section 3.3): CAV_ORDER_EXPLICIT_FIRST (default) runs the
+ * colour phases of patches with E_E entries, then the 8 colours of shared
+ * standard patches; CAV_ORDER_STANDARD_FIRST the reverse. Both are valid
+ * multiplicative orders; they differ in robustness at extreme stiffness
+ * (Table 1 diagnostic). Cleared only by another call. */
+cav_status cav_set_phase_order(cav_ctx ctx, int order);
 /* Per-level override (kind -1 restores the context's choice): level in
  * 1 .. n_levels-1 uses `kind` with damping `alpha`, e.g. the multiplicative
  * sweep on the finest level and the additive one below it. Cleared by
@@ -249,7 +258,8 @@ int32_t cav_level_N(cav_ctx ctx, int level);
 cav_status cav_export_patches(cav_ctx ctx, int level, int64_t* offsets, int32_t* dofs, int64_t* total);
 /* Multiplicative phases of level l: phases of explicit patches as seed-cell
  * indices (ptr has n_phases+1 offsets into cells). NULL arrays query the sizes.
- * The 8 phases of shared standard patches follow them in every sweep. */
+ * The 8 phases of shared standard patches follow them in every sweep
+ * (precede them under CAV_ORDER_STANDARD_FIRST). */
 cav_status cav_export_phases(cav_ctx ctx, int level, int32_t* ptr, int32_t* cells, int32_t* n_phases,
                              int32_t* n_cells);
 

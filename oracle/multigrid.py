@@ -40,8 +40,9 @@ class Level:
 
 class Hierarchy:
     def __init__(self, system, family: str = "cav", alpha: float = 1.0, smoother: str = "additive",
-                 box=(4, 2)):
+                 box=(4, 2), order: str = "explicit_first"):
         self.system = system
+        self.order = order
         self.alpha = alpha
         self.smoother = smoother
         self.family = family
@@ -101,7 +102,8 @@ class Hierarchy:
             if lev.phases is None:
                 # structural stencil pattern (unit coefficients so no coupling vanishes when mu = 0)
                 stencil = mac.reduced_operator(lev.N, 1.0, 1.0, 1.0, sp.csr_matrix((2 * lev.N ** 2, 2 * lev.N ** 2)))
-                lev.phases = pmod.coloured_order(lev.N, lev.patches, lev.pattern, stencil)
+                lev.phases = pmod.coloured_order(lev.N, lev.patches, lev.pattern, stencil,
+                                                 standard_first=self.order == "standard_first")
                 order = [c for ph in lev.phases for c in ph]
                 lev.msolvers = smoothers.PatchSolvers(lev.K, [lev.patches[c] for c in order], lev.standard[order])
             return smoothers.multiplicative_sweep(lev.K, lev.msolvers, b, w, lev.N)

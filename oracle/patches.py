@@ -106,7 +106,7 @@ def box_patches(N: int, b: int, o: int):
     return patches, inject
 
 
-def coloured_order(N: int, patches, ee_pattern, stencil_K) -> list:
+def coloured_order(N: int, patches, ee_pattern, stencil_K, standard_first: bool = False) -> list:
     """A multiplicative ordering whose consecutive runs ("phases") hold
     mutually independent patches: no shared unknown and no structural K_E
     entry between them, so applying a phase simultaneously equals applying its
@@ -118,7 +118,8 @@ def coloured_order(N: int, patches, ee_pattern, stencil_K) -> list:
     taking the smallest colour not used by a conflicting, already coloured
     patch; then the E_E-free standard patches in 8 phases by colour
     (i + 3 j) mod 8, which separates every pair of standard patches coupled
-    by the MAC stencils. Returns a list of phases, each a sorted list of cells.
+    by the MAC stencils (with standard_first, those 8 phases come first).
+    Returns a list of phases, each a sorted list of cells.
     """
     n2 = N * N
     P = ee_pattern.tocsr()
@@ -149,14 +150,14 @@ def coloured_order(N: int, patches, ee_pattern, stencil_K) -> list:
         while k in used:
             k += 1
         colour[c] = k
-    phases = []
+    exp_phases = []
     if colour:
         for k in range(max(colour.values()) + 1):
-            phases.append(sorted(c for c in expl if colour[c] == k))
+            exp_phases.append(sorted(c for c in expl if colour[c] == k))
     ex = set(expl)
     rest = [c for c in range(n2) if c not in ex]
-    for k in range(8):
-        phases.append([c for c in rest if ((c // N) + 3 * (c % N)) % 8 == k])
+    std_phases = [[c for c in rest if ((c // N) + 3 * (c % N)) % 8 == k] for k in range(8)]
+    phases = std_phases + exp_phases if standard_first else exp_phases + std_phases
     return [p for p in phases if p]
 
 

@@ -126,6 +126,7 @@ _SIGS = {
     "cav_autotune": ([_P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "cav_set_level_smoother": ([_P, C.c_int, C.c_int, C.c_double], C.c_int),
     "cav_error_propagation": ([_P, C.c_int32, _P, _P], C.c_int),
+    "cav_set_phase_order": ([_P, C.c_int], C.c_int),
     "cav_set_tuning": ([_P, C.POINTER(C.c_int32)], C.c_int),
     "cav_fgmres_solve_graph": ([_P, _P, _P, C.POINTER(FgmresOpts), C.POINTER(SolveInfo)], C.c_int),
     "cav_batch_solve": ([C.POINTER(_P), C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(FgmresOpts),
@@ -413,6 +414,10 @@ class Solver:
         T = self._torch.empty_like(X)
         self._check(self._L.cav_error_propagation(self._h, int(X.shape[0]), _dev_ptr(X), _dev_ptr(T)))
         return T
+
+    def set_phase_order(self, order: str = "explicit_first") -> None:
+        """Multiplicative sweep order: 'explicit_first' (default) or 'standard_first'."""
+        self._check(self._L.cav_set_phase_order(self._h, {"explicit_first": 0, "standard_first": 1}[order]))
 
     def set_level_smoother(self, level: int, kind: Optional[str], alpha: float = 0.7) -> None:
         """Override the smoother of one smoothed level (None restores the context's)."""

@@ -1335,4 +1335,16 @@ cav_status cav_error_propagation(cav_ctx ctx, int32_t k, const double* X, double
   API_END
 }
 
+cav_status cav_set_phase_order(cav_ctx ctx, int order) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  if (order != CAV_ORDER_EXPLICIT_FIRST && order != CAV_ORDER_STANDARD_FIRST) {
+    c.err = "order must be CAV_ORDER_EXPLICIT_FIRST or CAV_ORDER_STANDARD_FIRST";
+    return CAV_ERR_INVALID_ARG;
+  }
+  c.std_first = order == CAV_ORDER_STANDARD_FIRST;
+  ++c.generation;
+  return CAV_OK;
+}
+
 }  // extern "C"

@@ -172,6 +172,7 @@ struct Ctx {
   int family = CAV_FAMILY_CAV;
   double alpha = 0.7;
   int pre = 1, post = 1;
+  bool std_first = false;  // multiplicative sweep: shared-patch colours before the explicit phases
   int smoother = CAV_SMOOTHER_ADDITIVE;
   // coarsest bordered inverse (nb x nb, column-major) and its column permutation
   int nc = 0;                              // bordered size

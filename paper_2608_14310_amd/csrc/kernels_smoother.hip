@@ -495,6 +495,7 @@ struct SweepArgs {
   unsigned long long* bar;
   int* err;
   unsigned limit;
+  int std_first;           // shared-patch colours before the explicit phases
 };
 
 // The whole multiplicative sweep of one level in one cooperative launch: the
@@ -508,24 +509,32 @@ __global__ __launch_bounds__(NT) void k_mult_sweep(SweepArgs a) {
   extern __shared__ double smem[];
   const unsigned long long G = gridDim.x;
   unsigned long long target = 0;
-  for (int ph = 0; ph < a.nph; ++ph) {
-    const int p1 = a.ph_ptr[ph + 1];
-    for (int p = a.ph_ptr[ph] + int(blockIdx.x); p < p1; p += int(G)) {
-      const MultRec rec = a.recs[p];
-      mx_patch<NT>(rec, smem, a.a64, a.a32, a.slot_dof, a.sc, a.erow, a.ecol, a.eval, a.b, a.x, a.alpha);
-      __syncthreads();
-    }
-    target += G;
-    if (!grid_sync(a.bar, target, a.err, a.limit)) return;
-  }
   const int N = a.sc.N;
   const int64_t total = int64_t(N) * (N / 8);
-  for (int col = 0; col < 8; ++col) {
-    for (int64_t t = int64_t(blockIdx.x) * NT + threadIdx.x; t < total; t += int64_t(G) * NT)
-      std_cell(N, col, t, a.flag, a.std_inv, a.sc, a.b, a.x, a.alpha);
-    if (col == 7) break;
-    target += G;
-    if (!grid_sync(a.bar, target, a.err, a.limit)) return;
+  // stage 0: explicit colour phases; stage 1: shared-patch colours (order swapped by std_first)
+  for (int stage = 0; stage < 2; ++stage) {
+    const bool explicit_stage = (stage == 0) != (a.std_first != 0);
+    if (explicit_stage) {
+      for (int ph = 0; ph < a.nph; ++ph) {
+        const int p1 = a.ph_ptr[ph + 1];
+        for (int p = a.ph_ptr[ph] + int(blockIdx.x); p < p1; p += int(G)) {
+          const MultRec rec = a.recs[p];
+          mx_patch<NT>(rec, smem, a.a64, a.a32, a.slot_dof, a.sc, a.erow, a.ecol, a.eval, a.b, a.x, a.alpha);
+          __syncthreads();
+        }
+        if (stage == 1 && ph == a.nph - 1) break;
+        target += G;
+        if (!grid_sync(a.bar, target, a.err, a.limit)) return;
+      }
+    } else {
+      for (int col = 0; col < 8; ++col) {
+        for (int64_t t = int64_t(blockIdx.x) * NT + threadIdx.x; t < total; t += int64_t(G) * NT)
+          std_cell(N, col, t, a.flag, a.std_inv, a.sc, a.b, a.x, a.alpha);
+        if (stage == 1 && col == 7) break;
+        target += G;
+        if (!grid_sync(a.bar, target, a.err, a.limit)) return;
+      }
+    }
   }
 }
 
@@ -572,7 +581,7 @@ bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t
   if (L.sweep_grid <= 0) return false;
   SweepArgs a{L.d_mrec, L.d_ph_ptr, nph, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full, L.d_ecol, L.d_eval,
               L.d_cellflag, L.d_std_inv, b, x, level_alpha(c, L), c.d_bar, reinterpret_cast<int*>(c.d_bar + 1),
-              1u << 21};
+              1u << 21, c.std_first ? 1 : 0};
   k_zero_bar<<<1, 64, 0, s>>>(c.d_bar, 1);
   double bytes = 0.0;
   for (double v : L.ph_bytes) bytes += v;
@@ -592,6 +601,13 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
     launch_pressure_mean_remove(x, L.N, L.d_part, s);
     return;
   }
+  const int64_t per_colour = n2 / 8;
+  auto standard = [&]() {
+    for (int col = 0; col < 8; ++col)
+      k_mult_std<<<nblocks(per_colour), TPB, 0, s>>>(L.N, col, L.d_cellflag, L.d_std_inv, L.sc, b, x,
+                                                     level_alpha(c, L));
+  };
+  if (c.std_first) standard();
   if (nph > 0) {
     // one bracket around the run of phase launches of this sweep
     timing_begin(c, s);
@@ -602,10 +618,7 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
     }
     timing_end(c, s, bytes, nph);
   }
-  const int64_t per_colour = n2 / 8;
-  for (int col = 0; col < 8; ++col)
-    k_mult_std<<<nblocks(per_colour), TPB, 0, s>>>(L.N, col, L.d_cellflag, L.d_std_inv, L.sc, b, x,
-                                                   level_alpha(c, L));
+  if (!c.std_first) standard();
   launch_pressure_mean_remove(x, L.N, L.d_part, s);
 }
 

@@ -209,6 +209,28 @@ def test_multiplicative_fgmres_matches_oracle(mpair):
     assert np.linalg.norm(xg - res.x) / np.linalg.norm(res.x) < 1e-8
 
 
+@pytest.mark.parametrize("name", sorted(MCASES))
+def test_standard_first_order_matches_oracle(name):
+    s = MCASES[name]()
+    print(f"[gpu parity] standard-first order {name}", flush=True)
+    H = multigrid.Hierarchy(s, alpha=1.0, smoother="coloured", order="standard_first")
+    g = _solver()
+    stats, fst = g.setup(s, alpha=1.0, smoother="multiplicative")
+    g.set_phase_order("standard_first")
+    tol = _tol(fst)
+    rng = np.random.default_rng(12)
+    l = len(H.levels) - 1
+    b = rng.standard_normal(H.levels[l].K.shape[0])
+    assert _rel(_np(g.level_apply(l, 3, _t(b))), H.smooth(l, b, np.zeros_like(b))) < tol
+    assert _rel(_np(g.vcycle(_t(s.b))), H.vcycle(s.b)) < 4 * tol
+    K = H.levels[-1].K
+    res = krylov.fgmres(lambda x: K @ x, H.vcycle, s.b, 1e-10, 150)
+    x, info = g.fgmres_solve(_t(s.b), rtol=1e-10, max_it=150)
+    g.close()
+    assert info["converged"] == 1 and info["iterations"] == res.iterations
+    assert np.linalg.norm(_np(x) - res.x) / np.linalg.norm(res.x) < 1e-8
+
+
 # ------------------------------------------------------- mixed precision ---
 
 @pytest.mark.parametrize("smoother,alpha,name", [("additive", 0.7, "target32"), ("multiplicative", 1.0, "beam64")])
