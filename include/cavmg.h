@@ -58,7 +58,7 @@ typedef enum {
 enum { CAV_LAW_TARGET = 0, CAV_LAW_MEMBRANE = 1, CAV_LAW_BEAM_CLOSED = 2, CAV_LAW_BEAM_OPEN = 3,
        CAV_LAW_CSR = 4 };
 
-enum { CAV_FAMILY_CAV = 0, CAV_FAMILY_VANKA = 1 };         /* patch families (Section 3) */
+enum { CAV_FAMILY_CAV = 0, CAV_FAMILY_VANKA = 1, CAV_FAMILY_BOX = 2 };  /* patch families (Section 3) */
 /* Smoothers: ADDITIVE is the weighted additive sweep of Appendix A
  * (Eq. additive_cav_saddle, Theta = 1/cnt); MULTIPLICATIVE is the
  * multiplicative Schwarz sweep of Section 3.3 in a coloured order (patches
@@ -153,6 +153,17 @@ const char* cav_last_error(cav_ctx ctx);
  *   coarsest bordered matrix [[K_0, e], [e^T, 0]] (e = constant pressure). */
 cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* grid, const cav_structure_desc* st);
 cav_status cav_build_cav_patches(cav_ctx ctx, int family, cav_level_stats* out);
+/* B(b,o) box family (Section 3.1): one patch per b x b block of cells (block
+ * lower-left cells (i, j) with i, j multiples of b), the union of the Vanka
+ * patches of the block expanded by o cells in every direction; smoothing
+ * injects each box's correction only into the unknowns of its unexpanded
+ * block (restricted injection, Section 3.3), so adjacent blocks both write
+ * their shared faces. Both smoothers apply (additive: sum of injected
+ * corrections; multiplicative: boxes in greedy colour phases on the K_E
+ * conflict graph, block order). Every smoothed grid must be a multiple of b.
+ * Patch exports list the box dofs at its block's lower-left cell and nothing
+ * elsewhere; out[l].n_patches is the number of boxes. */
+cav_status cav_build_box_patches(cav_ctx ctx, int b, int o, cav_level_stats* out);
 cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold, cav_factor_stats* out);
 /* Smoother choice (kind = CAV_SMOOTHER_*). Additive (Appendix A,
  * Eq. additive_cav_saddle): w <- w + alpha sum_p R_p^T Theta_p K_p^{-1} R_p (b - K w),
@@ -270,6 +281,7 @@ cav_status cav_export_phases(cav_ctx ctx, int level, int32_t* ptr, int32_t* cell
  * host handle whose levels can be exported like a context's. */
 typedef struct cav_analysis_s* cav_analysis;
 cav_status cav_analyze(const cav_grid_desc* grid, const cav_structure_desc* st, int family, cav_analysis* out);
+cav_status cav_analyze_box(const cav_grid_desc* grid, const cav_structure_desc* st, int b, int o, cav_analysis* out);
 cav_status cav_analysis_destroy(cav_analysis a);
 cav_status cav_analysis_export_ee(cav_analysis a, int level, int64_t* rowptr, int32_t* col, double* val,
                                   int64_t* nnz);

@@ -36,6 +36,7 @@ class Level:
     theta: Optional[list] = None
     phases: Optional[list] = None
     msolvers: Optional[smoothers.PatchSolvers] = None
+    minject: Optional[list] = None
 
 
 class Hierarchy:
@@ -98,6 +99,15 @@ class Hierarchy:
             return smoothers.seed_restricted_sweep(lev.K, lev.solvers, lev.theta, b, w, self.alpha, lev.N)
         if self.smoother == "multiplicative":
             return smoothers.multiplicative_sweep(lev.K, lev.solvers, b, w, lev.N, lev.inject)
+        if self.smoother == "coloured" and self.family == "box":
+            if lev.phases is None:
+                stencil = mac.reduced_operator(lev.N, 1.0, 1.0, 1.0, sp.csr_matrix((2 * lev.N ** 2, 2 * lev.N ** 2)))
+                lev.phases = pmod.coloured_box_order(lev.N, lev.patches, lev.pattern, stencil)
+                order = [k for ph in lev.phases for k in ph]
+                lev.minject = [lev.inject[k] for k in order]
+                lev.msolvers = smoothers.PatchSolvers(lev.K, [lev.patches[k] for k in order], lev.standard[order],
+                                                      lev.minject)
+            return smoothers.multiplicative_sweep(lev.K, lev.msolvers, b, w, lev.N, lev.minject)
         if self.smoother == "coloured":
             if lev.phases is None:
                 # structural stencil pattern (unit coefficients so no coupling vanishes when mu = 0)

@@ -161,6 +161,35 @@ def coloured_order(N: int, patches, ee_pattern, stencil_K, standard_first: bool 
     return [p for p in phases if p]
 
 
+def coloured_box_order(N: int, patches, ee_pattern, stencil_K) -> list:
+    """A multiplicative ordering of the B(b,o) box family (reading: the paper
+    visits boxes in lexicographic order of their blocks; this is the parallel
+    form): boxes greedily coloured in order of decreasing size, ties by block
+    order, on the same conflict graph as `coloured_order` (a shared unknown or a
+    structural K_E entry between two boxes). Returns phases of box indices."""
+    n2 = N * N
+    P = ee_pattern.tocsr()
+    Kb = (abs(stencil_K) + sp.identity(stencil_K.shape[0])).tocsr()
+    Kb.data[:] = 1.0
+    Kb = (Kb + sp.bmat([[(P + P.T), None], [None, sp.csr_matrix((n2, n2))]]) != 0).tocsr()
+    owners = {}
+    for k, p in enumerate(patches):
+        for d in p.tolist():
+            owners.setdefault(d, []).append(k)
+    colour = {}
+    for k in sorted(range(len(patches)), key=lambda k: (-len(patches[k]), k)):
+        used = set()
+        for d in np.unique(Kb[patches[k]].indices).tolist():
+            for q in owners.get(d, ()):
+                if q in colour:
+                    used.add(colour[q])
+        c = 0
+        while c in used:
+            c += 1
+        colour[k] = c
+    return [sorted(k for k in colour if colour[k] == c) for c in range(max(colour.values()) + 1)]
+
+
 def patch_counts(n: int, patches) -> np.ndarray:
     """cnt(d): the number of patches that contain unknown d."""
     cnt = np.zeros(n, dtype=np.int64)

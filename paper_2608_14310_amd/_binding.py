@@ -27,7 +27,7 @@ class CAVError(RuntimeError):
 
 
 CAV_LAW = {"target": 0, "membrane": 1, "beam_closed": 2, "beam_open": 3, "csr": 4}
-FAMILY = {"cav": 0, "vanka": 1}
+FAMILY = {"cav": 0, "vanka": 1, "box": 2}
 SMOOTHER = {"additive": 0, "multiplicative": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
 WARN_NOT_CONVERGED, WARN_FLOOR_LIMITED = 100, 101
@@ -127,6 +127,8 @@ _SIGS = {
     "cav_set_level_smoother": ([_P, C.c_int, C.c_int, C.c_double], C.c_int),
     "cav_error_propagation": ([_P, C.c_int32, _P, _P], C.c_int),
     "cav_set_phase_order": ([_P, C.c_int], C.c_int),
+    "cav_build_box_patches": ([_P, C.c_int, C.c_int, C.POINTER(LevelStats)], C.c_int),
+    "cav_analyze_box": ([C.POINTER(GridDesc), C.POINTER(StructureDesc), C.c_int, C.c_int, C.POINTER(_P)], C.c_int),
     "cav_set_tuning": ([_P, C.POINTER(C.c_int32)], C.c_int),
     "cav_fgmres_solve_graph": ([_P, _P, _P, C.POINTER(FgmresOpts), C.POINTER(SolveInfo)], C.c_int),
     "cav_batch_solve": ([C.POINTER(_P), C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(FgmresOpts),
@@ -188,12 +190,15 @@ class Analysis:
     """Host-only setup of one system (no device): E_E per level, patch sets,
     multiplicative phases and partition-of-unity weights, from libcavmg."""
 
-    def __init__(self, system, family: str = "cav"):
+    def __init__(self, system, family: str = "cav", box=(4, 2)):
         self._L = lib()
         g = GridDesc(system.N, system.n_levels, system.rho, system.mu, system.dt)
         d, keep = describe_structure(system)
         h = C.c_void_p()
-        st = self._L.cav_analyze(C.byref(g), C.byref(d), FAMILY[family], C.byref(h))
+        if family == "box":
+            st = self._L.cav_analyze_box(C.byref(g), C.byref(d), int(box[0]), int(box[1]), C.byref(h))
+        else:
+            st = self._L.cav_analyze(C.byref(g), C.byref(d), FAMILY[family], C.byref(h))
         del keep
         if st != 0:
             raise CAVError(st, "cav_analyze failed")
@@ -393,10 +398,14 @@ class Solver:
         del keep
         self.N, self.n_levels = system.N, system.n_levels
 
-    def build_cav_patches(self, family: str = "cav") -> List[Dict]:
+    def build_cav_patches(self, family: str = "cav", box=(4, 2)) -> List[Dict]:
+        """Patch family per smoothed level: 'cav', 'vanka', or 'box' (B(b,o), box = (b, o))."""
         self._sync_stream()
         out = (LevelStats * self.n_levels)()
-        self._check(self._L.cav_build_cav_patches(self._h, FAMILY[family], out))
+        if family == "box":
+            self._check(self._L.cav_build_box_patches(self._h, int(box[0]), int(box[1]), out))
+        else:
+            self._check(self._L.cav_build_cav_patches(self._h, FAMILY[family], out))
         return [{f: getattr(o, f) for f, _ in LevelStats._fields_} for o in out]
 
     def factor_patches(self, precision: str = "fp64", cond_threshold: float = 1e6) -> Dict:
@@ -424,9 +433,10 @@ class Solver:
         self._check(self._L.cav_set_level_smoother(self._h, int(level), -1 if kind is None else SMOOTHER[kind],
                                                    float(alpha)))
 
-    def setup(self, system, family="cav", precision="fp64", cond_threshold=1e6, alpha=0.7, smoother="additive"):
+    def setup(self, system, family="cav", precision="fp64", cond_threshold=1e6, alpha=0.7, smoother="additive",
+              box=(4, 2)):
         self.build_operator(system)
-        stats = self.build_cav_patches(family)
+        stats = self.build_cav_patches(family, box)
         fstats = self.factor_patches(precision, cond_threshold)
         self.set_smoother(smoother, alpha)
         return stats, fstats

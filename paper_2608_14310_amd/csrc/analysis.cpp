@@ -15,11 +15,17 @@ struct cav_analysis_s {
 
 extern "C" {
 
-cav_status cav_analyze(const cav_grid_desc* g, const cav_structure_desc* st, int family, cav_analysis* out) {
+static cav_status analyze(const cav_grid_desc* g, const cav_structure_desc* st, int family, int box_b, int box_o,
+                          cav_analysis* out) {
   if (!g || !out) return CAV_ERR_INVALID_ARG;
   const int N = g->N, L = g->n_levels;
   if (!(N >= 4 && (N & (N - 1)) == 0) || L < 1 || L > 30 || (N >> (L - 1)) < 4) return CAV_ERR_INVALID_ARG;
-  if (family != CAV_FAMILY_CAV && family != CAV_FAMILY_VANKA) return CAV_ERR_INVALID_ARG;
+  if (family != CAV_FAMILY_CAV && family != CAV_FAMILY_VANKA && family != CAV_FAMILY_BOX) return CAV_ERR_INVALID_ARG;
+  if (family == CAV_FAMILY_BOX) {
+    if (box_b < 1 || box_o < 0) return CAV_ERR_INVALID_ARG;
+    for (int l = 1; l < L; ++l)
+      if ((N >> (L - 1 - l)) % box_b != 0) return CAV_ERR_INVALID_ARG;
+  }
   cav::Structure S;
   std::string err;
   const cav_status ss = cav::make_structure(st, S, err);
@@ -32,7 +38,12 @@ cav_status cav_analyze(const cav_grid_desc* g, const cav_structure_desc* st, int
     for (int l = 0; l < L; ++l) a->lv[l].N = N >> (L - 1 - l);
     cav::assemble_ee_finest(N, S, a->lv[L - 1].ee);
     for (int l = L - 1; l >= 1; --l) cav::galerkin_coarsen(a->lv[l - 1].N, a->lv[l].ee, a->lv[l - 1].ee);
-    for (int l = 1; l < L; ++l) cav::build_patches(a->lv[l].N, a->lv[l].ee, family, a->lv[l]);
+    for (int l = 1; l < L; ++l) {
+      if (family == CAV_FAMILY_BOX)
+        cav::build_box_patches(a->lv[l].N, a->lv[l].ee, box_b, box_o, a->lv[l]);
+      else
+        cav::build_patches(a->lv[l].N, a->lv[l].ee, family, a->lv[l]);
+    }
     a->patched = true;
   } catch (const std::bad_alloc&) {
     delete a;
@@ -40,6 +51,15 @@ cav_status cav_analyze(const cav_grid_desc* g, const cav_structure_desc* st, int
   }
   *out = a;
   return CAV_OK;
+}
+
+cav_status cav_analyze(const cav_grid_desc* g, const cav_structure_desc* st, int family, cav_analysis* out) {
+  if (family == CAV_FAMILY_BOX) return CAV_ERR_INVALID_ARG;
+  return analyze(g, st, family, 0, 0, out);
+}
+
+cav_status cav_analyze_box(const cav_grid_desc* g, const cav_structure_desc* st, int b, int o, cav_analysis* out) {
+  return analyze(g, st, CAV_FAMILY_BOX, b, o, out);
 }
 
 cav_status cav_analysis_destroy(cav_analysis a) {

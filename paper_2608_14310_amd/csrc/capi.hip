@@ -67,7 +67,7 @@ void free_level(Ctx& c, Level& L) {
                   (void*)L.d_cellflag, (void*)L.d_slot_dof, (void*)L.d_delta, (void*)L.d_t_dof, (void*)L.d_t_inv,
                   (void*)L.d_t_ptr, (void*)L.d_t_slot, (void*)L.d_std_inv, (void*)L.d_rec64, (void*)L.d_rec32,
                   (void*)L.d_f64, (void*)L.d_f32, (void*)L.d_b, (void*)L.d_x, (void*)L.d_r, (void*)L.d_z,
-                  (void*)L.d_part, (void*)L.d_mrec, (void*)L.d_wrk, (void*)L.d_ph_ptr})
+                  (void*)L.d_part, (void*)L.d_mrec, (void*)L.d_wrk, (void*)L.d_ph_ptr, (void*)L.d_slot_mask})
     dev_free(c, p);
   L = Level();
 }
@@ -76,7 +76,7 @@ void free_patches(Ctx& c, Level& L) {
   for (void** p : {(void**)&L.d_cellflag, (void**)&L.d_slot_dof, (void**)&L.d_delta, (void**)&L.d_t_dof,
                    (void**)&L.d_t_inv, (void**)&L.d_t_ptr, (void**)&L.d_t_slot, (void**)&L.d_std_inv,
                    (void**)&L.d_rec64, (void**)&L.d_rec32, (void**)&L.d_f64, (void**)&L.d_f32,
-                   (void**)&L.d_mrec, (void**)&L.d_wrk, (void**)&L.d_ph_ptr}) {
+                   (void**)&L.d_mrec, (void**)&L.d_wrk, (void**)&L.d_ph_ptr, (void**)&L.d_slot_mask}) {
     dev_free(c, *p);
     *p = nullptr;
   }
@@ -550,20 +550,29 @@ cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* g, const cav_str
   API_END
 }
 
-cav_status cav_build_cav_patches(cav_ctx ctx, int family, cav_level_stats* out) {
-  if (!ctx) return CAV_ERR_INVALID_ARG;
+static cav_status build_family(cav_ctx ctx, int family, int box_b, int box_o, cav_level_stats* out) {
   Ctx& c = ctx->c;
   ++c.generation;
   API_BEGIN
   require(c.built, CAV_ERR_NOT_BUILT, "cav_build_operator has not succeeded");
-  require(family == CAV_FAMILY_CAV || family == CAV_FAMILY_VANKA, CAV_ERR_INVALID_ARG, "unknown patch family");
+  require(family == CAV_FAMILY_CAV || family == CAV_FAMILY_VANKA || family == CAV_FAMILY_BOX, CAV_ERR_INVALID_ARG,
+          "unknown patch family");
+  if (family == CAV_FAMILY_BOX) {
+    require(box_b >= 1 && box_o >= 0, CAV_ERR_INVALID_ARG, "box size must be >= 1 and overlap >= 0");
+    for (int l = 1; l < c.n_levels; ++l)
+      require(c.lv[l].N % box_b == 0, CAV_ERR_INVALID_ARG, "every smoothed grid must be a multiple of the box size");
+  }
   CAV_HIP(hipSetDevice(c.device));
   c.family = family;
   c.patched = c.factored = false;
   for (int l = 1; l < c.n_levels; ++l) {
     Level& L = c.lv[l];
     free_patches(c, L);
-    build_patches(L.N, L.ee, family, L);
+    if (family == CAV_FAMILY_BOX)
+      build_box_patches(L.N, L.ee, box_b, box_o, L);
+    else
+      build_patches(L.N, L.ee, family, L);
+    if (!L.slot_mask_h.empty()) L.d_slot_mask = upload(c, L.slot_mask_h);
     L.d_cellflag = upload(c, L.cellflag);
     L.d_slot_dof = upload(c, L.slot_dof_h);
     L.d_delta = static_cast<double*>(dev_alloc(c, size_t(std::max<int64_t>(L.n_slots, 1)) * sizeof(double)));
@@ -583,6 +592,20 @@ cav_status cav_build_cav_patches(cav_ctx ctx, int family, cav_level_stats* out) 
   c.patched = true;
   return CAV_OK;
   API_END
+}
+
+cav_status cav_build_cav_patches(cav_ctx ctx, int family, cav_level_stats* out) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  if (family == CAV_FAMILY_BOX) {
+    ctx->c.err = "use cav_build_box_patches for the box family";
+    return CAV_ERR_INVALID_ARG;
+  }
+  return build_family(ctx, family, 0, 0, out);
+}
+
+cav_status cav_build_box_patches(cav_ctx ctx, int b, int o, cav_level_stats* out) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  return build_family(ctx, CAV_FAMILY_BOX, b, o, out);
 }
 
 cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold, cav_factor_stats* out) {

@@ -67,6 +67,8 @@ struct Level {
   std::vector<int32_t> exp_cells;          // explicit patch -> seed cell
   std::vector<int64_t> exp_off;            // explicit patch -> slot offset (n_exp + 1)
   std::vector<int32_t> slot_dof_h;
+  std::vector<uint8_t> slot_mask_h;        // box family: 1 where the slot's unknown is injected
+  uint8_t* d_slot_mask = nullptr;           // nullptr for the CAV / Vanka families
   uint8_t* d_cellflag = nullptr;
   int32_t n_exp = 0;
   int64_t n_slots = 0;
@@ -247,6 +249,7 @@ cav_status make_structure(const cav_structure_desc* st, Structure& out, std::str
 void assemble_ee_finest(int N, const Structure& s, HostCSR& ee);
 void galerkin_coarsen(int Nc, const HostCSR& fine, HostCSR& coarse);
 void build_patches(int N, const HostCSR& ee, int family, Level& L);
+void build_box_patches(int N, const HostCSR& ee, int b, int o, Level& L);
 
 // ---- device launches (kernels_*.hip) ----
 void launch_apply_op(const Level& L, const double* x, double* y, const double* b, hipStream_t s);

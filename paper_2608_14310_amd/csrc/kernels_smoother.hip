@@ -305,7 +305,8 @@ __device__ __forceinline__ void mx_patch(const MultRec& rec, double* smem, const
                                          const float* __restrict__ a32, const int32_t* __restrict__ slot_dof,
                                          StencilCoef sc, const int32_t* __restrict__ erow,
                                          const int32_t* __restrict__ ecol, const double* __restrict__ eval,
-                                         const double* __restrict__ b, double* __restrict__ x, double alpha) {
+                                         const double* __restrict__ b, double* __restrict__ x, double alpha,
+                                         const uint8_t* __restrict__ smask) {
   const int n = rec.n;
   const int nb = (n + MX_CB - 1) / MX_CB;
   double* rp = smem;             // n
@@ -332,7 +333,7 @@ __device__ __forceinline__ void mx_patch(const MultRec& rec, double* smem, const
   for (int i = threadIdx.x; i < n; i += NT) {
     double s = 0.0;
     for (int cb = 0; cb < nb; ++cb) s += pp[int64_t(cb) * n + i];
-    x[dofs[i]] += alpha * s;
+    if (!smask || smask[rec.slot + i]) x[dofs[i]] += alpha * s;
   }
 }
 
@@ -346,10 +347,11 @@ __global__ __launch_bounds__(NT) void k_mult_exp(const MultRec* __restrict__ rec
                                                  const float* __restrict__ a32, const int32_t* __restrict__ slot_dof,
                                                  StencilCoef sc, const int32_t* __restrict__ erow,
                                                  const int32_t* __restrict__ ecol, const double* __restrict__ eval,
-                                                 const double* __restrict__ b, double* __restrict__ x, double alpha) {
+                                                 const double* __restrict__ b, double* __restrict__ x, double alpha,
+                                                 const uint8_t* __restrict__ smask) {
   extern __shared__ double smem[];
   const MultRec rec = recs[blockIdx.x];
-  mx_patch<NT>(rec, smem, a64, a32, slot_dof, sc, erow, ecol, eval, b, x, alpha);
+  mx_patch<NT>(rec, smem, a64, a32, slot_dof, sc, erow, ecol, eval, b, x, alpha, smask);
 }
 
 // Split form of one phase, for patches too large for one workgroup to stream
@@ -379,7 +381,7 @@ __global__ __launch_bounds__(256) void k_mult_gemv(const int2* __restrict__ item
                                                    const double* __restrict__ a64, const float* __restrict__ a32,
                                                    const int32_t* __restrict__ slot_dof,
                                                    const double* __restrict__ rbuf, double* __restrict__ x,
-                                                   double alpha) {
+                                                   double alpha, const uint8_t* __restrict__ smask) {
   extern __shared__ double smem[];
   const int2 it = items[blockIdx.x];
   const MultRec rec = recs[it.x];
@@ -406,7 +408,7 @@ __global__ __launch_bounds__(256) void k_mult_gemv(const int2* __restrict__ item
   for (int ii = threadIdx.x; ii < nr; ii += 256) {
     double s = 0.0;
     for (int cb = 0; cb < nb; ++cb) s += pp[cb * MX_RB + ii];
-    x[dofs[r0 + ii]] += alpha * s;
+    if (!smask || smask[rec.slot + r0 + ii]) x[dofs[r0 + ii]] += alpha * s;
   }
 }
 
@@ -496,6 +498,7 @@ struct SweepArgs {
   int* err;
   unsigned limit;
   int std_first;           // shared-patch colours before the explicit phases
+  const uint8_t* smask;    // injection mask of the box family, or nullptr
 };
 
 // The whole multiplicative sweep of one level in one cooperative launch: the
@@ -519,7 +522,8 @@ __global__ __launch_bounds__(NT) void k_mult_sweep(SweepArgs a) {
         const int p1 = a.ph_ptr[ph + 1];
         for (int p = a.ph_ptr[ph] + int(blockIdx.x); p < p1; p += int(G)) {
           const MultRec rec = a.recs[p];
-          mx_patch<NT>(rec, smem, a.a64, a.a32, a.slot_dof, a.sc, a.erow, a.ecol, a.eval, a.b, a.x, a.alpha);
+          mx_patch<NT>(rec, smem, a.a64, a.a32, a.slot_dof, a.sc, a.erow, a.ecol, a.eval, a.b, a.x, a.alpha,
+                       a.smask);
           __syncthreads();
         }
         if (stage == 1 && ph == a.nph - 1) break;
@@ -581,7 +585,7 @@ bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t
   if (L.sweep_grid <= 0) return false;
   SweepArgs a{L.d_mrec, L.d_ph_ptr, nph, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full, L.d_ecol, L.d_eval,
               L.d_cellflag, L.d_std_inv, b, x, level_alpha(c, L), c.d_bar, reinterpret_cast<int*>(c.d_bar + 1),
-              1u << 21, c.std_first ? 1 : 0};
+              1u << 21, c.std_first ? 1 : 0, L.d_slot_mask};
   k_zero_bar<<<1, 64, 0, s>>>(c.d_bar, 1);
   double bytes = 0.0;
   for (double v : L.ph_bytes) bytes += v;
@@ -630,21 +634,21 @@ void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double
     k_mult_res<<<unsigned(nw), 256, 0, s>>>(L.d_wrk + w0, L.d_mrec, L.d_slot_dof, L.sc, L.d_erow_full, L.d_ecol,
                                             L.d_eval, b, x, L.d_delta);
     k_mult_gemv<<<unsigned(nw), 256, L.sp_lds, s>>>(L.d_wrk + w0, L.d_mrec, L.d_f64, L.d_f32, L.d_slot_dof,
-                                                    L.d_delta, x, level_alpha(c, L));
+                                                    L.d_delta, x, level_alpha(c, L), L.d_slot_mask);
     return;
   }
   switch (nt) {
     case 256:
       k_mult_exp<256><<<g, 256, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full,
-                                               L.d_ecol, L.d_eval, b, x, level_alpha(c, L));
+                                               L.d_ecol, L.d_eval, b, x, level_alpha(c, L), L.d_slot_mask);
       break;
     case 512:
       k_mult_exp<512><<<g, 512, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full,
-                                               L.d_ecol, L.d_eval, b, x, level_alpha(c, L));
+                                               L.d_ecol, L.d_eval, b, x, level_alpha(c, L), L.d_slot_mask);
       break;
     default:
       k_mult_exp<1024><<<g, 1024, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full,
-                                                 L.d_ecol, L.d_eval, b, x, level_alpha(c, L));
+                                                 L.d_ecol, L.d_eval, b, x, level_alpha(c, L), L.d_slot_mask);
   }
 }
 

@@ -439,7 +439,101 @@ void visit_reach(int N, const HostCSR& ee, const Level& L, int e, V&& visit) {
 // CAV patch family (Eq. cav_patch_set) on one level, plus the arrays the
 // smoother needs: cell flags, explicit patch slots and the unknown -> slot
 // transpose with 1/cnt weights (Appendix A's partition of unity).
+// B(b,o) box family (Section 3.1): one patch per b x b block, the union of the
+// Vanka patches of the block expanded by o cells on every side; restricted
+// injection keeps the unknowns of the unexpanded block (Section 3.3). Every
+// cell is flagged as handled by an explicit patch (no shared standard
+// patches); the touched lists hold the injected slots only, with weight 1.
+void build_box_patches(int N, const HostCSR& ee, int b, int o, Level& L) {
+  const int64_t n2 = int64_t(N) * N, n = 3 * n2;
+  auto vanka = [&](int i, int j, int32_t* d) {
+    d[0] = int32_t(int64_t(i) * N + j);
+    d[1] = int32_t(int64_t(pmod(i + 1, N)) * N + j);
+    d[2] = int32_t(n2 + int64_t(i) * N + j);
+    d[3] = int32_t(n2 + int64_t(i) * N + pmod(j + 1, N));
+    d[4] = int32_t(2 * n2 + int64_t(i) * N + j);
+  };
+  L.cellflag.assign(n2, 1);
+  L.patch_off.assign(n2 + 1, 0);
+  L.patch_dofs.clear();
+  L.exp_cells.clear();
+  L.exp_off.assign(1, 0);
+  L.slot_dof_h.clear();
+  L.slot_mask_h.clear();
+  std::vector<int32_t> mark(n, -1), core(n, -1);
+  std::vector<int32_t> dofs;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const int32_t cell = int32_t(int64_t(i) * N + j);
+      int64_t len = 0;
+      if (i % b == 0 && j % b == 0) {
+        dofs.clear();
+        int32_t d[5];
+        for (int r = -o; r < b + o; ++r)
+          for (int t = -o; t < b + o; ++t) {
+            vanka(pmod(i + r, N), pmod(j + t, N), d);
+            for (int k = 0; k < 5; ++k)
+              if (mark[d[k]] != cell) {
+                mark[d[k]] = cell;
+                dofs.push_back(d[k]);
+              }
+          }
+        for (int r = 0; r < b; ++r)
+          for (int t = 0; t < b; ++t) {
+            vanka(pmod(i + r, N), pmod(j + t, N), d);
+            for (int k = 0; k < 5; ++k) core[d[k]] = cell;
+          }
+        std::sort(dofs.begin(), dofs.end());
+        L.patch_dofs.insert(L.patch_dofs.end(), dofs.begin(), dofs.end());
+        L.exp_cells.push_back(cell);
+        L.exp_off.push_back(L.exp_off.back() + int64_t(dofs.size()));
+        for (int32_t q : dofs) {
+          L.slot_dof_h.push_back(q);
+          L.slot_mask_h.push_back(core[q] == cell ? 1 : 0);
+        }
+        len = int64_t(dofs.size());
+      }
+      L.patch_off[cell + 1] = L.patch_off[cell] + len;
+    }
+  L.n_exp = int32_t(L.exp_cells.size());
+  L.n_slots = int64_t(L.slot_dof_h.size());
+  // unknown -> injected slots (ascending), weight 1
+  std::vector<int32_t> nsl(n + 1, 0);
+  for (int64_t sl = 0; sl < L.n_slots; ++sl)
+    if (L.slot_mask_h[sl]) nsl[L.slot_dof_h[sl] + 1]++;
+  L.t_dof_h.clear();
+  L.t_ptr_h.assign(1, 0);
+  std::vector<int64_t> start(n, -1);
+  for (int64_t d = 0; d < n; ++d)
+    if (nsl[d + 1] > 0) {
+      start[d] = L.t_ptr_h.back();
+      L.t_dof_h.push_back(int32_t(d));
+      L.t_ptr_h.push_back(L.t_ptr_h.back() + nsl[d + 1]);
+    }
+  L.t_slot_h.assign(size_t(L.t_ptr_h.back()), 0);
+  for (int64_t sl = 0; sl < L.n_slots; ++sl)
+    if (L.slot_mask_h[sl]) L.t_slot_h[start[L.slot_dof_h[sl]]++] = int32_t(sl);
+  L.t_inv_h.assign(L.t_dof_h.size(), 1.0);
+  L.n_touched = int32_t(L.t_dof_h.size());
+  colour_explicit(N, ee, L);
+  cav_level_stats& st = L.stats;
+  st.N = N;
+  st.n_patches = L.n_exp;
+  st.n_explicit = L.n_exp;
+  st.max_np = 0;
+  st.sum_np2 = 0;
+  for (int32_t e = 0; e < L.n_exp; ++e) {
+    const int64_t np = L.exp_off[e + 1] - L.exp_off[e];
+    st.max_np = std::max<int32_t>(st.max_np, int32_t(np));
+    st.sum_np2 += np * np;
+  }
+  st.avg_np = L.n_exp ? double(L.patch_dofs.size()) / double(L.n_exp) : 0.0;
+  st.ee_nnz = ee.nnz();
+  st.n_touched = L.n_touched;
+}
+
 void build_patches(int N, const HostCSR& ee, int family, Level& L) {
+  L.slot_mask_h.clear();
   const int64_t n2 = int64_t(N) * N, nv = 2 * n2, n = 3 * n2;
   auto U_of = [&](int i, int j, int32_t* U) {
     U[0] = int32_t(int64_t(i) * N + j);

@@ -94,3 +94,56 @@ def test_vanka_family_is_standard():
         got = a.patches(l)
         assert all(len(p) == 5 for p in got)
         assert all(np.array_equal(g, pmod.vanka_patch(N, c // N, c % N)) for c, g in enumerate(got))
+
+
+@pytest.mark.parametrize("name", ["membrane32", "beam64"])
+def test_box_family_matches_oracle(name):
+    """B(4,2) boxes (Section 3.1): dof sets exactly, colour phases equal to the
+    oracle's coloured box order (seed cells = block lower-left cells), and the
+    injected-slot lists: each unknown receives exactly the boxes whose
+    unexpanded block holds it, with weight 1."""
+    from paper_2608_14310_amd._binding import Analysis
+    s = CASES[name]()
+    a = Analysis(s, "box", (4, 2))
+    EE, pat = ib.eulerian_elasticity(s)
+    ee = [None] * s.n_levels
+    ee[-1] = (EE, pat)
+    for l in range(s.n_levels - 1, 0, -1):
+        ee[l - 1] = hierarchy.galerkin(ee[l][0], ee[l][1], s.N >> (s.n_levels - l))
+    for l in range(1, s.n_levels):
+        N = s.N >> (s.n_levels - 1 - l)
+        ps, inj = pmod.box_patches(N, 4, 2)
+        seeds = [I * N + J for I in range(0, N, 4) for J in range(0, N, 4)]
+        got = a.patches(l)
+        for c in range(N * N):
+            if c in seeds:
+                assert np.array_equal(got[c], ps[seeds.index(c)]), (name, l, c)
+            else:
+                assert len(got[c]) == 0
+        stencil = mac.reduced_operator(N, 1.0, 1.0, 1.0, sp.csr_matrix((2 * N * N, 2 * N * N)))
+        want = [[seeds[k] for k in ph] for ph in pmod.coloured_box_order(N, ps, ee[l][1], stencil)]
+        assert a.phases(l) == want, (name, l)
+        dofs, inv = a.weights(l)
+        cnt = np.zeros(3 * N * N, dtype=int)
+        for p, m in zip(ps, inj):
+            cnt[p[m]] += 1
+        assert np.array_equal(dofs, np.nonzero(cnt)[0]) and np.all(inv == 1.0)
+        assert np.all(cnt > 0)                      # the blocks cover every unknown
+    a.close()
+
+
+def test_box_oracle_sweeps_are_consistent():
+    """The oracle's coloured box sweep equals its lexicographic box sweep in the
+    coloured order (same patches, same injection), and phases are independent:
+    applying a phase's boxes in reverse order gives the same result."""
+    from oracle import smoothers
+    s = CASES["membrane32"]()
+    H = multigrid.Hierarchy(s, family="box", alpha=1.0, smoother="coloured")
+    l = s.n_levels - 1
+    lev = H.levels[l]
+    b = np.random.default_rng(4).standard_normal(lev.K.shape[0])
+    x = H.smooth(l, b, np.zeros_like(b))
+    rev = [k for ph in lev.phases for k in reversed(ph)]
+    sol = smoothers.PatchSolvers(lev.K, [lev.patches[k] for k in rev], lev.standard[rev], [lev.inject[k] for k in rev])
+    x2 = smoothers.multiplicative_sweep(lev.K, sol, b, np.zeros_like(b), lev.N, [lev.inject[k] for k in rev])
+    assert np.abs(x - x2).max() <= 1e-12 * np.abs(x).max()
