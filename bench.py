@@ -214,6 +214,52 @@ def two_grid_leg():
     return rows
 
 
+def box_comparison_leg():
+    """CAV against B(b,o) box relaxation on the paper's membrane (Section 5.1):
+    two-grid spectral radii of Fig. 2 (N = 32, coarse 16^2) assembled on the
+    GPU, and FGMRES iteration counts with V-cycles down to 8^2 at N = 16, 32,
+    64 (seeded random right-hand sides; the paper uses the physical first-step
+    right-hand side). The paper's values are given beside ours as context."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2608_14310_amd import Solver, spectral
+    fig2, counts = [], {}
+    with open(os.path.join(ROOT, "tests", "golden", "paper_box_comparison.txt")) as f:
+        for line in f:
+            t = line.split()
+            if not t or t[0].startswith("#"):
+                continue
+            if t[0] == "fig2":
+                fig2.append((t[1], int(t[2]), int(t[3]), float(t[4]), float(t[5])))
+            else:
+                counts[int(t[1])] = (int(t[2]), int(t[3]))
+    out = {"fig2": [], "fgmres": []}
+    for fam, b, o, mu, paper in fig2:
+        s = workloads.paper_membrane(32, kappa=1e4, mu=mu)
+        s.n_levels = 2
+        g = Solver(0)
+        family = "cav" if fam == "CAV" else ("vanka" if (b, o) == (1, 0) else "box")
+        g.setup(s, family=family, precision="fp64", alpha=1.0, smoother="multiplicative", box=(b, o))
+        sp = spectral.spectrum(spectral.iteration_matrix(g), 32)
+        g.close()
+        out["fig2"].append({"patches": "CAV" if fam == "CAV" else f"B({b},{o})", "mu": mu,
+                            "rho_T": round(sp["rho_T"], 3), "paper_rho_T": paper})
+    for N, (p_cav, p_box) in sorted(counts.items()):
+        s = workloads.paper_membrane(N, kappa=1e4, mu=1e-2)
+        s.n_levels = workloads.levels_to(N, 8)
+        row = {"N": N, "paper_cav": p_cav, "paper_box42": p_box}
+        for fam in ("cav", "box"):
+            g = Solver(0)
+            g.setup(s, family=fam, precision="fp64", alpha=1.0, smoother="multiplicative", box=(4, 2))
+            _, inf = g.fgmres_solve(torch.from_numpy(s.b).to(torch.device("cuda", 0)), 1e-10, 150)
+            g.close()
+            row["cav" if fam == "cav" else "box42"] = inf["iterations"]
+        out["fgmres"].append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,6 +419,7 @@ def main():
         line["learned"] = learned_leg(g, b, a.learned_pairs, a.learned_steps)
     if not a.no_two_grid:
         line["two_grid_table1"] = two_grid_leg()
+        line["box_comparison"] = box_comparison_leg()
     if a.verbose:
         line["level_stats"] = last["stats"]
         line["factor_stats"] = last["fst"]
