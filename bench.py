@@ -260,6 +260,23 @@ def box_comparison_leg():
     return out
 
 
+def summarize_counters(path: str):
+    """Per kernel and counter of a rocprofv3 counter-collection CSV: the number
+    of dispatches and the mean value per dispatch (no GPU needed)."""
+    import csv
+    tot, cnt = {}, {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            k = r["Kernel_Name"].replace("cav::(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+            key = (k, r["Counter_Name"])
+            tot[key] = tot.get(key, 0.0) + float(r["Counter_Value"])
+            cnt[key] = cnt.get(key, 0) + 1
+    out = {}
+    for (k, c), v in sorted(tot.items()):
+        out.setdefault(k, {})[c] = {"dispatches": cnt[(k, c)], "mean": v / cnt[(k, c)]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +290,8 @@ def main():
                     help="phase-kernel table of the timed steps: 1024 threads per patch everywhere (none), "
                          "autotuned, or the split form everywhere; the autotuned table is reported after them")
     ap.add_argument("--no-other-precision", action="store_true")
+    ap.add_argument("--no-autotune-report", action="store_true",
+                    help="skip the autotuner run reported beside the timed table")
     ap.add_argument("--no-two-grid", action="store_true", help="skip the Table 1 two-grid spectra")
     ap.add_argument("--batch", type=int, default=64, help="systems in the batched leg (0: skip)")
     ap.add_argument("--learned-pairs", type=int, default=600, help="training pairs of the learned leg (0: skip)")
@@ -280,7 +299,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, help="run only a plain copy of this many bytes")
+    ap.add_argument("--summarize-counters", default="",
+                    help="print per-kernel dispatch counts and mean values of a rocprofv3 counter CSV, then exit")
     a = ap.parse_args()
+    if a.summarize_counters:
+        print(json.dumps(summarize_counters(a.summarize_counters), indent=1))
+        return
     if a.calibrate_copy:
         copy_calibration(a.calibrate_copy)
         return
@@ -382,7 +406,7 @@ def main():
     }
     if table is not None:
         line["tuning_table"] = np.asarray(table).tolist()
-    if a.tune != "auto":
+    if a.tune != "auto" and not a.no_autotune_report:
         # the autotuner on the same hierarchy, reported beside the timed table
         setup(a.precision)
         tuned = g.autotune(reps=3)
