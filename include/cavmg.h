@@ -108,7 +108,7 @@ typedef struct {
   int32_t n_fp32;          /* explicit patches stored in FP32 (mixed policy, kappa_1 <= threshold) */
   double max_cond;         /* largest kappa_1 of an equilibrated patch matrix */
   int64_t factor_bytes;    /* bytes the smoother streams per sweep over all levels */
-  double coarse_cond_est;  /* ||B||_1 ||B^-1||_1 of the bordered coarse matrix */
+  double coarse_cond_est;  /* not estimated: always -1 */
 } cav_factor_stats;
 
 typedef struct {
@@ -149,8 +149,11 @@ const char* cav_last_error(cav_ctx ctx);
  *   it by Gauss-Jordan elimination with partial pivoting, folds the scalings
  *   into the stored inverse and records kappa_1 (Section 3.3). Patches with no
  *   E_E entry share one 5x5 inverse per level. Under CAV_PREC_MIXED a patch
- *   whose kappa_1 <= cond_threshold is stored in FP32. Also factors the
- *   coarsest bordered matrix [[K_0, e], [e^T, 0]] (e = constant pressure). */
+ *   whose kappa_1 <= cond_threshold is stored in FP32. Also forms the
+ *   coarsest level's solution operator: the solution of the bordered system
+ *   [[K_0, e], [e^T, 0]] (e = constant pressure) on (u, p), computed as the
+ *   inverse of the quasi-definite [[A, G], [G^T, -gamma e e^T]] with the
+ *   pressure mean removed from its columns (same u, p up to a multiple of e). */
 cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* grid, const cav_structure_desc* st);
 cav_status cav_build_cav_patches(cav_ctx ctx, int family, cav_level_stats* out);
 /* B(b,o) box family (Section 3.1): one patch per b x b block of cells (block

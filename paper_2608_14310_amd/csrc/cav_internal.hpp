@@ -176,10 +176,9 @@ struct Ctx {
   int pre = 1, post = 1;
   bool std_first = false;  // multiplicative sweep: shared-patch colours before the explicit phases
   int smoother = CAV_SMOOTHER_ADDITIVE;
-  // coarsest bordered inverse (nb x nb, column-major) and its column permutation
-  int nc = 0;                              // bordered size
+  // coarsest solution operator (nc x nc, row-major, nc = 3 N0^2)
+  int nc = 0;
   double* d_cinv = nullptr;
-  int32_t* d_cperm = nullptr;
   // FGMRES workspace
   int ws_maxit = 0;
   int64_t ws_n = 0;  // vector length the workspace was sized for

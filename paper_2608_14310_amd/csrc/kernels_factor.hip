@@ -318,200 +318,231 @@ __global__ __launch_bounds__(256) void k_finalize(const PatchRec* __restrict__ w
 }
 
 // ------------------------------------------------------ coarsest level ---
-// Panel width of the coarse factorisation: 8 keeps four rows per thread in
-// registers for bordered sizes up to 4096.
-constexpr int CNB = 8;
+// The coarsest level is solved through an explicit inverse (Section 4). K_0 =
+// [[A, G], [G^T, 0]] is symmetric with A (velocity) SPD and G^T = -D, and
+// its null space is the constant pressure e. Instead of the bordered matrix
+// [[K_0, e], [e^T, 0]] we invert the quasi-definite matrix
+//   Q = [[A, G], [G^T, -gamma e e^T]],
+// whose (2,2) Schur complement -(gamma e e^T + G^T A^{-1} G) is negative
+// definite. For any right-hand side the solutions of the two systems share u
+// and differ in p by a multiple of e (G e = 0 and e^T G^T = 0), so removing
+// the pressure mean from every column of Q^{-1} gives the bordered solution
+// operator on (u, p). Every leading principal submatrix of a quasi-definite
+// matrix is nonsingular, so Q is inverted by blocked Gauss-Jordan elimination
+// that pivots only inside each QB x QB diagonal block: per block, the block
+// inverse (one workgroup, LDS), the pivot-row block R = D^{-1} W[C, :] and the
+// eliminated column block X, then one rank-QB update of the whole matrix
+//   W <- base - X R   (an FP64 tiled product, every entry written once).
+constexpr int QB = 64;       // diagonal block of the coarse elimination
+constexpr int QT = 64;       // output tile of the coarse update (QT x QT per workgroup)
 
-// Bordered matrix B = [[K_0, e], [e^T, 0]] (row-major, size nb = 3 N^2 + 1),
-// inverted by the same blocked Gauss-Jordan, spread over the device.
-__global__ void k_coarse_assemble(double* __restrict__ B, int nb, StencilCoef sc) {
+__global__ void k_coarse_assemble(double* __restrict__ W, int n, StencilCoef sc, double gamma) {
   const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (e >= int64_t(nb) * nb) return;
-  const int a = int(e / nb), b = int(e % nb);
-  const int n0 = nb - 1;
-  const int64_t n2 = int64_t(sc.N) * sc.N;
-  double v;
-  if (a < n0 && b < n0) v = stencil_entry(a, b, sc);
-  else if (a == n0 && b == n0) v = 0.0;
-  else if (a == n0) v = (b >= 2 * n2) ? 1.0 : 0.0;
-  else v = (a >= 2 * n2) ? 1.0 : 0.0;
-  B[e] = v;
+  if (e >= int64_t(n) * n) return;
+  const int a = int(e / n), b = int(e % n);
+  const int64_t p0 = 2 * int64_t(sc.N) * sc.N;
+  W[e] = stencil_entry(a, b, sc) - ((a >= p0 && b >= p0) ? gamma : 0.0);
 }
 
-__global__ void k_coarse_add_ee(double* __restrict__ B, int nb, int64_t nv, const int32_t* __restrict__ rptr,
+__global__ void k_coarse_add_ee(double* __restrict__ W, int n, int64_t nv, const int32_t* __restrict__ rptr,
                                 const int32_t* __restrict__ col, const double* __restrict__ val) {
   const int64_t a = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (a >= nv) return;
-  for (int q = rptr[a]; q < rptr[a + 1]; ++q) B[a * nb + col[q]] += val[q];
+  for (int q = rptr[a]; q < rptr[a + 1]; ++q) W[a * n + col[q]] += val[q];
 }
 
-__global__ void k_cp_load(const double* __restrict__ W, int n, int c0, int nbp, double* __restrict__ Pb) {
-  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (e >= int64_t(n) * nbp) return;
-  const int a = int(e / nbp), t = int(e % nbp);
-  Pb[int64_t(a) * CNB + t] = W[int64_t(a) * n + c0 + t];
-}
-
-// One workgroup of 1024 threads: Gauss-Jordan steps on the n x nbp panel,
-// held in registers (thread t owns rows t, t + 1024, ...). Reads the panel
-// columns of W, leaves the eliminated panel in Pb (row-major, CNB wide) and
-// the pivot rows in piv.
-// One Gauss-Jordan step on the register panel for the compile-time column T.
-template <int RPT, int T>
-__device__ __forceinline__ void cp_step(double (&P)[RPT][CNB], int c0, int nbp, int n, double* sv, int* si,
-                                        double* rowC, double* rowP, int32_t* piv, int& bad) {
-  if (T >= nbp || bad) return;  // both uniform across the workgroup
+// In-place Gauss-Jordan inverse of the m x m diagonal block W[c0.., c0..]
+// (m <= QB) with partial pivoting inside the block (first maximum on ties);
+// the column interchanges are undone at the end, so Dv (QB x QB, row-major,
+// zero outside m x m) holds the block inverse. status = 1 on a zero or
+// non-finite pivot. 1024 threads, four entries each; the interchange of rows
+// k and p is folded into step k's update (row p receives old row k).
+__global__ __launch_bounds__(1024) void k_cq_diag(const double* __restrict__ W, int n, int c0, int m,
+                                                  double* __restrict__ Dv, int32_t* __restrict__ status) {
+  __shared__ double D[QB][QB + 1];
+  __shared__ int piv[QB];
+  __shared__ double rowk[QB], colk[QB], oldk[QB];
+  __shared__ int s_p;
+  __shared__ int s_bad;
   const int tid = threadIdx.x;
-  const int c = c0 + T;
-  double bv = -1.0;
-  int bi = n;
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int a = tid + 1024 * k;
-    if (a >= c && a < n) argmax_combine(bv, bi, fabs(P[k][T]), a);
+  for (int e = tid; e < QB * QB; e += 1024) {
+    const int i = e / QB, j = e % QB;
+    D[i][j] = (i < m && j < m) ? W[int64_t(c0 + i) * n + c0 + j] : 0.0;
   }
-  block_argmax(bv, bi, sv, si);
-  if (!(bv > 0.0) || !isfinite(bv)) {
-    bad = 1;
-    return;
-  }
-  if (tid == 0) piv[c] = bi;
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int a = tid + 1024 * k;
-    if (a == c)
-#pragma unroll
-      for (int u = 0; u < CNB; ++u) rowC[u] = P[k][u];
-    if (a == bi)
-#pragma unroll
-      for (int u = 0; u < CNB; ++u) rowP[u] = P[k][u];
-  }
+  if (tid == 0) s_bad = 0;
   __syncthreads();
-  // after the interchange row c holds old row bi, scaled by its pivot
-  const double pv = rowP[T];
-  auto prow = [&](int u) { return (u == T ? 1.0 : rowP[u]) / pv; };
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int a = tid + 1024 * k;
-    if (a >= n) continue;
-    if (a == c) {
-#pragma unroll
-      for (int u = 0; u < CNB; ++u) P[k][u] = prow(u);
-      continue;
+  for (int k = 0; k < m; ++k) {
+    if (tid < 64) {  // one wavefront finds the pivot row
+      double bv = -1.0;
+      int bi = m;
+      const int i = k + tid;
+      if (i < m) {
+        bv = fabs(D[i][k]);
+        bi = i;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double v2 = __shfl_down(bv, o, 64);
+        const int i2 = __shfl_down(bi, o, 64);
+        if (v2 > bv || (v2 == bv && i2 < bi)) {
+          bv = v2;
+          bi = i2;
+        }
+      }
+      if (tid == 0) {
+        s_p = bi;
+        piv[k] = bi;
+        if (!(bv > 0.0) || !isfinite(bv)) s_bad = 1;
+      }
     }
-    if (a == bi)
-#pragma unroll
-      for (int u = 0; u < CNB; ++u) P[k][u] = rowC[u];
-    const double f = P[k][T];
-#pragma unroll
-    for (int u = 0; u < CNB; ++u)
-      if (u != T) P[k][u] -= f * prow(u);
-    P[k][T] = -f * prow(T);
+    __syncthreads();
+    if (s_bad) break;
+    const int p = s_p;
+    // pivot row (old row p) scaled; column k after the interchange; old row k
+    if (tid < QB) {
+      const int j = tid;
+      const double pv = D[p][k];
+      rowk[j] = (j == k ? 1.0 : D[p][j]) / pv;
+      colk[j] = D[j == p ? k : j][k];
+      oldk[j] = D[k][j];
+    }
+    __syncthreads();
+    for (int e = tid; e < QB * QB; e += 1024) {
+      const int i = e / QB, j = e % QB;
+      if (i >= m || j >= m) continue;
+      if (i == k) {
+        D[i][j] = rowk[j];
+      } else {
+        const double f = colk[i];
+        const double src = (i == p) ? oldk[j] : D[i][j];
+        D[i][j] = (j == k) ? -f * rowk[k] : src - f * rowk[j];
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-}
-
-template <int RPT, int... Ts>
-__device__ __forceinline__ void cp_steps(double (&P)[RPT][CNB], int c0, int nbp, int n, double* sv, int* si,
-                                         double* rowC, double* rowP, int32_t* piv, int& bad,
-                                         std::integer_sequence<int, Ts...>) {
-  (cp_step<RPT, Ts>(P, c0, nbp, n, sv, si, rowC, rowP, piv, bad), ...);
-}
-
-// One workgroup of 1024 threads: Gauss-Jordan steps on the n x nbp panel,
-// held in registers (thread t owns rows t, t + 1024, ...). Reads the panel
-// columns of W, leaves the eliminated panel in Pb (row-major, CNB wide) and
-// the pivot rows in piv.
-template <int RPT>
-__global__ __launch_bounds__(1024) void k_cp_panel(const double* __restrict__ W, double* __restrict__ Pb, int n,
-                                                   int c0, int nbp, int32_t* __restrict__ piv,
-                                                   int32_t* __restrict__ status) {
-  __shared__ double sv[16];
-  __shared__ int si[16];
-  __shared__ double rowC[CNB], rowP[CNB];
-  const int tid = threadIdx.x;
-  double P[RPT][CNB];
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int a = tid + 1024 * k;
-#pragma unroll
-    for (int u = 0; u < CNB; ++u) P[k][u] = (a < n && u < nbp) ? W[int64_t(a) * n + c0 + u] : 0.0;
-  }
-  int bad = 0;
-  cp_steps<RPT>(P, c0, nbp, n, sv, si, rowC, rowP, piv, bad, std::make_integer_sequence<int, CNB>{});
-  if (bad) {
+  if (s_bad) {
     if (tid == 0) status[0] = 1;
     return;
   }
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int a = tid + 1024 * k;
-    if (a < n)
-#pragma unroll
-      for (int u = 0; u < CNB; ++u) Pb[int64_t(a) * CNB + u] = P[k][u];
-  }
-}
-
-// Apply this panel's composite row interchange to the other columns and copy
-// the (interchanged) pivot rows into Y (nbp x n).
-__global__ void k_cp_perm(double* __restrict__ W, int n, int c0, int nbp, const int32_t* __restrict__ piv,
-                          double* __restrict__ Y) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= n || (j >= c0 && j < c0 + nbp)) return;
-  for (int t = 0; t < nbp; ++t) {
-    const int r = piv[c0 + t];
-    if (r == c0 + t) continue;
-    const double tmp = W[int64_t(c0 + t) * n + j];
-    W[int64_t(c0 + t) * n + j] = W[int64_t(r) * n + j];
-    W[int64_t(r) * n + j] = tmp;
-  }
-  for (int t = 0; t < nbp; ++t) Y[int64_t(t) * n + j] = W[int64_t(c0 + t) * n + j];
-}
-
-// W[a][j] (+)= sum_t Pb[a][t] Y[t][j]; panel columns receive the panel.
-__global__ __launch_bounds__(256) void k_cp_update(double* __restrict__ W, int n, int c0, int nbp,
-                                                   const double* __restrict__ Pb, const double* __restrict__ Y, int rows_per) {
-  __shared__ double Ps[64 * CNB];
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  const int a0 = blockIdx.y * rows_per;
-  const int a1 = min(n, a0 + rows_per);
-  for (int e = threadIdx.x; e < (a1 - a0) * CNB; e += 256) Ps[e] = Pb[int64_t(a0) * CNB + e];
+  // undo the column interchanges: one thread per row applies them in reverse
+  if (tid < m)
+    for (int k = m - 1; k >= 0; --k) {
+      const int p = piv[k];
+      if (p != k) {
+        const double tmp = D[tid][k];
+        D[tid][k] = D[tid][p];
+        D[tid][p] = tmp;
+      }
+    }
   __syncthreads();
-  if (j >= n) return;
-  if (j >= c0 && j < c0 + nbp) {
-    for (int a = a0; a < a1; ++a) W[int64_t(a) * n + j] = Ps[(a - a0) * CNB + (j - c0)];
-    return;
-  }
-  double y[CNB];
-#pragma unroll
-  for (int t = 0; t < CNB; ++t) y[t] = (t < nbp) ? Y[int64_t(t) * n + j] : 0.0;
-  for (int a = a0; a < a1; ++a) {
-    double s = 0.0;
-#pragma unroll
-    for (int t = 0; t < CNB; ++t) s += Ps[(a - a0) * CNB + t] * y[t];
-    if (a >= c0 && a < c0 + nbp)
-      W[int64_t(a) * n + j] = s;
-    else
-      W[int64_t(a) * n + j] += s;
+  for (int e = tid; e < QB * QB; e += 1024) Dv[e] = D[e / QB][e % QB];
+}
+
+// blockIdx.y == 0: R (QB x n, row-major): R[t][j] = (D^{-1} W[C, j])_t for
+// j outside C, D^{-1}[t][j - c0] inside; rows t >= m are zero.
+// blockIdx.y == 1: X (n x QB, row-major): X[a][t] = W[a][c0 + t] for rows a
+// outside C, zero for rows of C and for t >= m.
+__global__ __launch_bounds__(256) void k_cq_prep(const double* __restrict__ W, int n, int c0, int m,
+                                                 const double* __restrict__ Dv, double* __restrict__ R,
+                                                 double* __restrict__ X) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= int64_t(n) * QB) return;
+  if (blockIdx.y == 0) {
+    const int t = int(e / n), j = int(e % n);
+    double v = 0.0;
+    if (t < m) {
+      if (j >= c0 && j < c0 + m) {
+        v = Dv[t * QB + (j - c0)];
+      } else {
+        for (int s = 0; s < m; ++s) v += Dv[t * QB + s] * W[int64_t(c0 + s) * n + j];
+      }
+    }
+    R[e] = v;
+  } else {
+    const int a = int(e / QB), t = int(e % QB);
+    X[e] = (t < m && (a < c0 || a >= c0 + m)) ? W[int64_t(a) * n + c0 + t] : 0.0;
   }
 }
 
-// y[i] = sum_k W[i][k] xb[perm[k]], xb = [b; 0] (perm[k] == n0 selects the 0).
-__global__ __launch_bounds__(256) void k_coarse_gemv(const double* __restrict__ W, int nb, const int32_t* __restrict__ perm,
-                                                     const double* __restrict__ b, double* __restrict__ y) {
-  extern __shared__ double xp[];
-  const int n0 = nb - 1;
-  for (int k = threadIdx.x; k < nb; k += 256) {
-    const int q = perm[k];
-    xp[k] = (q < n0) ? b[q] : 0.0;
+// W[a][j] <- base(a, j) - sum_t X[a][t] R[t][j] on one QT x QT tile, with
+// base = R[a - c0][j] on the rows of C, 0 on the columns of C elsewhere, and
+// W[a][j] otherwise. 256 threads, 4 x 4 outputs each (rows ty + 16 p,
+// columns tx + 16 q), X and R tiles in LDS; the sum runs over t in order.
+__global__ __launch_bounds__(256) void k_cq_update(double* __restrict__ W, int n, int c0, int m,
+                                                   const double* __restrict__ X, const double* __restrict__ R) {
+  __shared__ double Xs[QT][QB + 1];
+  __shared__ double Rs[QB][QT + 1];
+  const int tid = threadIdx.x;
+  const int a0 = blockIdx.y * QT, j0 = blockIdx.x * QT;
+  for (int e = tid; e < QT * QB; e += 256) {
+    const int r = e / QB, t = e % QB;
+    Xs[r][t] = (a0 + r < n) ? X[int64_t(a0 + r) * QB + t] : 0.0;
   }
+  for (int e = tid; e < QB * QT; e += 256) {
+    const int t = e / QT, cc = e % QT;
+    Rs[t][cc] = (j0 + cc < n) ? R[int64_t(t) * n + j0 + cc] : 0.0;
+  }
+  __syncthreads();
+  const int tx = tid % 16, ty = tid / 16;
+  double acc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+  for (int t = 0; t < QB; ++t) {
+    double xv[4], rv[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) xv[p] = Xs[ty + 16 * p][t];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rv[q] = Rs[t][tx + 16 * q];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[p][q] += xv[p] * rv[q];
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int a = a0 + ty + 16 * p;
+    if (a >= n) continue;
+    const bool rowC = a >= c0 && a < c0 + m;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + tx + 16 * q;
+      if (j >= n) continue;
+      double* w = W + int64_t(a) * n + j;
+      const double base = rowC ? Rs[a - c0][tx + 16 * q] : ((j >= c0 && j < c0 + m) ? 0.0 : *w);
+      *w = base - acc[p][q];
+    }
+  }
+}
+
+// Remove the pressure mean from every column of the inverse (rows p0..n-1):
+// 64 columns per workgroup, four row strides summed in a fixed order.
+__global__ __launch_bounds__(256) void k_cq_meanfix(double* __restrict__ W, int n, int p0) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  double s = 0.0;
+  if (j < n)
+    for (int a = p0 + w; a < n; a += 4) s += W[int64_t(a) * n + j];
+  part[w][lane] = s;
+  __syncthreads();
+  const double mean = (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]) / double(n - p0);
+  if (j < n)
+    for (int a = p0 + w; a < n; a += 4) W[int64_t(a) * n + j] -= mean;
+}
+
+// y[i] = sum_k W[i][k] b[k] (one wavefront per row).
+__global__ __launch_bounds__(256) void k_coarse_gemv(const double* __restrict__ W, int n, const double* __restrict__ b,
+                                                     double* __restrict__ y) {
+  extern __shared__ double xb[];
+  for (int k = threadIdx.x; k < n; k += 256) xb[k] = b[k];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n0) return;
-  const double* Wr = W + int64_t(row) * nb;
+  if (row >= n) return;
+  const double* Wr = W + int64_t(row) * n;
   double acc = 0.0;
-  for (int k = lane; k < nb; k += 64) acc += Wr[k] * xp[k];
+  for (int k = lane; k < n; k += 64) acc += Wr[k] * xb[k];
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
   if (lane == 0) y[row] = acc;
 }
@@ -735,62 +766,48 @@ cav_status factor_coarse(Ctx& c) {
   Level& L = c.lv[0];
   const int N = L.N;
   const int64_t n2 = int64_t(N) * N;
-  const int n0 = int(3 * n2);
-  const int nb = n0 + 1;
-  if (nb > 4096) throw StatusError(CAV_ERR_INVALID_ARG, "coarsest grid too large for the dense solve (3 N0^2 + 1 > 4096)");
+  const int n = int(3 * n2);
+  if (n > 4096) throw StatusError(CAV_ERR_INVALID_ARG, "coarsest grid too large for the dense solve (3 N0^2 > 4096)");
   if (c.d_cinv) dev_free(c, c.d_cinv);
-  if (c.d_cperm) dev_free(c, c.d_cperm);
-  c.nc = nb;
-  double* W = static_cast<double*>(dev_alloc(c, size_t(nb) * nb * sizeof(double)));
-  double* Pb = static_cast<double*>(dev_alloc(c, size_t(nb) * CNB * sizeof(double)));
-  double* Y = static_cast<double*>(dev_alloc(c, size_t(nb) * CNB * sizeof(double)));
-  int32_t* piv = static_cast<int32_t*>(dev_alloc(c, size_t(nb) * sizeof(int32_t)));
+  c.d_cinv = nullptr;
+  c.nc = n;
+  // gamma n0^2 matches the Schur complement scale 4 / (h^2 diag(A_stokes))
+  const double gamma = 4.0 * L.sc.invh * L.sc.invh / (L.sc.diag * double(n2));
+  double* W = static_cast<double*>(dev_alloc(c, size_t(n) * n * sizeof(double)));
+  double* Dv = static_cast<double*>(dev_alloc(c, size_t(QB) * QB * sizeof(double)));
+  double* R = static_cast<double*>(dev_alloc(c, size_t(QB) * n * sizeof(double)));
+  double* X = static_cast<double*>(dev_alloc(c, size_t(n) * QB * sizeof(double)));
   int32_t* sts = static_cast<int32_t*>(dev_alloc(c, sizeof(int32_t)));
   CAV_HIP(hipMemsetAsync(sts, 0, sizeof(int32_t), s));
-  k_coarse_assemble<<<nblk(int64_t(nb) * nb), 256, 0, s>>>(W, nb, L.sc);
-  if (L.ee.nnz() > 0)
-    k_coarse_add_ee<<<nblk(2 * n2), 256, 0, s>>>(W, nb, 2 * n2, L.d_erow_full, L.d_ecol, L.d_eval);
-  const int rows_per = 64;
-  for (int c0 = 0; c0 < nb; c0 += CNB) {
-    const int nbp = std::min(CNB, nb - c0);
-    switch ((nb + 1023) / 1024) {
-      case 1: k_cp_panel<1><<<1, 1024, 0, s>>>(W, Pb, nb, c0, nbp, piv, sts); break;
-      case 2: k_cp_panel<2><<<1, 1024, 0, s>>>(W, Pb, nb, c0, nbp, piv, sts); break;
-      case 3: k_cp_panel<3><<<1, 1024, 0, s>>>(W, Pb, nb, c0, nbp, piv, sts); break;
-      default: k_cp_panel<4><<<1, 1024, 0, s>>>(W, Pb, nb, c0, nbp, piv, sts); break;
-    }
-    k_cp_perm<<<nblk(nb), 256, 0, s>>>(W, nb, c0, nbp, piv, Y);
-    dim3 g(nblk(nb), unsigned((nb + rows_per - 1) / rows_per));
-    k_cp_update<<<g, 256, 0, s>>>(W, nb, c0, nbp, Pb, Y, rows_per);
+  k_coarse_assemble<<<nblk(int64_t(n) * n), 256, 0, s>>>(W, n, L.sc, gamma);
+  if (L.ee.nnz() > 0) k_coarse_add_ee<<<nblk(2 * n2), 256, 0, s>>>(W, n, 2 * n2, L.d_erow_full, L.d_ecol, L.d_eval);
+  const dim3 gu(unsigned((n + QT - 1) / QT), unsigned((n + QT - 1) / QT));
+  for (int c0 = 0; c0 < n; c0 += QB) {
+    const int m = std::min(QB, n - c0);
+    k_cq_diag<<<1, 1024, 0, s>>>(W, n, c0, m, Dv, sts);
+    k_cq_prep<<<dim3(nblk(int64_t(n) * QB), 2), 256, 0, s>>>(W, n, c0, m, Dv, R, X);
+    k_cq_update<<<gu, 256, 0, s>>>(W, n, c0, m, X, R);
   }
+  k_cq_meanfix<<<nblk(n, 64), 256, 0, s>>>(W, n, int(2 * n2));
   CAV_HIP(hipGetLastError());
   int32_t sts_h = 0;
-  std::vector<int32_t> piv_h(nb);
   CAV_HIP(hipMemcpyAsync(&sts_h, sts, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  CAV_HIP(hipMemcpyAsync(piv_h.data(), piv, nb * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   CAV_HIP(hipStreamSynchronize(s));
-  dev_free(c, Pb);
-  dev_free(c, Y);
-  dev_free(c, piv);
+  dev_free(c, Dv);
+  dev_free(c, R);
+  dev_free(c, X);
   dev_free(c, sts);
   if (sts_h) {
     dev_free(c, W);
-    throw StatusError(CAV_ERR_SINGULAR_COARSE, "zero pivot in the coarsest bordered factorisation");
+    throw StatusError(CAV_ERR_SINGULAR_COARSE, "zero or non-finite pivot in the coarsest factorisation");
   }
-  // column j of the inverse is column sigma[j] of W; the GEMV reads x[sigma^-1(k)] at column k
-  std::vector<int32_t> sigma(nb), perm(nb);
-  for (int k = 0; k < nb; ++k) sigma[k] = k;
-  for (int k = nb - 1; k >= 0; --k) std::swap(sigma[k], sigma[piv_h[k]]);
-  for (int j = 0; j < nb; ++j) perm[sigma[j]] = j;
   c.d_cinv = W;
-  c.d_cperm = upload(c, perm);
-  CAV_HIP(hipStreamSynchronize(s));
   return CAV_OK;
 }
 
 void launch_coarse_solve(const Ctx& c, const double* b, double* x, hipStream_t s) {
-  const int nb = c.nc;
-  k_coarse_gemv<<<nblk(nb - 1, 4), 256, size_t(nb) * sizeof(double), s>>>(c.d_cinv, nb, c.d_cperm, b, x);
+  const int n = c.nc;
+  k_coarse_gemv<<<nblk(n, 4), 256, size_t(n) * sizeof(double), s>>>(c.d_cinv, n, b, x);
 }
 
 }  // namespace cav
