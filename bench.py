@@ -286,7 +286,7 @@ def main():
     ap.add_argument("--smoother", default="multiplicative", choices=["multiplicative", "additive"])
     ap.add_argument("--kappa-b", type=float, default=1e-2)
     ap.add_argument("--stiff-sweep", type=float, nargs="*", default=[1.0, 1e2])
-    ap.add_argument("--tune", default="none", choices=["auto", "none", "split", "sweep"],
+    ap.add_argument("--tune", default="none", choices=["auto", "none", "split", "sweep", "coop64", "coop128"],
                     help="phase-kernel table of the timed steps: 1024 threads per patch everywhere (none), "
                          "autotuned, or the split form everywhere; the autotuned table is reported after them")
     ap.add_argument("--no-other-precision", action="store_true")
@@ -359,6 +359,10 @@ def main():
     elif a.tune == "sweep":
         table = np.full((s.n_levels, 5), 1024, dtype=np.int32)
         table[:, 4] = 1
+    elif a.tune in ("coop64", "coop128"):
+        table = np.full((s.n_levels, 5), 1024, dtype=np.int32)
+        table[:, 4] = 0
+        table[:, 2:4] = 1 if a.tune == "coop64" else 2
     for _ in range(a.warmup):
         one_step(a.precision)
     torch.cuda.synchronize()

@@ -234,8 +234,13 @@ cav_status cav_batch_solve(cav_ctx* ctxs, int32_t n_sys, const double* const* b,
  * The multiplicative sweep launches one kernel per colour phase; each patch
  * of a phase gets one workgroup of 256, 512 or 1024 threads, or (entry 0) the
  * split form: its residual rows and GEMV row blocks spread over several
- * workgroups in two launches. Alternatively the whole sweep of a level runs
- * in one cooperative launch with a bounded grid barrier after each phase.
+ * workgroups in two launches, or (entries 1 and 2) the cooperative form: one
+ * launch in which a patch of n rows gets ceil(n / 64) or ceil(n / 128)
+ * workgroups that each form all residual rows, meet at a bounded barrier on a
+ * per-patch counter, and apply 64 or 128 rows of the inverse (inside a
+ * captured graph the one-workgroup form runs instead). Alternatively the
+ * whole sweep of a level runs in one cooperative launch with a bounded grid
+ * barrier after each phase.
  * cav_autotune times the choices on the context's own phases, per smoothed
  * level and per size bucket of a phase's largest patch (<= 64, <= 128,
  * <= 256, larger), then per level per-phase launches against the one-launch
@@ -243,9 +248,9 @@ cav_status cav_batch_solve(cav_ctx* ctxs, int32_t n_sys, const double* const* b,
  * (5 ints per level, levels 0 .. n_levels-1, level 0 unused: 4 bucket
  * entries, then 1 for the one-launch sweep) to `table` (optional). Results do
  * not depend on the choice (every patch's and cell's arithmetic is the same).
- * Uses the levels' scratch vectors; synchronises. A one-launch sweep whose
- * barrier wait times out stops early and makes the next FGMRES solve return
- * CAV_ERR_HIP. cav_set_tuning applies a stored table, e.g. one cached in a
+ * Uses the levels' scratch vectors; synchronises. A barrier wait that times
+ * out (cooperative phase form or one-launch sweep) leaves x unwritten from
+ * that point and makes the next FGMRES solve return CAV_ERR_HIP. cav_set_tuning applies a stored table, e.g. one cached in a
  * file by the caller. */
 cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table);
 cav_status cav_set_tuning(cav_ctx ctx, const int32_t* table);

@@ -532,8 +532,9 @@ class Solver:
         return t.reshape(self.n_levels, 5)
 
     def set_tuning(self, table) -> None:
-        """Apply a phase-kernel table (n_levels x 5: four bucket entries of 0, 256,
-        512 or 1024, then 1 for the one-launch sweep of that level)."""
+        """Apply a phase-kernel table (n_levels x 5: four bucket entries of 256, 512
+        or 1024 threads, 0 for the split form or 1/2 for the cooperative form
+        with 64/128 rows per workgroup, then 1 for the one-launch sweep)."""
         t = np.ascontiguousarray(table, dtype=np.int32).ravel()
         self._check(self._L.cav_set_tuning(self._h, _arr(t, C.c_int32)))
 

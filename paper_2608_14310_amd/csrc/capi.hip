@@ -1,5 +1,7 @@
 // C ABI: context lifecycle, setup orchestration, V-cycle and FGMRES.
 #include <algorithm>
+#include <exception>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -67,7 +69,8 @@ void free_level(Ctx& c, Level& L) {
                   (void*)L.d_cellflag, (void*)L.d_slot_dof, (void*)L.d_delta, (void*)L.d_t_dof, (void*)L.d_t_inv,
                   (void*)L.d_t_ptr, (void*)L.d_t_slot, (void*)L.d_std_inv, (void*)L.d_rec64, (void*)L.d_rec32,
                   (void*)L.d_f64, (void*)L.d_f32, (void*)L.d_b, (void*)L.d_x, (void*)L.d_r, (void*)L.d_z,
-                  (void*)L.d_part, (void*)L.d_mrec, (void*)L.d_wrk, (void*)L.d_ph_ptr, (void*)L.d_slot_mask})
+                  (void*)L.d_part, (void*)L.d_mrec, (void*)L.d_wrk, (void*)L.d_ph_ptr, (void*)L.d_slot_mask,
+                  (void*)L.d_wrk2, (void*)L.d_pcnt, (void*)L.d_slot_q})
     dev_free(c, p);
   L = Level();
 }
@@ -76,7 +79,8 @@ void free_patches(Ctx& c, Level& L) {
   for (void** p : {(void**)&L.d_cellflag, (void**)&L.d_slot_dof, (void**)&L.d_delta, (void**)&L.d_t_dof,
                    (void**)&L.d_t_inv, (void**)&L.d_t_ptr, (void**)&L.d_t_slot, (void**)&L.d_std_inv,
                    (void**)&L.d_rec64, (void**)&L.d_rec32, (void**)&L.d_f64, (void**)&L.d_f32,
-                   (void**)&L.d_mrec, (void**)&L.d_wrk, (void**)&L.d_ph_ptr, (void**)&L.d_slot_mask}) {
+                   (void**)&L.d_mrec, (void**)&L.d_wrk, (void**)&L.d_ph_ptr, (void**)&L.d_slot_mask,
+                   (void**)&L.d_wrk2, (void**)&L.d_pcnt, (void**)&L.d_slot_q}) {
     dev_free(c, *p);
     *p = nullptr;
   }
@@ -162,7 +166,7 @@ void check_sweep_flags(Ctx& c) {
   CAV_HIP(hipStreamSynchronize(c.stream));
   if (f[1] != 0) {
     launch_clear_sweep_flags(c, c.stream);
-    throw StatusError(CAV_ERR_HIP, "a persistent smoother sweep timed out at a grid barrier; results are invalid");
+    throw StatusError(CAV_ERR_HIP, "a smoother sweep timed out at a workgroup barrier; results are invalid");
   }
 }
 
@@ -565,16 +569,41 @@ static cav_status build_family(cav_ctx ctx, int family, int box_b, int box_o, ca
   CAV_HIP(hipSetDevice(c.device));
   c.family = family;
   c.patched = c.factored = false;
+  for (int l = 1; l < c.n_levels; ++l) free_patches(c, c.lv[l]);
+  // the levels' host-side patch sets are independent: build them concurrently
+  {
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> errs(c.n_levels);
+    for (int l = 1; l < c.n_levels; ++l)
+      th.emplace_back([&, l] {
+        try {
+          Level& L = c.lv[l];
+          if (family == CAV_FAMILY_BOX)
+            build_box_patches(L.N, L.ee, box_b, box_o, L);
+          else
+            build_patches(L.N, L.ee, family, L);
+        } catch (...) {
+          errs[l] = std::current_exception();
+        }
+      });
+    for (auto& x : th) x.join();
+    for (auto& e : errs)
+      if (e) std::rethrow_exception(e);
+  }
   for (int l = 1; l < c.n_levels; ++l) {
     Level& L = c.lv[l];
-    free_patches(c, L);
-    if (family == CAV_FAMILY_BOX)
-      build_box_patches(L.N, L.ee, box_b, box_o, L);
-    else
-      build_patches(L.N, L.ee, family, L);
     if (!L.slot_mask_h.empty()) L.d_slot_mask = upload(c, L.slot_mask_h);
     L.d_cellflag = upload(c, L.cellflag);
     L.d_slot_dof = upload(c, L.slot_dof_h);
+    {
+      const int64_t nv = 2 * int64_t(L.N) * L.N;
+      std::vector<int2> sq(L.slot_dof_h.size());
+      for (size_t k = 0; k < sq.size(); ++k) {
+        const int64_t d = L.slot_dof_h[k];
+        sq[k] = d < nv ? make_int2(int(L.ee.rowptr[d]), int(L.ee.rowptr[d + 1])) : make_int2(0, 0);
+      }
+      L.d_slot_q = upload(c, sq);
+    }
     L.d_delta = static_cast<double*>(dev_alloc(c, size_t(std::max<int64_t>(L.n_slots, 1)) * sizeof(double)));
     L.d_t_dof = upload(c, L.t_dof_h);
     L.d_t_inv = upload(c, L.t_inv_h);
@@ -774,6 +803,7 @@ cav_status cav_fgmres_solve(cav_ctx ctx, const double* b, double* x, const cav_f
   // true residual in FP64
   launch_apply_op(F, x, c.d_w, c.d_bb, s);
   const double rn = dnorm(c, c.d_w, n);
+  check_sweep_flags(c);
   inf.iterations = k;
   inf.converged = conv ? 1 : 0;
   inf.est_rel_residual = est;
@@ -1238,7 +1268,7 @@ cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table) {
   const bool timing = c.timing;
   c.timing = false;
   launch_clear_sweep_flags(c, s);
-  const int cand[4] = {256, 512, 1024, 0};
+  const int cand[6] = {256, 512, 1024, 0, 1, 2};
   for (int l = 1; l < c.n_levels; ++l) {
     Level& L = c.lv[l];
     const int nph = int(L.ph_ptr.size()) - 1;
@@ -1304,8 +1334,8 @@ cav_status cav_set_tuning(cav_ctx ctx, const int32_t* table) {
   for (int l = 0; l < c.n_levels; ++l) {
     for (int bk = 0; bk < 4; ++bk) {
       const int v = table[5 * l + bk];
-      require(v == 256 || v == 512 || v == 1024 || v == 0, CAV_ERR_INVALID_ARG,
-              "bucket entries must be 256, 512, 1024 or 0 (split form)");
+      require(v == 256 || v == 512 || v == 1024 || v == 0 || v == 1 || v == 2, CAV_ERR_INVALID_ARG,
+              "bucket entries must be 256, 512, 1024, 0 (split form) or 1/2 (cooperative form, 64/128 rows)");
     }
     require(table[5 * l + 4] == 0 || table[5 * l + 4] == 1, CAV_ERR_INVALID_ARG, "the sweep entry must be 0 or 1");
   }

@@ -66,6 +66,8 @@ struct Level {
   std::vector<int32_t> patch_dofs;
   std::vector<int32_t> exp_cells;          // explicit patch -> seed cell
   std::vector<int64_t> exp_off;            // explicit patch -> slot offset (n_exp + 1)
+  std::vector<int64_t> exp_cov_off;        // explicit patch -> offset into exp_cov (n_exp + 1)
+  std::vector<int32_t> exp_cov;            // cells C_e whose unknowns make up patch e (host only)
   std::vector<int32_t> slot_dof_h;
   std::vector<uint8_t> slot_mask_h;        // box family: 1 where the slot's unknown is injected
   uint8_t* d_slot_mask = nullptr;           // nullptr for the CAV / Vanka families
@@ -73,6 +75,7 @@ struct Level {
   int32_t n_exp = 0;
   int64_t n_slots = 0;
   int32_t* d_slot_dof = nullptr;
+  int2* d_slot_q = nullptr;                // per slot: E_E entry range [x, y) of its unknown (empty for p)
   double* d_delta = nullptr;
   int32_t n_touched = 0;
   std::vector<int32_t> t_dof_h, t_ptr_h, t_slot_h;
@@ -91,7 +94,8 @@ struct Level {
   std::vector<int32_t> ph_maxn;           // largest patch of each phase
   int32_t smoother = -1;                  // per-level smoother kind (-1: the context's)
   double alpha = 0.0;                     // its damping when smoother >= 0
-  int32_t mx_nt[4] = {1024, 1024, 1024, 1024};  // per size bucket: 256/512/1024 threads, 0 = split form (autotuned)
+  int32_t mx_nt[4] = {1024, 1024, 1024, 1024};  // per size bucket: 256/512/1024 threads, 0 = split form,
+                                                // 1/2 = cooperative form with 64/128 rows per workgroup (autotuned)
   int32_t* d_ph_ptr = nullptr;            // device copy of ph_ptr (persistent sweep)
   bool persistent = false;                // whole sweep in one cooperative launch (autotuned)
   int sweep_grid = 0;                     // its workgroups (0: not yet computed)
@@ -99,6 +103,13 @@ struct Level {
   int2* d_wrk = nullptr;                  // (record index in d_mrec, first row)
   size_t sp_lds = 0;                      // dynamic LDS of the split GEMV kernel
   size_t mx_lds = 0;                      // dynamic LDS of the phase kernel
+  // cooperative phase form: items (record, first row) of 128-row blocks (the
+  // 64-row form reuses d_wrk), arrival counters (records of the 64-row form,
+  // then of the 128-row form), and its LDS
+  std::vector<int32_t> ph_wptr2;
+  int2* d_wrk2 = nullptr;
+  unsigned long long* d_pcnt = nullptr;
+  size_t cp_lds[2] = {0, 0};
 
   // factors
   bool factored = false;

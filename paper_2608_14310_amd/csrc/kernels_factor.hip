@@ -734,6 +734,22 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
     }
     if (L.d_wrk) dev_free(c, L.d_wrk);
     L.d_wrk = upload(c, wrk);
+    // cooperative form with 128-row blocks; one arrival counter per record
+    std::vector<int2> wrk2;
+    L.ph_wptr2.assign(1, 0);
+    for (size_t ph = 0; ph + 1 < L.ph_ptr.size(); ++ph) {
+      for (int32_t q = L.ph_ptr[ph]; q < L.ph_ptr[ph + 1]; ++q)
+        for (int32_t r0 = 0; r0 < mrec[q].n; r0 += 128) wrk2.push_back(make_int2(q, r0));
+      L.ph_wptr2.push_back(int32_t(wrk2.size()));
+    }
+    if (L.d_wrk2) dev_free(c, L.d_wrk2);
+    L.d_wrk2 = upload(c, wrk2);
+    // two counters per record, one per row-block size: a counter must only
+    // ever see rounds of its own k = ceil(n / rows)
+    if (L.d_pcnt) dev_free(c, L.d_pcnt);
+    const size_t ncnt = 2 * std::max<size_t>(mrec.size(), 1);
+    L.d_pcnt = static_cast<unsigned long long*>(dev_alloc(c, ncnt * sizeof(unsigned long long)));
+    CAV_HIP(hipMemsetAsync(L.d_pcnt, 0, ncnt * sizeof(unsigned long long), s));
     if (L.d_ph_ptr) dev_free(c, L.d_ph_ptr);
     L.d_ph_ptr = upload(c, L.ph_ptr);
     L.sweep_grid = 0;
@@ -742,7 +758,9 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
       CAV_HIP(hipMemsetAsync(c.d_bar, 0, 2 * sizeof(unsigned long long), s));
     }
     L.sp_lds = size_t(mn + ((mn + 15) / 16) * 64) * sizeof(double);
-    prepare_mult_smoother(L.sp_lds);
+    L.cp_lds[0] = L.sp_lds;
+    L.cp_lds[1] = size_t(mn + ((mn + 15) / 16) * 128) * sizeof(double);
+    prepare_mult_smoother(L.cp_lds[1]);
   }
   L.d_rec64 = upload(c, o64);
   L.d_rec32 = upload(c, o32);

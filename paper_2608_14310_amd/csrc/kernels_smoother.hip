@@ -185,26 +185,27 @@ constexpr int MX_RB = 64;   // rows per workgroup in the split phase kernels
 // kernel bit-identical.
 constexpr int MX_R = 4;
 template <typename Emit>
-__device__ __forceinline__ void mx_residual_rows(const int32_t* __restrict__ dofs, int r0, int step, int r1, int gl,
-                                                 StencilCoef sc, int64_t nv, const int32_t* __restrict__ erow,
+__device__ __forceinline__ void mx_residual_rows(const int32_t* __restrict__ dofs, const int2* __restrict__ sq, int r0,
+                                                 int step, int r1, int gl, StencilCoef sc,
                                                  const int32_t* __restrict__ ecol, const double* __restrict__ eval,
                                                  const double* __restrict__ b, const double* __restrict__ x,
                                                  Emit emit) {
   int64_t d[MX_R];
   int q0[MX_R], q1[MX_R];
+  // the unknown and its E_E entry range come from per-slot arrays, so both
+  // loads are in flight together
 #pragma unroll
   for (int u = 0; u < MX_R; ++u) {
     const int rr = r0 + u * step;
-    d[u] = rr < r1 ? int64_t(dofs[rr]) : int64_t(-1);
+    const bool ok = rr < r1;
+    d[u] = ok ? int64_t(dofs[rr]) : int64_t(-1);
+    const int2 q = ok ? sq[rr] : make_int2(0, 0);
+    q0[u] = q.x;
+    q1[u] = q.y;
   }
   int rounds = 0;
 #pragma unroll
-  for (int u = 0; u < MX_R; ++u) {
-    const bool ee = d[u] >= 0 && d[u] < nv;
-    q0[u] = ee ? erow[d[u]] : 0;
-    q1[u] = ee ? erow[d[u] + 1] : 0;
-    rounds = max(rounds, (q1[u] - q0[u] + MX_G * MX_PER - 1) / (MX_G * MX_PER));
-  }
+  for (int u = 0; u < MX_R; ++u) rounds = max(rounds, (q1[u] - q0[u] + MX_G * MX_PER - 1) / (MX_G * MX_PER));
   double acc[MX_R];
 #pragma unroll
   for (int u = 0; u < MX_R; ++u) acc[u] = 0.0;
@@ -303,7 +304,7 @@ __device__ __forceinline__ void mx_gemv_pairs(const T* __restrict__ arena, int64
 template <int NT>
 __device__ __forceinline__ void mx_patch(const MultRec& rec, double* smem, const double* __restrict__ a64,
                                          const float* __restrict__ a32, const int32_t* __restrict__ slot_dof,
-                                         StencilCoef sc, const int32_t* __restrict__ erow,
+                                         StencilCoef sc, const int2* __restrict__ slot_q,
                                          const int32_t* __restrict__ ecol, const double* __restrict__ eval,
                                          const double* __restrict__ b, double* __restrict__ x, double alpha,
                                          const uint8_t* __restrict__ smask) {
@@ -312,11 +313,11 @@ __device__ __forceinline__ void mx_patch(const MultRec& rec, double* smem, const
   double* rp = smem;             // n
   double* pp = smem + n;         // nb x n block partials
   const int32_t* dofs = slot_dof + rec.slot;
-  const int64_t nv = 2 * int64_t(sc.N) * sc.N;
+  const int2* sq = slot_q + rec.slot;
   const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
   constexpr int NG = NT / MX_G;
   for (int rb = grp; rb < n; rb += NG * MX_R)
-    mx_residual_rows(dofs, rb, NG, n, gl, sc, nv, erow, ecol, eval, b, x, [&](int rr, double r) { rp[rr] = r; });
+    mx_residual_rows(dofs, sq, rb, NG, n, gl, sc, ecol, eval, b, x, [&](int rr, double r) { rp[rr] = r; });
   __syncthreads();
   {
     auto ij = [n](int t, int& i, int& cb) {
@@ -345,13 +346,13 @@ __device__ __forceinline__ void mx_patch(const MultRec& rec, double* smem, const
 template <int NT>
 __global__ __launch_bounds__(NT) void k_mult_exp(const MultRec* __restrict__ recs, const double* __restrict__ a64,
                                                  const float* __restrict__ a32, const int32_t* __restrict__ slot_dof,
-                                                 StencilCoef sc, const int32_t* __restrict__ erow,
+                                                 StencilCoef sc, const int2* __restrict__ slot_q,
                                                  const int32_t* __restrict__ ecol, const double* __restrict__ eval,
                                                  const double* __restrict__ b, double* __restrict__ x, double alpha,
                                                  const uint8_t* __restrict__ smask) {
   extern __shared__ double smem[];
   const MultRec rec = recs[blockIdx.x];
-  mx_patch<NT>(rec, smem, a64, a32, slot_dof, sc, erow, ecol, eval, b, x, alpha, smask);
+  mx_patch<NT>(rec, smem, a64, a32, slot_dof, sc, slot_q, ecol, eval, b, x, alpha, smask);
 }
 
 // Split form of one phase, for patches too large for one workgroup to stream
@@ -362,18 +363,18 @@ __global__ __launch_bounds__(NT) void k_mult_exp(const MultRec* __restrict__ rec
 // at its rows' unknowns only. The results equal k_mult_exp's bit for bit.
 __global__ __launch_bounds__(256) void k_mult_res(const int2* __restrict__ items, const MultRec* __restrict__ recs,
                                                   const int32_t* __restrict__ slot_dof, StencilCoef sc,
-                                                  const int32_t* __restrict__ erow, const int32_t* __restrict__ ecol,
+                                                  const int2* __restrict__ slot_q, const int32_t* __restrict__ ecol,
                                                   const double* __restrict__ eval, const double* __restrict__ b,
                                                   const double* __restrict__ x, double* __restrict__ rbuf) {
   const int2 it = items[blockIdx.x];
   const MultRec rec = recs[it.x];
   const int r0 = it.y, r1 = min(rec.n, it.y + MX_RB);
   const int32_t* dofs = slot_dof + rec.slot;
-  const int64_t nv = 2 * int64_t(sc.N) * sc.N;
+  const int2* sq = slot_q + rec.slot;
   const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
   constexpr int NG = 256 / MX_G;
   for (int rb = r0 + grp; rb < r1; rb += NG * MX_R)
-    mx_residual_rows(dofs, rb, NG, r1, gl, sc, nv, erow, ecol, eval, b, x,
+    mx_residual_rows(dofs, sq, rb, NG, r1, gl, sc, ecol, eval, b, x,
                      [&](int rr, double r) { rbuf[rec.slot + rr] = r; });
 }
 
@@ -412,15 +413,98 @@ __global__ __launch_bounds__(256) void k_mult_gemv(const int2* __restrict__ item
   }
 }
 
+// Cooperative form of one phase: a patch with n > RB rows is spread over
+// k = ceil(n / RB) workgroups, item (patch, first row r0). Every workgroup of
+// the patch forms all n residual rows in LDS (the same rows and arithmetic as
+// k_mult_exp), then the k workgroups meet at a barrier on the patch's arrival
+// counter, so that no unknown of the patch is written before all of them have
+// read x; each then forms its RB rows of delta (items and block order as in
+// k_mult_exp) and updates x at those rows. The results equal k_mult_exp's bit
+// for bit. The counter only grows: an arrival that reads `old` waits for the
+// end of its round, (old / k + 1) k, so it never needs a reset. The k
+// workgroups of a patch are consecutive items of one launch, which the
+// dispatcher places in order; the wait is bounded all the same, and a timeout
+// sets err and leaves x unwritten (the host reports the failure).
+template <int RB>
+__global__ __launch_bounds__(1024) void k_mult_coop(const int2* __restrict__ items, const MultRec* __restrict__ recs,
+                                                    const double* __restrict__ a64, const float* __restrict__ a32,
+                                                    const int32_t* __restrict__ slot_dof, StencilCoef sc,
+                                                    const int2* __restrict__ slot_q, const int32_t* __restrict__ ecol,
+                                                    const double* __restrict__ eval, const double* __restrict__ b,
+                                                    double* __restrict__ x, double alpha,
+                                                    const uint8_t* __restrict__ smask,
+                                                    unsigned long long* __restrict__ cnt, int* __restrict__ err,
+                                                    unsigned limit) {
+  constexpr int NT = 1024;
+  extern __shared__ double smem[];
+  __shared__ int s_ok;
+  const int2 it = items[blockIdx.x];
+  const MultRec rec = recs[it.x];
+  const int n = rec.n;
+  const int nb = (n + MX_CB - 1) / MX_CB;
+  const int k = (n + RB - 1) / RB;
+  const int r0 = it.y, nr = min(RB, n - r0);
+  double* rp = smem;        // n
+  double* pp = smem + n;    // nb x RB block partials
+  const int32_t* dofs = slot_dof + rec.slot;
+  const int2* sq = slot_q + rec.slot;
+  const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
+  constexpr int NG = NT / MX_G;
+  for (int rb = grp; rb < n; rb += NG * MX_R)
+    mx_residual_rows(dofs, sq, rb, NG, n, gl, sc, ecol, eval, b, x, [&](int rr, double r) { rp[rr] = r; });
+  __syncthreads();
+  if (k > 1) {
+    if (threadIdx.x == 0) {
+      // every x load of this workgroup has returned (its values are in LDS)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      const unsigned long long old = __hip_atomic_fetch_add(cnt + it.x, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long target = (old / unsigned(k) + 1) * unsigned(k);
+      int good = 1;
+      unsigned spins = 0;
+      while (__hip_atomic_load(cnt + it.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          atomicExch(err, 1);
+          good = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      s_ok = good;
+    }
+    __syncthreads();
+    if (!s_ok) return;
+  }
+  {
+    auto ij = [nr, r0](int t, int& i, int& cb) {
+      i = r0 + t % nr;
+      cb = t / nr;
+    };
+    auto put = [pp, nr](int t, double v) { pp[(t / nr) * RB + t % nr] = v; };
+    if (rec.f32)
+      mx_gemv_pairs(a32, rec.fac, rp, n, nr * nb, NT, ij, put);
+    else
+      mx_gemv_pairs(a64, rec.fac, rp, n, nr * nb, NT, ij, put);
+  }
+  __syncthreads();
+  for (int ii = threadIdx.x; ii < nr; ii += NT) {
+    double s = 0.0;
+    for (int cb = 0; cb < nb; ++cb) s += pp[cb * RB + ii];
+    if (!smask || smask[rec.slot + r0 + ii]) x[dofs[r0 + ii]] += alpha * s;
+  }
+}
+
 // One colour phase of the shared standard patches: cells with
 // (i + 3 j) mod 8 == colour and no E_E entries solve their 5x5 patch from the
 // current residual and update x.
 __device__ __forceinline__ void std_cell(int N, int colour, int64_t t, const uint8_t* __restrict__ flag,
                                          const double* __restrict__ Minv, StencilCoef sc,
                                          const double* __restrict__ b, double* __restrict__ x, double alpha) {
-  const int per = N / 8;  // cells of one colour per column j
-  const int j = int(t / per), k = int(t % per);
-  const int i = ((colour - 3 * j) % 8 + 8) % 8 + 8 * k;
+  // cells of one colour in row i: j = 3 (colour - i) mod 8 + 8 m (3 is its own
+  // inverse mod 8); consecutive threads take consecutive m, 64 bytes apart
+  const int per = N / 8;
+  const int i = int(t / per), m = int(t % per);
+  const int j = ((3 * (colour - i)) % 8 + 8) % 8 + 8 * m;
   const int64_t n2 = int64_t(N) * N;
   const int64_t c = int64_t(i) * N + j;
   if (flag[c] & 1) return;
@@ -486,7 +570,7 @@ struct SweepArgs {
   const float* a32;
   const int32_t* slot_dof;
   StencilCoef sc;
-  const int32_t* erow;
+  const int2* slot_q;
   const int32_t* ecol;
   const double* eval;
   const uint8_t* flag;
@@ -522,7 +606,7 @@ __global__ __launch_bounds__(NT) void k_mult_sweep(SweepArgs a) {
         const int p1 = a.ph_ptr[ph + 1];
         for (int p = a.ph_ptr[ph] + int(blockIdx.x); p < p1; p += int(G)) {
           const MultRec rec = a.recs[p];
-          mx_patch<NT>(rec, smem, a.a64, a.a32, a.slot_dof, a.sc, a.erow, a.ecol, a.eval, a.b, a.x, a.alpha,
+          mx_patch<NT>(rec, smem, a.a64, a.a32, a.slot_dof, a.sc, a.slot_q, a.ecol, a.eval, a.b, a.x, a.alpha,
                        a.smask);
           __syncthreads();
         }
@@ -583,7 +667,7 @@ bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t
   if (nph <= 0 || !L.d_ph_ptr || !c.d_bar) return false;
   if (L.sweep_grid == 0) L.sweep_grid = sweep_grid(L);
   if (L.sweep_grid <= 0) return false;
-  SweepArgs a{L.d_mrec, L.d_ph_ptr, nph, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full, L.d_ecol, L.d_eval,
+  SweepArgs a{L.d_mrec, L.d_ph_ptr, nph, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_slot_q, L.d_ecol, L.d_eval,
               L.d_cellflag, L.d_std_inv, b, x, level_alpha(c, L), c.d_bar, reinterpret_cast<int*>(c.d_bar + 1),
               1u << 21, c.std_first ? 1 : 0, L.d_slot_mask};
   k_zero_bar<<<1, 64, 0, s>>>(c.d_bar, 1);
@@ -629,9 +713,31 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
 void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double* x, hipStream_t s) {
   const int a = L.ph_ptr[ph], cnt = L.ph_ptr[ph + 1] - a;
   const unsigned g = unsigned(cnt);
+  // the cooperative form waits on other workgroups of its launch; inside a
+  // captured graph (batched systems run concurrently) the one-workgroup form
+  // runs instead, with the same results
+  if ((nt == 1 || nt == 2) && c.capturing) nt = 1024;
+  if ((nt == 1 || nt == 2) && c.d_bar && L.d_pcnt) {
+    int* err = reinterpret_cast<int*>(c.d_bar + 1);
+    const double al = level_alpha(c, L);
+    if (nt == 1) {
+      const int w0 = L.ph_wptr[ph], nw = L.ph_wptr[ph + 1] - w0;
+      k_mult_coop<64><<<unsigned(nw), 1024, L.cp_lds[0], s>>>(L.d_wrk + w0, L.d_mrec, L.d_f64, L.d_f32, L.d_slot_dof,
+                                                              L.sc, L.d_slot_q, L.d_ecol, L.d_eval, b, x, al,
+                                                              L.d_slot_mask, L.d_pcnt, err, 1u << 21);
+    } else {
+      const int w0 = L.ph_wptr2[ph], nw = L.ph_wptr2[ph + 1] - w0;
+      k_mult_coop<128><<<unsigned(nw), 1024, L.cp_lds[1], s>>>(L.d_wrk2 + w0, L.d_mrec, L.d_f64, L.d_f32,
+                                                               L.d_slot_dof, L.sc, L.d_slot_q, L.d_ecol, L.d_eval,
+                                                               b, x, al, L.d_slot_mask, L.d_pcnt + L.ph_exp.size(), err,
+                                                               1u << 21);
+    }
+    return;
+  }
+  if (nt == 1 || nt == 2) nt = 1024;
   if (nt == 0) {
     const int w0 = L.ph_wptr[ph], nw = L.ph_wptr[ph + 1] - w0;
-    k_mult_res<<<unsigned(nw), 256, 0, s>>>(L.d_wrk + w0, L.d_mrec, L.d_slot_dof, L.sc, L.d_erow_full, L.d_ecol,
+    k_mult_res<<<unsigned(nw), 256, 0, s>>>(L.d_wrk + w0, L.d_mrec, L.d_slot_dof, L.sc, L.d_slot_q, L.d_ecol,
                                             L.d_eval, b, x, L.d_delta);
     k_mult_gemv<<<unsigned(nw), 256, L.sp_lds, s>>>(L.d_wrk + w0, L.d_mrec, L.d_f64, L.d_f32, L.d_slot_dof,
                                                     L.d_delta, x, level_alpha(c, L), L.d_slot_mask);
@@ -639,15 +745,15 @@ void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double
   }
   switch (nt) {
     case 256:
-      k_mult_exp<256><<<g, 256, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full,
+      k_mult_exp<256><<<g, 256, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_slot_q,
                                                L.d_ecol, L.d_eval, b, x, level_alpha(c, L), L.d_slot_mask);
       break;
     case 512:
-      k_mult_exp<512><<<g, 512, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full,
+      k_mult_exp<512><<<g, 512, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_slot_q,
                                                L.d_ecol, L.d_eval, b, x, level_alpha(c, L), L.d_slot_mask);
       break;
     default:
-      k_mult_exp<1024><<<g, 1024, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_erow_full,
+      k_mult_exp<1024><<<g, 1024, L.mx_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_slot_q,
                                                  L.d_ecol, L.d_eval, b, x, level_alpha(c, L), L.d_slot_mask);
   }
 }
@@ -659,7 +765,8 @@ void prepare_mult_smoother(size_t lds) {
   if (lds <= set_to) return;
   for (const void* f : {reinterpret_cast<const void*>(k_mult_exp<256>), reinterpret_cast<const void*>(k_mult_exp<512>),
                         reinterpret_cast<const void*>(k_mult_exp<1024>), reinterpret_cast<const void*>(k_mult_gemv),
-                        reinterpret_cast<const void*>(k_mult_sweep<1024>)})
+                        reinterpret_cast<const void*>(k_mult_sweep<1024>), reinterpret_cast<const void*>(k_mult_coop<64>),
+                        reinterpret_cast<const void*>(k_mult_coop<128>)})
     CAV_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   set_to = lds;
 }

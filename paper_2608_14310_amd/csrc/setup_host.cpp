@@ -1,6 +1,7 @@
 // Host-side setup: force laws, interpolation weights, E_E = S E J on the finest
 // level, Galerkin coarsening, and patch construction (Sections 2-4).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -17,21 +18,99 @@ inline int pmod(int64_t a, int n) {
   return int(r < 0 ? r + n : r);
 }
 
-// f(begin, end) over contiguous ranges of [0, n) on up to 16 host threads.
-template <typename F>
-void parallel_chunks(int64_t n, F&& f) {
+// f(state, i) for every i in [0, n) on up to 16 host threads, items handed out
+// in grains from a shared counter (the work per item is very uneven: patches
+// near the structure are large). make_state() builds each thread's scratch
+// once. Every item writes only its own output, so the result does not depend
+// on the schedule.
+template <typename MS, typename F>
+void parallel_items(int64_t n, int64_t grain, MS&& make_state, F&& f) {
   int nt = int(std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u));
-  if (n < 256) nt = 1;
+  if (n <= grain) nt = 1;
+  std::atomic<int64_t> next{0};
+  auto work = [&] {
+    auto st = make_state();
+    for (;;) {
+      const int64_t b = next.fetch_add(grain);
+      if (b >= n) break;
+      const int64_t e = std::min(n, b + grain);
+      for (int64_t i = b; i < e; ++i) f(st, i);
+    }
+  };
   if (nt <= 1) {
-    f(int64_t(0), n);
+    work();
     return;
   }
   std::vector<std::thread> th;
-  for (int t = 0; t < nt; ++t) {
-    const int64_t b = n * t / nt, e = n * (t + 1) / nt;
-    th.emplace_back([&f, b, e] { f(b, e); });
-  }
+  for (int t = 0; t < nt; ++t) th.emplace_back(work);
   for (auto& x : th) x.join();
+}
+
+// Rows [0, nrows) of a sparse matrix with ncols columns, built in parallel
+// blocks of rows: row(f, add) calls add(g, v) for every contribution to row f
+// in a fixed order; the contributions to one column are summed in that order
+// and the row is stored with ascending columns. skip(f0, f1) may report a
+// block of rows without any contribution. The blocks are concatenated in
+// order, so the result does not depend on the schedule.
+template <typename Skip, typename Row>
+void build_rows(int64_t nrows, int64_t ncols, HostCSR& out, Skip&& skip, Row&& row) {
+  constexpr int64_t RB = 1024;
+  const int64_t nblk = (nrows + RB - 1) / RB;
+  struct Block {
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    std::vector<int64_t> len;
+  };
+  struct Acc {
+    std::vector<double> acc;
+    std::vector<int64_t> mark;
+    std::vector<int32_t> touched;
+  };
+  std::vector<Block> blocks(nblk);
+  parallel_items(
+      nblk, 1, [] { return Acc{}; },
+      [&](Acc& A, int64_t b) {
+        Block& B = blocks[b];
+        const int64_t f0 = b * RB, f1 = std::min(nrows, f0 + RB);
+        B.len.assign(f1 - f0, 0);
+        if (skip(f0, f1)) return;
+        if (A.acc.empty()) {
+          A.acc.assign(ncols, 0.0);
+          A.mark.assign(ncols, -1);
+        }
+        for (int64_t f = f0; f < f1; ++f) {
+          A.touched.clear();
+          row(f, [&](int32_t g, double v) {
+            if (A.mark[g] != f) {
+              A.mark[g] = f;
+              A.acc[g] = 0.0;
+              A.touched.push_back(g);
+            }
+            A.acc[g] += v;
+          });
+          std::sort(A.touched.begin(), A.touched.end());
+          for (int32_t g : A.touched) {
+            B.col.push_back(g);
+            B.val.push_back(A.acc[g]);
+          }
+          B.len[f - f0] = int64_t(A.touched.size());
+        }
+      });
+  out.n = nrows;
+  out.rowptr.assign(nrows + 1, 0);
+  int64_t total = 0;
+  for (const Block& B : blocks) total += int64_t(B.col.size());
+  out.col.clear();
+  out.val.clear();
+  out.col.reserve(size_t(total));
+  out.val.reserve(size_t(total));
+  for (int64_t b = 0; b < nblk; ++b) {
+    const Block& B = blocks[b];
+    const int64_t f0 = b * RB;
+    for (size_t k = 0; k < B.len.size(); ++k) out.rowptr[f0 + int64_t(k) + 1] = out.rowptr[f0 + int64_t(k)] + B.len[k];
+    out.col.insert(out.col.end(), B.col.begin(), B.col.end());
+    out.val.insert(out.val.end(), B.val.begin(), B.val.end());
+  }
 }
 
 // Peskin's four-point kernel (the textbook closed form used in Section 2).
@@ -203,42 +282,19 @@ void assemble_ee_finest(int N, const Structure& s, HostCSR& ee) {
         fw[q] = sup[r].w[t];
       }
   }
-  ee.n = nv;
-  ee.rowptr.assign(nv + 1, 0);
-  ee.col.clear();
-  ee.val.clear();
-  std::vector<double> acc(nv, 0.0);
-  std::vector<int32_t> mark(nv, -1), touched;
-  touched.reserve(4096);
-  for (int64_t f = 0; f < nv; ++f) {
-    if (fptr[f + 1] > fptr[f]) {
-      touched.clear();
-      for (int64_t q = fptr[f]; q < fptr[f + 1]; ++q) {
-        const int64_t r = fr[q];
-        const double wf = fw[q] * s.omega[r / 2] * ih2;
-        for (int64_t k = s.E.rowptr[r]; k < s.E.rowptr[r + 1]; ++k) {
-          const int64_t r2 = s.E.col[k];
-          const double cf = wf * s.E.val[k];
-          const Support& sg = sup[r2];
-          for (int t = 0; t < 16; ++t) {
-            const int32_t g = sg.face[t];
-            if (mark[g] != int32_t(f)) {
-              mark[g] = int32_t(f);
-              acc[g] = 0.0;
-              touched.push_back(g);
-            }
-            acc[g] += cf * sg.w[t];
+  build_rows(
+      nv, nv, ee, [&](int64_t f0, int64_t f1) { return fptr[f1] == fptr[f0]; },
+      [&](int64_t f, auto&& add) {
+        for (int64_t q = fptr[f]; q < fptr[f + 1]; ++q) {
+          const int64_t r = fr[q];
+          const double wf = fw[q] * s.omega[r / 2] * ih2;
+          for (int64_t k = s.E.rowptr[r]; k < s.E.rowptr[r + 1]; ++k) {
+            const double cf = wf * s.E.val[k];
+            const Support& sg = sup[s.E.col[k]];
+            for (int t = 0; t < 16; ++t) add(sg.face[t], cf * sg.w[t]);
           }
         }
-      }
-      std::sort(touched.begin(), touched.end());
-      for (int32_t g : touched) {
-        ee.col.push_back(g);
-        ee.val.push_back(acc[g]);
-      }
-    }
-    ee.rowptr[f + 1] = int64_t(ee.col.size());
-  }
+      });
 }
 
 namespace {
@@ -290,40 +346,57 @@ inline int prow(int Nc, int64_t g, int32_t* G, double* w) {
 // E_E^(l-1) = R E_E^(l) P with R = P^T / 4, row by row (Section 4).
 void galerkin_coarsen(int Nc, const HostCSR& fine, HostCSR& coarse) {
   const int64_t nvc = 2 * int64_t(Nc) * Nc;
-  coarse.n = nvc;
-  coarse.rowptr.assign(nvc + 1, 0);
-  coarse.col.clear();
-  coarse.val.clear();
-  std::vector<double> acc(nvc, 0.0);
-  std::vector<int64_t> mark(nvc, -1);
-  std::vector<int32_t> touched;
-  int32_t f[6], G[2];
-  double wf[6], wg[2];
-  for (int64_t F = 0; F < nvc; ++F) {
-    const int nf = pcol(Nc, F, f, wf);
-    touched.clear();
-    for (int a = 0; a < nf; ++a) {
-      const int64_t r = f[a];
-      for (int64_t k = fine.rowptr[r]; k < fine.rowptr[r + 1]; ++k) {
-        const double e = 0.25 * wf[a] * fine.val[k];
-        const int ng = prow(Nc, fine.col[k], G, wg);
-        for (int b = 0; b < ng; ++b) {
-          if (mark[G[b]] != F) { mark[G[b]] = F; acc[G[b]] = 0.0; touched.push_back(G[b]); }
-          acc[G[b]] += e * wg[b];
+  build_rows(
+      nvc, nvc, coarse, [](int64_t, int64_t) { return false; },
+      [&](int64_t F, auto&& add) {
+        int32_t f[6], G[2];
+        double wf[6], wg[2];
+        const int nf = pcol(Nc, F, f, wf);
+        for (int a = 0; a < nf; ++a) {
+          const int64_t r = f[a];
+          for (int64_t k = fine.rowptr[r]; k < fine.rowptr[r + 1]; ++k) {
+            const double e = 0.25 * wf[a] * fine.val[k];
+            const int ng = prow(Nc, fine.col[k], G, wg);
+            for (int b = 0; b < ng; ++b) add(G[b], e * wg[b]);
+          }
         }
-      }
-    }
-    std::sort(touched.begin(), touched.end());
-    for (int32_t g : touched) {
-      coarse.col.push_back(g);
-      coarse.val.push_back(acc[g]);
-    }
-    coarse.rowptr[F + 1] = int64_t(coarse.col.size());
-  }
+      });
 }
 
+// Unknowns one unknown d reaches through a structural entry of K_E (itself
+// included): MAC stencil neighbours and its E_E row.
 template <typename V>
-void visit_reach(int N, const HostCSR& ee, const Level& L, int e, V&& visit);
+void visit_unknown_reach(int N, const HostCSR& ee, int64_t d, V&& visit) {
+  const int64_t n2 = int64_t(N) * N, nv = 2 * n2;
+  visit(d);
+  if (d < n2) {                      // u_ij: u neighbours, p_ij, p_{i-1,j}, E_E row
+    const int i = int(d / N), j = int(d % N);
+    visit(int64_t(pmod(i + 1, N)) * N + j);
+    visit(int64_t(pmod(i - 1, N)) * N + j);
+    visit(int64_t(i) * N + pmod(j + 1, N));
+    visit(int64_t(i) * N + pmod(j - 1, N));
+    visit(nv + d);
+    visit(nv + int64_t(pmod(i - 1, N)) * N + j);
+  } else if (d < nv) {               // v_ij: v neighbours, p_ij, p_{i,j-1}, E_E row
+    const int64_t q = d - n2;
+    const int i = int(q / N), j = int(q % N);
+    visit(n2 + int64_t(pmod(i + 1, N)) * N + j);
+    visit(n2 + int64_t(pmod(i - 1, N)) * N + j);
+    visit(n2 + int64_t(i) * N + pmod(j + 1, N));
+    visit(n2 + int64_t(i) * N + pmod(j - 1, N));
+    visit(nv + q);
+    visit(nv + int64_t(i) * N + pmod(j - 1, N));
+  } else {                           // p_ij: the four faces of its cell
+    const int64_t q = d - nv;
+    const int i = int(q / N), j = int(q % N);
+    visit(q);
+    visit(int64_t(pmod(i + 1, N)) * N + j);
+    visit(n2 + q);
+    visit(n2 + int64_t(i) * N + pmod(j + 1, N));
+  }
+  if (d < nv)
+    for (int64_t k = ee.rowptr[d]; k < ee.rowptr[d + 1]; ++k) visit(ee.col[k]);
+}
 
 // Phases of the multiplicative sweep for the explicit patches: greedy colouring
 // of the conflict graph (two patches conflict when one holds an unknown that
@@ -331,22 +404,73 @@ void visit_reach(int N, const HostCSR& ee, const Level& L, int e, V&& visit);
 // included), visiting patches by decreasing size then cell index and giving
 // each the smallest colour free among its coloured neighbours. Patches of one
 // colour share no unknown and no coupling, so they can be applied at once.
+//
+// Every explicit patch is the unknown set V(C_e) of a cell set C_e (V(c): the
+// four faces and the pressure of cell c), so the conflict graph is formed on
+// cells: RC(c) holds the cells c' with V(c') meeting the reach of V(c), and
+// e, o conflict iff some c in C_e has some c' of C_o in RC(c). This is the
+// same relation as on unknowns, with a fraction of the work.
 void colour_explicit(int N, const HostCSR& ee, Level& L) {
-  const int64_t n2 = int64_t(N) * N, nv = 2 * n2, n = 3 * n2;
+  const int64_t n2 = int64_t(N) * N;
   const int ne = L.n_exp;
   L.ph_ptr.assign(1, 0);
   L.ph_exp.clear();
   if (ne == 0) return;
-  // owners: unknown -> explicit patches holding it
-  std::vector<int32_t> optr(n + 1, 0);
-  for (int32_t d : L.slot_dof_h) optr[d + 1]++;
-  for (int64_t d = 0; d < n; ++d) optr[d + 1] += optr[d];
-  std::vector<int32_t> own(optr.back());
+  // cell owners: cell -> explicit patches whose cell set holds it
+  std::vector<int32_t> cptr(n2 + 1, 0);
+  for (int32_t c : L.exp_cov) cptr[c + 1]++;
+  for (int64_t c = 0; c < n2; ++c) cptr[c + 1] += cptr[c];
+  std::vector<int32_t> cown(cptr.back());
   {
-    std::vector<int32_t> pos(optr.begin(), optr.end() - 1);
+    std::vector<int32_t> pos(cptr.begin(), cptr.end() - 1);
     for (int e = 0; e < ne; ++e)
-      for (int64_t s = L.exp_off[e]; s < L.exp_off[e + 1]; ++s) own[pos[L.slot_dof_h[s]]++] = e;
+      for (int64_t s = L.exp_cov_off[e]; s < L.exp_cov_off[e + 1]; ++s) cown[pos[L.exp_cov[s]]++] = e;
   }
+  // RC(c) for every covered cell (index into `covered`)
+  std::vector<int32_t> covered, cidx(n2, -1);
+  for (int64_t c = 0; c < n2; ++c)
+    if (cptr[c + 1] > cptr[c]) {
+      cidx[c] = int32_t(covered.size());
+      covered.push_back(int32_t(c));
+    }
+  std::vector<std::vector<int32_t>> rc(covered.size());
+  auto cells_of = [&](int64_t d, int32_t* out) {   // cells whose V holds unknown d
+    const int64_t nv = 2 * n2;
+    if (d < n2) {
+      const int a = int(d / N), b = int(d % N);
+      out[0] = int32_t(d);
+      out[1] = int32_t(int64_t(pmod(a - 1, N)) * N + b);
+      return 2;
+    }
+    if (d < nv) {
+      const int64_t q = d - n2;
+      const int a = int(q / N), b = int(q % N);
+      out[0] = int32_t(q);
+      out[1] = int32_t(int64_t(a) * N + pmod(b - 1, N));
+      return 2;
+    }
+    out[0] = int32_t(d - nv);
+    return 1;
+  };
+  parallel_items(
+      int64_t(covered.size()), 16, [&] { return std::vector<int32_t>(n2, -1); },
+      [&](std::vector<int32_t>& mark, int64_t k) {
+        const int32_t c = covered[k];
+        const int a = c / N, b = c % N;
+        const int64_t V[5] = {c, int64_t(pmod(a + 1, N)) * N + b, n2 + c, n2 + int64_t(a) * N + pmod(b + 1, N),
+                              2 * n2 + c};
+        std::vector<int32_t>& out = rc[k];
+        for (int64_t d : V)
+          visit_unknown_reach(N, ee, d, [&](int64_t r) {
+            int32_t cc[2];
+            const int m = cells_of(r, cc);
+            for (int t = 0; t < m; ++t)
+              if (mark[cc[t]] != c) {
+                mark[cc[t]] = c;
+                out.push_back(cc[t]);
+              }
+          });
+      });
   std::vector<int> order(ne);
   for (int e = 0; e < ne; ++e) order[e] = e;
   auto np_of = [&](int e) { return L.exp_off[e + 1] - L.exp_off[e]; };
@@ -356,25 +480,27 @@ void colour_explicit(int N, const HostCSR& ee, Level& L) {
   });
   // conflict lists, independently per patch (in parallel); then the greedy pass
   std::vector<std::vector<int32_t>> nbr(ne);
-  parallel_chunks(ne, [&](int64_t e0, int64_t e1) {
-    std::vector<int32_t> stamp(n, -1), pmark(ne, -1);
-    for (int64_t ee_ = e0; ee_ < e1; ++ee_) {
-      const int e = int(ee_);
-      std::vector<int32_t>& out = nbr[e];
-      auto visit = [&](int64_t d) {
-        if (stamp[d] == e) return;
-        stamp[d] = e;
-        for (int32_t q = optr[d]; q < optr[d + 1]; ++q) {
-          const int32_t o = own[q];
-          if (o != e && pmark[o] != e) {
-            pmark[o] = e;
-            out.push_back(o);
+  struct Marks {
+    std::vector<int32_t> stamp, pmark;
+  };
+  parallel_items(
+      ne, 8, [&] { return Marks{std::vector<int32_t>(n2, -1), std::vector<int32_t>(ne, -1)}; },
+      [&](Marks& M, int64_t ee_) {
+        const int e = int(ee_);
+        std::vector<int32_t>& out = nbr[e];
+        for (int64_t s = L.exp_cov_off[e]; s < L.exp_cov_off[e + 1]; ++s)
+          for (int32_t c2 : rc[cidx[L.exp_cov[s]]]) {
+            if (M.stamp[c2] == e) continue;
+            M.stamp[c2] = e;
+            for (int32_t q = cptr[c2]; q < cptr[c2 + 1]; ++q) {
+              const int32_t o = cown[q];
+              if (o != e && M.pmark[o] != e) {
+                M.pmark[o] = e;
+                out.push_back(o);
+              }
+            }
           }
-        }
-      };
-      visit_reach(N, ee, L, e, visit);
-    }
-  });
+      });
   std::vector<int> colour(ne, -1), cmark;
   int ncol = 0;
   for (int e : order) {
@@ -392,47 +518,6 @@ void colour_explicit(int N, const HostCSR& ee, Level& L) {
   for (int c = 0; c < ncol; ++c) {
     L.ph_exp.insert(L.ph_exp.end(), by[c].begin(), by[c].end());
     L.ph_ptr.push_back(int32_t(L.ph_exp.size()));
-  }
-}
-
-// Visits every unknown that explicit patch e's unknowns reach through a
-// structural entry of K_E (themselves included): MAC stencil neighbours and
-// E_E rows.
-template <typename V>
-void visit_reach(int N, const HostCSR& ee, const Level& L, int e, V&& visit) {
-  const int64_t n2 = int64_t(N) * N, nv = 2 * n2;
-  {
-    for (int64_t s = L.exp_off[e]; s < L.exp_off[e + 1]; ++s) {
-      const int64_t d = L.slot_dof_h[s];
-      visit(d);
-      if (d < n2) {                      // u_ij: u neighbours, p_ij, p_{i-1,j}, E_E row
-        const int i = int(d / N), j = int(d % N);
-        visit(int64_t(pmod(i + 1, N)) * N + j);
-        visit(int64_t(pmod(i - 1, N)) * N + j);
-        visit(int64_t(i) * N + pmod(j + 1, N));
-        visit(int64_t(i) * N + pmod(j - 1, N));
-        visit(nv + d);
-        visit(nv + int64_t(pmod(i - 1, N)) * N + j);
-      } else if (d < nv) {               // v_ij: v neighbours, p_ij, p_{i,j-1}, E_E row
-        const int64_t q = d - n2;
-        const int i = int(q / N), j = int(q % N);
-        visit(n2 + int64_t(pmod(i + 1, N)) * N + j);
-        visit(n2 + int64_t(pmod(i - 1, N)) * N + j);
-        visit(n2 + int64_t(i) * N + pmod(j + 1, N));
-        visit(n2 + int64_t(i) * N + pmod(j - 1, N));
-        visit(nv + q);
-        visit(nv + int64_t(i) * N + pmod(j - 1, N));
-      } else {                           // p_ij: the four faces of its cell
-        const int64_t q = d - nv;
-        const int i = int(q / N), j = int(q % N);
-        visit(q);
-        visit(int64_t(pmod(i + 1, N)) * N + j);
-        visit(n2 + q);
-        visit(n2 + int64_t(i) * N + pmod(j + 1, N));
-      }
-      if (d < nv)
-        for (int64_t k = ee.rowptr[d]; k < ee.rowptr[d + 1]; ++k) visit(ee.col[k]);
-    }
   }
 }
 
@@ -458,9 +543,11 @@ void build_box_patches(int N, const HostCSR& ee, int b, int o, Level& L) {
   L.patch_dofs.clear();
   L.exp_cells.clear();
   L.exp_off.assign(1, 0);
+  L.exp_cov_off.assign(1, 0);
+  L.exp_cov.clear();
   L.slot_dof_h.clear();
   L.slot_mask_h.clear();
-  std::vector<int32_t> mark(n, -1), core(n, -1);
+  std::vector<int32_t> mark(n, -1), core(n, -1), cmark(n2, -1);
   std::vector<int32_t> dofs;
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j) {
@@ -472,6 +559,10 @@ void build_box_patches(int N, const HostCSR& ee, int b, int o, Level& L) {
         for (int r = -o; r < b + o; ++r)
           for (int t = -o; t < b + o; ++t) {
             vanka(pmod(i + r, N), pmod(j + t, N), d);
+            if (cmark[d[4] - 2 * n2] != cell) {
+              cmark[d[4] - 2 * n2] = cell;
+              L.exp_cov.push_back(int32_t(d[4] - 2 * n2));
+            }
             for (int k = 0; k < 5; ++k)
               if (mark[d[k]] != cell) {
                 mark[d[k]] = cell;
@@ -487,6 +578,7 @@ void build_box_patches(int N, const HostCSR& ee, int b, int o, Level& L) {
         L.patch_dofs.insert(L.patch_dofs.end(), dofs.begin(), dofs.end());
         L.exp_cells.push_back(cell);
         L.exp_off.push_back(L.exp_off.back() + int64_t(dofs.size()));
+        L.exp_cov_off.push_back(int64_t(L.exp_cov.size()));
         for (int32_t q : dofs) {
           L.slot_dof_h.push_back(q);
           L.slot_mask_h.push_back(core[q] == cell ? 1 : 0);
@@ -548,20 +640,26 @@ void build_patches(int N, const HostCSR& ee, int family, Level& L) {
   L.patch_dofs.reserve(size_t(n2) * 5 + 1024);
   L.exp_cells.clear();
   L.exp_off.assign(1, 0);
+  L.exp_cov_off.assign(1, 0);
+  L.exp_cov.clear();
   L.slot_dof_h.clear();
   // rows of cells in parallel; each range keeps its own output, merged in order
   struct Part {
-    std::vector<int32_t> dofs, plen, ecells, slot, elen, cov;
+    std::vector<int32_t> dofs, plen, ecells, slot, elen, cov, clen;
   };
-  const int nchunk = std::max(1, std::min(N, 64));
-  std::vector<Part> parts(nchunk);
-  parallel_chunks(nchunk, [&](int64_t k0, int64_t k1) {
-    std::vector<int32_t> cmark(n2, -1), dmark(n, -1);
-    std::vector<int32_t> cells, dofs;
-    for (int64_t kc = k0; kc < k1; ++kc) {
-    Part& P = parts[kc];
-    const int i0 = int(int64_t(N) * kc / nchunk), i1 = int(int64_t(N) * (kc + 1) / nchunk);
-    for (int i = i0; i < i1; ++i)
+  std::vector<Part> parts(N);
+  struct Scratch {
+    std::vector<int32_t> cmark, dmark, cells, dofs, uhat;
+  };
+  parallel_items(
+      N, 1, [&] { return Scratch{std::vector<int32_t>(n2, -1), std::vector<int32_t>(n, -1), {}, {}, {}}; },
+      [&](Scratch& S, int64_t row) {
+    std::vector<int32_t>& cmark = S.cmark;
+    std::vector<int32_t>& dmark = S.dmark;
+    std::vector<int32_t>& cells = S.cells;
+    std::vector<int32_t>& dofs = S.dofs;
+    Part& P = parts[row];
+    const int i = int(row);
     for (int j = 0; j < N; ++j) {
       const int32_t cell = int32_t(int64_t(i) * N + j);
       int32_t U[4];
@@ -573,7 +671,8 @@ void build_patches(int N, const HostCSR& ee, int family, Level& L) {
       bool enlarged = false;
       if (anyrow && family == CAV_FAMILY_CAV) {
         // U_hat = U plus every velocity coupled to U through E_E (pattern is symmetric)
-        std::vector<int32_t> uhat(U, U + 4);
+        std::vector<int32_t>& uhat = S.uhat;
+        uhat.assign(U, U + 4);
         for (int k = 0; k < 4; ++k)
           for (int64_t q = ee.rowptr[U[k]]; q < ee.rowptr[U[k] + 1]; ++q) {
             const int32_t w = ee.col[q];
@@ -617,8 +716,8 @@ void build_patches(int N, const HostCSR& ee, int family, Level& L) {
         P.slot.insert(P.slot.end(), dofs.begin(), dofs.end());
         P.elen.push_back(int32_t(dofs.size()));
         P.cov.insert(P.cov.end(), cells.begin(), cells.end());
+        P.clen.push_back(int32_t(cells.size()));
       }
-    }
     }
   });
   {
@@ -636,6 +735,8 @@ void build_patches(int N, const HostCSR& ee, int family, Level& L) {
       }
       L.slot_dof_h.insert(L.slot_dof_h.end(), P.slot.begin(), P.slot.end());
       for (int32_t cc : P.cov) L.cellflag[cc] |= 2;
+      for (int32_t len : P.clen) L.exp_cov_off.push_back(L.exp_cov_off.back() + len);
+      L.exp_cov.insert(L.exp_cov.end(), P.cov.begin(), P.cov.end());
     }
   }
   L.n_exp = int32_t(L.exp_cells.size());

@@ -171,7 +171,20 @@ def test_full_size_beam512(cav):
     y = g.apply_operator(_t(xr)).cpu().numpy()
     assert np.abs(y - K @ xr).max() <= 1e-13 * np.abs(K @ xr).max()
     x, inf = g.fgmres_solve(_t(s.b), 1e-10, 150)
-    g.close()
     assert inf["converged"] and inf["iterations"] == 28
     xg = x.cpu().numpy()
     assert np.linalg.norm(s.b - K @ xg) <= 2e-10 * np.linalg.norm(s.b)
+    # the cooperative phase forms (large patches spread over several
+    # workgroups) give the same V-cycle bit for bit at this size
+    print("[full size] beam512: cooperative phase forms", flush=True)
+    z0 = g.vcycle(_t(s.b)).cpu().numpy()
+    for form in (1, 2):
+        table = np.full((s.n_levels, 5), 1024, np.int32)
+        table[:, 4] = 0
+        table[:, 2:4] = form
+        g.set_tuning(table)
+        np.testing.assert_array_equal(g.vcycle(_t(s.b)).cpu().numpy(), z0)
+    x2, inf2 = g.fgmres_solve(_t(s.b), 1e-10, 150)
+    g.close()
+    assert inf2["iterations"] == 28
+    np.testing.assert_array_equal(x2.cpu().numpy(), xg)
