@@ -303,9 +303,11 @@ cav_status cav_analysis_export_weights(cav_analysis a, int level, int32_t* dofs,
  * Between cav_kernel_timing(ctx, 1, NULL) and a later call, the library
  * records HIP events on its stream around the explicit-patch kernels (the
  * smoother's dominant kernels): one pair around each additive GEMV launch and
- * one pair around each run of consecutive multiplicative phase launches (one
- * run per sweep and level), plus one pair around every top-level V-cycle. A
- * bracket's duration includes the dispatch gaps between the launches it holds.
+ * one pair around each run of consecutive multiplicative phase launches of
+ * one kernel form (per sweep and level), plus one pair around every top-level
+ * V-cycle. A bracket's duration includes the dispatch gaps between the
+ * launches it holds; the coop_* fields repeat the totals of the brackets of
+ * cooperative-form launches.
  * A call with out != NULL synchronises the stream and returns the totals
  * since recording started; every call clears the records; enable = 0 stops. */
 typedef struct {
@@ -314,6 +316,9 @@ typedef struct {
   double bytes;            /* their summed algorithmic bytes: sum_p n_p^2 s + 20 n_p */
   int64_t vcycles;         /* top-level V-cycles */
   double vcycle_ms;        /* their summed durations */
+  int64_t coop_launches;   /* of the above: cooperative-form phase launches */
+  double coop_ms;
+  double coop_bytes;
 } cav_kernel_timing_info;
 cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* out);
 

@@ -70,7 +70,8 @@ void free_level(Ctx& c, Level& L) {
                   (void*)L.d_t_ptr, (void*)L.d_t_slot, (void*)L.d_std_inv, (void*)L.d_rec64, (void*)L.d_rec32,
                   (void*)L.d_f64, (void*)L.d_f32, (void*)L.d_b, (void*)L.d_x, (void*)L.d_r, (void*)L.d_z,
                   (void*)L.d_part, (void*)L.d_mrec, (void*)L.d_wrk, (void*)L.d_ph_ptr, (void*)L.d_slot_mask,
-                  (void*)L.d_wrk2, (void*)L.d_pcnt, (void*)L.d_slot_q})
+                  (void*)L.d_citem[0], (void*)L.d_citem[1], (void*)L.d_pcnt,
+                  (void*)L.d_slot_q})
     dev_free(c, p);
   L = Level();
 }
@@ -80,7 +81,8 @@ void free_patches(Ctx& c, Level& L) {
                    (void**)&L.d_t_inv, (void**)&L.d_t_ptr, (void**)&L.d_t_slot, (void**)&L.d_std_inv,
                    (void**)&L.d_rec64, (void**)&L.d_rec32, (void**)&L.d_f64, (void**)&L.d_f32,
                    (void**)&L.d_mrec, (void**)&L.d_wrk, (void**)&L.d_ph_ptr, (void**)&L.d_slot_mask,
-                   (void**)&L.d_wrk2, (void**)&L.d_pcnt, (void**)&L.d_slot_q}) {
+                   (void**)&L.d_citem[0], (void**)&L.d_citem[1], (void**)&L.d_pcnt,
+                   (void**)&L.d_slot_q}) {
     dev_free(c, *p);
     *p = nullptr;
   }
@@ -913,6 +915,11 @@ cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* ou
       out->launches += m.launches;
       out->ms += ms;
       out->bytes += m.bytes;
+      if (m.coop) {
+        out->coop_launches += m.launches;
+        out->coop_ms += ms;
+        out->coop_bytes += m.bytes;
+      }
     }
     for (auto& m : c.vc_marks) {
       float ms = 0.f;

@@ -36,6 +36,14 @@ struct MultRec {
   int64_t fac;
 };
 
+// One workgroup of the cooperative phase form: the patch record, the first of
+// its rows, and the index of its arrival counter (one load per workgroup).
+struct CoopItem {
+  MultRec rec;
+  int32_t r0;
+  int32_t cnt;
+};
+
 // Stencil coefficients of one level's rediscretised Stokes part.
 struct StencilCoef {
   int N;
@@ -94,7 +102,7 @@ struct Level {
   std::vector<int32_t> ph_maxn;           // largest patch of each phase
   int32_t smoother = -1;                  // per-level smoother kind (-1: the context's)
   double alpha = 0.0;                     // its damping when smoother >= 0
-  int32_t mx_nt[4] = {1024, 1024, 1024, 1024};  // per size bucket: 256/512/1024 threads, 0 = split form,
+  int32_t mx_nt[4] = {1024, 1024, 1, 1};        // per size bucket: 256/512/1024 threads, 0 = split form,
                                                 // 1/2 = cooperative form with 64/128 rows per workgroup (autotuned)
   int32_t* d_ph_ptr = nullptr;            // device copy of ph_ptr (persistent sweep)
   bool persistent = false;                // whole sweep in one cooperative launch (autotuned)
@@ -103,11 +111,11 @@ struct Level {
   int2* d_wrk = nullptr;                  // (record index in d_mrec, first row)
   size_t sp_lds = 0;                      // dynamic LDS of the split GEMV kernel
   size_t mx_lds = 0;                      // dynamic LDS of the phase kernel
-  // cooperative phase form: items (record, first row) of 128-row blocks (the
-  // 64-row form reuses d_wrk), arrival counters (records of the 64-row form,
-  // then of the 128-row form), and its LDS
+  // cooperative phase form: items of 64- and 128-row blocks per phase (the
+  // 64-row form has the split form's item offsets ph_wptr), arrival counters
+  // (records of the 64-row form, then of the 128-row form), and its LDS
   std::vector<int32_t> ph_wptr2;
-  int2* d_wrk2 = nullptr;
+  CoopItem* d_citem[2] = {nullptr, nullptr};
   unsigned long long* d_pcnt = nullptr;
   size_t cp_lds[2] = {0, 0};
 
@@ -229,16 +237,17 @@ struct Ctx {
     int ev;          // event index of the start (the end is ev + 1)
     double bytes;    // algorithmic bytes of the bracketed launches
     int launches;    // launches inside the bracket
+    int coop;        // 1: cooperative-form phase launches
   };
   std::vector<KtMark> kt_marks;
   std::vector<std::pair<int, int>> vc_marks;      // event indices around each V-cycle
 };
 
 hipEvent_t next_event(Ctx& c);
-inline void timing_begin(Ctx& c, hipStream_t s) {
+inline void timing_begin(Ctx& c, hipStream_t s, int coop = 0) {
   if (!c.timing) return;
   hipEvent_t e = next_event(c);
-  c.kt_marks.push_back({int(c.ev_used - 1), 0.0, 0});
+  c.kt_marks.push_back({int(c.ev_used - 1), 0.0, 0, coop});
   (void)hipEventRecord(e, s);
 }
 inline void timing_end(Ctx& c, hipStream_t s, double bytes, int launches = 1) {

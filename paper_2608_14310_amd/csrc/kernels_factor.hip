@@ -6,7 +6,9 @@
 // place by Gauss-Jordan elimination with partial pivoting (first maximum on
 // ties). The elimination is blocked: NB pivot columns are processed in LDS,
 // then the remaining columns receive the accumulated transformation as a
-// rank-NB update (one thread per column, coalesced row-major rows).
+// rank-NB update (one thread per column, coalesced row-major rows, loads in
+// batches of rows). Row interchanges are kept as a row map, so rows of the
+// work matrix never move; the finalize kernel reads through it.
 // kappa_1 = ||K~||_1 ||K~^{-1}||_1 is exact given the inverse. The stored
 // operator is M_p = C K~^{-1} R (column-major), which equals K_p^{-1}.
 #include <algorithm>
@@ -65,6 +67,7 @@ struct FactorJob {
   double* rs;            // per slot
   double* cs;            // per slot
   int32_t* sigma;        // per slot: pivots during elimination, column order afterwards
+  int32_t* rowp;         // per slot: physical row of each logical row (interchanges are logical)
   double* kappa;         // per patch id
   int32_t* status;       // per patch id: 0 ok, 1 zero or non-finite pivot
   StencilCoef sc;
@@ -112,13 +115,10 @@ __device__ double block_max(double v, double* sv) {
 }
 
 __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
-  extern __shared__ double P[];  // panel, row-major n x NB
+  extern __shared__ double P[];  // panel, row-major n x NB, then the row map (n ints)
   __shared__ double sv[FT / 64];
   __shared__ int si[FT / 64];
   __shared__ int s_flag;
-  __shared__ int s_piv[NB];
-  __shared__ int s_nperm;
-  __shared__ int s_pd[2 * NB], s_ps[2 * NB];
   const PatchRec rec = J.recs[blockIdx.x];
   const int n = rec.n;
   const int tid = threadIdx.x;
@@ -127,6 +127,7 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
   double* rs = J.rs + rec.slot;
   double* cs = J.cs + rec.slot;
   int32_t* piv = J.sigma + rec.slot;
+  int32_t* rp = reinterpret_cast<int32_t*>(P + int64_t(n) * NB);
 
   // 1. K_p from the stencils
   for (int64_t e = tid; e < int64_t(n) * n; e += FT) {
@@ -179,13 +180,18 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
   if (tid == 0) s_flag = 0;
   __syncthreads();
 
-  // 4. blocked in-place Gauss-Jordan with partial pivoting
+  // 4. blocked in-place Gauss-Jordan with partial pivoting. Row interchanges
+  // act on the row map rp (logical row -> physical row of W), so no row of W
+  // is ever moved; every arithmetic operation is the one of the physically
+  // interchanged elimination.
+  for (int a = tid; a < n; a += FT) rp[a] = a;
+  __syncthreads();
   for (int c0 = 0; c0 < n; c0 += NB) {
     const int nbp = min(NB, n - c0);
     // columns past nbp stay zero: the rank-NB update below reads all NB of them
     for (int e = tid; e < n * NB; e += FT) {
       const int a = e / NB, t = e % NB;
-      P[e] = t < nbp ? W[int64_t(a) * n + c0 + t] : 0.0;
+      P[e] = t < nbp ? W[int64_t(rp[a]) * n + c0 + t] : 0.0;
     }
     __syncthreads();
     for (int t = 0; t < nbp; ++t) {
@@ -199,14 +205,16 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
         __syncthreads();
         break;
       }
-      if (tid == 0) {
-        s_piv[t] = bi;
-        piv[c] = bi;
-      }
+      if (tid == 0) piv[c] = bi;
       if (bi != c && tid < nbp) {
         const double tmp = P[c * NB + tid];
         P[c * NB + tid] = P[bi * NB + tid];
         P[bi * NB + tid] = tmp;
+      }
+      if (bi != c && tid == 0) {
+        const int32_t tr = rp[c];
+        rp[c] = rp[bi];
+        rp[bi] = tr;
       }
       __syncthreads();
       const double pv = P[c * NB + t];
@@ -225,34 +233,30 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
     if (s_flag) break;
     for (int e = tid; e < n * nbp; e += FT) {
       const int a = e / nbp, t = e % nbp;
-      W[int64_t(a) * n + c0 + t] = P[a * NB + t];
+      W[int64_t(rp[a]) * n + c0 + t] = P[a * NB + t];
     }
-    // this panel's row interchanges, in order, on the other columns (one thread per column)
-    for (int j = tid; j < n; j += FT) {
-      if (j >= c0 && j < c0 + nbp) continue;
-      for (int t = 0; t < nbp; ++t) {
-        const int r = s_piv[t];
-        if (r == c0 + t) continue;
-        const double tmp = W[int64_t(c0 + t) * n + j];
-        W[int64_t(c0 + t) * n + j] = W[int64_t(r) * n + j];
-        W[int64_t(r) * n + j] = tmp;
-      }
-    }
-    __syncthreads();
-    // rank-nbp update of the other columns: pivot rows <- P11 y, other rows += P_a y
+    // rank-nbp update of the other columns: pivot rows <- P11 y, other rows +=
+    // P_a y; rows in batches of RC whose loads are issued together
+    constexpr int RC = 8;
     for (int j = tid; j < n; j += FT) {
       if (j >= c0 && j < c0 + nbp) continue;
       double y[NB];
 #pragma unroll
-      for (int t = 0; t < NB; ++t) y[t] = (t < nbp) ? W[int64_t(c0 + t) * n + j] : 0.0;
-      for (int a = 0; a < n; ++a) {
-        double s = 0.0;
+      for (int t = 0; t < NB; ++t) y[t] = (t < nbp) ? W[int64_t(rp[c0 + t]) * n + j] : 0.0;
+      for (int a0 = 0; a0 < n; a0 += RC) {
+        double w[RC];
 #pragma unroll
-        for (int t = 0; t < NB; ++t) s += P[a * NB + t] * y[t];
-        if (a >= c0 && a < c0 + nbp)
-          W[int64_t(a) * n + j] = s;
-        else
-          W[int64_t(a) * n + j] += s;
+        for (int u = 0; u < RC; ++u) w[u] = (a0 + u < n) ? W[int64_t(rp[a0 + u]) * n + j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < RC; ++u) {
+          const int a = a0 + u;
+          if (a < n) {
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < NB; ++t) s += P[a * NB + t] * y[t];
+            W[int64_t(rp[a]) * n + j] = (a >= c0 && a < c0 + nbp) ? s : w[u] + s;
+          }
+        }
       }
     }
     __syncthreads();
@@ -268,9 +272,10 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
   double cm = 0.0;
   for (int b = tid; b < n; b += FT) {
     double sum = 0.0;
-    for (int a = 0; a < n; ++a) sum += fabs(W[int64_t(a) * n + b]);
+    for (int a = 0; a < n; ++a) sum += fabs(W[int64_t(rp[a]) * n + b]);
     cm = fmax(cm, sum);
   }
+  for (int a = tid; a < n; a += FT) J.rowp[rec.slot + a] = rp[a];
   const double ninv = block_max(cm, sv);
   if (tid == 0) {
     J.status[rec.id] = isfinite(ninv) ? 0 : 1;
@@ -297,12 +302,12 @@ __global__ void k_sigma(const PatchRec* __restrict__ recs, int count, int32_t* _
   }
 }
 
-// M[i + j n] = cs[i] * W[i][sigma[j]] * rs[j]  (= K_p^{-1}), cast to T.
+// M[i + j n] = cs[i] * W[rowp[i]][sigma[j]] * rs[j]  (= K_p^{-1}), cast to T.
 template <typename T>
 __global__ __launch_bounds__(256) void k_finalize(const PatchRec* __restrict__ wrec, const PatchRec* __restrict__ orec,
                                                   const double* __restrict__ work, const double* __restrict__ rs,
                                                   const double* __restrict__ cs, const int32_t* __restrict__ sigma,
-                                                  T* __restrict__ out) {
+                                                  const int32_t* __restrict__ rowp, T* __restrict__ out) {
   const PatchRec w = wrec[blockIdx.x];
   const PatchRec o = orec[blockIdx.x];
   const int n = w.n;
@@ -310,10 +315,11 @@ __global__ __launch_bounds__(256) void k_finalize(const PatchRec* __restrict__ w
   const double* r = rs + w.slot;
   const double* c = cs + w.slot;
   const int32_t* sg = sigma + w.slot;
+  const int32_t* rw = rowp + w.slot;
   T* M = out + o.fac;
   for (int64_t e = threadIdx.x; e < int64_t(n) * n; e += 256) {
     const int i = int(e % n), j = int(e / n);
-    M[e] = T(c[i] * W[int64_t(i) * n + sg[j]] * r[j]);
+    M[e] = T(c[i] * W[int64_t(rw[i]) * n + sg[j]] * r[j]);
   }
 }
 
@@ -587,6 +593,7 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   double* rs = static_cast<double*>(dev_alloc(c, size_t(nslot) * sizeof(double)));
   double* cs = static_cast<double*>(dev_alloc(c, size_t(nslot) * sizeof(double)));
   int32_t* sig = static_cast<int32_t*>(dev_alloc(c, size_t(nslot) * sizeof(int32_t)));
+  int32_t* rowp = static_cast<int32_t*>(dev_alloc(c, size_t(nslot) * sizeof(int32_t)));
   double* kap = static_cast<double*>(dev_alloc(c, size_t(ne + 1) * sizeof(double)));
   int32_t* sts = static_cast<int32_t*>(dev_alloc(c, size_t(ne + 1) * sizeof(int32_t)));
   int32_t* d_slot_all = upload(c, slot_all);
@@ -602,6 +609,7 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   J.rs = rs;
   J.cs = cs;
   J.sigma = sig;
+  J.rowp = rowp;
   J.kappa = kap;
   J.status = sts;
   J.sc = L.sc;
@@ -610,7 +618,7 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   J.eval = L.d_eval;
   // explicit patches with E_E, the shared patch without
   const int nmax = order.empty() ? 5 : order[0].n;
-  const size_t lds = size_t(std::max(nmax, 5)) * NB * sizeof(double);
+  const size_t lds = size_t(std::max(nmax, 5)) * (NB * sizeof(double) + sizeof(int32_t));
   if (lds > 64 * 1024)
     CAV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_factor),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
@@ -631,7 +639,7 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   }
   J.recs = d_std;
   J.use_ee = 0;
-  k_factor<<<1, FT, 5 * NB * sizeof(double), s>>>(J);
+  k_factor<<<1, FT, 5 * (NB * sizeof(double) + sizeof(int32_t)), s>>>(J);
   std::vector<PatchRec> all_rec(exp_only);
   all_rec.insert(all_rec.end(), std_only.begin(), std_only.end());
   PatchRec* d_all = upload(c, all_rec);
@@ -675,17 +683,17 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   if (!w64.empty()) {
     PatchRec* dw = upload(c, w64);
     PatchRec* dout = upload(c, o64);
-    k_finalize<double><<<unsigned(w64.size()), 256, 0, s>>>(dw, dout, work, rs, cs, sig, L.d_f64);
+    k_finalize<double><<<unsigned(w64.size()), 256, 0, s>>>(dw, dout, work, rs, cs, sig, rowp, L.d_f64);
   }
   if (!w32.empty()) {
     PatchRec* dw = upload(c, w32);
     PatchRec* dout = upload(c, o32);
-    k_finalize<float><<<unsigned(w32.size()), 256, 0, s>>>(dw, dout, work, rs, cs, sig, L.d_f32);
+    k_finalize<float><<<unsigned(w32.size()), 256, 0, s>>>(dw, dout, work, rs, cs, sig, rowp, L.d_f32);
   }
   {
     std::vector<PatchRec> so = {PatchRec{5, ne, std_slot, 0}};
     PatchRec* dout = upload(c, so);
-    k_finalize<double><<<1, 256, 0, s>>>(d_std, dout, work, rs, cs, sig, L.d_std_inv);
+    k_finalize<double><<<1, 256, 0, s>>>(d_std, dout, work, rs, cs, sig, rowp, L.d_std_inv);
   }
   CAV_HIP(hipGetLastError());
   // records the smoother launches, with slots in the level's slot space
@@ -734,16 +742,21 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
     }
     if (L.d_wrk) dev_free(c, L.d_wrk);
     L.d_wrk = upload(c, wrk);
-    // cooperative form with 128-row blocks; one arrival counter per record
-    std::vector<int2> wrk2;
-    L.ph_wptr2.assign(1, 0);
-    for (size_t ph = 0; ph + 1 < L.ph_ptr.size(); ++ph) {
-      for (int32_t q = L.ph_ptr[ph]; q < L.ph_ptr[ph + 1]; ++q)
-        for (int32_t r0 = 0; r0 < mrec[q].n; r0 += 128) wrk2.push_back(make_int2(q, r0));
-      L.ph_wptr2.push_back(int32_t(wrk2.size()));
+    // cooperative form: 64- and 128-row blocks, grouped by phase
+    const int32_t nrec = int32_t(mrec.size());
+    for (int f = 0; f < 2; ++f) {
+      const int rb = f == 0 ? 64 : 128;
+      std::vector<CoopItem> ci;
+      std::vector<int32_t>& wp = f == 0 ? L.ph_wptr : L.ph_wptr2;
+      wp.assign(1, 0);
+      for (size_t ph = 0; ph + 1 < L.ph_ptr.size(); ++ph) {
+        for (int32_t q = L.ph_ptr[ph]; q < L.ph_ptr[ph + 1]; ++q)
+          for (int32_t r0 = 0; r0 < mrec[q].n; r0 += rb) ci.push_back(CoopItem{mrec[q], r0, f * nrec + q});
+        wp.push_back(int32_t(ci.size()));
+      }
+      if (L.d_citem[f]) dev_free(c, L.d_citem[f]);
+      L.d_citem[f] = upload(c, ci);
     }
-    if (L.d_wrk2) dev_free(c, L.d_wrk2);
-    L.d_wrk2 = upload(c, wrk2);
     // two counters per record, one per row-block size: a counter must only
     // ever see rounds of its own k = ceil(n / rows)
     if (L.d_pcnt) dev_free(c, L.d_pcnt);
@@ -766,7 +779,7 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   L.d_rec32 = upload(c, o32);
   CAV_HIP(hipStreamSynchronize(s));
   // scratch is released once the finalize kernels are done
-  for (void* p : {(void*)work, (void*)rs, (void*)cs, (void*)sig, (void*)kap, (void*)sts, (void*)d_slot_all,
+  for (void* p : {(void*)work, (void*)rs, (void*)cs, (void*)sig, (void*)rowp, (void*)kap, (void*)sts, (void*)d_slot_all,
                   (void*)d_order, (void*)d_exp, (void*)d_std, (void*)d_all})
     if (p) dev_free(c, p);
   if (st) {

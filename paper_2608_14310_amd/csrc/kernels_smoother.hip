@@ -203,6 +203,15 @@ __device__ __forceinline__ void mx_residual_rows(const int32_t* __restrict__ dof
     q0[u] = q.x;
     q1[u] = q.y;
   }
+  // the stencil part and b of each row (lane 0) are loaded now, beside the
+  // E_E entries, and added where the row's sum needs them
+  double stv[MX_R], bv[MX_R];
+#pragma unroll
+  for (int u = 0; u < MX_R; ++u) {
+    const bool own = gl == 0 && d[u] >= 0;
+    stv[u] = own ? krow(d[u], x, sc, nullptr, nullptr, nullptr) : 0.0;
+    bv[u] = own ? b[d[u]] : 0.0;
+  }
   int rounds = 0;
 #pragma unroll
   for (int u = 0; u < MX_R; ++u) rounds = max(rounds, (q1[u] - q0[u] + MX_G * MX_PER - 1) / (MX_G * MX_PER));
@@ -234,10 +243,10 @@ __device__ __forceinline__ void mx_residual_rows(const int32_t* __restrict__ dof
   }
 #pragma unroll
   for (int u = 0; u < MX_R; ++u) {
-    if (gl == 0 && d[u] >= 0) acc[u] += krow(d[u], x, sc, nullptr, nullptr, nullptr);
+    if (gl == 0 && d[u] >= 0) acc[u] += stv[u];
 #pragma unroll
     for (int o = MX_G / 2; o > 0; o >>= 1) acc[u] += __shfl_down(acc[u], o, MX_G);
-    if (gl == 0 && d[u] >= 0) emit(r0 + u * step, b[d[u]] - acc[u]);
+    if (gl == 0 && d[u] >= 0) emit(r0 + u * step, bv[u] - acc[u]);
   }
 }
 
@@ -426,7 +435,7 @@ __global__ __launch_bounds__(256) void k_mult_gemv(const int2* __restrict__ item
 // dispatcher places in order; the wait is bounded all the same, and a timeout
 // sets err and leaves x unwritten (the host reports the failure).
 template <int RB>
-__global__ __launch_bounds__(1024) void k_mult_coop(const int2* __restrict__ items, const MultRec* __restrict__ recs,
+__global__ __launch_bounds__(1024) void k_mult_coop(const CoopItem* __restrict__ items,
                                                     const double* __restrict__ a64, const float* __restrict__ a32,
                                                     const int32_t* __restrict__ slot_dof, StencilCoef sc,
                                                     const int2* __restrict__ slot_q, const int32_t* __restrict__ ecol,
@@ -438,12 +447,12 @@ __global__ __launch_bounds__(1024) void k_mult_coop(const int2* __restrict__ ite
   constexpr int NT = 1024;
   extern __shared__ double smem[];
   __shared__ int s_ok;
-  const int2 it = items[blockIdx.x];
-  const MultRec rec = recs[it.x];
+  const CoopItem it = items[blockIdx.x];
+  const MultRec rec = it.rec;
   const int n = rec.n;
   const int nb = (n + MX_CB - 1) / MX_CB;
   const int k = (n + RB - 1) / RB;
-  const int r0 = it.y, nr = min(RB, n - r0);
+  const int r0 = it.r0, nr = min(RB, n - r0);
   double* rp = smem;        // n
   double* pp = smem + n;    // nb x RB block partials
   const int32_t* dofs = slot_dof + rec.slot;
@@ -457,11 +466,11 @@ __global__ __launch_bounds__(1024) void k_mult_coop(const int2* __restrict__ ite
     if (threadIdx.x == 0) {
       // every x load of this workgroup has returned (its values are in LDS)
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      const unsigned long long old = __hip_atomic_fetch_add(cnt + it.x, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long old = __hip_atomic_fetch_add(cnt + it.cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const unsigned long long target = (old / unsigned(k) + 1) * unsigned(k);
       int good = 1;
       unsigned spins = 0;
-      while (__hip_atomic_load(cnt + it.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      while (__hip_atomic_load(cnt + it.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         if (++spins > limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
           atomicExch(err, 1);
           good = 0;
@@ -681,6 +690,14 @@ bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t
   return true;
 }
 
+// The form a phase launch takes: the cooperative form waits on other
+// workgroups of its launch, so inside a captured graph (batched systems run
+// concurrently) the one-workgroup form runs instead, with the same results.
+static int phase_form(const Ctx& c, const Level& L, int nt) {
+  if ((nt == 1 || nt == 2) && (c.capturing || !c.d_bar || !L.d_pcnt || !L.d_citem[nt - 1])) return 1024;
+  return nt;
+}
+
 void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s) {
   const int64_t n2 = int64_t(L.N) * L.N, n = 3 * n2;
   if (zero_guess) launch_fill(x, 0.0, n, s);
@@ -697,14 +714,24 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
   };
   if (c.std_first) standard();
   if (nph > 0) {
-    // one bracket around the run of phase launches of this sweep
-    timing_begin(c, s);
+    // one bracket around each run of phase launches of one kernel form
+    int open = -1, cnt = 0;
     double bytes = 0.0;
     for (int ph = 0; ph < nph; ++ph) {
-      launch_mult_phase(c, L, ph, L.mx_nt[mx_bucket(L.ph_maxn[ph])], b, x, s);
+      const int nt = phase_form(c, L, L.mx_nt[mx_bucket(L.ph_maxn[ph])]);
+      const int kind = (nt == 1 || nt == 2) ? 1 : 0;
+      if (kind != open) {
+        if (open >= 0) timing_end(c, s, bytes, cnt);
+        timing_begin(c, s, kind);
+        open = kind;
+        cnt = 0;
+        bytes = 0.0;
+      }
+      launch_mult_phase(c, L, ph, nt, b, x, s);
       bytes += L.ph_bytes[ph];
+      ++cnt;
     }
-    timing_end(c, s, bytes, nph);
+    timing_end(c, s, bytes, cnt);
   }
   if (!c.std_first) standard();
   launch_pressure_mean_remove(x, L.N, L.d_part, s);
@@ -713,28 +740,23 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
 void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double* x, hipStream_t s) {
   const int a = L.ph_ptr[ph], cnt = L.ph_ptr[ph + 1] - a;
   const unsigned g = unsigned(cnt);
-  // the cooperative form waits on other workgroups of its launch; inside a
-  // captured graph (batched systems run concurrently) the one-workgroup form
-  // runs instead, with the same results
-  if ((nt == 1 || nt == 2) && c.capturing) nt = 1024;
-  if ((nt == 1 || nt == 2) && c.d_bar && L.d_pcnt) {
+  nt = phase_form(c, L, nt);
+  if (nt == 1 || nt == 2) {
     int* err = reinterpret_cast<int*>(c.d_bar + 1);
     const double al = level_alpha(c, L);
     if (nt == 1) {
       const int w0 = L.ph_wptr[ph], nw = L.ph_wptr[ph + 1] - w0;
-      k_mult_coop<64><<<unsigned(nw), 1024, L.cp_lds[0], s>>>(L.d_wrk + w0, L.d_mrec, L.d_f64, L.d_f32, L.d_slot_dof,
-                                                              L.sc, L.d_slot_q, L.d_ecol, L.d_eval, b, x, al,
-                                                              L.d_slot_mask, L.d_pcnt, err, 1u << 21);
+      k_mult_coop<64><<<unsigned(nw), 1024, L.cp_lds[0], s>>>(L.d_citem[0] + w0, L.d_f64, L.d_f32, L.d_slot_dof, L.sc,
+                                                              L.d_slot_q, L.d_ecol, L.d_eval, b, x, al, L.d_slot_mask,
+                                                              L.d_pcnt, err, 1u << 21);
     } else {
       const int w0 = L.ph_wptr2[ph], nw = L.ph_wptr2[ph + 1] - w0;
-      k_mult_coop<128><<<unsigned(nw), 1024, L.cp_lds[1], s>>>(L.d_wrk2 + w0, L.d_mrec, L.d_f64, L.d_f32,
-                                                               L.d_slot_dof, L.sc, L.d_slot_q, L.d_ecol, L.d_eval,
-                                                               b, x, al, L.d_slot_mask, L.d_pcnt + L.ph_exp.size(), err,
-                                                               1u << 21);
+      k_mult_coop<128><<<unsigned(nw), 1024, L.cp_lds[1], s>>>(L.d_citem[1] + w0, L.d_f64, L.d_f32, L.d_slot_dof,
+                                                               L.sc, L.d_slot_q, L.d_ecol, L.d_eval, b, x, al,
+                                                               L.d_slot_mask, L.d_pcnt, err, 1u << 21);
     }
     return;
   }
-  if (nt == 1 || nt == 2) nt = 1024;
   if (nt == 0) {
     const int w0 = L.ph_wptr[ph], nw = L.ph_wptr[ph + 1] - w0;
     k_mult_res<<<unsigned(nw), 256, 0, s>>>(L.d_wrk + w0, L.d_mrec, L.d_slot_dof, L.sc, L.d_slot_q, L.d_ecol,
