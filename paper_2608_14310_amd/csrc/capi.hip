@@ -1275,7 +1275,7 @@ cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table) {
   const bool timing = c.timing;
   c.timing = false;
   launch_clear_sweep_flags(c, s);
-  const int cand[6] = {256, 512, 1024, 0, 1, 2};
+  const int cand[7] = {256, 512, 1024, 0, 1, 2, 3};
   for (int l = 1; l < c.n_levels; ++l) {
     Level& L = c.lv[l];
     const int nph = int(L.ph_ptr.size()) - 1;
@@ -1341,8 +1341,9 @@ cav_status cav_set_tuning(cav_ctx ctx, const int32_t* table) {
   for (int l = 0; l < c.n_levels; ++l) {
     for (int bk = 0; bk < 4; ++bk) {
       const int v = table[5 * l + bk];
-      require(v == 256 || v == 512 || v == 1024 || v == 0 || v == 1 || v == 2, CAV_ERR_INVALID_ARG,
-              "bucket entries must be 256, 512, 1024, 0 (split form) or 1/2 (cooperative form, 64/128 rows)");
+      require(v == 256 || v == 512 || v == 1024 || (v >= 0 && v <= 3), CAV_ERR_INVALID_ARG,
+              "bucket entries must be 256, 512, 1024, 0 (split form), 1/2 (cooperative form, 64/128 rows) or 3 "
+              "(cooperative form with a shared residual)");
     }
     require(table[5 * l + 4] == 0 || table[5 * l + 4] == 1, CAV_ERR_INVALID_ARG, "the sweep entry must be 0 or 1");
   }

@@ -503,6 +503,89 @@ __global__ __launch_bounds__(1024) void k_mult_coop(const CoopItem* __restrict__
   }
 }
 
+// Cooperative form with a shared residual: as k_mult_coop<64>, but each of
+// the k workgroups of a patch forms only its own 64 residual rows and stores
+// them to the patch's slots of rbuf with device-coherent stores; after the
+// arrival barrier every workgroup reads the whole residual back with
+// device-coherent loads. Each workgroup's stores have completed (waitcnt)
+// before its arrival, so a workgroup that has seen all k arrivals reads the
+// final values. Rows, items and block order are those of k_mult_exp, so the
+// results equal it bit for bit.
+__global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict__ items,
+                                                     const double* __restrict__ a64, const float* __restrict__ a32,
+                                                     const int32_t* __restrict__ slot_dof, StencilCoef sc,
+                                                     const int2* __restrict__ slot_q, const int32_t* __restrict__ ecol,
+                                                     const double* __restrict__ eval, const double* __restrict__ b,
+                                                     double* __restrict__ x, double alpha,
+                                                     const uint8_t* __restrict__ smask, double* __restrict__ rbuf,
+                                                     unsigned long long* __restrict__ cnt, int* __restrict__ err,
+                                                     unsigned limit) {
+  constexpr int NT = 1024, RB = 64;
+  extern __shared__ double smem[];
+  __shared__ int s_ok;
+  const CoopItem it = items[blockIdx.x];
+  const MultRec rec = it.rec;
+  const int n = rec.n;
+  const int nb = (n + MX_CB - 1) / MX_CB;
+  const int k = (n + RB - 1) / RB;
+  const int r0 = it.r0, nr = min(RB, n - r0);
+  double* rp = smem;        // n
+  double* pp = smem + n;    // nb x RB block partials
+  const int32_t* dofs = slot_dof + rec.slot;
+  const int2* sq = slot_q + rec.slot;
+  const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
+  constexpr int NG = NT / MX_G;
+  if (k == 1) {
+    for (int rb = grp; rb < n; rb += NG * MX_R)
+      mx_residual_rows(dofs, sq, rb, NG, n, gl, sc, ecol, eval, b, x, [&](int rr, double r) { rp[rr] = r; });
+    __syncthreads();
+  } else {
+    double* rg = rbuf + rec.slot;
+    for (int rb = r0 + grp; rb < r0 + nr; rb += NG * MX_R)
+      mx_residual_rows(dofs, sq, rb, NG, r0 + nr, gl, sc, ecol, eval, b, x, [&](int rr, double r) {
+        __hip_atomic_store(rg + rr, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      });
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's stores and x loads have completed
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned long long old = __hip_atomic_fetch_add(cnt + it.cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long target = (old / unsigned(k) + 1) * unsigned(k);
+      int good = 1;
+      unsigned spins = 0;
+      while (__hip_atomic_load(cnt + it.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          atomicExch(err, 1);
+          good = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      s_ok = good;
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    for (int j = threadIdx.x; j < n; j += NT) rp[j] = __hip_atomic_load(rg + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+  }
+  {
+    auto ij = [nr, r0](int t, int& i, int& cb) {
+      i = r0 + t % nr;
+      cb = t / nr;
+    };
+    auto put = [pp, nr](int t, double v) { pp[(t / nr) * RB + t % nr] = v; };
+    if (rec.f32)
+      mx_gemv_pairs(a32, rec.fac, rp, n, nr * nb, NT, ij, put);
+    else
+      mx_gemv_pairs(a64, rec.fac, rp, n, nr * nb, NT, ij, put);
+  }
+  __syncthreads();
+  for (int ii = threadIdx.x; ii < nr; ii += NT) {
+    double s = 0.0;
+    for (int cb = 0; cb < nb; ++cb) s += pp[cb * RB + ii];
+    if (!smask || smask[rec.slot + r0 + ii]) x[dofs[r0 + ii]] += alpha * s;
+  }
+}
+
 // One colour phase of the shared standard patches: cells with
 // (i + 3 j) mod 8 == colour and no E_E entries solve their 5x5 patch from the
 // current residual and update x.
@@ -694,6 +777,7 @@ bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t
 // workgroups of its launch, so inside a captured graph (batched systems run
 // concurrently) the one-workgroup form runs instead, with the same results.
 static int phase_form(const Ctx& c, const Level& L, int nt) {
+  if (nt == 3 && (c.capturing || !c.d_bar || !L.d_pcnt || !L.d_citem[0] || !L.d_delta)) return 1024;
   if ((nt == 1 || nt == 2) && (c.capturing || !c.d_bar || !L.d_pcnt || !L.d_citem[nt - 1])) return 1024;
   return nt;
 }
@@ -719,7 +803,7 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
     double bytes = 0.0;
     for (int ph = 0; ph < nph; ++ph) {
       const int nt = phase_form(c, L, L.mx_nt[mx_bucket(L.ph_maxn[ph])]);
-      const int kind = (nt == 1 || nt == 2) ? 1 : 0;
+      const int kind = (nt == 1 || nt == 2 || nt == 3) ? 1 : 0;
       if (kind != open) {
         if (open >= 0) timing_end(c, s, bytes, cnt);
         timing_begin(c, s, kind);
@@ -741,6 +825,14 @@ void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double
   const int a = L.ph_ptr[ph], cnt = L.ph_ptr[ph + 1] - a;
   const unsigned g = unsigned(cnt);
   nt = phase_form(c, L, nt);
+  if (nt == 3) {
+    const int w0 = L.ph_wptr[ph], nw = L.ph_wptr[ph + 1] - w0;
+    k_mult_coopr<<<unsigned(nw), 1024, L.cp_lds[0], s>>>(L.d_citem[0] + w0, L.d_f64, L.d_f32, L.d_slot_dof, L.sc,
+                                                         L.d_slot_q, L.d_ecol, L.d_eval, b, x, level_alpha(c, L),
+                                                         L.d_slot_mask, L.d_delta, L.d_pcnt,
+                                                         reinterpret_cast<int*>(c.d_bar + 1), 1u << 21);
+    return;
+  }
   if (nt == 1 || nt == 2) {
     int* err = reinterpret_cast<int*>(c.d_bar + 1);
     const double al = level_alpha(c, L);
@@ -788,7 +880,7 @@ void prepare_mult_smoother(size_t lds) {
   for (const void* f : {reinterpret_cast<const void*>(k_mult_exp<256>), reinterpret_cast<const void*>(k_mult_exp<512>),
                         reinterpret_cast<const void*>(k_mult_exp<1024>), reinterpret_cast<const void*>(k_mult_gemv),
                         reinterpret_cast<const void*>(k_mult_sweep<1024>), reinterpret_cast<const void*>(k_mult_coop<64>),
-                        reinterpret_cast<const void*>(k_mult_coop<128>)})
+                        reinterpret_cast<const void*>(k_mult_coop<128>), reinterpret_cast<const void*>(k_mult_coopr)})
     CAV_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   set_to = lds;
 }

@@ -178,7 +178,7 @@ def test_full_size_beam512(cav):
     # workgroups) give the same V-cycle bit for bit at this size
     print("[full size] beam512: cooperative phase forms", flush=True)
     z0 = g.vcycle(_t(s.b)).cpu().numpy()
-    for form in (1, 2):
+    for form in (1, 2, 3):
         table = np.full((s.n_levels, 5), 1024, np.int32)
         table[:, 4] = 0
         table[:, 2:4] = form
