@@ -287,12 +287,12 @@ def main():
     ap.add_argument("--kappa-b", type=float, default=1e-2)
     ap.add_argument("--stiff-sweep", type=float, nargs="*", default=[1.0, 1e2])
     ap.add_argument("--tune", default="default",
-                    choices=["default", "auto", "exp1024", "split", "sweep", "coop64", "coop128", "coopr"],
-                    help="phase-kernel table of the timed steps: the library's default (one 1024-thread "
-                         "workgroup per patch for phases whose largest patch has <= 128 rows, the cooperative "
-                         "64-row form above), autotuned, one workgroup per patch everywhere (exp1024), the split "
-                         "form, the one-launch sweep, or the cooperative form for the larger buckets; the "
-                         "autotuned table is reported after them")
+                    choices=["default", "auto", "exp1024", "split", "sweep", "coop64", "coop128", "coopr", "coopr1", "coopr0"],
+                    help="phase-kernel table of the timed steps: the library's default (the cooperative form "
+                         "with a shared residual for every phase), autotuned, one workgroup per patch everywhere "
+                         "(exp1024), the split form, the one-launch sweep, or a cooperative form for phases with "
+                         "patches over 128 rows (coopr1: over 64 rows, coopr0: all); the autotuned table is "
+                         "reported after them")
     ap.add_argument("--no-other-precision", action="store_true")
     ap.add_argument("--no-autotune-report", action="store_true",
                     help="skip the autotuner run reported beside the timed table")
@@ -366,10 +366,14 @@ def main():
     elif a.tune == "exp1024":
         table = np.full((s.n_levels, 5), 1024, dtype=np.int32)
         table[:, 4] = 0
-    elif a.tune in ("coop64", "coop128", "coopr"):
+    elif a.tune in ("coop64", "coop128", "coopr", "coopr1", "coopr0"):
         table = np.full((s.n_levels, 5), 1024, dtype=np.int32)
         table[:, 4] = 0
-        table[:, 2:4] = {"coop64": 1, "coop128": 2, "coopr": 3}[a.tune]
+        table[:, 2:4] = {"coop64": 1, "coop128": 2, "coopr": 3, "coopr1": 3, "coopr0": 3}[a.tune]
+        if a.tune in ("coopr1", "coopr0"):
+            table[:, 1] = 3
+        if a.tune == "coopr0":
+            table[:, 0] = 3
     for _ in range(a.warmup):
         one_step(a.precision)
     torch.cuda.synchronize()
@@ -384,7 +388,7 @@ def main():
     co_ms = sum(r["kt"]["coop_ms"] for r in runs)
     all_ms = sum(r["kt"]["ms"] for r in runs)
     if co_ms > all_ms - co_ms:
-        kernel = {"coop128": "k_mult_coop<128>", "coopr": "k_mult_coopr"}.get(a.tune, "k_mult_coop<64>")
+        kernel = {"coop64": "k_mult_coop<64>", "coop128": "k_mult_coop<128>"}.get(a.tune, "k_mult_coopr")
         kb_bytes = sum(r["kt"]["coop_bytes"] for r in runs)
         kb_ms = co_ms
         kb_launch = sum(r["kt"]["coop_launches"] for r in runs)

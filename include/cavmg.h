@@ -237,10 +237,13 @@ cav_status cav_batch_solve(cav_ctx* ctxs, int32_t n_sys, const double* const* b,
  * workgroups in two launches, or (entries 1 and 2) the cooperative form: one
  * launch in which a patch of n rows gets ceil(n / 64) or ceil(n / 128)
  * workgroups that each form all residual rows, meet at a bounded barrier on a
- * per-patch counter, and apply 64 or 128 rows of the inverse (inside a
- * captured graph the one-workgroup form runs instead). Alternatively the
- * whole sweep of a level runs in one cooperative launch with a bounded grid
- * barrier after each phase.
+ * per-patch counter, and apply 64 or 128 rows of the inverse, or (entry 3,
+ * the default for every bucket) the cooperative form with a shared residual:
+ * each of the ceil(n / 64) workgroups forms only its own 64 residual rows,
+ * exchanged through device-coherent stores and loads after the barrier
+ * (inside a captured graph the one-workgroup form runs instead of any
+ * cooperative form). Alternatively the whole sweep of a level runs in one
+ * cooperative launch with a bounded grid barrier after each phase.
  * cav_autotune times the choices on the context's own phases, per smoothed
  * level and per size bucket of a phase's largest patch (<= 64, <= 128,
  * <= 256, larger), then per level per-phase launches against the one-launch

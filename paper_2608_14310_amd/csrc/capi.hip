@@ -71,7 +71,7 @@ void free_level(Ctx& c, Level& L) {
                   (void*)L.d_f64, (void*)L.d_f32, (void*)L.d_b, (void*)L.d_x, (void*)L.d_r, (void*)L.d_z,
                   (void*)L.d_part, (void*)L.d_mrec, (void*)L.d_wrk, (void*)L.d_ph_ptr, (void*)L.d_slot_mask,
                   (void*)L.d_citem[0], (void*)L.d_citem[1], (void*)L.d_pcnt,
-                  (void*)L.d_slot_q})
+                  (void*)L.d_slot_q, (void*)L.d_irow})
     dev_free(c, p);
   L = Level();
 }
@@ -82,7 +82,7 @@ void free_patches(Ctx& c, Level& L) {
                    (void**)&L.d_rec64, (void**)&L.d_rec32, (void**)&L.d_f64, (void**)&L.d_f32,
                    (void**)&L.d_mrec, (void**)&L.d_wrk, (void**)&L.d_ph_ptr, (void**)&L.d_slot_mask,
                    (void**)&L.d_citem[0], (void**)&L.d_citem[1], (void**)&L.d_pcnt,
-                   (void**)&L.d_slot_q}) {
+                   (void**)&L.d_slot_q, (void**)&L.d_irow}) {
     dev_free(c, *p);
     *p = nullptr;
   }

@@ -102,8 +102,9 @@ struct Level {
   std::vector<int32_t> ph_maxn;           // largest patch of each phase
   int32_t smoother = -1;                  // per-level smoother kind (-1: the context's)
   double alpha = 0.0;                     // its damping when smoother >= 0
-  int32_t mx_nt[4] = {1024, 1024, 1, 1};        // per size bucket: 256/512/1024 threads, 0 = split form,
-                                                // 1/2 = cooperative form with 64/128 rows per workgroup (autotuned)
+  int32_t mx_nt[4] = {3, 3, 3, 3};              // per size bucket: 256/512/1024 threads, 0 = split form,
+                                                // 1/2 = cooperative form with 64/128 rows per workgroup,
+                                                // 3 = cooperative form with a shared residual (autotuned)
   int32_t* d_ph_ptr = nullptr;            // device copy of ph_ptr (persistent sweep)
   bool persistent = false;                // whole sweep in one cooperative launch (autotuned)
   int sweep_grid = 0;                     // its workgroups (0: not yet computed)
@@ -116,6 +117,7 @@ struct Level {
   // (records of the 64-row form, then of the 128-row form), and its LDS
   std::vector<int32_t> ph_wptr2;
   CoopItem* d_citem[2] = {nullptr, nullptr};
+  int4* d_irow = nullptr;                 // 64 rows per 64-row item: unknown (-1 past the patch), E_E range
   unsigned long long* d_pcnt = nullptr;
   size_t cp_lds[2] = {0, 0};
 

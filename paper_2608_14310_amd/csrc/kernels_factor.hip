@@ -728,7 +728,8 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
       }
     // LDS of the phase kernel: residual (n doubles) and 16-column block partials
     const int64_t mn = std::max<int32_t>(L.mrec_max_n, 1);
-    L.mx_lds = size_t(mn + ((mn + 15) / 16) * mn) * sizeof(double);
+    // residual rows, pre-update values, block partials (doubles), then the unknowns (ints)
+    L.mx_lds = size_t(2 * mn + ((mn + 15) / 16) * mn) * sizeof(double) + size_t(mn) * sizeof(int32_t);
     prepare_mult_smoother(L.mx_lds);
     if (L.d_mrec) dev_free(c, L.d_mrec);
     L.d_mrec = upload(c, mrec);
@@ -756,6 +757,19 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
       }
       if (L.d_citem[f]) dev_free(c, L.d_citem[f]);
       L.d_citem[f] = upload(c, ci);
+      if (f == 0) {
+        // the rows of every 64-row item, at item * 64 + row
+        const int64_t nv = 2 * int64_t(L.N) * L.N;
+        std::vector<int4> ir(ci.size() * 64, make_int4(-1, 0, 0, 0));
+        for (size_t w = 0; w < ci.size(); ++w)
+          for (int q = 0; q < 64 && ci[w].r0 + q < ci[w].rec.n; ++q) {
+            const int32_t d = L.slot_dof_h[size_t(ci[w].rec.slot + ci[w].r0 + q)];
+            const bool ee = d < nv;
+            ir[w * 64 + q] = make_int4(d, ee ? int(L.ee.rowptr[d]) : 0, ee ? int(L.ee.rowptr[d + 1]) : 0, 0);
+          }
+        if (L.d_irow) dev_free(c, L.d_irow);
+        L.d_irow = upload(c, ir);
+      }
     }
     // two counters per record, one per row-block size: a counter must only
     // ever see rounds of its own k = ceil(n / rows)
@@ -771,8 +785,8 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
       CAV_HIP(hipMemsetAsync(c.d_bar, 0, 2 * sizeof(unsigned long long), s));
     }
     L.sp_lds = size_t(mn + ((mn + 15) / 16) * 64) * sizeof(double);
-    L.cp_lds[0] = L.sp_lds;
-    L.cp_lds[1] = size_t(mn + ((mn + 15) / 16) * 128) * sizeof(double);
+    L.cp_lds[0] = size_t(mn + 64 + ((mn + 15) / 16) * 64) * sizeof(double) + 64 * sizeof(int32_t);
+    L.cp_lds[1] = size_t(mn + 128 + ((mn + 15) / 16) * 128) * sizeof(double) + 128 * sizeof(int32_t);
     prepare_mult_smoother(L.cp_lds[1]);
   }
   L.d_rec64 = upload(c, o64);

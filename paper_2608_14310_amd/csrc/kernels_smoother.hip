@@ -184,33 +184,31 @@ constexpr int MX_RB = 64;   // rows per workgroup in the split phase kernels
 // value) does not depend on how rows are grouped, which keeps every phase
 // kernel bit-identical.
 constexpr int MX_R = 4;
-template <typename Emit>
-__device__ __forceinline__ void mx_residual_rows(const int32_t* __restrict__ dofs, const int2* __restrict__ sq, int r0,
-                                                 int step, int r1, int gl, StencilCoef sc,
+template <typename Src, typename Emit>
+__device__ __forceinline__ void mx_residual_rows(Src src, int r0, int step, int r1, int gl, StencilCoef sc,
                                                  const int32_t* __restrict__ ecol, const double* __restrict__ eval,
                                                  const double* __restrict__ b, const double* __restrict__ x,
                                                  Emit emit) {
   int64_t d[MX_R];
   int q0[MX_R], q1[MX_R];
-  // the unknown and its E_E entry range come from per-slot arrays, so both
-  // loads are in flight together
+  // src(rr) = {unknown (or -1), E_E entry range}: one load per row
 #pragma unroll
   for (int u = 0; u < MX_R; ++u) {
     const int rr = r0 + u * step;
-    const bool ok = rr < r1;
-    d[u] = ok ? int64_t(dofs[rr]) : int64_t(-1);
-    const int2 q = ok ? sq[rr] : make_int2(0, 0);
-    q0[u] = q.x;
-    q1[u] = q.y;
+    const int4 q = rr < r1 ? src(rr) : make_int4(-1, 0, 0, 0);
+    d[u] = q.x;
+    q0[u] = q.y;
+    q1[u] = q.z;
   }
-  // the stencil part and b of each row (lane 0) are loaded now, beside the
-  // E_E entries, and added where the row's sum needs them
-  double stv[MX_R], bv[MX_R];
+  // the stencil part, b and the unknown's own value (lane 0) are loaded now,
+  // beside the E_E entries; the sum adds them where it always has
+  double stv[MX_R], bv[MX_R], xd[MX_R];
 #pragma unroll
   for (int u = 0; u < MX_R; ++u) {
     const bool own = gl == 0 && d[u] >= 0;
     stv[u] = own ? krow(d[u], x, sc, nullptr, nullptr, nullptr) : 0.0;
     bv[u] = own ? b[d[u]] : 0.0;
+    xd[u] = own ? x[d[u]] : 0.0;
   }
   int rounds = 0;
 #pragma unroll
@@ -246,9 +244,19 @@ __device__ __forceinline__ void mx_residual_rows(const int32_t* __restrict__ dof
     if (gl == 0 && d[u] >= 0) acc[u] += stv[u];
 #pragma unroll
     for (int o = MX_G / 2; o > 0; o >>= 1) acc[u] += __shfl_down(acc[u], o, MX_G);
-    if (gl == 0 && d[u] >= 0) emit(r0 + u * step, bv[u] - acc[u]);
+    if (gl == 0 && d[u] >= 0) emit(r0 + u * step, bv[u] - acc[u], int32_t(d[u]), xd[u]);
   }
 }
+
+// Row source over a patch's slots: the unknown and its E_E entry range.
+struct SlotRows {
+  const int32_t* dofs;
+  const int2* sq;
+  __device__ __forceinline__ int4 operator()(int rr) const {
+    const int2 q = sq[rr];
+    return make_int4(dofs[rr], q.x, q.y, 0);
+  }
+};
 
 // GEMV item (row i, column block cb) of the stored inverse (column-major n x n)
 // against r: s0 over even and s1 over odd columns of the block, then s0 + s1.
@@ -319,14 +327,19 @@ __device__ __forceinline__ void mx_patch(const MultRec& rec, double* smem, const
                                          const uint8_t* __restrict__ smask) {
   const int n = rec.n;
   const int nb = (n + MX_CB - 1) / MX_CB;
-  double* rp = smem;             // n
-  double* pp = smem + n;         // nb x n block partials
-  const int32_t* dofs = slot_dof + rec.slot;
-  const int2* sq = slot_q + rec.slot;
+  double* rp = smem;             // n residual rows
+  double* xo = smem + n;         // n values of the unknowns before the update
+  double* pp = smem + 2 * n;     // nb x n block partials
+  int32_t* dd = reinterpret_cast<int32_t*>(pp + int64_t(nb) * n);  // n unknowns
+  const SlotRows src{slot_dof + rec.slot, slot_q + rec.slot};
   const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
   constexpr int NG = NT / MX_G;
   for (int rb = grp; rb < n; rb += NG * MX_R)
-    mx_residual_rows(dofs, sq, rb, NG, n, gl, sc, ecol, eval, b, x, [&](int rr, double r) { rp[rr] = r; });
+    mx_residual_rows(src, rb, NG, n, gl, sc, ecol, eval, b, x, [&](int rr, double r, int32_t d, double xv) {
+      rp[rr] = r;
+      xo[rr] = xv;
+      dd[rr] = d;
+    });
   __syncthreads();
   {
     auto ij = [n](int t, int& i, int& cb) {
@@ -343,7 +356,7 @@ __device__ __forceinline__ void mx_patch(const MultRec& rec, double* smem, const
   for (int i = threadIdx.x; i < n; i += NT) {
     double s = 0.0;
     for (int cb = 0; cb < nb; ++cb) s += pp[int64_t(cb) * n + i];
-    if (!smask || smask[rec.slot + i]) x[dofs[i]] += alpha * s;
+    if (!smask || smask[rec.slot + i]) x[dd[i]] = xo[i] + alpha * s;
   }
 }
 
@@ -378,13 +391,12 @@ __global__ __launch_bounds__(256) void k_mult_res(const int2* __restrict__ items
   const int2 it = items[blockIdx.x];
   const MultRec rec = recs[it.x];
   const int r0 = it.y, r1 = min(rec.n, it.y + MX_RB);
-  const int32_t* dofs = slot_dof + rec.slot;
-  const int2* sq = slot_q + rec.slot;
+  const SlotRows src{slot_dof + rec.slot, slot_q + rec.slot};
   const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
   constexpr int NG = 256 / MX_G;
   for (int rb = r0 + grp; rb < r1; rb += NG * MX_R)
-    mx_residual_rows(dofs, sq, rb, NG, r1, gl, sc, ecol, eval, b, x,
-                     [&](int rr, double r) { rbuf[rec.slot + rr] = r; });
+    mx_residual_rows(src, rb, NG, r1, gl, sc, ecol, eval, b, x,
+                     [&](int rr, double r, int32_t, double) { rbuf[rec.slot + rr] = r; });
 }
 
 __global__ __launch_bounds__(256) void k_mult_gemv(const int2* __restrict__ items, const MultRec* __restrict__ recs,
@@ -453,14 +465,21 @@ __global__ __launch_bounds__(1024) void k_mult_coop(const CoopItem* __restrict__
   const int nb = (n + MX_CB - 1) / MX_CB;
   const int k = (n + RB - 1) / RB;
   const int r0 = it.r0, nr = min(RB, n - r0);
-  double* rp = smem;        // n
-  double* pp = smem + n;    // nb x RB block partials
-  const int32_t* dofs = slot_dof + rec.slot;
-  const int2* sq = slot_q + rec.slot;
+  double* rp = smem;             // n residual rows
+  double* xo = smem + n;         // RB values of this item's unknowns before the update
+  double* pp = xo + RB;          // nb x RB block partials
+  int32_t* dd = reinterpret_cast<int32_t*>(pp + nb * RB);  // RB unknowns
+  const SlotRows src{slot_dof + rec.slot, slot_q + rec.slot};
   const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
   constexpr int NG = NT / MX_G;
   for (int rb = grp; rb < n; rb += NG * MX_R)
-    mx_residual_rows(dofs, sq, rb, NG, n, gl, sc, ecol, eval, b, x, [&](int rr, double r) { rp[rr] = r; });
+    mx_residual_rows(src, rb, NG, n, gl, sc, ecol, eval, b, x, [&](int rr, double r, int32_t d, double xv) {
+      rp[rr] = r;
+      if (rr >= r0 && rr < r0 + nr) {
+        xo[rr - r0] = xv;
+        dd[rr - r0] = d;
+      }
+    });
   __syncthreads();
   if (k > 1) {
     if (threadIdx.x == 0) {
@@ -499,7 +518,7 @@ __global__ __launch_bounds__(1024) void k_mult_coop(const CoopItem* __restrict__
   for (int ii = threadIdx.x; ii < nr; ii += NT) {
     double s = 0.0;
     for (int cb = 0; cb < nb; ++cb) s += pp[cb * RB + ii];
-    if (!smask || smask[rec.slot + r0 + ii]) x[dofs[r0 + ii]] += alpha * s;
+    if (!smask || smask[rec.slot + r0 + ii]) x[dd[ii]] = xo[ii] + alpha * s;
   }
 }
 
@@ -512,38 +531,47 @@ __global__ __launch_bounds__(1024) void k_mult_coop(const CoopItem* __restrict__
 // final values. Rows, items and block order are those of k_mult_exp, so the
 // results equal it bit for bit.
 __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict__ items,
-                                                     const double* __restrict__ a64, const float* __restrict__ a32,
-                                                     const int32_t* __restrict__ slot_dof, StencilCoef sc,
-                                                     const int2* __restrict__ slot_q, const int32_t* __restrict__ ecol,
-                                                     const double* __restrict__ eval, const double* __restrict__ b,
-                                                     double* __restrict__ x, double alpha,
-                                                     const uint8_t* __restrict__ smask, double* __restrict__ rbuf,
-                                                     unsigned long long* __restrict__ cnt, int* __restrict__ err,
-                                                     unsigned limit) {
+                                                     const int4* __restrict__ irow, const double* __restrict__ a64,
+                                                     const float* __restrict__ a32, StencilCoef sc,
+                                                     const int32_t* __restrict__ ecol, const double* __restrict__ eval,
+                                                     const double* __restrict__ b, double* __restrict__ x,
+                                                     double alpha, const uint8_t* __restrict__ smask,
+                                                     double* __restrict__ rbuf, unsigned long long* __restrict__ cnt,
+                                                     int* __restrict__ err, unsigned limit) {
   constexpr int NT = 1024, RB = 64;
   extern __shared__ double smem[];
   __shared__ int s_ok;
+  // this item's 64 rows (unknown, E_E range; unknown -1 past the patch) sit at
+  // a fixed place, so their loads do not wait for the item record
+  const int4* rows = irow + int64_t(blockIdx.x) * RB;
   const CoopItem it = items[blockIdx.x];
   const MultRec rec = it.rec;
   const int n = rec.n;
   const int nb = (n + MX_CB - 1) / MX_CB;
   const int k = (n + RB - 1) / RB;
   const int r0 = it.r0, nr = min(RB, n - r0);
-  double* rp = smem;        // n
-  double* pp = smem + n;    // nb x RB block partials
-  const int32_t* dofs = slot_dof + rec.slot;
-  const int2* sq = slot_q + rec.slot;
+  double* rp = smem;             // n residual rows
+  double* xo = smem + n;         // RB values of this item's unknowns before the update
+  double* pp = xo + RB;          // nb x RB block partials
+  int32_t* dd = reinterpret_cast<int32_t*>(pp + nb * RB);  // RB unknowns
   const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
   constexpr int NG = NT / MX_G;
+  auto src = [rows](int q) { return rows[q]; };
   if (k == 1) {
-    for (int rb = grp; rb < n; rb += NG * MX_R)
-      mx_residual_rows(dofs, sq, rb, NG, n, gl, sc, ecol, eval, b, x, [&](int rr, double r) { rp[rr] = r; });
+    for (int rb = grp; rb < RB; rb += NG * MX_R)
+      mx_residual_rows(src, rb, NG, RB, gl, sc, ecol, eval, b, x, [&](int q, double r, int32_t d, double xv) {
+        rp[q] = r;
+        xo[q] = xv;
+        dd[q] = d;
+      });
     __syncthreads();
   } else {
-    double* rg = rbuf + rec.slot;
-    for (int rb = r0 + grp; rb < r0 + nr; rb += NG * MX_R)
-      mx_residual_rows(dofs, sq, rb, NG, r0 + nr, gl, sc, ecol, eval, b, x, [&](int rr, double r) {
-        __hip_atomic_store(rg + rr, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double* rg = rbuf + rec.slot + r0;
+    for (int rb = grp; rb < RB; rb += NG * MX_R)
+      mx_residual_rows(src, rb, NG, RB, gl, sc, ecol, eval, b, x, [&](int q, double r, int32_t d, double xv) {
+        __hip_atomic_store(rg + q, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        xo[q] = xv;
+        dd[q] = d;
       });
     __builtin_amdgcn_s_waitcnt(0);   // this wave's stores and x loads have completed
     __syncthreads();
@@ -564,7 +592,8 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
     }
     __syncthreads();
     if (!s_ok) return;
-    for (int j = threadIdx.x; j < n; j += NT) rp[j] = __hip_atomic_load(rg + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double* ra = rbuf + rec.slot;
+    for (int j = threadIdx.x; j < n; j += NT) rp[j] = __hip_atomic_load(ra + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
   }
   {
@@ -582,7 +611,7 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
   for (int ii = threadIdx.x; ii < nr; ii += NT) {
     double s = 0.0;
     for (int cb = 0; cb < nb; ++cb) s += pp[cb * RB + ii];
-    if (!smask || smask[rec.slot + r0 + ii]) x[dofs[r0 + ii]] += alpha * s;
+    if (!smask || smask[rec.slot + r0 + ii]) x[dd[ii]] = xo[ii] + alpha * s;
   }
 }
 
@@ -777,7 +806,7 @@ bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t
 // workgroups of its launch, so inside a captured graph (batched systems run
 // concurrently) the one-workgroup form runs instead, with the same results.
 static int phase_form(const Ctx& c, const Level& L, int nt) {
-  if (nt == 3 && (c.capturing || !c.d_bar || !L.d_pcnt || !L.d_citem[0] || !L.d_delta)) return 1024;
+  if (nt == 3 && (c.capturing || !c.d_bar || !L.d_pcnt || !L.d_citem[0] || !L.d_irow || !L.d_delta)) return 1024;
   if ((nt == 1 || nt == 2) && (c.capturing || !c.d_bar || !L.d_pcnt || !L.d_citem[nt - 1])) return 1024;
   return nt;
 }
@@ -827,8 +856,8 @@ void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double
   nt = phase_form(c, L, nt);
   if (nt == 3) {
     const int w0 = L.ph_wptr[ph], nw = L.ph_wptr[ph + 1] - w0;
-    k_mult_coopr<<<unsigned(nw), 1024, L.cp_lds[0], s>>>(L.d_citem[0] + w0, L.d_f64, L.d_f32, L.d_slot_dof, L.sc,
-                                                         L.d_slot_q, L.d_ecol, L.d_eval, b, x, level_alpha(c, L),
+    k_mult_coopr<<<unsigned(nw), 1024, L.cp_lds[0], s>>>(L.d_citem[0] + w0, L.d_irow + int64_t(w0) * 64, L.d_f64,
+                                                         L.d_f32, L.sc, L.d_ecol, L.d_eval, b, x, level_alpha(c, L),
                                                          L.d_slot_mask, L.d_delta, L.d_pcnt,
                                                          reinterpret_cast<int*>(c.d_bar + 1), 1u << 21);
     return;
