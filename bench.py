@@ -5,10 +5,11 @@ length 0.4, ds = h/2, bending kappa_b = 1e-2, springs 1e4, 5-level V(1,1)):
 build_operator -> build_cav_patches -> factor_patches -> fgmres_solve to 1e-10.
 `value` is the mean wall time per step (T_total, ms, lower is better);
 `t_solve_ms` is the solve alone. Inputs (markers, RHS on the device) are
-prepared before the timed region; the phase kernels use 1024 threads per
-patch (the autotuned table is measured and reported after the timed steps). The dominant kernel (explicit-patch phase kernel of the
-multiplicative smoother) is timed live with HIP events on the library stream
-around each sweep's run of phase launches.
+prepared before the timed region; the phase kernels follow the library's
+default table (the cooperative form with a shared residual; the autotuned
+table is measured and reported after the timed steps). The dominant kernel
+(explicit-patch phase kernel of the multiplicative smoother) is timed live
+with HIP events on the library stream around each run of phase launches.
 After the timed steps: the other precision on the same system, the stiffer
 kappa_b values (reported with their iteration counts), the learned stage
 (trained on 256^2 pairs, judged on this solve), the batched mix of independent

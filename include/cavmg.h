@@ -246,10 +246,11 @@ cav_status cav_batch_solve(cav_ctx* ctxs, int32_t n_sys, const double* const* b,
  * cooperative launch with a bounded grid barrier after each phase.
  * cav_autotune times the choices on the context's own phases, per smoothed
  * level and per size bucket of a phase's largest patch (<= 64, <= 128,
- * <= 256, larger), then per level per-phase launches against the one-launch
- * sweep, `reps` repetitions each, keeps the fastest, and writes the table
- * (5 ints per level, levels 0 .. n_levels-1, level 0 unused: 4 bucket
- * entries, then 1 for the one-launch sweep) to `table` (optional). Results do
+ * <= 256, larger), `reps` repetitions each, keeps the fastest, and writes the
+ * table (5 ints per level, levels 0 .. n_levels-1, level 0 unused: 4 bucket
+ * entries, then 1 for the one-launch sweep, which the autotuner leaves at 0:
+ * a process's first cooperative launch slows later concurrent graph
+ * launches, and the sweep never won) to `table` (optional). Results do
  * not depend on the choice (every patch's and cell's arithmetic is the same).
  * Uses the levels' scratch vectors; synchronises. A barrier wait that times
  * out (cooperative phase form or one-launch sweep) leaves x unwritten from

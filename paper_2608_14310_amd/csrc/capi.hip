@@ -1307,21 +1307,13 @@ cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table) {
       }
       L.mx_nt[bk] = pick;
     }
-    // whole sweep: per-phase launches with the table above, or one cooperative launch
-    float t_sweep[2] = {0.f, 0.f};
-    for (int pers = 0; pers < 2; ++pers) {
-      L.persistent = pers != 0;
-      launch_mult_smoother(c, L, L.d_b, L.d_x, false, s);  // warm-up
-      CAV_HIP(hipEventRecord(e0, s));
-      for (int r = 0; r < reps; ++r) launch_mult_smoother(c, L, L.d_b, L.d_x, false, s);
-      CAV_HIP(hipEventRecord(e1, s));
-      CAV_HIP(hipEventSynchronize(e1));
-      CAV_HIP(hipGetLastError());
-      CAV_HIP(hipEventElapsedTime(&t_sweep[pers], e0, e1));
-    }
-    check_sweep_flags(c);
-    L.persistent = t_sweep[1] < t_sweep[0];
+    // The one-launch sweep (a cooperative launch) is not a candidate: it never
+    // beat per-phase launches here, and a process's first cooperative launch
+    // halves the concurrency of later graph launches on other streams. It
+    // stays available through cav_set_tuning.
+    L.persistent = false;
   }
+  check_sweep_flags(c);
   c.timing = timing;
   ++c.generation;
   if (table)
