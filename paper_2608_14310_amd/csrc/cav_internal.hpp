@@ -120,6 +120,8 @@ struct Level {
   int4* d_irow = nullptr;                 // 64 rows per 64-row item: unknown (-1 past the patch), E_E range
   unsigned long long* d_pcnt = nullptr;
   size_t cp_lds[2] = {0, 0};
+  int cr_pf = 0;                          // shared-residual form: LDS bytes for the prefetched GEMV slice
+  size_t cr_lds = 0;                      // and its whole dynamic LDS
 
   // factors
   bool factored = false;

@@ -787,7 +787,18 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
     L.sp_lds = size_t(mn + ((mn + 15) / 16) * 64) * sizeof(double);
     L.cp_lds[0] = size_t(mn + 64 + ((mn + 15) / 16) * 64) * sizeof(double) + 64 * sizeof(int32_t);
     L.cp_lds[1] = size_t(mn + 128 + ((mn + 15) / 16) * 128) * sizeof(double) + 128 * sizeof(int32_t);
-    prepare_mult_smoother(L.cp_lds[1]);
+    // shared-residual form: room for a 64-row slice of the largest inverse in
+    // FP64 (at most 128 KiB, within 159 KiB of LDS); patches whose slice does
+    // not fit read the inverse from global memory instead
+    {
+      const int64_t rest = int64_t(L.cp_lds[0]);
+      int64_t pf = std::min<int64_t>(int64_t(64) * mn * 8, 128 * 1024);
+      pf = std::min<int64_t>(pf, 159 * 1024 - rest);
+      pf = pf >= 64 * 8 * 8 ? (pf / 256) * 256 : 0;
+      L.cr_pf = int(pf);
+      L.cr_lds = size_t(pf + rest);
+    }
+    prepare_mult_smoother(std::max(L.cp_lds[1], L.cr_lds));
   }
   L.d_rec64 = upload(c, o64);
   L.d_rec32 = upload(c, o32);

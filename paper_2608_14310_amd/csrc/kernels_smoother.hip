@@ -522,6 +522,51 @@ __global__ __launch_bounds__(1024) void k_mult_coop(const CoopItem* __restrict__
   }
 }
 
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Direct-to-LDS copy of rows r0 .. r0+63 of every column of a patch inverse
+// (column-major, n x n, elements of S bytes at `col0`) into `slice`, column j
+// at slice + j * 64 * S bytes. One dword per lane per instruction lands at
+// the instruction's LDS base + lane * 4; rows at or past n read the column's
+// first element instead (kept in bounds, never used). Waves w0 .. 15 issue
+// the instructions round robin; the caller waits (vmcnt) before the slice is
+// read. A wave's loads complete in order, so loads issued after the copy wait
+// for it too.
+template <int S>
+__device__ __forceinline__ void mx_prefetch_slice(const unsigned char* __restrict__ col0, int n, int r0,
+                                                  unsigned char* slice, int w0) {
+  constexpr int PER_COL = 64 * S / 256;   // instructions per column (2 for FP64, 1 for FP32)
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave < w0) return;
+  const int total = n * PER_COL;
+  for (int q = wave - w0; q < total; q += 16 - w0) {
+    const int j = q / PER_COL, h = q % PER_COL;
+    const int dword = h * 64 + lane;                 // dword index inside the column's 64-row slot
+    const int row = r0 + dword / (S / 4);
+    const int part = dword % (S / 4);
+    const int64_t el = int64_t(j) * n + (row < n ? row : 0);
+    const unsigned char* g = col0 + el * S + part * 4;
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(g), (lds_ptr_t)(slice + int64_t(j) * 64 * S + h * 256),
+                                     4, 0, 0);
+  }
+}
+
+// GEMV items of one workgroup's rows from the LDS slice: the same items,
+// pairing and arithmetic as mx_gemv_pairs (only the loads differ).
+template <typename T, typename IJ, typename Put>
+__device__ __forceinline__ void mx_gemv_lds(const T* slice, int r0, const double* __restrict__ rp, int n, int count,
+                                            int stride, IJ ij, Put put) {
+  for (int t = threadIdx.x; t < count; t += stride) {
+    int i, cb;
+    ij(t, i, cb);
+    const int j0 = cb * MX_CB, w = min(MX_CB, n - j0);
+    T m[MX_CB];
+#pragma unroll
+    for (int jj = 0; jj < MX_CB; ++jj) m[jj] = jj < w ? slice[(j0 + jj) * 64 + (i - r0)] : T(0);
+    put(t, mx_dot_item(m, rp, n, cb));
+  }
+}
+
 // Cooperative form with a shared residual: as k_mult_coop<64>, but each of
 // the k workgroups of a patch forms only its own 64 residual rows and stores
 // them to the patch's slots of rbuf with device-coherent stores; after the
@@ -537,7 +582,7 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
                                                      const double* __restrict__ b, double* __restrict__ x,
                                                      double alpha, const uint8_t* __restrict__ smask,
                                                      double* __restrict__ rbuf, unsigned long long* __restrict__ cnt,
-                                                     int* __restrict__ err, unsigned limit) {
+                                                     int* __restrict__ err, unsigned limit, int pf_bytes) {
   constexpr int NT = 1024, RB = 64;
   extern __shared__ double smem[];
   __shared__ int s_ok;
@@ -550,13 +595,27 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
   const int nb = (n + MX_CB - 1) / MX_CB;
   const int k = (n + RB - 1) / RB;
   const int r0 = it.r0, nr = min(RB, n - r0);
-  double* rp = smem;             // n residual rows
-  double* xo = smem + n;         // RB values of this item's unknowns before the update
-  double* pp = xo + RB;          // nb x RB block partials
+  // LDS: the prefetched GEMV slice (pf_bytes), then the residual, pre-update
+  // values, block partials and unknowns
+  unsigned char* slice = reinterpret_cast<unsigned char*>(smem);
+  double* rp = smem + pf_bytes / 8;  // n residual rows
+  double* xo = rp + n;               // RB values of this item's unknowns before the update
+  double* pp = xo + RB;              // nb x RB block partials
   int32_t* dd = reinterpret_cast<int32_t*>(pp + nb * RB);  // RB unknowns
+  // this workgroup's 64 rows of the inverse go to LDS while the residual forms
+  const int sz = rec.f32 ? 4 : 8;
+  const bool pf = int64_t(64) * n * sz <= pf_bytes;
+  auto prefetch = [&](int w0) {
+    if (!pf) return;
+    if (rec.f32)
+      mx_prefetch_slice<4>(reinterpret_cast<const unsigned char*>(a32 + rec.fac), n, r0, slice, w0);
+    else
+      mx_prefetch_slice<8>(reinterpret_cast<const unsigned char*>(a64 + rec.fac), n, r0, slice, w0);
+  };
   const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
   constexpr int NG = NT / MX_G;
   auto src = [rows](int q) { return rows[q]; };
+  prefetch(0);
   if (k == 1) {
     for (int rb = grp; rb < RB; rb += NG * MX_R)
       mx_residual_rows(src, rb, NG, RB, gl, sc, ecol, eval, b, x, [&](int q, double r, int32_t d, double xv) {
@@ -564,6 +623,7 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
         xo[q] = xv;
         dd[q] = d;
       });
+    __builtin_amdgcn_s_waitcnt(0);   // the slice has landed
     __syncthreads();
   } else {
     double* rg = rbuf + rec.slot + r0;
@@ -594,6 +654,7 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
     if (!s_ok) return;
     const double* ra = rbuf + rec.slot;
     for (int j = threadIdx.x; j < n; j += NT) rp[j] = __hip_atomic_load(ra + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);   // the slice has landed
     __syncthreads();
   }
   {
@@ -602,10 +663,16 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
       cb = t / nr;
     };
     auto put = [pp, nr](int t, double v) { pp[(t / nr) * RB + t % nr] = v; };
-    if (rec.f32)
+    if (pf) {
+      if (rec.f32)
+        mx_gemv_lds(reinterpret_cast<const float*>(slice), r0, rp, n, nr * nb, NT, ij, put);
+      else
+        mx_gemv_lds(reinterpret_cast<const double*>(slice), r0, rp, n, nr * nb, NT, ij, put);
+    } else if (rec.f32) {
       mx_gemv_pairs(a32, rec.fac, rp, n, nr * nb, NT, ij, put);
-    else
+    } else {
       mx_gemv_pairs(a64, rec.fac, rp, n, nr * nb, NT, ij, put);
+    }
   }
   __syncthreads();
   for (int ii = threadIdx.x; ii < nr; ii += NT) {
@@ -856,10 +923,10 @@ void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double
   nt = phase_form(c, L, nt);
   if (nt == 3) {
     const int w0 = L.ph_wptr[ph], nw = L.ph_wptr[ph + 1] - w0;
-    k_mult_coopr<<<unsigned(nw), 1024, L.cp_lds[0], s>>>(L.d_citem[0] + w0, L.d_irow + int64_t(w0) * 64, L.d_f64,
+    k_mult_coopr<<<unsigned(nw), 1024, L.cr_lds, s>>>(L.d_citem[0] + w0, L.d_irow + int64_t(w0) * 64, L.d_f64,
                                                          L.d_f32, L.sc, L.d_ecol, L.d_eval, b, x, level_alpha(c, L),
                                                          L.d_slot_mask, L.d_delta, L.d_pcnt,
-                                                         reinterpret_cast<int*>(c.d_bar + 1), 1u << 21);
+                                                         reinterpret_cast<int*>(c.d_bar + 1), 1u << 21, L.cr_pf);
     return;
   }
   if (nt == 1 || nt == 2) {
