@@ -22,6 +22,7 @@ namespace cav {
 namespace {
 constexpr int FT = 256;  // threads per patch workgroup
 constexpr int NB = 16;   // Gauss-Jordan panel width
+constexpr int NBP = NB + 1;  // LDS row stride of the panel (odd: rows fall in different banks)
 
 __device__ __forceinline__ double pow2_recip(double m) {
   // 2^(1-e) for m = f 2^e, f in [1/2, 1): maps m into [1, 2) exactly
@@ -58,6 +59,28 @@ __device__ double stencil_entry(int64_t da, int64_t db, const StencilCoef& sc) {
     return 0.0;
   }
   return 0.0;
+}
+
+// Unknowns of the rediscretised Stokes stencil row of unknown d on an N grid
+// (the only columns where stencil_entry can be nonzero): for u_ij the u
+// neighbours, itself, p_ij and p_{i-1,j}; for v_ij likewise with p_{i,j-1};
+// for p_ij the four faces of its cell.
+__device__ __forceinline__ int stencil_cols(int32_t d, int N, int32_t* c) {
+  const int32_t n2 = N * N, m = N - 1;
+  const int t = d / n2, q = d - t * n2, i = q / N, j = q % N;
+  auto C = [N](int a, int b) { return a * N + b; };
+  if (t == 0) {
+    c[0] = d; c[1] = C((i + 1) & m, j); c[2] = C((i - 1) & m, j); c[3] = C(i, (j + 1) & m); c[4] = C(i, (j - 1) & m);
+    c[5] = 2 * n2 + q; c[6] = 2 * n2 + C((i - 1) & m, j);
+    return 7;
+  }
+  if (t == 1) {
+    c[0] = d; c[1] = n2 + C((i + 1) & m, j); c[2] = n2 + C((i - 1) & m, j); c[3] = n2 + C(i, (j + 1) & m);
+    c[4] = n2 + C(i, (j - 1) & m); c[5] = 2 * n2 + q; c[6] = 2 * n2 + C(i, (j - 1) & m);
+    return 7;
+  }
+  c[0] = q; c[1] = C((i + 1) & m, j); c[2] = n2 + q; c[3] = n2 + C(i, (j + 1) & m);
+  return 4;
 }
 
 struct FactorJob {
@@ -115,7 +138,7 @@ __device__ double block_max(double v, double* sv) {
 }
 
 __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
-  extern __shared__ double P[];  // panel, row-major n x NB, then the row map (n ints)
+  extern __shared__ double P[];  // panel, row-major n x NB (row stride NBP), then the row map (n ints)
   __shared__ double sv[FT / 64];
   __shared__ int si[FT / 64];
   __shared__ int s_flag;
@@ -127,12 +150,27 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
   double* rs = J.rs + rec.slot;
   double* cs = J.cs + rec.slot;
   int32_t* piv = J.sigma + rec.slot;
-  int32_t* rp = reinterpret_cast<int32_t*>(P + int64_t(n) * NB);
+  int32_t* rp = reinterpret_cast<int32_t*>(P + int64_t(n) * NBP);
 
-  // 1. K_p from the stencils
-  for (int64_t e = tid; e < int64_t(n) * n; e += FT) {
-    const int a = int(e / n), b = int(e % n);
-    W[e] = stencil_entry(dofs[a], dofs[b], J.sc);
+  // 1. K_p from the stencils: zero, then each row's (at most 7) stencil
+  // entries whose column lies in the patch (dofs are sorted)
+  for (int64_t e = tid; e < int64_t(n) * n; e += FT) W[e] = 0.0;
+  __syncthreads();
+  for (int a = tid; a < n; a += FT) {
+    const int32_t da = dofs[a];
+    int32_t cols[7];
+    const int nc = stencil_cols(da, J.sc.N, cols);
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      if (q >= nc) break;
+      const int32_t g = cols[q];
+      int lo = 0, hi = n;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (dofs[mid] < g) lo = mid + 1; else hi = mid;
+      }
+      if (lo < n && dofs[lo] == g) W[int64_t(a) * n + lo] = stencil_entry(da, g, J.sc);
+    }
   }
   __syncthreads();
   // 2. plus -dt E_E entries whose column lies in the patch (dofs are sorted)
@@ -153,13 +191,19 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
     }
   }
   __syncthreads();
-  // 3. row, then column max-norm equilibration
-  for (int a = tid; a < n; a += FT) {
-    double m = 0.0;
-    for (int b = 0; b < n; ++b) m = fmax(m, fabs(W[int64_t(a) * n + b]));
-    const double s = (m > 0.0 && isfinite(m)) ? pow2_recip(m) : 1.0;
-    rs[a] = s;
-    for (int b = 0; b < n; ++b) W[int64_t(a) * n + b] *= s;
+  // 3. row, then column max-norm equilibration (a wave per row: coalesced;
+  // the maximum does not depend on the order)
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int a = wv; a < n; a += FT / 64) {
+      double* Wr = W + int64_t(a) * n;
+      double m = 0.0;
+      for (int b = lane; b < n; b += 64) m = fmax(m, fabs(Wr[b]));
+      for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+      const double s = (m > 0.0 && isfinite(m)) ? pow2_recip(m) : 1.0;
+      if (lane == 0) rs[a] = s;
+      for (int b = lane; b < n; b += 64) Wr[b] *= s;
+    }
   }
   __syncthreads();
   double colmax = 0.0;
@@ -191,14 +235,14 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
     // columns past nbp stay zero: the rank-NB update below reads all NB of them
     for (int e = tid; e < n * NB; e += FT) {
       const int a = e / NB, t = e % NB;
-      P[e] = t < nbp ? W[int64_t(rp[a]) * n + c0 + t] : 0.0;
+      P[a * NBP + t] = t < nbp ? W[int64_t(rp[a]) * n + c0 + t] : 0.0;
     }
     __syncthreads();
     for (int t = 0; t < nbp; ++t) {
       const int c = c0 + t;
       double bv = -1.0;
       int bi = n;
-      for (int a = c + tid; a < n; a += FT) argmax_combine(bv, bi, fabs(P[a * NB + t]), a);
+      for (int a = c + tid; a < n; a += FT) argmax_combine(bv, bi, fabs(P[a * NBP + t]), a);
       block_argmax(bv, bi, sv, si);
       if (!(bv > 0.0) || !isfinite(bv)) {
         if (tid == 0) s_flag = 1;
@@ -207,9 +251,9 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
       }
       if (tid == 0) piv[c] = bi;
       if (bi != c && tid < nbp) {
-        const double tmp = P[c * NB + tid];
-        P[c * NB + tid] = P[bi * NB + tid];
-        P[bi * NB + tid] = tmp;
+        const double tmp = P[c * NBP + tid];
+        P[c * NBP + tid] = P[bi * NBP + tid];
+        P[bi * NBP + tid] = tmp;
       }
       if (bi != c && tid == 0) {
         const int32_t tr = rp[c];
@@ -217,27 +261,27 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
         rp[bi] = tr;
       }
       __syncthreads();
-      const double pv = P[c * NB + t];
+      const double pv = P[c * NBP + t];
       __syncthreads();
-      if (tid < nbp) P[c * NB + tid] = (tid == t ? 1.0 : P[c * NB + tid]) / pv;
+      if (tid < nbp) P[c * NBP + tid] = (tid == t ? 1.0 : P[c * NBP + tid]) / pv;
       __syncthreads();
       for (int a = tid; a < n; a += FT) {
         if (a == c) continue;
-        const double f = P[a * NB + t];
+        const double f = P[a * NBP + t];
         for (int u = 0; u < nbp; ++u)
-          if (u != t) P[a * NB + u] -= f * P[c * NB + u];
-        P[a * NB + t] = -f * P[c * NB + t];
+          if (u != t) P[a * NBP + u] -= f * P[c * NBP + u];
+        P[a * NBP + t] = -f * P[c * NBP + t];
       }
       __syncthreads();
     }
     if (s_flag) break;
     for (int e = tid; e < n * nbp; e += FT) {
       const int a = e / nbp, t = e % nbp;
-      W[int64_t(rp[a]) * n + c0 + t] = P[a * NB + t];
+      W[int64_t(rp[a]) * n + c0 + t] = P[a * NBP + t];
     }
     // rank-nbp update of the other columns: pivot rows <- P11 y, other rows +=
     // P_a y; rows in batches of RC whose loads are issued together
-    constexpr int RC = 8;
+    constexpr int RC = 16;
     for (int j = tid; j < n; j += FT) {
       if (j >= c0 && j < c0 + nbp) continue;
       double y[NB];
@@ -253,7 +297,7 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
           if (a < n) {
             double s = 0.0;
 #pragma unroll
-            for (int t = 0; t < NB; ++t) s += P[a * NB + t] * y[t];
+            for (int t = 0; t < NB; ++t) s += P[a * NBP + t] * y[t];
             W[int64_t(rp[a]) * n + j] = (a >= c0 && a < c0 + nbp) ? s : w[u] + s;
           }
         }
@@ -618,7 +662,7 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   J.eval = L.d_eval;
   // explicit patches with E_E, the shared patch without
   const int nmax = order.empty() ? 5 : order[0].n;
-  const size_t lds = size_t(std::max(nmax, 5)) * (NB * sizeof(double) + sizeof(int32_t));
+  const size_t lds = size_t(std::max(nmax, 5)) * (NBP * sizeof(double) + sizeof(int32_t));
   if (lds > 64 * 1024)
     CAV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_factor),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
@@ -639,7 +683,7 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   }
   J.recs = d_std;
   J.use_ee = 0;
-  k_factor<<<1, FT, 5 * (NB * sizeof(double) + sizeof(int32_t)), s>>>(J);
+  k_factor<<<1, FT, 5 * (NBP * sizeof(double) + sizeof(int32_t)), s>>>(J);
   std::vector<PatchRec> all_rec(exp_only);
   all_rec.insert(all_rec.end(), std_only.begin(), std_only.end());
   PatchRec* d_all = upload(c, all_rec);

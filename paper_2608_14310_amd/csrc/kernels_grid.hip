@@ -2,6 +2,7 @@
 // bilinear transfers, and fixed-order reductions for the Krylov loop.
 // Vectors are [u | v | p], each an N x N block indexed [i][j] with j fastest.
 #include "cav_internal.hpp"
+#include "dots.hpp"
 
 namespace cav {
 
@@ -118,21 +119,10 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// part[i * nblk + blk] = sum over this block's elements of V_i . w.
-// Each block owns a contiguous chunk; each thread strides through it.
 __global__ __launch_bounds__(TPB) void k_dots_partial(const double* __restrict__ V, int64_t ldv, int k,
                                                       const double* __restrict__ w, int64_t n, double* __restrict__ part,
                                                       int nblk) {
-  __shared__ double sh[TPB / 64];
-  const int64_t chunk = (n + nblk - 1) / nblk;
-  const int64_t s = int64_t(blockIdx.x) * chunk, e = min(n, s + chunk);
-  for (int i = 0; i < k; ++i) {
-    const double* vi = V + int64_t(i) * ldv;
-    double acc = 0.0;
-    for (int64_t t = s + threadIdx.x; t < e; t += TPB) acc += vi[t] * w[t];
-    const double r = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[int64_t(i) * nblk + blockIdx.x] = r;
-  }
+  dots_block<TPB>(V, ldv, k, w, n, part, nblk);
 }
 
 // out[i] = sum_b part[i * nblk + b], one block per i, fixed order.
@@ -191,7 +181,7 @@ inline unsigned nblocks(int64_t n) { return unsigned((n + TPB - 1) / TPB); }
 }  // namespace
 
 int dots_blocks(int64_t n) {
-  int64_t b = (n + 4095) / 4096;
+  int64_t b = (n + 2047) / 2048;   // one tile of TPB x DOT_EPT elements per block up to 2M elements
   if (b < 1) b = 1;
   if (b > 1024) b = 1024;
   return int(b);

@@ -10,6 +10,7 @@
 #include <cmath>
 
 #include "cav_internal.hpp"
+#include "dots.hpp"
 
 namespace cav {
 namespace {
@@ -42,22 +43,12 @@ __global__ __launch_bounds__(TPB) void k_col_put(double* __restrict__ Z, int64_t
   Z[int64_t(gi[GI_J]) * ldv + t] = in[t];
 }
 
-// k = j + 1 dot products of V_i with w: partial sums per block (same chunks
-// and order as the host-driven solve's reduction).
+// k = j + 1 dot products of V_i with w: partial sums per block (the same
+// chunks and order as the host-driven solve's reduction).
 __global__ __launch_bounds__(TPB) void k_dots_partial_dk(const double* __restrict__ V, int64_t ldv,
                                                           const int32_t* __restrict__ gi, const double* __restrict__ w,
                                                           int64_t n, double* __restrict__ part, int nblk) {
-  __shared__ double sh[TPB / 64];
-  const int k = gi[GI_J] + 1;
-  const int64_t chunk = (n + nblk - 1) / nblk;
-  const int64_t s = int64_t(blockIdx.x) * chunk, e = min(n, s + chunk);
-  for (int i = 0; i < k; ++i) {
-    const double* vi = V + int64_t(i) * ldv;
-    double acc = 0.0;
-    for (int64_t t = s + threadIdx.x; t < e; t += TPB) acc += vi[t] * w[t];
-    const double r = block_sum_k(acc, sh);
-    if (threadIdx.x == 0) part[int64_t(i) * nblk + blockIdx.x] = r;
-  }
+  dots_block<TPB>(V, ldv, gi[GI_J] + 1, w, n, part, nblk);
 }
 
 __global__ __launch_bounds__(TPB) void k_dots_final_dk(const double* __restrict__ part, int nblk,
