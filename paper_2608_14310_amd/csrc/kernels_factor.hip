@@ -347,11 +347,14 @@ __global__ void k_sigma(const PatchRec* __restrict__ recs, int count, int32_t* _
 }
 
 // M[i + j n] = cs[i] * W[rowp[i]][sigma[j]] * rs[j]  (= K_p^{-1}), cast to T.
+// 64 x 64 tiles through LDS: W is read along rows (consecutive threads take
+// consecutive j) and M written along its columns (consecutive i).
 template <typename T>
 __global__ __launch_bounds__(256) void k_finalize(const PatchRec* __restrict__ wrec, const PatchRec* __restrict__ orec,
                                                   const double* __restrict__ work, const double* __restrict__ rs,
                                                   const double* __restrict__ cs, const int32_t* __restrict__ sigma,
                                                   const int32_t* __restrict__ rowp, T* __restrict__ out) {
+  __shared__ double tile[64][65];
   const PatchRec w = wrec[blockIdx.x];
   const PatchRec o = orec[blockIdx.x];
   const int n = w.n;
@@ -361,10 +364,20 @@ __global__ __launch_bounds__(256) void k_finalize(const PatchRec* __restrict__ w
   const int32_t* sg = sigma + w.slot;
   const int32_t* rw = rowp + w.slot;
   T* M = out + o.fac;
-  for (int64_t e = threadIdx.x; e < int64_t(n) * n; e += 256) {
-    const int i = int(e % n), j = int(e / n);
-    M[e] = T(c[i] * W[int64_t(rw[i]) * n + sg[j]] * r[j]);
-  }
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  for (int i0 = 0; i0 < n; i0 += 64)
+    for (int j0 = 0; j0 < n; j0 += 64) {
+      for (int ii = grp; ii < 64; ii += 4) {
+        const int i = i0 + ii, j = j0 + lane;
+        if (i < n && j < n) tile[ii][lane] = c[i] * W[int64_t(rw[i]) * n + sg[j]] * r[j];
+      }
+      __syncthreads();
+      for (int jj = grp; jj < 64; jj += 4) {
+        const int i = i0 + lane, j = j0 + jj;
+        if (i < n && j < n) M[int64_t(j) * n + i] = T(tile[lane][jj]);
+      }
+      __syncthreads();
+    }
 }
 
 // ------------------------------------------------------ coarsest level ---
@@ -405,9 +418,10 @@ __global__ void k_coarse_add_ee(double* __restrict__ W, int n, int64_t nv, const
 // (m <= QB) with partial pivoting inside the block (first maximum on ties);
 // the column interchanges are undone at the end, so Dv (QB x QB, row-major,
 // zero outside m x m) holds the block inverse. status = 1 on a zero or
-// non-finite pivot. 1024 threads, four entries each; the interchange of rows
+// non-finite pivot. CQT threads, QB^2 / CQT entries each; the interchange of rows
 // k and p is folded into step k's update (row p receives old row k).
-__global__ __launch_bounds__(1024) void k_cq_diag(const double* __restrict__ W, int n, int c0, int m,
+constexpr int CQT = 1024;  // threads of the block-inverse workgroup
+__global__ __launch_bounds__(CQT) void k_cq_diag(const double* __restrict__ W, int n, int c0, int m,
                                                   double* __restrict__ Dv, int32_t* __restrict__ status) {
   __shared__ double D[QB][QB + 1];
   __shared__ int piv[QB];
@@ -415,7 +429,7 @@ __global__ __launch_bounds__(1024) void k_cq_diag(const double* __restrict__ W, 
   __shared__ int s_p;
   __shared__ int s_bad;
   const int tid = threadIdx.x;
-  for (int e = tid; e < QB * QB; e += 1024) {
+  for (int e = tid; e < QB * QB; e += CQT) {
     const int i = e / QB, j = e % QB;
     D[i][j] = (i < m && j < m) ? W[int64_t(c0 + i) * n + c0 + j] : 0.0;
   }
@@ -456,7 +470,7 @@ __global__ __launch_bounds__(1024) void k_cq_diag(const double* __restrict__ W, 
       oldk[j] = D[k][j];
     }
     __syncthreads();
-    for (int e = tid; e < QB * QB; e += 1024) {
+    for (int e = tid; e < QB * QB; e += CQT) {
       const int i = e / QB, j = e % QB;
       if (i >= m || j >= m) continue;
       if (i == k) {
@@ -484,7 +498,7 @@ __global__ __launch_bounds__(1024) void k_cq_diag(const double* __restrict__ W, 
       }
     }
   __syncthreads();
-  for (int e = tid; e < QB * QB; e += 1024) Dv[e] = D[e / QB][e % QB];
+  for (int e = tid; e < QB * QB; e += CQT) Dv[e] = D[e / QB][e % QB];
 }
 
 // blockIdx.y == 0: R (QB x n, row-major): R[t][j] = (D^{-1} W[C, j])_t for
@@ -884,7 +898,7 @@ cav_status factor_coarse(Ctx& c) {
   const dim3 gu(unsigned((n + QT - 1) / QT), unsigned((n + QT - 1) / QT));
   for (int c0 = 0; c0 < n; c0 += QB) {
     const int m = std::min(QB, n - c0);
-    k_cq_diag<<<1, 1024, 0, s>>>(W, n, c0, m, Dv, sts);
+    k_cq_diag<<<1, CQT, 0, s>>>(W, n, c0, m, Dv, sts);
     k_cq_prep<<<dim3(nblk(int64_t(n) * QB), 2), 256, 0, s>>>(W, n, c0, m, Dv, R, X);
     k_cq_update<<<gu, 256, 0, s>>>(W, n, c0, m, X, R);
   }
