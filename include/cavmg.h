@@ -181,6 +181,12 @@ cav_status cav_set_smoother(cav_ctx ctx, int kind, double alpha, int pre, int po
  * multiplicative orders; they differ in robustness at extreme stiffness
  * (Table 1 diagnostic). Cleared only by another call. */
 cav_status cav_set_phase_order(cav_ctx ctx, int order);
+/* Bound of every workgroup-barrier wait of the cooperative phase forms and
+ * the one-launch sweep, in polls (default 2^21, about a second). A wait that
+ * reaches it gives up: its workgroup leaves x unwritten, the kernel finishes,
+ * and the next FGMRES solve returns CAV_ERR_HIP (the flag is then cleared).
+ * A tiny bound forces that path, for tests of the failure handling. */
+cav_status cav_set_wait_limit(cav_ctx ctx, uint32_t polls);
 /* Per-level override (kind -1 restores the context's choice): level in
  * 1 .. n_levels-1 uses `kind` with damping `alpha`, e.g. the multiplicative
  * sweep on the finest level and the additive one below it. Cleared by

@@ -128,6 +128,7 @@ _SIGS = {
     "cav_set_level_smoother": ([_P, C.c_int, C.c_int, C.c_double], C.c_int),
     "cav_error_propagation": ([_P, C.c_int32, _P, _P], C.c_int),
     "cav_set_phase_order": ([_P, C.c_int], C.c_int),
+    "cav_set_wait_limit": ([_P, C.c_uint32], C.c_int),
     "cav_build_box_patches": ([_P, C.c_int, C.c_int, C.POINTER(LevelStats)], C.c_int),
     "cav_analyze_box": ([C.POINTER(GridDesc), C.POINTER(StructureDesc), C.c_int, C.c_int, C.POINTER(_P)], C.c_int),
     "cav_set_tuning": ([_P, C.POINTER(C.c_int32)], C.c_int),
@@ -424,6 +425,11 @@ class Solver:
         T = self._torch.empty_like(X)
         self._check(self._L.cav_error_propagation(self._h, int(X.shape[0]), _dev_ptr(X), _dev_ptr(T)))
         return T
+
+    def set_wait_limit(self, polls: int = 1 << 21) -> None:
+        """Bound (in polls) of the cooperative kernels' barrier waits; a wait that
+        reaches it makes the next solve raise instead of hanging."""
+        self._check(self._L.cav_set_wait_limit(self._h, int(polls)))
 
     def set_phase_order(self, order: str = "explicit_first") -> None:
         """Multiplicative sweep order: 'explicit_first' (default) or 'standard_first'."""

@@ -1400,4 +1400,10 @@ cav_status cav_set_phase_order(cav_ctx ctx, int order) {
   return CAV_OK;
 }
 
+cav_status cav_set_wait_limit(cav_ctx ctx, uint32_t polls) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  ctx->c.wait_limit = polls;
+  return CAV_OK;
+}
+
 }  // extern "C"

@@ -198,6 +198,7 @@ struct Ctx {
   double alpha = 0.7;
   int pre = 1, post = 1;
   bool std_first = false;  // multiplicative sweep: shared-patch colours before the explicit phases
+  uint32_t wait_limit = 1u << 21;  // polls of a bounded workgroup-barrier wait before it gives up
   int smoother = CAV_SMOOTHER_ADDITIVE;
   // coarsest solution operator (nc x nc, row-major, nc = 3 N0^2)
   int nc = 0;

@@ -857,7 +857,7 @@ bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t
   if (L.sweep_grid <= 0) return false;
   SweepArgs a{L.d_mrec, L.d_ph_ptr, nph, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_slot_q, L.d_ecol, L.d_eval,
               L.d_cellflag, L.d_std_inv, b, x, level_alpha(c, L), c.d_bar, reinterpret_cast<int*>(c.d_bar + 1),
-              1u << 21, c.std_first ? 1 : 0, L.d_slot_mask};
+              c.wait_limit, c.std_first ? 1 : 0, L.d_slot_mask};
   k_zero_bar<<<1, 64, 0, s>>>(c.d_bar, 1);
   double bytes = 0.0;
   for (double v : L.ph_bytes) bytes += v;
@@ -926,7 +926,7 @@ void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double
     k_mult_coopr<<<unsigned(nw), 1024, L.cr_lds, s>>>(L.d_citem[0] + w0, L.d_irow + int64_t(w0) * 64, L.d_f64,
                                                          L.d_f32, L.sc, L.d_ecol, L.d_eval, b, x, level_alpha(c, L),
                                                          L.d_slot_mask, L.d_delta, L.d_pcnt,
-                                                         reinterpret_cast<int*>(c.d_bar + 1), 1u << 21, L.cr_pf);
+                                                         reinterpret_cast<int*>(c.d_bar + 1), c.wait_limit, L.cr_pf);
     return;
   }
   if (nt == 1 || nt == 2) {
@@ -936,12 +936,12 @@ void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double
       const int w0 = L.ph_wptr[ph], nw = L.ph_wptr[ph + 1] - w0;
       k_mult_coop<64><<<unsigned(nw), 1024, L.cp_lds[0], s>>>(L.d_citem[0] + w0, L.d_f64, L.d_f32, L.d_slot_dof, L.sc,
                                                               L.d_slot_q, L.d_ecol, L.d_eval, b, x, al, L.d_slot_mask,
-                                                              L.d_pcnt, err, 1u << 21);
+                                                              L.d_pcnt, err, c.wait_limit);
     } else {
       const int w0 = L.ph_wptr2[ph], nw = L.ph_wptr2[ph + 1] - w0;
       k_mult_coop<128><<<unsigned(nw), 1024, L.cp_lds[1], s>>>(L.d_citem[1] + w0, L.d_f64, L.d_f32, L.d_slot_dof,
                                                                L.sc, L.d_slot_q, L.d_ecol, L.d_eval, b, x, al,
-                                                               L.d_slot_mask, L.d_pcnt, err, 1u << 21);
+                                                               L.d_slot_mask, L.d_pcnt, err, c.wait_limit);
     }
     return;
   }

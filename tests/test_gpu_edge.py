@@ -188,3 +188,26 @@ def test_full_size_beam512(cav):
     g.close()
     assert inf2["iterations"] == 28
     np.testing.assert_array_equal(x2.cpu().numpy(), xg)
+
+
+def test_barrier_wait_bound_reports_and_recovers(cav):
+    """The cooperative phase kernels' barrier waits are bounded. A bound of
+    zero polls forces the give-up path from the host: every kernel still
+    finishes, the solve raises CAV_ERR_HIP, and with the bound restored the
+    context solves again, bit for bit as before."""
+    from paper_2608_14310_amd import CAVError
+    s = workloads.beam_fibres(N=64, n_levels=4, kappa_b=1e-2)   # patches of up to 301 rows
+    print("[edge] barrier wait bound", flush=True)
+    g = cav.Solver(0)
+    g.setup(s, precision="fp64", alpha=1.0, smoother="multiplicative")
+    b = _t(s.b)
+    x0, i0 = g.fgmres_solve(b, 1e-10, 150)
+    g.set_wait_limit(0)
+    with pytest.raises(CAVError) as e:
+        g.fgmres_solve(b, 1e-10, 150)
+    assert e.value.status == 3
+    g.set_wait_limit()
+    x1, i1 = g.fgmres_solve(b, 1e-10, 150)
+    g.close()
+    assert i1["converged"] and i1["iterations"] == i0["iterations"]
+    np.testing.assert_array_equal(x1.cpu().numpy(), x0.cpu().numpy())
