@@ -138,7 +138,7 @@ __device__ double block_max(double v, double* sv) {
 }
 
 __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
-  extern __shared__ double P[];  // panel, row-major n x NB (row stride NBP), then the row map (n ints)
+  extern __shared__ double P[];  // panel, row-major n x NB (row stride NBP), row map and unknowns (n ints each)
   __shared__ double sv[FT / 64];
   __shared__ int si[FT / 64];
   __shared__ int s_flag;
@@ -151,11 +151,13 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
   double* cs = J.cs + rec.slot;
   int32_t* piv = J.sigma + rec.slot;
   int32_t* rp = reinterpret_cast<int32_t*>(P + int64_t(n) * NBP);
+  int32_t* dl = rp + n;   // the patch's unknowns (sorted), for the column searches
+  for (int a = tid; a < n; a += FT) dl[a] = dofs[a];
 
   // 1. K_p from the stencils: zero, then each row's (at most 7) stencil
   // entries whose column lies in the patch (dofs are sorted)
   for (int64_t e = tid; e < int64_t(n) * n; e += FT) W[e] = 0.0;
-  __syncthreads();
+  __syncthreads();   // also publishes dl
   for (int a = tid; a < n; a += FT) {
     const int32_t da = dofs[a];
     int32_t cols[7];
@@ -167,9 +169,9 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
       int lo = 0, hi = n;
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (dofs[mid] < g) lo = mid + 1; else hi = mid;
+        if (dl[mid] < g) lo = mid + 1; else hi = mid;
       }
-      if (lo < n && dofs[lo] == g) W[int64_t(a) * n + lo] = stencil_entry(da, g, J.sc);
+      if (lo < n && dl[lo] == g) W[int64_t(a) * n + lo] = stencil_entry(da, g, J.sc);
     }
   }
   __syncthreads();
@@ -184,9 +186,9 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
         int lo = 0, hi = n;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if (dofs[mid] < g) lo = mid + 1; else hi = mid;
+          if (dl[mid] < g) lo = mid + 1; else hi = mid;
         }
-        if (lo < n && dofs[lo] == g) W[int64_t(a) * n + lo] += J.eval[q];
+        if (lo < n && dl[lo] == g) W[int64_t(a) * n + lo] += J.eval[q];
       }
     }
   }
@@ -207,16 +209,30 @@ __global__ __launch_bounds__(FT) void k_factor(FactorJob J) {
   }
   __syncthreads();
   double colmax = 0.0;
+  constexpr int CB = 8;   // rows whose loads are issued together
   for (int b = tid; b < n; b += FT) {
     double m = 0.0;
-    for (int a = 0; a < n; ++a) m = fmax(m, fabs(W[int64_t(a) * n + b]));
+    for (int a0 = 0; a0 < n; a0 += CB) {
+      double v[CB];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) v[u] = a0 + u < n ? W[int64_t(a0 + u) * n + b] : 0.0;
+#pragma unroll
+      for (int u = 0; u < CB; ++u) m = fmax(m, fabs(v[u]));
+    }
     const double s = (m > 0.0 && isfinite(m)) ? pow2_recip(m) : 1.0;
     cs[b] = s;
     double sum = 0.0;
-    for (int a = 0; a < n; ++a) {
-      const double v = W[int64_t(a) * n + b] * s;
-      W[int64_t(a) * n + b] = v;
-      sum += fabs(v);
+    for (int a0 = 0; a0 < n; a0 += CB) {
+      double v[CB];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) v[u] = a0 + u < n ? W[int64_t(a0 + u) * n + b] : 0.0;
+#pragma unroll
+      for (int u = 0; u < CB; ++u)
+        if (a0 + u < n) {
+          const double sv = v[u] * s;
+          W[int64_t(a0 + u) * n + b] = sv;
+          sum += fabs(sv);
+        }
     }
     colmax = fmax(colmax, sum);
   }
@@ -676,7 +692,7 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   J.eval = L.d_eval;
   // explicit patches with E_E, the shared patch without
   const int nmax = order.empty() ? 5 : order[0].n;
-  const size_t lds = size_t(std::max(nmax, 5)) * (NBP * sizeof(double) + sizeof(int32_t));
+  const size_t lds = size_t(std::max(nmax, 5)) * (NBP * sizeof(double) + 2 * sizeof(int32_t));
   if (lds > 64 * 1024)
     CAV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_factor),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
@@ -697,7 +713,7 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   }
   J.recs = d_std;
   J.use_ee = 0;
-  k_factor<<<1, FT, 5 * (NBP * sizeof(double) + sizeof(int32_t)), s>>>(J);
+  k_factor<<<1, FT, 5 * (NBP * sizeof(double) + 2 * sizeof(int32_t)), s>>>(J);
   std::vector<PatchRec> all_rec(exp_only);
   all_rec.insert(all_rec.end(), std_only.begin(), std_only.end());
   PatchRec* d_all = upload(c, all_rec);
