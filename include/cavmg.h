@@ -198,6 +198,15 @@ cav_status cav_set_level_smoother(cav_ctx ctx, int level, int kind, double alpha
 cav_status cav_apply_operator(cav_ctx ctx, const double* x, double* y);
 /* z = V(r): one V(pre,post)-cycle on the finest level (Section 4). */
 cav_status cav_vcycle(cav_ctx ctx, const double* r, double* z);
+/* Z_q = V(R_q) for k right-hand sides (R, Z device, column-major, k columns
+ * of 3N^2, must not alias; k = 0 does nothing): the cycle of cav_vcycle on
+ * blocks of 16 columns. Each explicit-patch phase of the multiplicative
+ * smoother applies every stored inverse to all columns of a block in one
+ * launch as FP64 MFMA products (the inverse is read once per block, not once
+ * per column); the other steps run per column. Results agree with cav_vcycle
+ * column by column up to summation order (FP64 rounding). Allocates three
+ * 16-column buffers per level on first use. */
+cav_status cav_vcycle_multi(cav_ctx ctx, int32_t k, const double* R, double* Z);
 /* Right-preconditioned FGMRES from x0 = 0 (Section 5): one V-cycle per
  * iteration, CGS2 orthogonalisation with fixed-order reductions, Givens
  * rotations; stops when the estimate <= rtol or on exact breakdown. b is
@@ -269,7 +278,8 @@ cav_status cav_set_tuning(cav_ctx ctx, const int32_t* table);
  * T_q = X_q - V(K_E X_q) for the k columns X_q (device, column-major, each a
  * finest-level vector): the V-cycle's iteration matrix applied to X. With a
  * two-level hierarchy and X = I this assembles the two-grid iteration matrix
- * whose spectrum Table 1 reports. Enqueued on the context's stream. */
+ * whose spectrum Table 1 reports. The cycles run as in cav_vcycle_multi.
+ * Enqueued on the context's stream. */
 cav_status cav_error_propagation(cav_ctx ctx, int32_t k, const double* X, double* T);
 
 /* ---- per-level access for parity checks ----
@@ -385,7 +395,8 @@ cav_status cav_net_train_step_residual(cav_net net, cav_ctx ctx, int32_t kind, i
  * (device, count x 3N^2), b = K x*, x_0 = 0, x_k = x_{k-1} + V(b - K x_{k-1});
  * after iteration k (1..iters) writes rhat = r_k/||r_k||, ehat = (x* - x_k)/||r_k||
  * with r_k = b - K x_k, as FP32 at sample q*iters + k-1 of rhat/ehat (device,
- * count*iters x 3N^2). Synchronises. */
+ * count*iters x 3N^2). The solutions run in blocks of 16 through the cycle
+ * of cav_vcycle_multi. Synchronises. */
 cav_status cav_learned_pairs(cav_ctx ctx, int32_t count, const double* xstar, int32_t iters, float* rhat,
                              float* ehat);
 /* Attach (or detach with NULL) a net for cav_fgmres_solve with use_learned.

@@ -105,6 +105,7 @@ _SIGS = {
     "cav_set_smoother": ([_P, C.c_int, C.c_double, C.c_int, C.c_int], C.c_int),
     "cav_apply_operator": ([_P, _P, _P], C.c_int),
     "cav_vcycle": ([_P, _P, _P], C.c_int),
+    "cav_vcycle_multi": ([_P, C.c_int32, _P, _P], C.c_int),
     "cav_fgmres_solve": ([_P, _P, _P, C.POINTER(FgmresOpts), C.POINTER(SolveInfo)], C.c_int),
     "cav_level_apply": ([_P, C.c_int, C.c_int, _P, _P], C.c_int),
     "cav_level_N": ([_P, C.c_int], C.c_int32),
@@ -420,7 +421,7 @@ class Solver:
         self._check(self._L.cav_set_smoother(self._h, SMOOTHER[kind], float(alpha), int(pre), int(post)))
 
     def error_propagation(self, X):
-        """T = X - V(K X) column by column; X float64 device (k, n), rows are vectors."""
+        """T = X - V(K X) for every row of X (float64 device (k, n)), 16 at a time."""
         self._sync_stream()
         T = self._torch.empty_like(X)
         self._check(self._L.cav_error_propagation(self._h, int(X.shape[0]), _dev_ptr(X), _dev_ptr(T)))
@@ -467,6 +468,13 @@ class Solver:
         z = self.empty() if out is None else out
         self._check(self._L.cav_vcycle(self._h, _dev_ptr(r), _dev_ptr(z)))
         return z
+
+    def vcycle_multi(self, R):
+        """Z = V(R) for every row of R (float64 device (k, n)), 16 at a time."""
+        self._sync_stream()
+        Z = self._torch.empty_like(R)
+        self._check(self._L.cav_vcycle_multi(self._h, int(R.shape[0]), _dev_ptr(R), _dev_ptr(Z)))
+        return Z
 
     def level_apply(self, level: int, op: int, x, out_level: Optional[int] = None):
         self._sync_stream()

@@ -71,7 +71,7 @@ void free_level(Ctx& c, Level& L) {
                   (void*)L.d_f64, (void*)L.d_f32, (void*)L.d_b, (void*)L.d_x, (void*)L.d_r, (void*)L.d_z,
                   (void*)L.d_part, (void*)L.d_mrec, (void*)L.d_wrk, (void*)L.d_ph_ptr, (void*)L.d_slot_mask,
                   (void*)L.d_citem[0], (void*)L.d_citem[1], (void*)L.d_pcnt,
-                  (void*)L.d_slot_q, (void*)L.d_irow})
+                  (void*)L.d_slot_q, (void*)L.d_irow, (void*)L.d_mb, (void*)L.d_mx, (void*)L.d_mr})
     dev_free(c, p);
   L = Level();
 }
@@ -108,6 +108,43 @@ void vcycle_level(Ctx& c, int l, const double* b, double* x) {
   vcycle_level(c, l - 1, C.d_b, C.d_x);
   launch_prolong_add(L, C.d_x, x, s);
   for (int k = 0; k < c.post; ++k) launch_smoother(c, L, b, x, false, s);
+}
+
+// The V-cycle on kb <= 16 right-hand sides at once (columns of b and x with
+// stride 3 N^2 of level l): the same steps as vcycle_level for every column,
+// with the explicit-patch phases of the multiplicative smoother applied to all
+// columns in one launch (one read of each stored inverse per phase).
+constexpr int MR_COLS = 16;
+void vcycle_level_multi(Ctx& c, int l, const double* b, double* x, int kb) {
+  hipStream_t s = c.stream;
+  const int64_t n = 3 * int64_t(c.lv[l].N) * c.lv[l].N;
+  if (l == 0) {
+    for (int q = 0; q < kb; ++q) launch_coarse_solve(c, b + q * n, x + q * n, s);
+    return;
+  }
+  Level& L = c.lv[l];
+  if (c.pre == 0)
+    for (int q = 0; q < kb; ++q) launch_fill(x + q * n, 0.0, n, s);
+  for (int k = 0; k < c.pre; ++k) launch_smoother_multi(c, L, b, x, n, kb, k == 0, s);
+  Level& C = c.lv[l - 1];
+  const int64_t nc = 3 * int64_t(C.N) * C.N;
+  for (int q = 0; q < kb; ++q) {
+    launch_apply_op(L, x + q * n, L.d_mr + q * n, b + q * n, s);  // r = b - K x
+    launch_restrict(L, L.d_mr + q * n, C.d_mb + q * nc, s);
+  }
+  vcycle_level_multi(c, l - 1, C.d_mb, C.d_mx, kb);
+  for (int q = 0; q < kb; ++q) launch_prolong_add(L, C.d_mx + q * nc, x + q * n, s);
+  for (int k = 0; k < c.post; ++k) launch_smoother_multi(c, L, b, x, n, kb, false, s);
+}
+
+void ensure_multi_workspace(Ctx& c) {
+  for (Level& L : c.lv) {
+    if (L.d_mb) continue;
+    const size_t bytes = size_t(MR_COLS) * 3 * size_t(L.N) * L.N * sizeof(double);
+    L.d_mb = static_cast<double*>(dev_alloc(c, bytes));
+    L.d_mx = static_cast<double*>(dev_alloc(c, bytes));
+    L.d_mr = static_cast<double*>(dev_alloc(c, bytes));
+  }
 }
 
 void require(bool ok, cav_status st, const char* msg) {
@@ -977,32 +1014,38 @@ cav_status cav_learned_pairs(cav_ctx ctx, int32_t count, const double* xstar, in
   Level& F = c.lv.back();
   const int64_t n = 3 * int64_t(F.N) * F.N;
   const int nbk = dots_blocks(n);
+  // blocks of up to 16 solutions share each V-cycle (cav_vcycle_multi's cycle)
+  const int64_t nb = int64_t(MR_COLS) * n;
   if (!c.d_pw || c.pw_n != n) {
     dev_free(c, c.d_pw);
-    c.d_pw = static_cast<double*>(dev_alloc(c, size_t(5 * n + nbk + 1) * sizeof(double)));
+    c.d_pw = static_cast<double*>(dev_alloc(c, size_t(5 * nb + MR_COLS + nbk) * sizeof(double)));
     c.pw_n = n;
   }
+  ensure_multi_workspace(c);
   double* pb = c.d_pw;
-  double* px = pb + n;
-  double* pr = pb + 2 * n;
-  double* pz = pb + 3 * n;
-  double* pe = pb + 4 * n;
-  double* nrm = pb + 5 * n;
-  double* part = nrm + 1;
-  for (int32_t q = 0; q < count; ++q) {
-    const double* xs = xstar + int64_t(q) * n;
-    launch_apply_op(F, xs, pb, nullptr, s);  // b = K x*
-    launch_fill(px, 0.0, n, s);
+  double* px = pb + nb;
+  double* pr = pb + 2 * nb;
+  double* pz = pb + 3 * nb;
+  double* pe = pb + 4 * nb;
+  double* nrm = pb + 5 * nb;
+  double* part = nrm + MR_COLS;
+  for (int32_t q0 = 0; q0 < count; q0 += MR_COLS) {
+    const int kb = std::min<int32_t>(MR_COLS, count - q0);
+    const double* xs = xstar + int64_t(q0) * n;
+    for (int q = 0; q < kb; ++q) launch_apply_op(F, xs + q * n, pb + q * n, nullptr, s);  // b = K x*
+    launch_fill(px, 0.0, kb * n, s);
     for (int32_t k = 0; k < iters; ++k) {
-      launch_apply_op(F, px, pr, pb, s);     // r = b - K x
-      vcycle_top(c, pr, pz);
-      k_axpby<<<nblocks(n), TPB, 0, s>>>(px, 1.0, pz, 1.0, n);
-      launch_apply_op(F, px, pr, pb, s);
-      k_axpby<<<nblocks(n), TPB, 0, s>>>(pe, 1.0, xs, 0.0, n);
-      k_axpby<<<nblocks(n), TPB, 0, s>>>(pe, -1.0, px, 1.0, n);
-      launch_dots(pr, n, 1, pr, n, part, nbk, nrm, s);
-      const int64_t off = (int64_t(q) * iters + k) * n;
-      launch_pair_write(pr, pe, nrm, rhat + off, ehat + off, n, s);
+      for (int q = 0; q < kb; ++q) launch_apply_op(F, px + q * n, pr + q * n, pb + q * n, s);  // r = b - K x
+      vcycle_level_multi(c, c.n_levels - 1, pr, pz, kb);
+      k_axpby<<<nblocks(kb * n), TPB, 0, s>>>(px, 1.0, pz, 1.0, kb * n);
+      k_axpby<<<nblocks(kb * n), TPB, 0, s>>>(pe, 1.0, xs, 0.0, kb * n);
+      k_axpby<<<nblocks(kb * n), TPB, 0, s>>>(pe, -1.0, px, 1.0, kb * n);
+      for (int q = 0; q < kb; ++q) {
+        launch_apply_op(F, px + q * n, pr + q * n, pb + q * n, s);
+        launch_dots(pr + q * n, n, 1, pr + q * n, n, part, nbk, nrm + q, s);
+        const int64_t off = (int64_t(q0 + q) * iters + k) * n;
+        launch_pair_write(pr + q * n, pe + q * n, nrm + q, rhat + off, ehat + off, n, s);
+      }
     }
   }
   CAV_HIP(hipGetLastError());
@@ -1364,6 +1407,23 @@ cav_status cav_set_level_smoother(cav_ctx ctx, int level, int kind, double alpha
   API_END
 }
 
+cav_status cav_vcycle_multi(cav_ctx ctx, int32_t k, const double* R, double* Z) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require(k >= 0, CAV_ERR_INVALID_ARG, "k must be non-negative");
+  if (k == 0) return CAV_OK;
+  require(R && Z && R != Z, CAV_ERR_INVALID_ARG, "R and Z must be distinct device pointers");
+  ensure_multi_workspace(c);
+  const int64_t n = 3 * int64_t(c.lv.back().N) * c.lv.back().N;
+  for (int32_t q0 = 0; q0 < k; q0 += MR_COLS)
+    vcycle_level_multi(c, c.n_levels - 1, R + q0 * n, Z + q0 * n, std::min<int32_t>(MR_COLS, k - q0));
+  CAV_HIP(hipGetLastError());
+  return CAV_OK;
+  API_END
+}
+
 cav_status cav_error_propagation(cav_ctx ctx, int32_t k, const double* X, double* T) {
   if (!ctx) return CAV_ERR_INVALID_ARG;
   Ctx& c = ctx->c;
@@ -1372,16 +1432,16 @@ cav_status cav_error_propagation(cav_ctx ctx, int32_t k, const double* X, double
   require(k >= 0, CAV_ERR_INVALID_ARG, "k must be non-negative");
   if (k == 0) return CAV_OK;
   require(X && T && X != T, CAV_ERR_INVALID_ARG, "X and T must be distinct device pointers");
-  ensure_workspace(c, 1);
+  ensure_multi_workspace(c);
   Level& F = c.lv.back();
   hipStream_t s = c.stream;
   const int64_t n = 3 * int64_t(F.N) * F.N;
-  for (int32_t q = 0; q < k; ++q) {
-    const double* xq = X + int64_t(q) * n;
-    double* tq = T + int64_t(q) * n;
-    launch_apply_op(F, xq, c.d_w, nullptr, s);   // w = K x
-    vcycle_top(c, c.d_w, tq);                    // t = V(K x)
-    k_axpby<<<nblocks(n), TPB, 0, s>>>(tq, 1.0, xq, -1.0, n);  // t = x - V(K x)
+  // the finest level's block buffer holds K x (the cycle uses it only below the finest level)
+  for (int32_t q0 = 0; q0 < k; q0 += MR_COLS) {
+    const int kb = std::min<int32_t>(MR_COLS, k - q0);
+    for (int q = 0; q < kb; ++q) launch_apply_op(F, X + (q0 + q) * n, F.d_mb + q * n, nullptr, s);  // w = K x
+    vcycle_level_multi(c, c.n_levels - 1, F.d_mb, T + q0 * n, kb);                              // t = V(K x)
+    k_axpby<<<nblocks(kb * n), TPB, 0, s>>>(T + q0 * n, 1.0, X + q0 * n, -1.0, kb * n);         // t = x - V(K x)
   }
   CAV_HIP(hipGetLastError());
   return CAV_OK;

@@ -120,6 +120,7 @@ struct Level {
   int4* d_irow = nullptr;                 // 64 rows per 64-row item: unknown (-1 past the patch), E_E range
   unsigned long long* d_pcnt = nullptr;
   size_t cp_lds[2] = {0, 0};
+  size_t mr_lds = 0;                      // multi-RHS phase kernel: n x 16 residual block
   int cr_pf = 0;                          // shared-residual form: LDS bytes for the prefetched GEMV slice
   size_t cr_lds = 0;                      // and its whole dynamic LDS
 
@@ -135,6 +136,8 @@ struct Level {
 
   // per-level vectors (3 N^2)
   double *d_b = nullptr, *d_x = nullptr, *d_r = nullptr, *d_z = nullptr;
+  // 16-column blocks (column stride 3 N^2) of the multi-RHS cycle, made on first use
+  double *d_mb = nullptr, *d_mx = nullptr, *d_mr = nullptr;
   double* d_part = nullptr;               // reduction partials
 };
 
@@ -216,7 +219,7 @@ struct Ctx {
   double* d_st = nullptr;        // r', c, K c (3 n)
   double* d_sc = nullptr;        // stage scalars and counters
   int64_t st_n = 0;
-  double *d_pw = nullptr;        // residual-pair workspace (5 n)
+  double *d_pw = nullptr;        // residual-pair workspace (5 x 16 columns, 16 norms, partials)
   int64_t pw_n = 0;
   // graph-mode FGMRES: own stream (capture needs a non-default stream),
   // device state, fixed V-cycle input/output, captured iteration body
@@ -281,6 +284,8 @@ void launch_restrict(const Level& Lf, const double* rf, double* bc, hipStream_t 
 void launch_prolong_add(const Level& Lf, const double* xc, double* xf, hipStream_t s);
 void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
 void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
+void launch_smoother_multi(Ctx& c, Level& L, const double* b, double* x, int64_t ldv, int kb, bool zero_guess,
+                           hipStream_t s);
 void prepare_mult_smoother(size_t lds);
 // the whole multiplicative sweep of level L in one cooperative launch; false if not possible
 bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t s);

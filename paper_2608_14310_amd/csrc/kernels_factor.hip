@@ -872,7 +872,8 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
       L.cr_pf = int(pf);
       L.cr_lds = size_t(pf + rest);
     }
-    prepare_mult_smoother(std::max(L.cp_lds[1], L.cr_lds));
+    L.mr_lds = size_t(mn) * (16 * sizeof(double) + sizeof(int2) + sizeof(int32_t));
+    prepare_mult_smoother(std::max(std::max(L.cp_lds[1], L.cr_lds), L.mr_lds));
   }
   L.d_rec64 = upload(c, o64);
   L.d_rec32 = upload(c, o32);

@@ -682,6 +682,128 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
   }
 }
 
+// One phase of the multiplicative sweep for a block of kb <= 16 right-hand
+// sides (columns of B and X, stride ldv) sharing the level's factors: one
+// 1024-thread workgroup per patch. (0) The patch unknowns and their E_E entry
+// ranges into LDS. (1) The residual rows of all kb columns into LDS as an
+// n x 16 block: a wavefront takes MR_RR rows at once, lane = (column c,
+// entry slice e of 4): slice e sums the row's E_E entries e, e + 4, ... for
+// column c, slice 0 adds the stencil part, and the four slices are summed by
+// lane exchanges. (2) delta = K_p^{-1} R as FP64 MFMA 16x16x4 products, a
+// wavefront per 16-row tile, MR_KU loads of the stored inverse issued before
+// their products (A operand: row l % 16, column l / 16 of the step; B
+// operand: R row l / 16, column l % 16; result row l / 16 + 4 r, column
+// l % 16). (3) x += alpha delta at the patch unknowns. Every x read of the
+// patch precedes every x write (barrier after (1)); patches of one phase
+// share no unknown and no coupling.
+typedef double mx_d4 __attribute__((ext_vector_type(4)));
+constexpr int MR_CB = 16;   // right-hand sides per block
+constexpr int MR_RR = 4;    // residual rows per wavefront at once
+constexpr int MR_PER = 4;   // E_E entries a lane loads at once
+constexpr int MR_KU = 8;    // MFMA k-steps whose loads are issued together
+template <typename T>
+__device__ __forceinline__ mx_d4 mr_tile(const T* __restrict__ M, int n, int t0, const double* __restrict__ R,
+                                         int lane) {
+  const int li = lane % 16, lk = lane / 16, i = t0 + li;
+  mx_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  const T* col = M + i;
+  for (int k0 = 0; k0 < n; k0 += 4 * MR_KU) {
+    T a[MR_KU];
+#pragma unroll
+    for (int u = 0; u < MR_KU; ++u) {
+      const int kk = k0 + 4 * u + lk;
+      a[u] = (i < n && kk < n) ? col[int64_t(kk) * n] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < MR_KU; ++u) {
+      const int kk = k0 + 4 * u + lk;
+      const double bv = kk < n ? R[kk * MR_CB + li] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(double(a[u]), bv, acc, 0, 0, 0);
+    }
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(1024) void k_mult_mrhs(const MultRec* __restrict__ recs, const double* __restrict__ a64,
+                                                    const float* __restrict__ a32, const int32_t* __restrict__ slot_dof,
+                                                    StencilCoef sc, const int2* __restrict__ slot_q,
+                                                    const int32_t* __restrict__ ecol, const double* __restrict__ eval,
+                                                    const double* __restrict__ B, double* __restrict__ X, int64_t ldv,
+                                                    int kb, double alpha, const uint8_t* __restrict__ smask) {
+  extern __shared__ double smem[];
+  const MultRec rec = recs[blockIdx.x];
+  const int n = rec.n;
+  double* R = smem;                                            // n x MR_CB
+  int2* ql = reinterpret_cast<int2*>(smem + int64_t(n) * MR_CB);  // E_E entry ranges
+  int32_t* dl = reinterpret_cast<int32_t*>(ql + n);             // patch unknowns
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    dl[i] = slot_dof[rec.slot + i];
+    ql[i] = slot_q[rec.slot + i];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  {
+    const int c = lane & 15, e = lane >> 4;
+    const bool live = c < kb;
+    const double* xc = X + int64_t(c) * ldv;
+    for (int r0 = wave * MR_RR; r0 < n; r0 += 16 * MR_RR) {
+      int q0[MR_RR], q1[MR_RR];
+      double acc[MR_RR], st[MR_RR], bv[MR_RR];
+      int rounds = 0;
+#pragma unroll
+      for (int u = 0; u < MR_RR; ++u) {
+        const int rr = r0 + u;
+        const int2 q = (rr < n && live) ? ql[rr] : make_int2(0, 0);
+        q0[u] = q.x;
+        q1[u] = q.y;
+        rounds = max(rounds, (q.y - q.x + 4 * MR_PER - 1) / (4 * MR_PER));
+        const bool own = rr < n && live && e == 0;
+        st[u] = own ? krow(dl[rr], xc, sc, nullptr, nullptr, nullptr) : 0.0;
+        bv[u] = own ? B[int64_t(c) * ldv + dl[rr]] : 0.0;
+        acc[u] = 0.0;
+      }
+      for (int k0 = 0; k0 < rounds; ++k0) {
+        int ci[MR_RR][MR_PER];
+        double cv[MR_RR][MR_PER], xv[MR_RR][MR_PER];
+#pragma unroll
+        for (int u = 0; u < MR_RR; ++u)
+#pragma unroll
+          for (int k = 0; k < MR_PER; ++k) {
+            const int q = q0[u] + k0 * 4 * MR_PER + e + 4 * k;
+            ci[u][k] = q < q1[u] ? ecol[q] : -1;
+            cv[u][k] = q < q1[u] ? eval[q] : 0.0;
+          }
+#pragma unroll
+        for (int u = 0; u < MR_RR; ++u)
+#pragma unroll
+          for (int k = 0; k < MR_PER; ++k) xv[u][k] = ci[u][k] >= 0 ? xc[ci[u][k]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < MR_RR; ++u)
+#pragma unroll
+          for (int k = 0; k < MR_PER; ++k) acc[u] += cv[u][k] * xv[u][k];
+      }
+#pragma unroll
+      for (int u = 0; u < MR_RR; ++u) {
+        double v = acc[u] + st[u];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        const int rr = r0 + u;
+        if (e == 0 && rr < n) R[rr * MR_CB + c] = live ? bv[u] - v : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  const int li = lane % 16, lk = lane / 16;
+  for (int t0 = wave * 16; t0 < n; t0 += 256) {
+    const mx_d4 acc = rec.f32 ? mr_tile(a32 + rec.fac, n, t0, R, lane) : mr_tile(a64 + rec.fac, n, t0, R, lane);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = t0 + lk + 4 * r;
+      if (row < n && li < kb && (!smask || smask[rec.slot + row])) X[int64_t(li) * ldv + dl[row]] += alpha * acc[r];
+    }
+  }
+}
+
 // One colour phase of the shared standard patches: cells with
 // (i + 3 j) mod 8 == colour and no E_E entries solve their 5x5 patch from the
 // current residual and update x.
@@ -976,9 +1098,42 @@ void prepare_mult_smoother(size_t lds) {
   for (const void* f : {reinterpret_cast<const void*>(k_mult_exp<256>), reinterpret_cast<const void*>(k_mult_exp<512>),
                         reinterpret_cast<const void*>(k_mult_exp<1024>), reinterpret_cast<const void*>(k_mult_gemv),
                         reinterpret_cast<const void*>(k_mult_sweep<1024>), reinterpret_cast<const void*>(k_mult_coop<64>),
-                        reinterpret_cast<const void*>(k_mult_coop<128>), reinterpret_cast<const void*>(k_mult_coopr)})
+                        reinterpret_cast<const void*>(k_mult_coop<128>), reinterpret_cast<const void*>(k_mult_coopr),
+                        reinterpret_cast<const void*>(k_mult_mrhs)})
     CAV_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   set_to = lds;
+}
+
+// The smoother for a block of kb <= 16 right-hand sides (columns of b and x,
+// stride ldv). Multiplicative: every explicit phase in one multi-column
+// launch (MFMA), the shared-patch colours and the mean removal per column, in
+// the single-column order. Additive: the single-column sweep per column.
+void launch_smoother_multi(Ctx& c, Level& L, const double* b, double* x, int64_t ldv, int kb, bool zero_guess,
+                           hipStream_t s) {
+  const int64_t n2 = int64_t(L.N) * L.N, n = 3 * n2;
+  if (level_smoother(c, L) != CAV_SMOOTHER_MULTIPLICATIVE) {
+    for (int q = 0; q < kb; ++q) launch_smoother(c, L, b + q * ldv, x + q * ldv, zero_guess, s);
+    return;
+  }
+  if (zero_guess)
+    for (int q = 0; q < kb; ++q) launch_fill(x + q * ldv, 0.0, n, s);
+  const int nph = int(L.ph_ptr.size()) - 1;
+  const int64_t per_colour = n2 / 8;
+  const double al = level_alpha(c, L);
+  auto standard = [&]() {
+    for (int col = 0; col < 8; ++col)
+      for (int q = 0; q < kb; ++q)
+        k_mult_std<<<nblocks(per_colour), TPB, 0, s>>>(L.N, col, L.d_cellflag, L.d_std_inv, L.sc, b + q * ldv,
+                                                       x + q * ldv, al);
+  };
+  if (c.std_first) standard();
+  for (int ph = 0; ph < nph; ++ph) {
+    const int a = L.ph_ptr[ph], cnt = L.ph_ptr[ph + 1] - a;
+    k_mult_mrhs<<<unsigned(cnt), 1024, L.mr_lds, s>>>(L.d_mrec + a, L.d_f64, L.d_f32, L.d_slot_dof, L.sc, L.d_slot_q,
+                                                     L.d_ecol, L.d_eval, b, x, ldv, kb, al, L.d_slot_mask);
+  }
+  if (!c.std_first) standard();
+  for (int q = 0; q < kb; ++q) launch_pressure_mean_remove(x + q * ldv, L.N, L.d_part, s);
 }
 
 void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s) {

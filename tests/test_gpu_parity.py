@@ -137,6 +137,18 @@ def test_vcycle(pair):
     assert _rel(z, ref) < _tol(fst) * 4, (_rel(z, ref), _tol(fst))
 
 
+def test_vcycle_multi_additive_is_columnwise(pair):
+    """Multi-RHS cycle with the additive smoother: every step runs per column,
+    so each column equals the single-column cycle bit for bit (k = 19: one full
+    16-column block and a ragged one of 3)."""
+    name, s, H, g, stats, fst = pair
+    rng = np.random.default_rng(21)
+    R = rng.standard_normal((19, H.levels[-1].K.shape[0]))
+    Z = _np(g.vcycle_multi(_t(R)))
+    for q in range(R.shape[0]):
+        assert np.array_equal(Z[q], _np(g.vcycle(_t(R[q])))), (name, q)
+
+
 def test_fgmres_matches_oracle(pair):
     name, s, H, g, stats, fst = pair
     K = H.levels[-1].K
@@ -203,6 +215,27 @@ def test_multiplicative_sweep_and_vcycle(mpair):
     assert _rel(z, ref) < 4 * tol, (_rel(z, ref), tol)
 
 
+def test_vcycle_multi_matches_oracle(mpair):
+    """Multi-RHS cycle (explicit-patch phases as FP64 MFMA products over all
+    columns of a block) against the oracle's cycle and the single-column device
+    cycle, k = 19 columns: one full 16-column block, one ragged block of 3."""
+    name, s, H, g, stats, fst = mpair
+    rng = np.random.default_rng(12)
+    n = H.levels[-1].K.shape[0]
+    R = rng.standard_normal((19, n))
+    R[5] = s.b
+    Z = _np(g.vcycle_multi(_t(R)))
+    tol = _tol(fst)
+    pick = [0, 5, 15, 16, 18]
+    ref = H.vcycle(R[pick].T).T
+    for j, q in enumerate(pick):
+        assert _rel(Z[q], ref[j]) < 4 * tol, (name, q, _rel(Z[q], ref[j]), tol)
+    for q in range(R.shape[0]):
+        zq = _np(g.vcycle(_t(R[q])))
+        assert _rel(Z[q], zq) < tol, (name, q, _rel(Z[q], zq), tol)
+    assert g.vcycle_multi(_t(R[:0])).shape == (0, n)
+
+
 def test_multiplicative_fgmres_matches_oracle(mpair):
     name, s, H, g, stats, fst = mpair
     K = H.levels[-1].K
@@ -253,6 +286,11 @@ def test_mixed_precision_solve(smoother, alpha, name):
     ref = H.vcycle(s.b)
     tol = 64 * min(fst["max_cond"], 1e6) * 2.0 ** -24
     assert _rel(z, ref) < tol, (_rel(z, ref), tol)
+    # multi-RHS cycle: FP32-stored inverses, FP64 MFMA arithmetic (at least as accurate)
+    R = np.stack([s.b, np.random.default_rng(13).standard_normal(s.b.size)])
+    Z = _np(g.vcycle_multi(_t(R)))
+    assert _rel(Z[0], ref) < tol, (_rel(Z[0], ref), tol)
+    assert _rel(Z[1], _np(g.vcycle(_t(R[1])))) < 2 * tol
     K = H.levels[-1].K
     res = krylov.fgmres(lambda x: K @ x, H.vcycle, s.b, 1e-10, 150)
     x, info = g.fgmres_solve(_t(s.b), rtol=1e-10, max_it=150)
