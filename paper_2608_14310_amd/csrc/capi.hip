@@ -6,34 +6,112 @@
 #include <cstring>
 #include <new>
 #include <functional>
-#include <unordered_set>
+#include <unordered_map>
 
 #include "cav_internal.hpp"
 
 struct cav_ctx_s {
   cav::Ctx c;
-  std::unordered_set<void*> live;
+  std::unordered_map<void*, size_t> live;  // device blocks handed out, with their sizes
+  // released blocks kept for reuse, by size, each with the epoch of its release
+  std::unordered_multimap<size_t, std::pair<void*, uint64_t>> cache;
+  size_t cached_bytes = 0;
+  uint64_t epoch = 1;                      // advanced by every device-wide synchronisation
 };
 
 namespace cav {
 
 static cav_ctx_s* owner(Ctx& c) { return reinterpret_cast<cav_ctx_s*>(&c); }
 
+// Device memory of a context. Released blocks stay with the context (up to
+// DEV_CACHE_CAP bytes) and are handed out again for a request of the same
+// rounded size, so rebuilding a hierarchy of the same shape allocates
+// nothing. A block released after the last device-wide synchronisation
+// (device_sync_epoch) may still be used by queued work on some stream, so only
+// blocks released before it are handed out; the setup calls synchronise once
+// after releasing the previous hierarchy's memory.
+constexpr size_t DEV_CACHE_CAP = size_t(8) << 30;
+
+static void release_cache(cav_ctx_s* o) {
+  for (auto& kv : o->cache) (void)hipFree(kv.second.first);
+  o->cache.clear();
+  o->cached_bytes = 0;
+}
+
 void* dev_alloc(Ctx& c, size_t bytes) {
+  cav_ctx_s* o = owner(c);
+  const size_t sz = (std::max<size_t>(bytes, 16) + 255) & ~size_t(255);
+  if (!c.capturing) {
+    auto r = o->cache.equal_range(sz);
+    for (auto it = r.first; it != r.second; ++it)
+      if (it->second.second < o->epoch) {
+        void* p = it->second.first;
+        o->cache.erase(it);
+        o->cached_bytes -= sz;
+        o->live.emplace(p, sz);
+        return p;
+      }
+  }
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 16));
+  hipError_t e = hipMalloc(&p, sz);
+  if (e != hipSuccess && !o->cache.empty()) {
+    (void)hipGetLastError();
+    release_cache(o);
+    e = hipMalloc(&p, sz);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     throw StatusError(CAV_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
-  owner(c)->live.insert(p);
+  o->live.emplace(p, sz);
   return p;
+}
+
+// Start the coarsest factorisation on the side stream after the work queued
+// on c.stream (the operator's upload).
+void start_coarse(Ctx& c) {
+  if (!c.side) {
+    CAV_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+    CAV_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+    CAV_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+  }
+  CAV_HIP(hipEventRecord(c.ev_fork, c.stream));
+  CAV_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
+  c.coarse_pend = factor_coarse_launch(c, c.side);
+  CAV_HIP(hipEventRecord(c.ev_join, c.side));
+  c.coarse_pending = true;
+}
+
+// Forget the coarsest factorisation (a new operator is coming).
+void drop_coarse(Ctx& c) {
+  if (c.coarse_pending) {
+    (void)hipStreamSynchronize(c.side);
+    factor_coarse_release(c, c.coarse_pend);
+    c.coarse_pending = false;
+  }
+  dev_free(c, c.d_cinv);
+  c.d_cinv = nullptr;
+  c.coarse_ready = false;
+}
+
+void device_sync_epoch(Ctx& c) {
+  CAV_HIP(hipDeviceSynchronize());
+  ++owner(c)->epoch;
 }
 
 void dev_free(Ctx& c, void* p) {
   if (!p) return;
-  owner(c)->live.erase(p);
-  (void)hipFree(p);
+  cav_ctx_s* o = owner(c);
+  auto it = o->live.find(p);
+  if (it == o->live.end()) return;
+  const size_t sz = it->second;
+  o->live.erase(it);
+  if (o->cached_bytes + sz <= DEV_CACHE_CAP) {
+    o->cache.emplace(sz, std::make_pair(p, o->epoch));
+    o->cached_bytes += sz;
+  } else {
+    (void)hipFree(p);
+  }
 }
 
 hipEvent_t next_event(Ctx& c) {
@@ -65,6 +143,10 @@ T* upload(Ctx& c, const std::vector<T>& h) {
 }
 
 void free_level(Ctx& c, Level& L) {
+  if (L.fpending) {
+    factor_level_release(c, L.fpend);
+    L.fpending = false;
+  }
   for (void* p : {(void*)L.d_erow_id, (void*)L.d_erow_ptr, (void*)L.d_ecol, (void*)L.d_eval, (void*)L.d_erow_full,
                   (void*)L.d_cellflag, (void*)L.d_slot_dof, (void*)L.d_delta, (void*)L.d_t_dof, (void*)L.d_t_inv,
                   (void*)L.d_t_ptr, (void*)L.d_t_slot, (void*)L.d_std_inv, (void*)L.d_rec64, (void*)L.d_rec32,
@@ -77,6 +159,10 @@ void free_level(Ctx& c, Level& L) {
 }
 
 void free_patches(Ctx& c, Level& L) {
+  if (L.fpending) {
+    factor_level_release(c, L.fpend);   // blocks are reused only after a device-wide synchronisation
+    L.fpending = false;
+  }
   for (void** p : {(void**)&L.d_cellflag, (void**)&L.d_slot_dof, (void**)&L.d_delta, (void**)&L.d_t_dof,
                    (void**)&L.d_t_inv, (void**)&L.d_t_ptr, (void**)&L.d_t_slot, (void**)&L.d_std_inv,
                    (void**)&L.d_rec64, (void**)&L.d_rec32, (void**)&L.d_f64, (void**)&L.d_f32,
@@ -515,7 +601,14 @@ cav_status cav_destroy(cav_ctx ctx) {
     (void)hipStreamSynchronize(ctx->c.gstream);
     (void)hipStreamDestroy(ctx->c.gstream);
   }
-  for (void* p : ctx->live) (void)hipFree(p);
+  if (ctx->c.side) {
+    (void)hipStreamSynchronize(ctx->c.side);
+    (void)hipStreamDestroy(ctx->c.side);
+  }
+  for (hipEvent_t e : {ctx->c.ev_fork, ctx->c.ev_join})
+    if (e) (void)hipEventDestroy(e);
+  for (auto& kv : ctx->live) (void)hipFree(kv.first);
+  release_cache(ctx);
   if (ctx->c.h_pinned) (void)hipHostFree(ctx->c.h_pinned);
   for (hipEvent_t e : ctx->c.ev_pool) (void)hipEventDestroy(e);
   delete ctx;
@@ -541,7 +634,9 @@ cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* g, const cav_str
   const cav_status ss = make_structure(st, S, err);
   if (ss != CAV_OK) throw StatusError(ss, err);
   CAV_HIP(hipSetDevice(c.device));
+  drop_coarse(c);
   for (auto& lev : c.lv) free_level(c, lev);
+  device_sync_epoch(c);
   c.lv.assign(L, Level());
   c.built = c.patched = c.factored = false;
   c.n_levels = L;
@@ -589,6 +684,9 @@ cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* g, const cav_str
   }
   CAV_HIP(hipStreamSynchronize(c.stream));
   c.built = true;
+  // the coarsest inverse needs only the operator: it is computed on the GPU
+  // while the host builds the patch sets
+  if (3 * int64_t(c.lv[0].N) * c.lv[0].N <= 4096) start_coarse(c);
   return CAV_OK;
   API_END
 }
@@ -609,25 +707,50 @@ static cav_status build_family(cav_ctx ctx, int family, int box_b, int box_o, ca
   c.family = family;
   c.patched = c.factored = false;
   for (int l = 1; l < c.n_levels; ++l) free_patches(c, c.lv[l]);
-  // the levels' host-side patch sets are independent: build them concurrently
+  // the levels' host-side patch sets are independent: build them concurrently;
+  // then the patch factorisations (which need nothing more) are enqueued on the
+  // GPU while the host threads build the transposes, weights and colourings
   {
-    std::vector<std::thread> th;
-    std::vector<std::exception_ptr> errs(c.n_levels);
-    for (int l = 1; l < c.n_levels; ++l)
-      th.emplace_back([&, l] {
-        try {
-          Level& L = c.lv[l];
+    auto run_levels = [&](const std::function<void(Level&)>& f, const std::function<void()>& beside) {
+      std::vector<std::thread> th;
+      std::vector<std::exception_ptr> errs(c.n_levels);
+      for (int l = 1; l < c.n_levels; ++l)
+        th.emplace_back([&, l] {
+          try {
+            f(c.lv[l]);
+          } catch (...) {
+            errs[l] = std::current_exception();
+          }
+        });
+      std::exception_ptr mine;
+      try {
+        beside();
+      } catch (...) {
+        mine = std::current_exception();
+      }
+      for (auto& x : th) x.join();
+      if (mine) std::rethrow_exception(mine);
+      for (auto& e : errs)
+        if (e) std::rethrow_exception(e);
+    };
+    run_levels(
+        [&](Level& L) {
           if (family == CAV_FAMILY_BOX)
             build_box_patches(L.N, L.ee, box_b, box_o, L);
           else
-            build_patches(L.N, L.ee, family, L);
-        } catch (...) {
-          errs[l] = std::current_exception();
-        }
-      });
-    for (auto& x : th) x.join();
-    for (auto& e : errs)
-      if (e) std::rethrow_exception(e);
+            build_patch_sets(L.N, L.ee, family, L);
+        },
+        [] {});
+    run_levels(
+        [&](Level& L) {
+          if (family != CAV_FAMILY_BOX) build_patch_tables(L.N, L.ee, L);
+        },
+        [&] {
+          for (int l = c.n_levels - 1; l >= 1; --l) {
+            c.lv[l].fpend = factor_level_launch(c, c.lv[l]);
+            c.lv[l].fpending = true;
+          }
+        });
   }
   for (int l = 1; l < c.n_levels; ++l) {
     Level& L = c.lv[l];
@@ -687,8 +810,36 @@ cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold,
   CAV_HIP(hipSetDevice(c.device));
   c.factored = false;
   cav_factor_stats st{};
-  for (int l = 1; l < c.n_levels; ++l) factor_level(c, c.lv[l], precision, cond_threshold, &st);
-  factor_coarse(c);
+  // every level's patch factorisation is enqueued (finest first) before the
+  // first condition estimates are read; the coarsest factorisation normally
+  // started with the operator and is only checked here
+  std::vector<FactorPending> pend;
+  try {
+    if (!c.coarse_pending && !c.coarse_ready) start_coarse(c);
+    // factorisations normally enqueued by the patch build (a second call factors again)
+    for (int l = c.n_levels - 1; l >= 1; --l) {
+      Level& L = c.lv[l];
+      if (L.fpending) {
+        pend.push_back(std::move(L.fpend));
+        L.fpend = FactorPending();
+        L.fpending = false;
+      } else {
+        pend.push_back(factor_level_launch(c, L));
+      }
+    }
+    for (int l = c.n_levels - 1, k = 0; l >= 1; --l, ++k) factor_level_finish(c, c.lv[l], pend[k], precision,
+                                                                             cond_threshold, &st);
+    if (c.coarse_pending) {
+      c.coarse_pending = false;
+      factor_coarse_finish(c, c.coarse_pend, c.side);
+      c.coarse_ready = true;
+      CAV_HIP(hipStreamWaitEvent(c.stream, c.ev_join, 0));
+    }
+  } catch (...) {
+    (void)hipStreamSynchronize(c.stream);
+    for (auto& fp : pend) factor_level_release(c, fp);
+    throw;
+  }
   st.coarse_cond_est = -1.0;
   if (out) *out = st;
   c.factored = true;

@@ -28,6 +28,16 @@ struct PatchRec {
   int64_t fac;      // element offset into the factor arena of its precision
 };
 
+// Patch factorisations of one level in flight: records and device scratch.
+struct FactorPending {
+  int ne = 0;
+  int64_t std_slot = 0;
+  std::vector<PatchRec> exp_only, std_only;
+  double *work = nullptr, *rs = nullptr, *cs = nullptr, *kap = nullptr;
+  int32_t *sig = nullptr, *rowp = nullptr, *sts = nullptr, *slot_all = nullptr;
+  PatchRec *d_exp = nullptr, *d_std = nullptr, *d_all = nullptr;
+};
+
 // An explicit patch in a multiplicative phase: precision picks the arena.
 struct MultRec {
   int32_t n;
@@ -121,6 +131,9 @@ struct Level {
   unsigned long long* d_pcnt = nullptr;
   size_t cp_lds[2] = {0, 0};
   size_t mr_lds = 0;                      // multi-RHS phase kernel: n x 16 residual block
+  // factorisations enqueued while the host still builds the patch tables
+  FactorPending fpend;
+  bool fpending = false;
   int cr_pf = 0;                          // shared-residual form: LDS bytes for the prefetched GEMV slice
   size_t cr_lds = 0;                      // and its whole dynamic LDS
 
@@ -189,6 +202,12 @@ enum { GS_BETA = 0, GS_EST = 1, GS_INVHN = 2, GS_CS = 4 };
 constexpr int64_t GS_H(int m) { return GS_CS + 4 * int64_t(m) + 1; }
 constexpr int64_t GS_SIZE(int m) { return GS_H(m) + int64_t(m + 1) * m; }
 
+// Scratch and result of a coarsest factorisation in flight.
+struct CoarsePending {
+  double *W = nullptr, *Dv = nullptr, *R = nullptr, *X = nullptr;
+  int32_t* sts = nullptr;
+};
+
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -226,6 +245,13 @@ struct Ctx {
   unsigned long long* d_bar = nullptr;   // persistent-sweep barrier counter and error flag (2 x u64)
   bool capturing = false;                // set while a graph is being captured
   hipStream_t gstream = nullptr;
+  hipStream_t side = nullptr;            // default-priority stream for the coarsest factorisation
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // the coarsest factorisation starts when the operator is built (it needs
+  // nothing else) and is collected by cav_factor_patches
+  CoarsePending coarse_pend;
+  bool coarse_pending = false;            // launched on `side`, not yet checked
+  bool coarse_ready = false;              // d_cinv holds the current operator's inverse
   int32_t* d_gi = nullptr;
   double* d_gs = nullptr;
   double* d_vin = nullptr;
@@ -276,6 +302,10 @@ cav_status make_structure(const cav_structure_desc* st, Structure& out, std::str
 void assemble_ee_finest(int N, const Structure& s, HostCSR& ee);
 void galerkin_coarsen(int Nc, const HostCSR& fine, HostCSR& coarse);
 void build_patches(int N, const HostCSR& ee, int family, Level& L);
+// the two halves of build_patches: the patch sets (all a factorisation
+// needs), then the unknown -> slot transpose, weights, colouring and stats
+void build_patch_sets(int N, const HostCSR& ee, int family, Level& L);
+void build_patch_tables(int N, const HostCSR& ee, Level& L);
 void build_box_patches(int N, const HostCSR& ee, int b, int o, Level& L);
 
 // ---- device launches (kernels_*.hip) ----
@@ -299,8 +329,22 @@ void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
 void colour_explicit(int N, const HostCSR& ee, Level& L);
 void launch_coarse_solve(const Ctx& c, const double* b, double* x, hipStream_t s);
-cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, cav_factor_stats* st);
-cav_status factor_coarse(Ctx& c);
+// Patch factorisation of one smoothed level in two halves: `launch` enqueues
+// the factorisations on c.stream and returns their scratch; `finish` reads the
+// condition estimates back (synchronising), splits the precisions, writes the
+// stored inverses and the smoother tables, and releases the scratch. Every
+// level's launch can precede every finish, so the GPU factors all levels
+// back to back. `release` frees a pending level's scratch after a failure.
+FactorPending factor_level_launch(Ctx& c, Level& L);
+void factor_level_finish(Ctx& c, Level& L, FactorPending& fp, int precision, double cond_threshold,
+                         cav_factor_stats* st);
+void factor_level_release(Ctx& c, FactorPending& fp);
+// Coarsest factorisation on stream s (assembly, blocked quasi-definite
+// Gauss-Jordan, mean fix); `finish` synchronises s, checks the pivots and
+// installs the inverse (on a zero pivot it releases everything and throws).
+CoarsePending factor_coarse_launch(Ctx& c, hipStream_t s);
+void factor_coarse_finish(Ctx& c, CoarsePending& cp, hipStream_t s);
+void factor_coarse_release(Ctx& c, CoarsePending& cp);
 
 // vector helpers (kernels_grid.hip)
 void launch_dots(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* part, int nblk,
@@ -314,6 +358,8 @@ int dots_blocks(int64_t n);
 
 void* dev_alloc(Ctx& c, size_t bytes);
 void dev_free(Ctx& c, void* p);
+// Synchronise the device; memory released before this is reused from then on.
+void device_sync_epoch(Ctx& c);
 
 // learned stage (kernels_learned.hip)
 void net_alloc(Net& n, int64_t pix);

@@ -641,9 +641,28 @@ T* upload(Ctx& c, const std::vector<T>& h) {
 }
 }  // namespace
 
-cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, cav_factor_stats* st) {
+// Row table of the 64-row cooperative items: entry item * 64 + q holds the
+// unknown of row r0 + q of the item's patch and its E_E entry range (full row
+// pointer, velocity rows only), or -1 past the patch's last row.
+__global__ void k_item_rows(const CoopItem* __restrict__ items, int64_t nitems, const int32_t* __restrict__ slot_dof,
+                            const int32_t* __restrict__ erow_full, int64_t nv, int4* __restrict__ out) {
+  const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (t >= nitems * 64) return;
+  const CoopItem it = items[t / 64];
+  const int q = int(t % 64);
+  int4 v = make_int4(-1, 0, 0, 0);
+  if (it.r0 + q < it.rec.n) {
+    const int32_t d = slot_dof[it.rec.slot + it.r0 + q];
+    v = d < nv ? make_int4(d, erow_full[d], erow_full[d + 1], 0) : make_int4(d, 0, 0, 0);
+  }
+  out[t] = v;
+}
+
+FactorPending factor_level_launch(Ctx& c, Level& L) {
   hipStream_t s = c.stream;
+  FactorPending fp;
   const int ne = L.n_exp;
+  fp.ne = ne;
   // work records: every explicit patch plus the shared standard patch (index ne)
   std::vector<PatchRec> wrec(ne + 1);
   int64_t wtot = 0;
@@ -656,36 +675,35 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   const int N = L.N;
   const int64_t n2 = int64_t(N) * N;
   std::vector<int32_t> std_dofs = {0, int32_t(N), int32_t(n2), int32_t(n2 + 1), int32_t(2 * n2)};
-  const int64_t std_slot = L.n_slots;
-  wrec[ne] = PatchRec{5, ne, std_slot, wtot};
+  fp.std_slot = L.n_slots;
+  wrec[ne] = PatchRec{5, ne, fp.std_slot, wtot};
   wtot += 25;
   std::vector<int32_t> slot_all(L.slot_dof_h);
   slot_all.insert(slot_all.end(), std_dofs.begin(), std_dofs.end());
   const int64_t nslot = int64_t(slot_all.size());
 
-  double* work = static_cast<double*>(dev_alloc(c, size_t(wtot) * sizeof(double)));
-  double* rs = static_cast<double*>(dev_alloc(c, size_t(nslot) * sizeof(double)));
-  double* cs = static_cast<double*>(dev_alloc(c, size_t(nslot) * sizeof(double)));
-  int32_t* sig = static_cast<int32_t*>(dev_alloc(c, size_t(nslot) * sizeof(int32_t)));
-  int32_t* rowp = static_cast<int32_t*>(dev_alloc(c, size_t(nslot) * sizeof(int32_t)));
-  double* kap = static_cast<double*>(dev_alloc(c, size_t(ne + 1) * sizeof(double)));
-  int32_t* sts = static_cast<int32_t*>(dev_alloc(c, size_t(ne + 1) * sizeof(int32_t)));
-  int32_t* d_slot_all = upload(c, slot_all);
-  // sort work by size (largest first) so the long factorisations start first
+  fp.work = static_cast<double*>(dev_alloc(c, size_t(wtot) * sizeof(double)));
+  fp.rs = static_cast<double*>(dev_alloc(c, size_t(nslot) * sizeof(double)));
+  fp.cs = static_cast<double*>(dev_alloc(c, size_t(nslot) * sizeof(double)));
+  fp.sig = static_cast<int32_t*>(dev_alloc(c, size_t(nslot) * sizeof(int32_t)));
+  fp.rowp = static_cast<int32_t*>(dev_alloc(c, size_t(nslot) * sizeof(int32_t)));
+  fp.kap = static_cast<double*>(dev_alloc(c, size_t(ne + 1) * sizeof(double)));
+  fp.sts = static_cast<int32_t*>(dev_alloc(c, size_t(ne + 1) * sizeof(int32_t)));
+  fp.slot_all = upload(c, slot_all);
+  // largest first, so the long factorisations start first
   std::vector<PatchRec> order(wrec);
   std::stable_sort(order.begin(), order.end(), [](const PatchRec& a, const PatchRec& b) { return a.n > b.n; });
-  PatchRec* d_order = upload(c, order);
-  CAV_HIP(hipMemsetAsync(sts, 0, size_t(ne + 1) * sizeof(int32_t), s));
+  CAV_HIP(hipMemsetAsync(fp.sts, 0, size_t(ne + 1) * sizeof(int32_t), s));
 
   FactorJob J{};
-  J.work = work;
-  J.slot_dof = d_slot_all;
-  J.rs = rs;
-  J.cs = cs;
-  J.sigma = sig;
-  J.rowp = rowp;
-  J.kappa = kap;
-  J.status = sts;
+  J.work = fp.work;
+  J.slot_dof = fp.slot_all;
+  J.rs = fp.rs;
+  J.cs = fp.cs;
+  J.sigma = fp.sig;
+  J.rowp = fp.rowp;
+  J.kappa = fp.kap;
+  J.status = fp.sts;
   J.sc = L.sc;
   J.erow_full = L.d_erow_full;
   J.ecol = L.d_ecol;
@@ -696,34 +714,51 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   if (lds > 64 * 1024)
     CAV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_factor),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  int idx_std = -1;
-  for (size_t k = 0; k < order.size(); ++k)
-    if (order[k].id == ne) idx_std = int(k);
-  // launch the explicit patches (all records except the shared one) with E_E
-  std::vector<PatchRec> exp_only, std_only;
-  for (auto& r : order) (r.id == ne ? std_only : exp_only).push_back(r);
-  PatchRec* d_exp = upload(c, exp_only);
-  PatchRec* d_std = upload(c, std_only);
-  (void)idx_std;
-  (void)d_order;
-  if (!exp_only.empty()) {
-    J.recs = d_exp;
+  for (auto& r : order) (r.id == ne ? fp.std_only : fp.exp_only).push_back(r);
+  fp.d_exp = upload(c, fp.exp_only);
+  fp.d_std = upload(c, fp.std_only);
+  if (!fp.exp_only.empty()) {
+    J.recs = fp.d_exp;
     J.use_ee = 1;
-    k_factor<<<unsigned(exp_only.size()), FT, lds, s>>>(J);
+    k_factor<<<unsigned(fp.exp_only.size()), FT, lds, s>>>(J);
   }
-  J.recs = d_std;
+  J.recs = fp.d_std;
   J.use_ee = 0;
   k_factor<<<1, FT, 5 * (NBP * sizeof(double) + 2 * sizeof(int32_t)), s>>>(J);
-  std::vector<PatchRec> all_rec(exp_only);
-  all_rec.insert(all_rec.end(), std_only.begin(), std_only.end());
-  PatchRec* d_all = upload(c, all_rec);
-  k_sigma<<<nblk(int64_t(all_rec.size()), 64), 64, 0, s>>>(d_all, int(all_rec.size()), sig, sts);
+  std::vector<PatchRec> all_rec(fp.exp_only);
+  all_rec.insert(all_rec.end(), fp.std_only.begin(), fp.std_only.end());
+  fp.d_all = upload(c, all_rec);
+  k_sigma<<<nblk(int64_t(all_rec.size()), 64), 64, 0, s>>>(fp.d_all, int(all_rec.size()), fp.sig, fp.sts);
   CAV_HIP(hipGetLastError());
+  return fp;
+}
 
+void factor_level_release(Ctx& c, FactorPending& fp) {
+  for (void** p : {(void**)&fp.work, (void**)&fp.rs, (void**)&fp.cs, (void**)&fp.sig, (void**)&fp.rowp,
+                   (void**)&fp.kap, (void**)&fp.sts, (void**)&fp.slot_all, (void**)&fp.d_exp, (void**)&fp.d_std,
+                   (void**)&fp.d_all}) {
+    dev_free(c, *p);
+    *p = nullptr;
+  }
+}
+
+void factor_level_finish(Ctx& c, Level& L, FactorPending& fp, int precision, double cond_threshold,
+                         cav_factor_stats* st) {
+  hipStream_t s = c.stream;
+  const int ne = fp.ne;
+  const int N = L.N;
+  const std::vector<PatchRec>& exp_only = fp.exp_only;
+  double* work = fp.work;
+  double* rs = fp.rs;
+  double* cs = fp.cs;
+  int32_t* sig = fp.sig;
+  int32_t* rowp = fp.rowp;
+  PatchRec* d_std = fp.d_std;
+  const int64_t std_slot = fp.std_slot;
   std::vector<double> kap_h(ne + 1);
   std::vector<int32_t> sts_h(ne + 1);
-  CAV_HIP(hipMemcpyAsync(kap_h.data(), kap, kap_h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  CAV_HIP(hipMemcpyAsync(sts_h.data(), sts, sts_h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipMemcpyAsync(kap_h.data(), fp.kap, kap_h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipMemcpyAsync(sts_h.data(), fp.sts, sts_h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   CAV_HIP(hipStreamSynchronize(s));
   for (int e = 0; e <= ne; ++e)
     if (sts_h[e]) {
@@ -832,17 +867,15 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
       if (L.d_citem[f]) dev_free(c, L.d_citem[f]);
       L.d_citem[f] = upload(c, ci);
       if (f == 0) {
-        // the rows of every 64-row item, at item * 64 + row
-        const int64_t nv = 2 * int64_t(L.N) * L.N;
-        std::vector<int4> ir(ci.size() * 64, make_int4(-1, 0, 0, 0));
-        for (size_t w = 0; w < ci.size(); ++w)
-          for (int q = 0; q < 64 && ci[w].r0 + q < ci[w].rec.n; ++q) {
-            const int32_t d = L.slot_dof_h[size_t(ci[w].rec.slot + ci[w].r0 + q)];
-            const bool ee = d < nv;
-            ir[w * 64 + q] = make_int4(d, ee ? int(L.ee.rowptr[d]) : 0, ee ? int(L.ee.rowptr[d + 1]) : 0, 0);
-          }
+        // the rows of every 64-row item, at item * 64 + row (built on the device)
         if (L.d_irow) dev_free(c, L.d_irow);
-        L.d_irow = upload(c, ir);
+        L.d_irow = nullptr;
+        if (!ci.empty()) {
+          L.d_irow = static_cast<int4*>(dev_alloc(c, ci.size() * 64 * sizeof(int4)));
+          k_item_rows<<<nblk(int64_t(ci.size()) * 64, 256), 256, 0, s>>>(L.d_citem[0], int64_t(ci.size()),
+                                                                           L.d_slot_dof, L.d_erow_full,
+                                                                           2 * int64_t(L.N) * L.N, L.d_irow);
+        }
       }
     }
     // two counters per record, one per row-block size: a counter must only
@@ -877,11 +910,9 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
   }
   L.d_rec64 = upload(c, o64);
   L.d_rec32 = upload(c, o32);
-  CAV_HIP(hipStreamSynchronize(s));
-  // scratch is released once the finalize kernels are done
-  for (void* p : {(void*)work, (void*)rs, (void*)cs, (void*)sig, (void*)rowp, (void*)kap, (void*)sts, (void*)d_slot_all,
-                  (void*)d_order, (void*)d_exp, (void*)d_std, (void*)d_all})
-    if (p) dev_free(c, p);
+  // the scratch goes back to the allocator, which reuses a block only after a
+  // device-wide synchronisation (the finalize kernels still read it)
+  factor_level_release(c, fp);
   if (st) {
     st->n_fp64 += int32_t(w64.size());
     st->n_fp32 += int32_t(w32.size());
@@ -889,26 +920,28 @@ cav_status factor_level(Ctx& c, Level& L, int precision, double cond_threshold, 
     st->factor_bytes += a64 * 8 + a32 * 4;
   }
   L.factored = true;
-  return CAV_OK;
 }
 
-cav_status factor_coarse(Ctx& c) {
-  hipStream_t s = c.stream;
+CoarsePending factor_coarse_launch(Ctx& c, hipStream_t s) {
   Level& L = c.lv[0];
   const int N = L.N;
   const int64_t n2 = int64_t(N) * N;
   const int n = int(3 * n2);
   if (n > 4096) throw StatusError(CAV_ERR_INVALID_ARG, "coarsest grid too large for the dense solve (3 N0^2 > 4096)");
-  if (c.d_cinv) dev_free(c, c.d_cinv);
-  c.d_cinv = nullptr;
   c.nc = n;
   // gamma n0^2 matches the Schur complement scale 4 / (h^2 diag(A_stokes))
   const double gamma = 4.0 * L.sc.invh * L.sc.invh / (L.sc.diag * double(n2));
-  double* W = static_cast<double*>(dev_alloc(c, size_t(n) * n * sizeof(double)));
-  double* Dv = static_cast<double*>(dev_alloc(c, size_t(QB) * QB * sizeof(double)));
-  double* R = static_cast<double*>(dev_alloc(c, size_t(QB) * n * sizeof(double)));
-  double* X = static_cast<double*>(dev_alloc(c, size_t(n) * QB * sizeof(double)));
-  int32_t* sts = static_cast<int32_t*>(dev_alloc(c, sizeof(int32_t)));
+  CoarsePending cp;
+  cp.W = static_cast<double*>(dev_alloc(c, size_t(n) * n * sizeof(double)));
+  cp.Dv = static_cast<double*>(dev_alloc(c, size_t(QB) * QB * sizeof(double)));
+  cp.R = static_cast<double*>(dev_alloc(c, size_t(QB) * n * sizeof(double)));
+  cp.X = static_cast<double*>(dev_alloc(c, size_t(n) * QB * sizeof(double)));
+  cp.sts = static_cast<int32_t*>(dev_alloc(c, sizeof(int32_t)));
+  double* W = cp.W;
+  double* Dv = cp.Dv;
+  double* R = cp.R;
+  double* X = cp.X;
+  int32_t* sts = cp.sts;
   CAV_HIP(hipMemsetAsync(sts, 0, sizeof(int32_t), s));
   k_coarse_assemble<<<nblk(int64_t(n) * n), 256, 0, s>>>(W, n, L.sc, gamma);
   if (L.ee.nnz() > 0) k_coarse_add_ee<<<nblk(2 * n2), 256, 0, s>>>(W, n, 2 * n2, L.d_erow_full, L.d_ecol, L.d_eval);
@@ -921,19 +954,28 @@ cav_status factor_coarse(Ctx& c) {
   }
   k_cq_meanfix<<<nblk(n, 64), 256, 0, s>>>(W, n, int(2 * n2));
   CAV_HIP(hipGetLastError());
+  return cp;
+}
+
+void factor_coarse_release(Ctx& c, CoarsePending& cp) {
+  for (void** p : {(void**)&cp.W, (void**)&cp.Dv, (void**)&cp.R, (void**)&cp.X, (void**)&cp.sts}) {
+    dev_free(c, *p);
+    *p = nullptr;
+  }
+}
+
+void factor_coarse_finish(Ctx& c, CoarsePending& cp, hipStream_t s) {
   int32_t sts_h = 0;
-  CAV_HIP(hipMemcpyAsync(&sts_h, sts, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipMemcpyAsync(&sts_h, cp.sts, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   CAV_HIP(hipStreamSynchronize(s));
-  dev_free(c, Dv);
-  dev_free(c, R);
-  dev_free(c, X);
-  dev_free(c, sts);
   if (sts_h) {
-    dev_free(c, W);
+    factor_coarse_release(c, cp);
     throw StatusError(CAV_ERR_SINGULAR_COARSE, "zero or non-finite pivot in the coarsest factorisation");
   }
-  c.d_cinv = W;
-  return CAV_OK;
+  if (c.d_cinv) dev_free(c, c.d_cinv);
+  c.d_cinv = cp.W;
+  cp.W = nullptr;
+  factor_coarse_release(c, cp);
 }
 
 void launch_coarse_solve(const Ctx& c, const double* b, double* x, hipStream_t s) {

@@ -624,7 +624,7 @@ void build_box_patches(int N, const HostCSR& ee, int b, int o, Level& L) {
   st.n_touched = L.n_touched;
 }
 
-void build_patches(int N, const HostCSR& ee, int family, Level& L) {
+void build_patch_sets(int N, const HostCSR& ee, int family, Level& L) {
   L.slot_mask_h.clear();
   const int64_t n2 = int64_t(N) * N, nv = 2 * n2, n = 3 * n2;
   auto U_of = [&](int i, int j, int32_t* U) {
@@ -741,7 +741,10 @@ void build_patches(int N, const HostCSR& ee, int family, Level& L) {
   }
   L.n_exp = int32_t(L.exp_cells.size());
   L.n_slots = int64_t(L.slot_dof_h.size());
+}
 
+void build_patch_tables(int N, const HostCSR& ee, Level& L) {
+  const int64_t n2 = int64_t(N) * N, nv = 2 * n2, n = 3 * n2;
   // unknown -> slots transpose (counting sort, slots ascending within each unknown)
   std::vector<int32_t> nsl(n + 1, 0);
   for (int32_t d : L.slot_dof_h) nsl[d + 1]++;
@@ -794,6 +797,11 @@ void build_patches(int N, const HostCSR& ee, int family, Level& L) {
   }
   st.ee_nnz = ee.nnz();
   st.n_touched = L.n_touched;
+}
+
+void build_patches(int N, const HostCSR& ee, int family, Level& L) {
+  build_patch_sets(N, ee, family, L);
+  build_patch_tables(N, ee, L);
 }
 
 }  // namespace cav
