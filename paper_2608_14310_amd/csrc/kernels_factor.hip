@@ -642,8 +642,10 @@ T* upload(Ctx& c, const std::vector<T>& h) {
 }  // namespace
 
 // Row table of the 64-row cooperative items: entry item * 64 + q holds the
-// unknown of row r0 + q of the item's patch and its E_E entry range (full row
-// pointer, velocity rows only), or -1 past the patch's last row.
+// unknown of row r0 + q of the item's patch, its E_E entry range (full row
+// pointer, velocity rows only) and the row's place in the shared residual
+// buffer (slot index; -1 when the patch has a single item), or unknown -1
+// past the patch's last row.
 __global__ void k_item_rows(const CoopItem* __restrict__ items, int64_t nitems, const int32_t* __restrict__ slot_dof,
                             const int32_t* __restrict__ erow_full, int64_t nv, int4* __restrict__ out) {
   const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
@@ -653,7 +655,8 @@ __global__ void k_item_rows(const CoopItem* __restrict__ items, int64_t nitems, 
   int4 v = make_int4(-1, 0, 0, 0);
   if (it.r0 + q < it.rec.n) {
     const int32_t d = slot_dof[it.rec.slot + it.r0 + q];
-    v = d < nv ? make_int4(d, erow_full[d], erow_full[d + 1], 0) : make_int4(d, 0, 0, 0);
+    const int w = it.rec.n > 64 ? int(it.rec.slot + it.r0 + q) : -1;
+    v = d < nv ? make_int4(d, erow_full[d], erow_full[d + 1], w) : make_int4(d, 0, 0, w);
   }
   out[t] = v;
 }

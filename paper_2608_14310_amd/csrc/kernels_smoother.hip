@@ -164,47 +164,49 @@ __device__ __forceinline__ double krow(int64_t d, const double* __restrict__ x, 
 
 // One phase of the multiplicative sweep over explicit patches: one 1024-thread
 // workgroup per patch. (1) Residual rows r_i = b_i - (K x)_i of all patch
-// unknowns, 16 lanes per row over the row's E_E entries (indices loaded
+// unknowns, MX_G lanes per row over the row's E_E entries (indices loaded
 // before the gathers) and a fixed-tree reduction. (2) delta = K_p^{-1} r as
 // (row, 32-column block) items whose loads are all issued before use, with the
 // block partials summed in block order from LDS. (3) x[dofs] += alpha delta.
 // Patches of one phase share no unknown and no coupling, so nothing races.
-constexpr int MX_G = 16;    // lanes per residual row
-constexpr int MX_PER = 4;   // E_E entries a lane loads at once
+constexpr int MX_G = 8;     // lanes per residual row
+constexpr int MX_PER = 8;   // E_E entries a lane loads at once
 constexpr int MX_CB = 16;   // columns per GEMV item (keeps the tile in registers at 1024 threads)
 constexpr int MX_RB = 64;   // rows per workgroup in the split phase kernels
 
 // Residual rows r = b_d - (K x)_d of the patch unknowns dofs[rr], for rows
-// rr = r0 + u * step (u < MX_R, rr < r1), each computed by one group of MX_G
+// rr = r0 + u * step (u < RR, rr < r1), each computed by one group of MX_G
 // lanes (gl = lane in group): E_E entries strided over the group in rounds of
-// MX_G * MX_PER, indices loaded before the gathers, the stencil part added on
-// lane 0, then a fixed-tree reduction; lane 0 passes each row to `emit`.
-// The MX_R rows of a group are interleaved so that their dependent loads are
-// in flight together; each row's own sequence of operations (and so its
-// value) does not depend on how rows are grouped, which keeps every phase
-// kernel bit-identical.
-constexpr int MX_R = 4;
-template <typename Src, typename Emit>
+// MX_G * MX_PER (64: one round for every row of the beam workloads), indices
+// loaded before the gathers, the stencil part added on lane 0, then a
+// fixed-tree reduction; lane 0 passes each row to `emit` with the fourth
+// field of its row record. The RR rows of a group are interleaved so that
+// their dependent loads are in flight together; each row's own sequence of
+// operations (and so its value) does not depend on how rows are grouped,
+// which keeps every phase kernel bit-identical.
+constexpr int MX_R = 2;
+template <int RR = MX_R, typename Src, typename Emit>
 __device__ __forceinline__ void mx_residual_rows(Src src, int r0, int step, int r1, int gl, StencilCoef sc,
                                                  const int32_t* __restrict__ ecol, const double* __restrict__ eval,
                                                  const double* __restrict__ b, const double* __restrict__ x,
                                                  Emit emit) {
-  int64_t d[MX_R];
-  int q0[MX_R], q1[MX_R];
-  // src(rr) = {unknown (or -1), E_E entry range}: one load per row
+  int64_t d[RR];
+  int q0[RR], q1[RR], qw[RR];
+  // src(rr) = {unknown (or -1), E_E entry range, tag passed to emit}: one load per row
 #pragma unroll
-  for (int u = 0; u < MX_R; ++u) {
+  for (int u = 0; u < RR; ++u) {
     const int rr = r0 + u * step;
     const int4 q = rr < r1 ? src(rr) : make_int4(-1, 0, 0, 0);
     d[u] = q.x;
     q0[u] = q.y;
     q1[u] = q.z;
+    qw[u] = q.w;
   }
   // the stencil part, b and the unknown's own value (lane 0) are loaded now,
   // beside the E_E entries; the sum adds them where it always has
-  double stv[MX_R], bv[MX_R], xd[MX_R];
+  double stv[RR], bv[RR], xd[RR];
 #pragma unroll
-  for (int u = 0; u < MX_R; ++u) {
+  for (int u = 0; u < RR; ++u) {
     const bool own = gl == 0 && d[u] >= 0;
     stv[u] = own ? krow(d[u], x, sc, nullptr, nullptr, nullptr) : 0.0;
     bv[u] = own ? b[d[u]] : 0.0;
@@ -212,39 +214,39 @@ __device__ __forceinline__ void mx_residual_rows(Src src, int r0, int step, int 
   }
   int rounds = 0;
 #pragma unroll
-  for (int u = 0; u < MX_R; ++u) rounds = max(rounds, (q1[u] - q0[u] + MX_G * MX_PER - 1) / (MX_G * MX_PER));
-  double acc[MX_R];
+  for (int u = 0; u < RR; ++u) rounds = max(rounds, (q1[u] - q0[u] + MX_G * MX_PER - 1) / (MX_G * MX_PER));
+  double acc[RR];
 #pragma unroll
-  for (int u = 0; u < MX_R; ++u) acc[u] = 0.0;
+  for (int u = 0; u < RR; ++u) acc[u] = 0.0;
   for (int k0 = 0; k0 < rounds; ++k0) {
-    int cidx[MX_R][MX_PER];
-    double cv[MX_R][MX_PER];
+    int cidx[RR][MX_PER];
+    double cv[RR][MX_PER];
 #pragma unroll
-    for (int u = 0; u < MX_R; ++u)
+    for (int u = 0; u < RR; ++u)
 #pragma unroll
       for (int k = 0; k < MX_PER; ++k) {
         const int q = q0[u] + k0 * MX_G * MX_PER + gl + MX_G * k;
         cidx[u][k] = q < q1[u] ? ecol[q] : -1;
         cv[u][k] = q < q1[u] ? eval[q] : 0.0;
       }
-    double xv[MX_R][MX_PER];
+    double xv[RR][MX_PER];
 #pragma unroll
-    for (int u = 0; u < MX_R; ++u)
+    for (int u = 0; u < RR; ++u)
 #pragma unroll
       for (int k = 0; k < MX_PER; ++k) xv[u][k] = cidx[u][k] >= 0 ? x[cidx[u][k]] : 0.0;
 #pragma unroll
-    for (int u = 0; u < MX_R; ++u)
+    for (int u = 0; u < RR; ++u)
       if (q0[u] + k0 * MX_G * MX_PER < q1[u]) {
 #pragma unroll
         for (int k = 0; k < MX_PER; ++k) acc[u] += cv[u][k] * xv[u][k];
       }
   }
 #pragma unroll
-  for (int u = 0; u < MX_R; ++u) {
+  for (int u = 0; u < RR; ++u) {
     if (gl == 0 && d[u] >= 0) acc[u] += stv[u];
 #pragma unroll
     for (int o = MX_G / 2; o > 0; o >>= 1) acc[u] += __shfl_down(acc[u], o, MX_G);
-    if (gl == 0 && d[u] >= 0) emit(r0 + u * step, bv[u] - acc[u], int32_t(d[u]), xd[u]);
+    if (gl == 0 && d[u] >= 0) emit(r0 + u * step, bv[u] - acc[u], int32_t(d[u]), xd[u], qw[u]);
   }
 }
 
@@ -335,7 +337,7 @@ __device__ __forceinline__ void mx_patch(const MultRec& rec, double* smem, const
   const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
   constexpr int NG = NT / MX_G;
   for (int rb = grp; rb < n; rb += NG * MX_R)
-    mx_residual_rows(src, rb, NG, n, gl, sc, ecol, eval, b, x, [&](int rr, double r, int32_t d, double xv) {
+    mx_residual_rows(src, rb, NG, n, gl, sc, ecol, eval, b, x, [&](int rr, double r, int32_t d, double xv, int) {
       rp[rr] = r;
       xo[rr] = xv;
       dd[rr] = d;
@@ -396,7 +398,7 @@ __global__ __launch_bounds__(256) void k_mult_res(const int2* __restrict__ items
   constexpr int NG = 256 / MX_G;
   for (int rb = r0 + grp; rb < r1; rb += NG * MX_R)
     mx_residual_rows(src, rb, NG, r1, gl, sc, ecol, eval, b, x,
-                     [&](int rr, double r, int32_t, double) { rbuf[rec.slot + rr] = r; });
+                     [&](int rr, double r, int32_t, double, int) { rbuf[rec.slot + rr] = r; });
 }
 
 __global__ __launch_bounds__(256) void k_mult_gemv(const int2* __restrict__ items, const MultRec* __restrict__ recs,
@@ -473,7 +475,7 @@ __global__ __launch_bounds__(1024) void k_mult_coop(const CoopItem* __restrict__
   const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
   constexpr int NG = NT / MX_G;
   for (int rb = grp; rb < n; rb += NG * MX_R)
-    mx_residual_rows(src, rb, NG, n, gl, sc, ecol, eval, b, x, [&](int rr, double r, int32_t d, double xv) {
+    mx_residual_rows(src, rb, NG, n, gl, sc, ecol, eval, b, x, [&](int rr, double r, int32_t d, double xv, int) {
       rp[rr] = r;
       if (rr >= r0 && rr < r0 + nr) {
         xo[rr - r0] = xv;
@@ -574,7 +576,10 @@ __device__ __forceinline__ void mx_gemv_lds(const T* slice, int r0, const double
 // device-coherent loads. Each workgroup's stores have completed (waitcnt)
 // before its arrival, so a workgroup that has seen all k arrivals reads the
 // final values. Rows, items and block order are those of k_mult_exp, so the
-// results equal it bit for bit.
+// results equal it bit for bit. Waves 0 .. 7 form the residual without
+// waiting for the item record (row records hold everything, including the
+// row's place in rbuf); waves 8 .. 15 copy the 64-row slice of the inverse to
+// LDS meanwhile, so no residual load queues behind the copy.
 __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict__ items,
                                                      const int4* __restrict__ irow, const double* __restrict__ a64,
                                                      const float* __restrict__ a32, StencilCoef sc,
@@ -586,57 +591,64 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
   constexpr int NT = 1024, RB = 64;
   extern __shared__ double smem[];
   __shared__ int s_ok;
-  // this item's 64 rows (unknown, E_E range; unknown -1 past the patch) sit at
-  // a fixed place, so their loads do not wait for the item record
+  // this item's 64 rows (unknown, E_E range, place in the shared residual
+  // buffer or -1 for a patch of one item; unknown -1 past the patch) sit at a
+  // fixed place: the residual needs nothing from the item record, whose load
+  // completes meanwhile
   const int4* rows = irow + int64_t(blockIdx.x) * RB;
   const CoopItem it = items[blockIdx.x];
+  // LDS: the prefetched GEMV slice (pf_bytes), this item's pre-update values
+  // and unknowns (fixed offsets), then the residual (n rows) and block partials
+  unsigned char* slice = reinterpret_cast<unsigned char*>(smem);
+  double* xo = smem + pf_bytes / 8;                    // RB values of this item's unknowns before the update
+  int32_t* dd = reinterpret_cast<int32_t*>(xo + RB);   // RB unknowns
+  double* rp = xo + RB + RB / 2;                       // n residual rows
+  // waves 0 .. 7 form the residual (a group of MX_G lanes per row); waves
+  // 8 .. 15 copy this workgroup's 64 rows of the inverse to LDS meanwhile. A
+  // wave's loads complete in order, so no residual load waits behind the copy
+  // or behind the item record the copy needs.
+  constexpr int NR = RB * MX_G;   // residual threads
+  static_assert(NR % 64 == 0 && NR < NT, "residual and copy waves are disjoint");
   const MultRec rec = it.rec;
+  const int sz = rec.f32 ? 4 : 8;
+  auto prefetch = [&](int w0) {
+    const int n = rec.n;
+    if (int64_t(64) * n * sz > pf_bytes) return;
+    if (rec.f32)
+      mx_prefetch_slice<4>(reinterpret_cast<const unsigned char*>(a32 + rec.fac), n, it.r0, slice, w0);
+    else
+      mx_prefetch_slice<8>(reinterpret_cast<const unsigned char*>(a64 + rec.fac), n, it.r0, slice, w0);
+  };
+  if (threadIdx.x < NR) {
+    const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
+    auto src = [rows](int q) { return rows[q]; };
+    mx_residual_rows<1>(src, grp, RB, RB, gl, sc, ecol, eval, b, x, [&](int q, double r, int32_t d, double xv, int w) {
+      if (w >= 0)
+        __hip_atomic_store(rbuf + w, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else
+        rp[q] = r;
+      xo[q] = xv;
+      dd[q] = d;
+    });
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's residual stores and x loads have completed
+  } else {
+    prefetch(NR / 64);
+  }
+  __syncthreads();
   const int n = rec.n;
   const int nb = (n + MX_CB - 1) / MX_CB;
   const int k = (n + RB - 1) / RB;
   const int r0 = it.r0, nr = min(RB, n - r0);
-  // LDS: the prefetched GEMV slice (pf_bytes), then the residual, pre-update
-  // values, block partials and unknowns
-  unsigned char* slice = reinterpret_cast<unsigned char*>(smem);
-  double* rp = smem + pf_bytes / 8;  // n residual rows
-  double* xo = rp + n;               // RB values of this item's unknowns before the update
-  double* pp = xo + RB;              // nb x RB block partials
-  int32_t* dd = reinterpret_cast<int32_t*>(pp + nb * RB);  // RB unknowns
-  // this workgroup's 64 rows of the inverse go to LDS while the residual forms
-  const int sz = rec.f32 ? 4 : 8;
+  double* pp = rp + n;               // nb x RB block partials
   const bool pf = int64_t(64) * n * sz <= pf_bytes;
-  auto prefetch = [&](int w0) {
-    if (!pf) return;
-    if (rec.f32)
-      mx_prefetch_slice<4>(reinterpret_cast<const unsigned char*>(a32 + rec.fac), n, r0, slice, w0);
-    else
-      mx_prefetch_slice<8>(reinterpret_cast<const unsigned char*>(a64 + rec.fac), n, r0, slice, w0);
-  };
-  const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
-  constexpr int NG = NT / MX_G;
-  auto src = [rows](int q) { return rows[q]; };
-  prefetch(0);
   if (k == 1) {
-    for (int rb = grp; rb < RB; rb += NG * MX_R)
-      mx_residual_rows(src, rb, NG, RB, gl, sc, ecol, eval, b, x, [&](int q, double r, int32_t d, double xv) {
-        rp[q] = r;
-        xo[q] = xv;
-        dd[q] = d;
-      });
     __builtin_amdgcn_s_waitcnt(0);   // the slice has landed
     __syncthreads();
   } else {
-    double* rg = rbuf + rec.slot + r0;
-    for (int rb = grp; rb < RB; rb += NG * MX_R)
-      mx_residual_rows(src, rb, NG, RB, gl, sc, ecol, eval, b, x, [&](int q, double r, int32_t d, double xv) {
-        __hip_atomic_store(rg + q, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        xo[q] = xv;
-        dd[q] = d;
-      });
-    __builtin_amdgcn_s_waitcnt(0);   // this wave's stores and x loads have completed
-    __syncthreads();
+    unsigned long long old = 0;
+    if (threadIdx.x == 0)
+      old = __hip_atomic_fetch_add(cnt + it.cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (threadIdx.x == 0) {
-      const unsigned long long old = __hip_atomic_fetch_add(cnt + it.cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const unsigned long long target = (old / unsigned(k) + 1) * unsigned(k);
       int good = 1;
       unsigned spins = 0;
@@ -651,7 +663,10 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
       s_ok = good;
     }
     __syncthreads();
-    if (!s_ok) return;
+    if (!s_ok) {
+      __builtin_amdgcn_s_waitcnt(0);   // no copy into LDS outlives the workgroup
+      return;
+    }
     const double* ra = rbuf + rec.slot;
     for (int j = threadIdx.x; j < n; j += NT) rp[j] = __hip_atomic_load(ra + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_s_waitcnt(0);   // the slice has landed
