@@ -569,6 +569,21 @@ __device__ __forceinline__ void mx_gemv_lds(const T* slice, int r0, const double
   }
 }
 
+// GEMV items of one workgroup's rows read straight from the stored inverse,
+// one item at a time (fewer live registers than the paired form): the same
+// items and arithmetic as mx_gemv_pairs.
+template <typename T, typename IJ, typename Put>
+__device__ __forceinline__ void mx_gemv_single(const T* __restrict__ arena, int64_t fac, const double* __restrict__ rp,
+                                               int n, int count, int stride, IJ ij, Put put) {
+  for (int t = threadIdx.x; t < count; t += stride) {
+    int i, cb;
+    ij(t, i, cb);
+    T m[MX_CB];
+    mx_load_item(arena, fac, n, i, cb, true, m);
+    put(t, mx_dot_item(m, rp, n, cb));
+  }
+}
+
 // Cooperative form with a shared residual: as k_mult_coop<64>, but each of
 // the k workgroups of a patch forms only its own 64 residual rows and stores
 // them to the patch's slots of rbuf with device-coherent stores; after the
@@ -684,9 +699,9 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
       else
         mx_gemv_lds(reinterpret_cast<const double*>(slice), r0, rp, n, nr * nb, NT, ij, put);
     } else if (rec.f32) {
-      mx_gemv_pairs(a32, rec.fac, rp, n, nr * nb, NT, ij, put);
+      mx_gemv_single(a32, rec.fac, rp, n, nr * nb, NT, ij, put);
     } else {
-      mx_gemv_pairs(a64, rec.fac, rp, n, nr * nb, NT, ij, put);
+      mx_gemv_single(a64, rec.fac, rp, n, nr * nb, NT, ij, put);
     }
   }
   __syncthreads();
