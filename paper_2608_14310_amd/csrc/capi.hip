@@ -67,14 +67,19 @@ void* dev_alloc(Ctx& c, size_t bytes) {
   return p;
 }
 
+// The context's two extra streams (default priority) and their events.
+void ensure_aux_streams(Ctx& c) {
+  if (c.side) return;
+  CAV_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+  CAV_HIP(hipStreamCreateWithFlags(&c.fstream, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&c.ev_fork, &c.ev_join, &c.ev_fup, &c.ev_fdone})
+    CAV_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+}
+
 // Start the coarsest factorisation on the side stream after the work queued
 // on c.stream (the operator's upload).
 void start_coarse(Ctx& c) {
-  if (!c.side) {
-    CAV_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
-    CAV_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
-    CAV_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
-  }
+  ensure_aux_streams(c);
   CAV_HIP(hipEventRecord(c.ev_fork, c.stream));
   CAV_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
   c.coarse_pend = factor_coarse_launch(c, c.side);
@@ -601,11 +606,12 @@ cav_status cav_destroy(cav_ctx ctx) {
     (void)hipStreamSynchronize(ctx->c.gstream);
     (void)hipStreamDestroy(ctx->c.gstream);
   }
-  if (ctx->c.side) {
-    (void)hipStreamSynchronize(ctx->c.side);
-    (void)hipStreamDestroy(ctx->c.side);
-  }
-  for (hipEvent_t e : {ctx->c.ev_fork, ctx->c.ev_join})
+  for (hipStream_t s : {ctx->c.side, ctx->c.fstream})
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  for (hipEvent_t e : {ctx->c.ev_fork, ctx->c.ev_join, ctx->c.ev_fup, ctx->c.ev_fdone})
     if (e) (void)hipEventDestroy(e);
   for (auto& kv : ctx->live) (void)hipFree(kv.first);
   release_cache(ctx);
@@ -746,10 +752,13 @@ static cav_status build_family(cav_ctx ctx, int family, int box_b, int box_o, ca
           if (family != CAV_FAMILY_BOX) build_patch_tables(L.N, L.ee, L);
         },
         [&] {
+          ensure_aux_streams(c);
           for (int l = c.n_levels - 1; l >= 1; --l) {
-            c.lv[l].fpend = factor_level_launch(c, c.lv[l]);
+            c.lv[l].fpend = factor_level_launch(c, c.lv[l], c.fstream);
             c.lv[l].fpending = true;
           }
+          CAV_HIP(hipEventRecord(c.ev_fdone, c.fstream));
+          c.fwait = true;
         });
   }
   for (int l = 1; l < c.n_levels; ++l) {
@@ -824,8 +833,12 @@ cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold,
         L.fpend = FactorPending();
         L.fpending = false;
       } else {
-        pend.push_back(factor_level_launch(c, L));
+        pend.push_back(factor_level_launch(c, L, c.stream));
       }
+    }
+    if (c.fwait) {
+      CAV_HIP(hipStreamWaitEvent(c.stream, c.ev_fdone, 0));
+      c.fwait = false;
     }
     for (int l = c.n_levels - 1, k = 0; l >= 1; --l, ++k) factor_level_finish(c, c.lv[l], pend[k], precision,
                                                                              cond_threshold, &st);

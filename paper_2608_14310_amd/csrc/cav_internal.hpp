@@ -247,6 +247,11 @@ struct Ctx {
   hipStream_t gstream = nullptr;
   hipStream_t side = nullptr;            // default-priority stream for the coarsest factorisation
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // stream of the patch factorisations enqueued by the patch build, so that
+  // the build's own uploads on `stream` do not queue behind them
+  hipStream_t fstream = nullptr;
+  hipEvent_t ev_fup = nullptr, ev_fdone = nullptr;
+  bool fwait = false;                     // `stream` must wait for ev_fdone before reading their results
   // the coarsest factorisation starts when the operator is built (it needs
   // nothing else) and is collected by cav_factor_patches
   CoarsePending coarse_pend;
@@ -329,13 +334,14 @@ void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
 void colour_explicit(int N, const HostCSR& ee, Level& L);
 void launch_coarse_solve(const Ctx& c, const double* b, double* x, hipStream_t s);
-// Patch factorisation of one smoothed level in two halves: `launch` enqueues
-// the factorisations on c.stream and returns their scratch; `finish` reads the
+// Patch factorisation of one smoothed level in two halves: `launch` uploads
+// the records on c.stream, enqueues the factorisations on stream ks (after
+// the uploads) and returns their scratch; `finish` reads the
 // condition estimates back (synchronising), splits the precisions, writes the
 // stored inverses and the smoother tables, and releases the scratch. Every
 // level's launch can precede every finish, so the GPU factors all levels
 // back to back. `release` frees a pending level's scratch after a failure.
-FactorPending factor_level_launch(Ctx& c, Level& L);
+FactorPending factor_level_launch(Ctx& c, Level& L, hipStream_t ks);
 void factor_level_finish(Ctx& c, Level& L, FactorPending& fp, int precision, double cond_threshold,
                          cav_factor_stats* st);
 void factor_level_release(Ctx& c, FactorPending& fp);

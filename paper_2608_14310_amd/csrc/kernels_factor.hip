@@ -661,7 +661,7 @@ __global__ void k_item_rows(const CoopItem* __restrict__ items, int64_t nitems, 
   out[t] = v;
 }
 
-FactorPending factor_level_launch(Ctx& c, Level& L) {
+FactorPending factor_level_launch(Ctx& c, Level& L, hipStream_t ks) {
   hipStream_t s = c.stream;
   FactorPending fp;
   const int ne = L.n_exp;
@@ -720,18 +720,22 @@ FactorPending factor_level_launch(Ctx& c, Level& L) {
   for (auto& r : order) (r.id == ne ? fp.std_only : fp.exp_only).push_back(r);
   fp.d_exp = upload(c, fp.exp_only);
   fp.d_std = upload(c, fp.std_only);
-  if (!fp.exp_only.empty()) {
-    J.recs = fp.d_exp;
-    J.use_ee = 1;
-    k_factor<<<unsigned(fp.exp_only.size()), FT, lds, s>>>(J);
-  }
-  J.recs = fp.d_std;
-  J.use_ee = 0;
-  k_factor<<<1, FT, 5 * (NBP * sizeof(double) + 2 * sizeof(int32_t)), s>>>(J);
   std::vector<PatchRec> all_rec(fp.exp_only);
   all_rec.insert(all_rec.end(), fp.std_only.begin(), fp.std_only.end());
   fp.d_all = upload(c, all_rec);
-  k_sigma<<<nblk(int64_t(all_rec.size()), 64), 64, 0, s>>>(fp.d_all, int(all_rec.size()), fp.sig, fp.sts);
+  if (ks != s) {
+    CAV_HIP(hipEventRecord(c.ev_fup, s));
+    CAV_HIP(hipStreamWaitEvent(ks, c.ev_fup, 0));
+  }
+  if (!fp.exp_only.empty()) {
+    J.recs = fp.d_exp;
+    J.use_ee = 1;
+    k_factor<<<unsigned(fp.exp_only.size()), FT, lds, ks>>>(J);
+  }
+  J.recs = fp.d_std;
+  J.use_ee = 0;
+  k_factor<<<1, FT, 5 * (NBP * sizeof(double) + 2 * sizeof(int32_t)), ks>>>(J);
+  k_sigma<<<nblk(int64_t(all_rec.size()), 64), 64, 0, ks>>>(fp.d_all, int(all_rec.size()), fp.sig, fp.sts);
   CAV_HIP(hipGetLastError());
   return fp;
 }
