@@ -211,3 +211,59 @@ def test_barrier_wait_bound_reports_and_recovers(cav):
     g.close()
     assert i1["converged"] and i1["iterations"] == i0["iterations"]
     np.testing.assert_array_equal(x1.cpu().numpy(), x0.cpu().numpy())
+
+
+def test_setup_sequences_reproduce_a_fresh_context(cav):
+    """The setup keeps work in flight between calls (coarsest factorisation
+    started by build_operator, patch factorisations started by the patch
+    build) and reuses released device memory. Every call sequence gives
+    results bit-identical to a fresh context: patches rebuilt without a
+    factorisation in between (pending work released), a second factorisation
+    with another precision (coarsest inverse kept), a rebuilt operator of
+    another system (everything restarted, memory reused), and back."""
+    print("[edge] setup sequences", flush=True)
+    sa = workloads.beam_fibres(64, 2, 1.0, 1e4, seed=0)
+    sb = workloads.membrane_ellipse(32, 3, 1e4, 1)
+
+    def fresh(s, precision):
+        g = cav.Solver(0)
+        g.setup(s, precision=precision, alpha=1.0, smoother="multiplicative")
+        x, inf = g.fgmres_solve(_t(s.b), 1e-10, 150)
+        z = g.vcycle(_t(s.b))
+        torch.cuda.synchronize()
+        out = (x.cpu().numpy(), z.cpu().numpy(), inf["iterations"])
+        g.close()
+        return out
+
+    ref = {(s.name, p): fresh(s, p) for s in (sa, sb) for p in ("fp64", "mixed")}
+    g = cav.Solver(0)
+
+    def check(s, precision):
+        x, inf = g.fgmres_solve(_t(s.b), 1e-10, 150)
+        z = g.vcycle(_t(s.b))
+        torch.cuda.synchronize()
+        rx, rz, rits = ref[(s.name, precision)]
+        assert inf["iterations"] == rits, (s.name, precision)
+        assert np.array_equal(x.cpu().numpy(), rx), (s.name, precision)
+        assert np.array_equal(z.cpu().numpy(), rz), (s.name, precision)
+
+    g.build_operator(sa)
+    g.build_cav_patches("cav")
+    g.build_cav_patches("cav")                 # pending factorisations released, enqueued again
+    g.factor_patches("fp64", 1e6)
+    g.set_smoother("multiplicative", 1.0)
+    check(sa, "fp64")
+    g.factor_patches("mixed", 1e6)             # coarsest inverse kept, patches factored again
+    g.set_smoother("multiplicative", 1.0)
+    check(sa, "mixed")
+    g.build_operator(sb)                       # another hierarchy: released memory reused
+    g.build_cav_patches("cav")
+    g.factor_patches("mixed", 1e6)
+    g.set_smoother("multiplicative", 1.0)
+    check(sb, "mixed")
+    g.build_operator(sa)
+    g.build_cav_patches("cav")
+    g.factor_patches("fp64", 1e6)
+    g.set_smoother("multiplicative", 1.0)
+    check(sa, "fp64")
+    g.close()
