@@ -133,32 +133,40 @@ __global__ __launch_bounds__(TPB) void k_update(double* __restrict__ x, const do
 
 inline unsigned nblocks(int64_t n) { return unsigned((n + TPB - 1) / TPB); }
 
-// (K_E x)_d for one unknown: MAC stencil row plus the -dt E_E row.
+// Stencil part of (K_E x) for the unknown of kind kind (0 u, 1 v, 2 p) at
+// cell (i, j), without branches: the seven stencil values are loaded at once
+// (rows of u and v take their own component's five values and p at the cell
+// and its upwind neighbour; p rows take u at the cell and (i+1, j) and v at
+// the cell and (i, j+1) in the same slots), both formulas are evaluated with
+// the expressions of the MAC stencil, and the kind picks one. Rows of several
+// kinds in one wave then cost one round of loads, not one per kind.
+__device__ __forceinline__ double krow_at(int kind, int i, int j, const double* __restrict__ x, const StencilCoef& sc) {
+  const int N = sc.N;
+  const int64_t n2 = int64_t(N) * N;
+  const int ip = wrapi(i + 1, N), im = wrapi(i - 1, N), jp = wrapi(j + 1, N), jm = wrapi(j - 1, N);
+  auto C = [N](int a, int b) { return int64_t(a) * N + b; };
+  const int64_t c = C(i, j);
+  const double* w = x + (kind == 1 ? n2 : 0);              // u (u and p rows) or v (v rows)
+  const double* q = x + (kind == 2 ? n2 : 2 * n2);         // p (u and v rows) or v (p rows)
+  const int64_t q1 = kind == 0 ? C(im, j) : kind == 1 ? C(i, jm) : C(i, jp);
+  const double a0 = w[c], a1 = w[C(ip, j)], a2 = w[C(im, j)], a3 = w[C(i, jp)], a4 = w[C(i, jm)];
+  const double b0 = q[c], b1 = q[q1];
+  const double rp = -sc.invh * ((a1 - a0) + (b1 - b0));
+  const double ruv = sc.diag * a0 - sc.off * (a1 + a2 + a3 + a4) + sc.invh * (b0 - b1);
+  return kind == 2 ? rp : ruv;
+}
+
+// (K_E x)_d for one unknown d >= 0 (3 N^2 < 2^31, so 32-bit divisions): MAC
+// stencil row plus the -dt E_E row.
 __device__ __forceinline__ double krow(int64_t d, const double* __restrict__ x, const StencilCoef& sc,
                                        const int32_t* __restrict__ erow, const int32_t* __restrict__ ecol,
                                        const double* __restrict__ eval) {
-  const int N = sc.N;
-  const int64_t n2 = int64_t(N) * N;
-  const int t = int(d / n2);
-  const int64_t c = d - t * n2;
-  const int i = int(c / N), j = int(c % N);
-  const int ip = wrapi(i + 1, N), im = wrapi(i - 1, N), jp = wrapi(j + 1, N), jm = wrapi(j - 1, N);
-  auto C = [N](int a, int b) { return int64_t(a) * N + b; };
-  const double* u = x;
-  const double* v = x + n2;
-  const double* p = x + 2 * n2;
-  double acc;
-  if (t == 0) {
-    acc = sc.diag * u[c] - sc.off * (u[C(ip, j)] + u[C(im, j)] + u[C(i, jp)] + u[C(i, jm)]) +
-          sc.invh * (p[c] - p[C(im, j)]);
-  } else if (t == 1) {
-    acc = sc.diag * v[c] - sc.off * (v[C(ip, j)] + v[C(im, j)] + v[C(i, jp)] + v[C(i, jm)]) +
-          sc.invh * (p[c] - p[C(i, jm)]);
-  } else {
-    return -sc.invh * ((u[C(ip, j)] - u[c]) + (v[C(i, jp)] - v[c]));
-  }
-  if (erow)
-    for (int q = erow[d]; q < erow[d + 1]; ++q) acc += eval[q] * x[ecol[q]];
+  const uint32_t N = uint32_t(sc.N), n2 = N * N, ud = uint32_t(d);
+  const int kind = int(ud / n2);
+  const uint32_t c = ud - uint32_t(kind) * n2;
+  double acc = krow_at(kind, int(c / N), int(c % N), x, sc);
+  if (erow && kind < 2)
+    for (int k = erow[d]; k < erow[d + 1]; ++k) acc += eval[k] * x[ecol[k]];
   return acc;
 }
 
@@ -847,11 +855,18 @@ __device__ __forceinline__ void std_cell(int N, int colour, int64_t t, const uin
   const int j = ((3 * (colour - i)) % 8 + 8) % 8 + 8 * m;
   const int64_t n2 = int64_t(N) * N;
   const int64_t c = int64_t(i) * N + j;
-  if (flag[c] & 1) return;
-  const int64_t d[5] = {c, int64_t(wrapi(i + 1, N)) * N + j, n2 + c, n2 + int64_t(i) * N + wrapi(j + 1, N), 2 * n2 + c};
-  double r[5];
+  // the cell's flag loads beside the gathers (a cell with E_E entries is
+  // computed too and not written), so the gathers do not wait for it
+  const uint8_t fl = flag[c];
+  const int ip = wrapi(i + 1, N), jp = wrapi(j + 1, N);
+  const int64_t d[5] = {c, int64_t(ip) * N + j, n2 + c, n2 + int64_t(i) * N + jp, 2 * n2 + c};
+  const int kind[5] = {0, 0, 1, 1, 2}, ci[5] = {i, ip, i, i, i}, cj[5] = {j, j, j, jp, j};
+  double r[5], xv[5];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) r[q] = b[d[q]] - krow(d[q], x, sc, nullptr, nullptr, nullptr);
+  for (int q = 0; q < 5; ++q) {
+    r[q] = b[d[q]] - krow_at(kind[q], ci[q], cj[q], x, sc);
+    xv[q] = x[d[q]];
+  }
   double dl[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
@@ -860,8 +875,14 @@ __device__ __forceinline__ void std_cell(int N, int colour, int64_t t, const uin
     for (int m = 0; m < 5; ++m) s += Minv[q + 5 * m] * r[m];
     dl[q] = s;
   }
+  // an empty statement that takes the updates and old values as inputs: the
+  // compiler must form them (and so issue every load) before it branches on
+  // the flag
+  asm volatile("" ::"v"(dl[0]), "v"(dl[1]), "v"(dl[2]), "v"(dl[3]), "v"(dl[4]), "v"(xv[0]), "v"(xv[1]), "v"(xv[2]),
+               "v"(xv[3]), "v"(xv[4]));
+  if (fl & 1) return;
 #pragma unroll
-  for (int q = 0; q < 5; ++q) x[d[q]] += alpha * dl[q];
+  for (int q = 0; q < 5; ++q) x[d[q]] = xv[q] + alpha * dl[q];
 }
 
 __global__ __launch_bounds__(TPB) void k_mult_std(int N, int colour, const uint8_t* __restrict__ flag,
