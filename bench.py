@@ -384,15 +384,22 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / a.steps
 
-    # the dominant explicit-patch kernel: the cooperative-form phase kernel when
-    # its brackets hold most of the time, else the one-workgroup form
+    # the dominant explicit-patch kernel: the shared-residual form when its
+    # brackets hold most of the time, else the other cooperative forms, else
+    # the one-workgroup form
     co_ms = sum(r["kt"]["coop_ms"] for r in runs)
+    sh_ms = sum(r["kt"]["shared_ms"] for r in runs)
     all_ms = sum(r["kt"]["ms"] for r in runs)
-    if co_ms > all_ms - co_ms:
-        kernel = {"coop64": "k_mult_coop<64>", "coop128": "k_mult_coop<128>"}.get(a.tune, "k_mult_coopr")
-        kb_bytes = sum(r["kt"]["coop_bytes"] for r in runs)
-        kb_ms = co_ms
-        kb_launch = sum(r["kt"]["coop_launches"] for r in runs)
+    if sh_ms > all_ms - sh_ms:
+        kernel = "k_mult_coopr"
+        kb_bytes = sum(r["kt"]["shared_bytes"] for r in runs)
+        kb_ms = sh_ms
+        kb_launch = sum(r["kt"]["shared_launches"] for r in runs)
+    elif co_ms > all_ms - co_ms:
+        kernel = {"coop64": "k_mult_coop<64>", "coop128": "k_mult_coop<128>"}.get(a.tune, "k_mult_coop")
+        kb_bytes = sum(r["kt"]["coop_bytes"] - r["kt"]["shared_bytes"] for r in runs)
+        kb_ms = co_ms - sh_ms
+        kb_launch = sum(r["kt"]["coop_launches"] - r["kt"]["shared_launches"] for r in runs)
     else:
         kernel = "k_mult_exp" if a.smoother == "multiplicative" else "k_patch_apply"
         kb_bytes = sum(r["kt"]["bytes"] - r["kt"]["coop_bytes"] for r in runs)

@@ -339,6 +339,9 @@ typedef struct {
   int64_t coop_launches;   /* of the above: cooperative-form phase launches */
   double coop_ms;
   double coop_bytes;
+  int64_t shared_launches; /* of those: the shared-residual form (entry 3) */
+  double shared_ms;
+  double shared_bytes;
 } cav_kernel_timing_info;
 cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* out);
 

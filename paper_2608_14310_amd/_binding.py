@@ -76,7 +76,8 @@ class BatchStats(C.Structure):
 class KernelTiming(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double), ("vcycles", C.c_int64),
                 ("vcycle_ms", C.c_double), ("coop_launches", C.c_int64), ("coop_ms", C.c_double),
-                ("coop_bytes", C.c_double)]
+                ("coop_bytes", C.c_double), ("shared_launches", C.c_int64), ("shared_ms", C.c_double),
+                ("shared_bytes", C.c_double)]
 
 
 _P = C.c_void_p

@@ -1121,6 +1121,11 @@ cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* ou
         out->coop_ms += ms;
         out->coop_bytes += m.bytes;
       }
+      if (m.coop == 2) {
+        out->shared_launches += m.launches;
+        out->shared_ms += ms;
+        out->shared_bytes += m.bytes;
+      }
     }
     for (auto& m : c.vc_marks) {
       float ms = 0.f;

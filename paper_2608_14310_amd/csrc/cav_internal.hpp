@@ -276,7 +276,7 @@ struct Ctx {
     int ev;          // event index of the start (the end is ev + 1)
     double bytes;    // algorithmic bytes of the bracketed launches
     int launches;    // launches inside the bracket
-    int coop;        // 1: cooperative-form phase launches
+    int coop;        // 1: cooperative-form phase launches (64/128 rows), 2: shared-residual form
   };
   std::vector<KtMark> kt_marks;
   std::vector<std::pair<int, int>> vc_marks;      // event indices around each V-cycle

@@ -1072,7 +1072,7 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
     double bytes = 0.0;
     for (int ph = 0; ph < nph; ++ph) {
       const int nt = phase_form(c, L, L.mx_nt[mx_bucket(L.ph_maxn[ph])]);
-      const int kind = (nt == 1 || nt == 2 || nt == 3) ? 1 : 0;
+      const int kind = nt == 3 ? 2 : (nt == 1 || nt == 2) ? 1 : 0;   // shared residual / cooperative / other
       if (kind != open) {
         if (open >= 0) timing_end(c, s, bytes, cnt);
         timing_begin(c, s, kind);

@@ -267,3 +267,21 @@ def test_setup_sequences_reproduce_a_fresh_context(cav):
     g.set_smoother("multiplicative", 1.0)
     check(sa, "fp64")
     g.close()
+
+
+def test_kernel_timing_brackets(cav):
+    """Live timing: brackets around runs of phase launches of one form; the
+    shared-residual form is a part of the cooperative forms, which are a part
+    of all phase launches; one top-level V-cycle is counted."""
+    print("[edge] kernel timing", flush=True)
+    s = workloads.beam_fibres(N=64, n_levels=4, kappa_b=1e-2)
+    g = cav.Solver(0)
+    g.setup(s, precision="fp64", alpha=1.0, smoother="multiplicative")
+    g.kernel_timing(True)
+    g.vcycle(_t(s.b))
+    kt = g.kernel_timing(False)
+    g.close()
+    assert kt["vcycles"] == 1 and kt["vcycle_ms"] > 0
+    assert 0 < kt["shared_launches"] <= kt["coop_launches"] <= kt["launches"]
+    assert 0 < kt["shared_ms"] <= kt["coop_ms"] <= kt["ms"]
+    assert 0 < kt["shared_bytes"] <= kt["coop_bytes"] <= kt["bytes"]
