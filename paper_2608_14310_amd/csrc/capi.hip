@@ -72,7 +72,7 @@ void ensure_aux_streams(Ctx& c) {
   if (c.side) return;
   CAV_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
   CAV_HIP(hipStreamCreateWithFlags(&c.fstream, hipStreamNonBlocking));
-  for (hipEvent_t* e : {&c.ev_fork, &c.ev_join, &c.ev_fup, &c.ev_fdone})
+  for (hipEvent_t* e : {&c.ev_fork, &c.ev_join, &c.ev_fup, &c.ev_fdone, &c.ev_fdone2})
     CAV_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
 }
 
@@ -611,7 +611,7 @@ cav_status cav_destroy(cav_ctx ctx) {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);
     }
-  for (hipEvent_t e : {ctx->c.ev_fork, ctx->c.ev_join, ctx->c.ev_fup, ctx->c.ev_fdone})
+  for (hipEvent_t e : {ctx->c.ev_fork, ctx->c.ev_join, ctx->c.ev_fup, ctx->c.ev_fdone, ctx->c.ev_fdone2})
     if (e) (void)hipEventDestroy(e);
   for (auto& kv : ctx->live) (void)hipFree(kv.first);
   release_cache(ctx);
@@ -754,10 +754,13 @@ static cav_status build_family(cav_ctx ctx, int family, int box_b, int box_o, ca
         [&] {
           ensure_aux_streams(c);
           for (int l = c.n_levels - 1; l >= 1; --l) {
-            c.lv[l].fpend = factor_level_launch(c, c.lv[l], c.fstream);
+            // the finest level on its own stream; the smaller ones on the side
+            // stream (behind the coarsest factorisation), beside the finest's tail
+            c.lv[l].fpend = factor_level_launch(c, c.lv[l], l == c.n_levels - 1 ? c.fstream : c.side);
             c.lv[l].fpending = true;
           }
           CAV_HIP(hipEventRecord(c.ev_fdone, c.fstream));
+          CAV_HIP(hipEventRecord(c.ev_fdone2, c.side));
           c.fwait = true;
         });
   }
@@ -838,6 +841,7 @@ cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold,
     }
     if (c.fwait) {
       CAV_HIP(hipStreamWaitEvent(c.stream, c.ev_fdone, 0));
+      CAV_HIP(hipStreamWaitEvent(c.stream, c.ev_fdone2, 0));
       c.fwait = false;
     }
     for (int l = c.n_levels - 1, k = 0; l >= 1; --l, ++k) factor_level_finish(c, c.lv[l], pend[k], precision,

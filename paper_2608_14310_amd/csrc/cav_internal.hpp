@@ -250,8 +250,8 @@ struct Ctx {
   // stream of the patch factorisations enqueued by the patch build, so that
   // the build's own uploads on `stream` do not queue behind them
   hipStream_t fstream = nullptr;
-  hipEvent_t ev_fup = nullptr, ev_fdone = nullptr;
-  bool fwait = false;                     // `stream` must wait for ev_fdone before reading their results
+  hipEvent_t ev_fup = nullptr, ev_fdone = nullptr, ev_fdone2 = nullptr;
+  bool fwait = false;                     // `stream` must wait for ev_fdone and ev_fdone2 before reading their results
   // the coarsest factorisation starts when the operator is built (it needs
   // nothing else) and is collected by cav_factor_patches
   CoarsePending coarse_pend;
