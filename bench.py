@@ -301,6 +301,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="systems in the batched leg (0: skip)")
     ap.add_argument("--learned-pairs", type=int, default=600, help="training pairs of the learned leg (0: skip)")
     ap.add_argument("--learned-steps", type=int, default=600)
+    ap.add_argument("--multi-rhs", type=int, default=64,
+                    help="right-hand sides of the multi-RHS V-cycle leg, blocks of 16 (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, help="run only a plain copy of this many bytes")
@@ -457,6 +459,29 @@ def main():
             "precision": other, "t_total_ms": round(1e3 * (o["build"] + o["patches"] + o["factor"] + o["solve"]), 1),
             "t_solve_ms": round(1e3 * o["solve"], 1), "its": o["its"], "true": o["true"],
             "n_fp32_patches": o["fst"]["n_fp32"], "n_fp64_patches": o["fst"]["n_fp64"]}
+    if a.multi_rhs > 0:
+        # the V-cycle on blocks of 16 right-hand sides (explicit phases as FP64
+        # MFMA products) against one cycle per column, outside the timed steps
+        setup(a.precision)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(5)
+        R = torch.randn((a.multi_rhs, b.numel()), generator=gen, dtype=torch.float64, device=dev)
+        g.vcycle_multi(R[:16])
+        g.vcycle(R[0])
+        torch.cuda.synchronize()
+        t0m = time.perf_counter()
+        Z = g.vcycle_multi(R)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0m
+        t0c = time.perf_counter()
+        Zs = [g.vcycle(R[q]) for q in range(a.multi_rhs)]
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t0c
+        diff = max(float((Z[q] - Zs[q]).abs().max() / Zs[q].abs().max()) for q in range(a.multi_rhs))
+        line["multi_rhs"] = {"columns": a.multi_rhs, "block": 16,
+                             "ms_per_column": round(1e3 * tm / a.multi_rhs, 3),
+                             "single_cycle_ms_per_column": round(1e3 * tc / a.multi_rhs, 3),
+                             "speedup": round(tc / tm, 2), "max_rel_diff_vs_single": float("%.3g" % diff)}
     sweep = []
     for kb in a.stiff_sweep:
         sk = workloads.beam_512(kb)
