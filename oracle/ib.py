@@ -124,7 +124,16 @@ def segment_elasticity(law: str, kappa: dict, M: int, closed: bool, ds: float) -
 
 def elasticity(system) -> sp.csr_matrix:
     """Lagrangian E (2M x 2M, component-interleaved): each segment's scalar law
-    on both components, no coupling between components or segments."""
+    on both components, no coupling between components or segments; for the
+    flexible fibre (Section 5.3) the tangent of its nonlinear force, which
+    couples the components (oracle.fibre)."""
+    if system.law == "fibre":
+        from . import fibre
+        (seg,) = system.segments
+        k = system.kappa
+        p = dict(ds=seg.ds, EI=k["EI"], K_s=k["K_s"], K_p=k["K_p"], K_t=k["K_t"], m=int(k["m"]),
+                 Xc=np.array([k["clamp_x"], k["clamp_y"]]))
+        return fibre.tangent(np.asarray(seg.X, dtype=np.float64).ravel(), p)
     blocks = [segment_elasticity(system.law, system.kappa, len(s.X), s.closed, s.ds)
               for s in system.segments]
     Es = sp.block_diag(blocks, format="csr")
