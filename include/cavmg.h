@@ -54,9 +54,20 @@ typedef enum {
  *               (bending by second differences plus stretching springs, free ends)
  *  CSR          caller supplies E (2M x 2M, component-interleaved: row 2k+c is
  *               marker k, component c); E must be structurally symmetric and
- *               W E symmetric negative semidefinite for the method's guarantees. */
+ *               W E symmetric negative semidefinite for the method's guarantees.
+ *  FIBRE        the clamped flexible fibre of Section 5.3, linearised at X: with
+ *               links D_k = X_{k+1} - X_k and ds = seg_ds[0], the energies
+ *               bending    kappa_b/(2 ds^5) sum_k (D_k x D_{k+1})^2,
+ *               stretching kappa_s/(2 ds) sum_k (|D_k| - ds)^2,
+ *               position   K_p/2 |X_m - (clamp_x, clamp_y)|^2,
+ *               tangent    K_t/2 |(X_{m+1} - X_{m-1})/(2 ds) - (1, 0)|^2
+ *               (m = clamp_marker) give the force F = -(1/ds) grad(sum), and
+ *               E = DF = -(1/ds) Hess(sum) couples the two components.
+ *               One open segment, M >= 3, 1 <= m <= M-2; X is taken as given
+ *               (unwrapped) in the energies. Every 2 x 2 block of markers at
+ *               most two apart is stored, zero or not. */
 enum { CAV_LAW_TARGET = 0, CAV_LAW_MEMBRANE = 1, CAV_LAW_BEAM_CLOSED = 2, CAV_LAW_BEAM_OPEN = 3,
-       CAV_LAW_CSR = 4 };
+       CAV_LAW_CSR = 4, CAV_LAW_FIBRE = 5 };
 
 enum { CAV_FAMILY_CAV = 0, CAV_FAMILY_VANKA = 1, CAV_FAMILY_BOX = 2 };  /* patch families (Section 3) */
 /* Smoothers: ADDITIVE is the weighted additive sweep of Appendix A
@@ -90,6 +101,9 @@ typedef struct {
   const int32_t* E_rowptr; /* host, 2M+1 */
   const int32_t* E_col;    /* host, E_nnz */
   const double* E_val;     /* host, E_nnz */
+  double K_p, K_t;         /* CAV_LAW_FIBRE only: clamp position and tangent penalties */
+  int32_t clamp_marker;    /* CAV_LAW_FIBRE only: the clamped marker m */
+  double clamp_x, clamp_y; /* CAV_LAW_FIBRE only: the clamp point */
 } cav_structure_desc;
 
 typedef struct {           /* per smoothed level (index = level, 0 unused) */

@@ -26,7 +26,7 @@ class CAVError(RuntimeError):
         self.status = status
 
 
-CAV_LAW = {"target": 0, "membrane": 1, "beam_closed": 2, "beam_open": 3, "csr": 4}
+CAV_LAW = {"target": 0, "membrane": 1, "beam_closed": 2, "beam_open": 3, "csr": 4, "fibre": 5}
 FAMILY = {"cav": 0, "vanka": 1, "box": 2}
 SMOOTHER = {"additive": 0, "multiplicative": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
@@ -44,7 +44,8 @@ class StructureDesc(C.Structure):
                 ("n_segments", C.c_int32), ("seg_start", C.POINTER(C.c_int32)),
                 ("seg_closed", C.POINTER(C.c_int32)), ("seg_ds", C.POINTER(C.c_double)),
                 ("E_nnz", C.c_int32), ("E_rowptr", C.POINTER(C.c_int32)), ("E_col", C.POINTER(C.c_int32)),
-                ("E_val", C.POINTER(C.c_double))]
+                ("E_val", C.POINTER(C.c_double)), ("K_p", C.c_double), ("K_t", C.c_double),
+                ("clamp_marker", C.c_int32), ("clamp_x", C.c_double), ("clamp_y", C.c_double)]
 
 
 class LevelStats(C.Structure):
@@ -181,8 +182,13 @@ def describe_structure(system):
     d.omega = _arr(om, C.c_double)
     d.law = CAV_LAW[system.law]
     d.kappa_t = float(k.get("kappa_t", 0.0))
-    d.kappa_s = float(k.get("kappa_s", 0.0))
-    d.kappa_b = float(k.get("kappa_b", 0.0))
+    d.kappa_s = float(k.get("kappa_s", k.get("K_s", 0.0)))
+    d.kappa_b = float(k.get("kappa_b", k.get("EI", 0.0)))
+    d.K_p = float(k.get("K_p", 0.0))
+    d.K_t = float(k.get("K_t", 0.0))
+    d.clamp_marker = int(k.get("m", 0))
+    d.clamp_x = float(k.get("clamp_x", 0.0))
+    d.clamp_y = float(k.get("clamp_y", 0.0))
     d.n_segments = len(segs)
     d.seg_start = _arr(start, C.c_int32)
     d.seg_closed = _arr(closed, C.c_int32)

@@ -181,6 +181,101 @@ void segment_law(int law, double kt, double ks, double kb, int m0, int M, bool c
 
 }  // namespace
 
+// Tangent of the clamped flexible fibre's force (Section 5.3). The force is
+// F = -(1/ds) grad(U) for the total energy U of the bending, stretching,
+// position and tangent terms, so E = -(1/ds) Hess(U). Each term's Hessian is
+// formed from its own variables (link vectors, or the clamp coordinates) and
+// scattered onto the markers it involves; the stored pattern is every 2 x 2
+// block of markers at most two apart.
+namespace {
+cav_status fibre_law(const cav_structure_desc* st, Structure& s, std::string& err) {
+  const int M = s.M;
+  if (st->n_segments != 1 || !st->seg_start || !st->seg_closed || !st->seg_ds) {
+    err = "fibre law needs exactly one segment"; return CAV_ERR_INVALID_ARG;
+  }
+  if (st->seg_start[0] != 0 || st->seg_start[1] != M) { err = "seg_start must run from 0 to M"; return CAV_ERR_INVALID_ARG; }
+  if (st->seg_closed[0]) { err = "fibre law needs an open segment"; return CAV_ERR_INVALID_ARG; }
+  if (M < 3) { err = "fibre law needs M >= 3"; return CAV_ERR_INVALID_ARG; }
+  const int m = st->clamp_marker;
+  if (m < 1 || m > M - 2) { err = "clamp_marker must lie in [1, M-2]"; return CAV_ERR_INVALID_ARG; }
+  const double ds = st->seg_ds[0];
+  if (!(ds > 0) || !std::isfinite(ds)) { err = "segment spacing must be positive"; return CAV_ERR_INVALID_ARG; }
+  const double EI = st->kappa_b, Ks = st->kappa_s, Kp = st->K_p, Kt = st->K_t;
+  for (double v : {EI, Ks, Kp, Kt, st->clamp_x, st->clamp_y})
+    if (!std::isfinite(v)) { err = "non-finite fibre parameter"; return CAV_ERR_INVALID_ARG; }
+  // band storage: B[i][d][a][b] = Hess(U) block (marker i, marker i+d-2), d in 0..4
+  std::vector<double> B(size_t(M) * 5 * 4, 0.0);
+  auto blk = [&](int i, int j, int a, int b) -> double& {
+    return B[((size_t(i) * 5 + size_t(j - i + 2)) * 2 + a) * 2 + b];
+  };
+  const double* X = s.X.data();
+  auto link = [&](int k, int c) { return X[2 * (k + 1) + c] - X[2 * k + c]; };
+  // stretching: U_k = Ks/(2ds) (|d|-ds)^2 with d = X_{k+1} - X_k;
+  // d2U_k/dd2 = (Ks/ds) [ (1 - ds/|d|) I + ds d d^T / |d|^3 ]
+  for (int k = 0; k + 1 < M; ++k) {
+    const double d[2] = {link(k, 0), link(k, 1)};
+    const double len = std::hypot(d[0], d[1]);
+    if (!(len > 0)) { err = "coincident fibre markers"; return CAV_ERR_INVALID_ARG; }
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const double A = Ks / ds * ((a == b ? 1.0 - ds / len : 0.0) + ds * d[a] * d[b] / (len * len * len));
+        blk(k, k, a, b) += A;
+        blk(k + 1, k + 1, a, b) += A;
+        blk(k, k + 1, a, b) -= A;
+        blk(k + 1, k, a, b) -= A;
+      }
+  }
+  // bending: U_k = EI/(2ds^5) c^2, c = p0 q1 - p1 q0 with p = D_k, q = D_{k+1};
+  // in the variables v = (p0, p1, q0, q1): grad c = (q1, -q0, -p1, p0) and
+  // Hess c has +1 at (p0, q1), -1 at (p1, q0) and their transposes.
+  // Marker k+r moves p by sp[r] and q by sq[r].
+  static const double sp[3] = {-1.0, 1.0, 0.0}, sq[3] = {0.0, -1.0, 1.0};
+  const double wb = EI / std::pow(ds, 5);
+  for (int k = 0; k + 2 < M; ++k) {
+    const double p0 = link(k, 0), p1 = link(k, 1), q0 = link(k + 1, 0), q1 = link(k + 1, 1);
+    const double c = p0 * q1 - p1 * q0;
+    const double g[4] = {q1, -q0, -p1, p0};
+    double Hv[4][4];
+    for (int u = 0; u < 4; ++u)
+      for (int v = 0; v < 4; ++v) Hv[u][v] = wb * g[u] * g[v];
+    Hv[0][3] += wb * c; Hv[3][0] += wb * c;
+    Hv[1][2] -= wb * c; Hv[2][1] -= wb * c;
+    for (int r = 0; r < 3; ++r)
+      for (int t = 0; t < 3; ++t)
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b)
+            blk(k + r, k + t, a, b) += sp[r] * sp[t] * Hv[a][b] + sp[r] * sq[t] * Hv[a][2 + b] +
+                                       sq[r] * sp[t] * Hv[2 + a][b] + sq[r] * sq[t] * Hv[2 + a][2 + b];
+  }
+  // position penalty on marker m; tangent penalty on the central difference
+  // g = (X_{m+1} - X_{m-1})/(2ds): d2/dX2 of Kt/2 |g - e_x|^2 = Kt/(4ds^2) [[I, -I], [-I, I]]
+  const double wt = Kt / (4.0 * ds * ds);
+  for (int a = 0; a < 2; ++a) {
+    blk(m, m, a, a) += Kp;
+    blk(m - 1, m - 1, a, a) += wt;
+    blk(m + 1, m + 1, a, a) += wt;
+    blk(m - 1, m + 1, a, a) -= wt;
+    blk(m + 1, m - 1, a, a) -= wt;
+  }
+  HostCSR& E = s.E;
+  E.rowptr.assign(E.n + 1, 0);
+  E.col.clear();
+  E.val.clear();
+  for (int i = 0; i < M; ++i)
+    for (int a = 0; a < 2; ++a) {
+      for (int j = std::max(0, i - 2); j <= std::min(M - 1, i + 2); ++j)
+        for (int b = 0; b < 2; ++b) {
+          const double v = -blk(i, j, a, b) / ds;
+          if (!std::isfinite(v)) { err = "non-finite E value"; return CAV_ERR_INVALID_ARG; }
+          E.col.push_back(2 * j + b);
+          E.val.push_back(v);
+        }
+      E.rowptr[2 * int64_t(i) + a + 1] = int64_t(E.col.size());
+    }
+  return CAV_OK;
+}
+}  // namespace
+
 cav_status make_structure(const cav_structure_desc* st, Structure& s, std::string& err) {
   if (!st) { s.M = 0; s.E.n = 0; s.E.rowptr.assign(1, 0); return CAV_OK; }
   if (st->M < 0) { err = "M < 0"; return CAV_ERR_INVALID_ARG; }
@@ -220,6 +315,7 @@ cav_status make_structure(const cav_structure_desc* st, Structure& s, std::strin
     if (pairs != tr) { err = "E is not structurally symmetric"; return CAV_ERR_INVALID_ARG; }
     return CAV_OK;
   }
+  if (st->law == CAV_LAW_FIBRE) return fibre_law(st, s, err);
   if (st->law < CAV_LAW_TARGET || st->law > CAV_LAW_BEAM_OPEN) { err = "unknown law"; return CAV_ERR_INVALID_ARG; }
   if (M > 0 && (st->n_segments < 1 || !st->seg_start || !st->seg_closed || !st->seg_ds)) {
     err = "segments are required for the built-in laws"; return CAV_ERR_INVALID_ARG;

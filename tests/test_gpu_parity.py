@@ -45,6 +45,7 @@ CASES = {
     "target32": lambda: workloads.small_target(0),
     "membrane32": lambda: workloads.membrane_ellipse(32, 3, 1e4, 1),
     "beam64": lambda: workloads.beam_fibres(64, 4, 1.0, 1e4, seed=0),
+    "fibre64": lambda: workloads.flexible_fibre(64, 4, seed=0),
 }
 
 
@@ -171,6 +172,7 @@ def test_fgmres_matches_oracle(pair):
 MCASES = {
     "target32": lambda: workloads.small_target(0),
     "beam64": lambda: workloads.beam_fibres(64, 2, 1.0, 1e4, seed=0),
+    "fibre64": lambda: workloads.flexible_fibre(64, 2, seed=0),
 }
 
 

@@ -23,6 +23,7 @@ CASES = {
     "membrane32": lambda: workloads.membrane_ellipse(32, 3, 1e4, 1),
     "beam64": lambda: workloads.beam_fibres(64, 4, 1.0, 1e4, seed=0),
     "closedbeam32": lambda: workloads.paper_beam(32),
+    "fibre64": lambda: workloads.flexible_fibre(64, 4, seed=0),
 }
 
 
@@ -147,3 +148,24 @@ def test_box_oracle_sweeps_are_consistent():
     sol = smoothers.PatchSolvers(lev.K, [lev.patches[k] for k in rev], lev.standard[rev], [lev.inject[k] for k in rev])
     x2 = smoothers.multiplicative_sweep(lev.K, sol, b, np.zeros_like(b), lev.N, [lev.inject[k] for k in rev])
     assert np.abs(x - x2).max() <= 1e-12 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("bad", ["clamp_low", "clamp_high", "closed", "two_segments"])
+def test_fibre_law_rejects_invalid_structures(bad):
+    """The fibre law (Section 5.3) needs one open segment with the clamp marker
+    strictly inside it; anything else is an argument error, not a crash."""
+    import dataclasses
+    from paper_2608_14310_amd import CAVError
+    s = workloads.flexible_fibre(32, 2, seed=0)
+    M = len(s.segments[0].X)
+    if bad == "clamp_low":
+        s.kappa = dict(s.kappa, m=0)
+    elif bad == "clamp_high":
+        s.kappa = dict(s.kappa, m=M - 1)
+    elif bad == "closed":
+        s.segments = [dataclasses.replace(s.segments[0], closed=True)]
+    else:
+        seg = s.segments[0]
+        s.segments = [dataclasses.replace(seg, X=seg.X[:M // 2]), dataclasses.replace(seg, X=seg.X[M // 2:])]
+    with pytest.raises(CAVError):
+        _analysis(s)

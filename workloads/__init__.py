@@ -170,28 +170,35 @@ def beam_fibres(N: int = 512, n_levels: int = 5, kappa_b: float = 1.0, kappa_s: 
 
 
 def flexible_fibre(N: int = 64, n_levels: int = 4, amp: float = 0.3, seed: int = 0, **fluid) -> System:
-    """The clamped flexible fibre of Section 5.3 in the periodic unit square
-    (the paper's (0,2)^2 cell scaled by 1/2): length 0.1875, midpoint clamp at
-    (0.5, 0.75), markers ds = h/2 apart, in a bent configuration such as a
-    Newton iterate would give (midline y = 0.75 - amp s^2 / L, s the signed
-    arclength from the midpoint, plus seeded jitter of 5% of ds per
-    coordinate from default_rng([seed, 2])). Stiffness: EI = 2.63672e-2,
-    and K_s, K_p, K_t = 375, 1200, 7.03125 at h = 1/32, scaled by (1/32)/h;
-    fluid mu = 1.875e-3 (Section 5.3), rho = 1, dt = 1e-3. Coordinates are
-    given unwrapped (the fibre lies inside the cell); the law's parameters
-    ride in `kappa` (EI, K_s, K_p, K_t, clamp marker m, clamp point)."""
+    """The clamped flexible fibre of Section 5.3 mapped into the periodic unit
+    square by similarity: the paper's (0,2)^2 cell, lengths and times scaled
+    by 1/2 with the velocity scale, Reynolds number and energy scale kept.
+    Fibre length 0.1875 (paper 0.375), midpoint clamp at (0.5, 0.75) (paper
+    (1, 1.5)), markers ds = h/2 apart, so the fibre has the paper's marker
+    count at the same N. Bent configuration such as a Newton iterate would
+    give: midline y = 0.75 - amp s^2 / L (s the signed arclength from the
+    midpoint) plus seeded jitter of 5% of ds per coordinate from
+    default_rng([seed, 2]); coordinates unwrapped (the fibre lies inside the
+    cell). Stiffness: the paper's EI = 2.63672e-2 and, at N = 64,
+    K_s, K_p, K_t = 375, 1200, 7.03125, each doubled per halving of h (so
+    times N/64), then mapped by the length scale s = 1/2 through the energy
+    dimensions: EI s^3, K_s s, K_p, K_t s^2. Fluid: rho = 1,
+    mu = 1.875e-3 s (paper Re kept), dt = 0.05 h (the paper's dt/h). The
+    law's parameters ride in `kappa` (EI, K_s, K_p, K_t, clamp marker m,
+    clamp point)."""
     h = 1.0 / N
     ds = h / 2
-    L = 0.1875
+    sc = 0.5
+    L = 0.375 * sc
     M = int(round(L / ds)) + 1
     m = M // 2
     s = (np.arange(M) - m) * ds
     X = np.stack([0.5 + s, 0.75 - amp * s ** 2 / L], axis=1)
     X = X + np.random.default_rng([seed, 2]).uniform(-0.05, 0.05, X.shape) * ds
-    scale = (1.0 / 32) / h
-    kappa = {"EI": 2.63672e-2, "K_s": 375.0 * scale, "K_p": 1200.0 * scale, "K_t": 7.03125 * scale,
-             "m": m, "clamp_x": 0.5, "clamp_y": 0.75}
-    f = dict(FLUID, mu=1.875e-3)
+    refine = N / 64.0
+    kappa = {"EI": 2.63672e-2 * sc ** 3, "K_s": 375.0 * refine * sc, "K_p": 1200.0 * refine,
+             "K_t": 7.03125 * refine * sc ** 2, "m": m, "clamp_x": 0.5, "clamp_y": 0.75}
+    f = dict(FLUID, mu=1.875e-3 * sc, dt=0.05 * h)
     f.update(fluid)
     return System(f"flexible_fibre_N{N}_a{amp:g}_s{seed}", N, n_levels, f["rho"], f["mu"], f["dt"],
                   "fibre", kappa, [Segment(X, False, ds)], random_rhs(N, seed))
