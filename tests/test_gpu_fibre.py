@@ -1,0 +1,78 @@
+"""The flexible-fibre law (Section 5.3) through the whole device path.
+
+A Newton solve of the clamped fibre rebuilds the hierarchy for every linear
+system, each at a new fibre configuration. One context is set up for a
+sequence of such iterates (straight to strongly bent), and every solve is
+checked against the oracle: FGMRES iteration counts equal to the oracle's
+(additive smoother, same cycle), solutions against the oracle's direct
+solve. At 256² the multiplicative cycle's solution is checked by its true
+residual under the oracle's operator.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import direct, ib, krylov, mac, multigrid
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _t(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def _oracle_K(s):
+    EE, _ = ib.eulerian_elasticity(s)
+    return mac.reduced_operator(s.N, s.rho, s.mu, s.dt, EE)
+
+
+def test_newton_iterates_rebuild_in_one_context():
+    from paper_2608_14310_amd import Solver
+    g = Solver(0)
+    try:
+        for amp, seed in [(0.0, 1), (0.15, 2), (0.3, 3)]:
+            s = workloads.flexible_fibre(64, 4, amp=amp, seed=seed)
+            print(f"[fibre] iterate amp={amp} seed={seed} N=64", flush=True)
+            K = _oracle_K(s)
+            xd = direct.solve(K, s.N, s.b)
+            H = multigrid.Hierarchy(s, alpha=0.7)
+            res = krylov.fgmres(lambda v: K @ v, H.vcycle, s.b, 1e-10, 150)
+            g.setup(s, alpha=0.7)
+            x, info = g.fgmres_solve(_t(s.b), rtol=1e-10, max_it=150)
+            torch.cuda.synchronize()
+            xg = x.cpu().numpy()
+            assert info["converged"] == 1 and info["iterations"] == res.iterations, (amp, info["iterations"],
+                                                                                   res.iterations)
+            assert np.linalg.norm(xg - xd) / np.linalg.norm(xd) < 1e-8
+            g.setup(s, alpha=1.0, smoother="multiplicative")
+            x, info = g.fgmres_solve(_t(s.b), rtol=1e-10, max_it=150)
+            torch.cuda.synchronize()
+            xg = x.cpu().numpy()
+            print(f"[fibre] additive its={res.iterations} multiplicative its={info['iterations']}", flush=True)
+            assert info["converged"] == 1
+            assert np.linalg.norm(xg - xd) / np.linalg.norm(xd) < 1e-8
+    finally:
+        g.close()
+
+
+def test_fibre_256_multiplicative_true_residual():
+    from paper_2608_14310_amd import Solver
+    s = workloads.flexible_fibre(256, 6, amp=0.3, seed=4)
+    print("[fibre] N=256 levels=6 multiplicative", flush=True)
+    g = Solver(0)
+    try:
+        g.setup(s, alpha=1.0, smoother="multiplicative")
+        x, info = g.fgmres_solve(_t(s.b), rtol=1e-10, max_it=150)
+        torch.cuda.synchronize()
+        xg = x.cpu().numpy()
+    finally:
+        g.close()
+    K = _oracle_K(s)
+    true = np.linalg.norm(s.b - K @ xg) / np.linalg.norm(s.b)
+    floor = direct.rounding_floor(K, xg, s.b)
+    print(f"[fibre] its={info['iterations']} est={info['est_rel_residual']:.3e} true={true:.3e}", flush=True)
+    assert info["converged"] == 1
+    assert true <= 2 * max(1e-10, 10 * floor)
+    assert abs(true - info["true_rel_residual"]) <= 1e-2 * true + 10 * floor
+    assert abs(xg[2 * s.N * s.N:].mean()) < 1e-9 * np.abs(xg).max()
