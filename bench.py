@@ -215,6 +215,62 @@ def two_grid_leg():
     return rows
 
 
+def fibre_leg(grids, iterates: int = 3):
+    """The clamped flexible fibre of Section 5.3 at the grids of Table 3: for
+    each grid a sequence of configurations (straight to strongly bent), each
+    a full rebuild of the hierarchy in one context (operator with the fibre's
+    tangent law, patches, factors) and a multiplicative-CAV FGMRES solve to
+    1e-10, as every Newton linear system needs. The paper's Table 3 row is
+    given beside each as context (its counts are averages over a whole
+    time-dependent run, not over these configurations)."""
+    import numpy as np
+    import torch
+
+    from paper_2608_14310_amd import Solver
+    import workloads
+    paper = {}
+    with open(os.path.join(ROOT, "tests", "golden", "paper_table3.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                v = line.split()
+                paper[int(v[0])] = dict(zip(("M", "newton_avg", "fgmres_avg", "fgmres_max", "patch_avg",
+                                             "patch_max"), [float(t) for t in v[1:]]))
+    rows = []
+    for N in grids:
+        n_levels = int(round(np.log2(N / 8))) + 1
+        g = Solver(0)
+        its, t_setup, t_solve = [], [], []
+        for q in range(iterates + 1):
+            amp = 0.3 * max(q - 1, 0) / max(iterates - 1, 1)
+            s = workloads.flexible_fibre(N, n_levels, amp=amp, seed=q)
+            bt = torch.from_numpy(s.b).cuda()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.build_operator(s)
+            stats = g.build_cav_patches("cav")
+            g.factor_patches("fp64", 1e6)
+            g.set_smoother("multiplicative", 1.0)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, inf = g.fgmres_solve(bt, rtol=1e-10, max_it=150)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if q == 0:
+                continue  # warm-up: first use of this hierarchy shape
+            its.append(inf["iterations"])
+            t_setup.append(t1 - t0)
+            t_solve.append(t2 - t1)
+            assert inf["converged"] == 1, (N, amp)
+        g.close()
+        fin = stats[-1]
+        rows.append({"grid": N, "levels": n_levels, "M": len(s.markers()),
+                     "fgmres_its": its, "setup_ms": round(1e3 * float(np.mean(t_setup)), 2),
+                     "solve_ms": round(1e3 * float(np.mean(t_solve)), 2),
+                     "patch_avg": round(fin["avg_np"], 2), "patch_max": fin["max_np"],
+                     "paper": paper.get(N)})
+    return rows
+
+
 def box_comparison_leg():
     """CAV against B(b,o) box relaxation on the paper's membrane (Section 5.1):
     two-grid spectral radii of Fig. 2 (N = 32, coarse 16^2) assembled on the
@@ -303,6 +359,8 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=600)
     ap.add_argument("--multi-rhs", type=int, default=64,
                     help="right-hand sides of the multi-RHS V-cycle leg, blocks of 16 (0: skip)")
+    ap.add_argument("--fibre-grids", type=int, nargs="*", default=[32, 64, 128, 256],
+                    help="grids of the flexible-fibre leg (Table 3); none: skip")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, help="run only a plain copy of this many bytes")
@@ -482,6 +540,8 @@ def main():
                              "ms_per_column": round(1e3 * tm / a.multi_rhs, 3),
                              "single_cycle_ms_per_column": round(1e3 * tc / a.multi_rhs, 3),
                              "speedup": round(tc / tm, 2), "max_rel_diff_vs_single": float("%.3g" % diff)}
+    if a.fibre_grids:
+        line["fibre"] = fibre_leg(a.fibre_grids)
     sweep = []
     for kb in a.stiff_sweep:
         sk = workloads.beam_512(kb)

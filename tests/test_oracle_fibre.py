@@ -100,3 +100,17 @@ def test_penalties_closed_forms():
     Ht = fibre.hessian(x, p, parts=("t",)).toarray()
     k = p["K_t"] / (4 * p["ds"] ** 2)
     assert np.allclose(Ht[2 * (m + 1), 2 * (m - 1)], -k) and np.allclose(Ht[2 * (m - 1), 2 * (m - 1)], k)
+
+
+def test_workload_has_the_papers_marker_counts():
+    """The fibre workload puts the paper's number of markers on each grid of
+    Section 5.3, Table 3 (length 0.375 at ds = h/2 in the paper's cell)."""
+    import os
+    import workloads
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_table3.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    assert len(rows) == 4
+    for r in rows:
+        s = workloads.flexible_fibre(int(r[0]), 3)
+        assert len(s.markers()) == int(r[1])
+        assert s.kappa["m"] == int(r[1]) // 2

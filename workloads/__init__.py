@@ -179,10 +179,11 @@ def flexible_fibre(N: int = 64, n_levels: int = 4, amp: float = 0.3, seed: int =
     give: midline y = 0.75 - amp s^2 / L (s the signed arclength from the
     midpoint) plus seeded jitter of 5% of ds per coordinate from
     default_rng([seed, 2]); coordinates unwrapped (the fibre lies inside the
-    cell). Stiffness: the paper's EI = 2.63672e-2 and, at N = 64,
-    K_s, K_p, K_t = 375, 1200, 7.03125, each doubled per halving of h (so
-    times N/64), then mapped by the length scale s = 1/2 through the energy
-    dimensions: EI s^3, K_s s, K_p, K_t s^2. Fluid: rho = 1,
+    cell). Stiffness: the paper's EI = 2.63672e-2 and, on its 128 x 128
+    grid (h = 1/64 in its cell), K_s, K_p, K_t = 375, 1200, 7.03125, each
+    doubled per halving of h (so times N/128 here), then mapped by the
+    length scale s = 1/2 through the energy dimensions: EI s^3, K_s s, K_p,
+    K_t s^2. Fluid: rho = 1,
     mu = 1.875e-3 s (paper Re kept), dt = 0.05 h (the paper's dt/h). The
     law's parameters ride in `kappa` (EI, K_s, K_p, K_t, clamp marker m,
     clamp point)."""
@@ -195,7 +196,7 @@ def flexible_fibre(N: int = 64, n_levels: int = 4, amp: float = 0.3, seed: int =
     s = (np.arange(M) - m) * ds
     X = np.stack([0.5 + s, 0.75 - amp * s ** 2 / L], axis=1)
     X = X + np.random.default_rng([seed, 2]).uniform(-0.05, 0.05, X.shape) * ds
-    refine = N / 64.0
+    refine = N / 128.0
     kappa = {"EI": 2.63672e-2 * sc ** 3, "K_s": 375.0 * refine * sc, "K_p": 1200.0 * refine,
              "K_t": 7.03125 * refine * sc ** 2, "m": m, "clamp_x": 0.5, "clamp_y": 0.75}
     f = dict(FLUID, mu=1.875e-3 * sc, dt=0.05 * h)
