@@ -104,6 +104,9 @@ typedef struct {
   double K_p, K_t;         /* CAV_LAW_FIBRE only: clamp position and tangent penalties */
   int32_t clamp_marker;    /* CAV_LAW_FIBRE only: the clamped marker m */
   double clamp_x, clamp_y; /* CAV_LAW_FIBRE only: the clamp point */
+  const double* X_force;   /* CAV_LAW_FIBRE only, optional host 2M: positions at which the energies
+                              (force and tangent) are evaluated; NULL = X. Interpolation and spreading
+                              always use X (Section 2: S and J at the start of the time step) */
 } cav_structure_desc;
 
 typedef struct {           /* per smoothed level (index = level, 0 unused) */
@@ -229,6 +232,54 @@ cav_status cav_vcycle_multi(cav_ctx ctx, int32_t k, const double* R, double* Z);
  * estimate met rtol but the true FP64 residual exceeds 10 * rtol. */
 cav_status cav_fgmres_solve(cav_ctx ctx, const double* b, double* x, const cav_fgmres_opts* opts,
                             cav_solve_info* info);
+
+/* ---- implicit IB step with a nonlinear force (Section 2 scheme, Section 5.3) ----
+ * Interpolation U = J u (Section 2, Eq. intro_saddle) at the positions X of the
+ * last cav_build_operator: x device 3N^2 (u, v, p), U device 2M (interleaved).
+ * Spreading y_u += S F = h^-2 J^T W F: F device 2M, y device 3N^2 (velocity
+ * blocks updated, pressure untouched; each face sums its markers in a fixed
+ * order). Both need cav_build_operator; M = 0 is a no-op. */
+cav_status cav_ib_interpolate(cav_ctx ctx, const double* x, double* U);
+cav_status cav_ib_spread_add(cav_ctx ctx, const double* F, double* y);
+/* Host: the fibre law's force density F = -(1/ds) grad(energies) at X_force
+ * (else X), F host 2M interleaved (Section 5.3). CAV_ERR_INVALID_ARG for other
+ * laws or an invalid descriptor. */
+cav_status cav_structure_force(const cav_structure_desc* st, double* F);
+
+typedef struct {
+  double rtol, atol;       /* stop when ||R|| <= rtol ||R_0|| or ||R|| <= atol (2-norms) */
+  int32_t max_newton;      /* Newton corrections at most */
+  double lin_rtol;         /* FGMRES tolerance of every Newton system */
+  int32_t lin_max_it;
+  int32_t family;          /* CAV_FAMILY_*, rebuilt for every Newton system */
+  int32_t precision;       /* CAV_PREC_* */
+  double cond_threshold;
+  int32_t smoother;        /* CAV_SMOOTHER_* */
+  double alpha;
+} cav_newton_opts;
+
+typedef struct {
+  int32_t newton_its;      /* corrections taken */
+  int32_t converged;
+  int32_t fgmres_its_total, fgmres_its_max;
+  double res0, res;        /* ||R|| at the initial and the final iterate */
+} cav_newton_info;
+
+/* One backward-Euler step of the IB scheme of Section 2 with the fibre law
+ * (Section 5.3), solved by Newton's method: unknowns x = (u, p) (device 3N^2,
+ * in: initial guess, out: solution), X^{n+1} = X^n + dt J^n u with J^n, S^n at
+ * st->X = X^n, and the residual
+ *   R(x) = K_0 x - S^n F(X^n + dt J^n u) - rhs,
+ * K_0 the Stokes part of Eq. intro_saddle (A_0 = rho/dt I - mu L, G, -D) and
+ * rhs device 3N^2 (rho/dt u^n plus any explicit terms; pressure part). Each
+ * correction rebuilds the whole hierarchy with E = DF at the current
+ * iterate (st->X_force ignored) and solves K_E dx = -R with CAV-preconditioned
+ * FGMRES (lin_rtol) from zero. X_new: optional host 2M, X^{n+1} at the
+ * solution. The context keeps the hierarchy of the last Newton system.
+ * CAV_WARN_NOT_CONVERGED if max_newton corrections do not meet the tolerance;
+ * a linear solve's error status is returned as is. */
+cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_structure_desc* st, const double* rhs,
+                            double* x, double* X_new, const cav_newton_opts* opts, cav_newton_info* info);
 
 /* ---- graph execution and batches of independent systems ----
  * cav_fgmres_solve_graph: the same solve as cav_fgmres_solve (same kernels,

@@ -45,7 +45,19 @@ class StructureDesc(C.Structure):
                 ("seg_closed", C.POINTER(C.c_int32)), ("seg_ds", C.POINTER(C.c_double)),
                 ("E_nnz", C.c_int32), ("E_rowptr", C.POINTER(C.c_int32)), ("E_col", C.POINTER(C.c_int32)),
                 ("E_val", C.POINTER(C.c_double)), ("K_p", C.c_double), ("K_t", C.c_double),
-                ("clamp_marker", C.c_int32), ("clamp_x", C.c_double), ("clamp_y", C.c_double)]
+                ("clamp_marker", C.c_int32), ("clamp_x", C.c_double), ("clamp_y", C.c_double),
+                ("X_force", C.POINTER(C.c_double))]
+
+
+class NewtonOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_newton", C.c_int32), ("lin_rtol", C.c_double),
+                ("lin_max_it", C.c_int32), ("family", C.c_int32), ("precision", C.c_int32),
+                ("cond_threshold", C.c_double), ("smoother", C.c_int32), ("alpha", C.c_double)]
+
+
+class NewtonInfo(C.Structure):
+    _fields_ = [("newton_its", C.c_int32), ("converged", C.c_int32), ("fgmres_its_total", C.c_int32),
+                ("fgmres_its_max", C.c_int32), ("res0", C.c_double), ("res", C.c_double)]
 
 
 class LevelStats(C.Structure):
@@ -139,6 +151,11 @@ _SIGS = {
     "cav_batch_solve": ([C.POINTER(_P), C.c_int32, C.POINTER(_P), C.POINTER(_P), C.POINTER(FgmresOpts),
                          C.POINTER(SolveInfo), C.c_int32, C.POINTER(BatchStats)], C.c_int),
     "cav_attach_net": ([_P, _P, C.c_double], C.c_int),
+    "cav_ib_interpolate": ([_P, _P, _P], C.c_int),
+    "cav_ib_spread_add": ([_P, _P, _P], C.c_int),
+    "cav_structure_force": ([C.POINTER(StructureDesc), C.POINTER(C.c_double)], C.c_int),
+    "cav_newton_solve": ([_P, C.POINTER(GridDesc), C.POINTER(StructureDesc), _P, _P, C.POINTER(C.c_double),
+                          C.POINTER(NewtonOpts), C.POINTER(NewtonInfo)], C.c_int),
 }
 NET_WEIGHTS = 10944
 EXPORTED_SYMBOLS = tuple(_SIGS)
@@ -164,6 +181,22 @@ def lib():
 
 def _arr(a, ctype):
     return a.ctypes.data_as(C.POINTER(ctype)) if a is not None and a.size else None
+
+
+def structure_force(system, X_force=None) -> np.ndarray:
+    """Host force density of the fibre law at X_force (else at the markers),
+    interleaved 2M (cav_structure_force)."""
+    d, keep = describe_structure(system)
+    xf = None
+    if X_force is not None:
+        xf = np.ascontiguousarray(np.asarray(X_force, dtype=np.float64).ravel())
+        d.X_force = _arr(xf, C.c_double)
+    F = np.zeros(2 * d.M, dtype=np.float64)
+    st = lib().cav_structure_force(C.byref(d), _arr(F, C.c_double))
+    del keep, xf
+    if st != 0:
+        raise CAVError(st, "cav_structure_force failed")
+    return F
 
 
 def describe_structure(system):
@@ -407,6 +440,7 @@ class Solver:
         self._check(self._L.cav_build_operator(self._h, C.byref(g), C.byref(d)))
         del keep
         self.N, self.n_levels = system.N, system.n_levels
+        self._ib_rows = 2 * d.M
 
     def build_cav_patches(self, family: str = "cav", box=(4, 2)) -> List[Dict]:
         """Patch family per smoothed level: 'cav', 'vanka', or 'box' (B(b,o), box = (b, o))."""
@@ -503,6 +537,44 @@ class Solver:
         d["status"] = st
         d["history"] = hist[:info.iterations].copy()
         return x, d
+
+    def ib_interpolate(self, x):
+        """U = J u at the markers of the last operator build (device, 2M)."""
+        self._sync_stream()
+        M2 = int(self._ib_rows)
+        U = self._torch.empty(M2, dtype=self._torch.float64, device=self.device)
+        self._check(self._L.cav_ib_interpolate(self._h, _dev_ptr(x), _dev_ptr(U) if M2 else None))
+        return U
+
+    def ib_spread_add(self, F, y):
+        """y_u += S F in place (device)."""
+        self._sync_stream()
+        self._check(self._L.cav_ib_spread_add(self._h, _dev_ptr(F) if F.numel() else None, _dev_ptr(y)))
+        return y
+
+    def newton_solve(self, system, rhs, x0=None, rtol: float = 1e-8, atol: float = 1e-8, max_newton: int = 20,
+                     lin_rtol: float = 1e-9, lin_max_it: int = 150, family: str = "cav", precision: str = "fp64",
+                     cond_threshold: float = 1e6, smoother: str = "multiplicative", alpha: float = 1.0):
+        """One backward-Euler IB step with the fibre law by Newton's method
+        (cav_newton_solve): returns (x, X_new, info)."""
+        self._sync_stream()
+        g = GridDesc(system.N, system.n_levels, system.rho, system.mu, system.dt)
+        d, keep = describe_structure(system)
+        x = self._torch.zeros(3 * system.N * system.N, dtype=self._torch.float64, device=self.device)
+        if x0 is not None:
+            x.copy_(x0)
+        Xn = np.zeros(2 * d.M, dtype=np.float64)
+        o = NewtonOpts(float(rtol), float(atol), int(max_newton), float(lin_rtol), int(lin_max_it), FAMILY[family],
+                       PRECISION[precision], float(cond_threshold), SMOOTHER[smoother], float(alpha))
+        info = NewtonInfo()
+        st = self._check(self._L.cav_newton_solve(self._h, C.byref(g), C.byref(d), _dev_ptr(rhs), _dev_ptr(x),
+                                                  _arr(Xn, C.c_double), C.byref(o), C.byref(info)))
+        del keep
+        self.N, self.n_levels = system.N, system.n_levels
+        self._ib_rows = 2 * d.M
+        out = {f: getattr(info, f) for f, _ in NewtonInfo._fields_}
+        out["status"] = st
+        return x, Xn, out
 
     def train_net_residual(self, net: Net, rhat, index=None, lr: float = 1e-3, kind: str = "residual") -> float:
         """One Adam step of `net` on the residual-norm loss through this context's

@@ -147,6 +147,70 @@ T* upload(Ctx& c, const std::vector<T>& h) {
   return d;
 }
 
+void free_ib_tables(Ctx& c) {
+  for (void* p : {(void*)c.d_ib_face, (void*)c.d_ib_w, (void*)c.d_sp_face, (void*)c.d_sp_ptr, (void*)c.d_sp_row,
+                  (void*)c.d_sp_w})
+    dev_free(c, p);
+  c.d_ib_face = c.d_sp_face = c.d_sp_ptr = c.d_sp_row = nullptr;
+  c.d_ib_w = c.d_sp_w = nullptr;
+  c.ib_rows = c.ib_faces = 0;
+}
+
+// J as 16 (face, weight) pairs per Lagrangian row; S = h^-2 J^T W grouped by
+// face (rows of one face in increasing order), so that spreading is a
+// deterministic gather per touched face
+void build_ib_tables(Ctx& c, int N, const Structure& S) {
+  std::vector<int32_t> face;
+  std::vector<double> w;
+  ib_supports(N, S, face, w);
+  const int32_t nr = 2 * S.M;
+  const double ih2 = double(N) * N;
+  std::vector<std::pair<int32_t, int32_t>> fr;  // (face, row)
+  fr.reserve(face.size());
+  for (int32_t r = 0; r < nr; ++r)
+    for (int t = 0; t < 16; ++t) fr.push_back({face[size_t(r) * 16 + t], r * 16 + t});
+  std::sort(fr.begin(), fr.end());
+  std::vector<int32_t> sf, sptr(1, 0), srow;
+  std::vector<double> sw;
+  for (size_t q = 0; q < fr.size(); ++q) {
+    if (q == 0 || fr[q].first != fr[q - 1].first) {
+      if (q > 0) sptr.push_back(int32_t(srow.size()));
+      sf.push_back(fr[q].first);
+    }
+    const int32_t r = fr[q].second / 16;
+    srow.push_back(r);
+    sw.push_back(w[size_t(fr[q].second)] * S.omega[r / 2] * ih2);
+  }
+  if (!fr.empty()) sptr.push_back(int32_t(srow.size()));
+  c.ib_rows = nr;
+  c.ib_faces = int32_t(sf.size());
+  c.d_ib_face = upload(c, face);
+  c.d_ib_w = upload(c, w);
+  c.d_sp_face = upload(c, sf);
+  c.d_sp_ptr = upload(c, sptr);
+  c.d_sp_row = upload(c, srow);
+  c.d_sp_w = upload(c, sw);
+}
+
+__global__ void k_ib_interp(int32_t nr, const int32_t* __restrict__ face, const double* __restrict__ w,
+                            const double* __restrict__ x, double* __restrict__ U) {
+  const int32_t r = int32_t(blockIdx.x) * TPB + int32_t(threadIdx.x);
+  if (r >= nr) return;
+  double acc = 0.0;
+  for (int t = 0; t < 16; ++t) acc += w[int64_t(r) * 16 + t] * x[face[int64_t(r) * 16 + t]];
+  U[r] = acc;
+}
+
+__global__ void k_ib_spread(int32_t nf, const int32_t* __restrict__ face, const int32_t* __restrict__ ptr,
+                            const int32_t* __restrict__ row, const double* __restrict__ w, const double* __restrict__ F,
+                            double* __restrict__ y) {
+  const int32_t q = int32_t(blockIdx.x) * TPB + int32_t(threadIdx.x);
+  if (q >= nf) return;
+  double acc = 0.0;
+  for (int32_t k = ptr[q]; k < ptr[q + 1]; ++k) acc += w[k] * F[row[k]];
+  y[face[q]] += acc;
+}
+
 void free_level(Ctx& c, Level& L) {
   if (L.fpending) {
     factor_level_release(c, L.fpend);
@@ -642,6 +706,7 @@ cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* g, const cav_str
   CAV_HIP(hipSetDevice(c.device));
   drop_coarse(c);
   for (auto& lev : c.lv) free_level(c, lev);
+  free_ib_tables(c);
   device_sync_epoch(c);
   c.lv.assign(L, Level());
   c.built = c.patched = c.factored = false;
@@ -660,6 +725,7 @@ cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* g, const cav_str
   }
   assemble_ee_finest(N, S, c.lv[L - 1].ee);
   for (int l = L - 1; l >= 1; --l) galerkin_coarsen(c.lv[l - 1].N, c.lv[l].ee, c.lv[l - 1].ee);
+  build_ib_tables(c, N, S);
   for (int l = 0; l < L; ++l) {
     Level& lev = c.lv[l];
     const HostCSR& E = lev.ee;
@@ -1640,3 +1706,152 @@ cav_status cav_set_wait_limit(cav_ctx ctx, uint32_t polls) {
 }
 
 }  // extern "C"
+
+cav_status cav_ib_interpolate(cav_ctx ctx, const double* x, double* U) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.built, CAV_ERR_NOT_BUILT, "operator not built");
+  if (c.ib_rows == 0) return CAV_OK;
+  require(x && U, CAV_ERR_INVALID_ARG, "x and U must be device pointers");
+  k_ib_interp<<<nblocks(c.ib_rows), TPB, 0, c.stream>>>(c.ib_rows, c.d_ib_face, c.d_ib_w, x, U);
+  CAV_HIP(hipGetLastError());
+  return CAV_OK;
+  API_END
+}
+
+cav_status cav_ib_spread_add(cav_ctx ctx, const double* F, double* y) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  require(c.built, CAV_ERR_NOT_BUILT, "operator not built");
+  if (c.ib_faces == 0) return CAV_OK;
+  require(F && y, CAV_ERR_INVALID_ARG, "F and y must be device pointers");
+  k_ib_spread<<<nblocks(c.ib_faces), TPB, 0, c.stream>>>(c.ib_faces, c.d_sp_face, c.d_sp_ptr, c.d_sp_row, c.d_sp_w, F,
+                                                          y);
+  CAV_HIP(hipGetLastError());
+  return CAV_OK;
+  API_END
+}
+
+cav_status cav_structure_force(const cav_structure_desc* st, double* F) {
+  if (!st || !F) return CAV_ERR_INVALID_ARG;
+  try {
+    std::vector<double> f;
+    std::string err;
+    const cav_status s = fibre_force(st, f, err);
+    if (s != CAV_OK) return s;
+    std::copy(f.begin(), f.end(), F);
+    return CAV_OK;
+  } catch (const std::bad_alloc&) {
+    return CAV_ERR_OUT_OF_MEMORY;
+  }
+}
+
+cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_structure_desc* st, const double* rhs,
+                            double* x, double* X_new, const cav_newton_opts* o, cav_newton_info* info) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  std::vector<void*> bufs;
+  auto release = [&]() {
+    for (void* p : bufs) dev_free(c, p);
+    bufs.clear();
+  };
+  try {
+    require(g && st && o && rhs && x && rhs != x, CAV_ERR_INVALID_ARG,
+            "grid, structure, options, rhs and x are required (rhs and x distinct)");
+    require(st->law == CAV_LAW_FIBRE, CAV_ERR_INVALID_ARG, "the Newton step needs the fibre law");
+    require(std::isfinite(o->rtol) && o->rtol >= 0 && std::isfinite(o->atol) && o->atol >= 0 && o->max_newton >= 0 &&
+                o->max_newton <= 1000 && std::isfinite(o->lin_rtol) && o->lin_rtol >= 0 && o->lin_max_it >= 1,
+            CAV_ERR_INVALID_ARG, "bad Newton options");
+    auto call = [&](cav_status s) {
+      if (s != CAV_OK) throw StatusError(s, c.err);
+    };
+    cav_structure_desc d = *st;
+    d.X_force = nullptr;
+    // J^n, S^n and the Stokes stencil at X^n (the operator itself is rebuilt per correction)
+    call(cav_build_operator(ctx, g, &d));
+    const int M = st->M;
+    const int64_t n2 = int64_t(g->N) * g->N, n = 3 * n2;
+    const StencilCoef sc = c.lv.back().sc;
+    auto alloc = [&](size_t bytes) {
+      void* p = dev_alloc(c, bytes);
+      bufs.push_back(p);
+      return p;
+    };
+    double* dU = static_cast<double*>(alloc(2 * size_t(M) * sizeof(double)));
+    double* dF = static_cast<double*>(alloc(2 * size_t(M) * sizeof(double)));
+    double* dy = static_cast<double*>(alloc(size_t(n) * sizeof(double)));
+    double* ddx = static_cast<double*>(alloc(size_t(n) * sizeof(double)));
+    const int nblk = dots_blocks(n);
+    double* dpart = static_cast<double*>(alloc(size_t(nblk) * sizeof(double)));
+    double* dnrm = static_cast<double*>(alloc(sizeof(double)));
+    std::vector<double> Xk(2 * size_t(M)), U(2 * size_t(M)), Fh;
+    const std::vector<double> Xn(st->X, st->X + 2 * size_t(M));
+    cav_newton_info inf{};
+    cav_fgmres_opts fo{};
+    fo.rtol = o->lin_rtol;
+    fo.max_it = o->lin_max_it;
+    hipStream_t s = c.stream;
+    for (int it = 0;; ++it) {
+      // X_k = X^n + dt J^n u_k and the force there
+      if (M > 0) {
+        call(cav_ib_interpolate(ctx, x, dU));
+        CAV_HIP(hipMemcpyAsync(U.data(), dU, U.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        CAV_HIP(hipStreamSynchronize(s));
+      }
+      for (size_t k = 0; k < Xk.size(); ++k) Xk[k] = Xn[k] + g->dt * U[k];
+      d.X_force = Xk.data();
+      std::string err;
+      const cav_status fs = fibre_force(&d, Fh, err);
+      if (fs != CAV_OK) throw StatusError(fs, err);
+      if (M > 0) CAV_HIP(hipMemcpyAsync(dF, Fh.data(), Fh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      // y = rhs + S^n F(X_k) - K_0 x = -R(x)
+      launch_stencil(sc, x, dy, rhs, s);
+      call(cav_ib_spread_add(ctx, dF, dy));
+      launch_dots(dy, n, 1, dy, n, dpart, nblk, dnrm, s);
+      double r2 = 0.0;
+      CAV_HIP(hipMemcpyAsync(&r2, dnrm, sizeof(double), hipMemcpyDeviceToHost, s));
+      CAV_HIP(hipStreamSynchronize(s));
+      const double rn = std::sqrt(r2);
+      require(std::isfinite(rn), CAV_ERR_INVALID_ARG, "non-finite Newton residual");
+      if (it == 0) inf.res0 = rn;
+      inf.res = rn;
+      if (rn <= o->rtol * inf.res0 || rn <= o->atol) {
+        inf.converged = 1;
+        break;
+      }
+      if (it == o->max_newton) break;
+      // the Newton system at X_k: hierarchy rebuilt with E = DF[X_k]
+      call(cav_build_operator(ctx, g, &d));
+      call(cav_build_cav_patches(ctx, o->family, nullptr));
+      call(cav_factor_patches(ctx, o->precision, o->cond_threshold, nullptr));
+      call(cav_set_smoother(ctx, o->smoother, o->alpha, 1, 1));
+      cav_solve_info si{};
+      const cav_status ls = cav_fgmres_solve(ctx, dy, ddx, &fo, &si);
+      if (ls != CAV_OK && ls != CAV_WARN_FLOOR_LIMITED) throw StatusError(ls, c.err);
+      k_axpby<<<nblocks(n), TPB, 0, s>>>(x, 1.0, ddx, 1.0, n);
+      CAV_HIP(hipGetLastError());
+      ++inf.newton_its;
+      inf.fgmres_its_total += si.iterations;
+      inf.fgmres_its_max = std::max(inf.fgmres_its_max, si.iterations);
+    }
+    if (X_new) std::copy(Xk.begin(), Xk.end(), X_new);
+    CAV_HIP(hipStreamSynchronize(s));
+    release();
+    if (info) *info = inf;
+    return inf.converged ? CAV_OK : CAV_WARN_NOT_CONVERGED;
+  } catch (const StatusError& e) {
+    c.err = e.msg;
+    release();
+    return e.st;
+  } catch (const HipError& e) {
+    c.err = e.msg;
+    release();
+    return CAV_ERR_HIP;
+  } catch (const std::bad_alloc&) {
+    c.err = "host allocation failed";
+    release();
+    return CAV_ERR_OUT_OF_MEMORY;
+  }
+}

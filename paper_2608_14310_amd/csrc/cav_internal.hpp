@@ -222,6 +222,16 @@ struct Ctx {
   bool std_first = false;  // multiplicative sweep: shared-patch colours before the explicit phases
   uint32_t wait_limit = 1u << 21;  // polls of a bounded workgroup-barrier wait before it gives up
   int smoother = CAV_SMOOTHER_ADDITIVE;
+  // interpolation J and spreading S at the structure positions of the last
+  // operator build: per Lagrangian row its 16 faces and kernel weights; per
+  // touched velocity face its rows and the weights omega * w / h^2
+  int32_t ib_rows = 0, ib_faces = 0;
+  int32_t* d_ib_face = nullptr;
+  double* d_ib_w = nullptr;
+  int32_t* d_sp_face = nullptr;
+  int32_t* d_sp_ptr = nullptr;
+  int32_t* d_sp_row = nullptr;
+  double* d_sp_w = nullptr;
   // coarsest solution operator (nc x nc, row-major, nc = 3 N0^2)
   int nc = 0;
   double* d_cinv = nullptr;
@@ -304,6 +314,8 @@ struct Structure {
   HostCSR E;  // 2M x 2M, component interleaved
 };
 cav_status make_structure(const cav_structure_desc* st, Structure& out, std::string& err);
+cav_status fibre_force(const cav_structure_desc* st, std::vector<double>& F, std::string& err);
+void ib_supports(int N, const Structure& s, std::vector<int32_t>& face, std::vector<double>& w);
 void assemble_ee_finest(int N, const Structure& s, HostCSR& ee);
 void galerkin_coarsen(int Nc, const HostCSR& fine, HostCSR& coarse);
 void build_patches(int N, const HostCSR& ee, int family, Level& L);
@@ -315,6 +327,8 @@ void build_box_patches(int N, const HostCSR& ee, int b, int o, Level& L);
 
 // ---- device launches (kernels_*.hip) ----
 void launch_apply_op(const Level& L, const double* x, double* y, const double* b, hipStream_t s);
+// the Stokes part alone (A_0, G, -D): y = K_0 x, or y = b - K_0 x when b is given
+void launch_stencil(const StencilCoef& sc, const double* x, double* y, const double* b, hipStream_t s);
 void launch_restrict(const Level& Lf, const double* rf, double* bc, hipStream_t s);
 void launch_prolong_add(const Level& Lf, const double* xc, double* xf, hipStream_t s);
 void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);

@@ -195,6 +195,10 @@ void launch_apply_op(const Level& L, const double* x, double* y, const double* b
                                                  b ? -1.0 : 1.0);
 }
 
+void launch_stencil(const StencilCoef& sc, const double* x, double* y, const double* b, hipStream_t s) {
+  k_apply_stencil<<<nblocks(int64_t(sc.N) * sc.N), TPB, 0, s>>>(sc, x, y, b);
+}
+
 void launch_restrict(const Level& Lf, const double* rf, double* bc, hipStream_t s) {
   const int Nc = Lf.N / 2;
   k_restrict<<<nblocks(int64_t(Nc) * Nc), TPB, 0, s>>>(Nc, rf, bc);

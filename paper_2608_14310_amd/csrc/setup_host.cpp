@@ -203,12 +203,15 @@ cav_status fibre_law(const cav_structure_desc* st, Structure& s, std::string& er
   const double EI = st->kappa_b, Ks = st->kappa_s, Kp = st->K_p, Kt = st->K_t;
   for (double v : {EI, Ks, Kp, Kt, st->clamp_x, st->clamp_y})
     if (!std::isfinite(v)) { err = "non-finite fibre parameter"; return CAV_ERR_INVALID_ARG; }
+  if (st->X_force)
+    for (int64_t k = 0; k < 2 * int64_t(M); ++k)
+      if (!std::isfinite(st->X_force[k])) { err = "non-finite X_force"; return CAV_ERR_INVALID_ARG; }
   // band storage: B[i][d][a][b] = Hess(U) block (marker i, marker i+d-2), d in 0..4
   std::vector<double> B(size_t(M) * 5 * 4, 0.0);
   auto blk = [&](int i, int j, int a, int b) -> double& {
     return B[((size_t(i) * 5 + size_t(j - i + 2)) * 2 + a) * 2 + b];
   };
-  const double* X = s.X.data();
+  const double* X = st->X_force ? st->X_force : s.X.data();
   auto link = [&](int k, int c) { return X[2 * (k + 1) + c] - X[2 * k + c]; };
   // stretching: U_k = Ks/(2ds) (|d|-ds)^2 with d = X_{k+1} - X_k;
   // d2U_k/dd2 = (Ks/ds) [ (1 - ds/|d|) I + ds d d^T / |d|^3 ]
@@ -275,6 +278,77 @@ cav_status fibre_law(const cav_structure_desc* st, Structure& s, std::string& er
   return CAV_OK;
 }
 }  // namespace
+
+// Force density of the clamped fibre, F = -(1/ds) grad(U) (Section 5.3), at
+// X_force when given, else at X: each term's gradient in its own variables
+// (links, clamp coordinates), scattered onto the markers it involves.
+cav_status fibre_force(const cav_structure_desc* st, std::vector<double>& F, std::string& err) {
+  Structure s;
+  const cav_status v = make_structure(st, s, err);  // validates the descriptor and the parameters
+  if (v != CAV_OK) return v;
+  if (st->law != CAV_LAW_FIBRE) { err = "a force is defined here for the fibre law only"; return CAV_ERR_INVALID_ARG; }
+  const int M = s.M, m = st->clamp_marker;
+  const double ds = st->seg_ds[0];
+  const double EI = st->kappa_b, Ks = st->kappa_s, Kp = st->K_p, Kt = st->K_t;
+  const double* X = st->X_force ? st->X_force : s.X.data();
+  auto link = [&](int k, int c) { return X[2 * (k + 1) + c] - X[2 * k + c]; };
+  std::vector<double> G(2 * size_t(M), 0.0);  // grad(U)
+  // stretching: dU_k/dd = Ks/ds (|d| - ds) d/|d|, d = X_{k+1} - X_k
+  for (int k = 0; k + 1 < M; ++k) {
+    const double d0 = link(k, 0), d1 = link(k, 1);
+    const double len = std::hypot(d0, d1);
+    const double f = Ks / ds * (len - ds) / len;
+    G[2 * k] -= f * d0;
+    G[2 * k + 1] -= f * d1;
+    G[2 * (k + 1)] += f * d0;
+    G[2 * (k + 1) + 1] += f * d1;
+  }
+  // bending: dU_k/dv = EI/ds^5 c grad(c), v = (p, q) = (D_k, D_{k+1})
+  const double wb = EI / std::pow(ds, 5);
+  for (int k = 0; k + 2 < M; ++k) {
+    const double p0 = link(k, 0), p1 = link(k, 1), q0 = link(k + 1, 0), q1 = link(k + 1, 1);
+    const double c = wb * (p0 * q1 - p1 * q0);
+    const double gp0 = c * q1, gp1 = -c * q0, gq0 = -c * p1, gq1 = c * p0;
+    G[2 * k] -= gp0;
+    G[2 * k + 1] -= gp1;
+    G[2 * (k + 1)] += gp0 - gq0;
+    G[2 * (k + 1) + 1] += gp1 - gq1;
+    G[2 * (k + 2)] += gq0;
+    G[2 * (k + 2) + 1] += gq1;
+  }
+  // clamp: position penalty on marker m, tangent penalty on the central difference
+  G[2 * m] += Kp * (X[2 * m] - st->clamp_x);
+  G[2 * m + 1] += Kp * (X[2 * m + 1] - st->clamp_y);
+  const double t0 = (X[2 * (m + 1)] - X[2 * (m - 1)]) / (2.0 * ds) - 1.0;
+  const double t1 = (X[2 * (m + 1) + 1] - X[2 * (m - 1) + 1]) / (2.0 * ds);
+  const double wt = Kt / (2.0 * ds);
+  G[2 * (m + 1)] += wt * t0;
+  G[2 * (m + 1) + 1] += wt * t1;
+  G[2 * (m - 1)] -= wt * t0;
+  G[2 * (m - 1) + 1] -= wt * t1;
+  F.resize(G.size());
+  for (size_t k = 0; k < G.size(); ++k) {
+    F[k] = -G[k] / ds;
+    if (!std::isfinite(F[k])) { err = "non-finite fibre force"; return CAV_ERR_INVALID_ARG; }
+  }
+  return CAV_OK;
+}
+
+// The 16 faces and four-point kernel weights of every Lagrangian row (marker
+// k, component c at row 2k + c), at the structure's positions X.
+void ib_supports(int N, const Structure& s, std::vector<int32_t>& face, std::vector<double>& w) {
+  const int64_t nr = 2 * int64_t(s.M);
+  face.resize(size_t(nr) * 16);
+  w.resize(size_t(nr) * 16);
+  Support sg;
+  for (int64_t r = 0; r < nr; ++r) {
+    support(N, s.X[2 * (r / 2)], s.X[2 * (r / 2) + 1], int(r % 2), sg);
+    for (int t = 0; t < 16; ++t) {
+      face[size_t(r) * 16 + t] = sg.face[t];
+      w[size_t(r) * 16 + t] = sg.w[t];
+    }
+  }
+}
 
 cav_status make_structure(const cav_structure_desc* st, Structure& s, std::string& err) {
   if (!st) { s.M = 0; s.E.n = 0; s.E.rowptr.assign(1, 0); return CAV_OK; }

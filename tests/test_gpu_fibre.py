@@ -76,3 +76,60 @@ def test_fibre_256_multiplicative_true_residual():
     assert true <= 2 * max(1e-10, 10 * floor)
     assert abs(true - info["true_rel_residual"]) <= 1e-2 * true + 10 * floor
     assert abs(xg[2 * s.N * s.N:].mean()) < 1e-9 * np.abs(xg).max()
+
+
+def test_interpolation_and_spreading_match_oracle():
+    from paper_2608_14310_amd import Solver
+    s = workloads.flexible_fibre(64, 4, amp=0.3, seed=5)
+    print("[fibre] interpolation / spreading N=64", flush=True)
+    J = ib.interpolation(s.N, s.markers())
+    S = ib.spreading(s.N, J, s.weights())
+    rng = np.random.default_rng(6)
+    n2 = s.N * s.N
+    x = rng.uniform(-1, 1, 3 * n2)
+    F = rng.uniform(-1, 1, J.shape[0])
+    y0 = rng.uniform(-1, 1, 3 * n2)
+    g = Solver(0)
+    try:
+        g.build_operator(s)
+        U = g.ib_interpolate(_t(x)).cpu().numpy()
+        y = g.ib_spread_add(_t(F), _t(y0)).cpu().numpy()
+    finally:
+        g.close()
+    Uo = J @ x[:2 * n2]
+    assert np.abs(U - Uo).max() <= 1e-13 * np.abs(Uo).max()
+    yo = y0.copy()
+    yo[:2 * n2] += S @ F
+    assert np.abs(y - yo).max() <= 1e-13 * np.abs(yo).max()
+    assert np.array_equal(y[2 * n2:], y0[2 * n2:])
+
+
+@pytest.mark.parametrize("N,levels", [(64, 4), (128, 5)])
+def test_newton_step_matches_oracle(N, levels):
+    """One backward-Euler step of the fibre in the downward stream by Newton's
+    method: every correction rebuilds the hierarchy on the GPU and solves with
+    multiplicative-CAV FGMRES to 1e-9; the oracle solves every Newton system
+    directly. Same number of corrections, same solution."""
+    from oracle import newton
+    from paper_2608_14310_amd import Solver
+    s = workloads.flexible_fibre(N, levels, amp=0.3, seed=1)
+    un = workloads.fibre_inflow_velocity(N, seed=1)
+    rhs = np.concatenate([s.rho / s.dt * un, np.zeros(N * N)])
+    print(f"[fibre] Newton step N={N} levels={levels}", flush=True)
+    ref = newton.solve(s, rhs, rtol=1e-8, atol=1e-8, max_newton=10)
+    g = Solver(0)
+    try:
+        x, Xn, info = g.newton_solve(s, _t(rhs), rtol=1e-8, atol=1e-8, max_newton=10, lin_rtol=1e-9)
+        torch.cuda.synchronize()
+        xg = x.cpu().numpy()
+    finally:
+        g.close()
+    print(f"[fibre] oracle corrections={ref.corrections} residuals={['%.3e' % r for r in ref.residuals]}; "
+          f"gpu corrections={info['newton_its']} res0={info['res0']:.3e} res={info['res']:.3e} "
+          f"fgmres total={info['fgmres_its_total']} max={info['fgmres_its_max']}", flush=True)
+    assert ref.converged and info["converged"] == 1
+    assert info["newton_its"] == ref.corrections
+    assert abs(info["res0"] - ref.residuals[0]) <= 1e-12 * ref.residuals[0]
+    assert info["res"] <= 1e-8 * info["res0"]
+    assert np.linalg.norm(xg - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+    assert np.abs(Xn - ref.X).max() <= 1e-12

@@ -169,3 +169,19 @@ def test_fibre_law_rejects_invalid_structures(bad):
         s.segments = [dataclasses.replace(seg, X=seg.X[:M // 2]), dataclasses.replace(seg, X=seg.X[M // 2:])]
     with pytest.raises(CAVError):
         _analysis(s)
+
+
+def test_fibre_force_matches_oracle():
+    """The library's host force of the fibre law (Section 5.3) against the
+    oracle's, at the markers and at a displaced configuration (X_force)."""
+    from oracle import fibre, newton
+    from paper_2608_14310_amd import structure_force
+    s = workloads.flexible_fibre(64, 4, amp=0.3, seed=2)
+    p = newton.fibre_params(s)
+    X = s.markers().ravel()
+    for Xf in (None, X + np.random.default_rng(9).uniform(-0.3, 0.3, X.shape) * p["ds"]):
+        F = structure_force(s, Xf)
+        ref = fibre.force(X if Xf is None else Xf, p)
+        assert np.abs(F - ref).max() <= 1e-12 * np.abs(ref).max()
+    with pytest.raises(Exception):
+        structure_force(workloads.small_target(0))

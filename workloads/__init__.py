@@ -205,6 +205,15 @@ def flexible_fibre(N: int = 64, n_levels: int = 4, amp: float = 0.3, seed: int =
                   "fibre", kappa, [Segment(X, False, ds)], random_rhs(N, seed))
 
 
+def fibre_inflow_velocity(N: int, U: float = 1.0, noise: float = 0.1, seed: int = 0) -> np.ndarray:
+    """Velocity u^n (2N^2: u block, then v block) at the start of a fibre step:
+    the downward stream of Section 5.3, (0, -U), plus seeded uniform noise of
+    amplitude noise * U per face from default_rng([seed, 5])."""
+    u = np.zeros(2 * N * N)
+    u[N * N:] = -U
+    return u + noise * U * np.random.default_rng([seed, 5]).uniform(-1.0, 1.0, 2 * N * N)
+
+
 # Configurations named after the workloads they describe.
 def small_target(seed: int = 0) -> System:
     """32x32 grid, 3-level V-cycle, target points on a circle, kappa 1e4."""
