@@ -222,7 +222,8 @@ def fibre_leg(grids, iterates: int = 3):
     tangent law, patches, factors) and a multiplicative-CAV FGMRES solve to
     1e-10, as every Newton linear system needs. The paper's Table 3 row is
     given beside each as context (its counts are averages over a whole
-    time-dependent run, not over these configurations)."""
+    time-dependent run, not over these configurations). Each grid also times
+    one Newton step of the fibre in the downward stream (Section 2 scheme)."""
     import numpy as np
     import torch
 
@@ -261,12 +262,27 @@ def fibre_leg(grids, iterates: int = 3):
             t_setup.append(t1 - t0)
             t_solve.append(t2 - t1)
             assert inf["converged"] == 1, (N, amp)
+        # one backward-Euler step of the fibre in the downward stream by
+        # Newton's method (hierarchy rebuilt per Newton system, FGMRES 1e-9)
+        sn = workloads.flexible_fibre(N, n_levels, amp=0.3, seed=1)
+        un = workloads.fibre_inflow_velocity(N, seed=1)
+        rhs = torch.from_numpy(np.concatenate([sn.rho / sn.dt * un, np.zeros(N * N)])).cuda()
+        g.newton_solve(sn, rhs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, ninf = g.newton_solve(sn, rhs)
+        torch.cuda.synchronize()
+        t_newton = time.perf_counter() - t0
         g.close()
         fin = stats[-1]
         rows.append({"grid": N, "levels": n_levels, "M": len(s.markers()),
                      "fgmres_its": its, "setup_ms": round(1e3 * float(np.mean(t_setup)), 2),
                      "solve_ms": round(1e3 * float(np.mean(t_solve)), 2),
                      "patch_avg": round(fin["avg_np"], 2), "patch_max": fin["max_np"],
+                     "newton_step": {"corrections": ninf["newton_its"], "converged": ninf["converged"],
+                                     "fgmres_its_total": ninf["fgmres_its_total"],
+                                     "fgmres_its_max": ninf["fgmres_its_max"],
+                                     "ms": round(1e3 * t_newton, 2)},
                      "paper": paper.get(N)})
     return rows
 
