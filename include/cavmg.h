@@ -273,8 +273,9 @@ typedef struct {
  * K_0 the Stokes part of Eq. intro_saddle (A_0 = rho/dt I - mu L, G, -D) and
  * rhs device 3N^2 (rho/dt u^n plus any explicit terms; pressure part). Each
  * correction rebuilds the whole hierarchy with E = DF at the current
- * iterate (st->X_force ignored) and solves K_E dx = -R with CAV-preconditioned
- * FGMRES (lin_rtol) from zero. X_new: optional host 2M, X^{n+1} at the
+ * iterate (st->X_force ignored; the operator is kept when the iterate's
+ * configuration is the one it was built at) and solves K_E dx = -R with
+ * CAV-preconditioned FGMRES (lin_rtol) from zero. X_new: optional host 2M, X^{n+1} at the
  * solution. The context keeps the hierarchy of the last Newton system.
  * CAV_WARN_NOT_CONVERGED if max_newton corrections do not meet the tolerance;
  * a linear solve's error status is returned as is. */

@@ -233,10 +233,14 @@ class Analysis:
     """Host-only setup of one system (no device): E_E per level, patch sets,
     multiplicative phases and partition-of-unity weights, from libcavmg."""
 
-    def __init__(self, system, family: str = "cav", box=(4, 2)):
+    def __init__(self, system, family: str = "cav", box=(4, 2), X_force=None):
         self._L = lib()
         g = GridDesc(system.N, system.n_levels, system.rho, system.mu, system.dt)
         d, keep = describe_structure(system)
+        if X_force is not None:
+            xf = np.ascontiguousarray(np.asarray(X_force, dtype=np.float64).ravel())
+            d.X_force = _arr(xf, C.c_double)
+            keep = keep + (xf,)
         h = C.c_void_p()
         if family == "box":
             st = self._L.cav_analyze_box(C.byref(g), C.byref(d), int(box[0]), int(box[1]), C.byref(h))
@@ -433,12 +437,18 @@ class Solver:
             pass
 
     # ---- setup ----
-    def build_operator(self, system) -> None:
+    def build_operator(self, system, X_force=None) -> None:
+        """Operator and hierarchy of `system`; X_force (fibre law only): positions
+        at which the energies' tangent is evaluated, J and S staying at the markers."""
         self._sync_stream()
         g = GridDesc(system.N, system.n_levels, system.rho, system.mu, system.dt)
         d, keep = describe_structure(system)
+        xf = None
+        if X_force is not None:
+            xf = np.ascontiguousarray(np.asarray(X_force, dtype=np.float64).ravel())
+            d.X_force = _arr(xf, C.c_double)
         self._check(self._L.cav_build_operator(self._h, C.byref(g), C.byref(d)))
-        del keep
+        del keep, xf
         self.N, self.n_levels = system.N, system.n_levels
         self._ib_rows = 2 * d.M
 

@@ -1788,6 +1788,7 @@ cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_struc
     double* dnrm = static_cast<double*>(alloc(sizeof(double)));
     std::vector<double> Xk(2 * size_t(M)), U(2 * size_t(M)), Fh;
     const std::vector<double> Xn(st->X, st->X + 2 * size_t(M));
+    std::vector<double> built = Xn;  // configuration of the operator the context holds
     cav_newton_info inf{};
     cav_fgmres_opts fo{};
     fo.rtol = o->lin_rtol;
@@ -1822,8 +1823,13 @@ cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_struc
         break;
       }
       if (it == o->max_newton) break;
-      // the Newton system at X_k: hierarchy rebuilt with E = DF[X_k]
-      call(cav_build_operator(ctx, g, &d));
+      // the Newton system at X_k: hierarchy rebuilt with E = DF[X_k] (the
+      // operator is kept when X_k is the configuration it was built at, as for
+      // the first correction from rest)
+      if (Xk != built) {
+        call(cav_build_operator(ctx, g, &d));
+        built = Xk;
+      }
       call(cav_build_cav_patches(ctx, o->family, nullptr));
       call(cav_factor_patches(ctx, o->precision, o->cond_threshold, nullptr));
       call(cav_set_smoother(ctx, o->smoother, o->alpha, 1, 1));

@@ -133,3 +133,28 @@ def test_newton_step_matches_oracle(N, levels):
     assert info["res"] <= 1e-8 * info["res0"]
     assert np.linalg.norm(xg - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
     assert np.abs(Xn - ref.X).max() <= 1e-12
+
+
+def test_newton_edge_cases():
+    """No correction allowed: the initial residual is reported and the step is
+    flagged unconverged; a law other than the fibre is an argument error; two
+    identical steps in one context give bit-identical results."""
+    from paper_2608_14310_amd import CAVError, Solver
+    s = workloads.flexible_fibre(32, 3, amp=0.3, seed=2)
+    un = workloads.fibre_inflow_velocity(32, seed=2)
+    rhs = _t(np.concatenate([s.rho / s.dt * un, np.zeros(32 * 32)]))
+    print("[fibre] Newton edge cases N=32", flush=True)
+    g = Solver(0)
+    try:
+        x, Xn, info = g.newton_solve(s, rhs, max_newton=0)
+        assert info["newton_its"] == 0 and info["converged"] == 0 and info["res"] == info["res0"] > 0
+        assert info["status"] != 0
+        with pytest.raises(CAVError):
+            g.newton_solve(workloads.small_target(0), rhs)
+        x1, X1, i1 = g.newton_solve(s, rhs)
+        x2, X2, i2 = g.newton_solve(s, rhs)
+        torch.cuda.synchronize()
+        assert i1["converged"] == 1 and i1 == i2
+        assert torch.equal(x1, x2) and np.array_equal(X1, X2)
+    finally:
+        g.close()

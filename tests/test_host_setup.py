@@ -185,3 +185,35 @@ def test_fibre_force_matches_oracle():
         assert np.abs(F - ref).max() <= 1e-12 * np.abs(ref).max()
     with pytest.raises(Exception):
         structure_force(workloads.small_target(0))
+
+
+def test_fibre_tangent_at_x_force_matches_oracle():
+    """With X_force the fibre's tangent is taken there while J and S stay at
+    the markers (Section 2: S and J at the start of the step, the force at the
+    new configuration): finest E_E = S E(X_force) J against the oracle."""
+    from oracle import fibre, newton
+    from paper_2608_14310_amd._binding import Analysis
+    s = workloads.flexible_fibre(64, 3, amp=0.2, seed=3)
+    p = newton.fibre_params(s)
+    X = s.markers().ravel()
+    Xf = X + np.random.default_rng(4).uniform(-0.4, 0.4, X.shape) * p["ds"]
+    a = Analysis(s, X_force=Xf)
+    try:
+        rp, col, val = a.ee(s.n_levels - 1)
+    finally:
+        a.close()
+    n = 2 * s.N * s.N
+    G = sp.csr_matrix((val, col, rp), shape=(n, n))
+    J = ib.interpolation(s.N, s.markers())
+    S = ib.spreading(s.N, J, s.weights())
+    ref = (S @ fibre.tangent(Xf, p) @ J).tocsr()
+    d = (G - ref).tocsr()
+    assert abs(d).max() <= 1e-13 * abs(ref).max()
+    # and it differs from the tangent at the markers
+    a0 = Analysis(s)
+    try:
+        rp0, col0, val0 = a0.ee(s.n_levels - 1)
+    finally:
+        a0.close()
+    G0 = sp.csr_matrix((val0, col0, rp0), shape=(n, n))
+    assert abs(G0 - G).max() > 1e-6 * abs(ref).max()
