@@ -287,6 +287,43 @@ def fibre_leg(grids, iterates: int = 3):
     return rows
 
 
+def fibre_robustness_leg(N: int = 128):
+    """Table 4's parameter rows on the 128² grid: for each (Re, gamma_b,
+    gamma_s, gamma_c) one Newton step of the fibre in the downward stream from
+    rest (hierarchy rebuilt per Newton system, FGMRES 1e-9) and the largest
+    finest-level patch, with the paper's row beside it as context (its counts
+    are averages over a whole run)."""
+    import numpy as np
+    import torch
+
+    from paper_2608_14310_amd import Solver
+    import workloads
+    rows = []
+    with open(os.path.join(ROOT, "tests", "golden", "paper_table4.txt")) as f:
+        table = [line.split() for line in f if line.strip() and not line.startswith("#")]
+    n_levels = int(round(np.log2(N / 8))) + 1
+    g = Solver(0)
+    for v in table:
+        Re, gb, gs, gc = (float(t) for t in v[:4])
+        s = workloads.flexible_fibre(N, n_levels, amp=0.3, seed=1, Re=Re, gamma=(gb, gs, gc))
+        un = workloads.fibre_inflow_velocity(N, seed=1)
+        rhs = torch.from_numpy(np.concatenate([s.rho / s.dt * un, np.zeros(N * N)])).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, inf = g.newton_solve(s, rhs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stats = g.build_cav_patches("cav")
+        rows.append({"Re": Re, "gamma": [gb, gs, gc], "corrections": inf["newton_its"],
+                     "converged": inf["converged"], "fgmres_its_total": inf["fgmres_its_total"],
+                     "fgmres_its_max": inf["fgmres_its_max"], "patch_max": stats[-1]["max_np"],
+                     "ms": round(1e3 * (t1 - t0), 2),
+                     "paper": dict(zip(("newton_avg", "fgmres_avg", "fgmres_max", "patch_max"),
+                                       (float(t) for t in v[4:])))})
+    g.close()
+    return rows
+
+
 def box_comparison_leg():
     """CAV against B(b,o) box relaxation on the paper's membrane (Section 5.1):
     two-grid spectral radii of Fig. 2 (N = 32, coarse 16^2) assembled on the
@@ -558,6 +595,7 @@ def main():
                              "speedup": round(tc / tm, 2), "max_rel_diff_vs_single": float("%.3g" % diff)}
     if a.fibre_grids:
         line["fibre"] = fibre_leg(a.fibre_grids)
+        line["fibre_robustness"] = fibre_robustness_leg()
     sweep = []
     for kb in a.stiff_sweep:
         sk = workloads.beam_512(kb)

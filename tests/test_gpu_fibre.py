@@ -104,18 +104,21 @@ def test_interpolation_and_spreading_match_oracle():
     assert np.array_equal(y[2 * n2:], y0[2 * n2:])
 
 
-@pytest.mark.parametrize("N,levels", [(64, 4), (128, 5)])
-def test_newton_step_matches_oracle(N, levels):
+@pytest.mark.parametrize("N,levels,Re,gamma", [(64, 4, 200.0, (1.0, 1.0, 1.0)), (128, 5, 200.0, (1.0, 1.0, 1.0)),
+                                               (64, 4, 2000.0, (10.0, 10.0, 10.0)),
+                                               (64, 4, 200.0, (0.1, 1.0, 1.0))])
+def test_newton_step_matches_oracle(N, levels, Re, gamma):
     """One backward-Euler step of the fibre in the downward stream by Newton's
     method: every correction rebuilds the hierarchy on the GPU and solves with
     multiplicative-CAV FGMRES to 1e-9; the oracle solves every Newton system
-    directly. Same number of corrections, same solution."""
+    directly. Same number of corrections, same solution; baseline parameters
+    and two of Table 4's extreme rows."""
     from oracle import newton
     from paper_2608_14310_amd import Solver
-    s = workloads.flexible_fibre(N, levels, amp=0.3, seed=1)
+    s = workloads.flexible_fibre(N, levels, amp=0.3, seed=1, Re=Re, gamma=gamma)
     un = workloads.fibre_inflow_velocity(N, seed=1)
     rhs = np.concatenate([s.rho / s.dt * un, np.zeros(N * N)])
-    print(f"[fibre] Newton step N={N} levels={levels}", flush=True)
+    print(f"[fibre] Newton step N={N} levels={levels} Re={Re} gamma={gamma}", flush=True)
     ref = newton.solve(s, rhs, rtol=1e-8, atol=1e-8, max_newton=10)
     g = Solver(0)
     try:

@@ -169,7 +169,8 @@ def beam_fibres(N: int = 512, n_levels: int = 5, kappa_b: float = 1.0, kappa_s: 
                   "beam_open", {"kappa_b": kappa_b, "kappa_s": kappa_s}, segs, random_rhs(N, seed))
 
 
-def flexible_fibre(N: int = 64, n_levels: int = 4, amp: float = 0.3, seed: int = 0, **fluid) -> System:
+def flexible_fibre(N: int = 64, n_levels: int = 4, amp: float = 0.3, seed: int = 0, Re: float = 200.0,
+                   gamma=(1.0, 1.0, 1.0), **fluid) -> System:
     """The clamped flexible fibre of Section 5.3 mapped into the periodic unit
     square by similarity: the paper's (0,2)^2 cell, lengths and times scaled
     by 1/2 with the velocity scale, Reynolds number and energy scale kept.
@@ -186,7 +187,9 @@ def flexible_fibre(N: int = 64, n_levels: int = 4, amp: float = 0.3, seed: int =
     K_t s^2. Fluid: rho = 1,
     mu = 1.875e-3 s (paper Re kept), dt = 0.05 h (the paper's dt/h). The
     law's parameters ride in `kappa` (EI, K_s, K_p, K_t, clamp marker m,
-    clamp point)."""
+    clamp point). Table 4's variations: Re (mu scaled by 200 / Re) and
+    gamma = (gamma_b, gamma_s, gamma_c) multiplying EI, K_s and both clamp
+    penalties."""
     h = 1.0 / N
     ds = h / 2
     sc = 0.5
@@ -197,9 +200,10 @@ def flexible_fibre(N: int = 64, n_levels: int = 4, amp: float = 0.3, seed: int =
     X = np.stack([0.5 + s, 0.75 - amp * s ** 2 / L], axis=1)
     X = X + np.random.default_rng([seed, 2]).uniform(-0.05, 0.05, X.shape) * ds
     refine = N / 128.0
-    kappa = {"EI": 2.63672e-2 * sc ** 3, "K_s": 375.0 * refine * sc, "K_p": 1200.0 * refine,
-             "K_t": 7.03125 * refine * sc ** 2, "m": m, "clamp_x": 0.5, "clamp_y": 0.75}
-    f = dict(FLUID, mu=1.875e-3 * sc, dt=0.05 * h)
+    gb, gs, gc = gamma
+    kappa = {"EI": 2.63672e-2 * sc ** 3 * gb, "K_s": 375.0 * refine * sc * gs, "K_p": 1200.0 * refine * gc,
+             "K_t": 7.03125 * refine * sc ** 2 * gc, "m": m, "clamp_x": 0.5, "clamp_y": 0.75}
+    f = dict(FLUID, mu=1.875e-3 * sc * 200.0 / Re, dt=0.05 * h)
     f.update(fluid)
     return System(f"flexible_fibre_N{N}_a{amp:g}_s{seed}", N, n_levels, f["rho"], f["mu"], f["dt"],
                   "fibre", kappa, [Segment(X, False, ds)], random_rhs(N, seed))
