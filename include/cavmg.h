@@ -278,7 +278,8 @@ typedef struct {
  * CAV-preconditioned FGMRES (lin_rtol) from zero. X_new: optional host 2M, X^{n+1} at the
  * solution. The context keeps the hierarchy of the last Newton system.
  * CAV_WARN_NOT_CONVERGED if max_newton corrections do not meet the tolerance;
- * a linear solve's error status is returned as is. */
+ * a linear solve's error status is returned as is. After any status x holds
+ * the last iterate. */
 cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_structure_desc* st, const double* rhs,
                             double* x, double* X_new, const cav_newton_opts* opts, cav_newton_info* info);
 
