@@ -154,12 +154,19 @@ void free_ib_tables(Ctx& c) {
   c.d_ib_face = c.d_sp_face = c.d_sp_ptr = c.d_sp_row = nullptr;
   c.d_ib_w = c.d_sp_w = nullptr;
   c.ib_rows = c.ib_faces = 0;
+  c.ib_ready = false;
 }
 
 // J as 16 (face, weight) pairs per Lagrangian row; S = h^-2 J^T W grouped by
 // face (rows of one face in increasing order), so that spreading is a
 // deterministic gather per touched face
-void build_ib_tables(Ctx& c, int N, const Structure& S) {
+void build_ib_tables(Ctx& c) {
+  if (c.ib_ready) return;
+  Structure S;
+  S.M = int(c.ib_omega.size());
+  S.X = c.ib_X;
+  S.omega = c.ib_omega;
+  const int N = c.ib_N;
   std::vector<int32_t> face;
   std::vector<double> w;
   ib_supports(N, S, face, w);
@@ -190,6 +197,7 @@ void build_ib_tables(Ctx& c, int N, const Structure& S) {
   c.d_sp_ptr = upload(c, sptr);
   c.d_sp_row = upload(c, srow);
   c.d_sp_w = upload(c, sw);
+  c.ib_ready = true;
 }
 
 __global__ void k_ib_interp(int32_t nr, const int32_t* __restrict__ face, const double* __restrict__ w,
@@ -706,7 +714,6 @@ cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* g, const cav_str
   CAV_HIP(hipSetDevice(c.device));
   drop_coarse(c);
   for (auto& lev : c.lv) free_level(c, lev);
-  free_ib_tables(c);
   device_sync_epoch(c);
   c.lv.assign(L, Level());
   c.built = c.patched = c.factored = false;
@@ -725,7 +732,12 @@ cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* g, const cav_str
   }
   assemble_ee_finest(N, S, c.lv[L - 1].ee);
   for (int l = L - 1; l >= 1; --l) galerkin_coarsen(c.lv[l - 1].N, c.lv[l].ee, c.lv[l - 1].ee);
-  build_ib_tables(c, N, S);
+  if (!(c.ib_N == N && c.ib_X == S.X && c.ib_omega == S.omega)) {
+    free_ib_tables(c);
+    c.ib_N = N;
+    c.ib_X = S.X;
+    c.ib_omega = S.omega;
+  }
   for (int l = 0; l < L; ++l) {
     Level& lev = c.lv[l];
     const HostCSR& E = lev.ee;
@@ -1712,6 +1724,7 @@ cav_status cav_ib_interpolate(cav_ctx ctx, const double* x, double* U) {
   Ctx& c = ctx->c;
   API_BEGIN
   require(c.built, CAV_ERR_NOT_BUILT, "operator not built");
+  build_ib_tables(c);
   if (c.ib_rows == 0) return CAV_OK;
   require(x && U, CAV_ERR_INVALID_ARG, "x and U must be device pointers");
   k_ib_interp<<<nblocks(c.ib_rows), TPB, 0, c.stream>>>(c.ib_rows, c.d_ib_face, c.d_ib_w, x, U);
@@ -1725,6 +1738,7 @@ cav_status cav_ib_spread_add(cav_ctx ctx, const double* F, double* y) {
   Ctx& c = ctx->c;
   API_BEGIN
   require(c.built, CAV_ERR_NOT_BUILT, "operator not built");
+  build_ib_tables(c);
   if (c.ib_faces == 0) return CAV_OK;
   require(F && y, CAV_ERR_INVALID_ARG, "F and y must be device pointers");
   k_ib_spread<<<nblocks(c.ib_faces), TPB, 0, c.stream>>>(c.ib_faces, c.d_sp_face, c.d_sp_ptr, c.d_sp_row, c.d_sp_w, F,

@@ -225,6 +225,11 @@ struct Ctx {
   // interpolation J and spreading S at the structure positions of the last
   // operator build: per Lagrangian row its 16 faces and kernel weights; per
   // touched velocity face its rows and the weights omega * w / h^2
+  // (built on first use from the positions kept here, and kept across
+  // operator builds at the same positions)
+  bool ib_ready = false;
+  int ib_N = 0;
+  std::vector<double> ib_X, ib_omega;
   int32_t ib_rows = 0, ib_faces = 0;
   int32_t* d_ib_face = nullptr;
   double* d_ib_w = nullptr;
