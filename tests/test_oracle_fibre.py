@@ -114,3 +114,23 @@ def test_workload_has_the_papers_marker_counts():
         s = workloads.flexible_fibre(int(r[0]), 3)
         assert len(s.markers()) == int(r[1])
         assert s.kappa["m"] == int(r[1]) // 2
+
+
+def test_workload_parameters_map_the_papers_values():
+    """On the 128² grid (the paper's 128 x 128 grid, h = 1/64 in its cell) the
+    fibre's parameters are the paper's (Section 5.3) mapped by the length
+    scale 1/2: EI s^3, K_s s, K_p, K_t s^2, mu s; they double per halving of
+    h, and Table 4's factors multiply them."""
+    import workloads
+    s = workloads.flexible_fibre(128, 5)
+    k = s.kappa
+    assert np.isclose(k["EI"] * 8, 2.63672e-2) and np.isclose(k["K_s"] * 2, 375.0)
+    assert np.isclose(k["K_p"], 1200.0) and np.isclose(k["K_t"] * 4, 7.03125)
+    assert np.isclose(s.mu * 2, 1.875e-3) and np.isclose(s.dt, 0.05 / 128)
+    s2 = workloads.flexible_fibre(256, 6)
+    assert np.isclose(s2.kappa["K_s"], 2 * k["K_s"]) and np.isclose(s2.kappa["EI"], k["EI"])
+    s3 = workloads.flexible_fibre(128, 5, Re=2000.0, gamma=(10.0, 0.1, 10.0))
+    assert np.isclose(s3.mu, s.mu / 10) and np.isclose(s3.kappa["EI"], 10 * k["EI"])
+    assert np.isclose(s3.kappa["K_s"], 0.1 * k["K_s"]) and np.isclose(s3.kappa["K_t"], 10 * k["K_t"])
+    # Reynolds number rho U L / mu with U = 1 and the scaled length 0.1875
+    assert np.isclose(1.0 * 1.0 * 0.1875 / s.mu, 200.0)
