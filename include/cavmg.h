@@ -271,7 +271,9 @@ typedef struct {
  * st->X = X^n, and the residual
  *   R(x) = K_0 x - S^n F(X^n + dt J^n u) - rhs,
  * K_0 the Stokes part of Eq. intro_saddle (A_0 = rho/dt I - mu L, G, -D) and
- * rhs device 3N^2 (rho/dt u^n plus any explicit terms; pressure part). Each
+ * rhs device 3N^2 (rho/dt u^n plus any explicit terms; pressure part, whose
+ * mean must be zero: constant pressure is outside the range of K_0, so a
+ * nonzero mean would leave a residual no correction removes). Each
  * correction rebuilds the whole hierarchy with E = DF at the current
  * iterate (st->X_force ignored; the operator is kept when the iterate's
  * configuration is the one it was built at) and solves K_E dx = -R with
