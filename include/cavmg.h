@@ -232,6 +232,22 @@ cav_status cav_vcycle_multi(cav_ctx ctx, int32_t k, const double* R, double* Z);
  * estimate met rtol but the true FP64 residual exceeds 10 * rtol. */
 cav_status cav_fgmres_solve(cav_ctx ctx, const double* b, double* x, const cav_fgmres_opts* opts,
                             cav_solve_info* info);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+ * cav_fgmres_solve with the same arguments, kernels and results, whose Krylov
+ * workspace lives in a fixed device scratch of 512 MiB that the library holds
+ * per device until the process ends (looked up by cav_create), so the call
+ * makes no hipMalloc, hipFree or other device allocation. The workspace needs
+ * (2 max_it + 3) 3N^2 doubles plus O(max_it) partials (e.g. max_it <= 40 at
+ * 512^2, <= 166 at 256^2); larger requests return CAV_ERR_INVALID_ARG with the
+ * sizes in cav_last_error. use_learned must be 0 (CAV_ERR_INVALID_ARG
+ * otherwise) and no live-timing events are recorded. The context must be
+ * built and factored as for cav_fgmres_solve. Every context on one device
+ * shares that device's scratch: calls that overlap on one device (other host
+ * threads, other streams) race and must be serialised by the caller; each call
+ * initialises every part of the scratch it reads. */
+cav_status cav_fgmres_solve_noalloc(cav_ctx ctx, const double* b, double* x, const cav_fgmres_opts* opts,
+                                    cav_solve_info* info);
 
 /* ---- implicit IB step with a nonlinear force (Section 2 scheme, Section 5.3) ----
  * Interpolation U = J u (Section 2, Eq. intro_saddle) at the positions X of the

@@ -121,6 +121,7 @@ _SIGS = {
     "cav_vcycle": ([_P, _P, _P], C.c_int),
     "cav_vcycle_multi": ([_P, C.c_int32, _P, _P], C.c_int),
     "cav_fgmres_solve": ([_P, _P, _P, C.POINTER(FgmresOpts), C.POINTER(SolveInfo)], C.c_int),
+    "cav_fgmres_solve_noalloc": ([_P, _P, _P, C.POINTER(FgmresOpts), C.POINTER(SolveInfo)], C.c_int),
     "cav_level_apply": ([_P, C.c_int, C.c_int, _P, _P], C.c_int),
     "cav_level_N": ([_P, C.c_int], C.c_int32),
     "cav_export_patches": ([_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
@@ -534,14 +535,19 @@ class Solver:
         return y
 
     def fgmres_solve(self, b, rtol: float = 1e-10, max_it: int = 150, out=None, history: bool = True,
-                     learned: bool = False, graph: bool = False):
-        """FGMRES to rtol; graph=True replays the captured iteration body (same results)."""
+                     learned: bool = False, graph: bool = False, noalloc: bool = False):
+        """FGMRES to rtol; graph=True replays the captured iteration body (same
+        results); noalloc=True calls cav_fgmres_solve_noalloc (workspace in the
+        library's fixed scratch; pass `out` so the call allocates nothing)."""
         self._sync_stream()
         x = self.empty() if out is None else out
         hist = np.zeros(max_it, dtype=np.float64)
         o = FgmresOpts(float(rtol), int(max_it), 1 if learned else 0, _arr(hist, C.c_double) if history else None)
         info = SolveInfo()
-        fn = self._L.cav_fgmres_solve_graph if graph else self._L.cav_fgmres_solve
+        if graph and noalloc:
+            raise ValueError("graph and noalloc are separate entry points")
+        fn = (self._L.cav_fgmres_solve_graph if graph else
+              self._L.cav_fgmres_solve_noalloc if noalloc else self._L.cav_fgmres_solve)
         st = self._check(fn(self._h, _dev_ptr(b), _dev_ptr(x), C.byref(o), C.byref(info)))
         d = {f: getattr(info, f) for f, _ in SolveInfo._fields_}
         d["status"] = st

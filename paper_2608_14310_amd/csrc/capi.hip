@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <functional>
+#include <mutex>
 #include <unordered_map>
 
 #include "cav_internal.hpp"
@@ -22,6 +23,41 @@ struct cav_ctx_s {
 namespace cav {
 
 static cav_ctx_s* owner(Ctx& c) { return reinterpret_cast<cav_ctx_s*>(&c); }
+
+// Fixed device scratch of cav_fgmres_solve_noalloc: the FGMRES workspace for
+// callers that cannot allocate. Every device the library runs on holds its
+// own copy until the process ends. Host code never uses the array's name as
+// an address: cav_create looks the device address up once per device (with
+// that device current) and the entry point passes that address on.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = size_t(1) << 26;  // 512 MiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+static bool g_scratch_looked[NOALLOC_MAX_DEVICES];
+
+// Looks up the scratch's device address on `device`, which must be current.
+static hipError_t noalloc_lookup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipSuccess;
+  if (g_scratch_looked[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e;
+  }
+  g_scratch_ptr[device] = static_cast<double*>(p);
+  g_scratch_looked[device] = true;
+  return hipSuccess;
+}
+
+// The device address of `device`'s scratch, or nullptr if it is not known.
+static double* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+  return g_scratch_ptr[device];
+}
 
 // Device memory of a context. Released blocks stay with the context (up to
 // DEV_CACHE_CAP bytes) and are handed out again for a request of the same
@@ -350,15 +386,17 @@ void ensure_workspace(Ctx& c, int max_it) {
   c.ws_maxit = max_it;
 }
 
-// ||x||_2 of a device vector (fixed-order reduction), synchronising.
-double dnorm(Ctx& c, const double* x, int64_t n) {
+// ||x||_2 of a device vector (fixed-order reduction over `part`, result in
+// h[0]), synchronising.
+double dnorm_ws(Ctx& c, const double* x, int64_t n, double* part, double* h) {
   const int nb = dots_blocks(n);
-  launch_dots(x, n, 1, x, n, c.d_part, nb, c.d_h, c.stream);
+  launch_dots(x, n, 1, x, n, part, nb, h, c.stream);
   double v = 0;
-  CAV_HIP(hipMemcpyAsync(&v, c.d_h, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  CAV_HIP(hipMemcpyAsync(&v, h, sizeof(double), hipMemcpyDeviceToHost, c.stream));
   CAV_HIP(hipStreamSynchronize(c.stream));
   return std::sqrt(v);
 }
+double dnorm(Ctx& c, const double* x, int64_t n) { return dnorm_ws(c, x, n, c.d_part, c.d_h); }
 
 // A persistent sweep whose grid barrier timed out leaves a flag: report it.
 void check_sweep_flags(Ctx& c) {
@@ -609,6 +647,144 @@ void learned_stage(Ctx& c, const double* v, double* z, int nbk) {
   launch_axpy_dev(z, c.d_sc + 3, cc, n, s);
 }
 
+// Workspace of one FGMRES solve: the Krylov bases V ((m + 1) n doubles) and
+// Z (m n), the operator output w and the projected right-hand side bb (n
+// each), the device Hessenberg column h (3 (m + 2)), the dot-product partials
+// (dots_blocks(n) (m + 2)), and hh, a host buffer of 3 (m + 2) doubles.
+struct KrylovWs {
+  double *V, *Z, *w, *bb, *h, *part, *hh;
+};
+
+// Arguments shared by the FGMRES entry points; returns max_it.
+int check_fgmres_args(const Ctx& c, const double* b, const double* x, const cav_fgmres_opts* opts) {
+  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require(b && x && b != x, CAV_ERR_INVALID_ARG, "b and x must be distinct device pointers");
+  const double rtol = opts ? opts->rtol : 1e-10;
+  const int max_it = opts ? opts->max_it : 150;
+  require(max_it >= 1 && max_it <= 10000 && rtol >= 0.0, CAV_ERR_INVALID_ARG, "bad FGMRES options");
+  return max_it;
+}
+
+// The FGMRES solve of cav_fgmres_solve on a given workspace (Section 5).
+cav_status fgmres_core(Ctx& c, const double* b, double* x, const cav_fgmres_opts* opts, cav_solve_info* info,
+                       const KrylovWs& ws) {
+  const double rtol = opts ? opts->rtol : 1e-10;
+  const int max_it = opts ? opts->max_it : 150;
+  hipStream_t s = c.stream;
+  Level& F = c.lv.back();
+  const int64_t n = 3 * int64_t(F.N) * F.N, n2 = int64_t(F.N) * F.N;
+  // b' = b with the pressure mean projected out (the range of K_E excludes constant pressure)
+  CAV_HIP(hipMemcpyAsync(ws.bb, b, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_block_sum(ws.bb + 2 * n2, n2, ws.part, ws.h, s);
+  double psum = 0.0;
+  CAV_HIP(hipMemcpyAsync(&psum, ws.h, sizeof(double), hipMemcpyDeviceToHost, s));
+  CAV_HIP(hipStreamSynchronize(s));
+  const double pmean = psum / double(n2);
+  require(std::isfinite(pmean), CAV_ERR_INVALID_ARG, "right-hand side is not finite");
+  launch_pressure_mean_remove(ws.bb, F.N, ws.part, s);
+  CAV_HIP(hipGetLastError());
+  const double beta = dnorm_ws(c, ws.bb, n, ws.part, ws.h);
+  cav_solve_info inf{};
+  if (!(beta > 0.0) || !std::isfinite(beta)) {
+    require(std::isfinite(beta), CAV_ERR_INVALID_ARG, "right-hand side is not finite");
+    launch_fill(x, 0.0, n, s);
+    CAV_HIP(hipStreamSynchronize(s));
+    inf.converged = 1;
+    if (info) *info = inf;
+    return CAV_OK;
+  }
+  double* V = ws.V;
+  double* Z = ws.Z;
+  k_axpby<<<nblocks(n), TPB, 0, s>>>(V, 1.0 / beta, ws.bb, 0.0, n);
+  const int nbk = dots_blocks(n);
+  launch_clear_sweep_flags(c, s);
+  const bool learned = opts && opts->use_learned;
+  if (learned) {
+    require(c.net != nullptr, CAV_ERR_NOT_BUILT, "use_learned is set but no net is attached");
+    ensure_stage_workspace(c);
+    CAV_HIP(hipMemsetAsync(c.d_sc, 0, 8 * sizeof(double), s));
+  }
+  std::vector<double> H(size_t(max_it + 1) * max_it, 0.0), cs(max_it), sn(max_it), g(max_it + 1, 0.0);
+  auto Hat = [&](int i, int j) -> double& { return H[size_t(j) * (max_it + 1) + i]; };
+  g[0] = beta;
+  int k = 0;
+  bool conv = false;
+  double est = 1.0;
+  double* hd1 = ws.h;
+  double* hd2 = ws.h + (max_it + 2);
+  double* hdn = ws.h + 2 * (max_it + 2);
+  double* hh = ws.hh;
+  for (int j = 0; j < max_it; ++j) {
+    double* vj = V + int64_t(j) * n;
+    double* zj = Z + int64_t(j) * n;
+    vcycle_top(c, vj, zj);
+    if (learned) learned_stage(c, vj, zj, nbk);
+    double* w = ws.w;
+    launch_apply_op(F, zj, w, nullptr, s);
+    // CGS2
+    launch_dots(V, n, j + 1, w, n, ws.part, nbk, hd1, s);
+    launch_multi_axpy(w, V, n, j + 1, hd1, -1.0, n, s);
+    launch_dots(V, n, j + 1, w, n, ws.part, nbk, hd2, s);
+    launch_multi_axpy(w, V, n, j + 1, hd2, -1.0, n, s);
+    launch_dots(w, n, 1, w, n, ws.part, nbk, hdn, s);
+    CAV_HIP(hipMemcpyAsync(hh, ws.h, size_t(3 * (max_it + 2)) * sizeof(double), hipMemcpyDeviceToHost, s));
+    CAV_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i <= j; ++i) Hat(i, j) = hh[i] + hh[(max_it + 2) + i];
+    const double hn = std::sqrt(hh[2 * (max_it + 2)]);
+    Hat(j + 1, j) = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = Hat(i, j), bq = Hat(i + 1, j);
+      Hat(i, j) = cs[i] * a + sn[i] * bq;
+      Hat(i + 1, j) = -sn[i] * a + cs[i] * bq;
+    }
+    const double rr = std::hypot(Hat(j, j), Hat(j + 1, j));
+    const double cj = rr == 0.0 ? 1.0 : Hat(j, j) / rr, sj = rr == 0.0 ? 0.0 : Hat(j + 1, j) / rr;
+    cs[j] = cj;
+    sn[j] = sj;
+    Hat(j, j) = rr;
+    Hat(j + 1, j) = 0.0;
+    g[j + 1] = -sj * g[j];
+    g[j] = cj * g[j];
+    k = j + 1;
+    est = std::fabs(g[j + 1]) / beta;
+    if (opts && opts->history) opts->history[j] = est;
+    if (!std::isfinite(est)) throw StatusError(CAV_ERR_INVALID_ARG, "non-finite value in FGMRES (check inputs)");
+    if (est <= rtol) { conv = true; break; }
+    if (hn == 0.0) { conv = true; break; }
+    k_axpby<<<nblocks(n), TPB, 0, s>>>(V + int64_t(j + 1) * n, 1.0 / hn, w, 0.0, n);
+  }
+  // y = H_k^{-1} g, x = Z_k y
+  std::vector<double> y(k, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int q = i + 1; q < k; ++q) acc -= Hat(i, q) * y[q];
+    y[i] = acc / Hat(i, i);
+  }
+  CAV_HIP(hipMemcpyAsync(ws.h, y.data(), size_t(k) * sizeof(double), hipMemcpyHostToDevice, s));
+  launch_fill(x, 0.0, n, s);
+  launch_multi_axpy(x, Z, n, k, ws.h, 1.0, n, s);
+  // true residual in FP64
+  launch_apply_op(F, x, ws.w, ws.bb, s);
+  const double rn = dnorm_ws(c, ws.w, n, ws.part, ws.h);
+  check_sweep_flags(c);
+  inf.iterations = k;
+  inf.converged = conv ? 1 : 0;
+  inf.est_rel_residual = est;
+  inf.true_rel_residual = rn / beta;
+  inf.pressure_mean_removed = pmean;
+  if (learned) {
+    double cnt[2] = {0.0, 0.0};
+    CAV_HIP(hipMemcpyAsync(cnt, c.d_sc + 4, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    CAV_HIP(hipStreamSynchronize(s));
+    inf.learned_accepted = int32_t(cnt[0]);
+    inf.learned_rejected = int32_t(cnt[1]);
+  }
+  if (info) *info = inf;
+  if (!conv) return CAV_WARN_NOT_CONVERGED;
+  if (inf.true_rel_residual > 10.0 * rtol) return CAV_WARN_FLOOR_LIMITED;
+  return CAV_OK;
+}
+
 }  // namespace
 }  // namespace cav
 
@@ -654,6 +830,7 @@ cav_status cav_create(cav_ctx* out, int device, void* stream) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CAV_ERR_INVALID_ARG;
   if (hipSetDevice(device) != hipSuccess) return CAV_ERR_HIP;
+  if (noalloc_lookup(device) != hipSuccess) return CAV_ERR_HIP;
   cav_ctx ctx = new (std::nothrow) cav_ctx_s();
   if (!ctx) return CAV_ERR_OUT_OF_MEMORY;
   ctx->c.device = device;
@@ -986,125 +1163,48 @@ cav_status cav_fgmres_solve(cav_ctx ctx, const double* b, double* x, const cav_f
   if (!ctx) return CAV_ERR_INVALID_ARG;
   Ctx& c = ctx->c;
   API_BEGIN
-  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
-  require(b && x && b != x, CAV_ERR_INVALID_ARG, "b and x must be distinct device pointers");
-  const double rtol = opts ? opts->rtol : 1e-10;
-  const int max_it = opts ? opts->max_it : 150;
-  require(max_it >= 1 && max_it <= 10000 && rtol >= 0.0, CAV_ERR_INVALID_ARG, "bad FGMRES options");
-  hipStream_t s = c.stream;
-  Level& F = c.lv.back();
-  const int64_t n = 3 * int64_t(F.N) * F.N, n2 = int64_t(F.N) * F.N;
+  const int max_it = check_fgmres_args(c, b, x, opts);
   ensure_workspace(c, max_it);
-  // b' = b with the pressure mean projected out (the range of K_E excludes constant pressure)
-  CAV_HIP(hipMemcpyAsync(c.d_bb, b, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
-  launch_block_sum(c.d_bb + 2 * n2, n2, c.d_part, c.d_h, s);
-  double psum = 0.0;
-  CAV_HIP(hipMemcpyAsync(&psum, c.d_h, sizeof(double), hipMemcpyDeviceToHost, s));
-  CAV_HIP(hipStreamSynchronize(s));
-  const double pmean = psum / double(n2);
-  require(std::isfinite(pmean), CAV_ERR_INVALID_ARG, "right-hand side is not finite");
-  launch_pressure_mean_remove(c.d_bb, F.N, c.d_part, s);
-  CAV_HIP(hipGetLastError());
-  const double beta = dnorm(c, c.d_bb, n);
-  cav_solve_info inf{};
-  if (!(beta > 0.0) || !std::isfinite(beta)) {
-    require(std::isfinite(beta), CAV_ERR_INVALID_ARG, "right-hand side is not finite");
-    CAV_HIP(hipMemsetAsync(x, 0, size_t(n) * sizeof(double), s));
-    CAV_HIP(hipStreamSynchronize(s));
-    inf.converged = 1;
-    if (info) *info = inf;
-    return CAV_OK;
+  const KrylovWs ws{c.d_V, c.d_Z, c.d_w, c.d_bb, c.d_h, c.d_part, c.h_pinned};
+  return fgmres_core(c, b, x, opts, info, ws);
+  API_END
+}
+
+cav_status cav_fgmres_solve_noalloc(cav_ctx ctx, const double* b, double* x, const cav_fgmres_opts* opts,
+                                    cav_solve_info* info) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  Ctx& c = ctx->c;
+  API_BEGIN
+  const int max_it = check_fgmres_args(c, b, x, opts);
+  require(!(opts && opts->use_learned), CAV_ERR_INVALID_ARG,
+          "cav_fgmres_solve_noalloc does not run the learned stage (its workspace is allocated on first use)");
+  double* base = noalloc_scratch(c.device);
+  require(base != nullptr, CAV_ERR_HIP, "the device address of the no-allocation scratch is not known");
+  const int64_t n = 3 * int64_t(c.lv.back().N) * c.lv.back().N;
+  const int64_t part = int64_t(dots_blocks(n)) * (max_it + 2);
+  // blocks of the workspace, each starting on a 256-byte boundary (32 doubles)
+  auto up = [](int64_t v) { return (v + 31) & ~int64_t(31); };
+  const int64_t oV = 0, oZ = oV + up((max_it + 1) * n), ow = oZ + up(int64_t(max_it) * n), obb = ow + up(n),
+                oh = obb + up(n), op = oh + up(3 * (max_it + 2)), total = op + up(part);
+  if (total > int64_t(NOALLOC_SCRATCH_DOUBLES))
+    throw StatusError(CAV_ERR_INVALID_ARG,
+                      "cav_fgmres_solve_noalloc: max_it " + std::to_string(max_it) + " at " +
+                          std::to_string(n) + " unknowns needs " + std::to_string(total * 8) +
+                          " bytes of workspace; the fixed scratch holds " +
+                          std::to_string(NOALLOC_SCRATCH_DOUBLES * 8) + " bytes");
+  std::vector<double> hh(size_t(3 * (max_it + 2)));
+  const KrylovWs ws{base + oV, base + oZ, base + ow, base + obb, base + oh, base + op, hh.data()};
+  // no timing events either (creating one is a runtime allocation)
+  const bool timing = c.timing;
+  c.timing = false;
+  try {
+    const cav_status st = fgmres_core(c, b, x, opts, info, ws);
+    c.timing = timing;
+    return st;
+  } catch (...) {
+    c.timing = timing;
+    throw;
   }
-  double* V = c.d_V;
-  double* Z = c.d_Z;
-  k_axpby<<<nblocks(n), TPB, 0, s>>>(V, 1.0 / beta, c.d_bb, 0.0, n);
-  const int nbk = dots_blocks(n);
-  launch_clear_sweep_flags(c, s);
-  const bool learned = opts && opts->use_learned;
-  if (learned) {
-    require(c.net != nullptr, CAV_ERR_NOT_BUILT, "use_learned is set but no net is attached");
-    ensure_stage_workspace(c);
-    CAV_HIP(hipMemsetAsync(c.d_sc, 0, 8 * sizeof(double), s));
-  }
-  std::vector<double> H(size_t(max_it + 1) * max_it, 0.0), cs(max_it), sn(max_it), g(max_it + 1, 0.0);
-  auto Hat = [&](int i, int j) -> double& { return H[size_t(j) * (max_it + 1) + i]; };
-  g[0] = beta;
-  int k = 0;
-  bool conv = false;
-  double est = 1.0;
-  double* hd1 = c.d_h;
-  double* hd2 = c.d_h + (max_it + 2);
-  double* hdn = c.d_h + 2 * (max_it + 2);
-  double* hh = c.h_pinned;
-  for (int j = 0; j < max_it; ++j) {
-    double* vj = V + int64_t(j) * n;
-    double* zj = Z + int64_t(j) * n;
-    vcycle_top(c, vj, zj);
-    if (learned) learned_stage(c, vj, zj, nbk);
-    double* w = c.d_w;
-    launch_apply_op(F, zj, w, nullptr, s);
-    // CGS2
-    launch_dots(V, n, j + 1, w, n, c.d_part, nbk, hd1, s);
-    launch_multi_axpy(w, V, n, j + 1, hd1, -1.0, n, s);
-    launch_dots(V, n, j + 1, w, n, c.d_part, nbk, hd2, s);
-    launch_multi_axpy(w, V, n, j + 1, hd2, -1.0, n, s);
-    launch_dots(w, n, 1, w, n, c.d_part, nbk, hdn, s);
-    CAV_HIP(hipMemcpyAsync(hh, c.d_h, size_t(3 * (max_it + 2)) * sizeof(double), hipMemcpyDeviceToHost, s));
-    CAV_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i <= j; ++i) Hat(i, j) = hh[i] + hh[(max_it + 2) + i];
-    const double hn = std::sqrt(hh[2 * (max_it + 2)]);
-    Hat(j + 1, j) = hn;
-    for (int i = 0; i < j; ++i) {
-      const double a = Hat(i, j), bq = Hat(i + 1, j);
-      Hat(i, j) = cs[i] * a + sn[i] * bq;
-      Hat(i + 1, j) = -sn[i] * a + cs[i] * bq;
-    }
-    const double rr = std::hypot(Hat(j, j), Hat(j + 1, j));
-    const double cj = rr == 0.0 ? 1.0 : Hat(j, j) / rr, sj = rr == 0.0 ? 0.0 : Hat(j + 1, j) / rr;
-    cs[j] = cj;
-    sn[j] = sj;
-    Hat(j, j) = rr;
-    Hat(j + 1, j) = 0.0;
-    g[j + 1] = -sj * g[j];
-    g[j] = cj * g[j];
-    k = j + 1;
-    est = std::fabs(g[j + 1]) / beta;
-    if (opts && opts->history) opts->history[j] = est;
-    if (!std::isfinite(est)) throw StatusError(CAV_ERR_INVALID_ARG, "non-finite value in FGMRES (check inputs)");
-    if (est <= rtol) { conv = true; break; }
-    if (hn == 0.0) { conv = true; break; }
-    k_axpby<<<nblocks(n), TPB, 0, s>>>(V + int64_t(j + 1) * n, 1.0 / hn, w, 0.0, n);
-  }
-  // y = H_k^{-1} g, x = Z_k y
-  std::vector<double> y(k, 0.0);
-  for (int i = k - 1; i >= 0; --i) {
-    double acc = g[i];
-    for (int q = i + 1; q < k; ++q) acc -= Hat(i, q) * y[q];
-    y[i] = acc / Hat(i, i);
-  }
-  CAV_HIP(hipMemcpyAsync(c.d_h, y.data(), size_t(k) * sizeof(double), hipMemcpyHostToDevice, s));
-  CAV_HIP(hipMemsetAsync(x, 0, size_t(n) * sizeof(double), s));
-  launch_multi_axpy(x, Z, n, k, c.d_h, 1.0, n, s);
-  // true residual in FP64
-  launch_apply_op(F, x, c.d_w, c.d_bb, s);
-  const double rn = dnorm(c, c.d_w, n);
-  check_sweep_flags(c);
-  inf.iterations = k;
-  inf.converged = conv ? 1 : 0;
-  inf.est_rel_residual = est;
-  inf.true_rel_residual = rn / beta;
-  inf.pressure_mean_removed = pmean;
-  if (learned) {
-    double cnt[2] = {0.0, 0.0};
-    CAV_HIP(hipMemcpyAsync(cnt, c.d_sc + 4, sizeof(cnt), hipMemcpyDeviceToHost, s));
-    CAV_HIP(hipStreamSynchronize(s));
-    inf.learned_accepted = int32_t(cnt[0]);
-    inf.learned_rejected = int32_t(cnt[1]);
-  }
-  if (info) *info = inf;
-  if (!conv) return CAV_WARN_NOT_CONVERGED;
-  if (inf.true_rel_residual > 10.0 * rtol) return CAV_WARN_FLOOR_LIMITED;
-  return CAV_OK;
   API_END
 }
 
