@@ -41,9 +41,15 @@ class Level:
 
 class Hierarchy:
     def __init__(self, system, family: str = "cav", alpha: float = 1.0, smoother: str = "additive",
-                 box=(4, 2), order: str = "explicit_first"):
+                 box=(4, 2), order: str = "explicit_first", lex: str = "y_fast"):
+        """lex: the reading of the paper's lexicographic patch order for the
+        sequential multiplicative smoother (Section 3.3): "y_fast" visits
+        cells (i, j) with the y index j fastest (the vector layout's order),
+        "x_fast" with the x index i fastest (boxes by their lower-left cells
+        alike)."""
         self.system = system
         self.order = order
+        self.lex = lex
         self.alpha = alpha
         self.smoother = smoother
         self.family = family
@@ -71,6 +77,17 @@ class Hierarchy:
             else:
                 raise ValueError(family)
             lev.cnt = pmod.patch_counts(lev.K.shape[0], lev.patches)
+            if smoother == "multiplicative" and lex == "x_fast":
+                # the same patches, visited with the x index fastest
+                if family == "box":
+                    nb = lev.N // box[0]
+                    perm = sorted(range(len(lev.patches)), key=lambda k: (k % nb, k // nb))
+                else:
+                    perm = sorted(range(len(lev.patches)), key=lambda c: (c % lev.N, c // lev.N))
+                lev.patches = [lev.patches[k] for k in perm]
+                lev.standard = np.asarray(lev.standard)[perm]
+                if lev.inject is not None:
+                    lev.inject = [lev.inject[k] for k in perm]
             lev.solvers = smoothers.PatchSolvers(lev.K, lev.patches, lev.standard, lev.inject)
         # coarsest: dense bordered LU
         K0 = self.levels[0].K.toarray()

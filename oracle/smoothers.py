@@ -169,11 +169,28 @@ def restricted_additive_sweep(K, solvers: PatchSolvers, b, w, alpha: float, N: i
     return remove_mean_pressure(w + alpha * z, N)
 
 
+def _update_columns(K, solvers: PatchSolvers, inject):
+    """K[:, q] for the unknowns q each patch updates (all of the patch, or its
+    injected part), sliced once and kept on the solvers object for later
+    sweeps with the same K."""
+    key = (id(K), inject is not None)
+    cached = getattr(solvers, "_update_cols", None)
+    if cached is None or cached[0] != key:
+        Kc = K.tocsc()
+        cols = []
+        for k, p in enumerate(solvers.patches):
+            q = p[inject[k]] if inject is not None else p
+            cols.append(Kc[:, q])
+        cached = (key, cols)
+        solvers._update_cols = cached
+    return cached[1]
+
+
 def multiplicative_sweep(K, solvers: PatchSolvers, b, w, N: int, inject=None):
     """Multiplicative Schwarz in the given patch order (Section 3.3). With
     `inject` masks only the unknowns of the unexpanded block are updated
     (restricted injection for box patches)."""
-    Kc = K.tocsc()
+    cols = _update_columns(K, solvers, inject)
     w = w.copy()
     r = b - K @ w
     for k, p in enumerate(solvers.patches):
@@ -182,5 +199,5 @@ def multiplicative_sweep(K, solvers: PatchSolvers, b, w, N: int, inject=None):
             m = inject[k]
             p, d = p[m], d[m]
         w[p] += d
-        r -= Kc[:, p] @ d
+        r -= cols[k] @ d
     return remove_mean_pressure(w, N)
