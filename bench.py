@@ -5,15 +5,20 @@ length 0.4, ds = h/2, bending kappa_b = 1e-2, springs 1e4, 5-level V(1,1)):
 build_operator -> build_cav_patches -> factor_patches -> fgmres_solve to 1e-10.
 `value` is the mean wall time per step (T_total, ms, lower is better);
 `t_solve_ms` is the solve alone. Inputs (markers, RHS on the device) are
-prepared before the timed region; the phase kernels follow the library's
-default table (the cooperative form with a shared residual; the autotuned
-table is measured and reported after the timed steps). The dominant kernel
-(explicit-patch phase kernel of the multiplicative smoother) is timed live
-with HIP events on the library stream around each run of phase launches.
+prepared before the timed region; the smoother follows the library's
+default table (a launch per colour phase in the cooperative form with a
+shared residual; the autotuned table, which may pick the one-launch dataflow
+sweep per level, is measured and reported after the timed steps).
+The dominant kernel (the explicit-patch kernel of the multiplicative
+smoother) is timed live with HIP events on the library stream around its
+launches.
 After the timed steps: the other precision on the same system, the stiffer
-kappa_b values (reported with their iteration counts), the learned stage
-(trained on 256^2 pairs, judged on this solve), the batched mix of independent
-systems in one captured graph, and the CPU oracle on a bounded sample.
+kappa_b values (reported with their iteration counts), the weighted additive
+smoother (its V-cycle here, time-to-1e-10 on the 256^2 membrane), the
+learned stage (trained on 256^2 pairs, judged on this solve), the batched
+mix of independent systems in one captured graph, and the CPU oracle (a
+bounded sample of this workload, and whole solves of the 32^2 and 256^2
+systems). `vcycle_gbs` is the V-cycle's algorithmic bytes over its time.
 """
 from __future__ import annotations
 
@@ -49,21 +54,42 @@ def measured_traffic(kernel: str, precision: str, smoother: str, tune: str):
     return int(kib * 1024)
 
 
-def cpu_baseline(kappa_b: float, iters_gpu: int, smoother: str, alpha: float, sample_patches: int = 400):
-    """The FP64 oracle on a bounded sample of the same 512^2 workload, timed on
-    one host core: E_E, the Galerkin hierarchy and every level's patch family
-    are built in full; the local factorisations and the smoother's per-patch
-    work are timed on a sample of patches per level and scaled to the level's
-    patch count; one V(1,1) cycle is then two sweeps per smoothed level, and the
-    solve is the GPU's iteration count of V-cycle + operator apply."""
+def host_cores() -> int:
+    """Host cores this process may use (its affinity set, capped by OMP_NUM_THREADS)."""
+    n = len(os.sched_getaffinity(0))
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    return max(n, 1)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_sampled_512(kappa_b: float, iters_gpu: int, threads: int, sample_patches: int):
+    """The FP64 oracle on a bounded sample of the 512^2 headline workload with
+    `threads` BLAS threads: E_E, the Galerkin hierarchy and every level's patch
+    family are built in full; the local factorisations and the multiplicative
+    smoother's per-patch work are timed on a sample of patches per level and
+    scaled to the level's patch count; one V(1,1) cycle is then two sweeps per
+    smoothed level, and the solve is the GPU's iteration count of V-cycle +
+    operator apply. Returns (total ms, sweep s, build s)."""
     import numpy as np
-    import scipy.sparse as sp
     from threadpoolctl import threadpool_limits
 
     import workloads
     from oracle import hierarchy, ib, mac, patches as pmod, smoothers
 
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         s = workloads.beam_512(kappa_b)
         t0 = time.perf_counter()
         EE, pat = ib.eulerian_elasticity(s)
@@ -98,12 +124,138 @@ def cpu_baseline(kappa_b: float, iters_gpu: int, smoother: str, alpha: float, sa
         t_apply = (time.perf_counter() - ta) / 3
     setup = t_build + t_pat + t_fact
     per_it = 2 * t_sweep + t_apply
-    total_ms = 1e3 * (setup + iters_gpu * per_it)
-    return {"value": round(total_ms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": (f"512^2 beam kappa_b={kappa_b:g}, {smoother} CAV: E_E + hierarchy + patch families in full "
-                       f"({t_build + t_pat:.1f} s); factorisation and one smoother step timed on {sample_patches} "
-                       f"random patches per level and scaled to each level's patch count; V-cycle = 2 sweeps "
-                       f"({2 * t_sweep:.1f} s est.) + K apply; extrapolated to {iters_gpu} iterations")}
+    return 1e3 * (setup + iters_gpu * per_it), 2 * t_sweep, t_build + t_pat
+
+
+def cpu_full_solve(system, alpha: float, threads: int):
+    """A whole oracle FGMRES solve (setup, then the solve to 1e-10) with the
+    weighted additive CAV V(1,1) cycle and `threads` BLAS threads."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import krylov, multigrid
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        H = multigrid.Hierarchy(system, alpha=alpha, smoother="additive")
+        K = H.levels[-1].K
+        t1 = time.perf_counter()
+        res = krylov.fgmres(lambda v: K @ v, H.vcycle, system.b, 1e-10, 150)
+        t2 = time.perf_counter()
+    return {"setup_ms": round(1e3 * (t1 - t0), 1), "solve_ms": round(1e3 * (t2 - t1), 1),
+            "total_ms": round(1e3 * (t2 - t0), 1), "iterations": res.iterations, "threads": threads}
+
+
+def cpu_baseline(kappa_b: float, iters_gpu: int, smoother: str, gpu_full: dict, sample_patches: int = 200):
+    """The oracle as it stands, on the host cores: the headline workload on a
+    bounded sample (extrapolated, all host cores and 1 thread), and whole
+    solves of the 32^2 target and 256^2 membrane systems (additive cycle,
+    all host cores and 1 thread) beside the GPU's solves of the same systems
+    in this run."""
+    import workloads
+    cores = host_cores()
+    total, sweep_s, build_s = cpu_sampled_512(kappa_b, iters_gpu, cores, sample_patches)
+    total1, _, _ = cpu_sampled_512(kappa_b, iters_gpu, 1, sample_patches)
+    full = {}
+    for key, system in (("target32", workloads.small_target(0)), ("membrane256", workloads.membrane_256(1e4))):
+        rows = [cpu_full_solve(system, 0.7, t) for t in (cores, 1)]
+        full[key] = {"all_cores": rows[0], "one_thread": rows[1], "gpu": gpu_full.get(key)}
+    return {"value": round(total, 1), "unit": "ms", "cores": cores, "kind": "oracle",
+            "sample": (f"512^2 beam kappa_b={kappa_b:g}, {smoother} CAV, {cores} BLAS threads: E_E + hierarchy + "
+                       f"patch families in full ({build_s:.1f} s); factorisation and one smoother step timed on "
+                       f"{sample_patches} random patches per level and scaled to each level's patch count; "
+                       f"V-cycle = 2 sweeps ({sweep_s:.1f} s est.) + K apply; extrapolated to {iters_gpu} "
+                       "iterations (an extrapolation, not a whole solve)"),
+            "one_thread_value": round(total1, 1), "cpu_model": cpu_model(),
+            "threads": {"blas": cores, "python": 1},
+            "full_solves": full}
+
+
+def vcycle_bytes(stats, fst, N: int, n_levels: int, precision: str) -> float:
+    """Algorithmic HBM bytes of one V(1,1) cycle (what the method must move):
+    per smoothed level two sweeps, each streaming its explicit patches'
+    inverses (sum n_p^2 s; the shared far-field inverse is free) and their
+    index / gathered residual / update (20 B per patch unknown), about ten
+    vector passes (residual, transfers, mean removal, far-field colours) and
+    the E_E rows of two operator applies (12 B per nonzero); then the dense
+    coarsest solution operator once (n_c^2 8 B)."""
+    total = 0.0
+    fbytes = float(fst["factor_bytes"])  # per sweep, all levels, at the stored precisions
+    for l in range(1, n_levels):
+        st = stats[l]
+        Nl = N >> (n_levels - 1 - l)
+        sum_np = st["avg_np"] * st["n_patches"] - 5.0 * (st["n_patches"] - st["n_explicit"])
+        total += 2 * 20.0 * sum_np + 10 * 3 * Nl * Nl * 8.0 + 2 * st["ee_nnz"] * 12.0
+    total += 2 * fbytes
+    nc = 3 * (N >> (n_levels - 1)) ** 2
+    return total + nc * nc * 8.0
+
+
+def additive_leg(dev, reps: int = 10, membrane: bool = True):
+    """North-star smoother (Appendix A, weighted additive CAV, alpha 0.7): its
+    V-cycle on the 512^2 beam system (FGMRES with it stalls there, so only
+    the cycle is timed), with the patch-inverse GEMV kernel's live
+    bandwidth; then time-to-1e-10 on the 256^2 membrane (kappa_s = 1e4),
+    where it converges, beside the multiplicative cycle."""
+    import torch
+
+    import workloads
+    from paper_2608_14310_amd import Solver
+    s = workloads.beam_512(1e-2)
+    g = Solver(0)
+    stats, fst = g.setup(s, precision="fp64", alpha=0.7, smoother="additive")
+    b = torch.from_numpy(s.b).to(dev)
+    for _ in range(2):
+        g.vcycle(b)
+    torch.cuda.synchronize()
+    g.kernel_timing(True)
+    for _ in range(reps):
+        g.vcycle(b)
+    kt = g.kernel_timing(False)
+    g.close()
+    bv = vcycle_bytes(stats, fst, s.N, s.n_levels, "fp64")
+    pa_ms = kt["ms"] - kt["coop_ms"] - kt["flow_ms"]
+    pa_bytes = kt["bytes"] - kt["coop_bytes"] - kt["flow_bytes"]
+    pa_launch = kt["launches"] - kt["coop_launches"] - kt["flow_launches"]
+    pa_gbs = pa_bytes / (pa_ms * 1e-3) / 1e9 if pa_ms > 0 else 0.0
+    out = {"workload": "beam512 (as the headline), weighted additive CAV V(1,1), alpha 0.7, FP64 factors",
+           "vcycle_ms": round(kt["vcycle_ms"], 4), "vcycles_per_s": round(1e3 / kt["vcycle_ms"], 1),
+           "vcycle_bytes": int(bv), "vcycle_gbs": round(bv / (kt["vcycle_ms"] * 1e-3) / 1e9, 1),
+           "vcycle_frac": round(bv / (kt["vcycle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "k_patch_apply": {"bound": "hbm", "achieved": round(pa_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(pa_gbs / HBM_PEAK_GBS, 4),
+                             "traffic": measured_traffic("k_patch_apply", "fp64", "additive", "default"),
+                             "launches": pa_launch,
+                             "bytes_per_launch": int(pa_bytes / max(pa_launch, 1)),
+                             "avg_launch_us": round(1e3 * pa_ms / max(pa_launch, 1), 3)}}
+    if not membrane:
+        return out
+    # time-to-1e-10 where the additive cycle converges
+    sm = workloads.membrane_256(1e4)
+    bm = torch.from_numpy(sm.b).to(dev)
+    rows = {}
+    for smoother, alpha in (("additive", 0.7), ("multiplicative", 1.0)):
+        g = Solver(0)
+        g.setup(sm, precision="fp64", alpha=alpha, smoother=smoother)
+        g.fgmres_solve(bm, rtol=1e-10, max_it=150)     # warm-up
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.build_operator(sm)
+            g.build_cav_patches("cav")
+            g.factor_patches("fp64", 1e6)
+            g.set_smoother(smoother, alpha)
+            t1 = time.perf_counter()
+            _, inf = g.fgmres_solve(bm, rtol=1e-10, max_it=150)
+            torch.cuda.synchronize()
+            times.append((t1 - t0, time.perf_counter() - t1))
+        g.close()
+        ts = sorted(times, key=lambda v: v[0] + v[1])[1]
+        rows[smoother] = {"iterations": inf["iterations"], "converged": inf["converged"],
+                          "true_rel_residual": float("%.3g" % inf["true_rel_residual"]),
+                          "t_total_ms": round(1e3 * (ts[0] + ts[1]), 2), "t_solve_ms": round(1e3 * ts[1], 2)}
+    out["membrane256"] = dict(workload="membrane256: 256x256, ellipse 0.2/0.15, kappa_s=1e4, 6 levels, FP64",
+                              **rows)
+    return out
 
 
 def copy_calibration(nbytes: int):
@@ -184,6 +336,84 @@ def learned_leg(g_eval, b_eval, train_pairs: int, steps: int):
             "loss_last": round(float(np.mean(losses[-50:])), 4), "eval": "512^2 beam kappa_b=1e-2, rtol 1e-10",
             "plain_its": rows[0]["plain"], "learned_its": rows[0]["learned"], "accepted": rows[0]["accepted"],
             "enabled": enabled}
+
+
+def learned_c5_leg(dev, pairs_per_class: int = 10000, steps: int = 2000, eval_N: int = 1024):
+    """The learned stage at its configured scale: 20k (residual, error) pairs
+    from CAV V-cycles on 256^2 membrane (kappa_s = 1e4) and beam (kappa_b =
+    1e-2) systems (3 pairs per exact solution), minimal-residual training on
+    the GPU through each class's own K_E, then FGMRES to 1e-10 at eval_N^2
+    on a membrane and a beam system, plain CAV against CAV + stage (the plain
+    cycle judges every application and is the fallback). Reports iterations,
+    time and accepted / rejected applications per solve."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2608_14310_amd import Net, Solver
+    from paper_2608_14310_amd import learned as LN
+    classes = [("membrane", workloads.membrane_ellipse(256, None, 1e4, seed=1)),
+               ("beam", workloads.beam_fibres(256, workloads.levels_to(256, 8), 1e-2, 1e4, seed=1))]
+    t0 = time.perf_counter()
+    data = []
+    for ci, (name, st) in enumerate(classes):
+        g = Solver(0)
+        g.setup(st, precision="mixed", alpha=1.0, smoother="multiplicative")
+        count = (pairs_per_class + 2) // 3
+        rs, es = [], []
+        for k in range(0, count, 64):
+            xs = torch.from_numpy(workloads.random_solutions(st.N, min(64, count - k), 1000 * (ci + 1) + k // 64)).to(dev)
+            r, e = LN.generate_pairs(g, xs, 3, chunk=64)
+            rs.append(r)
+            es.append(e)
+        data.append((g, torch.cat(rs)[:pairs_per_class], torch.cat(es)[:pairs_per_class]))
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    net = Net(0, workloads.net_init(0, out_scale=1e-2))
+    t0 = time.perf_counter()
+    losses = []
+    orders = [workloads.batch_order(pairs_per_class, 8, steps // 2, ci) for ci in range(2)]
+    for k in range(steps // 2):
+        for ci in range(2):
+            g, rh, eh = data[ci]
+            losses.append(g.train_net_residual(net, rh, next(orders[ci]), 1e-3, "minres"))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    for g, rh, eh in data:
+        g.close()
+    del data
+    torch.cuda.empty_cache()
+    L = workloads.levels_to(eval_N, 8)
+    evals = []
+    for name, se in (("membrane", workloads.membrane_ellipse(eval_N, L, 1e4, seed=2)),
+                     ("beam", workloads.beam_fibres(eval_N, L, 1e-2, 1e4, seed=2))):
+        g = Solver(0)
+        g.setup(se, precision="mixed", alpha=1.0, smoother="multiplicative")
+        b = torch.from_numpy(se.b).to(dev)
+        g.attach_net(net, 1e-3)
+        row = {"system": f"{name} {eval_N}^2, {L} levels", "unknowns": se.n}
+        for mode in ("plain", "learned"):
+            g.fgmres_solve(b, 1e-10, 150, learned=mode == "learned")   # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, inf = g.fgmres_solve(b, 1e-10, 150, learned=mode == "learned")
+            torch.cuda.synchronize()
+            row[mode] = {"iterations": inf["iterations"], "converged": inf["converged"],
+                         "true_rel_residual": float("%.3g" % inf["true_rel_residual"]),
+                         "solve_ms": round(1e3 * (time.perf_counter() - t1), 1),
+                         "accepted": inf["learned_accepted"], "rejected": inf["learned_rejected"]}
+        g.attach_net(None)
+        g.close()
+        evals.append(row)
+    net.close()
+    return {"train": f"{2 * pairs_per_class} pairs (256^2 membrane kappa_s=1e4 and beam kappa_b=1e-2, 3 V-cycle "
+                     f"iterations per exact solution), {steps} Adam steps (batch 8, minimal-residual loss through "
+                     "each class's K_E)",
+            "pairs_s": round(t_pairs, 2), "train_s": round(t_train, 2),
+            "loss_first": round(float(np.mean(losses[:40])), 4), "loss_last": round(float(np.mean(losses[-100:])), 4),
+            "eval": evals,
+            "enabled": all(r["learned"]["converged"] and r["learned"]["iterations"] < r["plain"]["iterations"]
+                           for r in evals)}
 
 
 def two_grid_leg():
@@ -410,10 +640,16 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="systems in the batched leg (0: skip)")
     ap.add_argument("--learned-pairs", type=int, default=600, help="training pairs of the learned leg (0: skip)")
     ap.add_argument("--learned-steps", type=int, default=600)
+    ap.add_argument("--learned-c5", action="store_true",
+                    help="the learned stage at its configured scale (20k pairs at 256^2, evaluated at 1024^2); "
+                         "not part of the default run")
     ap.add_argument("--multi-rhs", type=int, default=64,
                     help="right-hand sides of the multi-RHS V-cycle leg, blocks of 16 (0: skip)")
-    ap.add_argument("--fibre-grids", type=int, nargs="*", default=[32, 64, 128, 256],
-                    help="grids of the flexible-fibre leg (Table 3); none: skip")
+    ap.add_argument("--fibre-grids", type=int, nargs="*", default=[],
+                    help="grids of the flexible-fibre context leg (Table 3, e.g. 32 64 128 256; default: skip)")
+    ap.add_argument("--no-additive", action="store_true", help="skip the weighted additive smoother leg")
+    ap.add_argument("--additive-only", action="store_true",
+                    help="run only the additive V-cycles on the 512^2 beam (for profiling k_patch_apply), then exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, help="run only a plain copy of this many bytes")
@@ -429,6 +665,10 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
+    if a.additive_only:
+        import torch
+        print(json.dumps(additive_leg(torch.device("cuda", 0), membrane=False)))
+        return
 
     import numpy as np
     import torch
@@ -497,13 +737,19 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / a.steps
 
-    # the dominant explicit-patch kernel: the shared-residual form when its
-    # brackets hold most of the time, else the other cooperative forms, else
-    # the one-workgroup form
+    # the dominant explicit-patch kernel: the dataflow sweep when its brackets
+    # hold most of the time, else the shared-residual form, else the other
+    # cooperative forms, else the one-workgroup form
     co_ms = sum(r["kt"]["coop_ms"] for r in runs)
     sh_ms = sum(r["kt"]["shared_ms"] for r in runs)
+    fl_ms = sum(r["kt"]["flow_ms"] for r in runs)
     all_ms = sum(r["kt"]["ms"] for r in runs)
-    if sh_ms > all_ms - sh_ms:
+    if fl_ms > all_ms - fl_ms:
+        kernel = "k_mult_flow"
+        kb_bytes = sum(r["kt"]["flow_bytes"] for r in runs)
+        kb_ms = fl_ms
+        kb_launch = sum(r["kt"]["flow_launches"] for r in runs)
+    elif sh_ms > all_ms - sh_ms:
         kernel = "k_mult_coopr"
         kb_bytes = sum(r["kt"]["shared_bytes"] for r in runs)
         kb_ms = sh_ms
@@ -515,11 +761,12 @@ def main():
         kb_launch = sum(r["kt"]["coop_launches"] - r["kt"]["shared_launches"] for r in runs)
     else:
         kernel = "k_mult_exp" if a.smoother == "multiplicative" else "k_patch_apply"
-        kb_bytes = sum(r["kt"]["bytes"] - r["kt"]["coop_bytes"] for r in runs)
-        kb_ms = all_ms - co_ms
-        kb_launch = sum(r["kt"]["launches"] - r["kt"]["coop_launches"] for r in runs)
+        kb_bytes = sum(r["kt"]["bytes"] - r["kt"]["coop_bytes"] - r["kt"]["flow_bytes"] for r in runs)
+        kb_ms = all_ms - co_ms - fl_ms
+        kb_launch = sum(r["kt"]["launches"] - r["kt"]["coop_launches"] - r["kt"]["flow_launches"] for r in runs)
     achieved = kb_bytes / (kb_ms * 1e-3) / 1e9 if kb_ms > 0 else 0.0
     last = runs[-1]
+    bv = vcycle_bytes(last["stats"], last["fst"], s.N, s.n_levels, a.precision)
     solve_ms = [1e3 * r["solve"] for r in runs]
     line = {
         "metric": "FGMRES(CAV-MG) time-to-1e-10 rel. residual at 512^2; V-cycle HBM GB/s",
@@ -543,6 +790,8 @@ def main():
                      if k not in ("stats", "fst", "kt")},
         "vcycle_ms": round(last["kt"]["vcycle_ms"], 4),
         "vcycles_per_s": round(1e3 / last["kt"]["vcycle_ms"], 1) if last["kt"]["vcycle_ms"] else None,
+        "vcycle_bytes": int(bv),
+        "vcycle_gbs": round(bv / (last["kt"]["vcycle_ms"] * 1e-3) / 1e9, 1) if last["kt"]["vcycle_ms"] else None,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(kernel, a.precision, a.smoother, a.tune),
@@ -596,6 +845,29 @@ def main():
     if a.fibre_grids:
         line["fibre"] = fibre_leg(a.fibre_grids)
         line["fibre_robustness"] = fibre_robustness_leg()
+    gpu_full = {}
+    if not a.no_additive:
+        line["additive"] = additive_leg(dev)
+        gpu_full["membrane256"] = line["additive"]["membrane256"]["additive"]
+    # the 32^2 target system (additive cycle), for the CPU comparison
+    st32 = workloads.small_target(0)
+    g32 = Solver(0)
+    g32.setup(st32, precision="fp64", alpha=0.7, smoother="additive")
+    b32 = torch.from_numpy(st32.b).to(dev)
+    g32.fgmres_solve(b32, rtol=1e-10, max_it=150)
+    torch.cuda.synchronize()
+    t0c = time.perf_counter()
+    g32.build_operator(st32)
+    g32.build_cav_patches("cav")
+    g32.factor_patches("fp64", 1e6)
+    g32.set_smoother("additive", 0.7)
+    t1c = time.perf_counter()
+    _, inf32 = g32.fgmres_solve(b32, rtol=1e-10, max_it=150)
+    torch.cuda.synchronize()
+    t2c = time.perf_counter()
+    g32.close()
+    gpu_full["target32"] = {"iterations": inf32["iterations"], "t_total_ms": round(1e3 * (t2c - t0c), 2),
+                            "t_solve_ms": round(1e3 * (t2c - t1c), 2)}
     sweep = []
     for kb in a.stiff_sweep:
         sk = workloads.beam_512(kb)
@@ -613,6 +885,8 @@ def main():
     if a.learned_pairs > 0:
         setup("mixed")
         line["learned"] = learned_leg(g, b, a.learned_pairs, a.learned_steps)
+    if a.learned_c5:
+        line["learned_c5"] = learned_c5_leg(dev)
     if not a.no_two_grid:
         line["two_grid_table1"] = two_grid_leg()
         line["box_comparison"] = box_comparison_leg()
@@ -623,7 +897,7 @@ def main():
     if a.batch > 0:
         line["batched"] = batched_leg(a.batch, 150)
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(a.kappa_b, last["its"], a.smoother, alpha)
+        line["cpu_baseline"] = cpu_baseline(a.kappa_b, last["its"], a.smoother, gpu_full)
     print(json.dumps(line))
 
 

@@ -18,7 +18,8 @@
  * Ownership: the caller owns every pointer argument; host descriptors are
  * copied during the call; device vectors must stay valid until the work on
  * the stream has finished. The context owns all hierarchy, patch and factor
- * memory and frees it in cav_destroy.
+ * memory (from the caller's allocator when cav_create was given one) and
+ * releases it in cav_destroy.
  * Errors: functions return a cav_status; nothing throws across the ABI.
  * cav_last_error(ctx) gives a message for the most recent failure.
  */
@@ -145,11 +146,44 @@ typedef struct {
 } cav_solve_info;
 
 /* ---- lifecycle ---- */
-cav_status cav_create(cav_ctx* out, int device, void* hip_stream);
+/* Device memory source of a context or net. alloc(bytes, stream, user) returns
+ * a device block of at least `bytes` bytes on the object's device, usable by
+ * work enqueued on `stream` (the object's current stream) from then on, or
+ * NULL (the call that needed it then fails with CAV_ERR_OUT_OF_MEMORY).
+ * free(ptr, stream, user) returns a block the object no longer needs: work
+ * already enqueued on `stream` may still use it (the library first orders its
+ * own side streams before `stream`), so the allocator may hand it out again
+ * only to work ordered after that work, as a stream-ordered caching allocator
+ * (PyTorch's, for one) does. Both are called from the thread that called into
+ * the library, never from a device callback. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, void* stream, void* user);
+  void* user;
+} cav_allocator;
+/* Creates a context on `device` that enqueues its work on `hip_stream`. With
+ * `allocator` (copied; its functions must stay valid until cav_destroy) all of
+ * the context's device memory (operator, hierarchy, patch tables, factors,
+ * Krylov and smoother workspaces) comes from it and is returned to it; NULL
+ * makes the context call hipMalloc itself. CAV_ERR_INVALID_ARG for a bad device or an
+ * allocator without both functions. Either way, blocks the context releases
+ * stay with it (up to 8 GiB) for later requests of the same size and go back
+ * to their source in cav_destroy or when an allocation fails. */
+cav_status cav_create(cav_ctx* out, int device, void* hip_stream, const cav_allocator* allocator);
 cav_status cav_destroy(cav_ctx ctx);
 cav_status cav_set_stream(cav_ctx ctx, void* hip_stream);
 const char* cav_status_string(cav_status s);
 const char* cav_last_error(cav_ctx ctx);
+/* Device memory held by a context: blocks handed out and not yet released
+ * (live), released blocks kept for reuse (cached), and the numbers of
+ * hipMalloc calls the context made itself and
+ * of calls to the caller's allocator (0 and 0 respectively when there is
+ * none). Host only; does not synchronise. */
+typedef struct {
+  int64_t live_bytes, live_blocks, cached_bytes;
+  int64_t hip_malloc_calls, allocator_allocs, allocator_frees;
+} cav_memory_info;
+cav_status cav_memory_stats(cav_ctx ctx, cav_memory_info* out);
 
 /* ---- setup (Section 2, Section 3, Section 4) ----
  * cav_build_operator: assembles J (4-point kernel, fixed 4x4 face box per
@@ -279,6 +313,11 @@ typedef struct {
   int32_t converged;
   int32_t fgmres_its_total, fgmres_its_max;
   double res0, res;        /* ||R|| at the initial and the final iterate */
+  int32_t lin_unconverged; /* Newton systems whose FGMRES stopped at lin_max_it (their
+                              corrections are still applied: inexact Newton) */
+  int32_t failed_stage;    /* 0: none; on an error status, the stage that failed:
+                              1 operator build, 2 patches, 3 factorisation, 4 FGMRES,
+                              5 residual or force evaluation */
 } cav_newton_info;
 
 /* One backward-Euler step of the IB scheme of Section 2 with the fibre law
@@ -295,9 +334,14 @@ typedef struct {
  * configuration is the one it was built at) and solves K_E dx = -R with
  * CAV-preconditioned FGMRES (lin_rtol) from zero. X_new: optional host 2M, X^{n+1} at the
  * solution. The context keeps the hierarchy of the last Newton system.
- * CAV_WARN_NOT_CONVERGED if max_newton corrections do not meet the tolerance;
- * a linear solve's error status is returned as is. After any status x holds
- * the last iterate. */
+ * A Newton system whose FGMRES reaches lin_max_it without meeting lin_rtol
+ * still yields its correction (the best of its Krylov space: inexact Newton)
+ * and is counted in info->lin_unconverged. CAV_WARN_NOT_CONVERGED only if
+ * max_newton corrections do not meet the Newton tolerance; an error status of
+ * a stage (build, patches, factorisation, FGMRES, residual) is returned as is
+ * with info->failed_stage naming the stage. After any status x holds the last
+ * iterate, info the counts and residuals reached so far, and X_new (when the
+ * step got as far as a residual evaluation) the configuration of that iterate. */
 cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_structure_desc* st, const double* rhs,
                             double* x, double* X_new, const cav_newton_opts* opts, cav_newton_info* info);
 
@@ -343,14 +387,24 @@ cav_status cav_batch_solve(cav_ctx* ctxs, int32_t n_sys, const double* const* b,
  * exchanged through device-coherent stores and loads after the barrier
  * (inside a captured graph the one-workgroup form runs instead of any
  * cooperative form). Alternatively the whole sweep of a level runs in one
- * cooperative launch with a bounded grid barrier after each phase.
+ * cooperative launch with a bounded grid barrier after each phase, or every
+ * explicit phase of a sweep runs in one dataflow launch:
+ * workgroups claim the 64-row items of the shared-residual form in phase
+ * order from a ticket counter, and an item of patch p starts once every
+ * patch of an earlier colour that conflicts with p (shares an unknown or a
+ * K_E coupling) has finished the sweep, signalled through per-patch done
+ * counters with device-scope release and acquire; non-conflicting patches
+ * commute, so the sweep equals the per-phase form bit for bit (inside a
+ * captured graph the per-phase forms run instead).
  * cav_autotune times the choices on the context's own phases, per smoothed
  * level and per size bucket of a phase's largest patch (<= 64, <= 128,
  * <= 256, larger), `reps` repetitions each, keeps the fastest, and writes the
  * table (5 ints per level, levels 0 .. n_levels-1, level 0 unused: 4 bucket
- * entries, then 1 for the one-launch sweep, which the autotuner leaves at 0:
- * a process's first cooperative launch slows later concurrent graph
- * launches, and the sweep never won) to `table` (optional). Results do
+ * entries, then the sweep entry: 0 a launch per phase with the bucket
+ * entries, 1 the one-launch sweep, 2 the dataflow sweep; the autotuner times
+ * 0 against 2 per level and never picks 1: a process's first cooperative
+ * launch slows later concurrent graph launches, and that sweep never won) to
+ * `table` (optional). Results do
  * not depend on the choice (every patch's and cell's arithmetic is the same).
  * Uses the levels' scratch vectors; synchronises. A barrier wait that times
  * out (cooperative phase form or one-launch sweep) leaves x unwritten from
@@ -427,6 +481,9 @@ typedef struct {
   int64_t shared_launches; /* of those: the shared-residual form (entry 3) */
   double shared_ms;
   double shared_bytes;
+  int64_t flow_launches;   /* dataflow sweeps (one launch per level sweep); not in coop_* */
+  double flow_ms;
+  double flow_bytes;       /* the algorithmic bytes of every phase of those sweeps */
 } cav_kernel_timing_info;
 cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* out);
 
@@ -446,7 +503,8 @@ cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* ou
  * not thread safe; it may be attached to several contexts on its device. */
 #define CAV_NET_WEIGHTS 10944
 typedef struct cav_net_s* cav_net;
-cav_status cav_net_create(cav_net* out, int device, void* hip_stream); /* weights zero */
+/* weights zero; `allocator` as for cav_create (NULL: hipMalloc) */
+cav_status cav_net_create(cav_net* out, int device, void* hip_stream, const cav_allocator* allocator);
 cav_status cav_net_destroy(cav_net net);
 cav_status cav_net_set_stream(cav_net net, void* hip_stream);
 const char* cav_net_last_error(cav_net net);

@@ -7,8 +7,10 @@ into exceptions (warnings are returned in the solve summary).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -57,7 +59,8 @@ class NewtonOpts(C.Structure):
 
 class NewtonInfo(C.Structure):
     _fields_ = [("newton_its", C.c_int32), ("converged", C.c_int32), ("fgmres_its_total", C.c_int32),
-                ("fgmres_its_max", C.c_int32), ("res0", C.c_double), ("res", C.c_double)]
+                ("fgmres_its_max", C.c_int32), ("res0", C.c_double), ("res", C.c_double),
+                ("lin_unconverged", C.c_int32), ("failed_stage", C.c_int32)]
 
 
 class LevelStats(C.Structure):
@@ -90,10 +93,61 @@ class KernelTiming(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double), ("vcycles", C.c_int64),
                 ("vcycle_ms", C.c_double), ("coop_launches", C.c_int64), ("coop_ms", C.c_double),
                 ("coop_bytes", C.c_double), ("shared_launches", C.c_int64), ("shared_ms", C.c_double),
-                ("shared_bytes", C.c_double)]
+                ("shared_bytes", C.c_double), ("flow_launches", C.c_int64), ("flow_ms", C.c_double),
+                ("flow_bytes", C.c_double)]
 
 
 _P = C.c_void_p
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
+class MemoryInfo(C.Structure):
+    _fields_ = [("live_bytes", C.c_int64), ("live_blocks", C.c_int64), ("cached_bytes", C.c_int64),
+                ("hip_malloc_calls", C.c_int64), ("allocator_allocs", C.c_int64), ("allocator_frees", C.c_int64)]
+
+
+class TorchAllocator:
+    """cav_allocator backed by PyTorch's caching allocator on one device: the
+    library's device memory is torch memory, allocated and released on the
+    stream the library passes (stream-ordered reuse). Counts its calls."""
+
+    def __init__(self, device: int):
+        import torch
+        self._torch = torch
+        self.device = int(device)
+        self.allocs = 0
+        self.frees = 0
+        self.live_bytes = 0
+        self._sizes = {}
+
+        def _alloc(nbytes, stream, user):
+            try:
+                p = int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0)))
+            except Exception:
+                return None
+            self.allocs += 1
+            self.live_bytes += int(nbytes)
+            self._sizes[p] = int(nbytes)
+            return p
+
+        def _free(ptr, stream, user):
+            try:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:
+                return
+            self.frees += 1
+            self.live_bytes -= self._sizes.pop(int(ptr), 0)
+
+        # keep the callbacks alive as long as this object
+        self._cfn = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+        self.struct = Allocator(self._cfn[0], self._cfn[1], None)
+
+
 _SIGS = {
     "cav_kernel_timing": ([_P, C.c_int, C.POINTER(KernelTiming)], C.c_int),
     "cav_analyze": ([C.POINTER(GridDesc), C.POINTER(StructureDesc), C.c_int, C.POINTER(_P)], C.c_int),
@@ -108,7 +162,8 @@ _SIGS = {
                                      C.POINTER(C.c_int32)], C.c_int),
     "cav_export_phases": ([_P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                            C.POINTER(C.c_int32)], C.c_int),
-    "cav_create": ([C.POINTER(_P), C.c_int, _P], C.c_int),
+    "cav_create": ([C.POINTER(_P), C.c_int, _P, C.POINTER(Allocator)], C.c_int),
+    "cav_memory_stats": ([_P, C.POINTER(MemoryInfo)], C.c_int),
     "cav_destroy": ([_P], C.c_int),
     "cav_set_stream": ([_P, _P], C.c_int),
     "cav_status_string": ([C.c_int], C.c_char_p),
@@ -127,7 +182,7 @@ _SIGS = {
     "cav_export_patches": ([_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int),
     "cav_export_ee": ([_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                        C.POINTER(C.c_int64)], C.c_int),
-    "cav_net_create": ([C.POINTER(_P), C.c_int, _P], C.c_int),
+    "cav_net_create": ([C.POINTER(_P), C.c_int, _P, C.POINTER(Allocator)], C.c_int),
     "cav_net_destroy": ([_P], C.c_int),
     "cav_net_set_stream": ([_P, _P], C.c_int),
     "cav_net_last_error": ([_P], C.c_char_p),
@@ -305,6 +360,20 @@ class Analysis:
         return dofs, inv
 
 
+# Contexts and nets still open at interpreter exit are closed by an atexit
+# hook, while torch (their allocator) is still intact.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for o in list(_LIVE):
+        try:
+            o.close()
+        except Exception:
+            pass
+
+
 def _dev_ptr(t, dtype=None):
     import torch
     dtype = torch.float64 if dtype is None else dtype
@@ -317,16 +386,19 @@ class Net:
     """Learned correction net (3x3 periodic convs 3 -> 32 -> 32 -> 3) on one device:
     forward, FP64 correction, Adam training steps; weights live on the device."""
 
-    def __init__(self, device: int = 0, weights: Optional[np.ndarray] = None):
+    def __init__(self, device: int = 0, weights: Optional[np.ndarray] = None, allocator="torch"):
         import torch
         self._torch = torch
         self.device = torch.device("cuda", device)
         self._L = lib()
+        self.allocator = TorchAllocator(device) if allocator == "torch" else allocator
         h = C.c_void_p()
-        st = self._L.cav_net_create(C.byref(h), int(device), self._stream())
+        st = self._L.cav_net_create(C.byref(h), int(device), self._stream(),
+                                    C.byref(self.allocator.struct) if self.allocator is not None else None)
         if st != 0:
             raise CAVError(st, "cav_net_create failed")
         self._h = h
+        _LIVE.add(self)
         if weights is not None:
             self.set_weights(weights)
 
@@ -402,16 +474,22 @@ class Net:
 class Solver:
     """One solver context on one device; all work runs on the current torch stream."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, allocator="torch"):
+        """allocator: "torch" (default: the context's device memory comes from
+        PyTorch's caching allocator), None (the library calls hipMalloc), or an
+        object with a `struct` field holding a filled Allocator."""
         import torch
         self._torch = torch
         self.device = torch.device("cuda", device)
         self._L = lib()
+        self.allocator = TorchAllocator(device) if allocator == "torch" else allocator
         h = C.c_void_p()
-        st = self._L.cav_create(C.byref(h), int(device), self._stream())
+        st = self._L.cav_create(C.byref(h), int(device), self._stream(),
+                                C.byref(self.allocator.struct) if self.allocator is not None else None)
         if st != 0:
             raise CAVError(st, "cav_create failed (no ROCm device?)")
         self._h = h
+        _LIVE.add(self)
         self.N = None
         self.n_levels = None
 
@@ -425,6 +503,11 @@ class Solver:
 
     def _sync_stream(self):
         self._L.cav_set_stream(self._h, self._stream())
+
+    def memory_stats(self) -> Dict:
+        m = MemoryInfo()
+        self._check(self._L.cav_memory_stats(self._h, C.byref(m)))
+        return {f: getattr(m, f) for f, _ in MemoryInfo._fields_}
 
     def close(self):
         if getattr(self, "_h", None):

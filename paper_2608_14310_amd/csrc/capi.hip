@@ -18,6 +18,10 @@ struct cav_ctx_s {
   std::unordered_multimap<size_t, std::pair<void*, uint64_t>> cache;
   size_t cached_bytes = 0;
   uint64_t epoch = 1;                      // advanced by every device-wide synchronisation
+  // the caller's allocator (cav_create); without it the context calls hipMalloc
+  cav_allocator ua{};
+  bool has_ua = false;
+  int64_t n_hip_malloc = 0, n_ua_alloc = 0, n_ua_free = 0;
 };
 
 namespace cav {
@@ -59,17 +63,39 @@ static double* noalloc_scratch(int device) {
   return g_scratch_ptr[device];
 }
 
-// Device memory of a context. Released blocks stay with the context (up to
-// DEV_CACHE_CAP bytes) and are handed out again for a request of the same
-// rounded size, so rebuilding a hierarchy of the same shape allocates
-// nothing. A block released after the last device-wide synchronisation
+// Device memory of a context, from hipMalloc or from the caller's allocator.
+// Released blocks stay with the context (up to DEV_CACHE_CAP bytes) and are
+// handed out again for a request of the same rounded size, so rebuilding a
+// hierarchy of the same shape allocates nothing; they go back to their source
+// when the context is destroyed or an allocation fails. A block released after the last device-wide synchronisation
 // (device_sync_epoch) may still be used by queued work on some stream, so only
 // blocks released before it are handed out; the setup calls synchronise once
 // after releasing the previous hierarchy's memory.
 constexpr size_t DEV_CACHE_CAP = size_t(8) << 30;
 
+// Orders the work queued on the context's side streams before later work on
+// its main stream (before a block goes back to a stream-ordered allocator).
+static void join_side_streams(Ctx& c) {
+  if (!c.side) return;
+  CAV_HIP(hipEventRecord(c.ev_js[0], c.side));
+  CAV_HIP(hipStreamWaitEvent(c.stream, c.ev_js[0], 0));
+  CAV_HIP(hipEventRecord(c.ev_js[1], c.fstream));
+  CAV_HIP(hipStreamWaitEvent(c.stream, c.ev_js[1], 0));
+}
+
+static void ua_release(cav_ctx_s* o, void* p) {
+  o->ua.free(p, static_cast<void*>(o->c.stream), o->ua.user);
+  ++o->n_ua_free;
+}
+
+// Gives every cached block back to its source (hipFree or the caller's allocator).
 static void release_cache(cav_ctx_s* o) {
-  for (auto& kv : o->cache) (void)hipFree(kv.second.first);
+  if (o->has_ua && !o->cache.empty()) {
+    (void)hipDeviceSynchronize();
+    for (auto& kv : o->cache) ua_release(o, kv.second.first);
+  } else {
+    for (auto& kv : o->cache) (void)hipFree(kv.second.first);
+  }
   o->cache.clear();
   o->cached_bytes = 0;
 }
@@ -89,11 +115,25 @@ void* dev_alloc(Ctx& c, size_t bytes) {
       }
   }
   void* p = nullptr;
+  if (o->has_ua) {
+    p = o->ua.alloc(sz, static_cast<void*>(c.stream), o->ua.user);
+    if (!p && !o->cache.empty()) {
+      release_cache(o);
+      p = o->ua.alloc(sz, static_cast<void*>(c.stream), o->ua.user);
+    }
+    if (!p) throw StatusError(CAV_ERR_OUT_OF_MEMORY, "the caller's allocator returned no block of " +
+                                                         std::to_string(sz) + " bytes");
+    ++o->n_ua_alloc;
+    o->live.emplace(p, sz);
+    return p;
+  }
   hipError_t e = hipMalloc(&p, sz);
+  ++o->n_hip_malloc;
   if (e != hipSuccess && !o->cache.empty()) {
     (void)hipGetLastError();
     release_cache(o);
     e = hipMalloc(&p, sz);
+    ++o->n_hip_malloc;
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -108,7 +148,7 @@ void ensure_aux_streams(Ctx& c) {
   if (c.side) return;
   CAV_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
   CAV_HIP(hipStreamCreateWithFlags(&c.fstream, hipStreamNonBlocking));
-  for (hipEvent_t* e : {&c.ev_fork, &c.ev_join, &c.ev_fup, &c.ev_fdone, &c.ev_fdone2})
+  for (hipEvent_t* e : {&c.ev_fork, &c.ev_join, &c.ev_fup, &c.ev_fdone, &c.ev_fdone2, &c.ev_js[0], &c.ev_js[1]})
     CAV_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
 }
 
@@ -150,6 +190,9 @@ void dev_free(Ctx& c, void* p) {
   if (o->cached_bytes + sz <= DEV_CACHE_CAP) {
     o->cache.emplace(sz, std::make_pair(p, o->epoch));
     o->cached_bytes += sz;
+  } else if (o->has_ua) {
+    join_side_streams(c);
+    ua_release(o, p);
   } else {
     (void)hipFree(p);
   }
@@ -281,10 +324,13 @@ void free_patches(Ctx& c, Level& L) {
                    (void**)&L.d_rec64, (void**)&L.d_rec32, (void**)&L.d_f64, (void**)&L.d_f32,
                    (void**)&L.d_mrec, (void**)&L.d_wrk, (void**)&L.d_ph_ptr, (void**)&L.d_slot_mask,
                    (void**)&L.d_citem[0], (void**)&L.d_citem[1], (void**)&L.d_pcnt,
-                   (void**)&L.d_slot_q, (void**)&L.d_irow}) {
+                   (void**)&L.d_slot_q, (void**)&L.d_irow, (void**)&L.d_pr_ptr, (void**)&L.d_pr,
+                   (void**)&L.d_flow}) {
     dev_free(c, *p);
     *p = nullptr;
   }
+  L.flow_base = L.flow_sweep = 0;
+  L.flow_items = 0;
   L.rec64_h.clear();
   L.rec32_h.clear();
   L.has_patches = false;
@@ -406,6 +452,7 @@ void check_sweep_flags(Ctx& c) {
   CAV_HIP(hipStreamSynchronize(c.stream));
   if (f[1] != 0) {
     launch_clear_sweep_flags(c, c.stream);
+    reset_sweep_counters(c, c.stream);
     throw StatusError(CAV_ERR_HIP, "a smoother sweep timed out at a workgroup barrier; results are invalid");
   }
 }
@@ -647,6 +694,7 @@ void learned_stage(Ctx& c, const double* v, double* z, int nbk) {
   launch_axpy_dev(z, c.d_sc + 3, cc, n, s);
 }
 
+
 // Workspace of one FGMRES solve: the Krylov bases V ((m + 1) n doubles) and
 // Z (m n), the operator output w and the projected right-hand side bb (n
 // each), the device Hessenberg column h (3 (m + 2)), the dot-product partials
@@ -748,7 +796,10 @@ cav_status fgmres_core(Ctx& c, const double* b, double* x, const cav_fgmres_opts
     k = j + 1;
     est = std::fabs(g[j + 1]) / beta;
     if (opts && opts->history) opts->history[j] = est;
-    if (!std::isfinite(est)) throw StatusError(CAV_ERR_INVALID_ARG, "non-finite value in FGMRES (check inputs)");
+    if (!std::isfinite(est)) {
+      check_sweep_flags(c);   // a smoother wait that gave up is the better report
+      throw StatusError(CAV_ERR_INVALID_ARG, "non-finite value in FGMRES (check inputs)");
+    }
     if (est <= rtol) { conv = true; break; }
     if (hn == 0.0) { conv = true; break; }
     k_axpby<<<nblocks(n), TPB, 0, s>>>(V + int64_t(j + 1) * n, 1.0 / hn, w, 0.0, n);
@@ -825,8 +876,9 @@ const char* cav_status_string(cav_status s) {
 
 const char* cav_last_error(cav_ctx ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
 
-cav_status cav_create(cav_ctx* out, int device, void* stream) {
+cav_status cav_create(cav_ctx* out, int device, void* stream, const cav_allocator* allocator) {
   if (!out) return CAV_ERR_INVALID_ARG;
+  if (allocator && (!allocator->alloc || !allocator->free)) return CAV_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CAV_ERR_INVALID_ARG;
   if (hipSetDevice(device) != hipSuccess) return CAV_ERR_HIP;
@@ -835,7 +887,24 @@ cav_status cav_create(cav_ctx* out, int device, void* stream) {
   if (!ctx) return CAV_ERR_OUT_OF_MEMORY;
   ctx->c.device = device;
   ctx->c.stream = static_cast<hipStream_t>(stream);
+  if (allocator) {
+    ctx->ua = *allocator;
+    ctx->has_ua = true;
+  }
   *out = ctx;
+  return CAV_OK;
+}
+
+cav_status cav_memory_stats(cav_ctx ctx, cav_memory_info* out) {
+  if (!ctx || !out) return CAV_ERR_INVALID_ARG;
+  cav_memory_info m{};
+  for (auto& kv : ctx->live) m.live_bytes += int64_t(kv.second);
+  m.live_blocks = int64_t(ctx->live.size());
+  m.cached_bytes = int64_t(ctx->cached_bytes);
+  m.hip_malloc_calls = ctx->n_hip_malloc;
+  m.allocator_allocs = ctx->n_ua_alloc;
+  m.allocator_frees = ctx->n_ua_free;
+  *out = m;
   return CAV_OK;
 }
 
@@ -860,9 +929,15 @@ cav_status cav_destroy(cav_ctx ctx) {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);
     }
-  for (hipEvent_t e : {ctx->c.ev_fork, ctx->c.ev_join, ctx->c.ev_fup, ctx->c.ev_fdone, ctx->c.ev_fdone2})
+  for (hipEvent_t e : {ctx->c.ev_fork, ctx->c.ev_join, ctx->c.ev_fup, ctx->c.ev_fdone, ctx->c.ev_fdone2,
+                       ctx->c.ev_js[0], ctx->c.ev_js[1]})
     if (e) (void)hipEventDestroy(e);
-  for (auto& kv : ctx->live) (void)hipFree(kv.first);
+  // every stream has finished: the blocks go back to whoever gave them
+  if (ctx->has_ua) {
+    for (auto& kv : ctx->live) ua_release(ctx, kv.first);
+  } else {
+    for (auto& kv : ctx->live) (void)hipFree(kv.first);
+  }
   release_cache(ctx);
   if (ctx->c.h_pinned) (void)hipHostFree(ctx->c.h_pinned);
   for (hipEvent_t e : ctx->c.ev_pool) (void)hipEventDestroy(e);
@@ -1298,7 +1373,7 @@ cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* ou
       out->launches += m.launches;
       out->ms += ms;
       out->bytes += m.bytes;
-      if (m.coop) {
+      if (m.coop == 1 || m.coop == 2) {
         out->coop_launches += m.launches;
         out->coop_ms += ms;
         out->coop_bytes += m.bytes;
@@ -1307,6 +1382,11 @@ cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* ou
         out->shared_launches += m.launches;
         out->shared_ms += ms;
         out->shared_bytes += m.bytes;
+      }
+      if (m.coop == 3) {
+        out->flow_launches += m.launches;
+        out->flow_ms += ms;
+        out->flow_bytes += m.bytes;
       }
     }
     for (auto& m : c.vc_marks) {
@@ -1428,9 +1508,7 @@ cav_status cav_net_train_step_residual(cav_net net, cav_ctx ctx, int32_t kind, i
   const int nbk = dots_blocks(n3);
   if (n.rl_n != n3) {
     if (n.d_rl) {
-      auto it = std::find(n.allocs.begin(), n.allocs.end(), (void*)n.d_rl);
-      if (it != n.allocs.end()) n.allocs.erase(it);
-      CAV_HIP(hipFree(n.d_rl));
+      net_dev_free(n, n.d_rl);
       n.d_rl = nullptr;
     }
     n.d_rl = static_cast<double*>(net_dev_alloc(n, size_t(4 * n3 + nbk) * sizeof(double)));
@@ -1705,7 +1783,23 @@ cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table) {
     // beat per-phase launches here, and a process's first cooperative launch
     // halves the concurrency of later graph launches on other streams. It
     // stays available through cav_set_tuning.
-    L.persistent = false;
+    L.sweep_mode = 0;
+    // the dataflow sweep against the per-phase launches just chosen: the
+    // whole explicit part of a sweep, `reps` times each
+    if (L.flow_items > 0) {
+      float t_mode[2] = {0.f, 0.f};
+      for (int mode : {0, 2}) {
+        L.sweep_mode = mode;
+        launch_mult_smoother(c, L, L.d_b, L.d_x, false, s);   // warm-up
+        CAV_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch_mult_smoother(c, L, L.d_b, L.d_x, false, s);
+        CAV_HIP(hipEventRecord(e1, s));
+        CAV_HIP(hipEventSynchronize(e1));
+        CAV_HIP(hipGetLastError());
+        CAV_HIP(hipEventElapsedTime(&t_mode[mode / 2], e0, e1));
+      }
+      L.sweep_mode = t_mode[1] < t_mode[0] ? 2 : 0;
+    }
   }
   check_sweep_flags(c);
   c.timing = timing;
@@ -1713,7 +1807,7 @@ cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table) {
   if (table)
     for (int l = 0; l < c.n_levels; ++l) {
       for (int bk = 0; bk < 4; ++bk) table[5 * l + bk] = c.lv[l].mx_nt[bk];
-      table[5 * l + 4] = c.lv[l].persistent ? 1 : 0;
+      table[5 * l + 4] = c.lv[l].sweep_mode;
     }
   return CAV_OK;
   API_END
@@ -1731,11 +1825,12 @@ cav_status cav_set_tuning(cav_ctx ctx, const int32_t* table) {
               "bucket entries must be 256, 512, 1024, 0 (split form), 1/2 (cooperative form, 64/128 rows) or 3 "
               "(cooperative form with a shared residual)");
     }
-    require(table[5 * l + 4] == 0 || table[5 * l + 4] == 1, CAV_ERR_INVALID_ARG, "the sweep entry must be 0 or 1");
+    require(table[5 * l + 4] >= 0 && table[5 * l + 4] <= 2, CAV_ERR_INVALID_ARG,
+            "the sweep entry must be 0 (a launch per phase), 1 (one-launch sweep) or 2 (dataflow sweep)");
   }
   for (int l = 0; l < c.n_levels; ++l) {
     for (int bk = 0; bk < 4; ++bk) c.lv[l].mx_nt[bk] = table[5 * l + bk];
-    c.lv[l].persistent = table[5 * l + 4] != 0;
+    c.lv[l].sweep_mode = table[5 * l + 4];
   }
   ++c.generation;
   return CAV_OK;
@@ -1871,6 +1966,15 @@ cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_struc
     for (void* p : bufs) dev_free(c, p);
     bufs.clear();
   };
+  cav_newton_info inf{};
+  std::vector<double> Xk;
+  bool have_X = false;
+  // every exit reports what was reached: counts, residuals, the last configuration
+  auto report = [&]() {
+    if (info) *info = inf;
+    if (X_new && have_X) std::copy(Xk.begin(), Xk.end(), X_new);
+  };
+  int stage = 0;
   try {
     require(g && st && o && rhs && x && rhs != x, CAV_ERR_INVALID_ARG,
             "grid, structure, options, rhs and x are required (rhs and x distinct)");
@@ -1881,6 +1985,7 @@ cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_struc
     auto call = [&](cav_status s) {
       if (s != CAV_OK) throw StatusError(s, c.err);
     };
+    stage = 1;
     cav_structure_desc d = *st;
     d.X_force = nullptr;
     // J^n, S^n and the Stokes stencil at X^n (the operator itself is rebuilt per correction)
@@ -1900,22 +2005,24 @@ cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_struc
     const int nblk = dots_blocks(n);
     double* dpart = static_cast<double*>(alloc(size_t(nblk) * sizeof(double)));
     double* dnrm = static_cast<double*>(alloc(sizeof(double)));
-    std::vector<double> Xk(2 * size_t(M)), U(2 * size_t(M)), Fh;
+    Xk.assign(2 * size_t(M), 0.0);
+    std::vector<double> U(2 * size_t(M)), Fh;
     const std::vector<double> Xn(st->X, st->X + 2 * size_t(M));
     std::vector<double> built = Xn;  // configuration of the operator the context holds
-    cav_newton_info inf{};
     cav_fgmres_opts fo{};
     fo.rtol = o->lin_rtol;
     fo.max_it = o->lin_max_it;
     hipStream_t s = c.stream;
     for (int it = 0;; ++it) {
       // X_k = X^n + dt J^n u_k and the force there
+      stage = 5;
       if (M > 0) {
         call(cav_ib_interpolate(ctx, x, dU));
         CAV_HIP(hipMemcpyAsync(U.data(), dU, U.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         CAV_HIP(hipStreamSynchronize(s));
       }
       for (size_t k = 0; k < Xk.size(); ++k) Xk[k] = Xn[k] + g->dt * U[k];
+      have_X = true;
       d.X_force = Xk.data();
       std::string err;
       const cav_status fs = fibre_force(&d, Fh, err);
@@ -1941,37 +2048,49 @@ cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_struc
       // operator is kept when X_k is the configuration it was built at, as for
       // the first correction from rest)
       if (Xk != built) {
+        stage = 1;
         call(cav_build_operator(ctx, g, &d));
         built = Xk;
       }
+      stage = 2;
       call(cav_build_cav_patches(ctx, o->family, nullptr));
+      stage = 3;
       call(cav_factor_patches(ctx, o->precision, o->cond_threshold, nullptr));
       call(cav_set_smoother(ctx, o->smoother, o->alpha, 1, 1));
+      stage = 4;
       cav_solve_info si{};
       const cav_status ls = cav_fgmres_solve(ctx, dy, ddx, &fo, &si);
-      if (ls != CAV_OK && ls != CAV_WARN_FLOOR_LIMITED) throw StatusError(ls, c.err);
+      if (ls == CAV_WARN_NOT_CONVERGED)
+        ++inf.lin_unconverged;  // the correction is FGMRES's best: inexact Newton
+      else if (ls != CAV_OK && ls != CAV_WARN_FLOOR_LIMITED)
+        throw StatusError(ls, c.err);
       k_axpby<<<nblocks(n), TPB, 0, s>>>(x, 1.0, ddx, 1.0, n);
       CAV_HIP(hipGetLastError());
       ++inf.newton_its;
       inf.fgmres_its_total += si.iterations;
       inf.fgmres_its_max = std::max(inf.fgmres_its_max, si.iterations);
     }
-    if (X_new) std::copy(Xk.begin(), Xk.end(), X_new);
     CAV_HIP(hipStreamSynchronize(s));
     release();
-    if (info) *info = inf;
+    report();
     return inf.converged ? CAV_OK : CAV_WARN_NOT_CONVERGED;
   } catch (const StatusError& e) {
     c.err = e.msg;
     release();
+    inf.failed_stage = stage;
+    report();
     return e.st;
   } catch (const HipError& e) {
     c.err = e.msg;
     release();
+    inf.failed_stage = stage;
+    report();
     return CAV_ERR_HIP;
   } catch (const std::bad_alloc&) {
     c.err = "host allocation failed";
     release();
+    inf.failed_stage = stage;
+    report();
     return CAV_ERR_OUT_OF_MEMORY;
   }
 }

@@ -106,6 +106,8 @@ struct Level {
   // multiplicative sweep: explicit patches in colour phases
   std::vector<int32_t> ph_ptr;            // n_phases + 1 offsets into ph_exp
   std::vector<int32_t> ph_exp;            // explicit patch ids, phase-major
+  std::vector<int64_t> pred_ptr;          // explicit patch id -> offsets into pred (n_exp + 1)
+  std::vector<int32_t> pred;              // conflicting patches of earlier colours (explicit ids)
   MultRec* d_mrec = nullptr;              // records in ph_exp order
   int32_t mrec_max_n = 0;
   std::vector<double> ph_bytes;           // algorithmic bytes of each phase launch
@@ -116,7 +118,22 @@ struct Level {
                                                 // 1/2 = cooperative form with 64/128 rows per workgroup,
                                                 // 3 = cooperative form with a shared residual (autotuned)
   int32_t* d_ph_ptr = nullptr;            // device copy of ph_ptr (persistent sweep)
-  bool persistent = false;                // whole sweep in one cooperative launch (autotuned)
+  // explicit phases of a sweep: 0 one launch per phase (default), 1 one
+  // cooperative launch with a grid barrier per phase, 2 one dataflow launch
+  int sweep_mode = 0;
+  // dataflow sweep: per phase-order patch its successors (patches of later
+  // colours that conflict with it; d_pr_ptr holds n + 1 offsets, then the
+  // item completions each patch waits for per sweep) and the successor list
+  // (int32, in d_pr); the ticket counter and per-patch arrival counters
+  // (flow[0] ticket, flow[1 + p] completions signalled to patch p), both
+  // monotonic: the host keeps the ticket base and the sweep index of the next launch
+  int32_t* d_pr_ptr = nullptr;
+  int32_t* d_pr = nullptr;
+  unsigned long long* d_flow = nullptr;
+  uint64_t flow_base = 0, flow_sweep = 0;
+  int flow_grid = 0;
+  int64_t flow_items = 0;
+  double flow_bytes = 0;                  // algorithmic bytes of one dataflow sweep
   int sweep_grid = 0;                     // its workgroups (0: not yet computed)
   std::vector<int32_t> ph_wptr;           // split form: work items of each phase (offsets)
   int2* d_wrk = nullptr;                  // (record index in d_mrec, first row)
@@ -193,6 +210,8 @@ struct Net {
   double* d_rl = nullptr;        // residual-loss workspace: r, c, res, K res (4 x 3N^2) + partials
   int64_t rl_n = 0;
   std::vector<void*> allocs;
+  cav_allocator ua{};            // the caller's allocator (cav_net_create), if any
+  bool has_ua = false;
 };
 
 // Device-resident FGMRES state (graph mode). Integer slots:
@@ -266,6 +285,7 @@ struct Ctx {
   // the build's own uploads on `stream` do not queue behind them
   hipStream_t fstream = nullptr;
   hipEvent_t ev_fup = nullptr, ev_fdone = nullptr, ev_fdone2 = nullptr;
+  hipEvent_t ev_js[2] = {nullptr, nullptr};  // side streams joined into `stream` before a block is returned
   bool fwait = false;                     // `stream` must wait for ev_fdone and ev_fdone2 before reading their results
   // the coarsest factorisation starts when the operator is built (it needs
   // nothing else) and is collected by cav_factor_patches
@@ -291,7 +311,8 @@ struct Ctx {
     int ev;          // event index of the start (the end is ev + 1)
     double bytes;    // algorithmic bytes of the bracketed launches
     int launches;    // launches inside the bracket
-    int coop;        // 1: cooperative-form phase launches (64/128 rows), 2: shared-residual form
+    int coop;        // 1: cooperative-form phase launches (64/128 rows), 2: shared-residual form,
+                     // 3: dataflow sweep launches
   };
   std::vector<KtMark> kt_marks;
   std::vector<std::pair<int, int>> vc_marks;      // event indices around each V-cycle
@@ -344,6 +365,10 @@ void prepare_mult_smoother(size_t lds);
 // the whole multiplicative sweep of level L in one cooperative launch; false if not possible
 bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t s);
 void launch_clear_sweep_flags(Ctx& c, hipStream_t s);
+// the explicit phases of a sweep of level L as one dataflow launch; false if not possible
+bool launch_mult_flow(Ctx& c, Level& L, const double* b, double* x, hipStream_t s);
+void reset_sweep_counters(Ctx& c, hipStream_t s);
+void launch_zero_u64(unsigned long long* v, int64_t n, hipStream_t s);
 inline int level_smoother(const Ctx& c, const Level& L) { return L.smoother >= 0 ? L.smoother : c.smoother; }
 inline double level_alpha(const Ctx& c, const Level& L) { return L.smoother >= 0 ? L.alpha : c.alpha; }
 // size bucket of a phase by its largest patch: <= 64, <= 128, <= 256, larger
@@ -389,6 +414,7 @@ void device_sync_epoch(Ctx& c);
 // learned stage (kernels_learned.hip)
 void net_alloc(Net& n, int64_t pix);
 void* net_dev_alloc(Net& n, size_t bytes);
+void net_dev_free(Net& n, void* p);
 void net_pack(Net& n, hipStream_t s);
 void net_forward_f32(Net& n, int N, int B, const float* in, const int32_t* idx, float* out, hipStream_t s);
 // c = ||r|| N(r / ||r||) with the pressure mean of c removed; nrm2 = device ||r||^2 (one double)

@@ -894,6 +894,49 @@ void factor_level_finish(Ctx& c, Level& L, FactorPending& fp, int precision, dou
     if (L.d_ph_ptr) dev_free(c, L.d_ph_ptr);
     L.d_ph_ptr = upload(c, L.ph_ptr);
     L.sweep_grid = 0;
+    // dataflow sweep: every patch's successors by phase-order index (the
+    // patches of later colours that conflict with it) and the number of item
+    // completions it waits for per sweep (the 64-row items of all its
+    // predecessors); counters start at zero
+    {
+      const int32_t nr = int32_t(L.ph_exp.size());
+      std::vector<int32_t> pos(size_t(ne), -1);
+      for (int32_t q = 0; q < nr; ++q) pos[L.ph_exp[q]] = q;
+      std::vector<int32_t> need(size_t(std::max(nr, 1)), 0), sptr(size_t(nr) + 1, 0);
+      for (int32_t q = 0; q < nr; ++q) {
+        const int32_t e = L.ph_exp[q];
+        for (int64_t t = L.pred_ptr[e]; t < L.pred_ptr[e + 1]; ++t) {
+          const int32_t pq = pos[L.pred[t]];
+          need[q] += (mrec[pq].n + 63) / 64;
+          ++sptr[pq + 1];
+        }
+      }
+      for (int32_t q = 0; q < nr; ++q) sptr[q + 1] += sptr[q];
+      std::vector<int32_t> succ(size_t(std::max(sptr[nr], 1)), 0);
+      {
+        std::vector<int32_t> fill(sptr.begin(), sptr.end() - 1);
+        for (int32_t q = 0; q < nr; ++q) {
+          const int32_t e = L.ph_exp[q];
+          for (int64_t t = L.pred_ptr[e]; t < L.pred_ptr[e + 1]; ++t) succ[fill[pos[L.pred[t]]]++] = q;
+        }
+      }
+      for (void** pp : {(void**)&L.d_pr_ptr, (void**)&L.d_pr, (void**)&L.d_flow}) {
+        if (*pp) dev_free(c, *pp);
+        *pp = nullptr;
+      }
+      // d_pr_ptr: successor offsets (nr + 1), then the completions each patch waits for (nr)
+      std::vector<int32_t> tab(sptr);
+      tab.insert(tab.end(), need.begin(), need.begin() + nr);
+      L.d_pr_ptr = upload(c, tab);
+      L.d_pr = upload(c, succ);
+      const size_t nf = 1 + std::max<size_t>(mrec.size(), 1);
+      L.d_flow = static_cast<unsigned long long*>(dev_alloc(c, nf * sizeof(unsigned long long)));
+      launch_zero_u64(L.d_flow, int64_t(nf), s);
+      L.flow_base = L.flow_sweep = 0;
+      L.flow_items = int64_t(L.ph_wptr.back());
+      L.flow_bytes = 0.0;
+      for (double v : L.ph_bytes) L.flow_bytes += v;
+    }
     if (!c.d_bar) {
       c.d_bar = static_cast<unsigned long long*>(dev_alloc(c, 2 * sizeof(unsigned long long)));
       CAV_HIP(hipMemsetAsync(c.d_bar, 0, 2 * sizeof(unsigned long long), s));

@@ -592,7 +592,12 @@ inline int ilog2(int N) {
 
 void* net_dev_alloc(Net& n, size_t bytes) {
   void* p = nullptr;
-  if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+  const size_t sz = (std::max<size_t>(bytes, 16) + 255) & ~size_t(255);
+  if (n.has_ua) {
+    p = n.ua.alloc(sz, static_cast<void*>(n.stream), n.ua.user);
+    if (!p) throw StatusError(CAV_ERR_OUT_OF_MEMORY, "the caller's allocator returned no block of " +
+                                                         std::to_string(sz) + " bytes");
+  } else if (hipMalloc(&p, sz) != hipSuccess) {
     (void)hipGetLastError();
     throw StatusError(CAV_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
@@ -600,17 +605,27 @@ void* net_dev_alloc(Net& n, size_t bytes) {
   return p;
 }
 
-static void net_free(Net& n, void* p) {
+// Returns a block to its source (the work using it is already enqueued on
+// the net's stream, which a stream-ordered allocator respects).
+static void net_release(Net& n, void* p) {
+  if (n.has_ua)
+    n.ua.free(p, static_cast<void*>(n.stream), n.ua.user);
+  else
+    (void)hipFree(p);
+}
+
+void net_dev_free(Net& n, void* p) {
   if (!p) return;
   auto it = std::find(n.allocs.begin(), n.allocs.end(), p);
-  if (it != n.allocs.end()) n.allocs.erase(it);
-  (void)hipFree(p);
+  if (it == n.allocs.end()) return;
+  n.allocs.erase(it);
+  net_release(n, p);
 }
 
 void net_alloc(Net& n, int64_t pix) {
   if (pix <= n.cap_pix) return;
   for (void* p : {(void*)n.d_a1, (void*)n.d_a2, (void*)n.d_y3, (void*)n.d_g3, (void*)n.d_g2, (void*)n.d_g1})
-    net_free(n, p);
+    net_dev_free(n, p);
   n.d_a1 = n.d_a2 = nullptr;
   n.d_y3 = n.d_g3 = n.d_g2 = n.d_g1 = nullptr;
   n.cap_pix = 0;
@@ -663,7 +678,7 @@ static int loss_blocks(int64_t n3) { return int(std::min<int64_t>(std::max<int64
 
 static void ensure_ls(Net& n, int B, int lblk) {
   if (int64_t(B) * (2 * lblk + 2) > n.ls_cap) {
-    net_free(n, n.d_ls);
+    net_dev_free(n, n.d_ls);
     n.ls_cap = int64_t(B) * (2 * lblk + 2);
     n.d_ls = static_cast<double*>(net_dev_alloc(n, size_t(n.ls_cap) * sizeof(double)));
   }
@@ -714,7 +729,7 @@ void net_backward_update(Net& n, int N, int B, const float* rhat, const int32_t*
   const int tiles = B * (N / 8) * (N / 8);
   const int nblk = std::min(tiles, 512);
   if (int64_t(nblk) * 9216 > n.wpart_cap) {
-    net_free(n, n.d_wpart);
+    net_dev_free(n, n.d_wpart);
     n.d_wpart = static_cast<float*>(net_dev_alloc(n, size_t(nblk) * 9216 * sizeof(float)));
     n.wpart_cap = int64_t(nblk) * 9216;
   }
@@ -768,7 +783,7 @@ const int32_t* net_upload_index(Net& n, const int32_t* index, int batch, int64_t
   for (int b = 0; b < batch; ++b)
     if (index[b] < 0 || index[b] >= n_samples) throw StatusError(CAV_ERR_INVALID_ARG, "sample index out of range");
   if (n.idx_cap < batch) {
-    net_free(n, n.d_idx);
+    net_dev_free(n, n.d_idx);
     n.d_idx = static_cast<int32_t*>(net_dev_alloc(n, size_t(batch) * sizeof(int32_t)));
     n.idx_cap = batch;
   }
@@ -815,8 +830,9 @@ void check_grid(int N) {
 
 extern "C" {
 
-cav_status cav_net_create(cav_net* out, int device, void* stream) {
+cav_status cav_net_create(cav_net* out, int device, void* stream, const cav_allocator* allocator) {
   if (!out) return CAV_ERR_INVALID_ARG;
+  if (allocator && (!allocator->alloc || !allocator->free)) return CAV_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CAV_ERR_INVALID_ARG;
   if (hipSetDevice(device) != hipSuccess) return CAV_ERR_HIP;
@@ -824,6 +840,10 @@ cav_status cav_net_create(cav_net* out, int device, void* stream) {
   if (!net) return CAV_ERR_OUT_OF_MEMORY;
   net->n.device = device;
   net->n.stream = static_cast<hipStream_t>(stream);
+  if (allocator) {
+    net->n.ua = *allocator;
+    net->n.has_ua = true;
+  }
   Net& n = net->n;
   try {
     n.d_w = static_cast<float*>(net_dev_alloc(n, NET_W * sizeof(float)));
@@ -839,7 +859,8 @@ cav_status cav_net_create(cav_net* out, int device, void* stream) {
     net_pack(n, n.stream);
     CAV_HIP(hipStreamSynchronize(n.stream));
   } catch (...) {
-    for (void* p : n.allocs) (void)hipFree(p);
+    (void)hipStreamSynchronize(n.stream);
+    for (void* p : n.allocs) net_release(n, p);
     delete net;
     return CAV_ERR_OUT_OF_MEMORY;
   }
@@ -851,7 +872,7 @@ cav_status cav_net_destroy(cav_net net) {
   if (!net) return CAV_OK;
   (void)hipSetDevice(net->n.device);
   if (net->n.stream) (void)hipStreamSynchronize(net->n.stream);
-  for (void* p : net->n.allocs) (void)hipFree(p);
+  for (void* p : net->n.allocs) net_release(net->n, p);
   delete net;
   return CAV_OK;
 }
@@ -913,7 +934,7 @@ cav_status cav_net_correct(cav_net net, int32_t N, const double* r, double* c) {
   const int64_t len = 3 * int64_t(N) * N;
   const int nbk = dots_blocks(len);
   if (n.red_cap < nbk + 1) {
-    net_free(n, n.d_red);
+    net_dev_free(n, n.d_red);
     n.d_red = static_cast<double*>(net_dev_alloc(n, size_t(nbk + 1) * sizeof(double)));
     n.red_cap = nbk + 1;
   }

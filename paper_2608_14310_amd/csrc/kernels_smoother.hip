@@ -493,9 +493,10 @@ __global__ __launch_bounds__(1024) void k_mult_coop(const CoopItem* __restrict__
   __syncthreads();
   if (k > 1) {
     if (threadIdx.x == 0) {
-      // every x load of this workgroup has returned (its values are in LDS)
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      const unsigned long long old = __hip_atomic_fetch_add(cnt + it.cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // release at device scope: every x load of this workgroup (ordered
+      // before this thread by the barrier above) happens before any write of
+      // x by a workgroup that sees this arrival
+      const unsigned long long old = __hip_atomic_fetch_add(cnt + it.cnt, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       const unsigned long long target = (old / unsigned(k) + 1) * unsigned(k);
       int good = 1;
       unsigned spins = 0;
@@ -507,7 +508,8 @@ __global__ __launch_bounds__(1024) void k_mult_coop(const CoopItem* __restrict__
         }
         __builtin_amdgcn_s_sleep(1);
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      // acquire at device scope, paired with the other workgroups' releases
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       s_ok = good;
     }
     __syncthreads();
@@ -596,9 +598,10 @@ __device__ __forceinline__ void mx_gemv_single(const T* __restrict__ arena, int6
 // the k workgroups of a patch forms only its own 64 residual rows and stores
 // them to the patch's slots of rbuf with device-coherent stores; after the
 // arrival barrier every workgroup reads the whole residual back with
-// device-coherent loads. Each workgroup's stores have completed (waitcnt)
-// before its arrival, so a workgroup that has seen all k arrivals reads the
-// final values. Rows, items and block order are those of k_mult_exp, so the
+// device-coherent loads. The arrival is a release and the wait ends with an
+// acquire, both at device scope, so a workgroup that has seen all k arrivals
+// reads the final values, and every workgroup's x loads happen before any x
+// write of the patch. Rows, items and block order are those of k_mult_exp, so the
 // results equal it bit for bit. Waves 0 .. 7 form the residual without
 // waiting for the item record (row records hold everything, including the
 // row's place in rbuf); waves 8 .. 15 copy the 64-row slice of the inverse to
@@ -669,8 +672,11 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
     __syncthreads();
   } else {
     unsigned long long old = 0;
+    // release at device scope: this workgroup's residual stores (ordered
+    // before this thread by the barrier above) are visible to every workgroup
+    // that sees the arrival, and its x loads happen before their x writes
     if (threadIdx.x == 0)
-      old = __hip_atomic_fetch_add(cnt + it.cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      old = __hip_atomic_fetch_add(cnt + it.cnt, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     if (threadIdx.x == 0) {
       const unsigned long long target = (old / unsigned(k) + 1) * unsigned(k);
       int good = 1;
@@ -683,6 +689,8 @@ __global__ __launch_bounds__(1024) void k_mult_coopr(const CoopItem* __restrict_
         }
         __builtin_amdgcn_s_sleep(1);
       }
+      // acquire at device scope, paired with the other workgroups' releases
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       s_ok = good;
     }
     __syncthreads();
@@ -987,6 +995,247 @@ __global__ __launch_bounds__(NT) void k_mult_sweep(SweepArgs a) {
   }
 }
 
+// ---- dataflow form of a level's explicit-patch sweep ----
+// One launch runs every explicit phase of a sweep. Work items are the
+// (patch, 64-row block) items of the shared-residual form in phase order; a
+// workgroup claims the next item from a ticket counter, and an item of patch
+// p starts its residual only when every patch of an earlier colour that
+// conflicts with p (shares an unknown or a K_E coupling) has finished this
+// sweep: each finished item adds one to the arrival counter of every
+// successor of its patch (after a release fence at device scope), and p
+// waits, on one counter with one lane, for the number of items of all its
+// predecessors. Non-conflicting patches commute, so the result equals the
+// sweep in phase order bit for bit, while independent regions of the
+// structure run through their colours without waiting for each other and no
+// phase waits for a launch. Before that wait the item's row records, E_E
+// entries, b and its 64-row slice of the inverse are already loaded.
+// Progress: items are claimed in order and an item waits only on items of
+// smaller index, all claimed by running workgroups, so the smallest unfinished
+// item can always proceed. Every wait is bounded (a timeout sets err; then
+// every workgroup stops claiming and the host reports the failure).
+// Counters are monotonic: the ticket is `base` plus items claimed, and the
+// arrival counter of patch p reaches `sweep` times its wait count when every
+// predecessor has finished this sweep.
+struct FlowArgs {
+  const CoopItem* items;
+  const int4* irow;
+  int64_t n_items;
+  const double* a64;
+  const float* a32;
+  StencilCoef sc;
+  const int32_t* ecol;
+  const double* eval;
+  const double* b;
+  double* x;
+  double alpha;
+  const uint8_t* smask;
+  double* rbuf;
+  unsigned long long* pcnt;     // arrival counters of the 64-row items of each patch
+  unsigned long long* flow;     // [0] ticket, [1 + p] completions signalled to patch p
+  unsigned long long base, sweep;
+  const int32_t* succ_ptr;      // phase-order patch -> successor range (n + 1), then its wait count (n)
+  const int32_t* succ;          // successors
+  int32_t n_rec;                // patches
+  int* err;
+  unsigned limit;
+  int pf_bytes;
+};
+
+// One lane waits until *ctr >= target (bounded); false on a timeout (err set)
+// or when another workgroup has reported one.
+__device__ __forceinline__ bool flow_wait(const unsigned long long* ctr, unsigned long long target, int* err,
+                                          unsigned limit) {
+  unsigned spins = 0;
+  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (++spins > limit) {
+      atomicExch(err, 1);
+      return false;
+    }
+    if ((spins & 63) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(1024) void k_mult_flow(FlowArgs a) {
+  constexpr int NT = 1024, RB = 64;
+  constexpr int NR = RB * MX_G;            // waves 0 .. 7 form the residual rows
+  constexpr int POLL_WAVE = NR / 64;       // wave 8 waits for the predecessors
+  constexpr int COPY_W0 = POLL_WAVE + 1;   // waves 9 .. 15 copy the inverse slice
+  static_assert(COPY_W0 < NT / 64, "copy waves exist");
+  extern __shared__ double smem[];
+  __shared__ int s_t, s_ok;
+  unsigned char* slice = reinterpret_cast<unsigned char*>(smem);
+  double* xo = smem + a.pf_bytes / 8;                  // RB values of this item's unknowns before the update
+  int32_t* dd = reinterpret_cast<int32_t*>(xo + RB);   // RB unknowns
+  double* rp = xo + RB + RB / 2;                       // n residual rows, then the block partials
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = threadIdx.x / MX_G, gl = threadIdx.x % MX_G;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int t = -1;
+      if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        const unsigned long long q =
+            __hip_atomic_fetch_add(a.flow, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - a.base;
+        if (q < static_cast<unsigned long long>(a.n_items)) t = int(q);
+      }
+      s_t = t;
+      s_ok = 1;
+    }
+    __syncthreads();
+    const int t = s_t;
+    if (t < 0) return;
+    const CoopItem it = a.items[t];
+    const MultRec rec = it.rec;
+    const int n = rec.n, k = (n + RB - 1) / RB, r0 = it.r0, nr = min(RB, n - r0);
+    const int p = it.cnt;
+    const int sz = rec.f32 ? 4 : 8;
+    const bool pf = int64_t(64) * n * sz <= a.pf_bytes;
+    // (1) before the wait: row records, the first round of E_E entries and b
+    // (residual waves), the predecessor wait (poll wave), the slice (copy waves)
+    int d = -1, q0 = 0, q1 = 0, qw = -1;
+    double bv = 0.0;
+    int cidx[MX_PER];
+    double cv[MX_PER];
+    if (threadIdx.x < NR) {
+      const int4 q = a.irow[int64_t(t) * RB + grp];
+      d = q.x;
+      q0 = q.y;
+      q1 = q.z;
+      qw = q.w;
+      bv = (gl == 0 && d >= 0) ? a.b[d] : 0.0;
+#pragma unroll
+      for (int kk = 0; kk < MX_PER; ++kk) {
+        const int e = q0 + gl + MX_G * kk;
+        cidx[kk] = e < q1 ? a.ecol[e] : -1;
+        cv[kk] = e < q1 ? a.eval[e] : 0.0;
+      }
+    } else if (wave == POLL_WAVE) {
+      if (lane == 0) {
+        const unsigned long long need = static_cast<unsigned long long>(a.succ_ptr[a.n_rec + 1 + p]);
+        if (!flow_wait(a.flow + 1 + p, a.sweep * need, a.err, a.limit)) s_ok = 0;
+      }
+      // acquire at device scope, paired with every predecessor's release
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    } else if (pf) {
+      if (rec.f32)
+        mx_prefetch_slice<4>(reinterpret_cast<const unsigned char*>(a.a32 + rec.fac), n, r0, slice, COPY_W0);
+      else
+        mx_prefetch_slice<8>(reinterpret_cast<const unsigned char*>(a.a64 + rec.fac), n, r0, slice, COPY_W0);
+    }
+    __syncthreads();
+    if (!s_ok) {
+      __builtin_amdgcn_s_waitcnt(0);   // no copy into LDS outlives the workgroup
+      return;
+    }
+    // (2) residual rows (the arithmetic of mx_residual_rows, row by row)
+    if (threadIdx.x < NR) {
+      const bool own = gl == 0 && d >= 0;
+      const double stv = own ? krow(d, a.x, a.sc, nullptr, nullptr, nullptr) : 0.0;
+      const double xd = own ? a.x[d] : 0.0;
+      double xv[MX_PER];
+#pragma unroll
+      for (int kk = 0; kk < MX_PER; ++kk) xv[kk] = cidx[kk] >= 0 ? a.x[cidx[kk]] : 0.0;
+      double acc = 0.0;
+      if (q0 < q1) {
+#pragma unroll
+        for (int kk = 0; kk < MX_PER; ++kk) acc += cv[kk] * xv[kk];
+      }
+      const int rounds = (q1 - q0 + MX_G * MX_PER - 1) / (MX_G * MX_PER);
+      for (int k0 = 1; k0 < rounds; ++k0) {
+        int ci[MX_PER];
+        double cw[MX_PER], xw[MX_PER];
+#pragma unroll
+        for (int kk = 0; kk < MX_PER; ++kk) {
+          const int e = q0 + k0 * MX_G * MX_PER + gl + MX_G * kk;
+          ci[kk] = e < q1 ? a.ecol[e] : -1;
+          cw[kk] = e < q1 ? a.eval[e] : 0.0;
+        }
+#pragma unroll
+        for (int kk = 0; kk < MX_PER; ++kk) xw[kk] = ci[kk] >= 0 ? a.x[ci[kk]] : 0.0;
+#pragma unroll
+        for (int kk = 0; kk < MX_PER; ++kk) acc += cw[kk] * xw[kk];
+      }
+      if (own) acc += stv;
+#pragma unroll
+      for (int o = MX_G / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, MX_G);
+      if (own) {
+        const double r = bv - acc;
+        if (qw >= 0)
+          __hip_atomic_store(a.rbuf + qw, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+          rp[grp] = r;
+        xo[grp] = xd;
+        dd[grp] = d;
+      }
+      __builtin_amdgcn_s_waitcnt(0);   // this wave's residual stores and x loads have completed
+    }
+    __syncthreads();
+    // (3) a patch over several items: exchange the residual rows
+    if (k > 1) {
+      if (threadIdx.x == 0) {
+        const unsigned long long old =
+            __hip_atomic_fetch_add(a.pcnt + p, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long target = (old / unsigned(k) + 1) * unsigned(k);
+        const bool ok = flow_wait(a.pcnt + p, target, a.err, a.limit);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_ok = ok ? 1 : 0;
+      }
+      __syncthreads();
+      if (!s_ok) {
+        __builtin_amdgcn_s_waitcnt(0);
+        return;
+      }
+      const double* ra = a.rbuf + rec.slot;
+      for (int j = threadIdx.x; j < n; j += NT) rp[j] = __hip_atomic_load(ra + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // the slice has landed
+    __syncthreads();
+    // (4) this item's rows of delta = K_p^{-1} r (items and block order of k_mult_exp)
+    const int nb = (n + MX_CB - 1) / MX_CB;
+    double* pp = rp + n;
+    {
+      auto ij = [nr, r0](int q, int& i, int& cb) {
+        i = r0 + q % nr;
+        cb = q / nr;
+      };
+      auto put = [pp, nr](int q, double v) { pp[(q / nr) * RB + q % nr] = v; };
+      if (pf) {
+        if (rec.f32)
+          mx_gemv_lds(reinterpret_cast<const float*>(slice), r0, rp, n, nr * nb, NT, ij, put);
+        else
+          mx_gemv_lds(reinterpret_cast<const double*>(slice), r0, rp, n, nr * nb, NT, ij, put);
+      } else if (rec.f32) {
+        mx_gemv_single(a.a32, rec.fac, rp, n, nr * nb, NT, ij, put);
+      } else {
+        mx_gemv_single(a.a64, rec.fac, rp, n, nr * nb, NT, ij, put);
+      }
+    }
+    __syncthreads();
+    // (5) x at this item's rows, then the done count (release at device scope)
+    for (int ii = threadIdx.x; ii < nr; ii += NT) {
+      double sacc = 0.0;
+      for (int cb = 0; cb < nb; ++cb) sacc += pp[cb * RB + ii];
+      if (!a.smask || a.smask[rec.slot + r0 + ii])
+        __hip_atomic_store(a.x + dd[ii], xo[ii] + a.alpha * sacc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // every wave's x stores have completed
+    __syncthreads();
+    // signal every successor: release at device scope, then one arrival each
+    if (wave == 0) {
+      const int sa = a.succ_ptr[p], sb = a.succ_ptr[p + 1];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      for (int i = sa + lane; i < sb; i += 64)
+        __hip_atomic_fetch_add(a.flow + 1 + a.succ[i], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* v, int64_t n) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) v[t] = 0ull;
+}
+
 __global__ void k_zero_bar(unsigned long long* bar, int words) {
   if (blockIdx.x == 0 && int(threadIdx.x) < words) bar[threadIdx.x] = 0ull;
 }
@@ -1042,6 +1291,57 @@ bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t
   return true;
 }
 
+void launch_zero_u64(unsigned long long* v, int64_t n, hipStream_t s) {
+  if (n > 0) k_zero_u64<<<unsigned((n + 255) / 256), 256, 0, s>>>(v, n);
+}
+
+// Workgroups of the dataflow sweep of level L: as many as stay resident (one
+// item each at a time), at most one per item; 0 if not possible.
+static int flow_grid(const Level& L) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_mult_flow), 1024,
+                                                   L.cr_lds) != hipSuccess)
+    return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess)
+    return 0;
+  const int grid = int(std::min<int64_t>(int64_t(per_cu) * cus, L.flow_items));
+  // the items of one patch meet at a barrier: all of them must be claimable at once
+  const int k_max = (std::max<int32_t>(L.mrec_max_n, 1) + 63) / 64;
+  return grid >= std::min<int64_t>(k_max, L.flow_items) ? grid : 0;
+}
+
+bool launch_mult_flow(Ctx& c, Level& L, const double* b, double* x, hipStream_t s) {
+  if (c.capturing || L.flow_items <= 0 || !L.d_flow || !L.d_pr || !L.d_pr_ptr || !L.d_irow || !L.d_citem[0] ||
+      !L.d_pcnt || !L.d_delta || !c.d_bar)
+    return false;
+  if (L.flow_grid == 0) L.flow_grid = flow_grid(L);
+  if (L.flow_grid <= 0) return false;
+  ++L.flow_sweep;
+  FlowArgs a{L.d_citem[0], L.d_irow, L.flow_items, L.d_f64, L.d_f32, L.sc, L.d_ecol, L.d_eval, b, x,
+             level_alpha(c, L), L.d_slot_mask, L.d_delta, L.d_pcnt, L.d_flow, L.flow_base, L.flow_sweep,
+             L.d_pr_ptr, L.d_pr, int32_t(L.ph_exp.size()), reinterpret_cast<int*>(c.d_bar + 1), c.wait_limit,
+             L.cr_pf};
+  timing_begin(c, s, 3);
+  k_mult_flow<<<unsigned(L.flow_grid), 1024, L.cr_lds, s>>>(a);
+  timing_end(c, s, L.flow_bytes, 1);
+  // every workgroup ends with one claim past the last item
+  L.flow_base += uint64_t(L.flow_items) + uint64_t(L.flow_grid);
+  return true;
+}
+
+// Zeroes every level's arrival and dataflow counters (after a wait gave up,
+// when their counts no longer follow whole rounds).
+void reset_sweep_counters(Ctx& c, hipStream_t s) {
+  for (Level& L : c.lv) {
+    const int64_t nrec = std::max<int64_t>(int64_t(L.ph_exp.size()), 1);
+    if (L.d_pcnt) launch_zero_u64(L.d_pcnt, 2 * nrec, s);
+    if (L.d_flow) launch_zero_u64(L.d_flow, 1 + nrec, s);
+    L.flow_base = L.flow_sweep = 0;
+  }
+}
+
 // The form a phase launch takes: the cooperative form waits on other
 // workgroups of its launch, so inside a captured graph (batched systems run
 // concurrently) the one-workgroup form runs instead, with the same results.
@@ -1055,7 +1355,7 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
   const int64_t n2 = int64_t(L.N) * L.N, n = 3 * n2;
   if (zero_guess) launch_fill(x, 0.0, n, s);
   const int nph = int(L.ph_ptr.size()) - 1;
-  if (L.persistent && !c.capturing && launch_mult_sweep(c, L, b, x, s)) {
+  if (L.sweep_mode == 1 && !c.capturing && launch_mult_sweep(c, L, b, x, s)) {
     launch_pressure_mean_remove(x, L.N, L.d_part, s);
     return;
   }
@@ -1066,7 +1366,7 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
                                                      level_alpha(c, L));
   };
   if (c.std_first) standard();
-  if (nph > 0) {
+  if (nph > 0 && !(L.sweep_mode == 2 && launch_mult_flow(c, L, b, x, s))) {
     // one bracket around each run of phase launches of one kernel form
     int open = -1, cnt = 0;
     double bytes = 0.0;
@@ -1150,6 +1450,7 @@ void prepare_mult_smoother(size_t lds) {
                         reinterpret_cast<const void*>(k_mult_exp<1024>), reinterpret_cast<const void*>(k_mult_gemv),
                         reinterpret_cast<const void*>(k_mult_sweep<1024>), reinterpret_cast<const void*>(k_mult_coop<64>),
                         reinterpret_cast<const void*>(k_mult_coop<128>), reinterpret_cast<const void*>(k_mult_coopr),
+                        reinterpret_cast<const void*>(k_mult_flow),
                         reinterpret_cast<const void*>(k_mult_mrhs)})
     CAV_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   set_to = lds;

@@ -689,6 +689,23 @@ void colour_explicit(int N, const HostCSR& ee, Level& L) {
     L.ph_exp.insert(L.ph_exp.end(), by[c].begin(), by[c].end());
     L.ph_ptr.push_back(int32_t(L.ph_exp.size()));
   }
+  // predecessors of every patch in this order: its conflicting patches of an
+  // earlier colour (the conflict relation is symmetric: the reach of an
+  // unknown through the K_E pattern is, and the colouring relies on it)
+  L.pred_ptr.assign(size_t(ne) + 1, 0);
+  for (int e = 0; e < ne; ++e) {
+    int64_t k = 0;
+    for (int32_t q : nbr[e]) k += colour[q] < colour[e];
+    L.pred_ptr[e + 1] = L.pred_ptr[e] + k;
+  }
+  L.pred.resize(size_t(L.pred_ptr[ne]));
+  parallel_items(
+      ne, 64, [] { return 0; },
+      [&](int&, int64_t e) {
+        int64_t o = L.pred_ptr[e];
+        for (int32_t q : nbr[e])
+          if (colour[q] < colour[e]) L.pred[o++] = q;
+      });
 }
 
 // CAV patch family (Eq. cav_patch_set) on one level, plus the arrays the

@@ -277,11 +277,26 @@ def test_kernel_timing_brackets(cav):
     s = workloads.beam_fibres(N=64, n_levels=4, kappa_b=1e-2)
     g = cav.Solver(0)
     g.setup(s, precision="fp64", alpha=1.0, smoother="multiplicative")
+    # per-phase launches of the cooperative forms
+    table = np.full((s.n_levels, 5), 3, np.int32)
+    table[:, 4] = 0
+    g.set_tuning(table)
     g.kernel_timing(True)
     g.vcycle(_t(s.b))
     kt = g.kernel_timing(False)
-    g.close()
     assert kt["vcycles"] == 1 and kt["vcycle_ms"] > 0
     assert 0 < kt["shared_launches"] <= kt["coop_launches"] <= kt["launches"]
     assert 0 < kt["shared_ms"] <= kt["coop_ms"] <= kt["ms"]
     assert 0 < kt["shared_bytes"] <= kt["coop_bytes"] <= kt["bytes"]
+    assert kt["flow_launches"] == 0
+    phase_bytes = kt["bytes"]
+    # the dataflow sweep: one launch per level sweep, the same algorithmic bytes
+    table[:, 4] = 2
+    g.set_tuning(table)
+    g.kernel_timing(True)
+    g.vcycle(_t(s.b))
+    kt = g.kernel_timing(False)
+    g.close()
+    assert kt["coop_launches"] == 0 and 0 < kt["flow_launches"] == kt["launches"]
+    assert 0 < kt["flow_ms"] <= kt["ms"]
+    assert kt["flow_bytes"] == kt["bytes"] == phase_bytes

@@ -161,3 +161,31 @@ def test_newton_edge_cases():
         assert torch.equal(x1, x2) and np.array_equal(X1, X2)
     finally:
         g.close()
+
+
+def test_newton_with_capped_linear_solves_reports_every_field():
+    """lin_max_it = 1: no Newton system's FGMRES meets lin_rtol, yet each
+    correction is applied (inexact Newton) and counted as unconverged; the
+    info fields and X_new are filled whatever the final status."""
+    from paper_2608_14310_amd import Solver
+    s = workloads.flexible_fibre(32, 3, amp=0.3, seed=2)
+    un = workloads.fibre_inflow_velocity(32, seed=2)
+    rhs = _t(np.concatenate([s.rho / s.dt * un, np.zeros(32 * 32)]))
+    print("[fibre] Newton with lin_max_it=1 N=32", flush=True)
+    g = Solver(0)
+    try:
+        x, Xn, info = g.newton_solve(s, rhs, max_newton=4, lin_max_it=1)
+        torch.cuda.synchronize()
+        print(f"[fibre] capped Newton info {info}", flush=True)
+        assert info["status"] in (0, 100)
+        assert info["newton_its"] >= 1 and info["failed_stage"] == 0
+        assert info["lin_unconverged"] == info["newton_its"]
+        assert info["fgmres_its_max"] == 1 and info["fgmres_its_total"] == info["newton_its"]
+        assert np.isfinite(info["res"]) and info["res0"] > 0 and info["res"] < info["res0"]
+        assert info["converged"] == (1 if info["status"] == 0 else 0)
+        # X_new is the configuration of the last iterate: X^n + dt J^n u
+        U = g.ib_interpolate(x).cpu().numpy()
+        X0 = s.markers().ravel()
+        assert np.abs(Xn - (X0 + s.dt * U)).max() <= 1e-14 * max(1.0, np.abs(X0).max())
+    finally:
+        g.close()
