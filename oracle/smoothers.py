@@ -170,9 +170,11 @@ def restricted_additive_sweep(K, solvers: PatchSolvers, b, w, alpha: float, N: i
 
 
 def _update_columns(K, solvers: PatchSolvers, inject):
-    """K[:, q] for the unknowns q each patch updates (all of the patch, or its
-    injected part), sliced once and kept on the solvers object for later
-    sweeps with the same K."""
+    """For each patch, the rows touched by K[:, q] (q the unknowns the patch
+    updates: all of it, or its injected part) and K[rows, q] (CSC, the same
+    columns in the same order), sliced once and kept on the solvers object
+    for later sweeps with the same K. K[rows, q] @ d gives every touched row
+    the sum K[:, q] @ d gives it, in the same order; the other rows are zero."""
     key = (id(K), inject is not None)
     cached = getattr(solvers, "_update_cols", None)
     if cached is None or cached[0] != key:
@@ -180,7 +182,9 @@ def _update_columns(K, solvers: PatchSolvers, inject):
         cols = []
         for k, p in enumerate(solvers.patches):
             q = p[inject[k]] if inject is not None else p
-            cols.append(Kc[:, q])
+            Kq = Kc[:, q]
+            rows = np.unique(Kq.indices)
+            cols.append((rows, Kq[rows, :].tocsc()))
         cached = (key, cols)
         solvers._update_cols = cached
     return cached[1]
@@ -199,5 +203,6 @@ def multiplicative_sweep(K, solvers: PatchSolvers, b, w, N: int, inject=None):
             m = inject[k]
             p, d = p[m], d[m]
         w[p] += d
-        r -= cols[k] @ d
+        rows, Kq = cols[k]
+        r[rows] -= Kq @ d
     return remove_mean_pressure(w, N)
