@@ -359,6 +359,97 @@ def test_additive_sweep_matches_dense_formula():
     assert np.linalg.norm(got - z) < 1e-10 * np.linalg.norm(z)
 
 
+def test_seed_weights_are_partition_of_unity():
+    """Restricted-injection weights of the one-patch-per-cell families (the
+    Appendix A alternative to 1/cnt): every unknown's weights over the patches
+    sum to one, and a patch injects only into its own cell's Vanka unknowns."""
+    s = workloads.membrane_ellipse(16, 2, 1e4, 0)
+    H = multigrid.Hierarchy(s, alpha=0.7)
+    lev = H.levels[1]
+    N = lev.N
+    theta = smoothers.seed_weights(N, lev.patches)
+    acc = np.zeros(lev.K.shape[0])
+    for c, (p, t) in enumerate(zip(lev.patches, theta)):
+        acc[p] += t
+        own = set(patches.vanka_patch(N, *divmod(c, N)).tolist())
+        assert all(int(d) in own for d in p[t != 0])
+    assert np.abs(acc - 1).max() < 1e-15
+
+
+def test_seed_restricted_sweep_with_one_patch_is_exact():
+    """seed_restricted_sweep with weights of one on a single patch covering
+    every unknown is one exact solve (up to the pressure gauge)."""
+    s = workloads.target_circle(8, 1, 1e4, 0)
+    K = mac.reduced_operator(s.N, s.rho, s.mu, s.dt, ib.eulerian_elasticity(s)[0])
+    n = K.shape[0]
+    allp = [np.arange(n)]
+    sol = smoothers.PatchSolvers(K, allp, np.array([False]))
+    b = np.random.default_rng(3).standard_normal(n)
+    b[2 * 64:] -= b[2 * 64:].mean()
+    x = smoothers.seed_restricted_sweep(K, sol, [np.ones(n)], b, np.zeros(n), 1.0, s.N)
+    xs = direct.solve(K, s.N, b)
+    assert np.linalg.norm(x - xs) < 1e-9 * np.linalg.norm(xs)
+
+
+def test_restricted_box_sweeps_with_one_box_are_exact():
+    """B(N, 0) is a single box covering the grid and injecting everywhere:
+    the restricted additive sweep and the multiplicative sweep with injection
+    masks are both one exact solve (up to the pressure gauge)."""
+    s = workloads.target_circle(8, 2, 1e4, 0)
+    H = multigrid.Hierarchy(s, family="box", box=(8, 0), alpha=1.0)
+    lev = H.levels[1]
+    assert len(lev.patches) == 1 and lev.inject[0].all()
+    n = lev.K.shape[0]
+    b = np.random.default_rng(4).standard_normal(n)
+    b[2 * 64:] -= b[2 * 64:].mean()
+    xs = direct.solve(lev.K, lev.N, b)
+    x1 = smoothers.restricted_additive_sweep(lev.K, lev.solvers, b, np.zeros(n), 1.0, lev.N)
+    x2 = smoothers.multiplicative_sweep(lev.K, lev.solvers, b, np.zeros(n), lev.N, lev.inject)
+    for x in (x1, x2):
+        assert np.linalg.norm(x - xs) < 1e-9 * np.linalg.norm(xs)
+
+
+def test_coloured_phases_are_independent():
+    """Patches inside one colour phase share no unknown and no K_E coupling,
+    so reversing their order inside every phase leaves the sequential sweep
+    unchanged (to rounding), while reversing the whole order does not."""
+    s = workloads.beam_fibres(32, 2, 1.0, 1e4, seed=0)
+    H = multigrid.Hierarchy(s, alpha=1.0, smoother="coloured")
+    lev = H.levels[1]
+    n = lev.K.shape[0]
+    b = np.random.default_rng(5).standard_normal(n)
+    H.smooth(1, b, np.zeros(n))
+    phases = lev.phases
+    assert max(len(ph) for ph in phases) > 1
+
+    def sweep(order):
+        sol = smoothers.PatchSolvers(lev.K, [lev.patches[c] for c in order], lev.standard[order])
+        return smoothers.multiplicative_sweep(lev.K, sol, b, np.zeros(n), lev.N)
+
+    fwd = sweep([c for ph in phases for c in ph])
+    rev_in = sweep([c for ph in phases for c in reversed(ph)])
+    rev_all = sweep([c for ph in reversed(phases) for c in reversed(ph)])
+    scale = np.linalg.norm(fwd)
+    assert np.linalg.norm(rev_in - fwd) < 1e-12 * scale
+    assert np.linalg.norm(rev_all - fwd) > 1e-6 * scale
+
+
+def test_rounding_floor_matches_a_known_floor():
+    """For a diagonal K and b = K x the floor is u ||K x|| / ||b|| = 2^-53 for
+    positive entries; a nonzero floor appears only where |K||x| exceeds |K x|
+    (cancellation), here by a known factor of 5."""
+    n = 64
+    d = np.linspace(1.0, 2.0, n)
+    K = sp.diags(d).tocsr()
+    x = np.random.default_rng(6).uniform(0.5, 1.0, n)
+    assert abs(direct.rounding_floor(K, x, K @ x) - 2.0 ** -53) < 1e-30
+    # rows of [1, 1] and [-1, 1] against x = (2, 3): |K||x| = (5, 5), K x = (5, 1)
+    K2 = sp.csr_matrix(np.array([[1.0, 1.0], [-1.0, 1.0]]))
+    x2 = np.array([2.0, 3.0])
+    b2 = K2 @ x2
+    assert abs(direct.rounding_floor(K2, x2, b2) - 2.0 ** -53 * np.sqrt(50.0) / np.sqrt(26.0)) < 1e-30
+
+
 # ---------------------------------------------------- multigrid and krylov ---
 
 def test_one_level_vcycle_is_exact_and_fgmres_takes_one_step():
