@@ -338,7 +338,8 @@ def learned_leg(g_eval, b_eval, train_pairs: int, steps: int):
             "enabled": enabled}
 
 
-def learned_c5_leg(dev, pairs_per_class: int = 10000, steps: int = 2000, eval_N: int = 1024):
+def learned_c5_leg(dev, pairs_per_class: int = 10000, steps: int = 2000, eval_N: int = 1024,
+                   eval_precision: str = "mixed"):
     """The learned stage at its configured scale: 20k (residual, error) pairs
     from CAV V-cycles on 256^2 membrane (kappa_s = 1e4) and beam (kappa_b =
     1e-2) systems (3 pairs per exact solution), minimal-residual training on
@@ -388,10 +389,10 @@ def learned_c5_leg(dev, pairs_per_class: int = 10000, steps: int = 2000, eval_N:
     for name, se in (("membrane", workloads.membrane_ellipse(eval_N, L, 1e4, seed=2)),
                      ("beam", workloads.beam_fibres(eval_N, L, 1e-2, 1e4, seed=2))):
         g = Solver(0)
-        g.setup(se, precision="mixed", alpha=1.0, smoother="multiplicative")
+        g.setup(se, precision=eval_precision, alpha=1.0, smoother="multiplicative")
         b = torch.from_numpy(se.b).to(dev)
         g.attach_net(net, 1e-3)
-        row = {"system": f"{name} {eval_N}^2, {L} levels", "unknowns": se.n}
+        row = {"system": f"{name} {eval_N}^2, {L} levels, {eval_precision} factors", "unknowns": se.n}
         for mode in ("plain", "learned"):
             g.fgmres_solve(b, 1e-10, 150, learned=mode == "learned")   # warm-up
             torch.cuda.synchronize()
@@ -640,6 +641,7 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="systems in the batched leg (0: skip)")
     ap.add_argument("--learned-pairs", type=int, default=600, help="training pairs of the learned leg (0: skip)")
     ap.add_argument("--learned-steps", type=int, default=600)
+    ap.add_argument("--learned-c5-eval-precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--learned-c5", action="store_true",
                     help="the learned stage at its configured scale (20k pairs at 256^2, evaluated at 1024^2); "
                          "not part of the default run")
@@ -886,7 +888,7 @@ def main():
         setup("mixed")
         line["learned"] = learned_leg(g, b, a.learned_pairs, a.learned_steps)
     if a.learned_c5:
-        line["learned_c5"] = learned_c5_leg(dev)
+        line["learned_c5"] = learned_c5_leg(dev, eval_precision=a.learned_c5_eval_precision)
     if not a.no_two_grid:
         line["two_grid_table1"] = two_grid_leg()
         line["box_comparison"] = box_comparison_leg()

@@ -73,13 +73,14 @@ enum { CAV_LAW_TARGET = 0, CAV_LAW_MEMBRANE = 1, CAV_LAW_BEAM_CLOSED = 2, CAV_LA
 enum { CAV_FAMILY_CAV = 0, CAV_FAMILY_VANKA = 1, CAV_FAMILY_BOX = 2 };  /* patch families (Section 3) */
 /* Smoothers: ADDITIVE is the weighted additive sweep of Appendix A
  * (Eq. additive_cav_saddle, Theta = 1/cnt); MULTIPLICATIVE is the
- * multiplicative Schwarz sweep of Section 3.3 in a coloured order (patches
- * with E_E entries in greedy colour phases, then the shared standard patches
- * in 8 phases by (i + 3j) mod 8); patches in one phase are independent, so
- * the sweep equals the sequential sweep in that order. */
+ * multiplicative Schwarz sweep of Section 3.3 in a coloured order (the
+ * shared standard patches in 8 phases by (i + 3j) mod 8, then the patches
+ * with E_E entries in greedy colour phases; cav_set_phase_order swaps the two
+ * groups); patches in one phase are independent, so the sweep equals the
+ * sequential sweep in that order. */
 enum { CAV_SMOOTHER_ADDITIVE = 0, CAV_SMOOTHER_MULTIPLICATIVE = 1 };
 /* Order of the two groups of phases in every multiplicative sweep. */
-enum { CAV_ORDER_EXPLICIT_FIRST = 0, CAV_ORDER_STANDARD_FIRST = 1 };
+enum { CAV_ORDER_EXPLICIT_FIRST = 0, CAV_ORDER_STANDARD_FIRST = 1 };  /* default: STANDARD_FIRST */
 enum { CAV_PREC_FP64 = 0, CAV_PREC_MIXED = 1 };            /* factor storage policy */
 
 typedef struct {
@@ -106,8 +107,17 @@ typedef struct {
   int32_t clamp_marker;    /* CAV_LAW_FIBRE only: the clamped marker m */
   double clamp_x, clamp_y; /* CAV_LAW_FIBRE only: the clamp point */
   const double* X_force;   /* CAV_LAW_FIBRE only, optional host 2M: positions at which the energies
-                              (force and tangent) are evaluated; NULL = X. Interpolation and spreading
+                              (force and tangent) are evaluated, links taken as their differences;
+                              NULL = X. Ignored when X_disp is set. Interpolation and spreading
                               always use X (Section 2: S and J at the start of the time step) */
+  const double* X_disp;    /* CAV_LAW_FIBRE only, optional host 2M: displacement from X; the energies
+                              are evaluated at X + X_disp with the links updated incrementally
+                              (Section 5.3), D_k = D_k^0 + (X_disp_{k+1} - X_disp_k), so the bending
+                              term of a nearly straight fibre keeps the digits that differences of
+                              absolute positions would cancel. The Newton step passes dt J^n u here */
+  const double* links;     /* CAV_LAW_FIBRE only, optional host 2(M-1): the link vectors D^0 at X
+                              carried by a caller that updates them incrementally between steps;
+                              NULL = X_{k+1} - X_k. Not used with X_force (without X_disp) */
 } cav_structure_desc;
 
 typedef struct {           /* per smoothed level (index = level, 0 unused) */
@@ -226,11 +236,13 @@ cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold,
  * mean pressure after the sweep. pre/post = sweeps per V-cycle leg (1, 1). */
 cav_status cav_set_smoother(cav_ctx ctx, int kind, double alpha, int pre, int post);
 /* Multiplicative phase order (reading: the paper visits patches
- * lexicographically, Section 3.3): CAV_ORDER_EXPLICIT_FIRST (default) runs the
- * colour phases of patches with E_E entries, then the 8 colours of shared
- * standard patches; CAV_ORDER_STANDARD_FIRST the reverse. Both are valid
- * multiplicative orders; they differ in robustness at extreme stiffness
- * (Table 1 diagnostic). Cleared only by another call. */
+ * lexicographically, Section 3.3): CAV_ORDER_STANDARD_FIRST (default) runs
+ * the 8 colours of shared standard patches, then the colour phases of patches
+ * with E_E entries; CAV_ORDER_EXPLICIT_FIRST the reverse. Both are valid
+ * multiplicative orders; they differ in robustness at high stiffness (the
+ * standard-first two-grid cycle stays contracting on Table 1's stiffest
+ * membrane where the other diverges, and it needs fewer FGMRES iterations on
+ * stiff open fibres). Cleared only by another call. */
 cav_status cav_set_phase_order(cav_ctx ctx, int order);
 /* Bound of every workgroup-barrier wait of the cooperative phase forms and
  * the one-launch sweep, in polls (default 2^21, about a second). A wait that
@@ -330,8 +342,10 @@ typedef struct {
  * mean must be zero: constant pressure is outside the range of K_0, so a
  * nonzero mean would leave a residual no correction removes). Each
  * correction rebuilds the whole hierarchy with E = DF at the current
- * iterate (st->X_force ignored; the operator is kept when the iterate's
- * configuration is the one it was built at) and solves K_E dx = -R with
+ * iterate, the energies evaluated at X^n + dt J^n u with the links updated
+ * incrementally from st->links (else from X^n) by dt J^n u (st->X_force and
+ * st->X_disp ignored; the operator is kept when the iterate's displacement is
+ * the one it was built at) and solves K_E dx = -R with
  * CAV-preconditioned FGMRES (lin_rtol) from zero. X_new: optional host 2M, X^{n+1} at the
  * solution. The context keeps the hierarchy of the last Newton system.
  * A Newton system whose FGMRES reaches lin_max_it without meeting lin_rtol

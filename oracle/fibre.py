@@ -16,6 +16,13 @@ the linearised system is its tangent E = DF = -(1/ds) Hess(energy), which
 couples the x and y components. Gradients and Hessians below are written
 out term by term from those definitions; the tests pin them to finite
 differences, invariances and closed forms.
+
+Every function takes the links D as an optional argument. Section 5.3 updates
+displacements and links incrementally, D^{n+1}_k = D^n_k + (the increment of
+X_{k+1} - X_k), because on a nearly straight fibre the cross products of the
+bending term sit far below the rounding of the absolute positions; a caller
+that forms D that way passes it, and the tangent penalty uses
+X_{m+1} - X_{m-1} = D_{m-1} + D_m so that it too sees the links.
 """
 from __future__ import annotations
 
@@ -23,19 +30,23 @@ import numpy as np
 import scipy.sparse as sp
 
 
-def _links(x):
+def _links(x, D=None):
+    """Positions (M, 2) and links (M-1, 2): the given links D, else X_{k+1} - X_k."""
     X = np.asarray(x, dtype=np.float64).reshape(-1, 2)
-    return X, X[1:] - X[:-1]
+    if D is None:
+        return X, X[1:] - X[:-1]
+    return X, np.asarray(D, dtype=np.float64).reshape(-1, 2)
 
 
 def _cross(a, b):
     return a[..., 0] * b[..., 1] - a[..., 1] * b[..., 0]
 
 
-def energy(x, p) -> float:
+def energy(x, p, D=None) -> float:
     """Total energy E_b + E_s + E_p + E_t at the interleaved positions x.
-    p: dict with ds, EI, K_s, K_p, K_t, m (midpoint marker), Xc (2,)."""
-    X, D = _links(x)
+    p: dict with ds, EI, K_s, K_p, K_t, m (midpoint marker), Xc (2,).
+    D: the links when the caller carries them (else differences of x)."""
+    X, D = _links(x, D)
     ds = p["ds"]
     c = _cross(D[:-1], D[1:])
     Eb = p["EI"] / (2.0 * ds ** 5) * np.sum(c ** 2)
@@ -43,14 +54,14 @@ def energy(x, p) -> float:
     Es = p["K_s"] / (2.0 * ds) * np.sum((L - ds) ** 2)
     m = p["m"]
     Ep = 0.5 * p["K_p"] * np.sum((X[m] - np.asarray(p["Xc"])) ** 2)
-    g = (X[m + 1] - X[m - 1]) / (2.0 * ds) - np.array([1.0, 0.0])
+    g = (D[m - 1] + D[m]) / (2.0 * ds) - np.array([1.0, 0.0])   # X_{m+1} - X_{m-1}
     Et = 0.5 * p["K_t"] * np.sum(g ** 2)
     return float(Eb + Es + Ep + Et)
 
 
-def gradient(x, p, parts=("b", "s", "p", "t")) -> np.ndarray:
+def gradient(x, p, parts=("b", "s", "p", "t"), D=None) -> np.ndarray:
     """d energy / dx (interleaved), summed over the named energies."""
-    X, D = _links(x)
+    X, D = _links(x, D)
     M = len(X)
     ds = p["ds"]
     G = np.zeros((M, 2))
@@ -73,20 +84,20 @@ def gradient(x, p, parts=("b", "s", "p", "t")) -> np.ndarray:
     if "p" in parts:
         G[m] += p["K_p"] * (X[m] - np.asarray(p["Xc"]))
     if "t" in parts:
-        g = (X[m + 1] - X[m - 1]) / (2.0 * ds) - np.array([1.0, 0.0])
+        g = (D[m - 1] + D[m]) / (2.0 * ds) - np.array([1.0, 0.0])
         G[m + 1] += p["K_t"] * g / (2.0 * ds)
         G[m - 1] -= p["K_t"] * g / (2.0 * ds)
     return G.ravel()
 
 
-def force(x, p) -> np.ndarray:
+def force(x, p, D=None) -> np.ndarray:
     """Lagrangian force density F = -(1/ds) grad(energy) (Section 5.3)."""
-    return -gradient(x, p) / p["ds"]
+    return -gradient(x, p, D=D) / p["ds"]
 
 
-def hessian(x, p, parts=("b", "s", "p", "t")) -> sp.csr_matrix:
+def hessian(x, p, parts=("b", "s", "p", "t"), D=None) -> sp.csr_matrix:
     """d^2 energy / dx^2 (2M x 2M, interleaved), summed over the named energies."""
-    X, D = _links(x)
+    X, D = _links(x, D)
     M = len(X)
     ds = p["ds"]
     H = np.zeros((2 * M, 2 * M))
@@ -132,13 +143,13 @@ def hessian(x, p, parts=("b", "s", "p", "t")) -> sp.csr_matrix:
     return sp.csr_matrix(H)
 
 
-def tangent(x, p) -> sp.csr_matrix:
+def tangent(x, p, D=None) -> sp.csr_matrix:
     """The Lagrangian E of the linearised system: E = DF = -(1/ds) Hess(energy),
     component-interleaved, coupling x and y (Section 5.3). Structure (a
     reading, the couplings the energies create): full 2 x 2 blocks for every
     pair of markers at most two apart along the fibre, stored even where a
     value is zero, so that the pattern does not depend on the configuration."""
-    H = hessian(x, p).toarray()
+    H = hessian(x, p, D=D).toarray()
     M = H.shape[0] // 2
     rows, cols = [], []
     for i in range(M):

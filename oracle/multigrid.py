@@ -41,7 +41,7 @@ class Level:
 
 class Hierarchy:
     def __init__(self, system, family: str = "cav", alpha: float = 1.0, smoother: str = "additive",
-                 box=(4, 2), order: str = "explicit_first", lex: str = "y_fast"):
+                 box=(4, 2), order: str = "standard_first", lex: str = "y_fast"):
         """lex: the reading of the paper's lexicographic patch order for the
         sequential multiplicative smoother (Section 3.3): "y_fast" visits
         cells (i, j) with the y index j fastest (the vector layout's order),

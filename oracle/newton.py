@@ -13,7 +13,9 @@ is K_E with A = A_0 - dt S^n E J^n and E = DF at the current configuration
 (Section 2: the tangent of a nonlinear law replaces E). Newton's method takes
 x <- x + dx with K_E dx = -R(x) until ||R|| <= rtol ||R_0|| or ||R|| <= atol
 (Section 5.3). Here every Newton system is solved directly (oracle.direct,
-mean-zero pressure), so the iterates are those of exact Newton.
+mean-zero pressure), so the iterates are those of exact Newton. The force and
+its tangent see the links of X^n updated by the displacement's differences
+(Section 5.3), not differences of the absolute positions.
 """
 from __future__ import annotations
 
@@ -48,17 +50,28 @@ class Step:
         self.K0 = mac.reduced_operator(system.N, system.rho, system.mu, system.dt,
                                        sp.csr_matrix((2 * self.n2, 2 * self.n2)))
 
+    def displacement(self, x) -> np.ndarray:
+        """dt J^n u (interleaved)."""
+        return self.s.dt * (self.J @ x[:2 * self.n2])
+
     def configuration(self, x) -> np.ndarray:
         """X^n + dt J^n u (interleaved)."""
-        return self.Xn + self.s.dt * (self.J @ x[:2 * self.n2])
+        return self.Xn + self.displacement(x)
+
+    def links(self, x) -> np.ndarray:
+        """Links of the configuration, updated incrementally from those of X^n
+        (Section 5.3): D_k = D^n_k + (disp_{k+1} - disp_k)."""
+        Xn = self.Xn.reshape(-1, 2)
+        d = self.displacement(x).reshape(-1, 2)
+        return (Xn[1:] - Xn[:-1]) + (d[1:] - d[:-1])
 
     def residual(self, x, rhs) -> np.ndarray:
-        F = fibre.force(self.configuration(x), self.p)
+        F = fibre.force(self.configuration(x), self.p, D=self.links(x))
         SF = np.concatenate([self.S @ F, np.zeros(self.n2)])
         return self.K0 @ x - SF - rhs
 
     def jacobian(self, x) -> sp.csr_matrix:
-        E = fibre.tangent(self.configuration(x), self.p)
+        E = fibre.tangent(self.configuration(x), self.p, D=self.links(x))
         return mac.reduced_operator(self.N, self.s.rho, self.s.mu, self.s.dt, (self.S @ E @ self.J).tocsr())
 
 

@@ -48,7 +48,8 @@ class StructureDesc(C.Structure):
                 ("E_nnz", C.c_int32), ("E_rowptr", C.POINTER(C.c_int32)), ("E_col", C.POINTER(C.c_int32)),
                 ("E_val", C.POINTER(C.c_double)), ("K_p", C.c_double), ("K_t", C.c_double),
                 ("clamp_marker", C.c_int32), ("clamp_x", C.c_double), ("clamp_y", C.c_double),
-                ("X_force", C.POINTER(C.c_double))]
+                ("X_force", C.POINTER(C.c_double)), ("X_disp", C.POINTER(C.c_double)),
+                ("links", C.POINTER(C.c_double))]
 
 
 class NewtonOpts(C.Structure):
@@ -239,17 +240,27 @@ def _arr(a, ctype):
     return a.ctypes.data_as(C.POINTER(ctype)) if a is not None and a.size else None
 
 
-def structure_force(system, X_force=None) -> np.ndarray:
-    """Host force density of the fibre law at X_force (else at the markers),
-    interleaved 2M (cav_structure_force)."""
+def _fibre_config(d, X_force=None, X_disp=None, links=None):
+    """Set the fibre law's evaluation configuration on a StructureDesc; returns
+    the arrays the descriptor points into (keep them alive)."""
+    keep = []
+    for name, a in (("X_force", X_force), ("X_disp", X_disp), ("links", links)):
+        if a is not None:
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).ravel())
+            setattr(d, name, _arr(a, C.c_double))
+            keep.append(a)
+    return tuple(keep)
+
+
+def structure_force(system, X_force=None, X_disp=None, links=None) -> np.ndarray:
+    """Host force density of the fibre law, interleaved 2M (cav_structure_force):
+    at X_force, or at the markers displaced by X_disp with incrementally updated
+    links (from `links`, else the markers' differences), else at the markers."""
     d, keep = describe_structure(system)
-    xf = None
-    if X_force is not None:
-        xf = np.ascontiguousarray(np.asarray(X_force, dtype=np.float64).ravel())
-        d.X_force = _arr(xf, C.c_double)
+    keep = keep + _fibre_config(d, X_force, X_disp, links)
     F = np.zeros(2 * d.M, dtype=np.float64)
     st = lib().cav_structure_force(C.byref(d), _arr(F, C.c_double))
-    del keep, xf
+    del keep
     if st != 0:
         raise CAVError(st, "cav_structure_force failed")
     return F
@@ -293,10 +304,7 @@ class Analysis:
         self._L = lib()
         g = GridDesc(system.N, system.n_levels, system.rho, system.mu, system.dt)
         d, keep = describe_structure(system)
-        if X_force is not None:
-            xf = np.ascontiguousarray(np.asarray(X_force, dtype=np.float64).ravel())
-            d.X_force = _arr(xf, C.c_double)
-            keep = keep + (xf,)
+        keep = keep + _fibre_config(d, X_force)
         h = C.c_void_p()
         if family == "box":
             st = self._L.cav_analyze_box(C.byref(g), C.byref(d), int(box[0]), int(box[1]), C.byref(h))
@@ -521,18 +529,16 @@ class Solver:
             pass
 
     # ---- setup ----
-    def build_operator(self, system, X_force=None) -> None:
-        """Operator and hierarchy of `system`; X_force (fibre law only): positions
-        at which the energies' tangent is evaluated, J and S staying at the markers."""
+    def build_operator(self, system, X_force=None, X_disp=None, links=None) -> None:
+        """Operator and hierarchy of `system`; for the fibre law the energies'
+        tangent is evaluated at X_force, or at the markers displaced by X_disp
+        (links updated incrementally), J and S staying at the markers."""
         self._sync_stream()
         g = GridDesc(system.N, system.n_levels, system.rho, system.mu, system.dt)
         d, keep = describe_structure(system)
-        xf = None
-        if X_force is not None:
-            xf = np.ascontiguousarray(np.asarray(X_force, dtype=np.float64).ravel())
-            d.X_force = _arr(xf, C.c_double)
+        keep = keep + _fibre_config(d, X_force, X_disp, links)
         self._check(self._L.cav_build_operator(self._h, C.byref(g), C.byref(d)))
-        del keep, xf
+        del keep
         self.N, self.n_levels = system.N, system.n_levels
         self._ib_rows = 2 * d.M
 
@@ -567,8 +573,8 @@ class Solver:
         reaches it makes the next solve raise instead of hanging."""
         self._check(self._L.cav_set_wait_limit(self._h, int(polls)))
 
-    def set_phase_order(self, order: str = "explicit_first") -> None:
-        """Multiplicative sweep order: 'explicit_first' (default) or 'standard_first'."""
+    def set_phase_order(self, order: str = "standard_first") -> None:
+        """Multiplicative sweep order: 'standard_first' (default) or 'explicit_first'."""
         self._check(self._L.cav_set_phase_order(self._h, {"explicit_first": 0, "standard_first": 1}[order]))
 
     def set_level_smoother(self, level: int, kind: Optional[str], alpha: float = 0.7) -> None:

@@ -1988,6 +1988,7 @@ cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_struc
     stage = 1;
     cav_structure_desc d = *st;
     d.X_force = nullptr;
+    d.X_disp = nullptr;
     // J^n, S^n and the Stokes stencil at X^n (the operator itself is rebuilt per correction)
     call(cav_build_operator(ctx, g, &d));
     const int M = st->M;
@@ -2006,9 +2007,9 @@ cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_struc
     double* dpart = static_cast<double*>(alloc(size_t(nblk) * sizeof(double)));
     double* dnrm = static_cast<double*>(alloc(sizeof(double)));
     Xk.assign(2 * size_t(M), 0.0);
-    std::vector<double> U(2 * size_t(M)), Fh;
+    std::vector<double> U(2 * size_t(M)), disp(2 * size_t(M)), Fh;
     const std::vector<double> Xn(st->X, st->X + 2 * size_t(M));
-    std::vector<double> built = Xn;  // configuration of the operator the context holds
+    std::vector<double> built(2 * size_t(M), 0.0);  // displacement of the operator the context holds
     cav_fgmres_opts fo{};
     fo.rtol = o->lin_rtol;
     fo.max_it = o->lin_max_it;
@@ -2021,9 +2022,13 @@ cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_struc
         CAV_HIP(hipMemcpyAsync(U.data(), dU, U.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         CAV_HIP(hipStreamSynchronize(s));
       }
-      for (size_t k = 0; k < Xk.size(); ++k) Xk[k] = Xn[k] + g->dt * U[k];
+      // the energies see X^n displaced by dt J^n u_k, links updated incrementally
+      for (size_t k = 0; k < Xk.size(); ++k) {
+        disp[k] = g->dt * U[k];
+        Xk[k] = Xn[k] + disp[k];
+      }
       have_X = true;
-      d.X_force = Xk.data();
+      d.X_disp = disp.data();
       std::string err;
       const cav_status fs = fibre_force(&d, Fh, err);
       if (fs != CAV_OK) throw StatusError(fs, err);
@@ -2047,10 +2052,10 @@ cav_status cav_newton_solve(cav_ctx ctx, const cav_grid_desc* g, const cav_struc
       // the Newton system at X_k: hierarchy rebuilt with E = DF[X_k] (the
       // operator is kept when X_k is the configuration it was built at, as for
       // the first correction from rest)
-      if (Xk != built) {
+      if (disp != built) {
         stage = 1;
         call(cav_build_operator(ctx, g, &d));
-        built = Xk;
+        built = disp;
       }
       stage = 2;
       call(cav_build_cav_patches(ctx, o->family, nullptr));

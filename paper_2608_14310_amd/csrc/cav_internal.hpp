@@ -238,7 +238,7 @@ struct Ctx {
   int family = CAV_FAMILY_CAV;
   double alpha = 0.7;
   int pre = 1, post = 1;
-  bool std_first = false;  // multiplicative sweep: shared-patch colours before the explicit phases
+  bool std_first = true;   // multiplicative sweep: shared-patch colours before the explicit phases
   uint32_t wait_limit = 1u << 21;  // polls of a bounded workgroup-barrier wait before it gives up
   int smoother = CAV_SMOOTHER_ADDITIVE;
   // interpolation J and spreading S at the structure positions of the last

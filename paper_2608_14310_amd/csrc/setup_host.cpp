@@ -188,6 +188,38 @@ void segment_law(int law, double kt, double ks, double kb, int m0, int M, bool c
 // scattered onto the markers it involves; the stored pattern is every 2 x 2
 // block of markers at most two apart.
 namespace {
+// The configuration at which the fibre energies are evaluated: positions Xe
+// (2M) and links D (2(M-1)). With a displacement the links are updated
+// incrementally (Section 5.3), D_k = D_k^0 + (disp_{k+1} - disp_k), where D^0
+// is the caller's carried links or else X_{k+1} - X_k: on a nearly straight
+// fibre the cross products of the bending term are far below the positions'
+// rounding, so differences of absolute positions would lose them.
+cav_status fibre_configuration(const cav_structure_desc* st, int M, std::vector<double>& Xe,
+                               std::vector<double>& D, std::string& err) {
+  const size_t nx = 2 * size_t(M), nd = 2 * size_t(M - 1);
+  auto finite = [&](const double* a, size_t n, const char* what) {
+    for (size_t k = 0; k < n; ++k)
+      if (!std::isfinite(a[k])) { err = what; return false; }
+    return true;
+  };
+  if (st->X_force && !finite(st->X_force, nx, "non-finite X_force")) return CAV_ERR_INVALID_ARG;
+  if (st->X_disp && !finite(st->X_disp, nx, "non-finite X_disp")) return CAV_ERR_INVALID_ARG;
+  if (st->links && !finite(st->links, nd, "non-finite links")) return CAV_ERR_INVALID_ARG;
+  const double* X0 = (st->X_force && !st->X_disp) ? st->X_force : st->X;
+  Xe.assign(X0, X0 + nx);
+  D.resize(nd);
+  for (int k = 0; k + 1 < M; ++k)
+    for (int c = 0; c < 2; ++c)
+      D[2 * k + c] = (st->links && X0 == st->X) ? st->links[2 * k + c] : X0[2 * (k + 1) + c] - X0[2 * k + c];
+  if (st->X_disp) {
+    const double* u = st->X_disp;
+    for (size_t k = 0; k < nx; ++k) Xe[k] += u[k];
+    for (int k = 0; k + 1 < M; ++k)
+      for (int c = 0; c < 2; ++c) D[2 * k + c] += u[2 * (k + 1) + c] - u[2 * k + c];
+  }
+  return CAV_OK;
+}
+
 cav_status fibre_law(const cav_structure_desc* st, Structure& s, std::string& err) {
   const int M = s.M;
   if (st->n_segments != 1 || !st->seg_start || !st->seg_closed || !st->seg_ds) {
@@ -203,16 +235,14 @@ cav_status fibre_law(const cav_structure_desc* st, Structure& s, std::string& er
   const double EI = st->kappa_b, Ks = st->kappa_s, Kp = st->K_p, Kt = st->K_t;
   for (double v : {EI, Ks, Kp, Kt, st->clamp_x, st->clamp_y})
     if (!std::isfinite(v)) { err = "non-finite fibre parameter"; return CAV_ERR_INVALID_ARG; }
-  if (st->X_force)
-    for (int64_t k = 0; k < 2 * int64_t(M); ++k)
-      if (!std::isfinite(st->X_force[k])) { err = "non-finite X_force"; return CAV_ERR_INVALID_ARG; }
+  std::vector<double> Xe, D;
+  if (const cav_status v = fibre_configuration(st, M, Xe, D, err); v != CAV_OK) return v;
   // band storage: B[i][d][a][b] = Hess(U) block (marker i, marker i+d-2), d in 0..4
   std::vector<double> B(size_t(M) * 5 * 4, 0.0);
   auto blk = [&](int i, int j, int a, int b) -> double& {
     return B[((size_t(i) * 5 + size_t(j - i + 2)) * 2 + a) * 2 + b];
   };
-  const double* X = st->X_force ? st->X_force : s.X.data();
-  auto link = [&](int k, int c) { return X[2 * (k + 1) + c] - X[2 * k + c]; };
+  auto link = [&](int k, int c) { return D[2 * k + c]; };
   // stretching: U_k = Ks/(2ds) (|d|-ds)^2 with d = X_{k+1} - X_k;
   // d2U_k/dd2 = (Ks/ds) [ (1 - ds/|d|) I + ds d d^T / |d|^3 ]
   for (int k = 0; k + 1 < M; ++k) {
@@ -280,8 +310,8 @@ cav_status fibre_law(const cav_structure_desc* st, Structure& s, std::string& er
 }  // namespace
 
 // Force density of the clamped fibre, F = -(1/ds) grad(U) (Section 5.3), at
-// X_force when given, else at X: each term's gradient in its own variables
-// (links, clamp coordinates), scattered onto the markers it involves.
+// the configuration fibre_configuration forms: each term's gradient in its own
+// variables (links, clamp coordinates), scattered onto the markers it involves.
 cav_status fibre_force(const cav_structure_desc* st, std::vector<double>& F, std::string& err) {
   Structure s;
   const cav_status v = make_structure(st, s, err);  // validates the descriptor and the parameters
@@ -290,8 +320,9 @@ cav_status fibre_force(const cav_structure_desc* st, std::vector<double>& F, std
   const int M = s.M, m = st->clamp_marker;
   const double ds = st->seg_ds[0];
   const double EI = st->kappa_b, Ks = st->kappa_s, Kp = st->K_p, Kt = st->K_t;
-  const double* X = st->X_force ? st->X_force : s.X.data();
-  auto link = [&](int k, int c) { return X[2 * (k + 1) + c] - X[2 * k + c]; };
+  std::vector<double> X, D;
+  if (const cav_status c = fibre_configuration(st, M, X, D, err); c != CAV_OK) return c;
+  auto link = [&](int k, int c) { return D[2 * k + c]; };
   std::vector<double> G(2 * size_t(M), 0.0);  // grad(U)
   // stretching: dU_k/dd = Ks/ds (|d| - ds) d/|d|, d = X_{k+1} - X_k
   for (int k = 0; k + 1 < M; ++k) {
@@ -316,11 +347,12 @@ cav_status fibre_force(const cav_structure_desc* st, std::vector<double>& F, std
     G[2 * (k + 2)] += gq0;
     G[2 * (k + 2) + 1] += gq1;
   }
-  // clamp: position penalty on marker m, tangent penalty on the central difference
+  // clamp: position penalty on marker m, tangent penalty on the central
+  // difference X_{m+1} - X_{m-1} = D_{m-1} + D_m
   G[2 * m] += Kp * (X[2 * m] - st->clamp_x);
   G[2 * m + 1] += Kp * (X[2 * m + 1] - st->clamp_y);
-  const double t0 = (X[2 * (m + 1)] - X[2 * (m - 1)]) / (2.0 * ds) - 1.0;
-  const double t1 = (X[2 * (m + 1) + 1] - X[2 * (m - 1) + 1]) / (2.0 * ds);
+  const double t0 = (link(m - 1, 0) + link(m, 0)) / (2.0 * ds) - 1.0;
+  const double t1 = (link(m - 1, 1) + link(m, 1)) / (2.0 * ds);
   const double wt = Kt / (2.0 * ds);
   G[2 * (m + 1)] += wt * t0;
   G[2 * (m + 1) + 1] += wt * t1;

@@ -146,8 +146,10 @@ def test_error_paths(cav):
 
 def test_full_size_beam512(cav):
     """The benchmark's configuration, checked at full size: finest-level E_E
-    and patch sets exactly, K x, and the GPU solution's true residual measured
-    with the oracle's K_E (mixed precision, the faster of the two forms)."""
+    and patch sets exactly, K x, the mixed-precision solution's true residual
+    measured with the oracle's K_E, and bit-identical V-cycles and solves from
+    every phase-kernel form. (The FP64 solve against the oracle's iteration
+    count and solution is in test_gpu_golden.py.)"""
     s = workloads.beam_512(1e-2)
     print("[full size] beam512: oracle E_E and patches", flush=True)
     EE, pattern = ib.eulerian_elasticity(s)
@@ -171,22 +173,24 @@ def test_full_size_beam512(cav):
     y = g.apply_operator(_t(xr)).cpu().numpy()
     assert np.abs(y - K @ xr).max() <= 1e-13 * np.abs(K @ xr).max()
     x, inf = g.fgmres_solve(_t(s.b), 1e-10, 150)
-    assert inf["converged"] and inf["iterations"] == 28
+    print(f"[full size] beam512 mixed: {inf['iterations']} iterations", flush=True)
+    assert inf["converged"]
     xg = x.cpu().numpy()
     assert np.linalg.norm(s.b - K @ xg) <= 2e-10 * np.linalg.norm(s.b)
     # the cooperative phase forms (large patches spread over several
-    # workgroups) give the same V-cycle bit for bit at this size
+    # workgroups) and the dataflow sweep give the same V-cycle bit for bit at
+    # this size
     print("[full size] beam512: cooperative phase forms", flush=True)
     z0 = g.vcycle(_t(s.b)).cpu().numpy()
-    for form in (1, 2, 3):
+    for form, sweep in ((1, 0), (2, 0), (3, 0), (3, 2)):
         table = np.full((s.n_levels, 5), 1024, np.int32)
-        table[:, 4] = 0
+        table[:, 4] = sweep
         table[:, 2:4] = form
         g.set_tuning(table)
         np.testing.assert_array_equal(g.vcycle(_t(s.b)).cpu().numpy(), z0)
     x2, inf2 = g.fgmres_solve(_t(s.b), 1e-10, 150)
     g.close()
-    assert inf2["iterations"] == 28
+    assert inf2["iterations"] == inf["iterations"]
     np.testing.assert_array_equal(x2.cpu().numpy(), xg)
 
 

@@ -217,3 +217,35 @@ def test_fibre_tangent_at_x_force_matches_oracle():
         a0.close()
     G0 = sp.csr_matrix((val0, col0, rp0), shape=(n, n))
     assert abs(G0 - G).max() > 1e-6 * abs(ref).max()
+
+
+def test_fibre_force_with_incremental_links():
+    """The library's force at X + X_disp forms the links incrementally
+    (Section 5.3): on a nearly straight fibre at 256^2 it agrees with an
+    extended-precision evaluation to about 1e-12 of its size, where the
+    absolute-position form (X_force = X + X_disp) loses two more digits; carried
+    links equal to the markers' differences give the same force, and the
+    oracle's incremental force agrees."""
+    import dataclasses
+    import fibre_extended
+    from oracle import fibre, newton
+    from paper_2608_14310_amd import structure_force
+    s0 = workloads.flexible_fibre(256, 2)
+    p = newton.fibre_params(s0)
+    Xn, disp = fibre_extended.straight_fibre_step(s0)
+    seg = dataclasses.replace(s0.segments[0], X=Xn.reshape(-1, 2))
+    s = dataclasses.replace(s0, segments=[seg])
+    ref = fibre_extended.force(Xn, disp, p)
+    scale = np.abs(ref).max()
+    F = structure_force(s, X_disp=disp)
+    assert np.abs(F - ref).max() <= 5e-12 * scale
+    Fa = structure_force(s, X_force=Xn + disp)
+    assert np.abs(Fa - ref).max() >= 20 * np.abs(F - ref).max()
+    X2 = Xn.reshape(-1, 2)
+    Fl = structure_force(s, X_disp=disp, links=(X2[1:] - X2[:-1]).ravel())
+    assert np.array_equal(Fl, F)
+    d2 = disp.reshape(-1, 2)
+    Fo = fibre.force(Xn + disp, p, D=(X2[1:] - X2[:-1]) + (d2[1:] - d2[:-1]))
+    assert np.abs(F - Fo).max() <= 1e-12 * scale
+    with pytest.raises(Exception):
+        structure_force(s, X_disp=np.full_like(disp, np.nan))
