@@ -220,9 +220,9 @@ def additive_leg(dev, reps: int = 10, membrane: bool = True):
            "vcycle_ms": round(kt["vcycle_ms"], 4), "vcycles_per_s": round(1e3 / kt["vcycle_ms"], 1),
            "vcycle_bytes": int(bv), "vcycle_gbs": round(bv / (kt["vcycle_ms"] * 1e-3) / 1e9, 1),
            "vcycle_frac": round(bv / (kt["vcycle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-           "k_patch_apply": {"bound": "hbm", "achieved": round(pa_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "k_add_smooth": {"bound": "hbm", "achieved": round(pa_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(pa_gbs / HBM_PEAK_GBS, 4),
-                             "traffic": measured_traffic("k_patch_apply", "fp64", "additive", "default"),
+                             "traffic": measured_traffic("k_add_smooth", "fp64", "additive", "default"),
                              "launches": pa_launch,
                              "bytes_per_launch": int(pa_bytes / max(pa_launch, 1)),
                              "avg_launch_us": round(1e3 * pa_ms / max(pa_launch, 1), 3)}}
@@ -651,7 +651,7 @@ def main():
                     help="grids of the flexible-fibre context leg (Table 3, e.g. 32 64 128 256; default: skip)")
     ap.add_argument("--no-additive", action="store_true", help="skip the weighted additive smoother leg")
     ap.add_argument("--additive-only", action="store_true",
-                    help="run only the additive V-cycles on the 512^2 beam (for profiling k_patch_apply), then exit")
+                    help="run only the additive V-cycles on the 512^2 beam (for profiling k_add_smooth), then exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, help="run only a plain copy of this many bytes")
@@ -762,7 +762,7 @@ def main():
         kb_ms = co_ms - sh_ms
         kb_launch = sum(r["kt"]["coop_launches"] - r["kt"]["shared_launches"] for r in runs)
     else:
-        kernel = "k_mult_exp" if a.smoother == "multiplicative" else "k_patch_apply"
+        kernel = "k_mult_exp" if a.smoother == "multiplicative" else "k_add_smooth"
         kb_bytes = sum(r["kt"]["bytes"] - r["kt"]["coop_bytes"] - r["kt"]["flow_bytes"] for r in runs)
         kb_ms = all_ms - co_ms - fl_ms
         kb_launch = sum(r["kt"]["launches"] - r["kt"]["coop_launches"] - r["kt"]["flow_launches"] for r in runs)

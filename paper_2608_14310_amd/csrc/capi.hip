@@ -298,18 +298,13 @@ __global__ void k_ib_spread(int32_t nf, const int32_t* __restrict__ face, const 
   y[face[q]] += acc;
 }
 
+void free_patches(Ctx& c, Level& L);
+
 void free_level(Ctx& c, Level& L) {
-  if (L.fpending) {
-    factor_level_release(c, L.fpend);
-    L.fpending = false;
-  }
+  free_patches(c, L);  // every patch-level block, the dataflow tables included
   for (void* p : {(void*)L.d_erow_id, (void*)L.d_erow_ptr, (void*)L.d_ecol, (void*)L.d_eval, (void*)L.d_erow_full,
-                  (void*)L.d_cellflag, (void*)L.d_slot_dof, (void*)L.d_delta, (void*)L.d_t_dof, (void*)L.d_t_inv,
-                  (void*)L.d_t_ptr, (void*)L.d_t_slot, (void*)L.d_std_inv, (void*)L.d_rec64, (void*)L.d_rec32,
-                  (void*)L.d_f64, (void*)L.d_f32, (void*)L.d_b, (void*)L.d_x, (void*)L.d_r, (void*)L.d_z,
-                  (void*)L.d_part, (void*)L.d_mrec, (void*)L.d_wrk, (void*)L.d_ph_ptr, (void*)L.d_slot_mask,
-                  (void*)L.d_citem[0], (void*)L.d_citem[1], (void*)L.d_pcnt,
-                  (void*)L.d_slot_q, (void*)L.d_irow, (void*)L.d_mb, (void*)L.d_mx, (void*)L.d_mr})
+                  (void*)L.d_emask, (void*)L.d_b, (void*)L.d_x, (void*)L.d_r, (void*)L.d_z, (void*)L.d_part,
+                  (void*)L.d_mb, (void*)L.d_mx, (void*)L.d_mr})
     dev_free(c, p);
   L = Level();
 }
@@ -337,7 +332,11 @@ void free_patches(Ctx& c, Level& L) {
   L.factored = false;
 }
 
-void vcycle_level(Ctx& c, int l, const double* b, double* x) {
+// The pressure mean is removed once per cycle, at its end on the top level:
+// K_E, the smoothers' residuals and the transfers do not see a constant
+// pressure (G annihilates it and prolongation keeps means), so the means the
+// other smoothing steps and levels leave change nothing else.
+void vcycle_level(Ctx& c, int l, const double* b, double* x, bool top = true) {
   hipStream_t s = c.stream;
   if (l == 0) {
     launch_coarse_solve(c, b, x, s);
@@ -346,13 +345,14 @@ void vcycle_level(Ctx& c, int l, const double* b, double* x) {
   Level& L = c.lv[l];
   const int64_t n = 3 * int64_t(L.N) * L.N;
   if (c.pre == 0) launch_fill(x, 0.0, n, s);
-  for (int k = 0; k < c.pre; ++k) launch_smoother(c, L, b, x, k == 0, s);
+  for (int k = 0; k < c.pre; ++k) launch_smoother(c, L, b, x, k == 0, s, false);
   Level& C = c.lv[l - 1];
   launch_apply_op(L, x, L.d_r, b, s);  // r = b - K x
   launch_restrict(L, L.d_r, C.d_b, s);
-  vcycle_level(c, l - 1, C.d_b, C.d_x);
+  vcycle_level(c, l - 1, C.d_b, C.d_x, false);
   launch_prolong_add(L, C.d_x, x, s);
-  for (int k = 0; k < c.post; ++k) launch_smoother(c, L, b, x, false, s);
+  for (int k = 0; k < c.post; ++k) launch_smoother(c, L, b, x, false, s, top && k + 1 == c.post);
+  if (top && c.post == 0) launch_pressure_mean_remove(x, L.N, L.d_part, s);
 }
 
 // The V-cycle on kb <= 16 right-hand sides at once (columns of b and x with
@@ -360,7 +360,7 @@ void vcycle_level(Ctx& c, int l, const double* b, double* x) {
 // with the explicit-patch phases of the multiplicative smoother applied to all
 // columns in one launch (one read of each stored inverse per phase).
 constexpr int MR_COLS = 16;
-void vcycle_level_multi(Ctx& c, int l, const double* b, double* x, int kb) {
+void vcycle_level_multi(Ctx& c, int l, const double* b, double* x, int kb, bool top = true) {
   hipStream_t s = c.stream;
   const int64_t n = 3 * int64_t(c.lv[l].N) * c.lv[l].N;
   if (l == 0) {
@@ -370,16 +370,18 @@ void vcycle_level_multi(Ctx& c, int l, const double* b, double* x, int kb) {
   Level& L = c.lv[l];
   if (c.pre == 0)
     for (int q = 0; q < kb; ++q) launch_fill(x + q * n, 0.0, n, s);
-  for (int k = 0; k < c.pre; ++k) launch_smoother_multi(c, L, b, x, n, kb, k == 0, s);
+  for (int k = 0; k < c.pre; ++k) launch_smoother_multi(c, L, b, x, n, kb, k == 0, s, false);
   Level& C = c.lv[l - 1];
   const int64_t nc = 3 * int64_t(C.N) * C.N;
   for (int q = 0; q < kb; ++q) {
     launch_apply_op(L, x + q * n, L.d_mr + q * n, b + q * n, s);  // r = b - K x
     launch_restrict(L, L.d_mr + q * n, C.d_mb + q * nc, s);
   }
-  vcycle_level_multi(c, l - 1, C.d_mb, C.d_mx, kb);
+  vcycle_level_multi(c, l - 1, C.d_mb, C.d_mx, kb, false);
   for (int q = 0; q < kb; ++q) launch_prolong_add(L, C.d_mx + q * nc, x + q * n, s);
-  for (int k = 0; k < c.post; ++k) launch_smoother_multi(c, L, b, x, n, kb, false, s);
+  for (int k = 0; k < c.post; ++k) launch_smoother_multi(c, L, b, x, n, kb, false, s, top && k + 1 == c.post);
+  if (top && c.post == 0)
+    for (int q = 0; q < kb; ++q) launch_pressure_mean_remove(x + q * n, L.N, L.d_part, s);
 }
 
 void ensure_multi_workspace(Ctx& c) {
@@ -1006,6 +1008,13 @@ cav_status cav_build_operator(cav_ctx ctx, const cav_grid_desc* g, const cav_str
     std::vector<double> sval(E.val.size());
     for (size_t k = 0; k < sval.size(); ++k) sval[k] = -c.dt * E.val[k];
     lev.n_erows = int32_t(rid.size());
+    {
+      // bit 0 / bit 1: the cell's u / v row has E_E entries
+      const int64_t n2 = int64_t(lev.N) * lev.N;
+      std::vector<uint8_t> mask(size_t(n2), 0);
+      for (int32_t r : rid) mask[size_t(r % n2)] |= uint8_t(r < n2 ? 1 : 2);
+      lev.d_emask = upload(c, mask);
+    }
     lev.d_erow_id = upload(c, rid);
     lev.d_erow_ptr = upload(c, rptr);
     lev.d_ecol = upload(c, E.col);

@@ -71,6 +71,7 @@ struct Level {
   // device: compressed rows of -dt * E_E for the operator apply
   int32_t n_erows = 0;
   int32_t* d_erow_id = nullptr;   // velocity unknown of each compressed row
+  uint8_t* d_emask = nullptr;     // per cell: bit 0 / bit 1 = its u / v row has E_E entries
   int32_t* d_erow_ptr = nullptr;  // n_erows + 1
   int32_t* d_ecol = nullptr;
   double* d_eval = nullptr;       // -dt * E_E
@@ -79,7 +80,7 @@ struct Level {
 
   // patches (levels >= 1)
   bool has_patches = false;
-  std::vector<uint8_t> cellflag;           // bit0 explicit seed, bit1 covered
+  std::vector<uint8_t> cellflag;           // bit0 explicit seed, bit1 covered, bits 2/3/4: the cell's u/v/p is touched
   std::vector<int64_t> patch_off;          // all patches (N^2 + 1), for export
   std::vector<int32_t> patch_dofs;
   std::vector<int32_t> exp_cells;          // explicit patch -> seed cell
@@ -357,10 +358,15 @@ void launch_apply_op(const Level& L, const double* x, double* y, const double* b
 void launch_stencil(const StencilCoef& sc, const double* x, double* y, const double* b, hipStream_t s);
 void launch_restrict(const Level& Lf, const double* rf, double* bc, hipStream_t s);
 void launch_prolong_add(const Level& Lf, const double* xc, double* xf, hipStream_t s);
-void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
-void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s);
+// remove_mean = false leaves the pressure mean of the result in place: the
+// V-cycle skips it on every smoothing step but the level's last, since K_E
+// does not see a constant pressure and the last step removes the whole mean.
+void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s,
+                     bool remove_mean = true);
+void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s,
+                          bool remove_mean = true);
 void launch_smoother_multi(Ctx& c, Level& L, const double* b, double* x, int64_t ldv, int kb, bool zero_guess,
-                           hipStream_t s);
+                           hipStream_t s, bool remove_mean = true);
 void prepare_mult_smoother(size_t lds);
 // the whole multiplicative sweep of level L in one cooperative launch; false if not possible
 bool launch_mult_sweep(Ctx& c, Level& L, const double* b, double* x, hipStream_t s);

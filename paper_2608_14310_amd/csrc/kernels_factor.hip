@@ -611,20 +611,43 @@ __global__ __launch_bounds__(256) void k_cq_meanfix(double* __restrict__ W, int 
     for (int a = p0 + w; a < n; a += 4) W[int64_t(a) * n + j] -= mean;
 }
 
-// y[i] = sum_k W[i][k] b[k] (one wavefront per row).
+// y[i] = sum_k W[i][k] b[k] for the dense coarsest solution operator
+// (row-major n x n). Each wavefront takes CG_ROWS rows; a lane strides the
+// columns with four independent loads per row in flight (b comes through the
+// cache), then a wavefront reduction adds the lanes.
+constexpr int CG_ROWS = 2;
 __global__ __launch_bounds__(256) void k_coarse_gemv(const double* __restrict__ W, int n, const double* __restrict__ b,
                                                      double* __restrict__ y) {
-  extern __shared__ double xb[];
-  for (int k = threadIdx.x; k < n; k += 256) xb[k] = b[k];
-  __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n) return;
-  const double* Wr = W + int64_t(row) * n;
-  double acc = 0.0;
-  for (int k = lane; k < n; k += 64) acc += Wr[k] * xb[k];
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-  if (lane == 0) y[row] = acc;
+  const int row0 = (int(blockIdx.x) * 4 + int(threadIdx.x >> 6)) * CG_ROWS;
+  if (row0 >= n) return;  // whole wavefront
+  const double* Wr[CG_ROWS];
+#pragma unroll
+  for (int q = 0; q < CG_ROWS; ++q) Wr[q] = W + int64_t(min(row0 + q, n - 1)) * n;
+  double acc[CG_ROWS][4];
+#pragma unroll
+  for (int q = 0; q < CG_ROWS; ++q)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[q][u] = 0.0;
+  int k = lane;
+  for (; k + 192 < n; k += 256) {
+    const double bb[4] = {b[k], b[k + 64], b[k + 128], b[k + 192]};
+#pragma unroll
+    for (int q = 0; q < CG_ROWS; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[q][u] += Wr[q][k + 64 * u] * bb[u];
+  }
+  for (; k < n; k += 64) {
+    const double bk = b[k];
+#pragma unroll
+    for (int q = 0; q < CG_ROWS; ++q) acc[q][0] += Wr[q][k] * bk;
+  }
+#pragma unroll
+  for (int q = 0; q < CG_ROWS; ++q) {
+    double t = (acc[q][0] + acc[q][2]) + (acc[q][1] + acc[q][3]);
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_down(t, o, 64);
+    if (lane == 0 && row0 + q < n) y[row0 + q] = t;
+  }
 }
 
 inline unsigned nblk(int64_t n, int t = 256) { return unsigned((n + t - 1) / t); }
@@ -1030,7 +1053,7 @@ void factor_coarse_finish(Ctx& c, CoarsePending& cp, hipStream_t s) {
 
 void launch_coarse_solve(const Ctx& c, const double* b, double* x, hipStream_t s) {
   const int n = c.nc;
-  k_coarse_gemv<<<nblk(n, 4), 256, size_t(n) * sizeof(double), s>>>(c.d_cinv, n, b, x);
+  k_coarse_gemv<<<nblk(n, 4 * CG_ROWS), 256, 0, s>>>(c.d_cinv, n, b, x);
 }
 
 }  // namespace cav

@@ -11,52 +11,86 @@ constexpr int TPB = 256;
 
 __device__ __forceinline__ int wrapi(int a, int N) { return a & (N - 1); }  // N is a power of two
 
-// y = K x (stencil part) or r = b - K x when b != nullptr. One thread per cell
-// computes u_ij, v_ij and p_ij rows (Eq. intro_saddle):
+// Stencil rows of K (Eq. intro_saddle) at cell (i, j):
 //   (A0 u)_ij = diag u_ij - off (u_{i+-1,j} + u_{i,j+-1}),  (G p)_{u_ij} = (p_ij - p_{i-1,j})/h,
 //   (-D u)_ij = -(u_{i+1,j} - u_ij + v_{i,j+1} - v_ij)/h.
-__global__ __launch_bounds__(TPB) void k_apply_stencil(StencilCoef sc, const double* __restrict__ x,
-                                                       double* __restrict__ y, const double* __restrict__ b) {
+// Every thread that writes a u or v row evaluates it with these functions.
+__device__ __forceinline__ double stencil_u_row(const StencilCoef& sc, const double* __restrict__ x, int i, int j) {
   const int N = sc.N;
   const int64_t n2 = int64_t(N) * N;
-  const int64_t c = int64_t(blockIdx.x) * TPB + threadIdx.x;
-  if (c >= n2) return;
-  const int i = int(c / N), j = int(c % N);
-  const int ip = wrapi(i + 1, N), im = wrapi(i - 1, N), jp = wrapi(j + 1, N), jm = wrapi(j - 1, N);
   const double* u = x;
-  const double* v = x + n2;
   const double* p = x + 2 * n2;
-  const double uc = u[c], vc = v[c], pc = p[c];
-  const double u_ip = u[int64_t(ip) * N + j], u_im = u[int64_t(im) * N + j];
-  const double u_jp = u[int64_t(i) * N + jp], u_jm = u[int64_t(i) * N + jm];
-  const double v_ip = v[int64_t(ip) * N + j], v_im = v[int64_t(im) * N + j];
-  const double v_jp = v[int64_t(i) * N + jp], v_jm = v[int64_t(i) * N + jm];
-  const double p_im = p[int64_t(im) * N + j], p_jm = p[int64_t(i) * N + jm];
-  const double au = sc.diag * uc - sc.off * (u_ip + u_im + u_jp + u_jm) + sc.invh * (pc - p_im);
-  const double av = sc.diag * vc - sc.off * (v_ip + v_im + v_jp + v_jm) + sc.invh * (pc - p_jm);
-  const double ap = -sc.invh * ((u_ip - uc) + (v_jp - vc));
-  if (b) {
-    y[c] = b[c] - au;
-    y[n2 + c] = b[n2 + c] - av;
-    y[2 * n2 + c] = b[2 * n2 + c] - ap;
-  } else {
-    y[c] = au;
-    y[n2 + c] = av;
-    y[2 * n2 + c] = ap;
-  }
+  const int ip = wrapi(i + 1, N), im = wrapi(i - 1, N), jp = wrapi(j + 1, N), jm = wrapi(j - 1, N);
+  const int64_t c = int64_t(i) * N + j;
+  return sc.diag * u[c] - sc.off * (u[int64_t(ip) * N + j] + u[int64_t(im) * N + j] + u[int64_t(i) * N + jp] +
+                                    u[int64_t(i) * N + jm]) +
+         sc.invh * (p[c] - p[int64_t(im) * N + j]);
 }
 
-// Rows of -dt E_E: y[row] += sum val x (apply) or y[row] -= sum val x (residual).
-// One thread per compressed row, summing in column order.
-__global__ __launch_bounds__(TPB) void k_ee_rows(int nrows, const int32_t* __restrict__ rid,
-                                                 const int32_t* __restrict__ rptr, const int32_t* __restrict__ col,
-                                                 const double* __restrict__ val, const double* __restrict__ x,
-                                                 double* __restrict__ y, double sign) {
-  const int t = blockIdx.x * TPB + threadIdx.x;
-  if (t >= nrows) return;
+__device__ __forceinline__ double stencil_v_row(const StencilCoef& sc, const double* __restrict__ x, int i, int j) {
+  const int N = sc.N;
+  const int64_t n2 = int64_t(N) * N;
+  const double* v = x + n2;
+  const double* p = x + 2 * n2;
+  const int ip = wrapi(i + 1, N), im = wrapi(i - 1, N), jp = wrapi(j + 1, N), jm = wrapi(j - 1, N);
+  const int64_t c = int64_t(i) * N + j;
+  return sc.diag * v[c] - sc.off * (v[int64_t(ip) * N + j] + v[int64_t(im) * N + j] + v[int64_t(i) * N + jp] +
+                                    v[int64_t(i) * N + jm]) +
+         sc.invh * (p[c] - p[int64_t(i) * N + jm]);
+}
+
+// y = K x (b == nullptr) or r = b - K x in one launch. Blocks [0, ncb) take
+// one cell per thread and write its p row and each of its u / v rows without
+// E_E entries (emask bit 0 / bit 1 clear). The blocks after them take one
+// compressed E_E row (of -dt E_E) per EE_LANES lanes, never straddling a
+// wavefront: lane l sums the row's entries l, l + EE_LANES, ... in column
+// order, an xor tree adds the partial sums (one chain of dependent loads per
+// row, a fixed order), and lane 0 writes the whole row, its stencil part plus
+// that sum. Every row is written by exactly one thread.
+constexpr int EE_LANES = 16;
+__global__ __launch_bounds__(TPB) void k_apply_op(StencilCoef sc, int ncb, const uint8_t* __restrict__ emask,
+                                                  int nrows, const int32_t* __restrict__ rid,
+                                                  const int32_t* __restrict__ rptr, const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val, const double* __restrict__ x,
+                                                  double* __restrict__ y, const double* __restrict__ b) {
+  const int N = sc.N;
+  const int64_t n2 = int64_t(N) * N;
+  if (int(blockIdx.x) < ncb) {
+    const int64_t c = int64_t(blockIdx.x) * TPB + threadIdx.x;
+    if (c >= n2) return;
+    const int i = int(c / N), j = int(c % N);
+    const int ip = wrapi(i + 1, N), jp = wrapi(j + 1, N);
+    const double* u = x;
+    const double* v = x + n2;
+    const uint8_t m = emask ? emask[c] : uint8_t(0);
+    const double ap = -sc.invh * ((u[int64_t(ip) * N + j] - u[c]) + (v[int64_t(i) * N + jp] - v[c]));
+    if (!(m & 1)) {
+      const double au = stencil_u_row(sc, x, i, j);
+      y[c] = b ? b[c] - au : au;
+    }
+    if (!(m & 2)) {
+      const double av = stencil_v_row(sc, x, i, j);
+      y[n2 + c] = b ? b[n2 + c] - av : av;
+    }
+    y[2 * n2 + c] = b ? b[2 * n2 + c] - ap : ap;
+    return;
+  }
+  const int64_t g = int64_t(blockIdx.x - ncb) * TPB + threadIdx.x;
+  const int64_t t = g / EE_LANES;
+  const int l = int(g % EE_LANES);
   double acc = 0.0;
-  for (int q = rptr[t]; q < rptr[t + 1]; ++q) acc += val[q] * x[col[q]];
-  y[rid[t]] += sign * acc;
+  if (t < nrows)
+    for (int q = rptr[t] + l; q < rptr[t + 1]; q += EE_LANES) acc += val[q] * x[col[q]];
+#pragma unroll
+  for (int o = EE_LANES / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, EE_LANES);
+  if (t < nrows && l == 0) {
+    const int32_t r = rid[t];
+    const bool is_v = r >= n2;
+    const int64_t c = is_v ? r - n2 : r;
+    const int i = int(c / N), j = int(c % N);
+    const double st = is_v ? stencil_v_row(sc, x, i, j) : stencil_u_row(sc, x, i, j);
+    y[r] = b ? (b[r] - st) - acc : st + acc;
+  }
 }
 
 // Restriction to the coarse grid (Section 4): velocity R = P^T / 4 of the RT0
@@ -189,14 +223,15 @@ int dots_blocks(int64_t n) {
 
 void launch_apply_op(const Level& L, const double* x, double* y, const double* b, hipStream_t s) {
   const int64_t n2 = int64_t(L.N) * L.N;
-  k_apply_stencil<<<nblocks(n2), TPB, 0, s>>>(L.sc, x, y, b);
-  if (L.n_erows > 0)
-    k_ee_rows<<<nblocks(L.n_erows), TPB, 0, s>>>(L.n_erows, L.d_erow_id, L.d_erow_ptr, L.d_ecol, L.d_eval, x, y,
-                                                 b ? -1.0 : 1.0);
+  const int ncb = int(nblocks(n2));
+  const unsigned grid = unsigned(ncb) + (L.n_erows > 0 ? nblocks(int64_t(L.n_erows) * EE_LANES) : 0u);
+  k_apply_op<<<grid, TPB, 0, s>>>(L.sc, ncb, L.n_erows > 0 ? L.d_emask : nullptr, L.n_erows, L.d_erow_id,
+                                  L.d_erow_ptr, L.d_ecol, L.d_eval, x, y, b);
 }
 
 void launch_stencil(const StencilCoef& sc, const double* x, double* y, const double* b, hipStream_t s) {
-  k_apply_stencil<<<nblocks(int64_t(sc.N) * sc.N), TPB, 0, s>>>(sc, x, y, b);
+  const int ncb = int(nblocks(int64_t(sc.N) * sc.N));
+  k_apply_op<<<unsigned(ncb), TPB, 0, s>>>(sc, ncb, nullptr, 0, nullptr, nullptr, nullptr, nullptr, x, y, b);
 }
 
 void launch_restrict(const Level& Lf, const double* rf, double* bc, hipStream_t s) {

@@ -2,14 +2,15 @@
 //   w <- w + alpha * sum_p R_p^T Theta_p K_p^{-1} R_p r,  Theta_p = diag(1/cnt),
 // then mean-pressure removal (Section 3.3).
 //
-// Work split on the GPU:
-//  * patches without E_E entries are the standard Vanka patch and share one
-//    5x5 inverse per level; their contribution is evaluated on the fly, per
-//    unknown, by a grid kernel (no storage);
-//  * explicit patches (own inverse) run a gather -> GEMV -> per-slot delta
-//    kernel, bucketed by size, FP64 or FP32 factors;
-//  * unknowns inside an explicit patch ("touched") pull their slot deltas in a
-//    fixed order and apply 1/cnt. Every sum has a fixed order (no atomics).
+// Work split on the GPU, two launches per sweep:
+//  * k_add_smooth: explicit patches (own inverse, FP64 or FP32) gather their
+//    residual, apply the stored inverse and write one delta per slot; in the
+//    same launch, patches without E_E entries (the standard Vanka patch, one
+//    shared 5x5 inverse per level) are evaluated on the fly per cell, and
+//    unknowns outside every explicit patch are updated there;
+//  * k_touched: unknowns inside an explicit patch pull their slot deltas in a
+//    fixed order, apply 1/cnt and are updated. Every sum has a fixed order
+//    (no atomics).
 #include <algorithm>
 
 #include "cav_internal.hpp"
@@ -18,22 +19,89 @@ namespace cav {
 
 namespace {
 constexpr int TPB = 256;
-constexpr int PA_THREADS = 256;
 constexpr int MX_THREADS = 1024;
 
 __device__ __forceinline__ int wrapi(int a, int N) { return a & (N - 1); }
 
-// Shared-inverse part. Role order of a standard patch of cell (a,b):
-// 0 u_ab, 1 u_{a+1,b}, 2 v_ab, 3 v_{a,b+1}, 4 p_ab. Minv is column-major 5x5.
-// For untouched unknowns every incident patch is standard, cnt = 2 (velocity)
-// or 1 (pressure), and the weighted result is written; for touched unknowns
-// the raw sum over standard incident patches is written for k_touched.
-__global__ __launch_bounds__(TPB) void k_std_smooth(int N, const uint8_t* __restrict__ flag,
-                                                    const double* __restrict__ Minv, const double* __restrict__ r,
-                                                    double* __restrict__ z) {
+// One launch per smoothing step does the explicit patches of both precisions
+// and the shared-inverse cells (block ranges [0, P64), [P64, P64 + P32) and
+// the rest), and the touched unknowns follow in k_touched, which also applies
+// the update. AS_THREADS threads per block.
+constexpr int AS_THREADS = 512;
+constexpr int AS_UNROLL = 4;
+
+// delta[slot + i] = sum_j M[i + j n] r[dof_j] for one explicit patch. M is
+// column-major, so a wavefront reads one contiguous column segment per j.
+// Rows sit on lanes (nr = n rounded up to 64); when a patch fills less than
+// half the block, G = NT / nr column groups split the columns (group g takes
+// j = g, g + G, ...) and their partial sums are added in group order, so
+// small patches keep the block's loads in flight. Partial sums use
+// AS_UNROLL accumulators added pairwise at the end.
+template <typename T, int NT>
+__device__ __forceinline__ void patch_gemv(const PatchRec& rec, const T* __restrict__ arena,
+                                           const int32_t* __restrict__ slot_dof, const double* __restrict__ r,
+                                           double* __restrict__ delta, unsigned char* smem) {
+  const int n = rec.n;
+  T* xs = reinterpret_cast<T*>(smem);
+  T* part = xs + ((n + 1) & ~1);
+  const int32_t* dofs = slot_dof + rec.slot;
+  for (int i = threadIdx.x; i < n; i += NT) xs[i] = T(r[dofs[i]]);
+  __syncthreads();
+  const T* M = arena + rec.fac;
+  const int nr = ((n + 63) / 64) * 64;
+  const int G = nr >= NT ? 1 : NT / nr;
+  constexpr int U = AS_UNROLL;
+  if (G == 1) {
+    for (int i0 = 0; i0 < n; i0 += NT) {
+      const int i = i0 + threadIdx.x;
+      if (i < n) {
+        T a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = T(0);
+        const T* col = M + i;
+        int j = 0;
+        for (; j + U <= n; j += U)
+#pragma unroll
+          for (int u = 0; u < U; ++u) a[u] += col[int64_t(j + u) * n] * xs[j + u];
+        for (; j < n; ++j) a[0] += col[int64_t(j) * n] * xs[j];
+        delta[rec.slot + i] = double((a[0] + a[2]) + (a[1] + a[3]));
+      }
+    }
+    return;
+  }
+  const int i = threadIdx.x % nr, g = threadIdx.x / nr;
+  T a[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) a[u] = T(0);
+  if (i < n && g < G) {
+    const T* col = M + i;
+    int j = g;
+    for (; j + (U - 1) * G < n; j += U * G)
+#pragma unroll
+      for (int u = 0; u < U; ++u) a[u] += col[int64_t(j + u * G) * n] * xs[j + u * G];
+    for (; j < n; j += G) a[0] += col[int64_t(j) * n] * xs[j];
+  }
+  if (g < G) part[g * nr + i] = (a[0] + a[2]) + (a[1] + a[3]);
+  __syncthreads();
+  if (threadIdx.x < n) {
+    T sum = part[threadIdx.x];
+    for (int q = 1; q < G; ++q) sum += part[q * nr + threadIdx.x];
+    delta[rec.slot + threadIdx.x] = double(sum);
+  }
+}
+
+// Shared-inverse part for cell c = (i, j). Role order of a standard patch of
+// cell (a,b): 0 u_ab, 1 u_{a+1,b}, 2 v_ab, 3 v_{a,b+1}, 4 p_ab; Minv is
+// column-major 5x5. An unknown outside every explicit patch has only standard
+// incident patches (cnt = 2 for velocity, 1 for pressure) and is updated here,
+// x <- (zero ? 0 : x) + alpha * sum / cnt; for an unknown inside an explicit
+// patch the raw sum over its standard incident patches goes to z for
+// k_touched. flag bit 0: the cell's patch is explicit; bits 2, 3, 4: the
+// cell's u, v, p unknown is on k_touched's list.
+__device__ __forceinline__ void add_std_cell(int N, int64_t c, const uint8_t* __restrict__ flag,
+                                         const double* __restrict__ Minv, const double* __restrict__ r,
+                                         double* __restrict__ z, double* __restrict__ x, double alpha, bool zero) {
   const int64_t n2 = int64_t(N) * N;
-  const int64_t c = int64_t(blockIdx.x) * TPB + threadIdx.x;
-  if (c >= n2) return;
   double M[25];
 #pragma unroll
   for (int k = 0; k < 25; ++k) M[k] = Minv[k];
@@ -44,8 +112,7 @@ __global__ __launch_bounds__(TPB) void k_std_smooth(int N, const uint8_t* __rest
   const double* rp = r + 2 * n2;
   auto C = [N](int a, int b) { return int64_t(a) * N + b; };
   const uint8_t f0 = flag[c], fL = flag[C(im, j)], fB = flag[C(i, jm)];
-  // residual of this cell's standard patch
-  double q[5] = {ru[c], ru[C(ip, j)], rv[c], rv[C(i, jp)], rp[c]};
+  const double q[5] = {ru[c], ru[C(ip, j)], rv[c], rv[C(i, jp)], rp[c]};
   double su = 0.0, sv = 0.0, sp = 0.0;
   if (!(f0 & 1)) {
     double d0 = 0.0, d2 = 0.0, d4 = 0.0;
@@ -73,62 +140,54 @@ __global__ __launch_bounds__(TPB) void k_std_smooth(int N, const uint8_t* __rest
     for (int k = 0; k < 5; ++k) d3 += M[3 + 5 * k] * qB[k];
     sv += d3;
   }
-  const bool tu = (f0 & 2) || (fL & 2), tv = (f0 & 2) || (fB & 2);
-  z[c] = tu ? su : 0.5 * su;
-  z[n2 + c] = tv ? sv : 0.5 * sv;
-  z[2 * n2 + c] = sp;
+  const bool tu = f0 & 4, tv = f0 & 8, tp = f0 & 16;
+  if (tu) z[c] = su;
+  else x[c] = (zero ? 0.0 : x[c]) + alpha * (0.5 * su);
+  if (tv) z[n2 + c] = sv;
+  else x[n2 + c] = (zero ? 0.0 : x[n2 + c]) + alpha * (0.5 * sv);
+  if (tp) z[2 * n2 + c] = sp;
+  else x[2 * n2 + c] = (zero ? 0.0 : x[2 * n2 + c]) + alpha * sp;
 }
 
-// delta[slot + i] = sum_j M[i + j n] r[dof_j]; one workgroup per explicit patch.
-// M is column-major so a wavefront reads one contiguous column segment per j.
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_patch_apply(const PatchRec* __restrict__ recs, const T* __restrict__ arena,
-                                                    const int32_t* __restrict__ slot_dof, const double* __restrict__ r,
-                                                    double* __restrict__ delta) {
+__global__ __launch_bounds__(AS_THREADS) void k_add_smooth(
+    int p64, const PatchRec* __restrict__ rec64, const double* __restrict__ f64, int p32,
+    const PatchRec* __restrict__ rec32, const float* __restrict__ f32, const int32_t* __restrict__ slot_dof,
+    double* __restrict__ delta, int N, const uint8_t* __restrict__ flag, const double* __restrict__ Minv,
+    const double* __restrict__ r, double* __restrict__ z, double* __restrict__ x, double alpha, int zero) {
   extern __shared__ unsigned char smem_raw[];
-  T* xs = reinterpret_cast<T*>(smem_raw);
-  const PatchRec rec = recs[blockIdx.x];
-  const int n = rec.n;
-  const int32_t* dofs = slot_dof + rec.slot;
-  for (int i = threadIdx.x; i < n; i += NT) xs[i] = T(r[dofs[i]]);
-  __syncthreads();
-  const T* M = arena + rec.fac;
-  for (int i0 = 0; i0 < n; i0 += NT) {
-    const int i = i0 + threadIdx.x;
-    if (i < n) {
-      T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-      const T* col = M + i;
-      int jj = 0;
-      for (; jj + 4 <= n; jj += 4) {
-        a0 += col[int64_t(jj) * n] * xs[jj];
-        a1 += col[int64_t(jj + 1) * n] * xs[jj + 1];
-        a2 += col[int64_t(jj + 2) * n] * xs[jj + 2];
-        a3 += col[int64_t(jj + 3) * n] * xs[jj + 3];
-      }
-      for (; jj < n; ++jj) a0 += col[int64_t(jj) * n] * xs[jj];
-      delta[rec.slot + i] = double((a0 + a1) + (a2 + a3));
-    }
+  const int blk = int(blockIdx.x);
+  if (blk < p64) {
+    patch_gemv<double, AS_THREADS>(rec64[blk], f64, slot_dof, r, delta, smem_raw);
+  } else if (blk < p64 + p32) {
+    patch_gemv<float, AS_THREADS>(rec32[blk - p64], f32, slot_dof, r, delta, smem_raw);
+  } else {
+    const int64_t c = int64_t(blk - p64 - p32) * AS_THREADS + threadIdx.x;
+    if (c < int64_t(N) * N) add_std_cell(N, c, flag, Minv, r, z, x, alpha, zero != 0);
   }
 }
 
-// z[d] = (1/cnt(d)) * (z[d] + sum over d's slots of delta), slots ascending.
+// x[d] = (zero ? 0 : x[d]) + alpha / cnt(d) * (z[d] + sum over d's slots of
+// delta) for every unknown inside an explicit patch. TOUCH_LANES lanes per
+// touched unknown (never straddling a wavefront): lane l sums slots l,
+// l + TOUCH_LANES, ... in ascending order and an xor tree adds the partial
+// sums, a fixed order with one chain of dependent loads per unknown.
+constexpr int TOUCH_LANES = 8;
 __global__ __launch_bounds__(TPB) void k_touched(int nt, const int32_t* __restrict__ tdof, const double* __restrict__ tinv,
                                                  const int32_t* __restrict__ tptr, const int32_t* __restrict__ tslot,
-                                                 const double* __restrict__ delta, double* __restrict__ z) {
-  const int t = blockIdx.x * TPB + threadIdx.x;
-  if (t >= nt) return;
-  const int32_t d = tdof[t];
-  double s = z[d];
-  for (int q = tptr[t]; q < tptr[t + 1]; ++q) s += delta[tslot[q]];
-  z[d] = tinv[t] * s;
-}
-
-// x = (zero ? 0 : x) + alpha z
-__global__ __launch_bounds__(TPB) void k_update(double* __restrict__ x, const double* __restrict__ z, double alpha,
-                                                int zero, int64_t n) {
-  const int64_t t = int64_t(blockIdx.x) * TPB + threadIdx.x;
-  if (t >= n) return;
-  x[t] = (zero ? 0.0 : x[t]) + alpha * z[t];
+                                                 const double* __restrict__ delta, const double* __restrict__ z,
+                                                 double* __restrict__ x, double alpha, int zero) {
+  const int64_t g = int64_t(blockIdx.x) * TPB + threadIdx.x;
+  const int64_t t = g / TOUCH_LANES;
+  const int l = int(g % TOUCH_LANES);
+  double s = 0.0;
+  if (t < nt)
+    for (int q = tptr[t] + l; q < tptr[t + 1]; q += TOUCH_LANES) s += delta[tslot[q]];
+#pragma unroll
+  for (int o = TOUCH_LANES / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, TOUCH_LANES);
+  if (t < nt && l == 0) {
+    const int32_t d = tdof[t];
+    x[d] = (zero ? 0.0 : x[d]) + alpha * (tinv[t] * (z[d] + s));
+  }
 }
 
 inline unsigned nblocks(int64_t n) { return unsigned((n + TPB - 1) / TPB); }
@@ -1240,16 +1299,6 @@ __global__ void k_zero_bar(unsigned long long* bar, int words) {
   if (blockIdx.x == 0 && int(threadIdx.x) < words) bar[threadIdx.x] = 0ull;
 }
 
-template <typename T>
-void launch_patch_apply(Ctx& c, const std::vector<PatchRec>& recs_h, const PatchRec* recs_d, const T* arena,
-                        const Level& L, const double* r, double bytes, hipStream_t s) {
-  // one launch per level and precision; records are sorted by n descending
-  const int total = int(recs_h.size());
-  const size_t lds = size_t(recs_h[0].n) * sizeof(T);
-  timing_begin(c, s);
-  k_patch_apply<T, PA_THREADS><<<unsigned(total), PA_THREADS, lds, s>>>(recs_d, arena, L.d_slot_dof, r, L.d_delta);
-  timing_end(c, s, bytes);
-}
 }  // namespace
 
 // Workgroups of the cooperative sweep of level L (0: not possible).
@@ -1351,12 +1400,13 @@ static int phase_form(const Ctx& c, const Level& L, int nt) {
   return nt;
 }
 
-void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s) {
+void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s,
+                          bool remove_mean) {
   const int64_t n2 = int64_t(L.N) * L.N, n = 3 * n2;
   if (zero_guess) launch_fill(x, 0.0, n, s);
   const int nph = int(L.ph_ptr.size()) - 1;
   if (L.sweep_mode == 1 && !c.capturing && launch_mult_sweep(c, L, b, x, s)) {
-    launch_pressure_mean_remove(x, L.N, L.d_part, s);
+    if (remove_mean) launch_pressure_mean_remove(x, L.N, L.d_part, s);
     return;
   }
   const int64_t per_colour = n2 / 8;
@@ -1387,7 +1437,7 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
     timing_end(c, s, bytes, cnt);
   }
   if (!c.std_first) standard();
-  launch_pressure_mean_remove(x, L.N, L.d_part, s);
+  if (remove_mean) launch_pressure_mean_remove(x, L.N, L.d_part, s);
 }
 
 void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double* x, hipStream_t s) {
@@ -1461,10 +1511,10 @@ void prepare_mult_smoother(size_t lds) {
 // launch (MFMA), the shared-patch colours and the mean removal per column, in
 // the single-column order. Additive: the single-column sweep per column.
 void launch_smoother_multi(Ctx& c, Level& L, const double* b, double* x, int64_t ldv, int kb, bool zero_guess,
-                           hipStream_t s) {
+                           hipStream_t s, bool remove_mean) {
   const int64_t n2 = int64_t(L.N) * L.N, n = 3 * n2;
   if (level_smoother(c, L) != CAV_SMOOTHER_MULTIPLICATIVE) {
-    for (int q = 0; q < kb; ++q) launch_smoother(c, L, b + q * ldv, x + q * ldv, zero_guess, s);
+    for (int q = 0; q < kb; ++q) launch_smoother(c, L, b + q * ldv, x + q * ldv, zero_guess, s, remove_mean);
     return;
   }
   if (zero_guess)
@@ -1485,28 +1535,38 @@ void launch_smoother_multi(Ctx& c, Level& L, const double* b, double* x, int64_t
                                                      L.d_ecol, L.d_eval, b, x, ldv, kb, al, L.d_slot_mask);
   }
   if (!c.std_first) standard();
-  for (int q = 0; q < kb; ++q) launch_pressure_mean_remove(x + q * ldv, L.N, L.d_part, s);
+  if (remove_mean)
+    for (int q = 0; q < kb; ++q) launch_pressure_mean_remove(x + q * ldv, L.N, L.d_part, s);
 }
 
-void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s) {
+void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s,
+                     bool remove_mean) {
   if (level_smoother(c, L) == CAV_SMOOTHER_MULTIPLICATIVE) {
-    launch_mult_smoother(c, L, b, x, zero_guess, s);
+    launch_mult_smoother(c, L, b, x, zero_guess, s, remove_mean);
     return;
   }
-  const int64_t n2 = int64_t(L.N) * L.N, n = 3 * n2;
+  const int64_t n2 = int64_t(L.N) * L.N;
   const double* r = b;
   if (!zero_guess) {
     launch_apply_op(L, x, L.d_r, b, s);  // r = b - K x
     r = L.d_r;
   }
-  k_std_smooth<<<nblocks(n2), TPB, 0, s>>>(L.N, L.d_cellflag, L.d_std_inv, r, L.d_z);
-  if (!L.rec64_h.empty()) launch_patch_apply<double>(c, L.rec64_h, L.d_rec64, L.d_f64, L, r, L.bytes64, s);
-  if (!L.rec32_h.empty()) launch_patch_apply<float>(c, L.rec32_h, L.d_rec32, L.d_f32, L, r, L.bytes32, s);
+  const int p64 = int(L.rec64_h.size()), p32 = int(L.rec32_h.size());
+  int maxn = 0;
+  if (p64) maxn = L.rec64_h[0].n;
+  if (p32) maxn = std::max(maxn, L.rec32_h[0].n);
+  const size_t lds = (size_t(maxn) + 2 + AS_THREADS) * sizeof(double);
+  const unsigned grid = unsigned(p64 + p32) + unsigned((n2 + AS_THREADS - 1) / AS_THREADS);
+  const double al = level_alpha(c, L);
+  timing_begin(c, s);
+  k_add_smooth<<<grid, AS_THREADS, lds, s>>>(p64, L.d_rec64, L.d_f64, p32, L.d_rec32, L.d_f32, L.d_slot_dof,
+                                             L.d_delta, L.N, L.d_cellflag, L.d_std_inv, r, L.d_z, x, al,
+                                             zero_guess ? 1 : 0);
+  timing_end(c, s, L.bytes64 + L.bytes32 + 72.0 * double(n2));
   if (L.n_touched > 0)
-    k_touched<<<nblocks(L.n_touched), TPB, 0, s>>>(L.n_touched, L.d_t_dof, L.d_t_inv, L.d_t_ptr, L.d_t_slot, L.d_delta,
-                                                   L.d_z);
-  k_update<<<nblocks(n), TPB, 0, s>>>(x, L.d_z, level_alpha(c, L), zero_guess ? 1 : 0, n);
-  launch_pressure_mean_remove(x, L.N, L.d_part, s);
+    k_touched<<<nblocks(int64_t(L.n_touched) * TOUCH_LANES), TPB, 0, s>>>(
+        L.n_touched, L.d_t_dof, L.d_t_inv, L.d_t_ptr, L.d_t_slot, L.d_delta, L.d_z, x, al, zero_guess ? 1 : 0);
+  if (remove_mean) launch_pressure_mean_remove(x, L.N, L.d_part, s);
 }
 
 }  // namespace cav

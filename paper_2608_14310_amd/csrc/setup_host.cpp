@@ -748,6 +748,16 @@ void colour_explicit(int N, const HostCSR& ee, Level& L) {
 // injection keeps the unknowns of the unexpanded block (Section 3.3). Every
 // cell is flagged as handled by an explicit patch (no shared standard
 // patches); the touched lists hold the injected slots only, with weight 1.
+namespace {
+// Bits 2, 3, 4 of a cell's flag: its u, v, p unknown is on the touched list
+// (updated by the touched pass, not by the shared-inverse pass).
+void mark_touched(int N, Level& L) {
+  const int64_t n2 = int64_t(N) * N;
+  for (uint8_t& f : L.cellflag) f &= 3;
+  for (int32_t d : L.t_dof_h) L.cellflag[size_t(d % n2)] |= uint8_t(4 << (d / n2));
+}
+}  // namespace
+
 void build_box_patches(int N, const HostCSR& ee, int b, int o, Level& L) {
   const int64_t n2 = int64_t(N) * N, n = 3 * n2;
   auto vanka = [&](int i, int j, int32_t* d) {
@@ -826,6 +836,7 @@ void build_box_patches(int N, const HostCSR& ee, int b, int o, Level& L) {
     if (L.slot_mask_h[sl]) L.t_slot_h[start[L.slot_dof_h[sl]]++] = int32_t(sl);
   L.t_inv_h.assign(L.t_dof_h.size(), 1.0);
   L.n_touched = int32_t(L.t_dof_h.size());
+  mark_touched(N, L);
   colour_explicit(N, ee, L);
   cav_level_stats& st = L.stats;
   st.N = N;
@@ -999,6 +1010,7 @@ void build_patch_tables(int N, const HostCSR& ee, Level& L) {
     L.t_inv_h[t] = 1.0 / double(cnt);
   }
   L.n_touched = int32_t(L.t_dof_h.size());
+  mark_touched(N, L);
   colour_explicit(N, ee, L);
 
   // stats
