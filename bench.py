@@ -852,24 +852,25 @@ def main():
         line["additive"] = additive_leg(dev)
         gpu_full["membrane256"] = line["additive"]["membrane256"]["additive"]
     # the 32^2 target system (additive cycle), for the CPU comparison
-    st32 = workloads.small_target(0)
-    g32 = Solver(0)
-    g32.setup(st32, precision="fp64", alpha=0.7, smoother="additive")
-    b32 = torch.from_numpy(st32.b).to(dev)
-    g32.fgmres_solve(b32, rtol=1e-10, max_it=150)
-    torch.cuda.synchronize()
-    t0c = time.perf_counter()
-    g32.build_operator(st32)
-    g32.build_cav_patches("cav")
-    g32.factor_patches("fp64", 1e6)
-    g32.set_smoother("additive", 0.7)
-    t1c = time.perf_counter()
-    _, inf32 = g32.fgmres_solve(b32, rtol=1e-10, max_it=150)
-    torch.cuda.synchronize()
-    t2c = time.perf_counter()
-    g32.close()
-    gpu_full["target32"] = {"iterations": inf32["iterations"], "t_total_ms": round(1e3 * (t2c - t0c), 2),
-                            "t_solve_ms": round(1e3 * (t2c - t1c), 2)}
+    if not a.no_cpu_baseline:
+        st32 = workloads.small_target(0)
+        g32 = Solver(0)
+        g32.setup(st32, precision="fp64", alpha=0.7, smoother="additive")
+        b32 = torch.from_numpy(st32.b).to(dev)
+        g32.fgmres_solve(b32, rtol=1e-10, max_it=150)
+        torch.cuda.synchronize()
+        t0c = time.perf_counter()
+        g32.build_operator(st32)
+        g32.build_cav_patches("cav")
+        g32.factor_patches("fp64", 1e6)
+        g32.set_smoother("additive", 0.7)
+        t1c = time.perf_counter()
+        _, inf32 = g32.fgmres_solve(b32, rtol=1e-10, max_it=150)
+        torch.cuda.synchronize()
+        t2c = time.perf_counter()
+        g32.close()
+        gpu_full["target32"] = {"iterations": inf32["iterations"], "t_total_ms": round(1e3 * (t2c - t0c), 2),
+                                "t_solve_ms": round(1e3 * (t2c - t1c), 2)}
     sweep = []
     for kb in a.stiff_sweep:
         sk = workloads.beam_512(kb)
