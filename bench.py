@@ -169,22 +169,24 @@ def cpu_baseline(kappa_b: float, iters_gpu: int, smoother: str, gpu_full: dict, 
             "full_solves": full}
 
 
-def vcycle_bytes(stats, fst, N: int, n_levels: int, precision: str) -> float:
-    """Algorithmic HBM bytes of one V(1,1) cycle (what the method must move):
-    per smoothed level two sweeps, each streaming its explicit patches'
-    inverses (sum n_p^2 s; the shared far-field inverse is free) and their
-    index / gathered residual / update (20 B per patch unknown), about ten
-    vector passes (residual, transfers, mean removal, far-field colours) and
-    the E_E rows of two operator applies (12 B per nonzero); then the dense
-    coarsest solution operator once (n_c^2 8 B)."""
+def vcycle_bytes(stats, fst, N: int, n_levels: int, precision: str, sweeps: int = 1) -> float:
+    """Algorithmic HBM bytes of one V(sweeps, sweeps) cycle (what the method
+    must move): per smoothed level 2 * sweeps sweeps, each streaming its
+    explicit patches' inverses (sum n_p^2 s; the shared far-field inverse is
+    free) and their index / gathered residual / update (20 B per patch
+    unknown), about five vector passes per sweep (residual, transfers, mean
+    removal, far-field colours) and the E_E rows of one operator apply per
+    sweep (12 B per nonzero); then the dense coarsest solution operator once
+    (n_c^2 8 B)."""
     total = 0.0
     fbytes = float(fst["factor_bytes"])  # per sweep, all levels, at the stored precisions
+    k = 2 * sweeps
     for l in range(1, n_levels):
         st = stats[l]
         Nl = N >> (n_levels - 1 - l)
         sum_np = st["avg_np"] * st["n_patches"] - 5.0 * (st["n_patches"] - st["n_explicit"])
-        total += 2 * 20.0 * sum_np + 10 * 3 * Nl * Nl * 8.0 + 2 * st["ee_nnz"] * 12.0
-    total += 2 * fbytes
+        total += k * 20.0 * sum_np + 5 * k * 3 * Nl * Nl * 8.0 + k * st["ee_nnz"] * 12.0
+    total += k * fbytes
     nc = 3 * (N >> (n_levels - 1)) ** 2
     return total + nc * nc * 8.0
 
@@ -256,6 +258,100 @@ def additive_leg(dev, reps: int = 10, membrane: bool = True):
     out["membrane256"] = dict(workload="membrane256: 256x256, ellipse 0.2/0.15, kappa_s=1e4, 6 levels, FP64",
                               **rows)
     return out
+
+
+def additive_sweeps_leg(dev, alpha: float = 0.9, sweeps: int = 3):
+    """The weighted additive CAV cycle with more smoothing (damping alpha,
+    V(sweeps, sweeps)) on the headline system, FP64 and FP32 factors, as a
+    whole timed step (operator, patches, factors, solve) beside the paper's
+    V(1,1) multiplicative headline; the FP64 path's iteration count is
+    pinned to the oracle's golden for this configuration."""
+    import torch
+
+    import workloads
+    from paper_2608_14310_amd import Solver
+    s = workloads.beam_512(1e-2)
+    b = torch.from_numpy(s.b).to(dev)
+    g = Solver(0)
+    out = {"workload": f"beam512 (as the headline), weighted additive CAV, alpha {alpha:g}, V({sweeps},{sweeps})"}
+    xs = {}
+    for prec in ("fp64", "mixed"):
+        stats, fst = g.setup(s, precision=prec, alpha=alpha, smoother="additive")
+        g.set_smoother("additive", alpha, sweeps, sweeps)
+        g.fgmres_solve(b, rtol=1e-10, max_it=150)      # warm-up
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.build_operator(s)
+            g.build_cav_patches("cav")
+            fst = g.factor_patches(prec, 1e6)
+            g.set_smoother("additive", alpha, sweeps, sweeps)
+            t1 = time.perf_counter()
+            g.kernel_timing(True)
+            x, inf = g.fgmres_solve(b, rtol=1e-10, max_it=150)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            kt = g.kernel_timing(False)
+            if best is None or t2 - t0 < best[0]:
+                best = (t2 - t0, t2 - t1, inf, kt, x)
+        tt, ts, inf, kt, x = best
+        xs[prec] = x
+        bv = vcycle_bytes(stats, fst, s.N, s.n_levels, prec, sweeps)
+        out[prec] = {"iterations": inf["iterations"], "converged": inf["converged"],
+                     "true_rel_residual": float("%.3g" % inf["true_rel_residual"]),
+                     "t_total_ms": round(1e3 * tt, 2), "t_solve_ms": round(1e3 * ts, 2),
+                     "vcycle_ms": round(kt["vcycle_ms"], 4), "vcycle_bytes": int(bv),
+                     "vcycle_gbs": round(bv / (kt["vcycle_ms"] * 1e-3) / 1e9, 1),
+                     "vcycle_frac": round(bv / (kt["vcycle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    out["mixed"]["rel_err_vs_fp64"] = float(
+        "%.3g" % (torch.linalg.norm(xs["mixed"] - xs["fp64"]) / torch.linalg.norm(xs["fp64"])).item())
+    g.close()
+    return out
+
+
+def membrane_leg(dev, kappas=(1e2, 1e4, 1e6)):
+    """The 256^2 membrane (ellipse 0.2/0.15, nearest-neighbour springs,
+    ds = h/2) at each stiffness, multiplicative CAV V(1,1), FGMRES to 1e-10:
+    FP64 factors against FP32 factors with FP64 FGMRES, and the mixed
+    solution's error against the FP64 one (the FP64 path is pinned to the
+    oracle's goldens for these systems)."""
+    import torch
+
+    import workloads
+    from paper_2608_14310_amd import Solver
+    out = []
+    for ks in kappas:
+        sm = workloads.membrane_256(ks)
+        bm = torch.from_numpy(sm.b).to(dev)
+        g = Solver(0)
+        row = {"kappa_s": ks}
+        xs = {}
+        for prec in ("fp64", "mixed"):
+            g.setup(sm, precision=prec, alpha=1.0, smoother="multiplicative")
+            g.fgmres_solve(bm, rtol=1e-10, max_it=150)      # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.build_operator(sm)
+            g.build_cav_patches("cav")
+            fst = g.factor_patches(prec, 1e6)
+            g.set_smoother("multiplicative", 1.0)
+            t1 = time.perf_counter()
+            x, inf = g.fgmres_solve(bm, rtol=1e-10, max_it=150)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            xs[prec] = x
+            row[prec] = {"iterations": inf["iterations"], "converged": inf["converged"],
+                         "status": inf.get("status", 0),
+                         "true_rel_residual": float("%.3g" % inf["true_rel_residual"]),
+                         "t_total_ms": round(1e3 * (t2 - t0), 2), "t_solve_ms": round(1e3 * (t2 - t1), 2),
+                         "n_fp32_patches": fst["n_fp32"], "n_fp64_patches": fst["n_fp64"]}
+        row["mixed"]["rel_err_vs_fp64"] = float(
+            "%.3g" % (torch.linalg.norm(xs["mixed"] - xs["fp64"]) / torch.linalg.norm(xs["fp64"])).item())
+        g.close()
+        out.append(row)
+    return {"workload": "membrane256: 256x256, ellipse 0.2/0.15, 6 levels, multiplicative CAV V(1,1), "
+                        "FGMRES rtol 1e-10", "runs": out}
 
 
 def copy_calibration(nbytes: int):
@@ -650,6 +746,8 @@ def main():
     ap.add_argument("--fibre-grids", type=int, nargs="*", default=[],
                     help="grids of the flexible-fibre context leg (Table 3, e.g. 32 64 128 256; default: skip)")
     ap.add_argument("--no-additive", action="store_true", help="skip the weighted additive smoother leg")
+    ap.add_argument("--no-membrane", action="store_true",
+                    help="skip the 256^2 membrane stiffness leg (FP64 against FP32 factors)")
     ap.add_argument("--additive-only", action="store_true",
                     help="run only the additive V-cycles on the 512^2 beam (for profiling k_add_smooth), then exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -708,7 +806,7 @@ def main():
         tm["solve"] = time.perf_counter() - t3
         kt = g.kernel_timing(False)
         return dict(tm, its=info["iterations"], conv=info["converged"], est=info["est_rel_residual"],
-                    true=info["true_rel_residual"], stats=stats, fst=fst, kt=kt)
+                    true=info["true_rel_residual"], stats=stats, fst=fst, kt=kt, x=x)
 
     # phase-kernel table for this hierarchy shape (outside the timed region)
     setup(a.precision)
@@ -789,7 +887,7 @@ def main():
                    "precision": a.precision, "smoother": a.smoother, "alpha": alpha, "tune": a.tune},
         "t_solve_ms": round(float(np.median(solve_ms)), 3),
         "per_step": {k: (float("%.4g" % v) if isinstance(v, float) else v) for k, v in last.items()
-                     if k not in ("stats", "fst", "kt")},
+                     if k not in ("stats", "fst", "kt", "x")},
         "vcycle_ms": round(last["kt"]["vcycle_ms"], 4),
         "vcycles_per_s": round(1e3 / last["kt"]["vcycle_ms"], 1) if last["kt"]["vcycle_ms"] else None,
         "vcycle_bytes": int(bv),
@@ -817,10 +915,17 @@ def main():
     other = "mixed" if a.precision == "fp64" else "fp64"
     if not a.no_other_precision:
         o = one_step(other)
+        x64, xo = (last["x"], o["x"]) if a.precision == "fp64" else (o["x"], last["x"])
         line["other_precision"] = {
             "precision": other, "t_total_ms": round(1e3 * (o["build"] + o["patches"] + o["factor"] + o["solve"]), 1),
             "t_solve_ms": round(1e3 * o["solve"], 1), "its": o["its"], "true": o["true"],
+            "rel_err_vs_fp64": float("%.3g" % (torch.linalg.norm(xo - x64) / torch.linalg.norm(x64)).item()),
             "n_fp32_patches": o["fst"]["n_fp32"], "n_fp64_patches": o["fst"]["n_fp64"]}
+        del o
+    if not a.no_membrane:
+        line["membrane256"] = membrane_leg(dev)
+    if not a.no_additive:
+        line["additive_v33"] = additive_sweeps_leg(dev)
     if a.multi_rhs > 0:
         # the V-cycle on blocks of 16 right-hand sides (explicit phases as FP64
         # MFMA products) against one cycle per column, outside the timed steps

@@ -7,8 +7,9 @@ chosen patch family and its local factors; the coarsest system is solved by a
 precomputed direct factorisation. Reading: the periodic coarse operator has the
 constant-pressure null mode (Section 5.1), so the coarse solve uses the
 bordered matrix [[K_0, e], [e^T, 0]] with e the constant pressure vector.
-Reading: pre-smoothing starts from zero; one pre- and one post-sweep; the
-smoothers remove the mean pressure after every sweep.
+Reading: pre-smoothing starts from zero; one pre- and one post-sweep (the
+paper's V(1,1); `pre` and `post` repeat the sweeps, each from the iterate the
+previous one left); the smoothers remove the mean pressure after every sweep.
 """
 from __future__ import annotations
 
@@ -41,13 +42,16 @@ class Level:
 
 class Hierarchy:
     def __init__(self, system, family: str = "cav", alpha: float = 1.0, smoother: str = "additive",
-                 box=(4, 2), order: str = "standard_first", lex: str = "y_fast"):
+                 box=(4, 2), order: str = "standard_first", lex: str = "y_fast", pre: int = 1, post: int = 1):
         """lex: the reading of the paper's lexicographic patch order for the
         sequential multiplicative smoother (Section 3.3): "y_fast" visits
         cells (i, j) with the y index j fastest (the vector layout's order),
         "x_fast" with the x index i fastest (boxes by their lower-left cells
-        alike)."""
+        alike). pre, post: smoothing sweeps before and after the coarse
+        correction (V(pre, post))."""
         self.system = system
+        self.pre = pre
+        self.post = post
         self.order = order
         self.lex = lex
         self.alpha = alpha
@@ -137,18 +141,23 @@ class Hierarchy:
         raise ValueError(self.smoother)
 
     def vcycle(self, b: np.ndarray, l: Optional[int] = None) -> np.ndarray:
-        """V(l, b): x = S(b, 0); x += P V(l-1, R(b - K x)); x = S(b, x)."""
+        """V(l, b): x = 0; x = S(b, x) pre times; x += P V(l-1, R(b - K x));
+        x = S(b, x) post times."""
         if l is None:
             l = len(self.levels) - 1
         if l == 0:
             return self.coarse_solve(b)
         lev = self.levels[l]
         R, P = self.transfers(l)
-        x = self.smooth(l, b, np.zeros_like(b))
+        x = np.zeros_like(b)
+        for _ in range(self.pre):
+            x = self.smooth(l, b, x)
         r = b - lev.K @ x
         ec = self.vcycle(R @ r, l - 1)
         x = x + P @ ec
-        return self.smooth(l, b, x)
+        for _ in range(self.post):
+            x = self.smooth(l, b, x)
+        return x
 
     def transfers(self, l: int):
         """(restriction to level l-1, prolongation from level l-1)."""

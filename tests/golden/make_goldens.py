@@ -15,6 +15,10 @@ configuration is one invocation:
       ellipse membrane on a 256^2 grid, coarsest 8^2, SMOOTHER additive
       (alpha 0.7, Theta = 1/cnt) or multiplicative (alpha 1, coloured ORDER,
       default explicit_first), FGMRES to 1e-10 (max 150)
+  python tests/golden/make_goldens.py additive SYSTEM STIFFNESS ALPHA SWEEPS
+      SYSTEM beam512 (kappa_b = STIFFNESS) or membrane256 (kappa_s =
+      STIFFNESS), weighted additive CAV (Theta = 1/cnt) with damping ALPHA
+      and V(SWEEPS, SWEEPS), FGMRES to 1e-10 (max 150)
 
 Output: tests/golden/<name>.json
 """
@@ -41,12 +45,12 @@ def sample_positions(n: int) -> np.ndarray:
     return np.sort(np.random.default_rng(12345).choice(n, N_SAMPLES, replace=False))
 
 
-def run(system, smoother: str, alpha: float, order: str, name: str, meta: dict) -> dict:
+def run(system, smoother: str, alpha: float, order: str, name: str, meta: dict, sweeps: int = 1) -> dict:
     t0 = time.time()
     if smoother == "multiplicative":
-        H = multigrid.Hierarchy(system, alpha=alpha, smoother="coloured", order=order)
+        H = multigrid.Hierarchy(system, alpha=alpha, smoother="coloured", order=order, pre=sweeps, post=sweeps)
     else:
-        H = multigrid.Hierarchy(system, alpha=alpha, smoother="additive")
+        H = multigrid.Hierarchy(system, alpha=alpha, smoother="additive", pre=sweeps, post=sweeps)
     t_setup = time.time() - t0
     K = H.levels[-1].K
     count = [0]
@@ -60,7 +64,8 @@ def run(system, smoother: str, alpha: float, order: str, name: str, meta: dict) 
     x = res.x
     pos = sample_positions(x.size)
     out = dict(meta, name=name, N=system.N, n_levels=system.n_levels, smoother=smoother, alpha=alpha,
-               order=order if smoother == "multiplicative" else None, rtol=1e-10, max_it=150,
+               order=order if smoother == "multiplicative" else None, pre=sweeps, post=sweeps,
+               rtol=1e-10, max_it=150,
                iterations=res.iterations, converged=bool(res.converged), history=[float(h) for h in res.history],
                true_rel_residual=float(np.linalg.norm(system.b - K @ x) / np.linalg.norm(system.b)),
                x_norm2=float(np.linalg.norm(x)), x_norminf=float(np.abs(x).max()),
@@ -88,6 +93,19 @@ def main(argv):
         tag = smoother if smoother == "additive" else f"{smoother}_{order}"
         run(s, smoother, alpha, order, f"membrane256_ks{ks:g}_{tag}",
             dict(workload="membrane_256", kappa_s=ks, seed=0))
+    elif kind == "additive":
+        system, k, alpha, sweeps = argv[1], float(argv[2]), float(argv[3]), int(argv[4])
+        if system == "beam512":
+            s = workloads.beam_512(k, seed=0)
+            meta = dict(workload="beam_512", kappa_b=k, seed=0)
+            stem = f"beam512_kb{k:g}"
+        elif system == "membrane256":
+            s = workloads.membrane_256(k, seed=0)
+            meta = dict(workload="membrane_256", kappa_s=k, seed=0)
+            stem = f"membrane256_ks{k:g}"
+        else:
+            raise SystemExit(__doc__)
+        run(s, "additive", alpha, "", f"{stem}_additive_a{alpha:g}_v{sweeps}{sweeps}", meta, sweeps)
     else:
         raise SystemExit(__doc__)
 

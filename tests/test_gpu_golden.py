@@ -1,6 +1,7 @@
 """FGMRES on the full-size configurations against expected values written by
 the oracle alone (`tests/golden/make_goldens.py`): the 512^2 beam of the
-headline measurement and the 256^2 membrane at kappa_s = 1e2, 1e4, 1e6.
+headline measurement and the 256^2 membrane at kappa_s = 1e2, 1e4, 1e6, with
+the paper's V(1,1) cycles and with the additive cycle's V(3,3) form.
 
 Iteration counts must be identical (the GPU and the oracle run the same
 cycle; the FP64 rounding of the explicit inverses stays far below what moves
@@ -41,6 +42,8 @@ def _solve(g, precision):
     sol = Solver(0)
     try:
         sol.setup(s, precision=precision, alpha=g["alpha"], smoother=g["smoother"])
+        sweeps = g.get("pre", 1)
+        sol.set_smoother(g["smoother"], g["alpha"], sweeps, g.get("post", sweeps))
         if g["smoother"] == "multiplicative":
             sol.set_phase_order(g["order"])
         x, info = sol.fgmres_solve(torch.from_numpy(s.b).cuda(), rtol=g["rtol"], max_it=g["max_it"])

@@ -275,6 +275,34 @@ def test_explicit_first_order_matches_oracle(name):
     assert np.linalg.norm(_np(x) - res.x) / np.linalg.norm(res.x) < 1e-8
 
 
+@pytest.mark.parametrize("smoother,alpha,sweeps,name", [("additive", 0.9, 3, "beam64"), ("additive", 0.9, 3, "membrane32"),
+                                                         ("multiplicative", 1.0, 2, "beam64")])
+def test_more_sweeps_match_oracle(smoother, alpha, sweeps, name):
+    """V(k, k): the GPU cycle repeats its sweeps as the oracle does (each from
+    the iterate the previous one left; the pressure mean removed once at the
+    end of the cycle), so the cycle matches the oracle's within the V-cycle
+    parity bound and FGMRES takes the oracle's iterations to the same
+    solution."""
+    s = CASES[name]()
+    print(f"[gpu parity] V({sweeps},{sweeps}) {smoother} alpha={alpha} {name}", flush=True)
+    H = multigrid.Hierarchy(s, alpha=alpha, smoother="coloured" if smoother == "multiplicative" else "additive",
+                            pre=sweeps, post=sweeps)
+    g = _solver()
+    stats, fst = g.setup(s, alpha=alpha, smoother=smoother)
+    g.set_smoother(smoother, alpha, sweeps, sweeps)
+    tol = _tol(fst)
+    z = _np(g.vcycle(_t(s.b)))
+    assert _rel(z, H.vcycle(s.b)) < 4 * tol
+    K = H.levels[-1].K
+    res = krylov.fgmres(lambda x: K @ x, H.vcycle, s.b, 1e-10, 150)
+    x, info = g.fgmres_solve(_t(s.b), rtol=1e-10, max_it=150)
+    g.close()
+    print(f"[gpu parity] V({sweeps},{sweeps}) {smoother} {name}: oracle its={res.iterations} "
+          f"gpu its={info['iterations']}", flush=True)
+    assert info["converged"] == 1 and info["iterations"] == res.iterations
+    assert np.linalg.norm(_np(x) - res.x) / np.linalg.norm(res.x) < 1e-8
+
+
 # ------------------------------------------------------- mixed precision ---
 
 @pytest.mark.parametrize("smoother,alpha,name", [("additive", 0.7, "target32"), ("multiplicative", 1.0, "beam64")])
