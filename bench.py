@@ -75,12 +75,14 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_sampled_512(kappa_b: float, iters_gpu: int, threads: int, sample_patches: int):
-    """The FP64 oracle on a bounded sample of the 512^2 headline workload with
-    `threads` BLAS threads: E_E, the Galerkin hierarchy and every level's patch
-    family are built in full; the local factorisations and the multiplicative
-    smoother's per-patch work are timed on a sample of patches per level and
-    scaled to the level's patch count; one V(1,1) cycle is then two sweeps per
+def cpu_sampled_512(kappa_b: float, iters_gpu: int, threads: int, sample_patches: int, sweeps: int = 1):
+    """The FP64 oracle's multiplicative cycle on a bounded sample of the 512^2
+    headline workload with `threads` BLAS threads: E_E, the Galerkin hierarchy
+    and every level's patch family are built in full; the local
+    factorisations and the multiplicative smoother's per-patch work (local
+    solve and residual update, one patch at a time as the oracle's sweep does
+    it) are timed on a sample of patches per level and scaled to the level's
+    patch count; one V(sweeps, sweeps) cycle is then 2 sweeps sweeps per
     smoothed level, and the solve is the GPU's iteration count of V-cycle +
     operator apply. Returns (total ms, sweep s, build s)."""
     import numpy as np
@@ -123,8 +125,39 @@ def cpu_sampled_512(kappa_b: float, iters_gpu: int, threads: int, sample_patches
             K @ s.b
         t_apply = (time.perf_counter() - ta) / 3
     setup = t_build + t_pat + t_fact
-    per_it = 2 * t_sweep + t_apply
-    return 1e3 * (setup + iters_gpu * per_it), 2 * t_sweep, t_build + t_pat
+    per_it = 2 * sweeps * t_sweep + t_apply
+    return 1e3 * (setup + iters_gpu * per_it), 2 * sweeps * t_sweep, t_build + t_pat
+
+
+def cpu_additive_512(kappa_b: float, iters_gpu: int, threads: int, alpha: float, sweeps: int):
+    """The FP64 oracle's weighted additive cycle on the 512^2 headline
+    workload: the whole hierarchy (E_E, Galerkin levels, patch families, every
+    local LU factorisation) built with `threads` BLAS threads, one whole
+    V(sweeps, sweeps) cycle and one operator apply timed with all of them and
+    again with one thread, each extrapolated to the GPU's iteration count.
+    Returns (total ms, total ms on one thread, setup s, cycle s, cycle s on
+    one thread)."""
+    from threadpoolctl import threadpool_limits
+
+    import workloads
+    from oracle import multigrid
+    s = workloads.beam_512(kappa_b)
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        H = multigrid.Hierarchy(s, alpha=alpha, smoother="additive", pre=sweeps, post=sweeps)
+        K = H.levels[-1].K
+        t_setup = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        H.vcycle(s.b)
+        K @ s.b
+        t_cycle = time.perf_counter() - t1
+    with threadpool_limits(limits=1):
+        t2 = time.perf_counter()
+        H.vcycle(s.b)
+        K @ s.b
+        t_cycle1 = time.perf_counter() - t2
+    return (1e3 * (t_setup + iters_gpu * t_cycle), 1e3 * (t_setup + iters_gpu * t_cycle1), t_setup, t_cycle,
+            t_cycle1)
 
 
 def cpu_full_solve(system, alpha: float, threads: int):
@@ -144,7 +177,8 @@ def cpu_full_solve(system, alpha: float, threads: int):
             "total_ms": round(1e3 * (t2 - t0), 1), "iterations": res.iterations, "threads": threads}
 
 
-def cpu_baseline(kappa_b: float, iters_gpu: int, smoother: str, gpu_full: dict, sample_patches: int = 200):
+def cpu_baseline(kappa_b: float, iters_gpu: int, smoother: str, gpu_full: dict, sample_patches: int = 200,
+                 alpha: float = 1.0, sweeps: int = 1):
     """The oracle as it stands, on the host cores: the headline workload on a
     bounded sample (extrapolated, all host cores and 1 thread), and whole
     solves of the 32^2 target and 256^2 membrane systems (additive cycle,
@@ -152,18 +186,28 @@ def cpu_baseline(kappa_b: float, iters_gpu: int, smoother: str, gpu_full: dict, 
     in this run."""
     import workloads
     cores = host_cores()
-    total, sweep_s, build_s = cpu_sampled_512(kappa_b, iters_gpu, cores, sample_patches)
-    total1, _, _ = cpu_sampled_512(kappa_b, iters_gpu, 1, sample_patches)
+    if smoother == "additive":
+        total, total1, t_setup, t_cyc, t_cyc1 = cpu_additive_512(kappa_b, iters_gpu, cores, alpha, sweeps)
+        sample = (f"512^2 beam kappa_b={kappa_b:g}, weighted additive CAV V({sweeps},{sweeps}) alpha {alpha:g}: "
+                  f"the oracle's hierarchy built in full with {cores} BLAS threads ({t_setup:.1f} s), one whole "
+                  f"V-cycle + K apply timed with {cores} threads ({t_cyc:.1f} s) and with 1 thread "
+                  f"({t_cyc1:.1f} s, setup taken from the all-core run), extrapolated to {iters_gpu} iterations "
+                  "(an extrapolation, not a whole solve)")
+    else:
+        total, sweep_s, build_s = cpu_sampled_512(kappa_b, iters_gpu, cores, sample_patches, sweeps)
+        total1, _, _ = cpu_sampled_512(kappa_b, iters_gpu, 1, sample_patches, sweeps)
+        sample = (f"512^2 beam kappa_b={kappa_b:g}, multiplicative CAV V({sweeps},{sweeps}), "
+                  f"{cores} BLAS threads: E_E + hierarchy + "
+                  f"patch families in full ({build_s:.1f} s); factorisation and one smoother step timed on "
+                  f"{sample_patches} random patches per level and scaled to each level's patch count; "
+                  f"V-cycle = {2 * sweeps} sweeps ({sweep_s:.1f} s est.) + K apply; extrapolated to "
+                  f"{iters_gpu} iterations (an extrapolation, not a whole solve)")
     full = {}
     for key, system in (("target32", workloads.small_target(0)), ("membrane256", workloads.membrane_256(1e4))):
         rows = [cpu_full_solve(system, 0.7, t) for t in (cores, 1)]
         full[key] = {"all_cores": rows[0], "one_thread": rows[1], "gpu": gpu_full.get(key)}
     return {"value": round(total, 1), "unit": "ms", "cores": cores, "kind": "oracle",
-            "sample": (f"512^2 beam kappa_b={kappa_b:g}, {smoother} CAV, {cores} BLAS threads: E_E + hierarchy + "
-                       f"patch families in full ({build_s:.1f} s); factorisation and one smoother step timed on "
-                       f"{sample_patches} random patches per level and scaled to each level's patch count; "
-                       f"V-cycle = 2 sweeps ({sweep_s:.1f} s est.) + K apply; extrapolated to {iters_gpu} "
-                       "iterations (an extrapolation, not a whole solve)"),
+            "sample": sample,
             "one_thread_value": round(total1, 1), "cpu_model": cpu_model(),
             "threads": {"blas": cores, "python": 1},
             "full_solves": full}
@@ -306,6 +350,88 @@ def additive_sweeps_leg(dev, alpha: float = 0.9, sweeps: int = 3):
                      "vcycle_frac": round(bv / (kt["vcycle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     out["mixed"]["rel_err_vs_fp64"] = float(
         "%.3g" % (torch.linalg.norm(xs["mixed"] - xs["fp64"]) / torch.linalg.norm(xs["fp64"])).item())
+    g.close()
+    return out
+
+
+def dominant_kernel(kts, smoother: str, tune: str):
+    """The dominant smoothing kernel of timed solves from their live HIP-event
+    brackets (cav_kernel_timing): the dataflow sweep when its brackets hold
+    most of the time, else the shared-residual form, else the other
+    cooperative forms, else the one-workgroup phase form (multiplicative) or
+    k_add_smooth (additive). Returns (name, bytes, ms, launches)."""
+    co_ms = sum(k["coop_ms"] for k in kts)
+    sh_ms = sum(k["shared_ms"] for k in kts)
+    fl_ms = sum(k["flow_ms"] for k in kts)
+    all_ms = sum(k["ms"] for k in kts)
+    if fl_ms > all_ms - fl_ms:
+        return ("k_mult_flow", sum(k["flow_bytes"] for k in kts), fl_ms, sum(k["flow_launches"] for k in kts))
+    if sh_ms > all_ms - sh_ms:
+        return ("k_mult_coopr", sum(k["shared_bytes"] for k in kts), sh_ms,
+                sum(k["shared_launches"] for k in kts))
+    if co_ms > all_ms - co_ms:
+        name = {"coop64": "k_mult_coop<64>", "coop128": "k_mult_coop<128>"}.get(tune, "k_mult_coop")
+        return (name, sum(k["coop_bytes"] - k["shared_bytes"] for k in kts), co_ms - sh_ms,
+                sum(k["coop_launches"] - k["shared_launches"] for k in kts))
+    name = "k_mult_exp" if smoother == "multiplicative" else "k_add_smooth"
+    return (name, sum(k["bytes"] - k["coop_bytes"] - k["flow_bytes"] for k in kts), all_ms - co_ms - fl_ms,
+            sum(k["launches"] - k["coop_launches"] - k["flow_launches"] for k in kts))
+
+
+def paper_v11_leg(dev, kappa_b: float, steps: int = 2):
+    """The paper's cycle on the headline system: coloured multiplicative CAV
+    V(1,1) (standard-first phase order), FP64 factors, whole timed steps
+    (operator, patches, factors, solve) after one untimed one, with the
+    dominant phase kernel's live bandwidth and its counter-derived traffic;
+    then the same with FP32 factors. Its FP64 iteration count is pinned to
+    the oracle's golden."""
+    import torch
+
+    import workloads
+    from paper_2608_14310_amd import Solver
+    s = workloads.beam_512(kappa_b)
+    b = torch.from_numpy(s.b).to(dev)
+    g = Solver(0)
+
+    def step(prec):
+        t0 = time.perf_counter()
+        g.build_operator(s)
+        stats = g.build_cav_patches("cav")
+        fst = g.factor_patches(prec, 1e6)
+        g.set_smoother("multiplicative", 1.0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.kernel_timing(True)
+        x, inf = g.fgmres_solve(b, rtol=1e-10, max_it=150)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return dict(total=t2 - t0, solve=t2 - t1, inf=inf, kt=g.kernel_timing(False), stats=stats, fst=fst, x=x)
+
+    step("fp64")
+    runs = [step("fp64") for _ in range(steps)]
+    kernel, kb_bytes, kb_ms, kb_launch = dominant_kernel([r["kt"] for r in runs], "multiplicative", "default")
+    achieved = kb_bytes / (kb_ms * 1e-3) / 1e9 if kb_ms > 0 else 0.0
+    last = runs[-1]
+    bv = vcycle_bytes(last["stats"], last["fst"], s.N, s.n_levels, "fp64", 1)
+    vc = last["kt"]["vcycle_ms"]
+    mixed = step("mixed")
+    out = {"workload": "beam512 (as the headline), coloured multiplicative CAV V(1,1), alpha 1, standard-first "
+                       "phase order: the paper's cycle",
+           "t_total_ms": round(1e3 * min(r["total"] for r in runs), 2),
+           "t_solve_ms": round(1e3 * min(r["solve"] for r in runs), 2),
+           "iterations": last["inf"]["iterations"], "converged": last["inf"]["converged"],
+           "true_rel_residual": float("%.3g" % last["inf"]["true_rel_residual"]),
+           "vcycle_ms": round(vc, 4), "vcycle_bytes": int(bv), "vcycle_gbs": round(bv / (vc * 1e-3) / 1e9, 1),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic(kernel, "fp64", "multiplicative", "default"),
+                        "kernel": kernel, "launches": kb_launch, "bytes_per_launch": int(kb_bytes / max(kb_launch, 1)),
+                        "avg_launch_us": round(1e3 * kb_ms / max(kb_launch, 1), 3)},
+           "mixed": {"t_total_ms": round(1e3 * mixed["total"], 2), "t_solve_ms": round(1e3 * mixed["solve"], 2),
+                     "iterations": mixed["inf"]["iterations"],
+                     "true_rel_residual": float("%.3g" % mixed["inf"]["true_rel_residual"]),
+                     "rel_err_vs_fp64": float("%.3g" % (torch.linalg.norm(mixed["x"] - last["x"]) /
+                                                        torch.linalg.norm(last["x"])).item())}}
     g.close()
     return out
 
@@ -720,7 +846,13 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--smoother", default="multiplicative", choices=["multiplicative", "additive"])
+    ap.add_argument("--smoother", default="additive", choices=["multiplicative", "additive"],
+                    help="smoother of the timed steps: the weighted additive CAV cycle (Appendix A; default "
+                         "alpha 0.9, V(3,3)) or the paper's coloured multiplicative V(1,1); the other is timed "
+                         "beside it")
+    ap.add_argument("--alpha", type=float, default=None, help="damping (default 0.9 additive, 1 multiplicative)")
+    ap.add_argument("--sweeps", type=int, default=None,
+                    help="pre- and post-sweeps per level (default 3 additive, 1 multiplicative)")
     ap.add_argument("--kappa-b", type=float, default=1e-2)
     ap.add_argument("--stiff-sweep", type=float, nargs="*", default=[1.0, 1e2])
     ap.add_argument("--tune", default="default",
@@ -746,6 +878,9 @@ def main():
     ap.add_argument("--fibre-grids", type=int, nargs="*", default=[],
                     help="grids of the flexible-fibre context leg (Table 3, e.g. 32 64 128 256; default: skip)")
     ap.add_argument("--no-additive", action="store_true", help="skip the weighted additive smoother leg")
+    ap.add_argument("--no-paper-v11", action="store_true",
+                    help="skip the other smoother's leg (the paper's multiplicative V(1,1) when the timed steps "
+                         "are additive)")
     ap.add_argument("--no-membrane", action="store_true",
                     help="skip the 256^2 membrane stiffness leg (FP64 against FP32 factors)")
     ap.add_argument("--additive-only", action="store_true",
@@ -780,7 +915,8 @@ def main():
     s = workloads.beam_512(a.kappa_b)
     b = torch.from_numpy(s.b).to(dev)
     g = Solver(0)
-    alpha = 1.0 if a.smoother == "multiplicative" else 0.7
+    alpha = a.alpha if a.alpha is not None else (1.0 if a.smoother == "multiplicative" else 0.9)
+    sweeps = a.sweeps if a.sweeps is not None else (1 if a.smoother == "multiplicative" else 3)
     table = None
 
     def setup(precision):
@@ -790,7 +926,7 @@ def main():
         stats = g.build_cav_patches("cav")
         t2 = time.perf_counter()
         fst = g.factor_patches(precision, 1e6)
-        g.set_smoother(a.smoother, alpha)
+        g.set_smoother(a.smoother, alpha, sweeps, sweeps)
         if table is not None:
             g.set_tuning(table)
         torch.cuda.synchronize()
@@ -837,36 +973,10 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / a.steps
 
-    # the dominant explicit-patch kernel: the dataflow sweep when its brackets
-    # hold most of the time, else the shared-residual form, else the other
-    # cooperative forms, else the one-workgroup form
-    co_ms = sum(r["kt"]["coop_ms"] for r in runs)
-    sh_ms = sum(r["kt"]["shared_ms"] for r in runs)
-    fl_ms = sum(r["kt"]["flow_ms"] for r in runs)
-    all_ms = sum(r["kt"]["ms"] for r in runs)
-    if fl_ms > all_ms - fl_ms:
-        kernel = "k_mult_flow"
-        kb_bytes = sum(r["kt"]["flow_bytes"] for r in runs)
-        kb_ms = fl_ms
-        kb_launch = sum(r["kt"]["flow_launches"] for r in runs)
-    elif sh_ms > all_ms - sh_ms:
-        kernel = "k_mult_coopr"
-        kb_bytes = sum(r["kt"]["shared_bytes"] for r in runs)
-        kb_ms = sh_ms
-        kb_launch = sum(r["kt"]["shared_launches"] for r in runs)
-    elif co_ms > all_ms - co_ms:
-        kernel = {"coop64": "k_mult_coop<64>", "coop128": "k_mult_coop<128>"}.get(a.tune, "k_mult_coop")
-        kb_bytes = sum(r["kt"]["coop_bytes"] - r["kt"]["shared_bytes"] for r in runs)
-        kb_ms = co_ms - sh_ms
-        kb_launch = sum(r["kt"]["coop_launches"] - r["kt"]["shared_launches"] for r in runs)
-    else:
-        kernel = "k_mult_exp" if a.smoother == "multiplicative" else "k_add_smooth"
-        kb_bytes = sum(r["kt"]["bytes"] - r["kt"]["coop_bytes"] - r["kt"]["flow_bytes"] for r in runs)
-        kb_ms = all_ms - co_ms - fl_ms
-        kb_launch = sum(r["kt"]["launches"] - r["kt"]["coop_launches"] - r["kt"]["flow_launches"] for r in runs)
+    kernel, kb_bytes, kb_ms, kb_launch = dominant_kernel([r["kt"] for r in runs], a.smoother, a.tune)
     achieved = kb_bytes / (kb_ms * 1e-3) / 1e9 if kb_ms > 0 else 0.0
     last = runs[-1]
-    bv = vcycle_bytes(last["stats"], last["fst"], s.N, s.n_levels, a.precision)
+    bv = vcycle_bytes(last["stats"], last["fst"], s.N, s.n_levels, a.precision, sweeps)
     solve_ms = [1e3 * r["solve"] for r in runs]
     line = {
         "metric": "FGMRES(CAV-MG) time-to-1e-10 rel. residual at 512^2; V-cycle HBM GB/s",
@@ -881,10 +991,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "beam512: 512x512 MAC grid, 5-level V(1,1) CAV multigrid, 4 open fibres L=0.4 "
+        "config": {"workload": f"beam512: 512x512 MAC grid, 5-level V({sweeps},{sweeps}) CAV multigrid "
+                               f"({a.smoother} smoother, alpha {alpha:g}), 4 open fibres L=0.4 "
                                f"ds=h/2, kappa_b={a.kappa_b:g}, kappa_s=1e4, rho=1 mu=0.01 dt=1e-3, seeded U[-1,1] "
                                "RHS, FGMRES rtol 1e-10; value = T_total (operator + patches + factors + solve)",
-                   "precision": a.precision, "smoother": a.smoother, "alpha": alpha, "tune": a.tune},
+                   "precision": a.precision, "smoother": a.smoother, "alpha": alpha, "sweeps": sweeps,
+                   "tune": a.tune},
         "t_solve_ms": round(float(np.median(solve_ms)), 3),
         "per_step": {k: (float("%.4g" % v) if isinstance(v, float) else v) for k, v in last.items()
                      if k not in ("stats", "fst", "kt", "x")},
@@ -901,7 +1013,7 @@ def main():
     }
     if table is not None:
         line["tuning_table"] = np.asarray(table).tolist()
-    if a.tune != "auto" and not a.no_autotune_report:
+    if a.smoother == "multiplicative" and a.tune != "auto" and not a.no_autotune_report:
         # the autotuner on the same hierarchy, reported beside the timed table
         setup(a.precision)
         tuned = g.autotune(reps=3)
@@ -924,12 +1036,15 @@ def main():
         del o
     if not a.no_membrane:
         line["membrane256"] = membrane_leg(dev)
-    if not a.no_additive:
-        line["additive_v33"] = additive_sweeps_leg(dev)
+    if not a.no_paper_v11:
+        other_sm = "multiplicative" if a.smoother == "additive" else "additive"
+        line["multiplicative_v11" if other_sm == "multiplicative" else "additive_v33"] = (
+            paper_v11_leg(dev, a.kappa_b) if other_sm == "multiplicative" else additive_sweeps_leg(dev))
     if a.multi_rhs > 0:
         # the V-cycle on blocks of 16 right-hand sides (explicit phases as FP64
         # MFMA products) against one cycle per column, outside the timed steps
         setup(a.precision)
+        g.set_smoother("multiplicative", 1.0)
         gen = torch.Generator(device=dev)
         gen.manual_seed(5)
         R = torch.randn((a.multi_rhs, b.numel()), generator=gen, dtype=torch.float64, device=dev)
@@ -982,16 +1097,23 @@ def main():
         g.build_operator(sk)
         g.build_cav_patches("cav")
         g.factor_patches(a.precision, 1e6)
-        g.set_smoother(a.smoother, alpha)
-        t0s = time.perf_counter()
-        _, inf = g.fgmres_solve(torch.from_numpy(sk.b).to(dev), rtol=1e-10, max_it=150)
-        torch.cuda.synchronize()
-        sweep.append({"kappa_b": kb, "iterations": inf["iterations"], "converged": inf["converged"],
-                      "est_rel_residual": float("%.4g" % inf["est_rel_residual"]),
-                      "solve_ms": round(1e3 * (time.perf_counter() - t0s), 1)})
+        row = {"kappa_b": kb}
+        for sm, al, sw in ((a.smoother, alpha, sweeps), ("multiplicative", 1.0, 1)):
+            key = f"{sm}_v{sw}{sw}"
+            if key in row:
+                continue
+            g.set_smoother(sm, al, sw, sw)
+            t0s = time.perf_counter()
+            _, inf = g.fgmres_solve(torch.from_numpy(sk.b).to(dev), rtol=1e-10, max_it=150)
+            torch.cuda.synchronize()
+            row[key] = {"iterations": inf["iterations"], "converged": inf["converged"],
+                        "est_rel_residual": float("%.4g" % inf["est_rel_residual"]),
+                        "solve_ms": round(1e3 * (time.perf_counter() - t0s), 1)}
+        sweep.append(row)
     line["stiffness_sweep"] = sweep
     if a.learned_pairs > 0:
         setup("mixed")
+        g.set_smoother("multiplicative", 1.0)
         line["learned"] = learned_leg(g, b, a.learned_pairs, a.learned_steps)
     if a.learned_c5:
         line["learned_c5"] = learned_c5_leg(dev, eval_precision=a.learned_c5_eval_precision)
@@ -1005,7 +1127,8 @@ def main():
     if a.batch > 0:
         line["batched"] = batched_leg(a.batch, 150)
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(a.kappa_b, last["its"], a.smoother, gpu_full)
+        line["cpu_baseline"] = cpu_baseline(a.kappa_b, last["its"], a.smoother, gpu_full, alpha=alpha,
+                                            sweeps=sweeps)
     print(json.dumps(line))
 
 
