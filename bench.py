@@ -480,6 +480,28 @@ def membrane_leg(dev, kappas=(1e2, 1e4, 1e6)):
                         "FGMRES rtol 1e-10", "runs": out}
 
 
+def read_calibration(nbytes: int):
+    """A plain streaming read of known size (torch's sum over float64), timed
+    with events: the read rate HBM sustains on this part, for comparing a
+    kernel's achieved bandwidth with what a pure read stream reaches."""
+    import torch
+    n = nbytes // 8
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        x.sum()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        x.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"read_bytes": n * 8, "us_per_read": round(1e3 * ms, 2),
+                      "read_gbs": round(n * 8 / (ms * 1e-3) / 1e9, 1)}))
+
+
 def copy_calibration(nbytes: int):
     """A plain device-to-device copy of known size, for scaling HBM counters."""
     import torch
@@ -888,6 +910,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, help="run only a plain copy of this many bytes")
+    ap.add_argument("--calibrate-read", type=int, default=0,
+                    help="run only a plain streaming read of this many bytes and print its rate")
     ap.add_argument("--summarize-counters", default="",
                     help="print per-kernel dispatch counts and mean values of a rocprofv3 counter CSV, then exit")
     a = ap.parse_args()
@@ -896,6 +920,9 @@ def main():
         return
     if a.calibrate_copy:
         copy_calibration(a.calibrate_copy)
+        return
+    if a.calibrate_read:
+        read_calibration(a.calibrate_read)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))

@@ -36,8 +36,15 @@ constexpr int AS_UNROLL = 4;
 // half the block, G = NT / nr column groups split the columns (group g takes
 // j = g, g + G, ...) and their partial sums are added in group order, so
 // small patches keep the block's loads in flight. Partial sums use
-// AS_UNROLL accumulators added pairwise at the end.
-template <typename T, int NT>
+// AS_UNROLL accumulators added pairwise at the end. STREAM: non-temporal
+// loads of the inverse, for a level whose factors exceed the last-level
+// cache and are read once per sweep.
+template <typename T>
+__device__ __forceinline__ T ld_factor(const T* p, bool stream) {
+  return stream ? __builtin_nontemporal_load(p) : *p;
+}
+
+template <typename T, int NT, bool STREAM>
 __device__ __forceinline__ void patch_gemv(const PatchRec& rec, const T* __restrict__ arena,
                                            const int32_t* __restrict__ slot_dof, const double* __restrict__ r,
                                            double* __restrict__ delta, unsigned char* smem) {
@@ -62,7 +69,7 @@ __device__ __forceinline__ void patch_gemv(const PatchRec& rec, const T* __restr
         int j = 0;
         for (; j + U <= n; j += U)
 #pragma unroll
-          for (int u = 0; u < U; ++u) a[u] += col[int64_t(j + u) * n] * xs[j + u];
+          for (int u = 0; u < U; ++u) a[u] += ld_factor(col + int64_t(j + u) * n, STREAM) * xs[j + u];
         for (; j < n; ++j) a[0] += col[int64_t(j) * n] * xs[j];
         delta[rec.slot + i] = double((a[0] + a[2]) + (a[1] + a[3]));
       }
@@ -78,7 +85,7 @@ __device__ __forceinline__ void patch_gemv(const PatchRec& rec, const T* __restr
     int j = g;
     for (; j + (U - 1) * G < n; j += U * G)
 #pragma unroll
-      for (int u = 0; u < U; ++u) a[u] += col[int64_t(j + u * G) * n] * xs[j + u * G];
+      for (int u = 0; u < U; ++u) a[u] += ld_factor(col + int64_t(j + u * G) * n, STREAM) * xs[j + u * G];
     for (; j < n; j += G) a[0] += col[int64_t(j) * n] * xs[j];
   }
   if (g < G) part[g * nr + i] = (a[0] + a[2]) + (a[1] + a[3]);
@@ -149,6 +156,7 @@ __device__ __forceinline__ void add_std_cell(int N, int64_t c, const uint8_t* __
   else x[2 * n2 + c] = (zero ? 0.0 : x[2 * n2 + c]) + alpha * sp;
 }
 
+template <bool STREAM>
 __global__ __launch_bounds__(AS_THREADS) void k_add_smooth(
     int p64, const PatchRec* __restrict__ rec64, const double* __restrict__ f64, int p32,
     const PatchRec* __restrict__ rec32, const float* __restrict__ f32, const int32_t* __restrict__ slot_dof,
@@ -157,9 +165,9 @@ __global__ __launch_bounds__(AS_THREADS) void k_add_smooth(
   extern __shared__ unsigned char smem_raw[];
   const int blk = int(blockIdx.x);
   if (blk < p64) {
-    patch_gemv<double, AS_THREADS>(rec64[blk], f64, slot_dof, r, delta, smem_raw);
+    patch_gemv<double, AS_THREADS, STREAM>(rec64[blk], f64, slot_dof, r, delta, smem_raw);
   } else if (blk < p64 + p32) {
-    patch_gemv<float, AS_THREADS>(rec32[blk - p64], f32, slot_dof, r, delta, smem_raw);
+    patch_gemv<float, AS_THREADS, STREAM>(rec32[blk - p64], f32, slot_dof, r, delta, smem_raw);
   } else {
     const int64_t c = int64_t(blk - p64 - p32) * AS_THREADS + threadIdx.x;
     if (c < int64_t(N) * N) add_std_cell(N, c, flag, Minv, r, z, x, alpha, zero != 0);
@@ -1558,10 +1566,18 @@ void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_gue
   const size_t lds = (size_t(maxn) + 2 + AS_THREADS) * sizeof(double);
   const unsigned grid = unsigned(p64 + p32) + unsigned((n2 + AS_THREADS - 1) / AS_THREADS);
   const double al = level_alpha(c, L);
+  // factors beyond the 256 MB last-level cache are streamed (read once per
+  // sweep); smaller levels keep theirs cached between sweeps
+  const bool stream = L.bytes64 + L.bytes32 > 256e6;
   timing_begin(c, s);
-  k_add_smooth<<<grid, AS_THREADS, lds, s>>>(p64, L.d_rec64, L.d_f64, p32, L.d_rec32, L.d_f32, L.d_slot_dof,
-                                             L.d_delta, L.N, L.d_cellflag, L.d_std_inv, r, L.d_z, x, al,
-                                             zero_guess ? 1 : 0);
+  if (stream)
+    k_add_smooth<true><<<grid, AS_THREADS, lds, s>>>(p64, L.d_rec64, L.d_f64, p32, L.d_rec32, L.d_f32, L.d_slot_dof,
+                                                     L.d_delta, L.N, L.d_cellflag, L.d_std_inv, r, L.d_z, x, al,
+                                                     zero_guess ? 1 : 0);
+  else
+    k_add_smooth<false><<<grid, AS_THREADS, lds, s>>>(p64, L.d_rec64, L.d_f64, p32, L.d_rec32, L.d_f32, L.d_slot_dof,
+                                                      L.d_delta, L.N, L.d_cellflag, L.d_std_inv, r, L.d_z, x, al,
+                                                      zero_guess ? 1 : 0);
   timing_end(c, s, L.bytes64 + L.bytes32 + 72.0 * double(n2));
   if (L.n_touched > 0)
     k_touched<<<nblocks(int64_t(L.n_touched) * TOUCH_LANES), TPB, 0, s>>>(
