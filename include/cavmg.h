@@ -232,8 +232,12 @@ cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold,
 /* Smoother choice (kind = CAV_SMOOTHER_*). Additive (Appendix A,
  * Eq. additive_cav_saddle): w <- w + alpha sum_p R_p^T Theta_p K_p^{-1} R_p (b - K w),
  * Theta_p = diag(1/cnt). Multiplicative (Section 3.3): for each patch in the
- * coloured order, w <- w + alpha R_p^T K_p^{-1} R_p (b - K w). Both remove the
- * mean pressure after the sweep. pre/post = sweeps per V-cycle leg (1, 1). */
+ * coloured order, w <- w + alpha R_p^T K_p^{-1} R_p (b - K w). A stand-alone
+ * sweep (cav_level_apply) removes the mean pressure after it; inside a
+ * V-cycle the mean is removed once, after the top level's last sweep (K_E
+ * does not see a constant pressure, so the cycle's output is the same up to
+ * rounding). pre/post = sweeps per V-cycle leg, each starting from the iterate
+ * the previous one left (the paper's cycle is (1, 1)). */
 cav_status cav_set_smoother(cav_ctx ctx, int kind, double alpha, int pre, int post);
 /* Multiplicative phase order (reading: the paper visits patches
  * lexicographically, Section 3.3): CAV_ORDER_STANDARD_FIRST (default) runs
