@@ -483,7 +483,7 @@ def membrane_leg(dev, kappas=(1e2, 1e4, 1e6)):
         out.append(row)
     return {"workload": "membrane256: 256x256, ellipse 0.2/0.15, 6 levels, FGMRES rtol 1e-10", "runs": out}
 
-def read_calibration(nbytes: int):
+def measure_read(nbytes: int) -> dict:
     """A plain streaming read of known size (torch's sum over float64), timed
     with events: the read rate HBM sustains on this part, for comparing a
     kernel's achieved bandwidth with what a pure read stream reaches."""
@@ -501,8 +501,12 @@ def read_calibration(nbytes: int):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    print(json.dumps({"read_bytes": n * 8, "us_per_read": round(1e3 * ms, 2),
-                      "read_gbs": round(n * 8 / (ms * 1e-3) / 1e9, 1)}))
+    del x
+    return {"read_bytes": n * 8, "us_per_read": round(1e3 * ms, 2), "read_gbs": round(n * 8 / (ms * 1e-3) / 1e9, 1)}
+
+
+def read_calibration(nbytes: int):
+    print(json.dumps(measure_read(nbytes)))
 
 
 def copy_calibration(nbytes: int):
@@ -1041,6 +1045,15 @@ def main():
                      "bytes_per_launch": int(kb_bytes / max(kb_launch, 1)),
                      "avg_launch_us": round(1e3 * kb_ms / max(kb_launch, 1), 3)},
     }
+    line["solves_per_s"] = round(1e3 / ms_per_step, 2)
+    # the read rate a plain stream reaches on this part, over the size of the
+    # finest level's stored inverses (far beyond the last-level cache)
+    fin = last["stats"][s.n_levels - 1]
+    rc = measure_read(int(max(fin["sum_np2"] * (8 if a.precision == "fp64" else 4), 1 << 28)))
+    line["read_calibration"] = dict(rc, what="torch.sum over float64 of the finest level's factor-arena size")
+    if last["kt"]["vcycle_ms"]:
+        line["vcycle_frac_of_read"] = round(bv / (last["kt"]["vcycle_ms"] * 1e-3) / 1e9 / rc["read_gbs"], 4)
+    line["roofline"]["frac_of_read"] = round(achieved / rc["read_gbs"], 4)
     if table is not None:
         line["tuning_table"] = np.asarray(table).tolist()
     if a.smoother == "multiplicative" and a.tune != "auto" and not a.no_autotune_report:
