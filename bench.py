@@ -235,6 +235,16 @@ def vcycle_bytes(stats, fst, N: int, n_levels: int, precision: str, sweeps: int 
     return total + nc * nc * 8.0
 
 
+# storage of the patch inverses for the additive smoother: the symmetric
+# panel layout (lower panels only) unless --layout full; the multiplicative
+# kernels always get the full layout
+ADD_LAYOUT = "symmetric"
+
+
+def _layout(smoother: str) -> str:
+    return ADD_LAYOUT if smoother == "additive" else "full"
+
+
 def additive_leg(dev, reps: int = 10, membrane: bool = True):
     """North-star smoother (Appendix A, weighted additive CAV, alpha 0.7): its
     V-cycle on the 512^2 beam system (FGMRES with it stalls there, so only
@@ -247,7 +257,7 @@ def additive_leg(dev, reps: int = 10, membrane: bool = True):
     from paper_2608_14310_amd import Solver
     s = workloads.beam_512(1e-2)
     g = Solver(0)
-    stats, fst = g.setup(s, precision="fp64", alpha=0.7, smoother="additive")
+    stats, fst = g.setup(s, precision="fp64", alpha=0.7, smoother="additive", layout=_layout("additive"))
     b = torch.from_numpy(s.b).to(dev)
     for _ in range(2):
         g.vcycle(b)
@@ -262,7 +272,8 @@ def additive_leg(dev, reps: int = 10, membrane: bool = True):
     pa_bytes = kt["bytes"] - kt["coop_bytes"] - kt["flow_bytes"]
     pa_launch = kt["launches"] - kt["coop_launches"] - kt["flow_launches"]
     pa_gbs = pa_bytes / (pa_ms * 1e-3) / 1e9 if pa_ms > 0 else 0.0
-    out = {"workload": "beam512 (as the headline), weighted additive CAV V(1,1), alpha 0.7, FP64 factors",
+    out = {"workload": "beam512 (as the headline), weighted additive CAV V(1,1), alpha 0.7, FP64 factors, "
+                       f"{_layout('additive')} layout",
            "vcycle_ms": round(kt["vcycle_ms"], 4), "vcycles_per_s": round(1e3 / kt["vcycle_ms"], 1),
            "vcycle_bytes": int(bv), "vcycle_gbs": round(bv / (kt["vcycle_ms"] * 1e-3) / 1e9, 1),
            "vcycle_frac": round(bv / (kt["vcycle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -280,7 +291,7 @@ def additive_leg(dev, reps: int = 10, membrane: bool = True):
     rows = {}
     for smoother, alpha in (("additive", 0.7), ("multiplicative", 1.0)):
         g = Solver(0)
-        g.setup(sm, precision="fp64", alpha=alpha, smoother=smoother)
+        g.setup(sm, precision="fp64", alpha=alpha, smoother=smoother, layout=_layout(smoother))
         g.fgmres_solve(bm, rtol=1e-10, max_it=150)     # warm-up
         times = []
         for _ in range(3):
@@ -317,10 +328,11 @@ def additive_sweeps_leg(dev, alpha: float = 0.9, sweeps: int = 3):
     s = workloads.beam_512(1e-2)
     b = torch.from_numpy(s.b).to(dev)
     g = Solver(0)
-    out = {"workload": f"beam512 (as the headline), weighted additive CAV, alpha {alpha:g}, V({sweeps},{sweeps})"}
+    out = {"workload": f"beam512 (as the headline), weighted additive CAV, alpha {alpha:g}, V({sweeps},{sweeps}), "
+                       f"{_layout('additive')} layout"}
     xs = {}
     for prec in ("fp64", "mixed"):
-        stats, fst = g.setup(s, precision=prec, alpha=alpha, smoother="additive")
+        stats, fst = g.setup(s, precision=prec, alpha=alpha, smoother="additive", layout=_layout("additive"))
         g.set_smoother("additive", alpha, sweeps, sweeps)
         g.fgmres_solve(b, rtol=1e-10, max_it=150)      # warm-up
         best = None
@@ -458,7 +470,7 @@ def membrane_leg(dev, kappas=(1e2, 1e4, 1e6)):
             xs = {}
             row[key] = {}
             for prec in ("fp64", "mixed"):
-                g.setup(sm, precision=prec, alpha=alpha, smoother=smoother)
+                g.setup(sm, precision=prec, alpha=alpha, smoother=smoother, layout=_layout(smoother))
                 g.set_smoother(smoother, alpha, sweeps, sweeps)
                 g.fgmres_solve(bm, rtol=1e-10, max_it=150)      # warm-up
                 torch.cuda.synchronize()
@@ -882,6 +894,9 @@ def main():
     ap.add_argument("--alpha", type=float, default=None, help="damping (default 0.9 additive, 1 multiplicative)")
     ap.add_argument("--sweeps", type=int, default=None,
                     help="pre- and post-sweeps per level (default 3 additive, 1 multiplicative)")
+    ap.add_argument("--layout", default="symmetric", choices=["symmetric", "full"],
+                    help="storage of the patch inverses for the additive smoother (the multiplicative one always "
+                         "reads the full layout)")
     ap.add_argument("--kappa-b", type=float, default=1e-2)
     ap.add_argument("--stiff-sweep", type=float, nargs="*", default=[1.0, 1e2])
     ap.add_argument("--tune", default="default",
@@ -945,10 +960,14 @@ def main():
     import workloads
     from paper_2608_14310_amd import Solver
 
+    global ADD_LAYOUT
+    ADD_LAYOUT = a.layout
+    layout = _layout(a.smoother)
     dev = torch.device("cuda", 0)
     s = workloads.beam_512(a.kappa_b)
     b = torch.from_numpy(s.b).to(dev)
     g = Solver(0)
+    g.set_factor_layout(layout)
     alpha = a.alpha if a.alpha is not None else (1.0 if a.smoother == "multiplicative" else 0.9)
     sweeps = a.sweeps if a.sweeps is not None else (1 if a.smoother == "multiplicative" else 3)
     table = None
@@ -1030,7 +1049,7 @@ def main():
                                f"ds=h/2, kappa_b={a.kappa_b:g}, kappa_s=1e4, rho=1 mu=0.01 dt=1e-3, seeded U[-1,1] "
                                "RHS, FGMRES rtol 1e-10; value = T_total (operator + patches + factors + solve)",
                    "precision": a.precision, "smoother": a.smoother, "alpha": alpha, "sweeps": sweeps,
-                   "tune": a.tune},
+                   "factor_layout": layout, "tune": a.tune},
         "t_solve_ms": round(float(np.median(solve_ms)), 3),
         "per_step": {k: (float("%.4g" % v) if isinstance(v, float) else v) for k, v in last.items()
                      if k not in ("stats", "fst", "kt", "x")},
@@ -1047,10 +1066,9 @@ def main():
     }
     line["solves_per_s"] = round(1e3 / ms_per_step, 2)
     # the read rate a plain stream reaches on this part, over the size of the
-    # finest level's stored inverses (far beyond the last-level cache)
-    fin = last["stats"][s.n_levels - 1]
-    rc = measure_read(int(max(fin["sum_np2"] * (8 if a.precision == "fp64" else 4), 1 << 28)))
-    line["read_calibration"] = dict(rc, what="torch.sum over float64 of the finest level's factor-arena size")
+    # stored inverses (far beyond the last-level cache)
+    rc = measure_read(int(max(last["fst"]["factor_bytes"], 1 << 28)))
+    line["read_calibration"] = dict(rc, what="torch.sum over float64 of the stored factor bytes of all levels")
     if last["kt"]["vcycle_ms"]:
         line["vcycle_frac_of_read"] = round(bv / (last["kt"]["vcycle_ms"] * 1e-3) / 1e9 / rc["read_gbs"], 4)
     line["roofline"]["frac_of_read"] = round(achieved / rc["read_gbs"], 4)
@@ -1086,6 +1104,7 @@ def main():
     if a.multi_rhs > 0:
         # the V-cycle on blocks of 16 right-hand sides (explicit phases as FP64
         # MFMA products) against one cycle per column, outside the timed steps
+        g.set_factor_layout("full")
         setup(a.precision)
         g.set_smoother("multiplicative", 1.0)
         gen = torch.Generator(device=dev)
@@ -1107,6 +1126,7 @@ def main():
                              "ms_per_column": round(1e3 * tm / a.multi_rhs, 3),
                              "single_cycle_ms_per_column": round(1e3 * tc / a.multi_rhs, 3),
                              "speedup": round(tc / tm, 2), "max_rel_diff_vs_single": float("%.3g" % diff)}
+        g.set_factor_layout(layout)
     if a.fibre_grids:
         line["fibre"] = fibre_leg(a.fibre_grids)
         line["fibre_robustness"] = fibre_robustness_leg()
@@ -1118,7 +1138,7 @@ def main():
     if not a.no_cpu_baseline:
         st32 = workloads.small_target(0)
         g32 = Solver(0)
-        g32.setup(st32, precision="fp64", alpha=0.7, smoother="additive")
+        g32.setup(st32, precision="fp64", alpha=0.7, smoother="additive", layout=_layout("additive"))
         b32 = torch.from_numpy(st32.b).to(dev)
         g32.fgmres_solve(b32, rtol=1e-10, max_it=150)
         torch.cuda.synchronize()
@@ -1139,12 +1159,13 @@ def main():
         sk = workloads.beam_512(kb)
         g.build_operator(sk)
         g.build_cav_patches("cav")
-        g.factor_patches(a.precision, 1e6)
         row = {"kappa_b": kb}
         for sm, al, sw in ((a.smoother, alpha, sweeps), ("multiplicative", 1.0, 1)):
             key = f"{sm}_v{sw}{sw}"
             if key in row:
                 continue
+            g.set_factor_layout(_layout(sm))
+            g.factor_patches(a.precision, 1e6)
             g.set_smoother(sm, al, sw, sw)
             t0s = time.perf_counter()
             _, inf = g.fgmres_solve(torch.from_numpy(sk.b).to(dev), rtol=1e-10, max_it=150)
@@ -1155,6 +1176,7 @@ def main():
         sweep.append(row)
     line["stiffness_sweep"] = sweep
     if a.learned_pairs > 0:
+        g.set_factor_layout("full")
         setup("mixed")
         g.set_smoother("multiplicative", 1.0)
         line["learned"] = learned_leg(g, b, a.learned_pairs, a.learned_steps)

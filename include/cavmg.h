@@ -82,6 +82,8 @@ enum { CAV_SMOOTHER_ADDITIVE = 0, CAV_SMOOTHER_MULTIPLICATIVE = 1 };
 /* Order of the two groups of phases in every multiplicative sweep. */
 enum { CAV_ORDER_EXPLICIT_FIRST = 0, CAV_ORDER_STANDARD_FIRST = 1 };  /* default: STANDARD_FIRST */
 enum { CAV_PREC_FP64 = 0, CAV_PREC_MIXED = 1 };            /* factor storage policy */
+/* Storage of the explicit patch inverses (cav_set_factor_layout). */
+enum { CAV_LAYOUT_FULL = 0, CAV_LAYOUT_SYMMETRIC = 1 };    /* default: FULL */
 
 typedef struct {
   int32_t N;         /* finest cells per side; power of two, N >> (n_levels-1) >= 4 */
@@ -229,6 +231,20 @@ cav_status cav_build_cav_patches(cav_ctx ctx, int family, cav_level_stats* out);
  * elsewhere; out[l].n_patches is the number of boxes. */
 cav_status cav_build_box_patches(cav_ctx ctx, int b, int o, cav_level_stats* out);
 cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold, cav_factor_stats* out);
+/* Layout of the stored patch inverses, used from the next cav_factor_patches
+ * on (layout = CAV_LAYOUT_*). K_E is symmetric (Eq. intro_saddle with the
+ * divergence -D = G^T; A and E_E = S E J symmetric), so every K_p = R_p K_E
+ * R_p^T and its inverse are symmetric. CAV_LAYOUT_FULL stores all n_p^2
+ * entries, column-major. CAV_LAYOUT_SYMMETRIC stores n_p^2 / 2 + 8 n_p of
+ * them: for panel k = 0 .. ceil(n_p/16) - 1, columns 16k .. 16k + w - 1
+ * (w = min(16, n_p - 16k)) on rows 16k .. n_p - 1, column-major inside the
+ * panel, panels consecutive (panel k starts at 16 k n_p - 128 k (k - 1));
+ * entries above the panels' diagonal 16 x 16 blocks are taken from their
+ * mirror images (the computed inverse is symmetric up to rounding). Only the
+ * additive smoother reads the symmetric layout: with it, a V-cycle, sweep or
+ * solve on a level whose smoother is multiplicative, and cav_autotune,
+ * return CAV_ERR_INVALID_ARG. factor_bytes reports the stored bytes. */
+cav_status cav_set_factor_layout(cav_ctx ctx, int layout);
 /* Smoother choice (kind = CAV_SMOOTHER_*). Additive (Appendix A,
  * Eq. additive_cav_saddle): w <- w + alpha sum_p R_p^T Theta_p K_p^{-1} R_p (b - K w),
  * Theta_p = diag(1/cnt). Multiplicative (Section 3.3): for each patch in the

@@ -200,6 +200,7 @@ _SIGS = {
     "cav_set_level_smoother": ([_P, C.c_int, C.c_int, C.c_double], C.c_int),
     "cav_error_propagation": ([_P, C.c_int32, _P, _P], C.c_int),
     "cav_set_phase_order": ([_P, C.c_int], C.c_int),
+    "cav_set_factor_layout": ([_P, C.c_int], C.c_int),
     "cav_set_wait_limit": ([_P, C.c_uint32], C.c_int),
     "cav_build_box_patches": ([_P, C.c_int, C.c_int, C.POINTER(LevelStats)], C.c_int),
     "cav_analyze_box": ([C.POINTER(GridDesc), C.POINTER(StructureDesc), C.c_int, C.c_int, C.POINTER(_P)], C.c_int),
@@ -577,13 +578,19 @@ class Solver:
         """Multiplicative sweep order: 'standard_first' (default) or 'explicit_first'."""
         self._check(self._L.cav_set_phase_order(self._h, {"explicit_first": 0, "standard_first": 1}[order]))
 
+    def set_factor_layout(self, layout: str = "full") -> None:
+        """Storage of the patch inverses from the next factorisation on: 'full'
+        (default) or 'symmetric' (lower panels only; additive smoother only)."""
+        self._check(self._L.cav_set_factor_layout(self._h, {"full": 0, "symmetric": 1}[layout]))
+
     def set_level_smoother(self, level: int, kind: Optional[str], alpha: float = 0.7) -> None:
         """Override the smoother of one smoothed level (None restores the context's)."""
         self._check(self._L.cav_set_level_smoother(self._h, int(level), -1 if kind is None else SMOOTHER[kind],
                                                    float(alpha)))
 
     def setup(self, system, family="cav", precision="fp64", cond_threshold=1e6, alpha=0.7, smoother="additive",
-              box=(4, 2)):
+              box=(4, 2), layout="full"):
+        self.set_factor_layout(layout)
         self.build_operator(system)
         stats = self.build_cav_patches(family, box)
         fstats = self.factor_patches(precision, cond_threshold)

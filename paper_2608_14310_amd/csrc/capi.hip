@@ -398,6 +398,15 @@ void require(bool ok, cav_status st, const char* msg) {
   if (!ok) throw StatusError(st, msg);
 }
 
+// Factored patches, and no multiplicative level over inverses in the
+// symmetric panel layout (the multiplicative kernels read full inverses).
+void require_factored(const Ctx& c, const char* msg) {
+  require(c.factored, CAV_ERR_NOT_BUILT, msg);
+  for (int l = 1; l < c.n_levels; ++l)
+    require(!c.lv[l].packed || level_smoother(c, c.lv[l]) != CAV_SMOOTHER_MULTIPLICATIVE, CAV_ERR_INVALID_ARG,
+            "the multiplicative smoother reads full patch inverses: set CAV_LAYOUT_FULL and factor again");
+}
+
 // Top-level V-cycle on the finest level, timed when live timing is on.
 void vcycle_top(Ctx& c, const double* r, double* z) {
   int start = -1;
@@ -707,7 +716,7 @@ struct KrylovWs {
 
 // Arguments shared by the FGMRES entry points; returns max_it.
 int check_fgmres_args(const Ctx& c, const double* b, const double* x, const cav_fgmres_opts* opts) {
-  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require_factored(c, "cav_factor_patches has not succeeded");
   require(b && x && b != x, CAV_ERR_INVALID_ARG, "b and x must be distinct device pointers");
   const double rtol = opts ? opts->rtol : 1e-10;
   const int max_it = opts ? opts->max_it : 150;
@@ -1088,7 +1097,10 @@ static cav_status build_family(cav_ctx ctx, int family, int box_b, int box_o, ca
         [] {});
     run_levels(
         [&](Level& L) {
-          if (family != CAV_FAMILY_BOX) build_patch_tables(L.N, L.ee, L);
+          // the colour phases only feed the multiplicative kernels, which
+          // need the full layout: under the symmetric one they wait for a
+          // full-layout factorisation or a phase export
+          if (family != CAV_FAMILY_BOX) build_patch_tables(L.N, L.ee, L, c.layout == CAV_LAYOUT_FULL);
         },
         [&] {
           ensure_aux_streams(c);
@@ -1203,6 +1215,16 @@ cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold,
   API_END
 }
 
+cav_status cav_set_factor_layout(cav_ctx ctx, int layout) {
+  if (!ctx) return CAV_ERR_INVALID_ARG;
+  if (layout != CAV_LAYOUT_FULL && layout != CAV_LAYOUT_SYMMETRIC) {
+    ctx->c.err = "unknown factor layout";
+    return CAV_ERR_INVALID_ARG;
+  }
+  ctx->c.layout = layout;
+  return CAV_OK;
+}
+
 cav_status cav_set_smoother(cav_ctx ctx, int kind, double alpha, int pre, int post) {
   if (!ctx) return CAV_ERR_INVALID_ARG;
   if (!std::isfinite(alpha) || pre < 0 || post < 0 || pre + post < 1 ||
@@ -1234,7 +1256,7 @@ cav_status cav_vcycle(cav_ctx ctx, const double* r, double* z) {
   if (!ctx) return CAV_ERR_INVALID_ARG;
   Ctx& c = ctx->c;
   API_BEGIN
-  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require_factored(c, "cav_factor_patches has not succeeded");
   require(r && z && r != z, CAV_ERR_INVALID_ARG, "r and z must be distinct device pointers");
   vcycle_top(c, r, z);
   CAV_HIP(hipGetLastError());
@@ -1320,7 +1342,8 @@ cav_status cav_level_apply(cav_ctx ctx, int level, int op, const double* x, doub
       break;
     }
     case 3:
-      require(c.factored && level >= 1, CAV_ERR_NOT_BUILT, "smoother needs factored patches on level >= 1");
+      require(level >= 1, CAV_ERR_NOT_BUILT, "smoother needs factored patches on level >= 1");
+      require_factored(c, "smoother needs factored patches on level >= 1");
       launch_smoother(c, L, x, y, true, s);
       break;
     case 4:
@@ -1328,7 +1351,7 @@ cav_status cav_level_apply(cav_ctx ctx, int level, int op, const double* x, doub
       launch_coarse_solve(c, x, y, s);
       break;
     case 5:
-      require(c.factored, CAV_ERR_NOT_BUILT, "V-cycle needs factored patches");
+      require_factored(c, "V-cycle needs factored patches");
       vcycle_level(c, level, x, y);
       break;
     default: throw StatusError(CAV_ERR_INVALID_ARG, "unknown op");
@@ -1360,13 +1383,16 @@ cav_status cav_export_phases(cav_ctx ctx, int level, int32_t* ptr, int32_t* cell
     c.err = "no patches on this level";
     return CAV_ERR_NOT_BUILT;
   }
-  const Level& L = c.lv[level];
+  Level& L = c.lv[level];
+  API_BEGIN
+  if (!L.coloured) colour_explicit(L.N, L.ee, L);
   if (n_phases) *n_phases = int32_t(L.ph_ptr.size()) - 1;
   if (n_cells) *n_cells = int32_t(L.ph_exp.size());
   if (ptr) std::memcpy(ptr, L.ph_ptr.data(), L.ph_ptr.size() * sizeof(int32_t));
   if (cells)
     for (size_t k = 0; k < L.ph_exp.size(); ++k) cells[k] = L.exp_cells[L.ph_exp[k]];
   return CAV_OK;
+  API_END
 }
 
 cav_status cav_kernel_timing(cav_ctx ctx, int enable, cav_kernel_timing_info* out) {
@@ -1446,7 +1472,7 @@ cav_status cav_learned_pairs(cav_ctx ctx, int32_t count, const double* xstar, in
   if (!ctx) return CAV_ERR_INVALID_ARG;
   Ctx& c = ctx->c;
   API_BEGIN
-  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require_factored(c, "cav_factor_patches has not succeeded");
   require(count >= 0 && iters >= 1 && iters <= 64, CAV_ERR_INVALID_ARG, "count >= 0 and 1 <= iters <= 64");
   if (count == 0) return CAV_OK;
   require(xstar && rhat && ehat, CAV_ERR_INVALID_ARG, "xstar, rhat and ehat must be device pointers");
@@ -1568,7 +1594,7 @@ cav_status cav_fgmres_solve_graph(cav_ctx ctx, const double* b, double* x, const
   if (!ctx) return CAV_ERR_INVALID_ARG;
   Ctx& c = ctx->c;
   API_BEGIN
-  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require_factored(c, "cav_factor_patches has not succeeded");
   require(b && x && b != x, CAV_ERR_INVALID_ARG, "b and x must be distinct device pointers");
   require(!(opts && opts->use_learned), CAV_ERR_INVALID_ARG, "the graph solve has no learned stage");
   const double rtol = opts ? opts->rtol : 1e-10;
@@ -1613,7 +1639,7 @@ cav_status cav_batch_solve(cav_ctx* ctxs, int32_t n_sys, const double* const* b,
   require(max_it >= 1 && max_it <= 10000 && rtol >= 0.0, CAV_ERR_INVALID_ARG, "bad FGMRES options");
   for (int i = 0; i < n_sys; ++i) {
     Ctx& c = ctxs[i]->c;
-    require(c.factored, CAV_ERR_NOT_BUILT, "every context must be factored");
+    require_factored(c, "every context must be factored");
     require(c.device == c0.device, CAV_ERR_INVALID_ARG, "all contexts must share a device");
     require(b[i] && x[i] && b[i] != x[i], CAV_ERR_INVALID_ARG, "b and x must be distinct device pointers");
     for (int j = 0; j < i; ++j) require(ctxs[j] != ctxs[i], CAV_ERR_INVALID_ARG, "a context appears twice");
@@ -1740,8 +1766,11 @@ cav_status cav_autotune(cav_ctx ctx, int32_t reps, int32_t* table) {
   if (!ctx) return CAV_ERR_INVALID_ARG;
   Ctx& c = ctx->c;
   API_BEGIN
-  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require_factored(c, "cav_factor_patches has not succeeded");
   require(reps >= 1 && reps <= 1000, CAV_ERR_INVALID_ARG, "reps must be in [1, 1000]");
+  for (int l = 1; l < c.n_levels; ++l)
+    require(!c.lv[l].packed, CAV_ERR_INVALID_ARG,
+            "cav_autotune times the multiplicative phase kernels, which read full patch inverses");
   hipStream_t s = c.stream;
   hipEvent_t e0, e1;
   CAV_HIP(hipEventCreate(&e0));
@@ -1866,7 +1895,7 @@ cav_status cav_vcycle_multi(cav_ctx ctx, int32_t k, const double* R, double* Z) 
   if (!ctx) return CAV_ERR_INVALID_ARG;
   Ctx& c = ctx->c;
   API_BEGIN
-  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require_factored(c, "cav_factor_patches has not succeeded");
   require(k >= 0, CAV_ERR_INVALID_ARG, "k must be non-negative");
   if (k == 0) return CAV_OK;
   require(R && Z && R != Z, CAV_ERR_INVALID_ARG, "R and Z must be distinct device pointers");
@@ -1883,7 +1912,7 @@ cav_status cav_error_propagation(cav_ctx ctx, int32_t k, const double* X, double
   if (!ctx) return CAV_ERR_INVALID_ARG;
   Ctx& c = ctx->c;
   API_BEGIN
-  require(c.factored, CAV_ERR_NOT_BUILT, "cav_factor_patches has not succeeded");
+  require_factored(c, "cav_factor_patches has not succeeded");
   require(k >= 0, CAV_ERR_INVALID_ARG, "k must be non-negative");
   if (k == 0) return CAV_OK;
   require(X && T && X != T, CAV_ERR_INVALID_ARG, "X and T must be distinct device pointers");

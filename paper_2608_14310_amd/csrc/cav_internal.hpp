@@ -20,6 +20,28 @@ struct HostCSR {
   int64_t nnz() const { return rowptr.empty() ? 0 : rowptr.back(); }
 };
 
+// Symmetric panel layout of one explicit patch inverse (n x n): panel k
+// holds columns 16k .. 16k + w - 1 (w = min(16, n - 16k)) on rows 16k .. n - 1,
+// column-major inside the panel (column stride n - 16k); panels are stored
+// one after the other.
+constexpr int SYM_P = 16;
+__host__ __device__ inline int64_t sym_panel_off(int n, int k) {
+  return int64_t(SYM_P) * k * n - int64_t(SYM_P * SYM_P / 2) * k * (k - 1);
+}
+__host__ __device__ inline int64_t sym_size(int n) {
+  if (n <= 0) return 0;
+  const int t = (n + SYM_P - 1) / SYM_P, w = n - SYM_P * (t - 1);
+  return sym_panel_off(n, t - 1) + int64_t(w) * w;
+}
+// Work items of the symmetric GEMV: (64-row chunk R, panel k) for every
+// panel with a row in the chunk, k <= min(4R + 3, panels - 1).
+__host__ __device__ inline int sym_items(int n) {
+  const int t = (n + SYM_P - 1) / SYM_P, nr = (n + 63) / 64;
+  int items = 0;
+  for (int R = 0; R < nr; ++R) items += (4 * R + 4 < t ? 4 * R + 4 : t);
+  return items;
+}
+
 // One explicit patch as the device kernels see it.
 struct PatchRec {
   int32_t n;        // unknowns in the patch
@@ -164,6 +186,8 @@ struct Level {
   double* d_f64 = nullptr;
   float* d_f32 = nullptr;
   double bytes64 = 0, bytes32 = 0;        // algorithmic bytes of one GEMV launch per precision
+  bool packed = false;                    // inverses in the symmetric panel layout
+  bool coloured = false;                  // ph_ptr / ph_exp / pred hold this patch set's colour phases
 
   // per-level vectors (3 N^2)
   double *d_b = nullptr, *d_x = nullptr, *d_r = nullptr, *d_z = nullptr;
@@ -242,6 +266,7 @@ struct Ctx {
   bool std_first = true;   // multiplicative sweep: shared-patch colours before the explicit phases
   uint32_t wait_limit = 1u << 21;  // polls of a bounded workgroup-barrier wait before it gives up
   int smoother = CAV_SMOOTHER_ADDITIVE;
+  int layout = CAV_LAYOUT_FULL;   // patch-inverse storage of the next factorisation
   // interpolation J and spreading S at the structure positions of the last
   // operator build: per Lagrangian row its 16 faces and kernel weights; per
   // touched velocity face its rows and the weights omega * w / h^2
@@ -349,7 +374,9 @@ void build_patches(int N, const HostCSR& ee, int family, Level& L);
 // the two halves of build_patches: the patch sets (all a factorisation
 // needs), then the unknown -> slot transpose, weights, colouring and stats
 void build_patch_sets(int N, const HostCSR& ee, int family, Level& L);
-void build_patch_tables(int N, const HostCSR& ee, Level& L);
+// colour = false leaves the multiplicative colour phases to a later
+// colour_explicit call (they are only read by the multiplicative smoother).
+void build_patch_tables(int N, const HostCSR& ee, Level& L, bool colour = true);
 void build_box_patches(int N, const HostCSR& ee, int b, int o, Level& L);
 
 // ---- device launches (kernels_*.hip) ----
@@ -469,4 +496,10 @@ struct StatusError {
   std::string msg;
   StatusError(cav_status s, std::string m) : st(s), msg(std::move(m)) {}
 };
+// The multiplicative kernels read full column-major patch inverses.
+inline void require_full_layout(const Level& L) {
+  if (L.packed)
+    throw StatusError(CAV_ERR_INVALID_ARG,
+                      "the multiplicative smoother reads full patch inverses: set CAV_LAYOUT_FULL and factor again");
+}
 }  // namespace cav

@@ -396,6 +396,44 @@ __global__ __launch_bounds__(256) void k_finalize(const PatchRec* __restrict__ w
     }
 }
 
+// The same inverse in the symmetric panel layout (sym_panel_off): only the
+// entries on or below the panels' diagonal blocks, i >= 16 floor(j / 16), so
+// only the 64 x 64 tiles with j0 <= i0; the writes run down each stored
+// column (consecutive i).
+template <typename T>
+__global__ __launch_bounds__(256) void k_finalize_sym(const PatchRec* __restrict__ wrec,
+                                                      const PatchRec* __restrict__ orec,
+                                                      const double* __restrict__ work, const double* __restrict__ rs,
+                                                      const double* __restrict__ cs, const int32_t* __restrict__ sigma,
+                                                      const int32_t* __restrict__ rowp, T* __restrict__ out) {
+  __shared__ double tile[64][65];
+  const PatchRec w = wrec[blockIdx.x];
+  const PatchRec o = orec[blockIdx.x];
+  const int n = w.n;
+  const double* W = work + w.fac;
+  const double* r = rs + w.slot;
+  const double* c = cs + w.slot;
+  const int32_t* sg = sigma + w.slot;
+  const int32_t* rw = rowp + w.slot;
+  T* M = out + o.fac;
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  for (int i0 = 0; i0 < n; i0 += 64)
+    for (int j0 = 0; j0 <= i0; j0 += 64) {
+      for (int ii = grp; ii < 64; ii += 4) {
+        const int i = i0 + ii, j = j0 + lane;
+        if (i < n && j < n && i >= (j & ~(SYM_P - 1))) tile[ii][lane] = c[i] * W[int64_t(rw[i]) * n + sg[j]] * r[j];
+      }
+      __syncthreads();
+      for (int jj = grp; jj < 64; jj += 4) {
+        const int i = i0 + lane, j = j0 + jj;
+        const int k = j / SYM_P, c0 = SYM_P * k;
+        if (i < n && j < n && i >= c0)
+          M[sym_panel_off(n, k) + int64_t(j - c0) * (n - c0) + (i - c0)] = T(tile[lane][jj]);
+      }
+      __syncthreads();
+    }
+}
+
 // ------------------------------------------------------ coarsest level ---
 // The coarsest level is solved through an explicit inverse (Section 4). K_0 =
 // [[A, G], [G^T, 0]] is symmetric with A (velocity) SPD and G^T = -D, and
@@ -800,10 +838,11 @@ void factor_level_finish(Ctx& c, Level& L, FactorPending& fp, int precision, dou
   std::vector<PatchRec> w64, o64, w32, o32;
   int64_t a64 = 0, a32 = 0;
   double maxc = 0.0;
+  const bool packed = c.layout == CAV_LAYOUT_SYMMETRIC;
   for (auto& r : exp_only) {
     maxc = std::max(maxc, kap_h[r.id]);
     const bool f32 = precision == CAV_PREC_MIXED && kap_h[r.id] <= cond_threshold;
-    const int64_t sz = int64_t(r.n) * r.n;
+    const int64_t sz = packed ? sym_size(r.n) : int64_t(r.n) * r.n;
     if (f32) {
       w32.push_back(r);
       o32.push_back(PatchRec{r.n, r.id, r.slot, a32});
@@ -822,13 +861,20 @@ void factor_level_finish(Ctx& c, Level& L, FactorPending& fp, int precision, dou
   if (!w64.empty()) {
     PatchRec* dw = upload(c, w64);
     PatchRec* dout = upload(c, o64);
-    k_finalize<double><<<unsigned(w64.size()), 256, 0, s>>>(dw, dout, work, rs, cs, sig, rowp, L.d_f64);
+    if (packed)
+      k_finalize_sym<double><<<unsigned(w64.size()), 256, 0, s>>>(dw, dout, work, rs, cs, sig, rowp, L.d_f64);
+    else
+      k_finalize<double><<<unsigned(w64.size()), 256, 0, s>>>(dw, dout, work, rs, cs, sig, rowp, L.d_f64);
   }
   if (!w32.empty()) {
     PatchRec* dw = upload(c, w32);
     PatchRec* dout = upload(c, o32);
-    k_finalize<float><<<unsigned(w32.size()), 256, 0, s>>>(dw, dout, work, rs, cs, sig, rowp, L.d_f32);
+    if (packed)
+      k_finalize_sym<float><<<unsigned(w32.size()), 256, 0, s>>>(dw, dout, work, rs, cs, sig, rowp, L.d_f32);
+    else
+      k_finalize<float><<<unsigned(w32.size()), 256, 0, s>>>(dw, dout, work, rs, cs, sig, rowp, L.d_f32);
   }
+  L.packed = packed;
   {
     std::vector<PatchRec> so = {PatchRec{5, ne, std_slot, 0}};
     PatchRec* dout = upload(c, so);
@@ -840,13 +886,16 @@ void factor_level_finish(Ctx& c, Level& L, FactorPending& fp, int precision, dou
   if (L.d_rec32) dev_free(c, L.d_rec32);
   L.rec64_h = o64;
   L.rec32_h = o32;
-  // algorithmic bytes of one GEMV launch: factors n^2 s, slot indices 4n, gathered r 8n, delta 8n
+  // algorithmic bytes of one GEMV launch: the stored factors (n^2 entries, or
+  // sym_size(n) in the symmetric layout), slot indices 4n, gathered r 8n, delta 8n
   L.bytes64 = 0;
   L.bytes32 = 0;
-  for (auto& r : o64) L.bytes64 += double(r.n) * r.n * 8 + 20.0 * r.n;
-  for (auto& r : o32) L.bytes32 += double(r.n) * r.n * 4 + 20.0 * r.n;
+  for (auto& r : o64) L.bytes64 += double(packed ? sym_size(r.n) : int64_t(r.n) * r.n) * 8 + 20.0 * r.n;
+  for (auto& r : o32) L.bytes32 += double(packed ? sym_size(r.n) : int64_t(r.n) * r.n) * 4 + 20.0 * r.n;
   // multiplicative phases: records in colour order, each naming its arena
-  {
+  // (not built over symmetric-layout inverses, which those kernels cannot read)
+  if (!packed && !L.coloured) colour_explicit(N, L.ee, L);
+  if (!packed) {
     std::vector<MultRec> byid(ne);
     for (auto& r : o64) byid[r.id] = MultRec{r.n, 0, r.slot, r.fac};
     for (auto& r : o32) byid[r.id] = MultRec{r.n, 1, r.slot, r.fac};

@@ -39,9 +39,14 @@ constexpr int AS_UNROLL = 4;
 // AS_UNROLL accumulators added pairwise at the end. STREAM: non-temporal
 // loads of the inverse, for a level whose factors exceed the last-level
 // cache and are read once per sweep.
-template <typename T>
-__device__ __forceinline__ T ld_factor(const T* p, bool stream) {
-  return stream ? __builtin_nontemporal_load(p) : *p;
+// (a compile-time choice: a run-time select between the two loads of the
+// same address is merged into one plain load)
+template <bool STREAM, typename T>
+__device__ __forceinline__ T ld_factor(const T* p) {
+  if constexpr (STREAM)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
 }
 
 template <typename T, int NT, bool STREAM>
@@ -69,7 +74,7 @@ __device__ __forceinline__ void patch_gemv(const PatchRec& rec, const T* __restr
         int j = 0;
         for (; j + U <= n; j += U)
 #pragma unroll
-          for (int u = 0; u < U; ++u) a[u] += ld_factor(col + int64_t(j + u) * n, STREAM) * xs[j + u];
+          for (int u = 0; u < U; ++u) a[u] += ld_factor<STREAM>(col + int64_t(j + u) * n) * xs[j + u];
         for (; j < n; ++j) a[0] += col[int64_t(j) * n] * xs[j];
         delta[rec.slot + i] = double((a[0] + a[2]) + (a[1] + a[3]));
       }
@@ -85,7 +90,7 @@ __device__ __forceinline__ void patch_gemv(const PatchRec& rec, const T* __restr
     int j = g;
     for (; j + (U - 1) * G < n; j += U * G)
 #pragma unroll
-      for (int u = 0; u < U; ++u) a[u] += ld_factor(col + int64_t(j + u * G) * n, STREAM) * xs[j + u * G];
+      for (int u = 0; u < U; ++u) a[u] += ld_factor<STREAM>(col + int64_t(j + u * G) * n) * xs[j + u * G];
     for (; j < n; j += G) a[0] += col[int64_t(j) * n] * xs[j];
   }
   if (g < G) part[g * nr + i] = (a[0] + a[2]) + (a[1] + a[3]);
@@ -94,6 +99,157 @@ __device__ __forceinline__ void patch_gemv(const PatchRec& rec, const T* __restr
     T sum = part[threadIdx.x];
     for (int q = 1; q < G; ++q) sum += part[q * nr + threadIdx.x];
     delta[rec.slot + threadIdx.x] = double(sum);
+  }
+}
+
+// Cross-lane moves of 32-bit words, applied to each word of a T.
+template <typename T, typename F>
+__device__ __forceinline__ T per_word(T v, F f) {
+  constexpr int W = sizeof(T) / 4;
+  struct Words { uint32_t w[W]; };
+  Words a = __builtin_bit_cast(Words, v);
+#pragma unroll
+  for (int k = 0; k < W; ++k) a.w[k] = f(a.w[k]);
+  return __builtin_bit_cast(T, a);
+}
+// {x, y} -> {x with lanes 32..63 taken from y's lanes 0..31, y with lanes
+// 0..31 taken from x's lanes 32..63} (ROWS = 32), or the same between the odd
+// 16-lane rows of x and the even rows of y (ROWS = 16): afterwards x + y is,
+// in every lane, its own value plus the partner lane's (l ^ ROWS) of the
+// value it keeps (x below the split, y above it).
+template <int ROWS, typename T>
+__device__ __forceinline__ void swap_halves(T& x, T& y) {
+  constexpr int W = sizeof(T) / 4;
+  struct Words { uint32_t w[W]; };
+  Words a = __builtin_bit_cast(Words, x), b = __builtin_bit_cast(Words, y);
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const auto r = ROWS == 32 ? __builtin_amdgcn_permlane32_swap(a.w[k], b.w[k], false, false)
+                              : __builtin_amdgcn_permlane16_swap(a.w[k], b.w[k], false, false);
+    a.w[k] = r[0];
+    b.w[k] = r[1];
+  }
+  x = __builtin_bit_cast(T, a);
+  y = __builtin_bit_cast(T, b);
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp(T v) {
+  return per_word(v, [](uint32_t w) { return uint32_t(__builtin_amdgcn_update_dpp(0, int(w), CTRL, 0xf, 0xf, false)); });
+}
+constexpr int DPP_XOR1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+constexpr int DPP_XOR8 = 0x128;  // row_ror:8 within 16-lane rows
+
+// 16 partial sums per lane (t[q] for panel column q) reduced over the 64
+// lanes of a wavefront. Lane bits 5, 4, 3 and 0 halve the values in turn (each
+// lane keeps one half, adds its partner's copy of that half and hands the
+// other half over), bits 1 and 2 then add partners' sums. Lane l ends with
+// the sum of column (l & 1) + 2 ((l >> 3) & 1) + 4 ((l >> 4) & 1) + 8 (l >> 5),
+// identical in the four lanes that differ in bits 1 and 2; a fixed order.
+template <typename T>
+__device__ __forceinline__ T wave_colsum16(T (&t)[SYM_P], int lane) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    swap_halves<32>(t[q], t[q + 8]);
+    t[q] += t[q + 8];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    swap_halves<16>(t[q], t[q + 4]);
+    t[q] += t[q + 4];
+  }
+  const bool b3 = lane & 8, b0 = lane & 1;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const T keep = b3 ? t[q + 2] : t[q], send = b3 ? t[q] : t[q + 2];
+    t[q] = keep + dpp<DPP_XOR8>(send);
+  }
+  T x;
+  {
+    const T keep = b0 ? t[1] : t[0], send = b0 ? t[0] : t[1];
+    x = keep + dpp<DPP_XOR1>(send);
+  }
+  x += dpp<DPP_XOR2>(x);
+  x += per_word(x, [](uint32_t w) { return uint32_t(__builtin_amdgcn_ds_swizzle(int(w), 0x101F)); });  // lane ^ 4
+  return x;
+}
+
+// delta[slot + i] = sum_j M[i][j] r[dof_j] for one explicit patch whose
+// symmetric inverse is stored in the panel layout (sym_panel_off). Work items
+// (64-row chunk R, panel k), dealt round-robin to the block's wavefronts:
+// lane l takes row i = 64 R + l and loads its w entries of the panel (one
+// contiguous column segment per load), adds M[i][j] q_j over the panel's
+// columns (the direct part, every row of the panel) and, for rows below the
+// panel's diagonal block, forms M[i][j] q_i, whose sum over the chunk's rows
+// is M[j][i]'s contribution to row j (the mirrored part, reduced across the
+// wavefront). Both partials go to LDS; row i then adds its direct partials
+// over panels k <= i / 16 and its mirrored partials over chunks R >=
+// (i / 16) / 4, in that fixed order.
+template <typename T, int NT, bool STREAM>
+__device__ __forceinline__ void patch_gemv_sym(const PatchRec& rec, const T* __restrict__ arena,
+                                               const int32_t* __restrict__ slot_dof, const double* __restrict__ r,
+                                               double* __restrict__ delta, unsigned char* smem) {
+  constexpr int NW = NT / 64;
+  const int n = rec.n;
+  const int np = (n + SYM_P - 1) / SYM_P, nr = (n + 63) / 64;
+  const int items = sym_items(n);
+  T* xs = reinterpret_cast<T*>(smem);
+  T* dpart = xs + ((n + 1) & ~1);          // items x 64
+  T* tpart = dpart + int64_t(items) * 64;  // items x 16
+  const int32_t* dofs = slot_dof + rec.slot;
+  for (int i = threadIdx.x; i < n; i += NT) xs[i] = T(r[dofs[i]]);
+  __syncthreads();
+  const T* M = arena + rec.fac;
+  // the item loop is uniform over a wavefront: its indices live in scalar
+  // registers and each load is a scalar column base plus the lane's row offset
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int R = 0, base = 0, cnt = np < 4 ? np : 4;
+  for (int it = wave; it < items; it += NW) {
+    while (it >= base + cnt) {
+      base += cnt;
+      ++R;
+      cnt = 4 * R + 4 < np ? 4 * R + 4 : np;
+    }
+    const int k = it - base;
+    const int c0 = SYM_P * k, m = n - c0, w = m < SYM_P ? m : SYM_P;
+    const int i = 64 * R + lane;
+    const bool in = i >= c0 && i < n;
+    const T* pan = M + sym_panel_off(n, k);
+    // lanes outside the panel read its first row (same line) and drop it
+    const uint32_t off = in ? uint32_t(i - c0) : 0u;
+    T v[SYM_P];
+    if (w == SYM_P) {
+#pragma unroll
+      for (int q = 0; q < SYM_P; ++q) v[q] = ld_factor<STREAM>(pan + int64_t(q) * m + off);
+    } else {
+#pragma unroll
+      for (int q = 0; q < SYM_P; ++q) v[q] = q < w ? ld_factor<STREAM>(pan + int64_t(q) * m + off) : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < SYM_P; ++q) v[q] = in ? v[q] : T(0);
+    T a[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < SYM_P; ++q) a[q & 3] += v[q] * (q < w ? xs[c0 + q] : T(0));
+    dpart[it * 64 + lane] = (a[0] + a[2]) + (a[1] + a[3]);
+    const T qi = (in && i >= c0 + w) ? xs[i] : T(0);
+#pragma unroll
+    for (int q = 0; q < SYM_P; ++q) v[q] *= qi;
+    const T tsum = wave_colsum16(v, lane);
+    if ((lane & 6) == 0) tpart[it * 16 + ((lane & 1) | ((lane >> 2) & 14))] = tsum;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const int ri = i >> 6, ki = i / SYM_P;
+    int pre = 0;  // first item of chunk ri
+    for (int q = 0; q < ri; ++q) pre += 4 * q + 4 < np ? 4 * q + 4 : np;
+    T sum = T(0);
+    for (int k = 0; k <= ki; ++k) sum += dpart[(pre + k) * 64 + (i & 63)];
+    int pr = 0;  // first item of chunk q, for q from 0
+    for (int q = 0; q < nr; ++q) {
+      if (q >= (ki >> 2)) sum += tpart[(pr + ki) * 16 + (i & 15)];
+      pr += 4 * q + 4 < np ? 4 * q + 4 : np;
+    }
+    delta[rec.slot + i] = double(sum);
   }
 }
 
@@ -156,7 +312,7 @@ __device__ __forceinline__ void add_std_cell(int N, int64_t c, const uint8_t* __
   else x[2 * n2 + c] = (zero ? 0.0 : x[2 * n2 + c]) + alpha * sp;
 }
 
-template <bool STREAM>
+template <bool STREAM, bool SYM>
 __global__ __launch_bounds__(AS_THREADS) void k_add_smooth(
     int p64, const PatchRec* __restrict__ rec64, const double* __restrict__ f64, int p32,
     const PatchRec* __restrict__ rec32, const float* __restrict__ f32, const int32_t* __restrict__ slot_dof,
@@ -165,9 +321,15 @@ __global__ __launch_bounds__(AS_THREADS) void k_add_smooth(
   extern __shared__ unsigned char smem_raw[];
   const int blk = int(blockIdx.x);
   if (blk < p64) {
-    patch_gemv<double, AS_THREADS, STREAM>(rec64[blk], f64, slot_dof, r, delta, smem_raw);
+    if (SYM)
+      patch_gemv_sym<double, AS_THREADS, STREAM>(rec64[blk], f64, slot_dof, r, delta, smem_raw);
+    else
+      patch_gemv<double, AS_THREADS, STREAM>(rec64[blk], f64, slot_dof, r, delta, smem_raw);
   } else if (blk < p64 + p32) {
-    patch_gemv<float, AS_THREADS, STREAM>(rec32[blk - p64], f32, slot_dof, r, delta, smem_raw);
+    if (SYM)
+      patch_gemv_sym<float, AS_THREADS, STREAM>(rec32[blk - p64], f32, slot_dof, r, delta, smem_raw);
+    else
+      patch_gemv<float, AS_THREADS, STREAM>(rec32[blk - p64], f32, slot_dof, r, delta, smem_raw);
   } else {
     const int64_t c = int64_t(blk - p64 - p32) * AS_THREADS + threadIdx.x;
     if (c < int64_t(N) * N) add_std_cell(N, c, flag, Minv, r, z, x, alpha, zero != 0);
@@ -1410,6 +1572,7 @@ static int phase_form(const Ctx& c, const Level& L, int nt) {
 
 void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_guess, hipStream_t s,
                           bool remove_mean) {
+  require_full_layout(L);
   const int64_t n2 = int64_t(L.N) * L.N, n = 3 * n2;
   if (zero_guess) launch_fill(x, 0.0, n, s);
   const int nph = int(L.ph_ptr.size()) - 1;
@@ -1449,6 +1612,7 @@ void launch_mult_smoother(Ctx& c, Level& L, const double* b, double* x, bool zer
 }
 
 void launch_mult_phase(Ctx& c, Level& L, int ph, int nt, const double* b, double* x, hipStream_t s) {
+  require_full_layout(L);
   const int a = L.ph_ptr[ph], cnt = L.ph_ptr[ph + 1] - a;
   const unsigned g = unsigned(cnt);
   nt = phase_form(c, L, nt);
@@ -1525,6 +1689,7 @@ void launch_smoother_multi(Ctx& c, Level& L, const double* b, double* x, int64_t
     for (int q = 0; q < kb; ++q) launch_smoother(c, L, b + q * ldv, x + q * ldv, zero_guess, s, remove_mean);
     return;
   }
+  require_full_layout(L);
   if (zero_guess)
     for (int q = 0; q < kb; ++q) launch_fill(x + q * ldv, 0.0, n, s);
   const int nph = int(L.ph_ptr.size()) - 1;
@@ -1563,21 +1728,24 @@ void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_gue
   int maxn = 0;
   if (p64) maxn = L.rec64_h[0].n;
   if (p32) maxn = std::max(maxn, L.rec32_h[0].n);
-  const size_t lds = (size_t(maxn) + 2 + AS_THREADS) * sizeof(double);
+  // LDS: the gathered residual and either the column-group partials or the
+  // symmetric form's direct (64 per item) and mirrored (16 per item) partials
+  const size_t lds = L.packed ? (size_t(maxn) + 2 + size_t(sym_items(maxn)) * 80) * sizeof(double)
+                              : (size_t(maxn) + 2 + AS_THREADS) * sizeof(double);
   const unsigned grid = unsigned(p64 + p32) + unsigned((n2 + AS_THREADS - 1) / AS_THREADS);
   const double al = level_alpha(c, L);
   // factors beyond the 256 MB last-level cache are streamed (read once per
   // sweep); smaller levels keep theirs cached between sweeps
   const bool stream = L.bytes64 + L.bytes32 > 256e6;
+  auto go = [&](auto kern) {
+    kern<<<grid, AS_THREADS, lds, s>>>(p64, L.d_rec64, L.d_f64, p32, L.d_rec32, L.d_f32, L.d_slot_dof, L.d_delta, L.N,
+                                       L.d_cellflag, L.d_std_inv, r, L.d_z, x, al, zero_guess ? 1 : 0);
+  };
   timing_begin(c, s);
-  if (stream)
-    k_add_smooth<true><<<grid, AS_THREADS, lds, s>>>(p64, L.d_rec64, L.d_f64, p32, L.d_rec32, L.d_f32, L.d_slot_dof,
-                                                     L.d_delta, L.N, L.d_cellflag, L.d_std_inv, r, L.d_z, x, al,
-                                                     zero_guess ? 1 : 0);
+  if (L.packed)
+    stream ? go(k_add_smooth<true, true>) : go(k_add_smooth<false, true>);
   else
-    k_add_smooth<false><<<grid, AS_THREADS, lds, s>>>(p64, L.d_rec64, L.d_f64, p32, L.d_rec32, L.d_f32, L.d_slot_dof,
-                                                      L.d_delta, L.N, L.d_cellflag, L.d_std_inv, r, L.d_z, x, al,
-                                                      zero_guess ? 1 : 0);
+    stream ? go(k_add_smooth<true, false>) : go(k_add_smooth<false, false>);
   timing_end(c, s, L.bytes64 + L.bytes32 + 72.0 * double(n2));
   if (L.n_touched > 0)
     k_touched<<<nblocks(int64_t(L.n_touched) * TOUCH_LANES), TPB, 0, s>>>(

@@ -615,6 +615,7 @@ void visit_unknown_reach(int N, const HostCSR& ee, int64_t d, V&& visit) {
 void colour_explicit(int N, const HostCSR& ee, Level& L) {
   const int64_t n2 = int64_t(N) * N;
   const int ne = L.n_exp;
+  L.coloured = true;
   L.ph_ptr.assign(1, 0);
   L.ph_exp.clear();
   if (ne == 0) return;
@@ -973,7 +974,7 @@ void build_patch_sets(int N, const HostCSR& ee, int family, Level& L) {
   L.n_slots = int64_t(L.slot_dof_h.size());
 }
 
-void build_patch_tables(int N, const HostCSR& ee, Level& L) {
+void build_patch_tables(int N, const HostCSR& ee, Level& L, bool colour) {
   const int64_t n2 = int64_t(N) * N, nv = 2 * n2, n = 3 * n2;
   // unknown -> slots transpose (counting sort, slots ascending within each unknown)
   std::vector<int32_t> nsl(n + 1, 0);
@@ -1011,7 +1012,8 @@ void build_patch_tables(int N, const HostCSR& ee, Level& L) {
   }
   L.n_touched = int32_t(L.t_dof_h.size());
   mark_touched(N, L);
-  colour_explicit(N, ee, L);
+  L.coloured = false;
+  if (colour) colour_explicit(N, ee, L);
 
   // stats
   cav_level_stats& st = L.stats;

@@ -36,12 +36,12 @@ def _system(g):
     return workloads.membrane_256(g["kappa_s"], seed=g["seed"])
 
 
-def _solve(g, precision):
+def _solve(g, precision, layout="full"):
     from paper_2608_14310_amd import Solver
     s = _system(g)
     sol = Solver(0)
     try:
-        sol.setup(s, precision=precision, alpha=g["alpha"], smoother=g["smoother"])
+        sol.setup(s, precision=precision, alpha=g["alpha"], smoother=g["smoother"], layout=layout)
         sweeps = g.get("pre", 1)
         sol.set_smoother(g["smoother"], g["alpha"], sweeps, g.get("post", sweeps))
         if g["smoother"] == "multiplicative":
@@ -61,14 +61,28 @@ def _errors(x, g):
     return e_norm, e_samp
 
 
+ADDITIVE = [p for p in GOLDENS if "_additive" in os.path.basename(p)]
+
+
 @pytest.mark.parametrize("path", GOLDENS, ids=[os.path.basename(p)[:-5] for p in GOLDENS])
 def test_fgmres_matches_oracle_golden(path):
+    _check_fp64(path, "full")
+
+
+@pytest.mark.parametrize("path", ADDITIVE, ids=[os.path.basename(p)[:-5] for p in ADDITIVE])
+def test_symmetric_layout_matches_oracle_golden(path):
+    """The additive cycles with the patch inverses in the symmetric panel
+    layout (lower panels stored, upper entries mirrored): the same bounds."""
+    _check_fp64(path, "symmetric")
+
+
+def _check_fp64(path, layout):
     with open(path) as f:
         g = json.load(f)
-    print(f"[golden] {g['name']}: oracle {g['iterations']} iterations", flush=True)
-    x, info = _solve(g, "fp64")
+    print(f"[golden] {g['name']} ({layout} layout): oracle {g['iterations']} iterations", flush=True)
+    x, info = _solve(g, "fp64", layout)
     e_norm, e_samp = _errors(x, g)
-    print(f"[golden] {g['name']} fp64: {info['iterations']} iterations, true {info['true_rel_residual']:.2e}, "
+    print(f"[golden] {g['name']} fp64 {layout}: {info['iterations']} iterations, true {info['true_rel_residual']:.2e}, "
           f"norm err {e_norm:.1e}, sampled err {e_samp:.1e}", flush=True)
     assert info["converged"] == int(g["converged"])
     assert info["iterations"] == g["iterations"]
