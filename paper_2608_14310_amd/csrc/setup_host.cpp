@@ -867,13 +867,7 @@ void build_patch_sets(int N, const HostCSR& ee, int family, Level& L) {
   auto rowlen = [&](int64_t d) { return ee.rowptr[d + 1] - ee.rowptr[d]; };
   L.cellflag.assign(n2, 0);
   L.patch_off.assign(n2 + 1, 0);
-  L.patch_dofs.clear();
-  L.patch_dofs.reserve(size_t(n2) * 5 + 1024);
-  L.exp_cells.clear();
-  L.exp_off.assign(1, 0);
-  L.exp_cov_off.assign(1, 0);
-  L.exp_cov.clear();
-  L.slot_dof_h.clear();
+
   // rows of cells in parallel; each range keeps its own output, merged in order
   struct Part {
     std::vector<int32_t> dofs, plen, ecells, slot, elen, cov, clen;
@@ -951,24 +945,47 @@ void build_patch_sets(int N, const HostCSR& ee, int family, Level& L) {
       }
     }
   });
+  // concatenate the rows' parts in row order: offsets by prefix sums, then
+  // every row copies its part in parallel (each writes only its own ranges)
   {
-    int64_t c = 0;
-    for (auto& P : parts) {
-      for (int32_t len : P.plen) {
-        L.patch_off[c + 1] = L.patch_off[c] + len;
-        ++c;
-      }
-      L.patch_dofs.insert(L.patch_dofs.end(), P.dofs.begin(), P.dofs.end());
-      for (size_t k = 0; k < P.ecells.size(); ++k) {
-        L.cellflag[P.ecells[k]] |= 1;
-        L.exp_cells.push_back(P.ecells[k]);
-        L.exp_off.push_back(L.exp_off.back() + P.elen[k]);
-      }
-      L.slot_dof_h.insert(L.slot_dof_h.end(), P.slot.begin(), P.slot.end());
-      for (int32_t cc : P.cov) L.cellflag[cc] |= 2;
-      for (int32_t len : P.clen) L.exp_cov_off.push_back(L.exp_cov_off.back() + len);
-      L.exp_cov.insert(L.exp_cov.end(), P.cov.begin(), P.cov.end());
+    std::vector<int64_t> od(N + 1, 0), oe(N + 1, 0), os(N + 1, 0), oc(N + 1, 0);
+    for (int r = 0; r < N; ++r) {
+      const Part& P = parts[r];
+      od[r + 1] = od[r] + int64_t(P.dofs.size());
+      oe[r + 1] = oe[r] + int64_t(P.ecells.size());
+      os[r + 1] = os[r] + int64_t(P.slot.size());
+      oc[r + 1] = oc[r] + int64_t(P.cov.size());
     }
+    L.patch_dofs.resize(size_t(od[N]));
+    L.exp_cells.resize(size_t(oe[N]));
+    L.exp_off.assign(size_t(oe[N]) + 1, 0);
+    L.slot_dof_h.resize(size_t(os[N]));
+    L.exp_cov.resize(size_t(oc[N]));
+    L.exp_cov_off.assign(size_t(oe[N]) + 1, 0);
+    parallel_items(
+        N, 8, [] { return 0; },
+        [&](int&, int64_t r) {
+          const Part& P = parts[r];
+          int64_t a = od[r];
+          for (int j = 0; j < N; ++j) {
+            a += P.plen[j];
+            L.patch_off[r * N + j + 1] = a;
+          }
+          std::copy(P.dofs.begin(), P.dofs.end(), L.patch_dofs.begin() + od[r]);
+          std::copy(P.slot.begin(), P.slot.end(), L.slot_dof_h.begin() + os[r]);
+          std::copy(P.cov.begin(), P.cov.end(), L.exp_cov.begin() + oc[r]);
+          int64_t sa = os[r], ca = oc[r];
+          for (size_t k = 0; k < P.ecells.size(); ++k) {
+            const int64_t e = oe[r] + int64_t(k);
+            L.exp_cells[size_t(e)] = P.ecells[k];
+            L.cellflag[P.ecells[k]] |= 1;   // a row's own cells
+            sa += P.elen[k];
+            ca += P.clen[k];
+            L.exp_off[size_t(e) + 1] = sa;
+            L.exp_cov_off[size_t(e) + 1] = ca;
+          }
+        });
+    for (int32_t cc : L.exp_cov) L.cellflag[cc] |= 2;   // cells of other rows too: serial
   }
   L.n_exp = int32_t(L.exp_cells.size());
   L.n_slots = int64_t(L.slot_dof_h.size());
