@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def measured_traffic(kernel: str, precision: str, smoother: str, tune: str):
+def measured_traffic(kernel: str, precision: str, smoother: str, tune: str, layout: str = "full"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     passes (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
     counter reads for a plain copy of known size), or None when no pass
@@ -45,7 +45,8 @@ def measured_traffic(kernel: str, precision: str, smoother: str, tune: str):
             rec = json.load(f).get(kernel)
     except (OSError, ValueError):
         return None
-    if not rec or rec["precision"] != precision or rec["smoother"] != smoother or rec.get("tune", "default") != tune:
+    if (not rec or rec["precision"] != precision or rec["smoother"] != smoother or rec.get("tune", "default") != tune
+            or rec.get("layout", "full") != layout):
         return None
     with open(os.path.join(ROOT, rec["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
@@ -279,7 +280,8 @@ def additive_leg(dev, reps: int = 10, membrane: bool = True):
            "vcycle_frac": round(bv / (kt["vcycle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "k_add_smooth": {"bound": "hbm", "achieved": round(pa_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(pa_gbs / HBM_PEAK_GBS, 4),
-                             "traffic": measured_traffic("k_add_smooth", "fp64", "additive", "default"),
+                             "traffic": measured_traffic("k_add_smooth", "fp64", "additive", "default",
+                                                         _layout("additive")),
                              "launches": pa_launch,
                              "bytes_per_launch": int(pa_bytes / max(pa_launch, 1)),
                              "avg_launch_us": round(1e3 * pa_ms / max(pa_launch, 1), 3)}}
@@ -1059,7 +1061,7 @@ def main():
         "vcycle_gbs": round(bv / (last["kt"]["vcycle_ms"] * 1e-3) / 1e9, 1) if last["kt"]["vcycle_ms"] else None,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(kernel, a.precision, a.smoother, a.tune),
+                     "traffic": measured_traffic(kernel, a.precision, a.smoother, a.tune, layout),
                      "kernel": kernel, "launches": kb_launch,
                      "bytes_per_launch": int(kb_bytes / max(kb_launch, 1)),
                      "avg_launch_us": round(1e3 * kb_ms / max(kb_launch, 1), 3)},

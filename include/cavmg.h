@@ -238,12 +238,14 @@ cav_status cav_factor_patches(cav_ctx ctx, int precision, double cond_threshold,
  * entries, column-major. CAV_LAYOUT_SYMMETRIC stores n_p^2 / 2 + 8 n_p of
  * them: for panel k = 0 .. ceil(n_p/16) - 1, columns 16k .. 16k + w - 1
  * (w = min(16, n_p - 16k)) on rows 16k .. n_p - 1, column-major inside the
- * panel, panels consecutive (panel k starts at 16 k n_p - 128 k (k - 1));
+ * panel with column stride n16 - 16k (n16 = n_p rounded up to a multiple of
+ * 16, so columns start on 16-entry boundaries; the padding is never read),
+ * panels consecutive (panel k starts at 16 k n16 - 128 k (k - 1));
  * entries above the panels' diagonal 16 x 16 blocks are taken from their
  * mirror images (the computed inverse is symmetric up to rounding). Only the
  * additive smoother reads the symmetric layout: with it, a V-cycle, sweep or
  * solve on a level whose smoother is multiplicative, and cav_autotune,
- * return CAV_ERR_INVALID_ARG. factor_bytes reports the stored bytes. */
+ * return CAV_ERR_INVALID_ARG. factor_bytes counts the stored entries. */
 cav_status cav_set_factor_layout(cav_ctx ctx, int layout);
 /* Smoother choice (kind = CAV_SMOOTHER_*). Additive (Appendix A,
  * Eq. additive_cav_saddle): w <- w + alpha sum_p R_p^T Theta_p K_p^{-1} R_p (b - K w),

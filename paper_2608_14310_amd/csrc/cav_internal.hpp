@@ -22,16 +22,27 @@ struct HostCSR {
 
 // Symmetric panel layout of one explicit patch inverse (n x n): panel k
 // holds columns 16k .. 16k + w - 1 (w = min(16, n - 16k)) on rows 16k .. n - 1,
-// column-major inside the panel (column stride n - 16k); panels are stored
-// one after the other.
+// column-major inside the panel; panels are stored one after the other. A
+// column is stored with n16 - 16k slots, n16 = n rounded up to a multiple of
+// 16, so every column (and every 64-row chunk of one) starts on a 16-entry
+// boundary; the padding slots are never read.
 constexpr int SYM_P = 16;
+__host__ __device__ inline int sym_n16(int n) { return (n + SYM_P - 1) & ~(SYM_P - 1); }
+// offset of panel k (its column stride is sym_n16(n) - 16k)
 __host__ __device__ inline int64_t sym_panel_off(int n, int k) {
-  return int64_t(SYM_P) * k * n - int64_t(SYM_P * SYM_P / 2) * k * (k - 1);
+  return int64_t(SYM_P) * k * sym_n16(n) - int64_t(SYM_P * SYM_P / 2) * k * (k - 1);
 }
+// stored entries (what the smoother reads), sum over panels of (n - 16k) w
 __host__ __device__ inline int64_t sym_size(int n) {
+  int64_t s = 0;
+  for (int c0 = 0; c0 < n; c0 += SYM_P) s += int64_t(n - c0) * (n - c0 < SYM_P ? n - c0 : SYM_P);
+  return s;
+}
+// arena slots of one patch, padding included (a multiple of 16)
+__host__ __device__ inline int64_t sym_arena(int n) {
   if (n <= 0) return 0;
   const int t = (n + SYM_P - 1) / SYM_P, w = n - SYM_P * (t - 1);
-  return sym_panel_off(n, t - 1) + int64_t(w) * w;
+  return sym_panel_off(n, t - 1) + int64_t(SYM_P) * w;
 }
 // Work items of the symmetric GEMV: (64-row chunk R, panel k) for every
 // panel with a row in the chunk, k <= min(4R + 3, panels - 1).

@@ -428,7 +428,7 @@ __global__ __launch_bounds__(256) void k_finalize_sym(const PatchRec* __restrict
         const int i = i0 + lane, j = j0 + jj;
         const int k = j / SYM_P, c0 = SYM_P * k;
         if (i < n && j < n && i >= c0)
-          M[sym_panel_off(n, k) + int64_t(j - c0) * (n - c0) + (i - c0)] = T(tile[lane][jj]);
+          M[sym_panel_off(n, k) + int64_t(j - c0) * (sym_n16(n) - c0) + (i - c0)] = T(tile[lane][jj]);
       }
       __syncthreads();
     }
@@ -842,7 +842,7 @@ void factor_level_finish(Ctx& c, Level& L, FactorPending& fp, int precision, dou
   for (auto& r : exp_only) {
     maxc = std::max(maxc, kap_h[r.id]);
     const bool f32 = precision == CAV_PREC_MIXED && kap_h[r.id] <= cond_threshold;
-    const int64_t sz = packed ? sym_size(r.n) : int64_t(r.n) * r.n;
+    const int64_t sz = packed ? sym_arena(r.n) : int64_t(r.n) * r.n;
     if (f32) {
       w32.push_back(r);
       o32.push_back(PatchRec{r.n, r.id, r.slot, a32});
@@ -1039,7 +1039,9 @@ void factor_level_finish(Ctx& c, Level& L, FactorPending& fp, int precision, dou
     st->n_fp64 += int32_t(w64.size());
     st->n_fp32 += int32_t(w32.size());
     st->max_cond = std::max(st->max_cond, maxc);
-    st->factor_bytes += a64 * 8 + a32 * 4;
+    // the entries the smoother reads (the symmetric layout's padding is not)
+    for (auto& r : o64) st->factor_bytes += (packed ? sym_size(r.n) : int64_t(r.n) * r.n) * 8;
+    for (auto& r : o32) st->factor_bytes += (packed ? sym_size(r.n) : int64_t(r.n) * r.n) * 4;
   }
   L.factored = true;
 }

@@ -211,12 +211,13 @@ __device__ __forceinline__ void patch_gemv_sym(const PatchRec& rec, const T* __r
       cnt = 4 * R + 4 < np ? 4 * R + 4 : np;
     }
     const int k = it - base;
-    const int c0 = SYM_P * k, m = n - c0, w = m < SYM_P ? m : SYM_P;
+    const int c0 = SYM_P * k, w = n - c0 < SYM_P ? n - c0 : SYM_P, m = sym_n16(n) - c0;  // m: column stride
     const int i = 64 * R + lane;
     const bool in = i >= c0 && i < n;
     const T* pan = M + sym_panel_off(n, k);
-    // lanes outside the panel read its first row (same line) and drop it
-    const uint32_t off = in ? uint32_t(i - c0) : 0u;
+    // lanes outside the panel read its nearest row (a line the others read
+    // anyway: row c0 above the panel, row n - 1 past the patch) and drop it
+    const uint32_t off = uint32_t((i < c0 ? c0 : (i < n ? i : n - 1)) - c0);
     T v[SYM_P];
     if (w == SYM_P) {
 #pragma unroll
