@@ -338,23 +338,25 @@ __global__ __launch_bounds__(AS_THREADS) void k_add_smooth(
 }
 
 // x[d] = (zero ? 0 : x[d]) + alpha / cnt(d) * (z[d] + sum over d's slots of
-// delta) for every unknown inside an explicit patch. TOUCH_LANES lanes per
-// touched unknown (never straddling a wavefront): lane l sums slots l,
-// l + TOUCH_LANES, ... in ascending order and an xor tree adds the partial
-// sums, a fixed order with one chain of dependent loads per unknown.
-constexpr int TOUCH_LANES = 8;
+// delta) for every unknown inside an explicit patch. LANES lanes per touched
+// unknown (never straddling a wavefront): lane l sums slots l, l + LANES, ...
+// in ascending order and an xor tree adds the partial sums, a fixed order.
+// LANES follows the level's mean slots per unknown (8 to 64: the finest 512²
+// beam level averages 44), so each lane has a chain of one to three
+// dependent loads.
+template <int LANES>
 __global__ __launch_bounds__(TPB) void k_touched(int nt, const int32_t* __restrict__ tdof, const double* __restrict__ tinv,
                                                  const int32_t* __restrict__ tptr, const int32_t* __restrict__ tslot,
                                                  const double* __restrict__ delta, const double* __restrict__ z,
                                                  double* __restrict__ x, double alpha, int zero) {
   const int64_t g = int64_t(blockIdx.x) * TPB + threadIdx.x;
-  const int64_t t = g / TOUCH_LANES;
-  const int l = int(g % TOUCH_LANES);
+  const int64_t t = g / LANES;
+  const int l = int(g % LANES);
   double s = 0.0;
   if (t < nt)
-    for (int q = tptr[t] + l; q < tptr[t + 1]; q += TOUCH_LANES) s += delta[tslot[q]];
+    for (int q = tptr[t] + l; q < tptr[t + 1]; q += LANES) s += delta[tslot[q]];
 #pragma unroll
-  for (int o = TOUCH_LANES / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, TOUCH_LANES);
+  for (int o = LANES / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LANES);
   if (t < nt && l == 0) {
     const int32_t d = tdof[t];
     x[d] = (zero ? 0.0 : x[d]) + alpha * (tinv[t] * (z[d] + s));
@@ -1748,9 +1750,17 @@ void launch_smoother(Ctx& c, Level& L, const double* b, double* x, bool zero_gue
   else
     stream ? go(k_add_smooth<true, false>) : go(k_add_smooth<false, false>);
   timing_end(c, s, L.bytes64 + L.bytes32 + 72.0 * double(n2));
-  if (L.n_touched > 0)
-    k_touched<<<nblocks(int64_t(L.n_touched) * TOUCH_LANES), TPB, 0, s>>>(
-        L.n_touched, L.d_t_dof, L.d_t_inv, L.d_t_ptr, L.d_t_slot, L.d_delta, L.d_z, x, al, zero_guess ? 1 : 0);
+  if (L.n_touched > 0) {
+    const double per = double(L.n_slots) / double(L.n_touched);
+    auto go_t = [&](auto kern, int lanes) {
+      kern<<<nblocks(int64_t(L.n_touched) * lanes), TPB, 0, s>>>(L.n_touched, L.d_t_dof, L.d_t_inv, L.d_t_ptr,
+                                                                L.d_t_slot, L.d_delta, L.d_z, x, al, zero_guess ? 1 : 0);
+    };
+    if (per <= 12.0) go_t(k_touched<8>, 8);
+    else if (per <= 24.0) go_t(k_touched<16>, 16);
+    else if (per <= 48.0) go_t(k_touched<32>, 32);
+    else go_t(k_touched<64>, 64);
+  }
   if (remove_mean) launch_pressure_mean_remove(x, L.N, L.d_part, s);
 }
 
