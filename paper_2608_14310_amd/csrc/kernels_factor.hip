@@ -583,8 +583,12 @@ __global__ __launch_bounds__(256) void k_cq_prep(const double* __restrict__ W, i
 
 // W[a][j] <- base(a, j) - sum_t X[a][t] R[t][j] on one QT x QT tile, with
 // base = R[a - c0][j] on the rows of C, 0 on the columns of C elsewhere, and
-// W[a][j] otherwise. 256 threads, 4 x 4 outputs each (rows ty + 16 p,
-// columns tx + 16 q), X and R tiles in LDS; the sum runs over t in order.
+// W[a][j] otherwise. 256 threads; X and R tiles in LDS; the product on FP64
+// MFMA 16x16x4: wavefront w takes rows 16w .. 16w + 15 of the tile against
+// its four 16-column blocks, 16 k-steps of 4 (operand lanes: A[i][k] in lane
+// i + 16 k, B[k][j] in lane j + 16 k; result row k + 4 r, column j of lane
+// j + 16 k in its r-th value).
+typedef double cq_d4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_cq_update(double* __restrict__ W, int n, int c0, int m,
                                                    const double* __restrict__ X, const double* __restrict__ R) {
   __shared__ double Xs[QT][QB + 1];
@@ -600,37 +604,28 @@ __global__ __launch_bounds__(256) void k_cq_update(double* __restrict__ W, int n
     Rs[t][cc] = (j0 + cc < n) ? R[int64_t(t) * n + j0 + cc] : 0.0;
   }
   __syncthreads();
-  const int tx = tid % 16, ty = tid / 16;
-  double acc[4][4];
+  const int lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  cq_d4 acc[4];
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = cq_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int s4 = 0; s4 < QB; s4 += 4) {
+    const double av = Xs[16 * w + li][s4 + lk];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
-  for (int t = 0; t < QB; ++t) {
-    double xv[4], rv[4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) xv[p] = Xs[ty + 16 * p][t];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) rv[q] = Rs[t][tx + 16 * q];
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[p][q] += xv[p] * rv[q];
+    for (int ct = 0; ct < 4; ++ct)
+      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Rs[s4 + lk][16 * ct + li], acc[ct], 0, 0, 0);
   }
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const int a = a0 + ty + 16 * p;
-    if (a >= n) continue;
-    const bool rowC = a >= c0 && a < c0 + m;
+  for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = j0 + tx + 16 * q;
-      if (j >= n) continue;
-      double* w = W + int64_t(a) * n + j;
-      const double base = rowC ? Rs[a - c0][tx + 16 * q] : ((j >= c0 && j < c0 + m) ? 0.0 : *w);
-      *w = base - acc[p][q];
+    for (int r = 0; r < 4; ++r) {
+      const int a = a0 + 16 * w + lk + 4 * r, j = j0 + 16 * ct + li;
+      if (a >= n || j >= n) continue;
+      double* wp = W + int64_t(a) * n + j;
+      const bool rowC = a >= c0 && a < c0 + m;
+      const double base = rowC ? Rs[a - c0][16 * ct + li] : ((j >= c0 && j < c0 + m) ? 0.0 : *wp);
+      *wp = base - acc[ct][r];
     }
-  }
 }
 
 // Remove the pressure mean from every column of the inverse (rows p0..n-1):
