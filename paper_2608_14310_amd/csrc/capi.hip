@@ -200,8 +200,12 @@ void dev_free(Ctx& c, void* p) {
 
 hipEvent_t next_event(Ctx& c) {
   if (c.ev_used == c.ev_pool.size()) {
+    // timing-only events: no system-scope fence (a cache write-back and
+    // invalidate) when one is recorded, so the brackets neither cost a flush
+    // nor leave the next launch a cold cache; elapsed times are read after a
+    // stream synchronisation
     hipEvent_t e;
-    CAV_HIP(hipEventCreate(&e));
+    CAV_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     c.ev_pool.push_back(e);
   }
   return c.ev_pool[c.ev_used++];
