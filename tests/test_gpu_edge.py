@@ -304,3 +304,25 @@ def test_kernel_timing_brackets(cav):
     assert kt["coop_launches"] == 0 and 0 < kt["flow_launches"] == kt["launches"]
     assert 0 < kt["flow_ms"] <= kt["ms"]
     assert kt["flow_bytes"] == kt["bytes"] == phase_bytes
+
+
+def test_kernel_timing_leaves_results_unchanged(cav):
+    """Live timing brackets every weighted additive smoother launch with a pair
+    of events and every top-level V-cycle with another; the solve with them is
+    the solve without them, bit for bit, and every V-cycle counts one launch
+    per smoothing step on each smoothed level."""
+    print("[edge] kernel timing, additive V(3,3), symmetric layout", flush=True)
+    s = workloads.beam_fibres(N=64, n_levels=4, kappa_b=1e-2)
+    g = cav.Solver(0)
+    g.setup(s, precision="fp64", alpha=0.9, layout="symmetric")
+    g.set_smoother("additive", 0.9, 3, 3)
+    b = _t(s.b)
+    x0, i0 = g.fgmres_solve(b, rtol=1e-10, max_it=150)
+    g.kernel_timing(True)
+    x1, i1 = g.fgmres_solve(b, rtol=1e-10, max_it=150)
+    kt = g.kernel_timing(False)
+    g.close()
+    assert i0["converged"] and i1["iterations"] == i0["iterations"]
+    assert torch.equal(x0, x1)
+    assert kt["vcycles"] > 0 and kt["vcycle_ms"] > 0 and kt["ms"] > 0 and kt["bytes"] > 0
+    assert kt["launches"] == kt["vcycles"] * (s.n_levels - 1) * 6
